@@ -1,0 +1,197 @@
+"""Plain serial FP64 CPU oracle for Algorithm 1 (Section 3.1) run over replications.
+
+TEST INFRASTRUCTURE: only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark import this package. It never serves the product path, and it shares no code with
+the HIP library.
+
+The arithmetic lives in ``oracle.c`` (plain C, FP64, built with ``-ffp-contract=off``); this
+module only builds it and marshals arguments through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+MAX_D = 64
+MAX_CKPT = 8
+TAU_NONE = 0xFFFFFFFF
+NOISE_GAUSS, NOISE_T = 0, 1
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (plain gcc, no fast-math, no FMA contraction)."""
+    src = os.path.join(HERE, "oracle.c")
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-Wall", "-Wextra", "-fPIC", "-shared", "-o", tmp, src, "-lm"],
+                              cwd=HERE)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("N", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("noise", ctypes.c_int32), ("nu", ctypes.c_int32), ("n_ckpt", ctypes.c_int32),
+                ("instance", ctypes.c_uint32), ("pad_", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("lam", ctypes.c_double), ("gap_eps", ctypes.c_double),
+                ("mu", ctypes.POINTER(ctypes.c_double)), ("chol", ctypes.POINTER(ctypes.c_double)),
+                ("w0", ctypes.POINTER(ctypes.c_double)), ("ckpt", ctypes.c_int64 * MAX_CKPT)]
+
+
+class PathOut(ctypes.Structure):
+    _fields_ = [("y", ctypes.c_double), ("f_ckpt", ctypes.c_double * MAX_CKPT),
+                ("cnt", ctypes.c_uint32 * (MAX_D + 1)), ("wsum", ctypes.c_uint64 * MAX_D),
+                ("tau", ctypes.c_uint32), ("tau_lo", ctypes.c_uint32), ("tau_hi", ctypes.c_uint32),
+                ("n_ambiguous", ctypes.c_uint64), ("n_replayed", ctypes.c_uint64),
+                ("n_mismatch", ctypes.c_uint64), ("first_mismatch", ctypes.c_int64),
+                ("identity_err", ctypes.c_double), ("min_margin", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_uint64), ("T", ctypes.c_uint64), ("mean", ctypes.c_double),
+                ("var", ctypes.c_double), ("ci95", ctypes.c_double), ("ymin", ctypes.c_double),
+                ("ymax", ctypes.c_double), ("f_mean", ctypes.c_double * MAX_CKPT),
+                ("f_sd", ctypes.c_double * MAX_CKPT), ("rse_mean", ctypes.c_double * MAX_CKPT),
+                ("rse_sd", ctypes.c_double * MAX_CKPT), ("rse_undef", ctypes.c_uint64 * MAX_CKPT),
+                ("decision_total", ctypes.c_uint64 * (MAX_D + 1)), ("tau_count", ctypes.c_uint64),
+                ("tau_mean", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.or_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
+        L.or_uniform.argtypes = [ctypes.c_uint32]
+        L.or_uniform.restype = ctypes.c_double
+        L.or_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                 ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, dp]
+        L.or_draw_returns.argtypes = [ctypes.POINTER(Problem), ctypes.c_uint64, ctypes.c_uint64, dp]
+        L.or_sample_gradient.argtypes = [ctypes.POINTER(Problem), ctypes.c_uint64, ctypes.c_uint64,
+                                         dp, dp, dp, dp]
+        L.or_objective.argtypes = [ctypes.POINTER(Problem), dp]
+        L.or_objective.restype = ctypes.c_double
+        L.or_path.argtypes = [ctypes.POINTER(Problem), ctypes.c_uint64, ctypes.c_uint64,
+                              ctypes.POINTER(ctypes.c_uint8), ctypes.c_double,
+                              ctypes.POINTER(PathOut), ctypes.POINTER(ctypes.c_uint8)]
+        L.or_run_range.argtypes = [ctypes.POINTER(Problem), ctypes.c_uint64, ctypes.c_uint64,
+                                   ctypes.c_uint64, ctypes.POINTER(PathOut)]
+        L.or_reduce.argtypes = [ctypes.POINTER(Problem), ctypes.c_uint64, ctypes.POINTER(PathOut),
+                                ctypes.c_uint64, ctypes.POINTER(Stats)]
+        _lib = L
+    return _lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class OracleProblem:
+    """Keeps the numpy buffers of one problem alive next to its ctypes struct."""
+
+    def __init__(self, mu, sigma=None, chol=None, *, N, M=1, lam=0.5, w0=None, noise=NOISE_GAUSS,
+                 nu=3, seed=0, instance=0, ckpt=(), gap_eps=1e-2):
+        self.mu = np.ascontiguousarray(mu, dtype=np.float64)
+        d = self.mu.shape[0]
+        if chol is None:
+            chol = np.diag(np.asarray(sigma, dtype=np.float64))
+        self.chol = np.ascontiguousarray(chol, dtype=np.float64).reshape(d, d)
+        self.w0 = None if w0 is None else np.ascontiguousarray(w0, dtype=np.float64)
+        ck = list(ckpt)
+        if len(ck) > MAX_CKPT:
+            raise ValueError("at most 8 checkpoints")
+        p = Problem()
+        p.d, p.N, p.M, p.noise, p.nu, p.n_ckpt = d, N, M, noise, nu, len(ck)
+        p.instance, p.seed, p.lam, p.gap_eps = instance, seed, lam, gap_eps
+        p.mu, p.chol = _dptr(self.mu), _dptr(self.chol)
+        p.w0 = _dptr(self.w0) if self.w0 is not None else ctypes.POINTER(ctypes.c_double)()
+        for i, c in enumerate(ck):
+            p.ckpt[i] = int(c)
+        self.p = p
+        self.d, self.N, self.ckpt = d, N, ck
+
+    def path(self, rep, T, replay=None, uroff=0.0, want_decisions=False):
+        out = PathOut()
+        dec = np.zeros(T, dtype=np.uint8) if want_decisions else None
+        rp = None
+        if replay is not None:
+            replay = np.ascontiguousarray(replay, dtype=np.uint8)
+            assert replay.shape[0] >= T
+            rp = replay.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        rc = lib().or_path(ctypes.byref(self.p), rep, T, rp, uroff, ctypes.byref(out),
+                           dec.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)) if dec is not None else None)
+        if rc:
+            raise ValueError("or_path rejected the problem")
+        return (out, dec) if want_decisions else out
+
+    def run(self, R, T, r0=0):
+        outs = (PathOut * R)()
+        rc = lib().or_run_range(ctypes.byref(self.p), r0, r0 + R, T, outs)
+        if rc:
+            raise ValueError("or_run_range rejected the problem")
+        return outs
+
+    def reduce(self, outs, T):
+        st = Stats()
+        lib().or_reduce(ctypes.byref(self.p), T, outs, len(outs), ctypes.byref(st))
+        return st
+
+    def sample_gradient(self, rep, epoch, w):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        g, rbar, sw = (np.zeros(self.d) for _ in range(3))
+        lib().or_sample_gradient(ctypes.byref(self.p), rep, epoch, _dptr(w), _dptr(g), _dptr(rbar),
+                                 _dptr(sw))
+        return g, rbar, sw
+
+    def draw_returns(self, rep, epoch):
+        R = np.zeros((self.N, self.d))
+        lib().or_draw_returns(ctypes.byref(self.p), rep, epoch, _dptr(R))
+        return R
+
+    def objective(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        return lib().or_objective(ctypes.byref(self.p), _dptr(w))
+
+
+def philox(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().or_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+def uniform(x):
+    return lib().or_uniform(int(x) & 0xFFFFFFFF)
+
+
+def normals(seed, domain, instance, rep, epoch, q0, n):
+    out = np.zeros(n, dtype=np.float64)
+    lib().or_normals(seed, domain, instance, rep, epoch, q0, n, _dptr(out))
+    return out
+
+
+def path_arrays(outs, d, n_ckpt):
+    """Per-path outputs as numpy arrays (Y, f_ckpt, cnt, wsum, tau)."""
+    R = len(outs)
+    Y = np.array([o.y for o in outs])
+    F = np.array([[o.f_ckpt[c] for c in range(n_ckpt)] for o in outs]).reshape(R, n_ckpt)
+    cnt = np.array([[o.cnt[j] for j in range(d + 1)] for o in outs], dtype=np.uint64)
+    wsum = np.array([[o.wsum[j] for j in range(d)] for o in outs], dtype=np.uint64)
+    tau = np.array([o.tau for o in outs], dtype=np.uint64)
+    return Y, F, cnt, wsum, tau

@@ -1,0 +1,123 @@
+/*
+ * oracle.h -- plain serial FP64 CPU oracle for the batched stochastic
+ * Frank-Wolfe mean-variance simulation of He, Liu, Wu, Zheng and Zhu,
+ * "A Preliminary Study on Accelerating Simulation Optimization with GPU
+ * Implementation" (Section 3.1: problem Eq. (3), sample objective Eq. (4),
+ * sample mean Eq. (5), Algorithm 1).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library. It shares no code,
+ * header, table or constant with the HIP library; both sides implement the
+ * counter-based generator (Philox4x32-10, Salmon et al., SC'11) from its
+ * published definition.
+ *
+ * Everything here is slow on purpose: one replication at a time, the sample
+ * matrix R_i = mu + L y_i formed explicitly, the sample mean and the centred
+ * sample covariance applied to w exactly as Eq. (4)-(5) write them, and the
+ * iterate updated with the recurrence of Algorithm 1.
+ */
+#ifndef PAPER_2404_11631_ORACLE_H
+#define PAPER_2404_11631_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OR_MAX_D 64
+#define OR_MAX_CKPT 8
+#define OR_TAU_NONE 0xFFFFFFFFu
+
+enum { OR_NOISE_GAUSS = 0, OR_NOISE_T = 1 };
+enum { OR_DOMAIN_PATH = 0, OR_DOMAIN_PARAM = 1, OR_DOMAIN_CV_AUX = 2, OR_DOMAIN_MLP = 3 };
+
+/* One instance of problem Eq. (3) plus the sampling knobs of Algorithm 1. */
+typedef struct {
+    int32_t d;              /* number of assets, 1..64 */
+    int32_t N;              /* samples per resample, >= 2 (Eq. (4) divides by N-1) */
+    int32_t M;              /* iterations between resamples, >= 1 */
+    int32_t noise;          /* OR_NOISE_GAUSS or OR_NOISE_T */
+    int32_t nu;             /* t degrees of freedom (integer >= 3) when noise == OR_NOISE_T */
+    int32_t n_ckpt;         /* number of checkpoints, 0..8 */
+    uint32_t instance;      /* stream domain for batched instances, < 2^24 */
+    uint32_t pad_;
+    uint64_t seed;          /* Philox key */
+    double lambda;          /* risk coefficient: f(w) = lambda w'Sigma w - mu'w */
+    double gap_eps;         /* Frank-Wolfe gap threshold for the hitting time */
+    const double *mu;       /* d mean returns */
+    const double *chol;     /* d*d row-major lower-triangular L, Sigma = L L' */
+    const double *w0;       /* d starting point in W, or NULL for the origin */
+    int64_t ckpt[OR_MAX_CKPT]; /* iterate counts in [1, T] at which f(w_t) is recorded */
+} or_problem;
+
+/* Everything one replication produces. */
+typedef struct {
+    double y;                       /* f(w_T), Eq. (3) at the returned point */
+    double f_ckpt[OR_MAX_CKPT];     /* f(w_c) for each checkpoint c */
+    uint32_t cnt[OR_MAX_D + 1];     /* cnt[0]: origin chosen; cnt[j+1]: vertex e_j chosen */
+    uint64_t wsum[OR_MAX_D];        /* sum of (t+1) over the steps that chose e_j */
+    uint32_t tau;                   /* first step with FW gap <= eps, or OR_TAU_NONE */
+    uint32_t tau_lo, tau_hi;        /* range of hitting times consistent with the rounding bound */
+    uint64_t n_ambiguous;           /* steps whose LMO margin is within the rounding bound */
+    uint64_t n_replayed;            /* ambiguous steps where the replayed decision was adopted */
+    uint64_t n_mismatch;            /* unambiguous steps where the replayed decision differs */
+    int64_t first_mismatch;         /* step of the first mismatch, or -1 */
+    double identity_err;            /* max_j |w_T - 2 wsum/(T(T+1))| (recurrence vs closed form) */
+    double min_margin;              /* smallest LMO margin seen along the path */
+} or_path_out;
+
+typedef struct {
+    uint64_t R, T;
+    double mean, var, ci95, ymin, ymax;
+    double f_mean[OR_MAX_CKPT], f_sd[OR_MAX_CKPT];
+    double rse_mean[OR_MAX_CKPT], rse_sd[OR_MAX_CKPT];
+    uint64_t rse_undef[OR_MAX_CKPT];
+    uint64_t decision_total[OR_MAX_D + 1];
+    uint64_t tau_count;
+    double tau_mean;
+} or_stats;
+
+/* Philox4x32-10 block function: out = philox(ctr, key). */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Uniform in (0,1) from one 32-bit word: (2 (x mod 2^23) + 1) 2^-24. */
+double or_uniform(uint32_t x);
+
+/* Standard normals number q0 .. q0+n-1 of stream (seed, domain, instance, rep, epoch). */
+void or_normals(uint64_t seed, uint32_t domain, uint32_t instance, uint64_t rep,
+                uint64_t epoch, uint64_t q0, uint64_t n, double *out);
+
+/* The N x d sample matrix R_i = mu + L y_i of replication `rep`, epoch `epoch` (row-major). */
+void or_draw_returns(const or_problem *p, uint64_t rep, uint64_t epoch, double *Rmat);
+
+/* Sample mean Eq. (5), Sigma_hat w from Eq. (4) and the gradient 2 lambda Sigma_hat w - Rbar
+ * for replication `rep`, epoch `epoch`, at a fixed point w. */
+void or_sample_gradient(const or_problem *p, uint64_t rep, uint64_t epoch, const double *w,
+                        double *grad, double *rbar, double *sigma_w);
+
+/* True objective Eq. (3) with the risk coefficient lambda: lambda |L'w|^2 - mu'w. */
+double or_objective(const or_problem *p, const double *w);
+
+/* One replication of Algorithm 1 for T iterations.
+ * replay: NULL, or T decisions (0 = origin, j+1 = e_j) from the system under test. At a step
+ *         whose margin is within the rounding bound the replayed decision is adopted when it is
+ *         a near-optimal vertex; elsewhere a differing replayed decision is counted as a mismatch
+ *         and the oracle keeps its own.
+ * uroff:  unit roundoff of the system under test (2^-24 for FP32, 2^-53 for FP64); 0 disables
+ *         the bound (exact comparison).
+ * decisions: NULL or T bytes receiving the decisions taken. */
+int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay, double uroff,
+            or_path_out *out, uint8_t *decisions);
+
+/* Replications [r0, r1): per-path outputs into out[r - r0] (array of r1 - r0). */
+int or_run_range(const or_problem *p, uint64_t r0, uint64_t r1, uint64_t T, or_path_out *out);
+
+/* Cross-path statistics of n per-path outputs. */
+void or_reduce(const or_problem *p, uint64_t T, const or_path_out *paths, uint64_t n,
+               or_stats *st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,95 @@
+"""Seeded synthetic inputs for the batched Frank-Wolfe simulation.
+
+This module draws instance parameters (mean returns mu, standard deviations sigma, dense
+Cholesky factors L, the uneven batch of instances) and names the workload shapes. It holds none
+of the method's arithmetic, so both the HIP path and the CPU oracle can take their inputs from
+it. The path noise itself is not drawn here: each side generates it from the counter-based
+Philox4x32-10 stream.
+
+Parameter laws:
+  * "unit" regime: mu_j ~ U(0,1) and sigma_j ~ U(0,1), Sigma = diag(sigma^2).
+  * "paper" regime (Section 4.1, Task 1): mu_j ~ U(-1,1), sigma_j ~ U(0, 0.025).
+  * dense factor: L_jj = sigma_j and L_jk = sigma_j a_jk / sqrt(j+1) for k < j, a_jk ~ U(-1,1).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+#: iterations at which Table 2 reports the relative squared error
+TABLE2_ITERATIONS = (50, 100, 500, 1000)
+
+
+def _rng(seed: int, instance: int, stream: int) -> np.random.Generator:
+    key = np.array([seed & 0xFFFFFFFFFFFFFFFF, (instance << 8) | stream], dtype=np.uint64)
+    return np.random.Generator(np.random.Philox(key=key))
+
+
+def diag_instance(seed: int, instance: int, d: int, regime: str = "unit"):
+    """(mu, sigma) for one instance, float64 arrays of length d."""
+    g = _rng(seed, instance, 1)
+    if regime == "unit":
+        mu = g.uniform(0.0, 1.0, d)
+        sigma = g.uniform(0.0, 1.0, d)
+    elif regime == "paper":
+        mu = g.uniform(-1.0, 1.0, d)
+        sigma = g.uniform(0.0, 0.025, d)
+    else:
+        raise ValueError(f"unknown regime {regime!r}")
+    return mu, sigma
+
+
+def dense_instance(seed: int, instance: int, d: int, regime: str = "unit"):
+    """(mu, L) with L lower triangular, row-major float64 (d, d), Sigma = L L'."""
+    mu, sigma = diag_instance(seed, instance, d, regime)
+    g = _rng(seed, instance, 2)
+    a = g.uniform(-1.0, 1.0, (d, d))
+    L = np.zeros((d, d))
+    for j in range(d):
+        L[j, j] = sigma[j]
+        for k in range(j):
+            L[j, k] = sigma[j] * a[j, k] / math.sqrt(j + 1)
+    return mu, L
+
+
+@dataclass
+class BatchInstance:
+    instance: int
+    d: int
+    N: int
+    T: int
+    R: int
+    mu: np.ndarray = field(repr=False)
+    sigma: np.ndarray = field(repr=False)
+
+
+def uneven_batch(seed: int = 0, n_instances: int = 256, R: int = 4096, d_range=(2, 32),
+                 n_range=(2, 50), t_range=(100, 100_000)):
+    """Instances of uneven size and horizon: d ~ U{d_range}, N ~ U{n_range},
+    T = round(exp(U(ln t_lo, ln t_hi))), mu and sigma from the unit regime."""
+    g = _rng(seed, 0xFFFFFF, 3)
+    out = []
+    for i in range(n_instances):
+        d = int(g.integers(d_range[0], d_range[1] + 1))
+        N = int(g.integers(n_range[0], n_range[1] + 1))
+        T = int(round(math.exp(g.uniform(math.log(t_range[0]), math.log(t_range[1])))))
+        mu, sigma = diag_instance(seed, i, d)
+        out.append(BatchInstance(i, d, N, T, R, mu, sigma))
+    return out
+
+
+#: workload shapes (R replications, T iterations, d assets, N samples per gradient, M = 1)
+WORKLOADS = {
+    "tiny": dict(R=1_000, T=100, d=2, N=2, M=1, precision="fp64", noise="gauss",
+                 checkpoints=(50, 100), seed=0),
+    "paper_scale": dict(R=1_000_000, T=10_000, d=10, N=10, M=1, precision="fp32", noise="gauss",
+                        checkpoints=(50, 100, 500, 1000, 10_000), seed=0),
+    "uneven": dict(n_instances=256, R=4_096, d_range=(2, 32), n_range=(2, 50),
+                   t_range=(100, 100_000), precision="fp32", seed=0),
+    "control_variate": dict(R=100_000, T=10_000, d=10, N=10, M=1, precision="fp32",
+                            train_pairs=10_000_000, hidden=64, seed=100),
+    "stress": dict(R=10_000_000, T=1_000, d=64, N=100, M=1, precision="fp32", noise="t", nu=3,
+                   dense=True, checkpoints=(50, 100, 500, 1000), seed=0),
+}
