@@ -1,0 +1,156 @@
+/*
+ * sim.h -- C ABI of the MI355X batched stochastic Frank-Wolfe simulator.
+ *
+ * The library runs Algorithm 1 of He, Liu, Wu, Zheng and Zhu, "A Preliminary Study on
+ * Accelerating Simulation Optimization with GPU Implementation" (Section 3.1), over R
+ * independent replications on one gfx950 GPU and reduces the paths to FP64 statistics.
+ *
+ *   problem (Eq. (3)):   min_w f(w) = lambda w' Sigma w - w' mu   on W = {w >= 0, 1'w <= 1},
+ *                        returns R ~ N(mu, Sigma) with Sigma = L L' (diag(sigma^2) by default);
+ *                        lambda = 1/2 is Eq. (3), lambda = 1 is the sample objective Eq. (4).
+ *   estimator (Eq. (4)-(5)): N fresh samples every M iterations; gradient 2 lambda Sigma_hat w - Rbar
+ *                        with the centred sample covariance (divisor N-1) and the sample mean.
+ *   algorithm (Alg. 1):  linear subproblem over the vertices {0, e_1..e_d} of W (lowest index
+ *                        among equal minima; the origin when the smallest entry is >= 0), step
+ *                        2/(t+2) with t = kM+m, update w + gamma (s - w), outcome Y = f(w_T).
+ *
+ * Noise: replication r, epoch k = t div M, uses standard normals number q = 0, 1, ... of the
+ * Philox4x32-10 stream with key (seed lo, seed hi) and counter (q/4, k, r, instance_id), words
+ * (x0,x1) and (x2,x3) of each block mapped to Box-Muller pairs through u = (2 (x mod 2^23)+1) 2^-24.
+ * Sample i, asset j takes normal q = i d + j; Student-t noise scales sample i by
+ * sqrt((nu-2)/chi2) with chi2 the sum of squares of normals N d + nu i + k, k < nu.
+ *
+ * Conventions for every entry point:
+ *   - Input pointers are host pointers owned by the caller, read during the call only.
+ *   - Results live in device memory owned by the context until the next run or sim_destroy.
+ *   - Return 0 on success or a negative sim_status. Validation happens before any launch; a
+ *     rejected call changes nothing. No C++ exception crosses this boundary.
+ *   - A context is not thread-safe; calls that launch work are asynchronous on its stream, and
+ *     the calls that return results synchronise that stream.
+ */
+#ifndef PAPER_2404_11631_AMD_SIM_H
+#define PAPER_2404_11631_AMD_SIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIM_ABI_VERSION 1u
+#define SIM_MAX_D 64u          /* assets per instance */
+#define SIM_MAX_CKPT 8u        /* checkpoints per run */
+#define SIM_TAU_NONE 0xFFFFFFFFu
+
+typedef struct sim_ctx sim_ctx;
+
+typedef enum {
+    SIM_OK = 0,
+    SIM_EINVAL = -1,        /* an argument violates its stated range */
+    SIM_ENOMEM = -2,        /* device or host allocation failed */
+    SIM_EDEVICE = -3,       /* a HIP call failed; sim_last_error has its message */
+    SIM_ESTATE = -4,        /* call out of order (e.g. results before any run) */
+    SIM_EUNSUPPORTED = -5   /* a combination this build does not implement */
+} sim_status;
+
+typedef enum { SIM_NOISE_GAUSS = 0, SIM_NOISE_T = 1 } sim_noise;
+typedef enum { SIM_FP32 = 0, SIM_FP64 = 1 } sim_precision;
+
+typedef enum {
+    SIM_KEEP_PATHS = 1u,    /* keep per-path records (Y, checkpoints, cnt, wsum, tau) */
+    SIM_DECISION_LOG = 2u   /* log every decision of replications [log_rep_begin, +log_rep_count) */
+} sim_flag;
+
+/* One problem instance (Eq. (3)) and the sampling knobs of Algorithm 1. */
+typedef struct {
+    uint32_t abi_version;       /* SIM_ABI_VERSION */
+    uint32_t d;                 /* assets, 1..SIM_MAX_D */
+    const double *mu;           /* [d] mean returns */
+    const double *sigma;        /* [d] standard deviations >= 0, used when chol is NULL */
+    const double *chol;         /* [d*d] row-major lower-triangular L (Sigma = L L'), or NULL */
+    double risk_coef;           /* lambda > 0 */
+    const double *w0;           /* [d] starting point in W, or NULL for the origin */
+    uint32_t n_samples;         /* N >= 2 */
+    uint32_t resample_every;    /* M >= 1 */
+    uint32_t noise;             /* sim_noise */
+    uint32_t nu;                /* Student-t degrees of freedom, integer >= 3 (noise == SIM_NOISE_T) */
+    uint32_t state_precision;   /* sim_precision of normals, sums and iterate */
+    uint32_t n_checkpoints;     /* 0..SIM_MAX_CKPT */
+    uint64_t checkpoints[SIM_MAX_CKPT]; /* strictly increasing iterate counts in [1, T] */
+    double gap_eps;             /* Frank-Wolfe gap threshold of the hitting time tau, >= 0 */
+    uint32_t flags;             /* sim_flag bits */
+    uint32_t instance_id;       /* stream domain of this instance, < 2^24 */
+    uint64_t log_rep_begin;     /* SIM_DECISION_LOG: first logged replication */
+    uint64_t log_rep_count;     /* SIM_DECISION_LOG: number of logged replications (<= 65536) */
+} sim_params;
+
+/* FP64 statistics of one run. Means, variances and sums use compensated (double-double)
+ * accumulation over a fixed reduction tree, so they do not depend on scheduling. */
+typedef struct {
+    uint64_t R, T;
+    double mean, var, ci95_halfwidth, min, max;     /* of Y = f(w_T); var unbiased; 1.96 sqrt(var/R) */
+    double f_star;                                  /* min over W of f (diagonal Sigma), else NaN */
+    uint32_t n_checkpoints;
+    uint32_t pad_;
+    uint64_t checkpoints[SIM_MAX_CKPT];
+    double f_mean[SIM_MAX_CKPT], f_sd[SIM_MAX_CKPT];        /* f(w_c) across paths */
+    double rse_mean[SIM_MAX_CKPT], rse_sd[SIM_MAX_CKPT];    /* ((f(w_c) - Y)/f(w_c))^2, Table 2 */
+    uint64_t rse_undefined[SIM_MAX_CKPT];                   /* paths with f(w_c) == 0 */
+    uint64_t decision_total[SIM_MAX_D + 1];                 /* [0] origin, [j+1] vertex e_j */
+    uint64_t tau_count;                                     /* paths whose FW gap reached gap_eps */
+    double tau_mean;                                        /* mean hitting step over those paths */
+    double kernel_ms;                                       /* device time of the run (HIP events) */
+    double path_steps_per_s;                                /* R T / kernel time */
+} sim_stats_out;
+
+/* Device pointers (owned by the context) to the per-path records of the last run, structure of
+ * arrays indexed [field][r]. Fields not produced by the run are NULL. */
+typedef struct {
+    uint64_t R, T;
+    uint32_t d, n_checkpoints;
+    const double *y;            /* [R] f(w_T) */
+    const double *f_ckpt;       /* [n_checkpoints][R] */
+    const uint32_t *cnt;        /* [d+1][R] decision counts */
+    const uint64_t *wsum;       /* [d][R] sum of (t+1) over steps choosing e_j */
+    const uint32_t *tau;        /* [R] hitting step or SIM_TAU_NONE */
+    const uint8_t *decisions;   /* [T][log_rep_count] decisions, 0 = origin, j+1 = e_j */
+    uint64_t log_rep_begin, log_rep_count;
+} sim_path_view;
+
+/* Creates a context on HIP device `device`, launching on `hip_stream` (a hipStream_t, or NULL
+ * for the null stream). */
+int sim_create(int device, void *hip_stream, sim_ctx **out);
+
+/* Replaces the stream later calls launch on. */
+int sim_set_stream(sim_ctx *ctx, void *hip_stream);
+
+/* Runs R replications of Algorithm 1 for T iterations (Section 3.1) with noise seed `seed`,
+ * fused with the cross-path reduction in one launch. Asynchronous on the context's stream.
+ * Ranges: 1 <= R < 2^32, 1 <= T <= 2^32 - 2. */
+int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed);
+
+/* Checks a parameter set exactly as sim_run does, without a device. Returns 0 or the code sim_run
+ * would return, and writes the reason into msg (may be NULL). */
+int sim_validate(const sim_params *p, uint64_t R, uint64_t T, char *msg, size_t len);
+
+/* Statistics of the last run; synchronises the stream. */
+int sim_stats(sim_ctx *ctx, sim_stats_out *out);
+
+/* Per-path records of the last run (device pointers); synchronises the stream. */
+int sim_paths(sim_ctx *ctx, sim_path_view *out);
+
+/* Copies `bytes` from a device pointer returned by sim_paths into host memory. */
+int sim_copy_to_host(sim_ctx *ctx, void *host_dst, const void *device_src, size_t bytes);
+
+/* Static description of an error code, and the last detailed message of a context. */
+const char *sim_strerror(int code);
+int sim_last_error(sim_ctx *ctx, char *buf, size_t len);
+
+/* Frees every device allocation of the context. Safe on NULL. */
+void sim_destroy(sim_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,565 @@
+// fw_paths.hip -- one lane per replication of Algorithm 1 (Section 3.1), fused with the FP64
+// cross-path reduction (last workgroup finalises).
+//
+// Per iteration t of replication r (epoch k = t div M):
+//   w_t       = w_0 at t = 0, else 2 S_j / (t (t+1)) from the integer signature S_j = sum of
+//               (s+1) over the steps s < t that chose e_j (the step rule 2/(t+2) gives this
+//               closed form of the recurrence w + gamma (s - w));
+//   sampling  N samples R_i = mu + sigma .* z_i (Gaussian) or mu + sigma .* a_i z_i (elliptical t),
+//             reduced in one pass to s1 = sum_i z_i and s2 = sum_i z_i (z_i' v), v = sigma .* w, so
+//             Rbar = mu + sigma .* s1 / N                                        (Eq. (5))
+//             (N-1) Sigma_hat w = sigma .* (s2 - s1 (s1' v) / N)                 (Eq. (4));
+//   gradient  g = 2 lambda Sigma_hat w - Rbar;
+//   decision  e_j for the lowest index attaining min_j g_j when that minimum is negative, else the
+//             origin (the vertices of W);
+//   gap       g'(w - s) and its first passage below eps (tau);
+//   update    S_j += t+1 for the chosen e_j; checkpoint f(w_{t+1}) in FP64 from S.
+// The outcome is Y = f(w_T) in FP64 from the exact signature.
+//
+// State stays in registers: s1, s2, v (binary32 or binary64), S (u32 while T(T+1)/2 < 2^32, else
+// u64) and the decision counts. No HBM traffic per step except the optional decision log.
+#include <hip/hip_runtime.h>
+
+#include "device_rng.hpp"
+#include "sim_types.hpp"
+
+namespace fw {
+
+__device__ __forceinline__ void dd_add(double &h, double &l, double bh, double bl)
+{
+    const double s = h + bh;
+    const double bb = s - h;
+    double e = (h - (s - bb)) + (bh - bb);
+    e += l + bl;
+    const double hs = s + e;
+    l = e - (hs - s);
+    h = hs;
+}
+
+// Workgroup sum of a double-double; the result is valid in thread 0. Fixed tree: shuffle-down
+// within each wavefront, then the four wavefront partials in order.
+__device__ __forceinline__ void block_sum_dd(double &h, double &l, double *sm)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double oh = __shfl_down(h, off, 64);
+        const double ol = __shfl_down(l, off, 64);
+        dd_add(h, l, oh, ol);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        sm[2 * wave] = h;
+        sm[2 * wave + 1] = l;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        h = sm[0];
+        l = sm[1];
+        for (int k = 1; k < kBlock / 64; ++k) dd_add(h, l, sm[2 * k], sm[2 * k + 1]);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t x, uint64_t *sm)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_down(x, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sm[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 1; k < kBlock / 64; ++k) x += sm[k];
+    __syncthreads();
+    return x;
+}
+
+template <bool IS_MAX>
+__device__ __forceinline__ double block_extreme(double x, double *sm)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double o = __shfl_down(x, off, 64);
+        x = IS_MAX ? fmax(x, o) : fmin(x, o);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sm[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int k = 1; k < kBlock / 64; ++k) x = IS_MAX ? fmax(x, sm[k]) : fmin(x, sm[k]);
+    __syncthreads();
+    return x;
+}
+
+__device__ __forceinline__ void store_agent(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double load_agent(const double *p)
+{
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t load_agent(const uint64_t *p)
+{
+    return __hip_atomic_load(const_cast<uint64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------------------------
+// per-precision coefficient access
+// ---------------------------------------------------------------------------------------------
+template <typename Real>
+struct Coef;
+
+template <>
+struct Coef<float> {
+    const InstanceDesc *P;
+    __device__ float mu(int j) const { return P->mu_f[j]; }
+    __device__ float sz(int j) const { return P->sz_f[j]; }
+    __device__ float c1(int j) const { return P->c1_f[j]; }
+    __device__ float c2(int j) const { return P->c2_f[j]; }
+    __device__ float w0(int j) const { return P->w0_f[j]; }
+    __device__ float inv_n() const { return P->inv_n_f; }
+    __device__ float tscale() const { return P->tscale_f; }
+    __device__ static float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+};
+
+template <>
+struct Coef<double> {
+    const InstanceDesc *P;
+    __device__ double mu(int j) const { return P->mu_d[j]; }
+    __device__ double sz(int j) const { return P->sig_d[j]; }
+    __device__ double c1(int j) const { return P->c1_d[j]; }
+    __device__ double c2(int j) const { return P->c2_d[j]; }
+    __device__ double w0(int j) const { return P->w0_d[j]; }
+    __device__ double inv_n() const { return P->inv_n_d; }
+    __device__ double tscale() const { return P->tscale_d; }
+    __device__ static double rsqrt(double x) { return 1.0 / sqrt(x); }
+};
+
+constexpr int gcd_const(int a, int b) { return b == 0 ? a : gcd_const(b, a % b); }
+
+// f(w) = lambda sum_j sigma_j^2 w_j^2 - mu' w at w = c S (Eq. (3), diagonal Sigma), in FP64
+template <int D, bool EXACT, typename WS>
+__device__ __forceinline__ double objective_from_signature(const InstanceDesc *__restrict__ P,
+                                                           const WS (&S)[D], double c)
+{
+    const int d = EXACT ? D : static_cast<int>(P->d);
+    double quad = 0.0, lin = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        if (j < d) {
+            const double w = static_cast<double>(S[j]) * c;
+            const double sw = P->sig_d[j] * w;
+            quad += sw * sw;
+            lin += P->mu_d[j] * w;
+        }
+    }
+    return P->lambda * quad - lin;
+}
+
+struct LaneResult {
+    double y;
+    uint32_t tau;
+};
+
+// One replication of Algorithm 1; returns Y and tau, leaves decision counts in cnt.
+template <int D, bool EXACT, typename Real, int NOISE, typename WS>
+__device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, const RunBuffers &B,
+                                         uint32_t r, uint32_t (&cnt)[D + 1], WS (&S)[D],
+                                         LaneResult &res)
+{
+    const Coef<Real> C{P};
+    const int d = EXACT ? D : static_cast<int>(P->d);
+    const uint32_t N = P->N, M = P->M;
+    const uint64_t T = P->T;
+    const uint32_t k0 = static_cast<uint32_t>(P->seed), k1 = static_cast<uint32_t>(P->seed >> 32);
+    const uint32_t dom = P->instance & 0xFFFFFFu;   // domain 0: path noise
+    const uint64_t R = P->R;
+    const bool logged = (P->flags & 2u) && (static_cast<uint64_t>(r) - P->log_begin) < P->log_count;
+    const uint32_t n_ckpt = P->n_ckpt;
+
+#pragma unroll
+    for (int j = 0; j < D; ++j) S[j] = 0;
+#pragma unroll
+    for (int j = 0; j <= D; ++j) cnt[j] = 0;
+    uint32_t tau = kTauNone;
+    uint32_t ck = 0;
+    uint64_t next_ckpt = n_ckpt ? P->ckpt[0] : 0;
+    uint32_t epoch = 0, m_in_epoch = 0;   // t = epoch * M + m_in_epoch
+
+    for (uint64_t t = 0; t < T; ++t) {
+        // iterate w_t (scale factor of the signature) and v = sigma .* w_t
+        const double cw = t == 0 ? 0.0 : 2.0 / (static_cast<double>(t) * static_cast<double>(t + 1));
+        const Real cwr = static_cast<Real>(cw);
+        Real v[D], s1[D], s2[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const Real w = (t == 0) ? (P->has_w0 ? C.w0(j) : Real(0)) : static_cast<Real>(S[j]) * cwr;
+            v[j] = (j < d) ? C.sz(j) * w : Real(0);
+            s1[j] = Real(0);
+            s2[j] = Real(0);
+        }
+
+        if constexpr (EXACT && NOISE == 0) {
+            // groups of G samples hold a whole number of Philox blocks: static packing
+            constexpr int G = 4 / gcd_const(D, 4);
+            constexpr int NZ = G * D;
+            constexpr int NB = NZ / 4;
+            const uint32_t full = N / G, rem = N % G;
+            for (uint32_t gi = 0; gi < full; ++gi) {
+                Real z[NZ];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const Block4<Real> q = normals_block<Real>(gi * NB + b, epoch, r, dom, k0, k1);
+                    z[4 * b + 0] = q.z[0];
+                    z[4 * b + 1] = q.z[1];
+                    z[4 * b + 2] = q.z[2];
+                    z[4 * b + 3] = q.z[3];
+                }
+#pragma unroll
+                for (int s = 0; s < G; ++s) {
+                    Real dot = Real(0);
+#pragma unroll
+                    for (int j = 0; j < D; ++j) dot = fma(z[s * D + j], v[j], dot);
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        s1[j] += z[s * D + j];
+                        s2[j] = fma(z[s * D + j], dot, s2[j]);
+                    }
+                }
+            }
+            if (rem) {
+                Real z[NZ];
+                const uint32_t nb_needed = (rem * D + 3) / 4;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    if (static_cast<uint32_t>(b) < nb_needed) {
+                        const Block4<Real> q = normals_block<Real>(full * NB + b, epoch, r, dom, k0, k1);
+                        z[4 * b + 0] = q.z[0];
+                        z[4 * b + 1] = q.z[1];
+                        z[4 * b + 2] = q.z[2];
+                        z[4 * b + 3] = q.z[3];
+                    } else {
+                        z[4 * b + 0] = z[4 * b + 1] = z[4 * b + 2] = z[4 * b + 3] = Real(0);
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < G; ++s) {
+                    if (static_cast<uint32_t>(s) < rem) {
+                        Real dot = Real(0);
+#pragma unroll
+                        for (int j = 0; j < D; ++j) dot = fma(z[s * D + j], v[j], dot);
+#pragma unroll
+                        for (int j = 0; j < D; ++j) {
+                            s1[j] += z[s * D + j];
+                            s2[j] = fma(z[s * D + j], dot, s2[j]);
+                        }
+                    }
+                }
+            }
+        } else {
+            NormalCursor<Real> cur;
+            cur.seek(0u, epoch, r, dom, k0, k1);
+            NormalCursor<Real> ext;
+            if constexpr (NOISE == 1) ext.seek(N * static_cast<uint32_t>(d), epoch, r, dom, k0, k1);
+            for (uint32_t i = 0; i < N; ++i) {
+                Real z[D];
+#pragma unroll
+                for (int j = 0; j < D; ++j) z[j] = (j < d) ? cur.next(epoch, r, dom, k0, k1) : Real(0);
+                if constexpr (NOISE == 1) {
+                    Real ss = Real(0);
+                    for (uint32_t k = 0; k < P->nu; ++k) {
+                        const Real e = ext.next(epoch, r, dom, k0, k1);
+                        ss = fma(e, e, ss);
+                    }
+                    const Real a = C.tscale() * Coef<Real>::rsqrt(ss);
+#pragma unroll
+                    for (int j = 0; j < D; ++j) z[j] *= a;
+                }
+                Real dot = Real(0);
+#pragma unroll
+                for (int j = 0; j < D; ++j) dot = fma(z[j], v[j], dot);
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    s1[j] += z[j];
+                    s2[j] = fma(z[j], dot, s2[j]);
+                }
+            }
+        }
+
+        // gradient, linear subproblem over the vertices of W, Frank-Wolfe gap
+        Real dot1 = Real(0);
+#pragma unroll
+        for (int j = 0; j < D; ++j) dot1 = fma(s1[j], v[j], dot1);
+        const Real qn = dot1 * C.inv_n();
+        Real gmin = Real(0);
+        int jmin = -1;
+        Real gw = Real(0);
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (j < d) {
+                const Real g = C.c2(j) * (s2[j] - s1[j] * qn) - C.mu(j) - C.c1(j) * s1[j];
+                if (jmin < 0 || g < gmin) {
+                    gmin = g;
+                    jmin = j;
+                }
+                const Real w = (t == 0) ? (P->has_w0 ? C.w0(j) : Real(0)) : static_cast<Real>(S[j]) * cwr;
+                gw = fma(g, w, gw);
+            }
+        }
+        const int a = (gmin < Real(0)) ? jmin + 1 : 0;
+        const Real gap = gw - (gmin < Real(0) ? gmin : Real(0));
+        if (tau == kTauNone && gap <= static_cast<Real>(P->gap_eps)) tau = static_cast<uint32_t>(t);
+        if (logged) B.dlog[t * P->log_count + (r - P->log_begin)] = static_cast<uint8_t>(a);
+
+        // step 2/(t+2): the signature absorbs the update
+        const WS tp1 = static_cast<WS>(t + 1);
+        cnt[0] += (a == 0) ? 1u : 0u;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const bool hit = (a == j + 1);
+            S[j] += hit ? tp1 : WS(0);
+            cnt[j + 1] += hit ? 1u : 0u;
+        }
+        if (t + 1 == next_ckpt) {
+            const double c = 2.0 / (static_cast<double>(t + 1) * static_cast<double>(t + 2));
+            B.fck[static_cast<uint64_t>(ck) * R + r] = objective_from_signature<D, EXACT, WS>(P, S, c);
+            ++ck;
+            next_ckpt = ck < n_ckpt ? P->ckpt[ck] : 0;
+        }
+        if (++m_in_epoch == M) {
+            m_in_epoch = 0;
+            ++epoch;
+        }
+    }
+    res.y = objective_from_signature<D, EXACT, WS>(
+        P, S, 2.0 / (static_cast<double>(T) * static_cast<double>(T + 1)));
+    res.tau = tau;
+}
+
+// ---------------------------------------------------------------------------------------------
+// kernel: paths + per-workgroup partials + last-workgroup finalisation
+// ---------------------------------------------------------------------------------------------
+template <int D, bool EXACT, typename Real, int NOISE, typename WS>
+__global__ __launch_bounds__(kBlock) void fw_paths_kernel(const InstanceDesc *__restrict__ P,
+                                                          RunBuffers B)
+{
+    __shared__ double sm_f[2 * (kBlock / 64)];
+    __shared__ uint64_t sm_i[kBlock / 64];
+    __shared__ uint32_t sm_last;
+
+    const uint64_t R = P->R;
+    const uint64_t r = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const bool active = r < R;
+    const int d = EXACT ? D : static_cast<int>(P->d);
+
+    uint32_t cnt[D + 1];
+    WS S[D];
+    LaneResult res{0.0, kTauNone};
+    if (active) {
+        run_path<D, EXACT, Real, NOISE, WS>(P, B, static_cast<uint32_t>(r), cnt, S, res);
+        if (P->flags & 1u) {
+            B.y[r] = res.y;
+            B.tau[r] = res.tau;
+#pragma unroll
+            for (int j = 0; j <= D; ++j)
+                if (j <= d) B.cnt[static_cast<uint64_t>(j) * R + r] = cnt[j];
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                if (j < d) B.wsum[static_cast<uint64_t>(j) * R + r] = static_cast<uint64_t>(S[j]);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j <= D; ++j) cnt[j] = 0;
+    }
+
+    // per-workgroup partials: streams Y, f(w_c), RSE_c
+    const uint32_t nb = B.nblocks;
+    const uint32_t n_ckpt = P->n_ckpt;
+    const uint32_t n_streams = 1 + 2 * n_ckpt;
+    for (uint32_t s = 0; s < n_streams; ++s) {
+        double x = 0.0;
+        bool valid = active;
+        if (active) {
+            if (s == 0) {
+                x = res.y;
+            } else if (s <= n_ckpt) {
+                x = B.fck[static_cast<uint64_t>(s - 1) * R + r];
+            } else {
+                const double f = B.fck[static_cast<uint64_t>(s - 1 - n_ckpt) * R + r];
+                valid = (f != 0.0);
+                const double e = valid ? (f - res.y) / f : 0.0;
+                x = e * e;
+            }
+        }
+        if (!valid) x = 0.0;
+        double h = x, l = 0.0;
+        block_sum_dd(h, l, sm_f);
+        double qh = x * x, ql = fma(x, x, -(x * x));
+        block_sum_dd(qh, ql, sm_f);
+        double ch = valid ? 1.0 : 0.0, cl = 0.0;
+        block_sum_dd(ch, cl, sm_f);
+        if (threadIdx.x == 0) {
+            double *base = B.part_f + static_cast<uint64_t>(s) * kStreamFields * nb + blockIdx.x;
+            store_agent(base + 0 * nb, h);
+            store_agent(base + 1 * nb, l);
+            store_agent(base + 2 * nb, qh);
+            store_agent(base + 3 * nb, ql);
+            store_agent(base + 4 * nb, ch);
+        }
+    }
+    {
+        const double ymin = block_extreme<false>(active ? res.y : INFINITY, sm_f);
+        const double ymax = block_extreme<true>(active ? res.y : -INFINITY, sm_f);
+        if (threadIdx.x == 0) {
+            double *base = B.part_f + static_cast<uint64_t>(n_streams) * kStreamFields * nb + blockIdx.x;
+            store_agent(base, ymin);
+            store_agent(base + nb, ymax);
+        }
+    }
+    for (int j = 0; j <= d; ++j) {
+        uint32_t cj = 0;
+#pragma unroll
+        for (int k = 0; k <= D; ++k)
+            if (k == j) cj = cnt[k];
+        const uint64_t tot = block_sum_u64(cj, sm_i);
+        if (threadIdx.x == 0) store_agent(B.part_i + static_cast<uint64_t>(j) * nb + blockIdx.x, tot);
+    }
+    {
+        const bool hit = active && res.tau != kTauNone;
+        const uint64_t tc = block_sum_u64(hit ? 1u : 0u, sm_i);
+        const uint64_t ts = block_sum_u64(hit ? res.tau : 0u, sm_i);
+        if (threadIdx.x == 0) {
+            store_agent(B.part_i + static_cast<uint64_t>(d + 1) * nb + blockIdx.x, tc);
+            store_agent(B.part_i + static_cast<uint64_t>(d + 2) * nb + blockIdx.x, ts);
+        }
+    }
+
+    // the last workgroup to finish reduces every partial in a fixed order
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t prev = __hip_atomic_fetch_add(B.done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        sm_last = (prev == nb - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (!sm_last) return;
+    __threadfence();
+
+    for (uint32_t s = 0; s < n_streams; ++s) {
+        const double *base = B.part_f + static_cast<uint64_t>(s) * kStreamFields * nb;
+        double h = 0.0, l = 0.0, qh = 0.0, ql = 0.0, ch = 0.0, cl = 0.0;
+        for (uint32_t b = threadIdx.x; b < nb; b += kBlock) {
+            dd_add(h, l, load_agent(base + 0 * nb + b), load_agent(base + 1 * nb + b));
+            dd_add(qh, ql, load_agent(base + 2 * nb + b), load_agent(base + 3 * nb + b));
+            dd_add(ch, cl, load_agent(base + 4 * nb + b), 0.0);
+        }
+        block_sum_dd(h, l, sm_f);
+        block_sum_dd(qh, ql, sm_f);
+        block_sum_dd(ch, cl, sm_f);
+        if (threadIdx.x == 0) {
+            double *o = B.final_f + static_cast<uint64_t>(s) * kStreamFields;
+            o[0] = h;
+            o[1] = l;
+            o[2] = qh;
+            o[3] = ql;
+            o[4] = ch + cl;
+        }
+    }
+    {
+        const double *base = B.part_f + static_cast<uint64_t>(n_streams) * kStreamFields * nb;
+        double mn = INFINITY, mx = -INFINITY;
+        for (uint32_t b = threadIdx.x; b < nb; b += kBlock) {
+            mn = fmin(mn, load_agent(base + b));
+            mx = fmax(mx, load_agent(base + nb + b));
+        }
+        mn = block_extreme<false>(mn, sm_f);
+        mx = block_extreme<true>(mx, sm_f);
+        if (threadIdx.x == 0) {
+            B.final_f[n_streams * kStreamFields] = mn;
+            B.final_f[n_streams * kStreamFields + 1] = mx;
+        }
+    }
+    for (int j = 0; j < d + 3; ++j) {
+        uint64_t x = 0;
+        for (uint32_t b = threadIdx.x; b < nb; b += kBlock) x += load_agent(B.part_i + static_cast<uint64_t>(j) * nb + b);
+        x = block_sum_u64(x, sm_i);
+        if (threadIdx.x == 0) B.final_i[j] = x;
+    }
+    if (threadIdx.x == 0) __hip_atomic_store(B.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------------------------
+// host dispatch over the instantiated shapes
+// ---------------------------------------------------------------------------------------------
+using KernelFn = void (*)(const InstanceDesc *, RunBuffers);
+
+template <int D, bool EXACT, typename Real, int NOISE, typename WS>
+constexpr KernelFn kfn()
+{
+    return &fw_paths_kernel<D, EXACT, Real, NOISE, WS>;
+}
+
+struct KernelChoice {
+    KernelFn fn;
+    int D;
+    bool exact;
+};
+
+// Exact-width kernels pack each group of samples into whole Philox blocks at compile time; the
+// generic ones read the stream through a cursor and take d <= D at run time.
+template <typename Real, typename WS>
+static KernelChoice choose_gauss(uint32_t d)
+{
+    switch (d) {
+    case 1: return {kfn<1, true, Real, 0, WS>(), 1, true};
+    case 2: return {kfn<2, true, Real, 0, WS>(), 2, true};
+    case 3: return {kfn<3, true, Real, 0, WS>(), 3, true};
+    case 4: return {kfn<4, true, Real, 0, WS>(), 4, true};
+    case 5: return {kfn<5, true, Real, 0, WS>(), 5, true};
+    case 6: return {kfn<6, true, Real, 0, WS>(), 6, true};
+    case 8: return {kfn<8, true, Real, 0, WS>(), 8, true};
+    case 10: return {kfn<10, true, Real, 0, WS>(), 10, true};
+    case 12: return {kfn<12, true, Real, 0, WS>(), 12, true};
+    case 16: return {kfn<16, true, Real, 0, WS>(), 16, true};
+    default: break;
+    }
+    if (d <= 16) return {kfn<16, false, Real, 0, WS>(), 16, false};
+    if constexpr (sizeof(Real) == 4)
+        if (d <= 32) return {kfn<32, false, Real, 0, WS>(), 32, false};
+    return {nullptr, 0, false};
+}
+
+template <typename Real, typename WS>
+static KernelChoice choose_t(uint32_t d)
+{
+    if (d <= 8) return {kfn<8, false, Real, 1, WS>(), 8, false};
+    if (d <= 16) return {kfn<16, false, Real, 1, WS>(), 16, false};
+    if constexpr (sizeof(Real) == 4)
+        if (d <= 32) return {kfn<32, false, Real, 1, WS>(), 32, false};
+    return {nullptr, 0, false};
+}
+
+// Returns 0 and launches, or a negative code: -5 unsupported shape, -3 launch failure.
+int launch_fw_paths(const InstanceDesc &host_desc, const InstanceDesc *dev_desc, const RunBuffers &B,
+                    bool fp64, hipStream_t stream, int *kernel_width)
+{
+    const bool wide = host_desc.T > kMaxNarrowT;
+    KernelChoice kc{nullptr, 0, false};
+    if (host_desc.noise == 0) {
+        if (fp64) kc = wide ? choose_gauss<double, uint64_t>(host_desc.d) : choose_gauss<double, uint32_t>(host_desc.d);
+        else kc = wide ? choose_gauss<float, uint64_t>(host_desc.d) : choose_gauss<float, uint32_t>(host_desc.d);
+    } else {
+        if (fp64) kc = wide ? choose_t<double, uint64_t>(host_desc.d) : choose_t<double, uint32_t>(host_desc.d);
+        else kc = wide ? choose_t<float, uint64_t>(host_desc.d) : choose_t<float, uint32_t>(host_desc.d);
+    }
+    if (!kc.fn) return -5;
+    if (kernel_width) *kernel_width = kc.D;
+    hipLaunchKernelGGL(kc.fn, dim3(B.nblocks), dim3(kBlock), 0, stream, dev_desc, B);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+}  // namespace fw

@@ -1,0 +1,230 @@
+"""Thin ctypes binding of the C ABI in include/sim.h (argument marshalling only).
+
+Every step of the simulation runs in the HIP library ``libsim.so`` next to this file; if that
+library has not been built, loading it raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsim.so")
+
+ABI_VERSION = 1
+MAX_D = 64
+MAX_CKPT = 8
+TAU_NONE = 0xFFFFFFFF
+NOISE_GAUSS, NOISE_T = 0, 1
+FP32, FP64 = 0, 1
+KEEP_PATHS, DECISION_LOG = 1, 2
+STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EUNSUPPORTED"}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class SimParams(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("d", ctypes.c_uint32), ("mu", _dp),
+                ("sigma", _dp), ("chol", _dp), ("risk_coef", ctypes.c_double), ("w0", _dp),
+                ("n_samples", ctypes.c_uint32), ("resample_every", ctypes.c_uint32),
+                ("noise", ctypes.c_uint32), ("nu", ctypes.c_uint32),
+                ("state_precision", ctypes.c_uint32), ("n_checkpoints", ctypes.c_uint32),
+                ("checkpoints", ctypes.c_uint64 * MAX_CKPT), ("gap_eps", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("instance_id", ctypes.c_uint32),
+                ("log_rep_begin", ctypes.c_uint64), ("log_rep_count", ctypes.c_uint64)]
+
+
+class SimStats(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_uint64), ("T", ctypes.c_uint64), ("mean", ctypes.c_double),
+                ("var", ctypes.c_double), ("ci95_halfwidth", ctypes.c_double),
+                ("min", ctypes.c_double), ("max", ctypes.c_double), ("f_star", ctypes.c_double),
+                ("n_checkpoints", ctypes.c_uint32), ("pad_", ctypes.c_uint32),
+                ("checkpoints", ctypes.c_uint64 * MAX_CKPT),
+                ("f_mean", ctypes.c_double * MAX_CKPT), ("f_sd", ctypes.c_double * MAX_CKPT),
+                ("rse_mean", ctypes.c_double * MAX_CKPT), ("rse_sd", ctypes.c_double * MAX_CKPT),
+                ("rse_undefined", ctypes.c_uint64 * MAX_CKPT),
+                ("decision_total", ctypes.c_uint64 * (MAX_D + 1)),
+                ("tau_count", ctypes.c_uint64), ("tau_mean", ctypes.c_double),
+                ("kernel_ms", ctypes.c_double), ("path_steps_per_s", ctypes.c_double)]
+
+
+class SimPathView(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_uint64), ("T", ctypes.c_uint64), ("d", ctypes.c_uint32),
+                ("n_checkpoints", ctypes.c_uint32), ("y", ctypes.c_void_p),
+                ("f_ckpt", ctypes.c_void_p), ("cnt", ctypes.c_void_p), ("wsum", ctypes.c_void_p),
+                ("tau", ctypes.c_void_p), ("decisions", ctypes.c_void_p),
+                ("log_rep_begin", ctypes.c_uint64), ("log_rep_count", ctypes.c_uint64)]
+
+
+#: every symbol include/sim.h declares
+EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_stats", "sim_paths",
+           "sim_copy_to_host", "sim_strerror", "sim_last_error", "sim_destroy")
+
+_lib = None
+
+
+def load():
+    """Loads libsim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is missing: run python -m paper_2404_11631_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.sim_create.argtypes = [ctypes.c_int, vp, ctypes.POINTER(vp)]
+        L.sim_set_stream.argtypes = [vp, vp]
+        L.sim_run.argtypes = [vp, ctypes.POINTER(SimParams), ctypes.c_uint64, ctypes.c_uint64,
+                              ctypes.c_uint64]
+        L.sim_validate.argtypes = [ctypes.POINTER(SimParams), ctypes.c_uint64, ctypes.c_uint64,
+                                   ctypes.c_char_p, ctypes.c_size_t]
+        L.sim_stats.argtypes = [vp, ctypes.POINTER(SimStats)]
+        L.sim_paths.argtypes = [vp, ctypes.POINTER(SimPathView)]
+        L.sim_copy_to_host.argtypes = [vp, vp, vp, ctypes.c_size_t]
+        L.sim_strerror.argtypes = [ctypes.c_int]
+        L.sim_strerror.restype = ctypes.c_char_p
+        L.sim_last_error.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+        L.sim_destroy.argtypes = [vp]
+        L.sim_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+class SimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+@dataclass
+class Problem:
+    """One instance of problem Eq. (3) and the knobs of Algorithm 1."""
+    mu: np.ndarray
+    sigma: np.ndarray | None = None
+    chol: np.ndarray | None = None
+    N: int = 10
+    M: int = 1
+    lam: float = 0.5
+    w0: np.ndarray | None = None
+    noise: int = NOISE_GAUSS
+    nu: int = 3
+    precision: int = FP32
+    checkpoints: tuple = ()
+    gap_eps: float = 1e-2
+    keep_paths: bool = False
+    log_reps: tuple | None = None      # (begin, count) of replications whose decisions are logged
+    instance_id: int = 0
+
+
+def validate(p: Problem, R: int, T: int):
+    """(code, message) of the checks sim_run applies, without a device."""
+    sp, keep = Sim.params(p)
+    buf = ctypes.create_string_buffer(512)
+    rc = load().sim_validate(ctypes.byref(sp), R, T, buf, 512)
+    return rc, buf.value.decode()
+
+
+class Sim:
+    """A context on one device; ``run`` launches asynchronously, ``stats``/``paths`` synchronise."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.L = load()
+        h = ctypes.c_void_p()
+        rc = self.L.sim_create(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        if rc:
+            raise SimError(rc, self.L.sim_strerror(rc).decode())
+        self.h = h
+        self._keep = None
+
+    def close(self):
+        if self.h:
+            self.L.sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc:
+            buf = ctypes.create_string_buffer(512)
+            self.L.sim_last_error(self.h, buf, 512)
+            raise SimError(rc, buf.value.decode())
+
+    def set_stream(self, stream):
+        self._check(self.L.sim_set_stream(self.h, ctypes.c_void_p(stream) if stream else None))
+
+    @staticmethod
+    def params(p: Problem) -> tuple:
+        mu = np.ascontiguousarray(p.mu, dtype=np.float64)
+        keep = [mu]
+        sp = SimParams()
+        sp.abi_version = ABI_VERSION
+        sp.d = mu.shape[0]
+        sp.mu = mu.ctypes.data_as(_dp)
+        if p.sigma is not None:
+            s = np.ascontiguousarray(p.sigma, dtype=np.float64)
+            keep.append(s)
+            sp.sigma = s.ctypes.data_as(_dp)
+        if p.chol is not None:
+            c = np.ascontiguousarray(p.chol, dtype=np.float64)
+            keep.append(c)
+            sp.chol = c.ctypes.data_as(_dp)
+        if p.w0 is not None:
+            w = np.ascontiguousarray(p.w0, dtype=np.float64)
+            keep.append(w)
+            sp.w0 = w.ctypes.data_as(_dp)
+        sp.risk_coef = p.lam
+        sp.n_samples = p.N
+        sp.resample_every = p.M
+        sp.noise = p.noise
+        sp.nu = p.nu
+        sp.state_precision = p.precision
+        sp.n_checkpoints = len(p.checkpoints)      # the library rejects more than MAX_CKPT
+        for i, c in enumerate(p.checkpoints[:MAX_CKPT]):
+            sp.checkpoints[i] = int(c)
+        sp.gap_eps = p.gap_eps
+        sp.flags = (KEEP_PATHS if p.keep_paths else 0) | (DECISION_LOG if p.log_reps else 0)
+        sp.instance_id = p.instance_id
+        if p.log_reps:
+            sp.log_rep_begin, sp.log_rep_count = int(p.log_reps[0]), int(p.log_reps[1])
+        return sp, keep
+
+    def run(self, p: Problem, R: int, T: int, seed: int):
+        sp, keep = self.params(p)
+        self._keep = keep
+        self._check(self.L.sim_run(self.h, ctypes.byref(sp), R, T, seed))
+
+    def stats(self) -> SimStats:
+        st = SimStats()
+        self._check(self.L.sim_stats(self.h, ctypes.byref(st)))
+        return st
+
+    def _copy(self, ptr, dtype, count):
+        out = np.empty(count, dtype=dtype)
+        if count:
+            self._check(self.L.sim_copy_to_host(self.h, out.ctypes.data_as(ctypes.c_void_p),
+                                                ctypes.c_void_p(ptr), out.nbytes))
+        return out
+
+    def paths(self) -> dict:
+        v = SimPathView()
+        self._check(self.L.sim_paths(self.h, ctypes.byref(v)))
+        R, d, nc = v.R, v.d, v.n_checkpoints
+        out = {"R": R, "T": v.T, "d": d}
+        if v.y:
+            out["y"] = self._copy(v.y, np.float64, R)
+            out["cnt"] = self._copy(v.cnt, np.uint32, (d + 1) * R).reshape(d + 1, R)
+            out["wsum"] = self._copy(v.wsum, np.uint64, d * R).reshape(d, R)
+            out["tau"] = self._copy(v.tau, np.uint32, R)
+        if v.f_ckpt:
+            out["f_ckpt"] = self._copy(v.f_ckpt, np.float64, nc * R).reshape(nc, R)
+        if v.decisions:
+            n = v.log_rep_count
+            out["decisions"] = self._copy(v.decisions, np.uint8, v.T * n).reshape(v.T, n)
+            out["log_rep_begin"] = v.log_rep_begin
+        return out

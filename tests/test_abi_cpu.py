@@ -1,0 +1,128 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol include/sim.h declares, the
+ctypes layouts match the header, and host-side validation rejects what the header says it does."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2404_11631_amd import sim
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sim.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(sim_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(sim.LIB_PATH):
+        pytest.skip("libsim.so not built")
+    return sim.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = header_functions()
+    assert set(declared) == set(sim.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+    nm = subprocess.run(["nm", "-D", "--defined-only", sim.LIB_PATH], capture_output=True, text=True)
+    if nm.returncode == 0:
+        for name in declared:
+            assert re.search(rf"\bT {name}\b", nm.stdout), name
+
+
+def test_struct_layout_matches_header():
+    """sizeof/offsetof from a C compile of the header equal the ctypes mirrors."""
+    fields = {
+        "sim_params": [f[0] for f in sim.SimParams._fields_],
+        "sim_stats_out": [f[0] for f in sim.SimStats._fields_],
+        "sim_path_view": [f[0] for f in sim.SimPathView._fields_],
+    }
+    mirrors = {"sim_params": sim.SimParams, "sim_stats_out": sim.SimStats,
+               "sim_path_view": sim.SimPathView}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
+    for st, fs in fields.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0;}")
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "layout.c")
+        open(src, "w").write("\n".join(lines))
+        exe = os.path.join(d, "layout")
+        subprocess.check_call(["gcc", "-std=c11", "-Wall", "-o", exe, src])
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(line.split() for line in out if line)
+    for st, cls in mirrors.items():
+        assert int(got[st]) == ctypes.sizeof(cls), st
+        for f in fields[st]:
+            assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, (st, f)
+
+
+def test_strerror(lib):
+    assert lib.sim_strerror(0) == b"ok"
+    assert lib.sim_strerror(-1) == b"invalid argument"
+    assert lib.sim_strerror(-5) == b"unsupported combination"
+    assert lib.sim_strerror(-99) == b"unknown error"
+
+
+def _ok_problem(**kw):
+    base = dict(mu=np.array([0.3, 0.6]), sigma=np.array([0.5, 0.2]), N=4, checkpoints=(5, 10))
+    base.update(kw)
+    return sim.Problem(**base)
+
+
+@pytest.mark.parametrize("kw,R,T,code", [
+    ({}, 100, 10, 0),
+    ({}, 0, 10, -1),                                   # R >= 1
+    ({}, 2 ** 32, 10, -1),                             # R < 2^32
+    ({}, 10, 0, -1),                                   # T >= 1
+    ({"N": 1}, 10, 10, -1),                            # Eq. (4) needs N >= 2
+    ({"M": 0}, 10, 10, -1),
+    ({"lam": 0.0}, 10, 10, -1),
+    ({"lam": float("nan")}, 10, 10, -1),
+    ({"sigma": np.array([0.5, -0.1])}, 10, 10, -1),
+    ({"mu": np.array([0.3, np.inf])}, 10, 10, -1),
+    ({"w0": np.array([0.7, 0.4])}, 10, 10, -1),        # outside W
+    ({"w0": np.array([-0.1, 0.4])}, 10, 10, -1),
+    ({"w0": np.array([0.5, 0.5])}, 10, 10, 0),          # on the face 1'w = 1
+    ({"checkpoints": (10, 5)}, 10, 10, -1),            # strictly increasing
+    ({"checkpoints": (0,)}, 10, 10, -1),
+    ({"checkpoints": (11,)}, 10, 10, -1),              # <= T
+    ({"checkpoints": tuple(range(1, 10))}, 10, 10, -1),  # at most 8
+    ({"noise": sim.NOISE_T, "nu": 2}, 10, 10, -1),
+    ({"noise": 7}, 10, 10, -1),
+    ({"precision": 3}, 10, 10, -1),
+    ({"gap_eps": -1.0}, 10, 10, -1),
+    ({"instance_id": 1 << 24}, 10, 10, -1),
+    ({"log_reps": (5, 10)}, 10, 10, -1),               # beyond R
+    ({"log_reps": (0, 10)}, 10, 10, 0),
+    ({"chol": np.eye(2)}, 10, 10, -5),                  # dense factors not in sim_run
+])
+def test_validation(lib, kw, R, T, code):
+    rc, msg = sim.validate(_ok_problem(**kw), R, T)
+    assert rc == code, msg
+    if code:
+        assert msg
+
+
+def test_validation_d_range(lib):
+    rc, _ = sim.validate(sim.Problem(mu=np.zeros(65), sigma=np.ones(65)), 10, 10)
+    assert rc == -1
+
+
+def test_create_without_gpu_fails_cleanly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert lib.sim_create(0, None, ctypes.byref(h)) == -3
+    assert not h.value
