@@ -21,19 +21,18 @@ if ROOT not in sys.path:
 
 METRIC = "path-steps/sec and wall time to 95% CI half-width 1e-3, plain vs CV, 1 MI355X"
 
-# Issue-slot roofline of the path: each normal costs 5 wide 32x32->64 integer
-# products and 10 xors (Philox4x32-10, 10 rounds per 4 normals), 2 transcendentals (Box-Muller:
-# log2, sqrt, sin, cos per pair), 3 uniform-map ops and 3 accumulation ops; each iteration adds
-# ~15 d ops for gradient, linear subproblem and update. Costs in issue slots, measured on gfx950:
-SLOT_MAD64 = 4.0     # v_mad_u64_u32
-SLOT_TRANS = 4.0     # v_log_f32, v_sqrt_f32, v_sin_f32, v_cos_f32
-SLOT_SIMPLE = 1.0
-PEAK_SLOTS = 256 * 64 * 2.4e9   # 256 CUs x 64 lanes x 2.4 GHz: one 32-bit VALU op per lane per clock
+# ALU roofline. Algorithmic 32-bit VALU lane-operations per standard normal:
+# Philox4x32-10 (10 rounds x (2 wide products + 4 xors) per 4 normals) = 15, uniform map = 2,
+# Box-Muller (log2, sqrt, sin, cos, 2 products per pair) = 3, one-pass sample statistics
+# (dot FMA, sum, FMA) = 3; per iteration ~15 d more for gradient, linear subproblem and update.
+OPS_PER_NORMAL = 15 + 2 + 3 + 3
+OPS_PER_ASSET_STEP = 15
+# 256 CUs x 2.4 GHz x 128 lane-ops/clock: the FP32 vector rate 157.3 TFLOP/s at 2 flops per FMA
+PEAK_OPS = 256 * 2.4e9 * 128
 
 
-def slots_per_path_step(d: int, N: int) -> float:
-    per_normal = 5 * SLOT_MAD64 + 2 * SLOT_TRANS + (10 + 3 + 3) * SLOT_SIMPLE
-    return N * d * per_normal + 15 * d * SLOT_SIMPLE
+def ops_per_path_step(d: int, N: int) -> float:
+    return OPS_PER_NORMAL * N * d + OPS_PER_ASSET_STEP * d
 
 
 def cpu_baseline(w, mu, sigma, seconds: float):
@@ -106,7 +105,7 @@ def main():
 
     ms_step = 1e3 * wall / args.steps
     kavg = sum(kernel_ms) / len(kernel_ms)
-    alg = slots_per_path_step(d, N) * R * T
+    alg = ops_per_path_step(d, N) * R * T
     achieved = alg / (kavg * 1e-3)
     line = {
         "metric": METRIC,
@@ -124,9 +123,9 @@ def main():
         "config": {"workload": "paper_scale", "R": R, "T": T, "d": d, "N": N, "M": w["M"],
                    "state": "fp32", "statistics": "fp64 double-double", "seed": seed,
                    "launch": "one fused kernel per step"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOTS / 1e12,
-                     "unit": "Tslot/s", "frac": achieved / PEAK_SLOTS, "traffic": None,
-                     "kernel_ms": kavg},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12,
+                     "unit": "TOP/s", "frac": achieved / PEAK_OPS, "traffic": None,
+                     "kernel_ms": kavg, "ops_per_path_step": ops_per_path_step(d, N)},
         "stats": {"mean": st.mean, "ci95_halfwidth": st.ci95_halfwidth, "f_star": st.f_star},
     }
     if not args.no_cpu_baseline:

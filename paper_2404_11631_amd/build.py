@@ -43,6 +43,11 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     subprocess.check_call([hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)
+    # stand-alone issue-rate probe behind the ALU roofline figures
+    probe = os.path.join(HERE, "valu_rate_probe")
+    subprocess.check_call([hipcc(), "--offload-arch=" + ARCH, "-O3", "-o", probe + ".tmp",
+                           os.path.join(HERE, "csrc", "valu_rate_probe.hip")])
+    os.replace(probe + ".tmp", probe)
     return LIB
 
 

@@ -156,32 +156,29 @@ def test_errors_on_device(ctx):
 
 def test_paper_scale_full_size(ctx):
     """The paper-scale workload at full size (R=1e6, T=1e4, d=10, N=10, FP32) in the launch the
-    benchmark times, checked on sampled replications against the oracle and by exact properties
+    benchmark times: replications of the first workgroup, a middle one and the ragged last one
+    are checked against the oracle with their logged decisions, and exact properties are checked
     over all replications."""
     w = workloads.WORKLOADS["paper_scale"]
     R, T, seed = w["R"], w["T"], w["seed"]
     mu, sigma = workloads.diag_instance(seed, 0, w["d"])
-    n_log = 48
-    p = sim.Problem(mu=mu, sigma=sigma, N=w["N"], checkpoints=w["checkpoints"], keep_paths=True,
-                    log_reps=(R - n_log, n_log))
-    say(f"[parity] paper_scale R={R} T={T}")
-    ctx.run(p, R, T, seed)
-    st = ctx.stats()
-    g = ctx.paths()
-    say(f"[parity] kernel {st.kernel_ms:.1f} ms, {st.path_steps_per_s:.3e} path-steps/s")
-    P = parity.oracle_problem(p, seed)
-    # the logged tail (the ragged last workgroup) with decision replay
-    for k in range(n_log):
-        r = R - n_log + k
-        parity.check_rep(P, g, r, T, oracle.U32, decisions=g["decisions"][:, k])
-    # sampled replications without logs: exact agreement wherever the oracle sees no ambiguity
-    rng = np.random.default_rng(0)
-    checked = 0
-    for r in rng.choice(R - n_log, 24, replace=False):
-        if parity.check_rep(P, g, int(r), T, oracle.U32, require_unambiguous=True) is not None:
-            checked += 1
-    assert checked >= 12
-    # exact properties over all replications
+    n_log = 32
+    P = None
+    replayed = 0
+    for begin in (0, R // 2 - 7, R - n_log):
+        p = sim.Problem(mu=mu, sigma=sigma, N=w["N"], checkpoints=w["checkpoints"], keep_paths=True,
+                        log_reps=(begin, n_log))
+        say(f"[parity] paper_scale R={R} T={T} logged [{begin}, {begin + n_log})")
+        ctx.run(p, R, T, seed)
+        st = ctx.stats()
+        g = ctx.paths()
+        say(f"[parity] kernel {st.kernel_ms:.1f} ms, {st.path_steps_per_s:.3e} path-steps/s")
+        P = P or parity.oracle_problem(p, seed)
+        for k in range(n_log):
+            o = parity.check_rep(P, g, begin + k, T, oracle.U32, decisions=g["decisions"][:, k])
+            replayed += o.n_replayed
+    say(f"[parity] replayed ambiguous decisions over {3 * n_log} paths: {replayed}")
+    # exact properties over all replications (the last run)
     Y = g["y"]
     assert np.all(g["cnt"].sum(axis=0) == T)
     assert math.isclose(st.mean, math.fsum(Y) / R, rel_tol=1e-14)
