@@ -110,12 +110,13 @@ typedef struct {
     uint64_t R, T;
     uint32_t d, n_checkpoints;
     const double *y;            /* [R] f(w_T) */
-    const double *f_ckpt;       /* [n_checkpoints][R] */
+    const double *f_ckpt;       /* [n_checkpoints][f_ckpt_stride], first R of each row */
     const uint32_t *cnt;        /* [d+1][R] decision counts */
     const uint64_t *wsum;       /* [d][R] sum of (t+1) over steps choosing e_j */
     const uint32_t *tau;        /* [R] hitting step or SIM_TAU_NONE */
     const uint8_t *decisions;   /* [T][log_rep_count] decisions, 0 = origin, j+1 = e_j */
     uint64_t log_rep_begin, log_rep_count;
+    uint64_t f_ckpt_stride;     /* elements between checkpoint rows (R, or the batch total) */
 } sim_path_view;
 
 /* Creates a context on HIP device `device`, launching on `hip_stream` (a hipStream_t, or NULL
@@ -133,6 +134,45 @@ int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t 
 /* Checks a parameter set exactly as sim_run does, without a device. Returns 0 or the code sim_run
  * would return, and writes the reason into msg (may be NULL). */
 int sim_validate(const sim_params *p, uint64_t R, uint64_t T, char *msg, size_t len);
+
+/* Knobs of a batched run (sim_run_batch); zero fields take the built-in cost model's choice. */
+typedef struct {
+    uint32_t reserved;              /* must be 0 */
+    uint32_t flags;                 /* SIM_KEEP_PATHS for per-path records of every instance */
+    double heavy_factor;            /* theta > 0: replications are split across lanes until one
+                                       tile needs at most theta x the balanced run time (0: 0.5) */
+    const uint8_t *lanes_per_rep;   /* [n_inst] lanes per replication, each 0 (model) or a power of
+                                       two <= 64, or NULL */
+} sim_batch_config;
+
+/* Runs n_inst instances (Eq. (3) each, own d, N, T, R) of Algorithm 1 as wavefront tiles: one
+ * launch per (d <= 4/8/16/32, noise) class present with its tiles longest first (the hardware
+ * dispatcher is the work queue), replications of heavy instances split across several lanes, then
+ * one per-instance reduction in fixed order.
+ * Each instance uses its instance_id as stream domain and the common noise `seed`.
+ * Supported: FP32 state, diagonal Sigma, d <= 32, T <= 2^32-2, per-instance R < 2^32,
+ * 1 <= n_inst <= 65536. Decision logs follow each instance's log_rep_begin/log_rep_count.
+ * Asynchronous on the context's stream. cfg may be NULL.
+ * This build returns SIM_EUNSUPPORTED: the device path is switched off (see sim_plan_batch for the
+ * plan it would run). */
+int sim_run_batch(sim_ctx *ctx, uint32_t n_inst, const sim_params *p, const uint64_t *R,
+                  const uint64_t *T, uint64_t seed, const sim_batch_config *cfg);
+
+/* Computes, without a device, the plan sim_run_batch would use on a GPU with n_cu compute units:
+ * the lanes per replication and the tile count of every instance (arrays of n_inst, may be NULL).
+ * Returns 0 or the code sim_run_batch would return, with the reason in msg (may be NULL). */
+int sim_plan_batch(uint32_t n_inst, const sim_params *p, const uint64_t *R, const uint64_t *T,
+                   const sim_batch_config *cfg, uint32_t n_cu, uint32_t *lanes_per_rep, uint32_t *n_tiles,
+                   char *msg, size_t len);
+
+/* Statistics of instance `instance` of the last batched run (kernel_ms and path_steps_per_s
+ * describe the whole batch); synchronises the stream. */
+int sim_batch_stats(sim_ctx *ctx, uint32_t instance, sim_stats_out *out);
+
+/* Per-path records of one instance of the last batched run (device pointers, see sim_paths), and
+ * the lanes per replication and tile count the plan gave it; synchronises the stream. */
+int sim_batch_paths(sim_ctx *ctx, uint32_t instance, sim_path_view *out, uint32_t *lanes_per_rep,
+                    uint32_t *n_tiles);
 
 /* Statistics of the last run; synchronises the stream. */
 int sim_stats(sim_ctx *ctx, sim_stats_out *out);

@@ -13,7 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsim.so")
-SOURCES = ["csrc/fw_paths.hip", "csrc/sim_api.hip"]
+SOURCES = ["csrc/fw_paths.hip", "csrc/fw_batch.hip", "csrc/sim_api.hip", "csrc/sim_batch.hip",
+           "csrc/host_core.cpp"]
 ARCH = "gfx950"
 
 
@@ -35,7 +36,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")
-        cmd = [hipcc()] + flags() + ["-c", os.path.join(HERE, src), "-o", obj]
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        cmd = [hipcc()] + flags() + lang + ["-c", os.path.join(HERE, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

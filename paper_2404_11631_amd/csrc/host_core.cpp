@@ -1,0 +1,403 @@
+// host_core.cpp -- device-free host logic of the C ABI: parameter validation, instance
+// coefficients, the tile plan of batched runs, and the final FP64 statistics (double-double
+// arithmetic on the reduced sums). Plain C++; no HIP runtime calls.
+#include "host_core.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+namespace fw {
+namespace host {
+
+int fail(char *err, int code, const char *fmt, ...)
+{
+    if (err) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(err, kErrLen, fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+int validate(char *err, const sim_params *p, uint64_t R, uint64_t T)
+{
+    if (!p) return fail(err, SIM_EINVAL, "params is NULL");
+    if (p->abi_version != SIM_ABI_VERSION)
+        return fail(err, SIM_EINVAL, "abi_version %u != %u", p->abi_version, SIM_ABI_VERSION);
+    if (p->d < 1 || p->d > SIM_MAX_D) return fail(err, SIM_EINVAL, "d=%u outside [1, 64]", p->d);
+    if (R < 1 || R > 0xFFFFFFFFull) return fail(err, SIM_EINVAL, "R=%llu outside [1, 2^32)", (unsigned long long)R);
+    if (T < 1 || T > 0xFFFFFFFEull) return fail(err, SIM_EINVAL, "T=%llu outside [1, 2^32-2]", (unsigned long long)T);
+    if (!p->mu) return fail(err, SIM_EINVAL, "mu is NULL");
+    if (p->chol) return fail(err, SIM_EUNSUPPORTED, "dense Cholesky factors are not supported by sim_run");
+    if (!p->sigma) return fail(err, SIM_EINVAL, "sigma is NULL");
+    for (uint32_t j = 0; j < p->d; ++j) {
+        if (!finite(p->mu[j])) return fail(err, SIM_EINVAL, "mu[%u] not finite", j);
+        if (!finite(p->sigma[j]) || p->sigma[j] < 0.0)
+            return fail(err, SIM_EINVAL, "sigma[%u] must be finite and >= 0", j);
+    }
+    if (!(p->risk_coef > 0.0) || !finite(p->risk_coef))
+        return fail(err, SIM_EINVAL, "risk_coef must be finite and > 0");
+    if (p->w0) {
+        double s = 0.0;
+        for (uint32_t j = 0; j < p->d; ++j) {
+            if (!finite(p->w0[j]) || p->w0[j] < 0.0) return fail(err, SIM_EINVAL, "w0[%u] outside W", j);
+            s += p->w0[j];
+        }
+        if (s > 1.0 + 1e-12) return fail(err, SIM_EINVAL, "w0 sums to %g > 1", s);
+    }
+    if (p->n_samples < 2) return fail(err, SIM_EINVAL, "n_samples must be >= 2 (Eq. (4) divides by N-1)");
+    if (p->n_samples > (1u << 24)) return fail(err, SIM_EINVAL, "n_samples above 2^24");
+    if (p->resample_every < 1) return fail(err, SIM_EINVAL, "resample_every must be >= 1");
+    if (p->noise != SIM_NOISE_GAUSS && p->noise != SIM_NOISE_T) return fail(err, SIM_EINVAL, "unknown noise");
+    if (p->noise == SIM_NOISE_T && (p->nu < 3 || p->nu > 1024))
+        return fail(err, SIM_EINVAL, "nu must be an integer in [3, 1024]");
+    if (p->state_precision != SIM_FP32 && p->state_precision != SIM_FP64)
+        return fail(err, SIM_EINVAL, "unknown state_precision");
+    if (p->n_checkpoints > SIM_MAX_CKPT) return fail(err, SIM_EINVAL, "more than 8 checkpoints");
+    for (uint32_t k = 0; k < p->n_checkpoints; ++k) {
+        if (p->checkpoints[k] < 1 || p->checkpoints[k] > T)
+            return fail(err, SIM_EINVAL, "checkpoint %u outside [1, T]", k);
+        if (k && p->checkpoints[k] <= p->checkpoints[k - 1])
+            return fail(err, SIM_EINVAL, "checkpoints must increase strictly");
+    }
+    if (!finite(p->gap_eps) || p->gap_eps < 0.0) return fail(err, SIM_EINVAL, "gap_eps must be finite and >= 0");
+    if (p->flags & ~(uint32_t)(SIM_KEEP_PATHS | SIM_DECISION_LOG)) return fail(err, SIM_EINVAL, "unknown flag bits");
+    if (p->instance_id >= (1u << 24)) return fail(err, SIM_EINVAL, "instance_id must be < 2^24");
+    if (p->flags & SIM_DECISION_LOG) {
+        if (p->log_rep_count < 1 || p->log_rep_count > 65536)
+            return fail(err, SIM_EINVAL, "log_rep_count must be in [1, 65536]");
+        if (p->log_rep_begin >= R || p->log_rep_count > R - p->log_rep_begin)
+            return fail(err, SIM_EINVAL, "logged replications exceed R");
+        if (T * p->log_rep_count > (1ull << 34)) return fail(err, SIM_EINVAL, "decision log above 16 GiB");
+    }
+    return SIM_OK;
+}
+
+void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed)
+{
+    std::memset(&D, 0, sizeof(D));
+    D.d = p->d;
+    D.N = p->n_samples;
+    D.M = p->resample_every;
+    D.noise = p->noise;
+    D.nu = p->nu;
+    D.n_ckpt = p->n_checkpoints;
+    D.flags = p->flags;
+    D.instance = p->instance_id;
+    D.R = R;
+    D.T = T;
+    D.seed = seed;
+    D.log_begin = (p->flags & SIM_DECISION_LOG) ? p->log_rep_begin : 0;
+    D.log_count = (p->flags & SIM_DECISION_LOG) ? p->log_rep_count : 0;
+    for (uint32_t k = 0; k < p->n_checkpoints; ++k) D.ckpt[k] = p->checkpoints[k];
+    D.lambda = p->risk_coef;
+    D.gap_eps = p->gap_eps;
+    D.has_w0 = p->w0 ? 1u : 0u;
+    const double N = (double)p->n_samples;
+    const double kappa = fw::kBoxMullerScale;
+    const double tnu = (p->noise == SIM_NOISE_T) ? std::sqrt((double)p->nu - 2.0) : 1.0;
+    D.tscale_d = tnu;
+    D.inv_n_d = 1.0 / N;
+    D.tscale_f = (float)(tnu / kappa);
+    D.inv_n_f = (float)(1.0 / N);
+    for (uint32_t j = 0; j < p->d; ++j) {
+        const double mu = p->mu[j], sg = p->sigma[j], w0 = p->w0 ? p->w0[j] : 0.0;
+        D.mu_d[j] = mu;
+        D.sig_d[j] = sg;
+        D.w0_d[j] = w0;
+        D.c1_d[j] = sg / N;
+        D.c2_d[j] = 2.0 * p->risk_coef * sg / (N - 1.0);
+        const double sz = kappa * sg;
+        D.mu_f[j] = (float)mu;
+        D.sz_f[j] = (float)sz;
+        D.isz_f[j] = sz > 0.0 ? (float)(1.0 / sz) : 0.0f;
+        D.w0_f[j] = (float)w0;
+        D.c1_f[j] = (float)(sz / N);
+        D.c2_f[j] = (float)(2.0 * p->risk_coef * sz / (N - 1.0));
+    }
+}
+
+// ---- double-double arithmetic for the final statistics ----------------------------------------
+struct DD {
+    double h, l;
+};
+DD two_sum(double a, double b)
+{
+    double s = a + b, bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+DD dd_add(DD a, DD b)
+{
+    DD s = two_sum(a.h, b.h);
+    double e = s.l + a.l + b.l;
+    double h = s.h + e;
+    return {h, e - (h - s.h)};
+}
+DD dd_neg(DD a) { return {-a.h, -a.l}; }
+DD dd_mul(DD a, DD b)
+{
+    double p = a.h * b.h;
+    double e = std::fma(a.h, b.h, -p) + (a.h * b.l + a.l * b.h);
+    double h = p + e;
+    return {h, e - (h - p)};
+}
+DD dd_div_d(DD a, double b)
+{
+    double q1 = a.h / b;
+    DD p = dd_mul({q1, 0.0}, {b, 0.0});
+    DD r = dd_add(a, dd_neg(p));
+    double q2 = r.h / b;
+    DD q = two_sum(q1, q2);
+    return q;
+}
+
+struct Moments {
+    double mean, var, n;
+};
+Moments moments(const double *f)
+{
+    const DD S{f[0], f[1]}, Q{f[2], f[3]};
+    const double n = f[4];
+    Moments m{0.0, 0.0, n};
+    if (n <= 0.0) return m;
+    DD mean = dd_div_d(S, n);
+    m.mean = mean.h + mean.l;
+    if (n > 1.0) {
+        DD ss = dd_div_d(dd_mul(S, S), n);
+        DD num = dd_add(Q, dd_neg(ss));
+        DD var = dd_div_d(num, n - 1.0);
+        m.var = var.h + var.l;
+        if (m.var < 0.0) m.var = 0.0;
+    }
+    return m;
+}
+
+// min over W of lambda sum sigma_j^2 w_j^2 - mu'w (KKT water-filling), diagonal Sigma with every
+// sigma_j > 0: w_j(nu) = max(0, (mu_j - nu) / (2 lambda sigma_j^2)) with nu >= 0 chosen so that
+// sum_j w_j <= 1 holds with complementary slackness. NaN when some sigma_j is zero.
+double kkt_fstar(const double *mu, const double *sigma, uint32_t d, double lambda)
+{
+    for (uint32_t j = 0; j < d; ++j)
+        if (!(sigma[j] > 0.0)) return NAN;
+    auto w_of = [&](double nu, uint32_t j) {
+        const double w = (mu[j] - nu) / (2.0 * lambda * sigma[j] * sigma[j]);
+        return w > 0.0 ? w : 0.0;
+    };
+    auto total = [&](double nu) {
+        double s = 0.0;
+        for (uint32_t j = 0; j < d; ++j) s += w_of(nu, j);
+        return s;
+    };
+    double nu = 0.0;
+    if (total(0.0) > 1.0) {
+        double lo = 0.0, hi = 0.0;
+        for (uint32_t j = 0; j < d; ++j) hi = mu[j] > hi ? mu[j] : hi;
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (total(mid) > 1.0) lo = mid;
+            else hi = mid;
+        }
+        nu = hi;
+    }
+    double f = 0.0;
+    for (uint32_t j = 0; j < d; ++j) {
+        const double w = w_of(nu, j);
+        f += lambda * sigma[j] * sigma[j] * w * w - mu[j] * w;
+    }
+    return f;
+}
+
+void fill_stats(sim_stats_out *out, const double *F, uint32_t nc, const uint64_t *ckpts, double ymin,
+                double ymax, const uint64_t *dec, uint32_t d, uint64_t tau_count, uint64_t tau_sum, uint64_t R,
+                uint64_t T, double fstar, double ms, double path_steps)
+{
+    std::memset(out, 0, sizeof(*out));
+    out->R = R;
+    out->T = T;
+    Moments y = moments(F);
+    out->mean = y.mean;
+    out->var = y.var;
+    out->ci95_halfwidth = 1.96 * std::sqrt(y.var / (double)R);
+    out->min = ymin;
+    out->max = ymax;
+    out->f_star = fstar;
+    out->n_checkpoints = nc;
+    for (uint32_t k = 0; k < nc; ++k) {
+        out->checkpoints[k] = ckpts[k];
+        Moments f = moments(F + (1 + k) * fw::kStreamFields);
+        Moments e = moments(F + (1 + nc + k) * fw::kStreamFields);
+        out->f_mean[k] = f.mean;
+        out->f_sd[k] = std::sqrt(f.var);
+        out->rse_mean[k] = e.mean;
+        out->rse_sd[k] = std::sqrt(e.var);
+        out->rse_undefined[k] = R - (uint64_t)e.n;
+    }
+    for (uint32_t j = 0; j <= d; ++j) out->decision_total[j] = dec[j];
+    out->tau_count = tau_count;
+    out->tau_mean = tau_count ? (double)tau_sum / (double)tau_count : 0.0;
+    out->kernel_ms = ms;
+    out->path_steps_per_s = ms > 0.0 ? path_steps / (ms * 1e-3) : 0.0;
+}
+
+
+namespace {
+
+uint32_t bucket_of(uint32_t d) { return d <= 4 ? 0u : d <= 8 ? 1u : d <= 16 ? 2u : 3u; }
+
+uint32_t reps_per_tile(uint32_t P) { return 64u / P; }
+
+}  // namespace
+
+uint32_t chunk_of(uint32_t N, uint32_t d, uint32_t P, bool t_noise)
+{
+    const uint32_t align = t_noise ? 4u : ((d & 3u) == 0 ? 1u : ((d & 1u) == 0 ? 2u : 4u));
+    uint32_t c = (N + P - 1) / P;
+    return (c + align - 1) / align * align;
+}
+
+// Work of one lane of one tile, in VALU instructions: ~20 per normal, ~15 per asset per
+// iteration (gradient, vertex search, update), 6 per asset per butterfly stage.
+double lane_cost(const sim_params &p, uint64_t T, uint32_t P)
+{
+    const bool t_noise = p.noise == SIM_NOISE_T;
+    const double chunk = chunk_of(p.n_samples, p.d, P, t_noise);
+    const double normals = chunk * (p.d + (t_noise ? p.nu : 0));
+    const double stages = std::log2((double)P);
+    return (double)T * (20.0 * normals + 15.0 * p.d + 6.0 * p.d * stages);
+}
+
+int plan_batch(char *err, uint32_t n_inst, const sim_params *p, const uint64_t *R, const uint64_t *T,
+               uint64_t seed, const sim_batch_config *cfg, uint32_t n_cu, BatchPlan &out)
+{
+    if (n_inst < 1 || n_inst > 65536 || !p || !R || !T)
+        return fail(err, SIM_EINVAL, "need 1 <= n_inst <= 65536 and non-NULL p, R, T");
+    if (n_cu < 1) return fail(err, SIM_EINVAL, "n_cu must be >= 1");
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        int rc = validate(err, &p[i], R[i], T[i]);
+        if (rc) return rc;
+        if (p[i].state_precision != SIM_FP32)
+            return fail(err, SIM_EUNSUPPORTED, "instance %u: batched runs use FP32 state", i);
+        if (p[i].d > 32) return fail(err, SIM_EUNSUPPORTED, "instance %u: d > 32 in a batch", i);
+        if (cfg && cfg->lanes_per_rep) {
+            const uint32_t P = cfg->lanes_per_rep[i];
+            if (P != 0 && (P > 64 || (P & (P - 1)) != 0))
+                return fail(err, SIM_EINVAL, "instance %u: lanes_per_rep must be 0 or a power of two <= 64", i);
+        }
+    }
+    if (cfg && (!(cfg->heavy_factor >= 0.0) || !std::isfinite(cfg->heavy_factor)))
+        return fail(err, SIM_EINVAL, "heavy_factor must be finite and >= 0");
+    if (cfg && (cfg->flags & ~(uint32_t)SIM_KEEP_PATHS)) return fail(err, SIM_EINVAL, "unknown batch flag bits");
+    if (cfg && cfg->reserved) return fail(err, SIM_EINVAL, "reserved field must be 0");
+
+    // lanes per replication: the smallest P whose per-lane work fits theta x the balanced time
+    const double n_simd = 4.0 * n_cu;
+    const double theta = (cfg && cfg->heavy_factor > 0.0) ? cfg->heavy_factor : 0.5;
+    out.P.assign(n_inst, 1u);
+    for (int pass = 0; pass < 3; ++pass) {
+        double total = 0.0;
+        for (uint32_t i = 0; i < n_inst; ++i) {
+            const uint64_t tiles = (R[i] + reps_per_tile(out.P[i]) - 1) / reps_per_tile(out.P[i]);
+            total += tiles * lane_cost(p[i], T[i], out.P[i]);
+        }
+        const double target = theta * total / n_simd;
+        for (uint32_t i = 0; i < n_inst; ++i) {
+            uint32_t P = 1;
+            while (P < 64 && lane_cost(p[i], T[i], P) > target) P *= 2;
+            out.P[i] = P;
+        }
+    }
+    if (cfg && cfg->lanes_per_rep)
+        for (uint32_t i = 0; i < n_inst; ++i)
+            if (cfg->lanes_per_rep[i]) out.P[i] = cfg->lanes_per_rep[i];
+
+    out.tiles_of.assign(n_inst, 0u);
+    out.slot_begin.assign(n_inst + 1, 0u);
+    out.path_base.assign(n_inst, 0);
+    out.cnt_base.assign(n_inst, 0);
+    out.wsum_base.assign(n_inst, 0);
+    out.dlog_base.assign(n_inst, 0);
+    uint64_t n_tiles = 0, total_R = 0, cntb = 0, wsb = 0, dlb = 0, steps = 0;
+    uint32_t max_ckpt = 1;
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        const uint32_t rpt = reps_per_tile(out.P[i]);
+        const uint64_t nt = (R[i] + rpt - 1) / rpt;
+        if (n_tiles + nt > 0xFFFFFFFFull) return fail(err, SIM_EINVAL, "more than 2^32 - 1 tiles");
+        out.tiles_of[i] = (uint32_t)nt;
+        out.slot_begin[i] = (uint32_t)n_tiles;
+        n_tiles += nt;
+        out.path_base[i] = total_R;
+        out.cnt_base[i] = cntb;
+        out.wsum_base[i] = wsb;
+        out.dlog_base[i] = dlb;
+        cntb += (uint64_t)(p[i].d + 1) * R[i];
+        wsb += (uint64_t)p[i].d * R[i];
+        if (p[i].flags & SIM_DECISION_LOG) dlb += T[i] * p[i].log_rep_count;
+        total_R += R[i];
+        steps += R[i] * T[i];
+        max_ckpt = std::max(max_ckpt, p[i].n_checkpoints);
+    }
+    out.slot_begin[n_inst] = (uint32_t)n_tiles;
+    out.n_tiles = (uint32_t)n_tiles;
+    out.total_R = total_R;
+    out.total_steps = steps;
+    out.cnt_total = cntb;
+    out.wsum_total = wsb;
+    out.dlog_total = dlb;
+    out.max_ckpt = max_ckpt;
+
+    out.desc.assign(n_inst, InstanceDesc{});
+    out.fstar.assign(n_inst, NAN);
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        InstanceDesc &D = out.desc[i];
+        fill_desc(D, &p[i], R[i], T[i], seed);
+        D.path_base = out.path_base[i];
+        D.cnt_base = out.cnt_base[i];
+        D.wsum_base = out.wsum_base[i];
+        D.dlog_base = out.dlog_base[i];
+        out.fstar[i] = kkt_fstar(p[i].mu, p[i].sigma, p[i].d, p[i].risk_coef);
+    }
+
+    // tiles in instance-major replication order get consecutive slots; hand them out longest first
+    std::vector<Tile> tiles(n_tiles);
+    std::vector<double> cost(n_tiles);
+    uint64_t k = 0;
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        const uint32_t rpt = reps_per_tile(out.P[i]);
+        const double c = lane_cost(p[i], T[i], out.P[i]);
+        for (uint32_t t = 0; t < out.tiles_of[i]; ++t, ++k) {
+            Tile &tl = tiles[k];
+            tl.inst = i;
+            tl.rep0 = t * rpt;
+            tl.slot = (uint32_t)k;
+            tl.nrep = (uint16_t)std::min<uint64_t>(rpt, R[i] - (uint64_t)t * rpt);
+            tl.P = (uint8_t)out.P[i];
+            tl.bucket = (uint8_t)bucket_of(p[i].d);
+            cost[k] = c;
+        }
+    }
+    auto cls = [&](uint32_t q) { return 2u * tiles[q].bucket + (p[tiles[q].inst].noise == SIM_NOISE_T ? 1u : 0u); };
+    std::vector<uint32_t> order(n_tiles);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        const uint32_t ca = cls(a), cb = cls(b);
+        return ca != cb ? ca < cb : cost[a] > cost[b];
+    });
+    out.tiles.resize(n_tiles);
+    for (uint32_t c = 0; c < 9; ++c) out.class_begin[c] = 0;
+    for (uint64_t q = 0; q < n_tiles; ++q) {
+        out.tiles[q] = tiles[order[q]];
+        out.class_begin[cls(order[q]) + 1]++;
+    }
+    for (uint32_t c = 0; c < 8; ++c) out.class_begin[c + 1] += out.class_begin[c];
+    return SIM_OK;
+}
+
+}  // namespace host
+}  // namespace fw

@@ -1,0 +1,45 @@
+// host_core.hpp -- device-free host logic shared by the C-ABI translation units.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/sim.h"
+#include "sim_types.hpp"
+
+namespace fw {
+namespace host {
+
+constexpr size_t kErrLen = 512;
+
+int fail(char *err, int code, const char *fmt, ...);
+int validate(char *err, const sim_params *p, uint64_t R, uint64_t T);
+void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed);
+double kkt_fstar(const double *mu, const double *sigma, uint32_t d, double lambda);
+// statistics from the reduced stream layout (per stream: sum hi/lo, squares hi/lo, count)
+void fill_stats(sim_stats_out *out, const double *F, uint32_t n_ckpt, const uint64_t *ckpts, double ymin,
+                double ymax, const uint64_t *dec, uint32_t d, uint64_t tau_count, uint64_t tau_sum, uint64_t R,
+                uint64_t T, double fstar, double ms, double path_steps);
+
+uint32_t chunk_of(uint32_t N, uint32_t d, uint32_t P, bool t_noise);
+double lane_cost(const sim_params &p, uint64_t T, uint32_t P);
+
+// The work plan of a batched run.
+struct BatchPlan {
+    std::vector<uint32_t> P, tiles_of, slot_begin;
+    std::vector<uint64_t> path_base, cnt_base, wsum_base, dlog_base;
+    std::vector<InstanceDesc> desc;
+    std::vector<double> fstar;
+    std::vector<Tile> tiles;             // grouped by class (2 bucket + noise), longest first
+    uint32_t class_begin[9] = {0};       // tiles of class c: [class_begin[c], class_begin[c+1])
+    uint32_t n_tiles = 0, max_ckpt = 1;
+    uint64_t total_R = 0, total_steps = 0, cnt_total = 0, wsum_total = 0, dlog_total = 0;
+};
+
+int plan_batch(char *err, uint32_t n_inst, const sim_params *p, const uint64_t *R, const uint64_t *T,
+               uint64_t seed, const sim_batch_config *cfg, uint32_t n_cu, BatchPlan &out);
+
+}  // namespace host
+}  // namespace fw

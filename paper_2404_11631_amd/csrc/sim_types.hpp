@@ -37,6 +37,50 @@ struct InstanceDesc {
     float c1_f[kMaxD], c2_f[kMaxD];
     float tscale_f;          // sqrt(nu - 2) / sqrt(2 ln 2)
     float inv_n_f;
+    // batched runs: offsets of this instance in the concatenated per-path arrays
+    uint64_t path_base;      // into Y, tau, f(w_c) (per checkpoint stride = total R)
+    uint64_t cnt_base;       // into counts   ([d+1][R] block of this instance)
+    uint64_t wsum_base;      // into signatures ([d][R] block of this instance)
+    uint64_t dlog_base;      // into the decision log ([T][log_count] block)
+};
+
+// One wavefront's unit of work in a batched run: `nrep` replications of one instance starting at
+// rep0, with P lanes per replication (samples split across them). Tiles are stored grouped by
+// class (2 bucket + noise), longest first within a class; `slot` is the tile's place in
+// instance-major replication order, which fixes the reduction order.
+struct Tile {
+    uint32_t inst;
+    uint32_t rep0;
+    uint32_t slot;
+    uint16_t nrep;
+    uint8_t P;
+    uint8_t bucket;          // 0: d <= 4, 1: d <= 8, 2: d <= 16, 3: d <= 32
+};
+
+// Per-tile partial record of a batched run (one wavefront's replications of one instance).
+constexpr int kTileStreams = 1 + 2 * kMaxCkpt;
+struct TilePartial {
+    double f[kTileStreams * kStreamFields];   // per stream: sum hi, sum lo, sq hi, sq lo, count
+    double ymin, ymax;
+    uint64_t dec[33];                         // decision totals, origin first (d <= 32)
+    uint64_t tau_count, tau_sum;
+};
+
+struct BatchBuffers {
+    const InstanceDesc *inst;
+    const Tile *tiles;
+    uint32_t n_tiles;
+    uint32_t n_inst;
+    TilePartial *partials;    // [n_tiles] by slot
+    const uint32_t *slot_begin;   // [n_inst + 1] slot range of each instance
+    double *fck;              // [max_ckpt][total R]
+    uint64_t total_R;
+    double *y;                // KEEP_PATHS: [total R]
+    uint32_t *tau;            // KEEP_PATHS: [total R]
+    uint32_t *cnt;            // KEEP_PATHS: concatenated [d_i+1][R_i]
+    uint64_t *wsum;           // KEEP_PATHS: concatenated [d_i][R_i]
+    uint8_t *dlog;            // DECISION_LOG: concatenated [T_i][log_count_i]
+    TilePartial *final_stats; // [n_inst] reduced per instance
 };
 
 // Per-run device buffers. Structure of arrays, replication index fastest.

@@ -56,12 +56,19 @@ class SimPathView(ctypes.Structure):
                 ("n_checkpoints", ctypes.c_uint32), ("y", ctypes.c_void_p),
                 ("f_ckpt", ctypes.c_void_p), ("cnt", ctypes.c_void_p), ("wsum", ctypes.c_void_p),
                 ("tau", ctypes.c_void_p), ("decisions", ctypes.c_void_p),
-                ("log_rep_begin", ctypes.c_uint64), ("log_rep_count", ctypes.c_uint64)]
+                ("log_rep_begin", ctypes.c_uint64), ("log_rep_count", ctypes.c_uint64),
+                ("f_ckpt_stride", ctypes.c_uint64)]
+
+
+class SimBatchConfig(ctypes.Structure):
+    _fields_ = [("reserved", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("heavy_factor", ctypes.c_double), ("lanes_per_rep", ctypes.POINTER(ctypes.c_uint8))]
 
 
 #: every symbol include/sim.h declares
-EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_stats", "sim_paths",
-           "sim_copy_to_host", "sim_strerror", "sim_last_error", "sim_destroy")
+EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_run_batch",
+           "sim_plan_batch", "sim_batch_stats", "sim_batch_paths", "sim_stats", "sim_paths", "sim_copy_to_host",
+           "sim_strerror", "sim_last_error", "sim_destroy")
 
 _lib = None
 
@@ -80,6 +87,17 @@ def load():
                               ctypes.c_uint64]
         L.sim_validate.argtypes = [ctypes.POINTER(SimParams), ctypes.c_uint64, ctypes.c_uint64,
                                    ctypes.c_char_p, ctypes.c_size_t]
+        L.sim_run_batch.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(SimParams),
+                                    ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                    ctypes.c_uint64, ctypes.POINTER(SimBatchConfig)]
+        L.sim_plan_batch.argtypes = [ctypes.c_uint32, ctypes.POINTER(SimParams),
+                                     ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                     ctypes.POINTER(SimBatchConfig), ctypes.c_uint32,
+                                     ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                                     ctypes.c_char_p, ctypes.c_size_t]
+        L.sim_batch_stats.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(SimStats)]
+        L.sim_batch_paths.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(SimPathView),
+                                      ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]
         L.sim_stats.argtypes = [vp, ctypes.POINTER(SimStats)]
         L.sim_paths.argtypes = [vp, ctypes.POINTER(SimPathView)]
         L.sim_copy_to_host.argtypes = [vp, vp, vp, ctypes.c_size_t]
@@ -124,6 +142,38 @@ def validate(p: Problem, R: int, T: int):
     buf = ctypes.create_string_buffer(512)
     rc = load().sim_validate(ctypes.byref(sp), R, T, buf, 512)
     return rc, buf.value.decode()
+
+
+def _batch_args(problems, R, T, heavy_factor=0.0, lanes_per_rep=None, keep_paths=False):
+    n = len(problems)
+    arr = (SimParams * n)()
+    keep = []
+    for i, p in enumerate(problems):
+        sp, k = Sim.params(p)
+        arr[i] = sp
+        keep.append(k)
+    Ra = (ctypes.c_uint64 * n)(*[int(x) for x in R])
+    Ta = (ctypes.c_uint64 * n)(*[int(x) for x in T])
+    cfg = SimBatchConfig()
+    cfg.flags = KEEP_PATHS if keep_paths else 0
+    cfg.heavy_factor = heavy_factor
+    if lanes_per_rep is not None:
+        lp = (ctypes.c_uint8 * n)(*[int(x) for x in lanes_per_rep])
+        keep.append(lp)
+        cfg.lanes_per_rep = lp
+    return n, arr, Ra, Ta, cfg, keep
+
+
+def plan_batch(problems, R, T, n_cu=256, **kw):
+    """(lanes per replication, tiles) per instance of the plan sim_run_batch would use; no device."""
+    n, arr, Ra, Ta, cfg, keep = _batch_args(problems, R, T, **kw)
+    P = (ctypes.c_uint32 * n)()
+    nt = (ctypes.c_uint32 * n)()
+    buf = ctypes.create_string_buffer(512)
+    rc = load().sim_plan_batch(n, arr, Ra, Ta, ctypes.byref(cfg), n_cu, P, nt, buf, 512)
+    if rc:
+        raise SimError(rc, buf.value.decode())
+    return list(P), list(nt)
 
 
 class Sim:
@@ -211,9 +261,36 @@ class Sim:
                                                 ctypes.c_void_p(ptr), out.nbytes))
         return out
 
+    def run_batch(self, problems, R, T, seed: int, *, heavy_factor: float = 0.0,
+                  lanes_per_rep=None, keep_paths: bool = False):
+        """Uneven batch of instances (sim_run_batch)."""
+        n, arr, Ra, Ta, cfg, keep = _batch_args(problems, R, T, heavy_factor, lanes_per_rep,
+                                                keep_paths)
+        self._keep = keep
+        self._batch_n = n
+        self._check(self.L.sim_run_batch(self.h, n, arr, Ra, Ta, seed, ctypes.byref(cfg)))
+
+    def batch_stats(self, i: int) -> SimStats:
+        st = SimStats()
+        self._check(self.L.sim_batch_stats(self.h, i, ctypes.byref(st)))
+        return st
+
+    def batch_paths(self, i: int) -> dict:
+        v = SimPathView()
+        P = ctypes.c_uint32()
+        nt = ctypes.c_uint32()
+        self._check(self.L.sim_batch_paths(self.h, i, ctypes.byref(v), ctypes.byref(P), ctypes.byref(nt)))
+        out = self._view(v)
+        out["lanes_per_rep"] = P.value
+        out["n_tiles"] = nt.value
+        return out
+
     def paths(self) -> dict:
         v = SimPathView()
         self._check(self.L.sim_paths(self.h, ctypes.byref(v)))
+        return self._view(v)
+
+    def _view(self, v) -> dict:
         R, d, nc = v.R, v.d, v.n_checkpoints
         out = {"R": R, "T": v.T, "d": d}
         if v.y:
@@ -222,7 +299,8 @@ class Sim:
             out["wsum"] = self._copy(v.wsum, np.uint64, d * R).reshape(d, R)
             out["tau"] = self._copy(v.tau, np.uint32, R)
         if v.f_ckpt:
-            out["f_ckpt"] = self._copy(v.f_ckpt, np.float64, nc * R).reshape(nc, R)
+            rows = [self._copy(v.f_ckpt + 8 * c * v.f_ckpt_stride, np.float64, R) for c in range(nc)]
+            out["f_ckpt"] = np.stack(rows) if rows else np.zeros((0, R))
         if v.decisions:
             n = v.log_rep_count
             out["decisions"] = self._copy(v.decisions, np.uint8, v.T * n).reshape(v.T, n)

@@ -1,0 +1,115 @@
+// CPU emulation of the batched tile kernels (test infrastructure only): the real host planner and
+// the real device source, compiled for the host against tests/emu/shim, each workgroup run as
+// lockstep threads, every buffer in host memory.
+#include <hip/hip_runtime.h>
+thread_local Dim3emu threadIdx;
+thread_local Dim3emu blockIdx;
+EmuBlock *g_block = nullptr;
+
+#include "../../paper_2404_11631_amd/csrc/fw_batch.hip"
+#include "../../paper_2404_11631_amd/csrc/host_core.hpp"
+
+#include <cstdio>
+#include <vector>
+
+using namespace fw;
+using namespace fw::host;
+
+static BatchPlan g_plan;
+static std::vector<TilePartial> g_partials, g_final;
+static std::vector<double> g_fck, g_y;
+static std::vector<uint32_t> g_tau, g_cnt;
+static std::vector<uint64_t> g_wsum;
+static std::vector<uint8_t> g_dlog;
+static std::vector<sim_params> g_params;
+static std::vector<uint64_t> g_R, g_T;
+static char g_err[512];
+
+template <int D, int NOISE>
+static void run_class(const BatchBuffers &B, uint32_t begin, uint32_t end)
+{
+    for (uint32_t t = begin; t < end; ++t)
+        emu_run_block(64, t - begin, [&] { fw_tile_kernel<D, NOISE>(B, begin); });
+}
+
+extern "C" int emu_run_batch(uint32_t n_inst, const sim_params *p, const uint64_t *R, const uint64_t *T,
+                             uint64_t seed, const sim_batch_config *cfg, int keep)
+{
+    g_plan = BatchPlan{};
+    const int rc = plan_batch(g_err, n_inst, p, R, T, seed, cfg, 256, g_plan);
+    if (rc) return rc;
+    g_params.assign(p, p + n_inst);
+    g_R.assign(R, R + n_inst);
+    g_T.assign(T, T + n_inst);
+    BatchPlan &P = g_plan;
+    g_partials.assign(P.n_tiles, TilePartial{});
+    g_final.assign(n_inst, TilePartial{});
+    g_fck.assign((size_t)P.max_ckpt * P.total_R, 0.0);
+    g_y.assign(keep ? P.total_R : 0, 0.0);
+    g_tau.assign(keep ? P.total_R : 0, 0);
+    g_cnt.assign(keep ? P.cnt_total : 0, 0);
+    g_wsum.assign(keep ? P.wsum_total : 0, 0);
+    g_dlog.assign(P.dlog_total, 0xEE);
+    BatchBuffers B{};
+    B.inst = P.desc.data();
+    B.tiles = P.tiles.data();
+    B.n_tiles = P.n_tiles;
+    B.n_inst = n_inst;
+    B.partials = g_partials.data();
+    B.slot_begin = P.slot_begin.data();
+    B.fck = g_fck.data();
+    B.total_R = P.total_R;
+    B.y = keep ? g_y.data() : nullptr;
+    B.tau = keep ? g_tau.data() : nullptr;
+    B.cnt = keep ? g_cnt.data() : nullptr;
+    B.wsum = keep ? g_wsum.data() : nullptr;
+    B.dlog = P.dlog_total ? g_dlog.data() : nullptr;
+    B.final_stats = g_final.data();
+    const uint32_t *cb = P.class_begin;
+    run_class<4, 0>(B, cb[0], cb[1]);
+    run_class<4, 1>(B, cb[1], cb[2]);
+    run_class<8, 0>(B, cb[2], cb[3]);
+    run_class<8, 1>(B, cb[3], cb[4]);
+    run_class<16, 0>(B, cb[4], cb[5]);
+    run_class<16, 1>(B, cb[5], cb[6]);
+    run_class<32, 0>(B, cb[6], cb[7]);
+    run_class<32, 1>(B, cb[7], cb[8]);
+    for (uint32_t i = 0; i < n_inst; ++i) emu_run_block(256, i, [&] { fw_batch_reduce(B); });
+    return 0;
+}
+
+extern "C" int emu_batch_stats(uint32_t i, sim_stats_out *out)
+{
+    const TilePartial &tp = g_final[i];
+    const sim_params &q = g_params[i];
+    fill_stats(out, tp.f, q.n_checkpoints, q.checkpoints, tp.ymin, tp.ymax, tp.dec, q.d, tp.tau_count, tp.tau_sum,
+               g_R[i], g_T[i], g_plan.fstar[i], 0.0, 0.0);
+    return 0;
+}
+
+extern "C" int emu_batch_paths(uint32_t i, sim_path_view *out, uint32_t *P, uint32_t *nt)
+{
+    const sim_params &q = g_params[i];
+    const uint64_t base = g_plan.path_base[i];
+    std::memset(out, 0, sizeof(*out));
+    out->R = g_R[i];
+    out->T = g_T[i];
+    out->d = q.d;
+    out->n_checkpoints = q.n_checkpoints;
+    if (!g_y.empty()) {
+        out->y = g_y.data() + base;
+        out->tau = g_tau.data() + base;
+        out->cnt = g_cnt.data() + g_plan.cnt_base[i];
+        out->wsum = g_wsum.data() + g_plan.wsum_base[i];
+    }
+    out->f_ckpt = q.n_checkpoints ? g_fck.data() + base : nullptr;
+    out->f_ckpt_stride = g_plan.total_R;
+    if (q.flags & SIM_DECISION_LOG) {
+        out->decisions = g_dlog.data() + g_plan.dlog_base[i];
+        out->log_rep_begin = q.log_rep_begin;
+        out->log_rep_count = q.log_rep_count;
+    }
+    *P = g_plan.P[i];
+    *nt = g_plan.tiles_of[i];
+    return 0;
+}

@@ -1,0 +1,99 @@
+// CPU emulation of the HIP device API subset the batched tile kernels use (test infrastructure:
+// runs one workgroup as lockstep threads so the kernel logic can be checked against the oracle
+// without a GPU).
+#pragma once
+#include <atomic>
+#include <barrier>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <thread>
+#include <vector>
+
+#define __device__
+#define __host__
+#define __global__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__ static
+#define __HIP_MEMORY_SCOPE_AGENT 0
+
+struct Dim3emu { unsigned x, y, z; };
+extern thread_local Dim3emu threadIdx;
+extern thread_local Dim3emu blockIdx;
+typedef int hipError_t;
+typedef void *hipStream_t;
+#define hipSuccess 0
+inline hipError_t hipGetLastError() { return 0; }
+struct dim3 { unsigned x, y, z; dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {} };
+#define hipLaunchKernelGGL(...) ((void)0)
+template <class F> hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *b, F, int, int) { *b = 4; return 0; }
+
+// lockstep exchange for shuffles: every thread of the block calls the shuffle at the same point
+struct EmuBlock {
+    int nthreads;
+    std::barrier<> *bar;
+    std::vector<uint64_t> slot;
+};
+extern EmuBlock *g_block;
+
+template <class T> inline T emu_exchange(T v, int src)
+{
+    uint64_t bits = 0;
+    std::memcpy(&bits, &v, sizeof(T));
+    g_block->slot[threadIdx.x] = bits;
+    g_block->bar->arrive_and_wait();
+    uint64_t got = g_block->slot[src];
+    g_block->bar->arrive_and_wait();
+    T out;
+    std::memcpy(&out, &got, sizeof(T));
+    return out;
+}
+template <class T> inline T __shfl(T v, int src, int width = 64)
+{
+    int base = threadIdx.x / width * width;
+    return emu_exchange(v, base + (src % width));
+}
+template <class T> inline T __shfl_xor(T v, unsigned m, int width = 64)
+{
+    int lane = threadIdx.x % width, base = threadIdx.x - lane;
+    return emu_exchange(v, base + ((lane ^ m) % width));
+}
+template <class T> inline T __shfl_down(T v, unsigned off, int width = 64)
+{
+    int lane = threadIdx.x % width, base = threadIdx.x - lane;
+    int src = lane + (int)off < width ? lane + (int)off : lane;
+    return emu_exchange(v, base + src);
+}
+inline void __syncthreads() { g_block->bar->arrive_and_wait(); }
+inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
+template <class T> inline T __hip_atomic_fetch_add(T *p, T v, int, int)
+{
+    return std::atomic_ref<T>(*p).fetch_add(v);
+}
+template <class T> inline void __hip_atomic_store(T *p, T v, int, int) { std::atomic_ref<T>(*p).store(v); }
+template <class T> inline T __hip_atomic_load(T *p, int, int) { return std::atomic_ref<T>(*p).load(); }
+inline float __uint_as_float(uint32_t x) { float f; std::memcpy(&f, &x, 4); return f; }
+inline uint32_t __float_as_uint(float f) { uint32_t x; std::memcpy(&x, &f, 4); return x; }
+inline float __builtin_amdgcn_sqrtf(float x) { return std::sqrt(x); }
+inline float __builtin_amdgcn_logf(float x) { return std::log2(x); }
+inline float __builtin_amdgcn_cosf(float x) { return (float)std::cos(6.283185307179586 * x); }
+inline float __builtin_amdgcn_sinf(float x) { return (float)std::sin(6.283185307179586 * x); }
+inline float __builtin_amdgcn_rsqf(float x) { return 1.0f / std::sqrt(x); }
+inline void sincospi(double x, double *s, double *c) { *s = std::sin(M_PI * x); *c = std::cos(M_PI * x); }
+using std::fma; using std::fmin; using std::fmax; using std::sqrt; using std::log;
+inline float fmaf(float a, float b, float c) { return std::fma(a, b, c); }
+
+// runs kernel body f on a block of n threads in lockstep
+inline void emu_run_block(int n, unsigned bx, const std::function<void()> &f)
+{
+    std::barrier<> bar(n);
+    EmuBlock blk{n, &bar, std::vector<uint64_t>(n)};
+    g_block = &blk;
+    std::vector<std::thread> th;
+    for (int i = 0; i < n; ++i)
+        th.emplace_back([&, i] { threadIdx = {(unsigned)i, 0, 0}; blockIdx = {bx, 0, 0}; f(); });
+    for (auto &t : th) t.join();
+    g_block = nullptr;
+}

@@ -1,0 +1,158 @@
+"""Batched runs of uneven instances vs the CPU oracle.
+
+Skipped: the batched device path is switched off in this build (sim_run_batch returns
+SIM_EUNSUPPORTED). Its first device run, an earlier persistent-kernel design launched from a captured
+graph, stopped responding and the cause has not been shown; the tile kernels that replaced it pass
+the same parity checks in a CPU emulation of the device code (tests/test_batch_emulated.py) but are
+not run on a device until that cause is understood.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_11631_amd import sim, workloads
+from tests import parity
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skip(reason="batched device path switched off: an earlier design stopped "
+                                      "responding on the device and the cause is not shown")]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    s = sim.Sim(0)
+    yield s
+    s.close()
+
+
+def make(i, d, N, noise=sim.NOISE_GAUSS, nu=3, ckpt=(), w0=None, log=None):
+    mu, sigma = workloads.diag_instance(77, i, d)
+    return sim.Problem(mu=mu, sigma=sigma, N=N, noise=noise, nu=nu, checkpoints=ckpt, gap_eps=0.05,
+                       w0=w0, instance_id=i, log_reps=log)
+
+
+SMALL = [  # (d, N, T, R, P, noise)
+    (2, 2, 300, 130, 1, 0),
+    (3, 5, 200, 70, 2, 0),
+    (5, 7, 150, 100, 4, 0),
+    (8, 4, 120, 64, 8, 0),
+    (13, 9, 100, 40, 16, 0),
+    (20, 11, 80, 33, 64, 0),
+    (32, 6, 60, 65, 2, 0),
+    (4, 6, 100, 50, 4, 1),
+    (17, 5, 60, 30, 1, 1),
+    (7, 3, 150, 90, 0, 0),     # 0: the cost model chooses
+]
+
+
+def test_small_batch_parity(ctx):
+    probs, R, T, P = [], [], [], []
+    for i, (d, N, t, r, p, noise) in enumerate(SMALL):
+        w0 = np.full(d, 0.5 / d) if i == 2 else None
+        probs.append(make(i, d, N, noise=noise, nu=4 if noise else 3, ckpt=(10, t), w0=w0, log=(0, r)))
+        R.append(r)
+        T.append(t)
+        P.append(p)
+    say(f"[batch] small batch {len(probs)} instances")
+    ctx.run_batch(probs, R, T, seed=99, lanes_per_rep=P, keep_paths=True)
+    for i, p in enumerate(probs):
+        st = ctx.batch_stats(i)
+        g = ctx.batch_paths(i)
+        if P[i]:
+            assert g["lanes_per_rep"] == P[i]
+        op = parity.oracle_problem(p, 99)
+        outs = (oracle.PathOut * R[i])()
+        for r in range(R[i]):
+            outs[r] = parity.check_rep(op, g, r, T[i], oracle.U32, decisions=g["decisions"][:, r])
+        parity.check_stats(st, op.reduce(outs, T[i]), len(p.checkpoints), len(p.mu), g["tau"])
+        say(f"[batch] instance {i} d={len(p.mu)} P={g['lanes_per_rep']} ok")
+
+
+def test_batch_equals_single_run_at_one_lane(ctx):
+    """P = 1 runs the same arithmetic in the same order as sim_run: identical bits."""
+    d, N, T, R = 10, 10, 400, 300
+    p = make(3, d, N, ckpt=(100, 400))
+    p.keep_paths = True
+    ctx.run(p, R, T, 5)
+    a = ctx.paths()
+    sa = ctx.stats()
+    other = make(4, 6, 3, ckpt=(50,))
+    ctx.run_batch([other, p], [100, R], [200, T], seed=5, lanes_per_rep=[2, 1], keep_paths=True)
+    b = ctx.batch_paths(1)
+    sb = ctx.batch_stats(1)
+    assert np.array_equal(a["y"], b["y"])
+    assert np.array_equal(a["cnt"], b["cnt"]) and np.array_equal(a["wsum"], b["wsum"])
+    assert np.array_equal(a["tau"], b["tau"]) and np.array_equal(a["f_ckpt"], b["f_ckpt"])
+    assert sa.mean == sb.mean and sa.var == sb.var
+
+
+def test_batch_composition_invariance(ctx):
+    """An instance's paths do not depend on the other instances, their order or the tiling."""
+    A = make(10, 12, 8, ckpt=(30,))
+    Bp = make(11, 5, 20, ckpt=(30,))
+    Cp = make(12, 30, 4, ckpt=(30,))
+    ctx.run_batch([A, Bp, Cp], [200, 100, 150], [120, 300, 60], seed=7, lanes_per_rep=[4, 2, 8], keep_paths=True)
+    ya = ctx.batch_paths(0)["y"].copy()
+    sa = ctx.batch_stats(0)
+    ctx.run_batch([Cp, A], [150, 200], [60, 120], seed=7, lanes_per_rep=[1, 4], keep_paths=True, )
+    yb = ctx.batch_paths(1)["y"]
+    sb = ctx.batch_stats(1)
+    assert np.array_equal(ya, yb)
+    assert sa.mean == sb.mean and sa.var == sb.var and list(sa.decision_total) == list(sb.decision_total)
+
+
+def test_batch_errors(ctx):
+    p = make(0, 40, 4)
+    with pytest.raises(sim.SimError) as e:
+        ctx.run_batch([p], [10], [10], seed=1)
+    assert e.value.code == -5
+    q = make(0, 4, 4)
+    q.precision = sim.FP64
+    with pytest.raises(sim.SimError) as e:
+        ctx.run_batch([q], [10], [10], seed=1)
+    assert e.value.code == -5
+    with pytest.raises(sim.SimError) as e:
+        ctx.run_batch([make(0, 4, 4)], [10], [10], seed=1, lanes_per_rep=[3])
+    assert e.value.code == -1
+
+
+def test_uneven_full_size(ctx):
+    """The uneven workload at full size: 256 instances x 4,096 replications, T log-uniform on
+    [100, 1e5]; replications of several instances are checked
+    against the oracle with their decision logs, every instance by exact properties."""
+    w = workloads.WORKLOADS["uneven"]
+    batch = workloads.uneven_batch(w["seed"], w["n_instances"], w["R"], w["d_range"], w["n_range"], w["t_range"])
+    costs = np.array([b.T * b.N * b.d for b in batch], dtype=float)
+    order = np.argsort(costs)
+    checked = [int(order[0]), int(order[40]), int(order[128]), int(order[200])]
+    probs = []
+    for b in batch:
+        log = (b.R - 3, 3) if b.instance in checked else None
+        probs.append(sim.Problem(mu=b.mu, sigma=b.sigma, N=b.N, checkpoints=(min(50, b.T), b.T),
+                                 instance_id=b.instance, log_reps=log))
+    steps = sum(b.R * b.T for b in batch)
+    say(f"[batch] uneven: {len(batch)} instances, {steps:.3e} path-steps")
+    ctx.run_batch(probs, [b.R for b in batch], [b.T for b in batch], seed=w["seed"], keep_paths=True)
+    st0 = ctx.batch_stats(0)
+    say(f"[batch] uneven: {st0.kernel_ms:.1f} ms, {st0.path_steps_per_s:.3e} path-steps/s")
+    for i, b in enumerate(batch):
+        st = ctx.batch_stats(i)
+        g = ctx.batch_paths(i)
+        assert np.all(g["cnt"].sum(axis=0) == b.T)
+        assert math.isclose(st.mean, math.fsum(g["y"]) / b.R, rel_tol=1e-13)
+        assert st.min == g["y"].min() and st.max == g["y"].max()
+        assert np.all(g["y"] >= st.f_star - 1e-12)
+        assert np.array_equal(g["f_ckpt"][-1], g["y"])
+        if i in checked:
+            op = parity.oracle_problem(probs[i], w["seed"])
+            for k in range(3):
+                parity.check_rep(op, g, b.R - 3 + k, b.T, oracle.U32, decisions=g["decisions"][:, k])
+            say(f"[batch] instance {i} (d={b.d} N={b.N} T={b.T} P={g['lanes_per_rep']}) matches the oracle")
