@@ -79,7 +79,7 @@ void or_normals(uint64_t seed, uint32_t domain, uint32_t instance, uint64_t rep,
  * t scaled to unit covariance, chi2 from nu extra normals per sample (normals N d + nu i + k).
  * ------------------------------------------------------------------------------------------- */
 static void draw_returns(const or_problem *p, uint64_t rep, uint64_t epoch, double *Rmat,
-                         double *noise /* N*d: L y_i, the return minus its mean */)
+                         double *noise /* N*d: y_i, the unit-covariance noise of each return */)
 {
     const int d = p->d, N = p->N;
     const uint64_t n_main = (uint64_t)N * (uint64_t)d;
@@ -101,7 +101,7 @@ static void draw_returns(const or_problem *p, uint64_t rep, uint64_t epoch, doub
         for (int j = 0; j < d; ++j) {
             double acc = 0.0;
             for (int k = 0; k <= j; ++k) acc += p->chol[j * d + k] * y[k];
-            noise[(size_t)i * d + j] = acc;
+            noise[(size_t)i * d + j] = y[j];
             Rmat[(size_t)i * d + j] = p->mu[j] + acc;
         }
     }
@@ -180,6 +180,9 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
     double *rbar = (double *)malloc(sizeof(double) * (size_t)d);
     double *sw = (double *)malloc(sizeof(double) * (size_t)d);
     double *vals = (double *)malloc(sizeof(double) * (size_t)(d + 1));
+    double *vabs = (double *)malloc(sizeof(double) * (size_t)d);
+    double *habs = (double *)malloc(sizeof(double) * (size_t)d);
+    double *pabs = (double *)malloc(sizeof(double) * (size_t)N);
 
     memset(out, 0, sizeof(*out));
     out->tau = out->tau_lo = out->tau_hi = OR_TAU_NONE;
@@ -212,22 +215,38 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
         double margin = second - best;
         if (margin < out->min_margin) out->min_margin = margin;
 
-        /* rounding bound of a system that evaluates this gradient with unit roundoff uroff */
+        /* rounding bound of a system that evaluates this gradient with unit roundoff uroff,
+         * with every sum taken in absolute values. It follows the gradient through the noise
+         * coordinates y of R_i = mu + L y_i, which covers both evaluation orders a system may use:
+         * return space (Sigma_hat w from the centred R_i) and noise space (L applied to sums of y,
+         * with v = L'w); for a diagonal L the two coincide. */
         double bound = 0.0;
         if (uroff > 0.0) {
             double amax = 0.0;
             double wabs = 0.0;
             for (int j = 0; j < d; ++j) wabs += fabs(w[j]);
-            for (int j = 0; j < d; ++j) {
+            for (int m = 0; m < d; ++m) {            /* |L|' |w| */
+                double acc = 0.0;
+                for (int l = m; l < d; ++l) acc += fabs(p->chol[l * d + m]) * fabs(w[l]);
+                vabs[m] = acc;
+            }
+            for (int i = 0; i < N; ++i) {            /* |y_i|' |L|' |w| */
+                double acc = 0.0;
+                for (int m = 0; m < d; ++m) acc += fabs(noise[(size_t)i * d + m]) * vabs[m];
+                pabs[i] = acc;
+            }
+            for (int k = 0; k < d; ++k) {
                 double quad = 0.0, lin = 0.0;
                 for (int i = 0; i < N; ++i) {
-                    double proj = 0.0;
-                    for (int k = 0; k < d; ++k) proj += fabs(noise[(size_t)i * d + k] * w[k]);
-                    quad += fabs(noise[(size_t)i * d + j]) * proj;
-                    lin += fabs(noise[(size_t)i * d + j]);
+                    quad += fabs(noise[(size_t)i * d + k]) * pabs[i];
+                    lin += fabs(noise[(size_t)i * d + k]);
                 }
-                double aj = 2.0 * p->lambda * quad / (double)(N - 1) + lin / (double)N +
-                            fabs(p->mu[j]) + fabs(g[j]);
+                habs[k] = 2.0 * p->lambda * quad / (double)(N - 1) + lin / (double)N;
+            }
+            for (int j = 0; j < d; ++j) {
+                double acc = 0.0;
+                for (int k = 0; k <= j; ++k) acc += fabs(p->chol[j * d + k]) * habs[k];
+                double aj = acc + fabs(p->mu[j]) + fabs(g[j]);
                 if (aj > amax) amax = aj;
             }
             bound = kappa * uroff * amax * (1.0 + wabs);
@@ -277,6 +296,7 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
         double e = fabs(w[j] - closed);
         if (e > out->identity_err) out->identity_err = e;
     }
+    free(pabs); free(habs); free(vabs);
     free(vals); free(sw); free(rbar); free(g); free(w); free(noise); free(Rmat);
     return 0;
 }
