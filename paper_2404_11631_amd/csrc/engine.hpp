@@ -13,6 +13,9 @@ namespace fw {
 int launch_fw_paths(const InstanceDesc &host_desc, const InstanceDesc *dev_desc, const RunBuffers &B,
                     bool fp64, hipStream_t stream, int *kernel_width);
 int launch_fw_batch(const BatchBuffers &B, const uint32_t *class_begin, hipStream_t stream);
+int launch_fw_dense(const InstanceDesc &host_desc, const InstanceDesc *dev_desc, const RunBuffers &B,
+                    hipStream_t stream);
+constexpr int kDenseRepsPerBlock = kBlock / 2;   // dense-L kernels: two lanes per replication
 }  // namespace fw
 
 using fw::InstanceDesc;
@@ -48,6 +51,8 @@ struct sim_ctx {
     InstanceDesc *desc_host = nullptr;    // pinned staging for the async upload
     InstanceDesc *desc_dev = nullptr;
     DevBuf y, fck, cnt, wsum, tau, dlog, part_f, part_i, done, final_f, final_i;
+    DevBuf dense;                         // dense-L operands: Ag, Av (FP32), L (FP64)
+    void *dense_host = nullptr;           // pinned staging of the same
     RunBuffers bufs{};
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     bool have_run = false;

@@ -35,12 +35,27 @@ int validate(char *err, const sim_params *p, uint64_t R, uint64_t T)
     if (R < 1 || R > 0xFFFFFFFFull) return fail(err, SIM_EINVAL, "R=%llu outside [1, 2^32)", (unsigned long long)R);
     if (T < 1 || T > 0xFFFFFFFEull) return fail(err, SIM_EINVAL, "T=%llu outside [1, 2^32-2]", (unsigned long long)T);
     if (!p->mu) return fail(err, SIM_EINVAL, "mu is NULL");
-    if (p->chol) return fail(err, SIM_EUNSUPPORTED, "dense Cholesky factors are not supported by sim_run");
-    if (!p->sigma) return fail(err, SIM_EINVAL, "sigma is NULL");
-    for (uint32_t j = 0; j < p->d; ++j) {
+    for (uint32_t j = 0; j < p->d; ++j)
         if (!finite(p->mu[j])) return fail(err, SIM_EINVAL, "mu[%u] not finite", j);
-        if (!finite(p->sigma[j]) || p->sigma[j] < 0.0)
-            return fail(err, SIM_EINVAL, "sigma[%u] must be finite and >= 0", j);
+    if (p->chol) {
+        const uint32_t d = p->d;
+        for (uint32_t j = 0; j < d; ++j)
+            for (uint32_t k = 0; k < d; ++k) {
+                const double x = p->chol[j * d + k];
+                if (!finite(x)) return fail(err, SIM_EINVAL, "chol[%u][%u] not finite", j, k);
+                if (k > j && x != 0.0) return fail(err, SIM_EINVAL, "chol[%u][%u] above the diagonal is not 0", j, k);
+            }
+        if (d != 32 && d != 64)
+            return fail(err, SIM_EUNSUPPORTED, "dense Cholesky factors need d = 32 or 64 (d=%u)", d);
+        if (p->state_precision != SIM_FP32)
+            return fail(err, SIM_EUNSUPPORTED, "dense Cholesky factors run in FP32 state only");
+        if (T > kMaxDenseT)
+            return fail(err, SIM_EUNSUPPORTED, "dense Cholesky factors need T <= %llu", (unsigned long long)kMaxDenseT);
+    } else {
+        if (!p->sigma) return fail(err, SIM_EINVAL, "sigma is NULL");
+        for (uint32_t j = 0; j < p->d; ++j)
+            if (!finite(p->sigma[j]) || p->sigma[j] < 0.0)
+                return fail(err, SIM_EINVAL, "sigma[%u] must be finite and >= 0", j);
     }
     if (!(p->risk_coef > 0.0) || !finite(p->risk_coef))
         return fail(err, SIM_EINVAL, "risk_coef must be finite and > 0");
@@ -108,7 +123,15 @@ void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uin
     D.tscale_f = (float)(tnu / kappa);
     D.inv_n_f = (float)(1.0 / N);
     for (uint32_t j = 0; j < p->d; ++j) {
-        const double mu = p->mu[j], sg = p->sigma[j], w0 = p->w0 ? p->w0[j] : 0.0;
+        // with a dense L the per-asset scale is the marginal standard deviation |row j of L|
+        double sg = 0.0;
+        if (p->chol) {
+            for (uint32_t k = 0; k <= j; ++k) sg += p->chol[j * p->d + k] * p->chol[j * p->d + k];
+            sg = std::sqrt(sg);
+        } else {
+            sg = p->sigma[j];
+        }
+        const double mu = p->mu[j], w0 = p->w0 ? p->w0[j] : 0.0;
         D.mu_d[j] = mu;
         D.sig_d[j] = sg;
         D.w0_d[j] = w0;
@@ -182,6 +205,24 @@ Moments moments(const double *f)
 // min over W of lambda sum sigma_j^2 w_j^2 - mu'w (KKT water-filling), diagonal Sigma with every
 // sigma_j > 0: w_j(nu) = max(0, (mu_j - nu) / (2 lambda sigma_j^2)) with nu >= 0 chosen so that
 // sum_j w_j <= 1 holds with complementary slackness. NaN when some sigma_j is zero.
+int dense_asset_of(int p, int k) { return (k >> 2) * 8 + 4 * p + (k & 3); }
+
+void dense_operands(const double *L, uint32_t d, float *Ag, float *Av, double *L64)
+{
+    const double kappa = fw::kBoxMullerScale;
+    const uint32_t H = d / 2;
+    for (uint32_t mt = 0; mt < d / 32; ++mt)
+        for (uint32_t kk = 0; kk < H; ++kk)
+            for (uint32_t lane = 0; lane < 64; ++lane) {
+                const uint32_t row = 32 * mt + (lane & 31);
+                const uint32_t col = (uint32_t)dense_asset_of((int)(lane >> 5), (int)kk);
+                const size_t at = ((size_t)mt * H + kk) * 64 + lane;
+                Ag[at] = (float)(kappa * L[row * d + col]);   // g = L h
+                Av[at] = (float)(kappa * L[col * d + row]);   // v = L'w
+            }
+    for (uint32_t i = 0; i < d * d; ++i) L64[i] = L[i];
+}
+
 double kkt_fstar(const double *mu, const double *sigma, uint32_t d, double lambda)
 {
     for (uint32_t j = 0; j < d; ++j)
@@ -285,6 +326,7 @@ int plan_batch(char *err, uint32_t n_inst, const sim_params *p, const uint64_t *
         if (p[i].state_precision != SIM_FP32)
             return fail(err, SIM_EUNSUPPORTED, "instance %u: batched runs use FP32 state", i);
         if (p[i].d > 32) return fail(err, SIM_EUNSUPPORTED, "instance %u: d > 32 in a batch", i);
+        if (p[i].chol) return fail(err, SIM_EUNSUPPORTED, "instance %u: batched runs take diagonal Sigma", i);
         if (cfg && cfg->lanes_per_rep) {
             const uint32_t P = cfg->lanes_per_rep[i];
             if (P != 0 && (P > 64 || (P & (P - 1)) != 0))

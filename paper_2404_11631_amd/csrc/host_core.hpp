@@ -13,10 +13,16 @@ namespace fw {
 namespace host {
 
 constexpr size_t kErrLen = 512;
+// dense-L runs keep per-path decision counts in 16 bits
+constexpr uint64_t kMaxDenseT = 65535;
 
 int fail(char *err, int code, const char *fmt, ...);
 int validate(char *err, const sim_params *p, uint64_t R, uint64_t T);
 void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed);
+// The two FP32 operands of the dense-L kernels, sqrt(2 ln 2) L (for g = L h) and its transpose
+// (for v = L'w), each [d/32][d/2][64] in the lane order of v_mfma_f32_32x32x2f32 (row 32 mt +
+// lane mod 32, column the asset that lane lane/32 holds in register kk), and L copied in FP64.
+void dense_operands(const double *L, uint32_t d, float *Ag, float *Av, double *L64);
 double kkt_fstar(const double *mu, const double *sigma, uint32_t d, double lambda);
 // statistics from the reduced stream layout (per stream: sum hi/lo, squares hi/lo, count)
 void fill_stats(sim_stats_out *out, const double *F, uint32_t n_ckpt, const uint64_t *ckpts, double ymin,

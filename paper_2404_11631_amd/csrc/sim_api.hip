@@ -134,8 +134,9 @@ void sim_destroy(sim_ctx *ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     for (DevBuf *b : {&ctx->y, &ctx->fck, &ctx->cnt, &ctx->wsum, &ctx->tau, &ctx->dlog, &ctx->part_f,
-                      &ctx->part_i, &ctx->done, &ctx->final_f, &ctx->final_i})
+                      &ctx->part_i, &ctx->done, &ctx->final_f, &ctx->final_i, &ctx->dense})
         free_buf(*b);
+    if (ctx->dense_host) (void)hipHostFree(ctx->dense_host);
     if (ctx->desc_dev) (void)hipFree(ctx->desc_dev);
     if (ctx->desc_host) (void)hipHostFree(ctx->desc_host);
     if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
@@ -164,7 +165,9 @@ int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t 
     const uint32_t d = p->d;
     const bool keep = (p->flags & SIM_KEEP_PATHS) != 0;
     const bool log = (p->flags & SIM_DECISION_LOG) != 0;
-    const uint32_t nblocks = (uint32_t)((R + fw::kBlock - 1) / fw::kBlock);
+    const bool dense = p->chol != nullptr;
+    const uint32_t reps_per_block = dense ? fw::kDenseRepsPerBlock : fw::kBlock;
+    const uint32_t nblocks = (uint32_t)((R + reps_per_block - 1) / reps_per_block);
     const uint32_t n_streams = 1 + 2 * p->n_checkpoints;
     if ((rc = ensure(ctx, ctx->fck, sizeof(double) * (size_t)R * (p->n_checkpoints ? p->n_checkpoints : 1)))) return rc;
     if ((rc = ensure(ctx, ctx->part_f, sizeof(double) * ((size_t)n_streams * fw::kStreamFields + 2) * nblocks))) return rc;
@@ -178,6 +181,21 @@ int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t 
         if ((rc = ensure(ctx, ctx->wsum, sizeof(uint64_t) * (size_t)d * R))) return rc;
     }
     if (log && (rc = ensure(ctx, ctx->dlog, (size_t)T * p->log_rep_count))) return rc;
+
+    // dense L: the two MFMA-ordered FP32 operands and L in FP64, staged through pinned memory
+    const size_t dense_f = (size_t)SIM_MAX_D * SIM_MAX_D;
+    const size_t dense_bytes = 2 * dense_f * sizeof(float) + dense_f * sizeof(double);
+    if (dense) {
+        if ((rc = ensure(ctx, ctx->dense, dense_bytes))) return rc;
+        if (!ctx->dense_host && hipHostMalloc(&ctx->dense_host, dense_bytes, hipHostMallocDefault) != hipSuccess) {
+            ctx->dense_host = nullptr;
+            return set_err(ctx, SIM_ENOMEM, "pinned staging of %zu bytes", dense_bytes);
+        }
+        float *ag = (float *)ctx->dense_host;
+        double *l64 = (double *)(ag + 2 * dense_f);
+        dense_operands(p->chol, d, ag, ag + dense_f, l64);
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->dense.ptr, ctx->dense_host, dense_bytes, hipMemcpyHostToDevice, ctx->stream));
+    }
 
     fill_desc(*ctx->desc_host, p, R, T, seed);
     HIP_TRY(ctx, hipMemcpyAsync(ctx->desc_dev, ctx->desc_host, sizeof(InstanceDesc), hipMemcpyHostToDevice, ctx->stream));
@@ -196,10 +214,18 @@ int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t 
     B.final_i = (uint64_t *)ctx->final_i.ptr;
     B.nblocks = nblocks;
     B.n_streams = n_streams;
+    B.dense_g = dense ? (const float *)ctx->dense.ptr : nullptr;
+    B.dense_v = dense ? (const float *)ctx->dense.ptr + dense_f : nullptr;
+    B.dense_l64 = dense ? (const double *)((const float *)ctx->dense.ptr + 2 * dense_f) : nullptr;
 
     HIP_TRY(ctx, hipEventRecord(ctx->ev_start, ctx->stream));
     int width = 0;
-    rc = fw::launch_fw_paths(*ctx->desc_host, ctx->desc_dev, B, p->state_precision == SIM_FP64, ctx->stream, &width);
+    if (dense) {
+        rc = fw::launch_fw_dense(*ctx->desc_host, ctx->desc_dev, B, ctx->stream);
+        width = 2;
+    } else {
+        rc = fw::launch_fw_paths(*ctx->desc_host, ctx->desc_dev, B, p->state_precision == SIM_FP64, ctx->stream, &width);
+    }
     if (rc == -5) return set_err(ctx, SIM_EUNSUPPORTED, "no kernel for d=%u with this precision and noise", d);
     if (rc) return set_err(ctx, SIM_EDEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
     HIP_TRY(ctx, hipEventRecord(ctx->ev_stop, ctx->stream));
@@ -208,9 +234,9 @@ int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t 
     ctx->last.mu = ctx->last.sigma = ctx->last.chol = ctx->last.w0 = nullptr;
     for (uint32_t j = 0; j < d; ++j) {
         ctx->last_mu[j] = p->mu[j];
-        ctx->last_sigma[j] = p->sigma[j];
+        ctx->last_sigma[j] = dense ? 0.0 : p->sigma[j];
     }
-    ctx->last_diag = true;
+    ctx->last_diag = !dense;
     ctx->R = R;
     ctx->T = T;
     ctx->kernel_width = width;

@@ -98,6 +98,11 @@ struct RunBuffers {
     uint64_t *final_i;    // [(d+1) + 2]
     uint32_t nblocks;
     uint32_t n_streams;
+    // dense correlated returns: sqrt(2 ln 2) L and its transpose, columns permuted and laid out in
+    // the order the matrix-core instruction consumes them, and L itself in FP64 (row-major)
+    const float *dense_g;
+    const float *dense_v;
+    const double *dense_l64;
 };
 
 }  // namespace fw

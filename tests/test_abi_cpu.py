@@ -9,7 +9,7 @@ import tempfile
 import numpy as np
 import pytest
 
-from paper_2404_11631_amd import sim
+from paper_2404_11631_amd import sim, workloads
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "sim.h")
@@ -105,13 +105,31 @@ def _ok_problem(**kw):
     ({"instance_id": 1 << 24}, 10, 10, -1),
     ({"log_reps": (5, 10)}, 10, 10, -1),               # beyond R
     ({"log_reps": (0, 10)}, 10, 10, 0),
-    ({"chol": np.eye(2)}, 10, 10, -5),                  # dense factors not in sim_run
+    ({"chol": np.eye(2)}, 10, 10, -5),                  # dense factors need d = 32 or 64
 ])
 def test_validation(lib, kw, R, T, code):
     rc, msg = sim.validate(_ok_problem(**kw), R, T)
     assert rc == code, msg
     if code:
         assert msg
+
+
+def test_dense_validation(lib):
+    mu, L = workloads.dense_instance(0, 0, 32)
+    ok = dict(mu=mu, chol=L, N=10)
+    assert sim.validate(sim.Problem(**ok), 100, 65535)[0] == 0
+    assert sim.validate(sim.Problem(**ok), 100, 65536)[0] == -5            # 16-bit counts
+    assert sim.validate(sim.Problem(**ok, precision=sim.FP64), 100, 10)[0] == -5
+    up = L.copy()
+    up[3, 7] = 1e-3
+    assert sim.validate(sim.Problem(mu=mu, chol=up, N=10), 100, 10)[0] == -1   # not lower triangular
+    bad = L.copy()
+    bad[5, 2] = np.nan
+    assert sim.validate(sim.Problem(mu=mu, chol=bad, N=10), 100, 10)[0] == -1
+    mu64, L64 = workloads.dense_instance(0, 0, 64)
+    assert sim.validate(sim.Problem(mu=mu64, chol=L64, N=10, noise=sim.NOISE_T, nu=3), 100, 10)[0] == 0
+    mu16, L16 = workloads.dense_instance(0, 0, 16)
+    assert sim.validate(sim.Problem(mu=mu16, chol=L16, N=10), 100, 10)[0] == -5
 
 
 def test_validation_d_range(lib):
