@@ -27,12 +27,13 @@ U64 = 2.0 ** -53
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so (plain gcc, no fast-math, no FMA contraction)."""
-    src = os.path.join(HERE, "oracle.c")
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
+    """Compile oracle.c and cv.c into liboracle.so (plain gcc, no fast-math, no FMA contraction)."""
+    srcs = [os.path.join(HERE, f) for f in ("oracle.c", "cv.c")]
+    stale = any(os.path.getmtime(LIB_PATH) < os.path.getmtime(f) for f in srcs) if os.path.exists(LIB_PATH) else True
+    if force or stale:
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-Wall", "-Wextra", "-fPIC", "-shared", "-o", tmp, src, "-lm"],
+                               "-Wall", "-Wextra", "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"],
                               cwd=HERE)
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -53,7 +54,17 @@ class PathOut(ctypes.Structure):
                 ("tau", ctypes.c_uint32), ("tau_lo", ctypes.c_uint32), ("tau_hi", ctypes.c_uint32),
                 ("n_ambiguous", ctypes.c_uint64), ("n_replayed", ctypes.c_uint64),
                 ("n_mismatch", ctypes.c_uint64), ("first_mismatch", ctypes.c_int64),
-                ("identity_err", ctypes.c_double), ("min_margin", ctypes.c_double)]
+                ("identity_err", ctypes.c_double), ("min_margin", ctypes.c_double),
+                ("feat", ctypes.c_double * (MAX_D + 2))]
+
+
+class CvStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("n_aux", ctypes.c_uint64), ("beta", ctypes.c_double),
+                ("mean_plain", ctypes.c_double), ("var_plain", ctypes.c_double),
+                ("ci95_plain", ctypes.c_double), ("mean_resid", ctypes.c_double),
+                ("var_resid", ctypes.c_double), ("mean_h_aux", ctypes.c_double),
+                ("var_h_aux", ctypes.c_double), ("mean_cv", ctypes.c_double),
+                ("var_est", ctypes.c_double), ("ci95_cv", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -93,6 +104,24 @@ def lib():
                                    ctypes.c_uint64, ctypes.POINTER(PathOut)]
         L.or_reduce.argtypes = [ctypes.POINTER(Problem), ctypes.c_uint64, ctypes.POINTER(PathOut),
                                 ctypes.c_uint64, ctypes.POINTER(Stats)]
+        u64 = ctypes.c_uint64
+        L.or_cv_late_epochs.argtypes = [u64]
+        L.or_cv_late_epochs.restype = u64
+        L.or_cv_weight_norm.argtypes = [u64, ctypes.c_int]
+        L.or_cv_weight_norm.restype = ctypes.c_double
+        L.or_cv_eta_corr.argtypes = [u64, ctypes.c_int, ctypes.c_int]
+        L.or_cv_eta_corr.restype = ctypes.c_double
+        L.or_cv_aux.argtypes = [ctypes.POINTER(Problem), u64, u64, dp]
+        L.or_cv_aux.restype = ctypes.c_int
+        L.or_bf16.argtypes = [ctypes.c_double]
+        L.or_bf16.restype = ctypes.c_double
+        L.or_mlp_param_count.argtypes = [ctypes.c_int]
+        L.or_mlp_param_count.restype = ctypes.c_size_t
+        L.or_mlp_forward.argtypes = [dp, ctypes.c_int, dp, u64, ctypes.c_int, dp]
+        L.or_mlp_grad.argtypes = [dp, ctypes.c_int, dp, dp, u64, ctypes.c_int, dp]
+        L.or_mlp_grad.restype = ctypes.c_double
+        L.or_cv_beta.argtypes = [dp, dp, u64, dp, dp]
+        L.or_cv_estimate.argtypes = [dp, dp, u64, dp, u64, ctypes.c_double, ctypes.POINTER(CvStats)]
         _lib = L
     return _lib
 
@@ -195,3 +224,70 @@ def path_arrays(outs, d, n_ckpt):
     wsum = np.array([[o.wsum[j] for j in range(d)] for o in outs], dtype=np.uint64)
     tau = np.array([o.tau for o in outs], dtype=np.uint64)
     return Y, F, cnt, wsum, tau
+
+
+# ---- control-variate pieces ----------------------------------------------------------------
+
+
+def _arr(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def cv_aux(P: OracleProblem, T: int, k0: int, n: int):
+    """Draws k0 .. k0+n-1 from the exact law of the path features: (n, d+2), and the tries."""
+    out = np.zeros((n, P.d + 2))
+    tries = np.zeros(n, dtype=np.int64)
+    row = np.zeros(P.d + 2)
+    for i in range(n):
+        tries[i] = lib().or_cv_aux(ctypes.byref(P.p), T, k0 + i, _dptr(row))
+        out[i] = row
+    return out, tries
+
+
+def cv_eta_corr(T: int, M: int, d: int) -> float:
+    return lib().or_cv_eta_corr(T, M, d)
+
+
+def cv_weight_norm(T: int, M: int) -> float:
+    return lib().or_cv_weight_norm(T, M)
+
+
+def cv_late_epochs(E: int) -> int:
+    return lib().or_cv_late_epochs(E)
+
+
+def bf16(v: float) -> float:
+    return lib().or_bf16(float(v))
+
+
+def mlp_param_count(F: int) -> int:
+    return lib().or_mlp_param_count(F)
+
+
+def mlp_forward(theta, F: int, x, quantize: bool = False):
+    theta, x = _arr(theta), _arr(x).reshape(-1, F)
+    out = np.zeros(x.shape[0])
+    lib().or_mlp_forward(_dptr(theta), F, _dptr(x), x.shape[0], int(quantize), _dptr(out))
+    return out
+
+
+def mlp_grad(theta, F: int, x, y, quantize: bool = False):
+    """(loss, gradient) of the mean squared error of h over the rows of x against y."""
+    theta, x, y = _arr(theta), _arr(x).reshape(-1, F), _arr(y)
+    g = np.zeros_like(theta)
+    loss = lib().or_mlp_grad(_dptr(theta), F, _dptr(x), _dptr(y), x.shape[0], int(quantize), _dptr(g))
+    return loss, g
+
+
+def cv_beta(Y, H):
+    Y, H = _arr(Y), _arr(H)
+    b, r = ctypes.c_double(), ctypes.c_double()
+    lib().or_cv_beta(_dptr(Y), _dptr(H), Y.shape[0], ctypes.byref(b), ctypes.byref(r))
+    return b.value, r.value
+
+
+def cv_estimate(Y, H, Haux, beta: float) -> CvStats:
+    Y, H, Haux = _arr(Y), _arr(H), _arr(Haux)
+    st = CvStats()
+    lib().or_cv_estimate(_dptr(Y), _dptr(H), Y.shape[0], _dptr(Haux), Haux.shape[0], beta, ctypes.byref(st))
+    return st

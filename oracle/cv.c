@@ -1,0 +1,286 @@
+/*
+ * cv.c -- plain serial FP64 CPU oracle for the control-variate pieces (test infrastructure only;
+ * see oracle.h): the law of the path features, draws from that law, the small MLP surrogate
+ * (forward and backward written as plain loops), and the control-variate estimator.
+ *
+ * The surrogate is not part of the paper's method; it is a variance-reduction layer over the
+ * Monte Carlo estimate of E f(w_T) from Algorithm 1. Its features are summaries of the Gaussian
+ * noise each path consumed, chosen so that their joint law is known exactly:
+ *   u_{e,j} = sum_i z_{e,i,j} / sqrt(N)         ~ N(0,1), i.i.d. over epochs e and assets j,
+ *   q_e     = sum_j sum_i (z_{e,i,j} - zbar)^2  ~ chi-square(d (N-1)), independent of u,
+ *   xi_j    = sum_t (t+1) u_{e(t),j} / sqrt(sum_e C_e^2),  C_e = sum of (t+1) over epoch e,
+ *   eta     = sum over the last W epochs of sum_j u_{e,j} / sqrt(W d),  W = ceil(E / 10),
+ *   zeta    = (sum_e q_e - k) / sqrt(2 k),  k = E d (N-1),  E = ceil(T / M) epochs.
+ * So xi ~ N(0, I_d), eta ~ N(0,1) with Cov(xi_j, eta) = a (or_cv_eta_corr), and zeta is a
+ * standardized chi-square(k) independent of both.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+uint64_t or_cv_late_epochs(uint64_t n_epochs)
+{
+    uint64_t w = (n_epochs + 9) / 10;
+    return w < 1 ? 1 : w;
+}
+
+/* C_e = sum of (t+1) over the iterations t of epoch e (the last epoch may be short). */
+static double epoch_weight(uint64_t e, uint64_t T, int M)
+{
+    const uint64_t t0 = e * (uint64_t)M;
+    uint64_t t1 = t0 + (uint64_t)M;
+    if (t1 > T) t1 = T;
+    double c = 0.0;
+    for (uint64_t t = t0; t < t1; ++t) c += (double)(t + 1);
+    return c;
+}
+
+double or_cv_weight_norm(uint64_t T, int M)
+{
+    const uint64_t E = (T + (uint64_t)M - 1) / (uint64_t)M;
+    double s = 0.0;
+    for (uint64_t e = 0; e < E; ++e) {
+        const double c = epoch_weight(e, T, M);
+        s += c * c;
+    }
+    return sqrt(s);
+}
+
+double or_cv_eta_corr(uint64_t T, int M, int d)
+{
+    const uint64_t E = (T + (uint64_t)M - 1) / (uint64_t)M;
+    const uint64_t W = or_cv_late_epochs(E);
+    double late = 0.0;
+    for (uint64_t e = E - W; e < E; ++e) late += epoch_weight(e, T, M);
+    return late / (or_cv_weight_norm(T, M) * sqrt((double)W * (double)d));
+}
+
+/* Gamma(alpha, 1) by Marsaglia and Tsang, "A simple method for generating gamma variables",
+ * ACM TOMS 26(3), 2000: for shape a >= 1, d = a - 1/3, c = 1/sqrt(9 d); with x ~ N(0,1) and
+ * v = (1 + c x)^3 > 0, accept d v when log U < x^2/2 + d - d v + d log v. A shape alpha < 1 runs
+ * with a = alpha + 1 and scales the result by V^(1/alpha), V uniform (same paper, Section 6).
+ * Try i uses Philox block 64 + i of the draw's stream: its first pair gives x by Box-Muller (cosine
+ * branch), word 2 gives U and word 3 gives V. Returns the number of tries used, or -1 if none of
+ * 64 accepted (then *g = d). */
+static int gamma_mt(double alpha, uint64_t seed, uint32_t instance, uint64_t k, double *g)
+{
+    const int boost = alpha < 1.0;
+    if (boost) alpha += 1.0;
+    const double dd = alpha - 1.0 / 3.0;
+    const double c = 1.0 / sqrt(9.0 * dd);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int i = 0; i < 64; ++i) {
+        uint32_t ctr[4] = {64u + (uint32_t)i, 0u, (uint32_t)k, (OR_DOMAIN_CV_AUX << 24) | (instance & 0xFFFFFFu)};
+        uint32_t w[4];
+        or_philox4x32_10(ctr, key, w);
+        double x;
+        or_normals(seed, OR_DOMAIN_CV_AUX, instance, k, 0, 4u * (64u + (uint32_t)i), 1, &x);
+        const double u = or_uniform(w[2]);
+        const double b = 1.0 + c * x;
+        if (b <= 0.0) continue;
+        const double v = b * b * b;
+        if (log(u) < 0.5 * x * x + dd - dd * v + dd * log(v)) {
+            *g = dd * v;
+            if (boost) *g *= pow(or_uniform(w[3]), 1.0 / (alpha - 1.0));
+            return i + 1;
+        }
+    }
+    *g = dd;
+    return -1;
+}
+
+int or_cv_aux(const or_problem *p, uint64_t T, uint64_t k, double *x)
+{
+    const int d = p->d;
+    double z[OR_MAX_D + 1];
+    or_normals(p->seed, OR_DOMAIN_CV_AUX, p->instance, k, 0, 0, (uint64_t)d + 1, z);
+    const double a = or_cv_eta_corr(T, p->M, d);
+    double s = 0.0;
+    for (int j = 0; j < d; ++j) {
+        x[j] = z[j];
+        s += z[j];
+    }
+    x[d] = a * s + sqrt(1.0 - (double)d * a * a) * z[d];
+    const uint64_t E = (T + (uint64_t)p->M - 1) / (uint64_t)p->M;
+    const double kdof = (double)E * (double)d * (double)(p->N - 1);
+    double g = 0.0;
+    const int tries = gamma_mt(0.5 * kdof, p->seed, p->instance, k, &g);
+    x[d + 1] = (2.0 * g - kdof) / sqrt(2.0 * kdof);
+    return tries;
+}
+
+/* ---------------------------------------------------------------------------------------------
+ * The surrogate h: F -> 64 -> 64 -> 1 with exact GELU, x Phi(x). Parameters theta, flat:
+ *   W1 [64][F], b1 [64], W2 [64][64], b2 [64], w3 [64], b3.
+ * With quantize != 0 every operand of the two matrix products (x, W1, h1, W2 in the forward
+ * pass; the back-propagated pre-activation gradients, h1, x and W2 in the backward pass) is
+ * rounded to bfloat16 (round to nearest even, through binary32), as the matrix cores take them;
+ * everything else stays FP64.
+ * ------------------------------------------------------------------------------------------- */
+double or_bf16(double v)
+{
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u) return v;     /* inf / nan: unchanged */
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    u &= 0xFFFF0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+static double gelu(double a) { return 0.5 * a * (1.0 + erf(a / sqrt(2.0))); }
+
+static double gelu_grad(double a)
+{
+    const double inv_sqrt_2pi = 0.39894228040143267793994605993438;
+    return 0.5 * (1.0 + erf(a / sqrt(2.0))) + a * inv_sqrt_2pi * exp(-0.5 * a * a);
+}
+
+size_t or_mlp_param_count(int F) { return (size_t)64 * F + 64 + 64 * 64 + 64 + 64 + 1; }
+
+typedef struct {
+    const double *W1, *b1, *W2, *b2, *w3, *b3;
+} mlp_view;
+
+static mlp_view view_of(const double *th, int F)
+{
+    mlp_view v;
+    v.W1 = th;
+    v.b1 = v.W1 + 64 * F;
+    v.W2 = v.b1 + 64;
+    v.b2 = v.W2 + 64 * 64;
+    v.w3 = v.b2 + 64;
+    v.b3 = v.w3 + 64;
+    return v;
+}
+
+/* forward of one row; keeps the pre-activations for the backward pass */
+static double forward_row(const mlp_view *m, int F, const double *x, int qz, double *a1, double *a2,
+                          double *h1, double *h2)
+{
+    for (int o = 0; o < 64; ++o) {
+        double acc = 0.0;
+        for (int f = 0; f < F; ++f) {
+            const double w = qz ? or_bf16(m->W1[o * F + f]) : m->W1[o * F + f];
+            const double xv = qz ? or_bf16(x[f]) : x[f];
+            acc += w * xv;
+        }
+        a1[o] = acc + m->b1[o];
+        h1[o] = gelu(a1[o]);
+    }
+    for (int o = 0; o < 64; ++o) {
+        double acc = 0.0;
+        for (int i = 0; i < 64; ++i) {
+            const double w = qz ? or_bf16(m->W2[o * 64 + i]) : m->W2[o * 64 + i];
+            const double hv = qz ? or_bf16(h1[i]) : h1[i];
+            acc += w * hv;
+        }
+        a2[o] = acc + m->b2[o];
+        h2[o] = gelu(a2[o]);
+    }
+    double out = m->b3[0];
+    for (int o = 0; o < 64; ++o) out += m->w3[o] * h2[o];
+    return out;
+}
+
+void or_mlp_forward(const double *theta, int F, const double *x, uint64_t n, int quantize, double *out)
+{
+    const mlp_view m = view_of(theta, F);
+    double a1[64], a2[64], h1[64], h2[64];
+    for (uint64_t r = 0; r < n; ++r) out[r] = forward_row(&m, F, x + r * (uint64_t)F, quantize, a1, a2, h1, h2);
+}
+
+double or_mlp_grad(const double *theta, int F, const double *x, const double *y, uint64_t n, int quantize,
+                   double *grad)
+{
+    const mlp_view m = view_of(theta, F);
+    const size_t P = or_mlp_param_count(F);
+    for (size_t i = 0; i < P; ++i) grad[i] = 0.0;
+    double *gW1 = grad, *gb1 = gW1 + 64 * F, *gW2 = gb1 + 64, *gb2 = gW2 + 64 * 64, *gw3 = gb2 + 64,
+           *gb3 = gw3 + 64;
+    double a1[64], a2[64], h1[64], h2[64], da2[64], da1[64];
+    double loss = 0.0;
+    for (uint64_t r = 0; r < n; ++r) {
+        const double *xr = x + r * (uint64_t)F;
+        const double out = forward_row(&m, F, xr, quantize, a1, a2, h1, h2);
+        const double e = out - y[r];
+        loss += e * e;
+        const double dout = 2.0 * e / (double)n;       /* d/d out of the mean squared error */
+        gb3[0] += dout;
+        for (int o = 0; o < 64; ++o) {
+            gw3[o] += dout * h2[o];
+            da2[o] = dout * m.w3[o] * gelu_grad(a2[o]);
+            gb2[o] += da2[o];
+        }
+        for (int o = 0; o < 64; ++o) {
+            const double g = quantize ? or_bf16(da2[o]) : da2[o];
+            for (int i = 0; i < 64; ++i) gW2[o * 64 + i] += g * (quantize ? or_bf16(h1[i]) : h1[i]);
+        }
+        for (int i = 0; i < 64; ++i) {
+            double acc = 0.0;
+            for (int o = 0; o < 64; ++o) {
+                const double w = quantize ? or_bf16(m.W2[o * 64 + i]) : m.W2[o * 64 + i];
+                acc += w * (quantize ? or_bf16(da2[o]) : da2[o]);
+            }
+            da1[i] = acc * gelu_grad(a1[i]);
+            gb1[i] += da1[i];
+        }
+        for (int o = 0; o < 64; ++o) {
+            const double g = quantize ? or_bf16(da1[o]) : da1[o];
+            for (int f = 0; f < F; ++f) gW1[o * F + f] += g * (quantize ? or_bf16(xr[f]) : xr[f]);
+        }
+    }
+    return loss / (double)n;
+}
+
+/* ---------------------------------------------------------------------------------------------
+ * Control-variate estimator: with h(x) the surrogate, Y_r the outcomes and x'_k independent draws
+ * from the exact law of x,
+ *   Y_cv = mean_r (Y_r - beta h(x_r)) + beta mean_k h(x'_k),
+ * unbiased for E Y whatever h and beta (fixed before the run); its variance is estimated by
+ * var(Y - beta h) / R + beta^2 var(h(x')) / R_aux.
+ * ------------------------------------------------------------------------------------------- */
+static void mean_var(const double *v, uint64_t n, double *mean, double *var)
+{
+    double s = 0.0;
+    for (uint64_t i = 0; i < n; ++i) s += v[i];
+    const double m = n ? s / (double)n : 0.0;
+    double q = 0.0;
+    for (uint64_t i = 0; i < n; ++i) q += (v[i] - m) * (v[i] - m);
+    *mean = m;
+    *var = n > 1 ? q / (double)(n - 1) : 0.0;
+}
+
+void or_cv_beta(const double *Y, const double *H, uint64_t n, double *beta, double *rho2)
+{
+    double my, vy, mh, vh;
+    mean_var(Y, n, &my, &vy);
+    mean_var(H, n, &mh, &vh);
+    double c = 0.0;
+    for (uint64_t i = 0; i < n; ++i) c += (Y[i] - my) * (H[i] - mh);
+    c = n > 1 ? c / (double)(n - 1) : 0.0;
+    *beta = vh > 0.0 ? c / vh : 0.0;
+    *rho2 = (vh > 0.0 && vy > 0.0) ? c * c / (vh * vy) : 0.0;
+}
+
+void or_cv_estimate(const double *Y, const double *H, uint64_t n, const double *Haux, uint64_t n_aux,
+                    double beta, or_cv_stats *st)
+{
+    memset(st, 0, sizeof(*st));
+    st->n = n;
+    st->n_aux = n_aux;
+    st->beta = beta;
+    mean_var(Y, n, &st->mean_plain, &st->var_plain);
+    double *D = (double *)malloc(sizeof(double) * (size_t)(n ? n : 1));
+    for (uint64_t i = 0; i < n; ++i) D[i] = Y[i] - beta * H[i];
+    mean_var(D, n, &st->mean_resid, &st->var_resid);
+    free(D);
+    mean_var(Haux, n_aux, &st->mean_h_aux, &st->var_h_aux);
+    st->mean_cv = st->mean_resid + beta * st->mean_h_aux;
+    st->var_est = st->var_resid / (double)n + beta * beta * st->var_h_aux / (double)n_aux;
+    st->ci95_cv = 1.96 * sqrt(st->var_est);
+    st->ci95_plain = 1.96 * sqrt(st->var_plain / (double)n);
+}

@@ -79,7 +79,8 @@ void or_normals(uint64_t seed, uint32_t domain, uint32_t instance, uint64_t rep,
  * t scaled to unit covariance, chi2 from nu extra normals per sample (normals N d + nu i + k).
  * ------------------------------------------------------------------------------------------- */
 static void draw_returns(const or_problem *p, uint64_t rep, uint64_t epoch, double *Rmat,
-                         double *noise /* N*d: y_i, the unit-covariance noise of each return */)
+                         double *noise /* N*d: y_i, the unit-covariance noise of each return */,
+                         double *zraw /* NULL or N*d: the Gaussian numerators z_i */)
 {
     const int d = p->d, N = p->N;
     const uint64_t n_main = (uint64_t)N * (uint64_t)d;
@@ -98,6 +99,8 @@ static void draw_returns(const or_problem *p, uint64_t rep, uint64_t epoch, doub
             scale = sqrt((double)(p->nu - 2) / chi2);
         }
         for (int j = 0; j < d; ++j) y[j] = scale * z[(uint64_t)i * d + j];
+        if (zraw)
+            for (int j = 0; j < d; ++j) zraw[(size_t)i * d + j] = z[(uint64_t)i * d + j];
         for (int j = 0; j < d; ++j) {
             double acc = 0.0;
             for (int k = 0; k <= j; ++k) acc += p->chol[j * d + k] * y[k];
@@ -131,7 +134,7 @@ static void sample_statistics(const or_problem *p, const double *Rmat, const dou
 void or_draw_returns(const or_problem *p, uint64_t rep, uint64_t epoch, double *Rmat)
 {
     double *noise = (double *)malloc(sizeof(double) * (size_t)p->N * p->d);
-    draw_returns(p, rep, epoch, Rmat, noise);
+    draw_returns(p, rep, epoch, Rmat, noise, NULL);
     free(noise);
 }
 
@@ -141,7 +144,7 @@ void or_sample_gradient(const or_problem *p, uint64_t rep, uint64_t epoch, const
     const int d = p->d, N = p->N;
     double *Rmat = (double *)malloc(sizeof(double) * (size_t)N * d);
     double *noise = (double *)malloc(sizeof(double) * (size_t)N * d);
-    draw_returns(p, rep, epoch, Rmat, noise);
+    draw_returns(p, rep, epoch, Rmat, noise, NULL);
     sample_statistics(p, Rmat, w, rbar, sigma_w);
     for (int j = 0; j < d; ++j) grad[j] = 2.0 * p->lambda * sigma_w[j] - rbar[j];
     free(noise);
@@ -159,6 +162,27 @@ double or_objective(const or_problem *p, const double *w)
     }
     for (int j = 0; j < d; ++j) lin += p->mu[j] * w[j];
     return p->lambda * quad - lin;
+}
+
+/* Per-epoch noise summaries for the control-variate features: u_j = sum_i z_ij / sqrt(N), which
+ * is N(0,1), and q = sum_j sum_i (z_ij - zbar_j)^2, which is chi-square with d (N-1) degrees of
+ * freedom and independent of u (sample mean and sample variance of a Gaussian sample). */
+static void cv_epoch_summaries(int d, int N, const double *z, double *u, double *q)
+{
+    double qs = 0.0;
+    for (int j = 0; j < d; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < N; ++i) s += z[(size_t)i * d + j];
+        const double mean = s / (double)N;
+        double ss = 0.0;
+        for (int i = 0; i < N; ++i) {
+            const double e = z[(size_t)i * d + j] - mean;
+            ss += e * e;
+        }
+        u[j] = s / sqrt((double)N);
+        qs += ss;
+    }
+    *q = qs;
 }
 
 /* ---------------------------------------------------------------------------------------------
@@ -183,6 +207,12 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
     double *vabs = (double *)malloc(sizeof(double) * (size_t)d);
     double *habs = (double *)malloc(sizeof(double) * (size_t)d);
     double *pabs = (double *)malloc(sizeof(double) * (size_t)N);
+    double *zraw = (double *)malloc(sizeof(double) * (size_t)N * d);
+    double *u_e = (double *)malloc(sizeof(double) * (size_t)d);
+    double *xi = (double *)calloc((size_t)d, sizeof(double));
+    double q_e = 0.0, eta = 0.0, zeta = 0.0;
+    const uint64_t n_epochs = (T + (uint64_t)M - 1) / (uint64_t)M;
+    const uint64_t late = or_cv_late_epochs(n_epochs);
 
     memset(out, 0, sizeof(*out));
     out->tau = out->tau_lo = out->tau_hi = OR_TAU_NONE;
@@ -194,7 +224,15 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
     int ck = 0;
     for (uint64_t t = 0; t < T; ++t) {
         const uint64_t epoch = t / (uint64_t)M;        /* k = t div M, m = t mod M */
-        if (t % (uint64_t)M == 0) draw_returns(p, rep, epoch, Rmat, noise);   /* resample */
+        if (t % (uint64_t)M == 0) {                    /* resample */
+            draw_returns(p, rep, epoch, Rmat, noise, zraw);
+            cv_epoch_summaries(d, N, zraw, u_e, &q_e);
+            if (epoch >= n_epochs - late) {
+                for (int j = 0; j < d; ++j) eta += u_e[j];
+            }
+            zeta += q_e;
+        }
+        for (int j = 0; j < d; ++j) xi[j] += (double)(t + 1) * u_e[j];
 
         /* gradient of the sample objective at w_m */
         sample_statistics(p, Rmat, w, rbar, sw);
@@ -290,12 +328,22 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
     }
     out->y = or_objective(p, w);   /* return w: the outcome is f at the last iterate */
 
+    /* control-variate features (noise summaries with a known joint law) */
+    {
+        const double xnorm = or_cv_weight_norm(T, M);
+        for (int j = 0; j < d; ++j) out->feat[j] = xi[j] / xnorm;
+        out->feat[d] = eta / sqrt((double)late * (double)d);
+        const double k = (double)n_epochs * (double)d * (double)(N - 1);
+        out->feat[d + 1] = (zeta - k) / sqrt(2.0 * k);
+    }
+
     double tt = (double)T * (double)(T + 1);
     for (int j = 0; j < d; ++j) {
         double closed = 2.0 * (double)out->wsum[j] / tt;
         double e = fabs(w[j] - closed);
         if (e > out->identity_err) out->identity_err = e;
     }
+    free(xi); free(u_e); free(zraw);
     free(pabs); free(habs); free(vabs);
     free(vals); free(sw); free(rbar); free(g); free(w); free(noise); free(Rmat);
     return 0;

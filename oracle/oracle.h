@@ -19,6 +19,7 @@
 #ifndef PAPER_2404_11631_ORACLE_H
 #define PAPER_2404_11631_ORACLE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -65,6 +66,7 @@ typedef struct {
     int64_t first_mismatch;         /* step of the first mismatch, or -1 */
     double identity_err;            /* max_j |w_T - 2 wsum/(T(T+1))| (recurrence vs closed form) */
     double min_margin;              /* smallest LMO margin seen along the path */
+    double feat[OR_MAX_D + 2];      /* control-variate features xi_0..xi_{d-1}, eta, zeta */
 } or_path_out;
 
 typedef struct {
@@ -116,6 +118,44 @@ int or_run_range(const or_problem *p, uint64_t r0, uint64_t r1, uint64_t T, or_p
 /* Cross-path statistics of n per-path outputs. */
 void or_reduce(const or_problem *p, uint64_t T, const or_path_out *paths, uint64_t n,
                or_stats *st);
+
+/* ---- control-variate pieces (cv.c) ------------------------------------------------------ */
+
+typedef struct {
+    uint64_t n, n_aux;
+    double beta;
+    double mean_plain, var_plain, ci95_plain;   /* plain Monte Carlo: mean, variance of Y, CI */
+    double mean_resid, var_resid;               /* Y - beta h(x) over the paths */
+    double mean_h_aux, var_h_aux;               /* h over the draws from the law of x */
+    double mean_cv, var_est, ci95_cv;           /* the estimate, its variance, 95% half-width */
+} or_cv_stats;
+
+/* Epochs E = ceil(T/M); the late window holds the last ceil(E/10) epochs. */
+uint64_t or_cv_late_epochs(uint64_t n_epochs);
+/* sqrt(sum_e C_e^2), C_e = sum of (t+1) over the iterations of epoch e. */
+double or_cv_weight_norm(uint64_t T, int M);
+/* Cov(xi_j, eta) of the path features. */
+double or_cv_eta_corr(uint64_t T, int M, int d);
+/* Draw k (stream domain 2) from the exact joint law of the d+2 path features; returns the
+ * gamma sampler's tries, or -1 if it did not accept within 64. */
+int or_cv_aux(const or_problem *p, uint64_t T, uint64_t k, double *x);
+
+/* bfloat16 rounding (to nearest even, through binary32). */
+double or_bf16(double v);
+/* Parameters of the F -> 64 -> 64 -> 1 surrogate: 64 F + 4289. */
+size_t or_mlp_param_count(int F);
+/* h(x_r) for n rows of F features (row-major). quantize: round matrix-product operands to bf16. */
+void or_mlp_forward(const double *theta, int F, const double *x, uint64_t n, int quantize, double *out);
+/* Mean squared error of h over n rows against y, and its gradient with respect to theta. */
+double or_mlp_grad(const double *theta, int F, const double *x, const double *y, uint64_t n, int quantize,
+                   double *grad);
+
+/* beta = Cov(Y, H) / Var(H) and rho^2 = Corr(Y, H)^2. */
+void or_cv_beta(const double *Y, const double *H, uint64_t n, double *beta, double *rho2);
+/* The control-variate estimate from path outcomes Y, surrogate values H = h(x_r), and surrogate
+ * values Haux at draws from the law of x. */
+void or_cv_estimate(const double *Y, const double *H, uint64_t n, const double *Haux, uint64_t n_aux,
+                    double beta, or_cv_stats *st);
 
 #ifdef __cplusplus
 }
