@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -127,6 +128,9 @@ def main():
     ap.add_argument("--workload", default="paper_scale", choices=("paper_scale", "stress"))
     ap.add_argument("--reps", type=int, default=0, help="replications (stress only; 0: the full 1e7)")
     ap.add_argument("--copy-probe", type=int, default=0)
+    ap.add_argument("--no-cv", action="store_true", help="skip the control-variate leg")
+    ap.add_argument("--cv-train-runs", type=int, default=10, help="training simulations of 1e6 paths")
+    ap.add_argument("--cv-epochs", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the simulation shards replications across GPUs only by "
@@ -165,6 +169,7 @@ def main():
         kernel_ms.append(st.kernel_ms)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    cv = None if args.no_cv else cv_leg(ctx, sim, w, mu, sigma, args)
     ctx.close()
 
     ms_step = 1e3 * wall / args.steps
@@ -192,9 +197,81 @@ def main():
                      "kernel_ms": kavg, "ops_per_path_step": ops_per_path_step(d, N)},
         "stats": {"mean": st.mean, "ci95_halfwidth": st.ci95_halfwidth, "f_star": st.f_star},
     }
+    if cv is not None:
+        line["cv"] = cv
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, mu, sigma, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def cv_leg(ctx, sim, w, mu, sigma, args):
+    """Wall time to a 95% CI half-width h for E f(w_T) on the paper-scale instance, plain Monte
+    Carlo vs the control variate, each by Stein's two-stage procedure: a pilot of 2^16 paths
+    estimates the standard deviation, then a fresh run of R* = ceil((1.96 s / h)^2) paths. The
+    control-variate form's pilot and main run include features, surrogate evaluation and the draws
+    from the features' law; its one-off training (simulation of the pairs, Adam, beta on a
+    held-out run) is reported separately. Reported at h = 1e-3 and at the h for which the plain
+    form needs 1e6 paths (below ~1e5 paths both forms are bound by one path's latency)."""
+    import torch
+
+    T, N = w["T"], w["N"]
+    p = sim.Problem(mu=mu, sigma=sigma, N=N, M=w["M"], precision=sim.FP32, checkpoints=(T,))
+    cvw = __import__("paper_2404_11631_amd.workloads", fromlist=["WORKLOADS"]).WORKLOADS["control_variate"]
+    eval_seed = cvw["seed"]
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t
+
+    t0 = time.perf_counter()
+    fit = ctx.cv_fit(p, T, 1, n_runs=args.cv_train_runs, epochs=args.cv_epochs, R_train=1_000_000,
+                     R_pilot=1 << 16, batch=4096, lr=1e-3)
+    train_wall = time.perf_counter() - t0
+    print(f"[cv] trained on {fit.n_train} pairs: loss {fit.loss_first_epoch:.4f} -> {fit.loss_last_epoch:.4f}, "
+          f"beta {fit.beta:.3f}, pilot rho2 {fit.rho2:.3f}, {train_wall:.1f} s", file=sys.stderr, flush=True)
+
+    pilot_R = 1 << 16
+
+    def plain_run(R, seed):
+        ctx.run(p, R, T, seed)
+        return ctx.stats()
+
+    def cv_run(R, seed, R_aux):
+        return ctx.run_cv(p, R, T, seed, R_aux)
+
+    # pilots (each form's own): standard deviation of Y, and of Y - beta h with the aux variance
+    ps, plain_pilot_s = timed(lambda: plain_run(pilot_R, eval_seed + 1))
+    cs, cv_pilot_s = timed(lambda: cv_run(pilot_R, eval_seed + 2, 1 << 20))
+    s_plain = math.sqrt(ps.var)
+    s_resid = math.sqrt(max(cs.var_resid, 0.0))
+    beta2_vh = cs.beta ** 2 * cs.var_h_aux
+    out = {"workload": "control_variate", "instance": "paper_scale (seed 0)", "T": T, "d": len(mu), "N": N,
+           "train": {"pairs": fit.n_train, "steps": fit.steps, "epochs": args.cv_epochs, "wall_s": train_wall,
+                     "sim_ms": fit.sim_ms, "train_ms": fit.train_ms, "loss_first_epoch": fit.loss_first_epoch,
+                     "loss_last_epoch": fit.loss_last_epoch, "beta": fit.beta, "pilot_rho2": fit.rho2},
+           "pilot_paths": pilot_R, "sd_plain": s_plain, "sd_resid": s_resid,
+           "variance_ratio": ps.var / max(cs.var_resid, 1e-300), "targets": []}
+    for h in (1e-3, 1.96 * s_plain / 1000.0):
+        r_plain = max(2, math.ceil((1.96 * s_plain / h) ** 2))
+        r_cv = max(2, math.ceil((1.96 * s_resid / h) ** 2))
+        r_aux = max(1 << 20, 50 * r_cv)
+        r_aux = min(r_aux, 1 << 31)
+        pm, plain_s = timed(lambda: plain_run(r_plain, eval_seed + 3))
+        cm, cv_s = timed(lambda: cv_run(r_cv, eval_seed + 4, r_aux))
+        out["targets"].append({
+            "h": h,
+            "plain": {"R": r_plain, "pilot_s": plain_pilot_s, "main_s": plain_s, "total_s": plain_pilot_s + plain_s,
+                      "mean": pm.mean, "ci95": pm.ci95_halfwidth},
+            "cv": {"R": r_cv, "R_aux": r_aux, "pilot_s": cv_pilot_s, "main_s": cv_s, "total_s": cv_pilot_s + cv_s,
+                   "mean": cm.mean_cv, "ci95": cm.ci95_cv, "plain_mean_same_paths": cm.mean_plain},
+            "speedup": (plain_pilot_s + plain_s) / (cv_pilot_s + cv_s),
+        })
+        print(f"[cv] h={h:.2e}: plain R={r_plain} {plain_pilot_s + plain_s:.3f} s, cv R={r_cv} "
+              f"{cv_pilot_s + cv_s:.3f} s", file=sys.stderr, flush=True)
+    return out
 
 
 def stress(args):

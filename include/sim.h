@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 1u
+#define SIM_ABI_VERSION 2u
 #define SIM_MAX_D 64u          /* assets per instance */
 #define SIM_MAX_CKPT 8u        /* checkpoints per run */
 #define SIM_TAU_NONE 0xFFFFFFFFu
@@ -59,7 +59,8 @@ typedef enum { SIM_FP32 = 0, SIM_FP64 = 1 } sim_precision;
 
 typedef enum {
     SIM_KEEP_PATHS = 1u,    /* keep per-path records (Y, checkpoints, cnt, wsum, tau) */
-    SIM_DECISION_LOG = 2u   /* log every decision of replications [log_rep_begin, +log_rep_count) */
+    SIM_DECISION_LOG = 2u,  /* log every decision of replications [log_rep_begin, +log_rep_count) */
+    SIM_CV_FEATURES = 4u    /* write each path's d+2 control-variate features (see sim_path_view.x) */
 } sim_flag;
 
 /* One problem instance (Eq. (3)) and the sampling knobs of Algorithm 1. */
@@ -104,6 +105,18 @@ typedef struct {
     double path_steps_per_s;                                /* R T / kernel time */
 } sim_stats_out;
 
+/* Control-variate features (SIM_CV_FEATURES). A variance-reduction layer over the Monte Carlo
+ * estimate of E f(w_T); not part of the paper's method. With z the Gaussian numerators a path draws
+ * (for t noise, before the chi-square scaling), per epoch e of E = ceil(T/M):
+ *   u_ej = sum_i z_eij / sqrt(N) and q_e = sum_j sum_i (z_eij - zbar_ej)^2;
+ *   xi_j = sum_e C_e u_ej / sqrt(sum_e C_e^2), C_e = sum of (t+1) over the iterations of epoch e
+ *          (the weights the step rule 2/(t+2) gives each iteration in w_T);
+ *   eta  = sum of u_ej over the last W = ceil(E/10) epochs and all j, over sqrt(W d);
+ *   zeta = (sum_e q_e - k) / sqrt(2k), k = E d (N-1).
+ * Their joint law is exact: xi ~ N(0, I_d), eta ~ N(0,1) with Cov(xi_j, eta) = sum of C_e over the
+ * late epochs / (sqrt(sum_e C_e^2) sqrt(W d)), zeta a standardized chi-square(k) independent of both.
+ * Supported with FP32 state, diagonal Sigma and T <= 92681. */
+
 /* Device pointers (owned by the context) to the per-path records of the last run, structure of
  * arrays indexed [field][r]. Fields not produced by the run are NULL. */
 typedef struct {
@@ -117,6 +130,9 @@ typedef struct {
     const uint8_t *decisions;   /* [T][log_rep_count] decisions, 0 = origin, j+1 = e_j */
     uint64_t log_rep_begin, log_rep_count;
     uint64_t f_ckpt_stride;     /* elements between checkpoint rows (R, or the batch total) */
+    const float *x;             /* SIM_CV_FEATURES: [d+2][R] features xi_0..xi_{d-1}, eta, zeta */
+    uint32_t n_features;        /* d+2 when x is set, else 0 */
+    uint32_t pad_;
 } sim_path_view;
 
 /* Creates a context on HIP device `device`, launching on `hip_stream` (a hipStream_t, or NULL
@@ -173,6 +189,85 @@ int sim_batch_stats(sim_ctx *ctx, uint32_t instance, sim_stats_out *out);
  * the lanes per replication and tile count the plan gave it; synchronises the stream. */
 int sim_batch_paths(sim_ctx *ctx, uint32_t instance, sim_path_view *out, uint32_t *lanes_per_rep,
                     uint32_t *n_tiles);
+
+/* ---- control variate ----------------------------------------------------------------------
+ * A variance-reduction layer over the Monte Carlo estimate of E f(w_T) (not part of the paper's
+ * method): a surrogate h(x) of Y = f(w_T) from the path's features x (SIM_CV_FEATURES), trained
+ * on pairs the simulation generates, and the estimator
+ *   Y_cv = mean_r (Y_r - beta h(x_r)) + beta mean_k h(x'_k),
+ * with x'_k drawn from the features' exact law. Y_cv is unbiased for E Y whatever h and beta
+ * (both fixed before the run); the plain mean stays the fallback and the judge of its bias.
+ * The surrogate: F = d + 2 inputs -> 64 -> 64 -> 1, exact GELU (x Phi(x)), parameters flat
+ * theta = W1 [64][F], b1 [64], W2 [64][64], b2 [64], w3 [64], b3 (P = 64 F + 4289 floats), matrix
+ * products on the matrix cores with bfloat16 operands and FP32 accumulation, FP32 master weights,
+ * Adam. */
+
+typedef struct {
+    uint32_t n_runs;        /* training simulations, seeds seed, seed+1, ...; >= 1 */
+    uint32_t epochs;        /* passes over the training pairs, >= 1 */
+    uint64_t R_train;       /* replications per training simulation, >= batch */
+    uint64_t R_pilot;       /* replications of the held-out simulation (seed + n_runs) fitting beta */
+    uint32_t batch;         /* minibatch rows, a multiple of 128 in [128, 65536] */
+    uint32_t reinit;        /* 1: fresh weights (Philox stream domain 3 of seed); 0: continue */
+    double lr;              /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
+} sim_cv_opts;
+
+typedef struct {
+    uint64_t n_train, steps;
+    double y_mean, y_sd;    /* standardization of the training target */
+    double loss_first_epoch, loss_last_epoch;   /* mean squared error of the standardized target */
+    double beta, rho2;      /* Cov(Y, h) / Var(h) and Corr(Y, h)^2 on the pilot */
+    double pilot_var_y;
+    double sim_ms, train_ms, pilot_ms;          /* device time of each phase (HIP events) */
+} sim_cv_fit_out;
+
+typedef struct {
+    uint64_t R, R_aux;
+    double beta;
+    double mean_plain, var_plain, ci95_plain;   /* plain Monte Carlo over the same paths */
+    double mean_resid, var_resid;               /* Y - beta h(x) */
+    double mean_h_aux, var_h_aux;               /* h over the aux draws */
+    double mean_cv, var_est, ci95_cv;           /* estimate, its variance, 95% half-width */
+    double rho2;                                /* Corr(Y, h)^2 on this run */
+    uint64_t aux_gamma_failures;                /* aux draws whose gamma sampler did not accept (0) */
+    double kernel_ms;                           /* device time: paths, features, h, aux, reductions */
+} sim_cv_stats_out;
+
+/* Trains the surrogate for problem p (with T iterations) on the device: runs n_runs simulations
+ * of R_train replications with features, standardizes Y, takes epochs x (n / batch) Adam steps
+ * over minibatches in a fresh affine permutation of the pairs per epoch, then fits beta on a
+ * held-out pilot run. Synchronous. Supported problems: those SIM_CV_FEATURES supports. */
+int sim_cv_fit(sim_ctx *ctx, const sim_params *p, uint64_t T, uint64_t seed, const sim_cv_opts *o,
+               sim_cv_fit_out *out);
+
+/* Control-variate estimate of E f(w_T) from R replications (seed `seed`) and R_aux draws from the
+ * features' law (stream domain 2 of `seed`), with the fitted surrogate and beta. Synchronous. */
+int sim_run_cv(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed, uint64_t R_aux,
+               sim_cv_stats_out *out);
+
+/* Device pointers to the last sim_run_cv: Y [R], h(x_r) [R], x [F][R], and the last chunk of aux
+ * draws x' [F][n_aux] with h(x') [n_aux] (all of them when R_aux <= 4,194,304). */
+typedef struct {
+    uint64_t R, n_aux;
+    uint32_t F, pad_;
+    const double *y;
+    const float *h, *x, *x_aux, *h_aux;
+} sim_cv_view;
+int sim_cv_paths(sim_ctx *ctx, sim_cv_view *out);
+
+/* Surrogate primitives (host arrays). set/get: P = 64 F + 4289 parameters, F in [3, 66];
+ * forward: raw network outputs of n rows of features x [F][n] (feature-major); grad: the mean
+ * squared error against y [n] and its gradient [P] at the current parameters. */
+int sim_mlp_set_params(sim_ctx *ctx, uint32_t F, const float *theta);
+int sim_mlp_get_params(sim_ctx *ctx, uint32_t F, float *theta);
+int sim_mlp_forward(sim_ctx *ctx, const float *x, uint64_t n, float *out);
+int sim_mlp_grad(sim_ctx *ctx, const float *x, const float *y, uint64_t n, float *grad, double *loss);
+
+/* Draws k0 .. k0+n-1 from the exact law of the features of problem p with T iterations (stream
+ * domain 2 of seed) into host x [F][n]; failures (may be NULL): draws whose gamma sampler did not
+ * accept within 64 tries. */
+int sim_cv_aux_draws(sim_ctx *ctx, const sim_params *p, uint64_t T, uint64_t seed, uint64_t k0, uint64_t n,
+                     float *x, uint64_t *failures);
 
 /* Statistics of the last run; synchronises the stream. */
 int sim_stats(sim_ctx *ctx, sim_stats_out *out);

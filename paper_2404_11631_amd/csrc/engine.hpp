@@ -7,6 +7,7 @@
 
 #include "../../include/sim.h"
 #include "host_core.hpp"
+#include "mlp.hpp"
 #include "sim_types.hpp"
 
 namespace fw {
@@ -44,6 +45,19 @@ struct BatchState {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
+// Control-variate surrogate, its training data and the estimator's buffers.
+struct CvState {
+    bool have_mlp = false, have_fit = false;
+    int F = 0;
+    DevBuf theta, w1a, w2a, w2t, mom1, mom2, part, grad, loss_hist;
+    DevBuf xtrain, ytrain, ttrain;        // training pairs: [F][n] features, Y (FP64), target (FP32)
+    DevBuf xio, yio, hout;                // staging of sim_mlp_forward / sim_mlp_grad, and h(x) of a run
+    DevBuf xaux, haux, mpart, mout, mdone, fails;
+    uint64_t n_train = 0, n_steps = 0, R = 0, n_aux_last = 0;
+    double y_mean = 0.0, y_sd = 1.0, beta = 0.0, rho2 = 0.0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
 struct sim_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -52,6 +66,7 @@ struct sim_ctx {
     InstanceDesc *desc_dev = nullptr;
     DevBuf y, fck, cnt, wsum, tau, dlog, part_f, part_i, done, final_f, final_i;
     DevBuf dense;                         // dense-L operands: Ag, Av (FP32), L (FP64)
+    DevBuf feat;                          // control-variate features [(d+2)][R]
     void *dense_host = nullptr;           // pinned staging of the same
     RunBuffers bufs{};
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
@@ -62,11 +77,13 @@ struct sim_ctx {
     uint64_t R = 0, T = 0;
     int kernel_width = 0;
     BatchState batch;
+    CvState cv;
 };
 
 
 namespace fw {
 namespace host {
+int run_impl(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed, uint32_t internal);
 int set_err(sim_ctx *ctx, int code, const char *fmt, ...);
 int ensure(sim_ctx *ctx, DevBuf &b, size_t bytes);
 void free_buf(DevBuf &b);

@@ -235,6 +235,7 @@ __global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P,
                                         2.0 / (static_cast<double>(T) * static_cast<double>(T + 1)), sS);
     const bool leader = active && p == 0;
 
+    if (active && p == 0 && (P->flags & 8u) && !(P->flags & 1u)) B.y[r64] = y;   // outcomes only
     if (active && (P->flags & 1u)) {
         if (p == 0) {
             B.y[r64] = y;

@@ -85,7 +85,7 @@ struct LaneResult {
 };
 
 // One replication of Algorithm 1; returns Y and tau, leaves decision counts in cnt.
-template <int D, bool EXACT, typename Real, int NOISE, typename WS>
+template <int D, bool EXACT, typename Real, int NOISE, typename WS, bool FEAT>
 __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, const RunBuffers &B,
                                          uint32_t r, uint32_t (&cnt)[D + 1], WS (&S)[D],
                                          LaneResult &res)
@@ -108,19 +108,28 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
     uint32_t ck = 0;
     uint64_t next_ckpt = n_ckpt ? P->ckpt[0] : 0;
     uint32_t epoch = 0, m_in_epoch = 0;   // t = epoch * M + m_in_epoch
+    // control-variate feature accumulators (FP64): sum_e C_e u_ej, late-window sum of u, sum_e q_e
+    double fxi[D];
+    double feta = 0.0, fzeta = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) fxi[j] = 0.0;
 
     for (uint64_t t = 0; t < T; ++t) {
         // iterate w_t (scale factor of the signature) and v = sigma .* w_t
         const double cw = t == 0 ? 0.0 : 2.0 / (static_cast<double>(t) * static_cast<double>(t + 1));
         const Real cwr = static_cast<Real>(cw);
         Real v[D], s1[D], s2[D];
+        Real sq[D], g1[D];   // FEAT: sum of squares and (t noise) sum of the Gaussian numerators
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             const Real w = (t == 0) ? (P->has_w0 ? C.w0(j) : Real(0)) : static_cast<Real>(S[j]) * cwr;
             v[j] = (j < d) ? C.sz(j) * w : Real(0);
             s1[j] = Real(0);
             s2[j] = Real(0);
+            sq[j] = Real(0);
+            g1[j] = Real(0);
         }
+        const bool feat_epoch = FEAT && m_in_epoch == 0;   // draws repeat within an epoch
 
         if constexpr (EXACT && NOISE == 0) {
             // groups of G samples hold a whole number of Philox blocks: static packing
@@ -147,6 +156,7 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
                     for (int j = 0; j < D; ++j) {
                         s1[j] += z[s * D + j];
                         s2[j] = fma(z[s * D + j], dot, s2[j]);
+                        if constexpr (FEAT) sq[j] = fma(z[s * D + j], z[s * D + j], sq[j]);
                     }
                 }
             }
@@ -175,6 +185,7 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
                         for (int j = 0; j < D; ++j) {
                             s1[j] += z[s * D + j];
                             s2[j] = fma(z[s * D + j], dot, s2[j]);
+                            if constexpr (FEAT) sq[j] = fma(z[s * D + j], z[s * D + j], sq[j]);
                         }
                     }
                 }
@@ -188,6 +199,13 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
                 Real z[D];
 #pragma unroll
                 for (int j = 0; j < D; ++j) z[j] = (j < d) ? cur.next(epoch, r, dom, k0, k1) : Real(0);
+                if constexpr (FEAT) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) {
+                        sq[j] = fma(z[j], z[j], sq[j]);
+                        if constexpr (NOISE == 1) g1[j] += z[j];
+                    }
+                }
                 if constexpr (NOISE == 1) {
                     Real ss = Real(0);
                     for (uint32_t k = 0; k < P->nu; ++k) {
@@ -206,6 +224,27 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
                     s1[j] += z[j];
                     s2[j] = fma(z[j], dot, s2[j]);
                 }
+            }
+        }
+
+        if constexpr (FEAT) {
+            if (feat_epoch) {
+                // C_e = sum of (t+1) over the iterations of this epoch, [t, min(t + M, T))
+                const uint64_t t1 = (t + M < T) ? t + M : T;
+                const double ce = 0.5 * (static_cast<double>(t1) * static_cast<double>(t1 + 1) -
+                                         static_cast<double>(t) * static_cast<double>(t + 1));
+                Real qsum = Real(0), usum = Real(0);
+#pragma unroll
+                for (int j = 0; j < D; ++j) {
+                    if (j < d) {
+                        const Real u = (NOISE == 1) ? g1[j] : s1[j];
+                        fxi[j] = fma(ce, static_cast<double>(u), fxi[j]);
+                        qsum += sq[j] - u * u * C.inv_n();
+                        usum += u;
+                    }
+                }
+                fzeta += static_cast<double>(qsum);
+                if (epoch >= P->cv_late_begin) feta += static_cast<double>(usum);
             }
         }
 
@@ -257,12 +296,20 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
     res.y = objective_from_signature<D, EXACT, WS>(
         P, S, 2.0 / (static_cast<double>(T) * static_cast<double>(T + 1)));
     res.tau = tau;
+    if constexpr (FEAT) {
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            if (j < d) B.feat[static_cast<uint64_t>(j) * R + r] = static_cast<float>(fxi[j] * P->cv_xi_scale);
+        B.feat[static_cast<uint64_t>(d) * R + r] = static_cast<float>(feta * P->cv_eta_scale);
+        B.feat[static_cast<uint64_t>(d + 1) * R + r] =
+            static_cast<float>((fzeta * P->cv_kappa2 - P->cv_k) * P->cv_zeta_inv);
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
 // kernel: paths + per-workgroup partials + last-workgroup finalisation
 // ---------------------------------------------------------------------------------------------
-template <int D, bool EXACT, typename Real, int NOISE, typename WS>
+template <int D, bool EXACT, typename Real, int NOISE, typename WS, bool FEAT>
 __global__ __launch_bounds__(kBlock) void fw_paths_kernel(const InstanceDesc *__restrict__ P,
                                                           RunBuffers B)
 {
@@ -279,7 +326,8 @@ __global__ __launch_bounds__(kBlock) void fw_paths_kernel(const InstanceDesc *__
     WS S[D];
     LaneResult res{0.0, kTauNone};
     if (active) {
-        run_path<D, EXACT, Real, NOISE, WS>(P, B, static_cast<uint32_t>(r), cnt, S, res);
+        run_path<D, EXACT, Real, NOISE, WS, FEAT>(P, B, static_cast<uint32_t>(r), cnt, S, res);
+        if ((P->flags & 8u) && !(P->flags & 1u)) B.y[r] = res.y;   // outcomes only
         if (P->flags & 1u) {
             B.y[r] = res.y;
             B.tau[r] = res.tau;
@@ -416,10 +464,10 @@ __global__ __launch_bounds__(kBlock) void fw_paths_kernel(const InstanceDesc *__
 // ---------------------------------------------------------------------------------------------
 using KernelFn = void (*)(const InstanceDesc *, RunBuffers);
 
-template <int D, bool EXACT, typename Real, int NOISE, typename WS>
+template <int D, bool EXACT, typename Real, int NOISE, typename WS, bool FEAT>
 constexpr KernelFn kfn()
 {
-    return &fw_paths_kernel<D, EXACT, Real, NOISE, WS>;
+    return &fw_paths_kernel<D, EXACT, Real, NOISE, WS, FEAT>;
 }
 
 struct KernelChoice {
@@ -430,50 +478,56 @@ struct KernelChoice {
 
 // Exact-width kernels pack each group of samples into whole Philox blocks at compile time; the
 // generic ones read the stream through a cursor and take d <= D at run time.
-template <typename Real, typename WS>
+template <typename Real, typename WS, bool FEAT>
 static KernelChoice choose_gauss(uint32_t d)
 {
     switch (d) {
-    case 1: return {kfn<1, true, Real, 0, WS>(), 1, true};
-    case 2: return {kfn<2, true, Real, 0, WS>(), 2, true};
-    case 3: return {kfn<3, true, Real, 0, WS>(), 3, true};
-    case 4: return {kfn<4, true, Real, 0, WS>(), 4, true};
-    case 5: return {kfn<5, true, Real, 0, WS>(), 5, true};
-    case 6: return {kfn<6, true, Real, 0, WS>(), 6, true};
-    case 8: return {kfn<8, true, Real, 0, WS>(), 8, true};
-    case 10: return {kfn<10, true, Real, 0, WS>(), 10, true};
-    case 12: return {kfn<12, true, Real, 0, WS>(), 12, true};
-    case 16: return {kfn<16, true, Real, 0, WS>(), 16, true};
+    case 1: return {kfn<1, true, Real, 0, WS, FEAT>(), 1, true};
+    case 2: return {kfn<2, true, Real, 0, WS, FEAT>(), 2, true};
+    case 3: return {kfn<3, true, Real, 0, WS, FEAT>(), 3, true};
+    case 4: return {kfn<4, true, Real, 0, WS, FEAT>(), 4, true};
+    case 5: return {kfn<5, true, Real, 0, WS, FEAT>(), 5, true};
+    case 6: return {kfn<6, true, Real, 0, WS, FEAT>(), 6, true};
+    case 8: return {kfn<8, true, Real, 0, WS, FEAT>(), 8, true};
+    case 10: return {kfn<10, true, Real, 0, WS, FEAT>(), 10, true};
+    case 12: return {kfn<12, true, Real, 0, WS, FEAT>(), 12, true};
+    case 16: return {kfn<16, true, Real, 0, WS, FEAT>(), 16, true};
     default: break;
     }
-    if (d <= 16) return {kfn<16, false, Real, 0, WS>(), 16, false};
+    if (d <= 16) return {kfn<16, false, Real, 0, WS, FEAT>(), 16, false};
     if constexpr (sizeof(Real) == 4)
-        if (d <= 32) return {kfn<32, false, Real, 0, WS>(), 32, false};
+        if (d <= 32) return {kfn<32, false, Real, 0, WS, FEAT>(), 32, false};
     return {nullptr, 0, false};
 }
 
-template <typename Real, typename WS>
+template <typename Real, typename WS, bool FEAT>
 static KernelChoice choose_t(uint32_t d)
 {
-    if (d <= 8) return {kfn<8, false, Real, 1, WS>(), 8, false};
-    if (d <= 16) return {kfn<16, false, Real, 1, WS>(), 16, false};
+    if (d <= 8) return {kfn<8, false, Real, 1, WS, FEAT>(), 8, false};
+    if (d <= 16) return {kfn<16, false, Real, 1, WS, FEAT>(), 16, false};
     if constexpr (sizeof(Real) == 4)
-        if (d <= 32) return {kfn<32, false, Real, 1, WS>(), 32, false};
+        if (d <= 32) return {kfn<32, false, Real, 1, WS, FEAT>(), 32, false};
     return {nullptr, 0, false};
 }
 
 // Returns 0 and launches, or a negative code: -5 unsupported shape, -3 launch failure.
+// Feature-writing kernels exist for binary32 state and the 32-bit signature (T <= 92681).
 int launch_fw_paths(const InstanceDesc &host_desc, const InstanceDesc *dev_desc, const RunBuffers &B,
                     bool fp64, hipStream_t stream, int *kernel_width)
 {
     const bool wide = host_desc.T > kMaxNarrowT;
+    const bool feat = (host_desc.flags & 4u) != 0;
     KernelChoice kc{nullptr, 0, false};
-    if (host_desc.noise == 0) {
-        if (fp64) kc = wide ? choose_gauss<double, uint64_t>(host_desc.d) : choose_gauss<double, uint32_t>(host_desc.d);
-        else kc = wide ? choose_gauss<float, uint64_t>(host_desc.d) : choose_gauss<float, uint32_t>(host_desc.d);
+    if (feat) {
+        if (fp64 || wide) return -5;
+        kc = host_desc.noise == 0 ? choose_gauss<float, uint32_t, true>(host_desc.d)
+                                  : choose_t<float, uint32_t, true>(host_desc.d);
+    } else if (host_desc.noise == 0) {
+        if (fp64) kc = wide ? choose_gauss<double, uint64_t, false>(host_desc.d) : choose_gauss<double, uint32_t, false>(host_desc.d);
+        else kc = wide ? choose_gauss<float, uint64_t, false>(host_desc.d) : choose_gauss<float, uint32_t, false>(host_desc.d);
     } else {
-        if (fp64) kc = wide ? choose_t<double, uint64_t>(host_desc.d) : choose_t<double, uint32_t>(host_desc.d);
-        else kc = wide ? choose_t<float, uint64_t>(host_desc.d) : choose_t<float, uint32_t>(host_desc.d);
+        if (fp64) kc = wide ? choose_t<double, uint64_t, false>(host_desc.d) : choose_t<double, uint32_t, false>(host_desc.d);
+        else kc = wide ? choose_t<float, uint64_t, false>(host_desc.d) : choose_t<float, uint32_t, false>(host_desc.d);
     }
     if (!kc.fn) return -5;
     if (kernel_width) *kernel_width = kc.D;

@@ -83,7 +83,15 @@ int validate(char *err, const sim_params *p, uint64_t R, uint64_t T)
             return fail(err, SIM_EINVAL, "checkpoints must increase strictly");
     }
     if (!finite(p->gap_eps) || p->gap_eps < 0.0) return fail(err, SIM_EINVAL, "gap_eps must be finite and >= 0");
-    if (p->flags & ~(uint32_t)(SIM_KEEP_PATHS | SIM_DECISION_LOG)) return fail(err, SIM_EINVAL, "unknown flag bits");
+    if (p->flags & ~(uint32_t)(SIM_KEEP_PATHS | SIM_DECISION_LOG | SIM_CV_FEATURES))
+        return fail(err, SIM_EINVAL, "unknown flag bits");
+    if (p->flags & SIM_CV_FEATURES) {
+        if (p->state_precision != SIM_FP32)
+            return fail(err, SIM_EUNSUPPORTED, "control-variate features need FP32 state");
+        if (p->chol) return fail(err, SIM_EUNSUPPORTED, "control-variate features need diagonal Sigma");
+        if (T > kMaxNarrowT)
+            return fail(err, SIM_EUNSUPPORTED, "control-variate features need T <= %llu", (unsigned long long)kMaxNarrowT);
+    }
     if (p->instance_id >= (1u << 24)) return fail(err, SIM_EINVAL, "instance_id must be < 2^24");
     if (p->flags & SIM_DECISION_LOG) {
         if (p->log_rep_count < 1 || p->log_rep_count > 65536)
@@ -122,6 +130,15 @@ void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uin
     D.inv_n_d = 1.0 / N;
     D.tscale_f = (float)(tnu / kappa);
     D.inv_n_f = (float)(1.0 / N);
+    if (p->flags & SIM_CV_FEATURES) {
+        const CvConstants c = cv_constants(T, p->resample_every, p->d, p->n_samples);
+        D.cv_xi_scale = kappa / (std::sqrt(N) * c.weight_norm);
+        D.cv_eta_scale = kappa / (std::sqrt(N) * std::sqrt((double)c.late * (double)p->d));
+        D.cv_kappa2 = kappa * kappa;
+        D.cv_k = c.k;
+        D.cv_zeta_inv = 1.0 / std::sqrt(2.0 * c.k);
+        D.cv_late_begin = (uint32_t)(c.epochs - c.late);
+    }
     for (uint32_t j = 0; j < p->d; ++j) {
         // with a dense L the per-asset scale is the marginal standard deviation |row j of L|
         double sg = 0.0;
@@ -205,6 +222,25 @@ Moments moments(const double *f)
 // min over W of lambda sum sigma_j^2 w_j^2 - mu'w (KKT water-filling), diagonal Sigma with every
 // sigma_j > 0: w_j(nu) = max(0, (mu_j - nu) / (2 lambda sigma_j^2)) with nu >= 0 chosen so that
 // sum_j w_j <= 1 holds with complementary slackness. NaN when some sigma_j is zero.
+CvConstants cv_constants(uint64_t T, uint32_t M, uint32_t d, uint32_t N)
+{
+    CvConstants c;
+    c.epochs = (T + M - 1) / M;
+    c.late = (c.epochs + 9) / 10;
+    if (c.late < 1) c.late = 1;
+    double s = 0.0, late = 0.0;
+    for (uint64_t e = 0; e < c.epochs; ++e) {
+        const uint64_t t0 = e * M, t1 = std::min<uint64_t>(t0 + M, T);
+        const double w = 0.5 * ((double)t1 * (double)(t1 + 1) - (double)t0 * (double)(t0 + 1));
+        s += w * w;
+        if (e >= c.epochs - c.late) late += w;
+    }
+    c.weight_norm = std::sqrt(s);
+    c.eta_corr = late / (c.weight_norm * std::sqrt((double)c.late * (double)d));
+    c.k = (double)c.epochs * (double)d * (double)(N - 1);
+    return c;
+}
+
 int dense_asset_of(int p, int k) { return (k >> 2) * 8 + 4 * p + (k & 3); }
 
 void dense_operands(const double *L, uint32_t d, float *Ag, float *Av, double *L64)
@@ -327,6 +363,8 @@ int plan_batch(char *err, uint32_t n_inst, const sim_params *p, const uint64_t *
             return fail(err, SIM_EUNSUPPORTED, "instance %u: batched runs use FP32 state", i);
         if (p[i].d > 32) return fail(err, SIM_EUNSUPPORTED, "instance %u: d > 32 in a batch", i);
         if (p[i].chol) return fail(err, SIM_EUNSUPPORTED, "instance %u: batched runs take diagonal Sigma", i);
+        if (p[i].flags & SIM_CV_FEATURES)
+            return fail(err, SIM_EUNSUPPORTED, "instance %u: batched runs do not write features", i);
         if (cfg && cfg->lanes_per_rep) {
             const uint32_t P = cfg->lanes_per_rep[i];
             if (P != 0 && (P > 64 || (P & (P - 1)) != 0))

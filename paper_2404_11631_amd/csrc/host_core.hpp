@@ -19,6 +19,16 @@ constexpr uint64_t kMaxDenseT = 65535;
 int fail(char *err, int code, const char *fmt, ...);
 int validate(char *err, const sim_params *p, uint64_t R, uint64_t T);
 void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed);
+// Constants of the control-variate features' law for a run of T iterations, resampling every M.
+struct CvConstants {
+    uint64_t epochs;       // E = ceil(T / M)
+    uint64_t late;         // W = ceil(E / 10), at least 1
+    double weight_norm;    // sqrt(sum_e C_e^2), C_e = sum of (t+1) over epoch e
+    double eta_corr;       // Cov(xi_j, eta)
+    double k;              // E d (N-1), degrees of freedom of the pooled sum of squares
+};
+CvConstants cv_constants(uint64_t T, uint32_t M, uint32_t d, uint32_t N);
+
 // The two FP32 operands of the dense-L kernels, sqrt(2 ln 2) L (for g = L h) and its transpose
 // (for v = L'w), each [d/32][d/2][64] in the lane order of v_mfma_f32_32x32x2f32 (row 32 mt +
 // lane mod 32, column the asset that lane lane/32 holds in register kk), and L copied in FP64.

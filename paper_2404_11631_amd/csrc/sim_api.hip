@@ -134,7 +134,8 @@ void sim_destroy(sim_ctx *ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     for (DevBuf *b : {&ctx->y, &ctx->fck, &ctx->cnt, &ctx->wsum, &ctx->tau, &ctx->dlog, &ctx->part_f,
-                      &ctx->part_i, &ctx->done, &ctx->final_f, &ctx->final_i, &ctx->dense})
+                      &ctx->part_i, &ctx->done, &ctx->final_f, &ctx->final_i, &ctx->dense,
+                      &ctx->feat})
         free_buf(*b);
     if (ctx->dense_host) (void)hipHostFree(ctx->dense_host);
     if (ctx->desc_dev) (void)hipFree(ctx->desc_dev);
@@ -150,10 +151,24 @@ void sim_destroy(sim_ctx *ctx)
     if (b.slots_host) (void)hipHostFree(b.slots_host);
     if (b.ev0) (void)hipEventDestroy(b.ev0);
     if (b.ev1) (void)hipEventDestroy(b.ev1);
+    CvState &cv = ctx->cv;
+    for (DevBuf *x : {&cv.theta, &cv.w1a, &cv.w2a, &cv.w2t, &cv.mom1, &cv.mom2, &cv.part, &cv.grad, &cv.loss_hist,
+                      &cv.xtrain, &cv.ytrain, &cv.ttrain, &cv.xio, &cv.yio, &cv.hout, &cv.xaux, &cv.haux, &cv.mpart,
+                      &cv.mout, &cv.mdone, &cv.fails})
+        free_buf(*x);
+    if (cv.ev0) (void)hipEventDestroy(cv.ev0);
+    if (cv.ev1) (void)hipEventDestroy(cv.ev1);
     delete ctx;
 }
 
-int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed)
+}  // extern "C"
+
+namespace fw {
+namespace host {
+
+// One run of Algorithm 1 over R replications; `internal` adds descriptor flag bits the public
+// flags do not carry (kFlagYOnly).
+int run_impl(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed, uint32_t internal)
 {
     if (!ctx) return SIM_EINVAL;
     int rc = validate(ctx->err, p, R, T);
@@ -164,6 +179,7 @@ int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t 
 
     const uint32_t d = p->d;
     const bool keep = (p->flags & SIM_KEEP_PATHS) != 0;
+    const bool want_y = keep || (internal & fw::kFlagYOnly);
     const bool log = (p->flags & SIM_DECISION_LOG) != 0;
     const bool dense = p->chol != nullptr;
     const uint32_t reps_per_block = dense ? fw::kDenseRepsPerBlock : fw::kBlock;
@@ -174,13 +190,15 @@ int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t 
     if ((rc = ensure(ctx, ctx->part_i, sizeof(uint64_t) * (size_t)(d + 3) * nblocks))) return rc;
     if ((rc = ensure(ctx, ctx->final_f, sizeof(double) * ((size_t)fw::kMaxStreams * fw::kStreamFields + 2)))) return rc;
     if ((rc = ensure(ctx, ctx->final_i, sizeof(uint64_t) * (fw::kMaxD + 3)))) return rc;
+    if (want_y && (rc = ensure(ctx, ctx->y, sizeof(double) * R))) return rc;
     if (keep) {
-        if ((rc = ensure(ctx, ctx->y, sizeof(double) * R))) return rc;
         if ((rc = ensure(ctx, ctx->tau, sizeof(uint32_t) * R))) return rc;
         if ((rc = ensure(ctx, ctx->cnt, sizeof(uint32_t) * (size_t)(d + 1) * R))) return rc;
         if ((rc = ensure(ctx, ctx->wsum, sizeof(uint64_t) * (size_t)d * R))) return rc;
     }
     if (log && (rc = ensure(ctx, ctx->dlog, (size_t)T * p->log_rep_count))) return rc;
+    const bool feat = (p->flags & SIM_CV_FEATURES) != 0;
+    if (feat && (rc = ensure(ctx, ctx->feat, sizeof(float) * (size_t)(d + 2) * R))) return rc;
 
     // dense L: the two MFMA-ordered FP32 operands and L in FP64, staged through pinned memory
     const size_t dense_f = (size_t)SIM_MAX_D * SIM_MAX_D;
@@ -198,15 +216,17 @@ int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t 
     }
 
     fill_desc(*ctx->desc_host, p, R, T, seed);
+    ctx->desc_host->flags |= internal;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->desc_dev, ctx->desc_host, sizeof(InstanceDesc), hipMemcpyHostToDevice, ctx->stream));
 
     RunBuffers &B = ctx->bufs;
-    B.y = keep ? (double *)ctx->y.ptr : nullptr;
+    B.y = want_y ? (double *)ctx->y.ptr : nullptr;
     B.fck = (double *)ctx->fck.ptr;
     B.cnt = keep ? (uint32_t *)ctx->cnt.ptr : nullptr;
     B.wsum = keep ? (uint64_t *)ctx->wsum.ptr : nullptr;
     B.tau = keep ? (uint32_t *)ctx->tau.ptr : nullptr;
     B.dlog = log ? (uint8_t *)ctx->dlog.ptr : nullptr;
+    B.feat = feat ? (float *)ctx->feat.ptr : nullptr;
     B.part_f = (double *)ctx->part_f.ptr;
     B.part_i = (uint64_t *)ctx->part_i.ptr;
     B.done = (uint32_t *)ctx->done.ptr;
@@ -242,6 +262,16 @@ int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t 
     ctx->kernel_width = width;
     ctx->have_run = true;
     return SIM_OK;
+}
+
+}  // namespace host
+}  // namespace fw
+
+extern "C" {
+
+int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed)
+{
+    return run_impl(ctx, p, R, T, seed, 0u);
 }
 
 int sim_stats(sim_ctx *ctx, sim_stats_out *out)
@@ -288,6 +318,10 @@ int sim_paths(sim_ctx *ctx, sim_path_view *out)
         out->decisions = (const uint8_t *)ctx->dlog.ptr;
         out->log_rep_begin = ctx->last.log_rep_begin;
         out->log_rep_count = ctx->last.log_rep_count;
+    }
+    if (ctx->last.flags & SIM_CV_FEATURES) {
+        out->x = (const float *)ctx->feat.ptr;
+        out->n_features = ctx->last.d + 2;
     }
     return SIM_OK;
 }

@@ -42,6 +42,14 @@ struct InstanceDesc {
     uint64_t cnt_base;       // into counts   ([d+1][R] block of this instance)
     uint64_t wsum_base;      // into signatures ([d][R] block of this instance)
     uint64_t dlog_base;      // into the decision log ([T][log_count] block)
+    // control-variate features (flag 4): per-epoch accumulators are scaled at the end by these
+    double cv_xi_scale;      // kappa / (sqrt(N) sqrt(sum_e C_e^2))
+    double cv_eta_scale;     // kappa / (sqrt(N) sqrt(W d))
+    double cv_kappa2;        // kappa^2: squares of binary32 normals back to unit scale
+    double cv_k;             // E d (N-1)
+    double cv_zeta_inv;      // 1 / sqrt(2 k)
+    uint32_t cv_late_begin;  // first epoch of the late window, E - W
+    uint32_t cv_pad_;
 };
 
 // One wavefront's unit of work in a batched run: `nrep` replications of one instance starting at
@@ -83,9 +91,13 @@ struct BatchBuffers {
     TilePartial *final_stats; // [n_inst] reduced per instance
 };
 
+// Descriptor flag bits: 1 keep per-path records, 2 decision log, 4 control-variate features,
+// 8 outcomes Y only (set by the library for its own control-variate runs).
+constexpr uint32_t kFlagYOnly = 8u;
+
 // Per-run device buffers. Structure of arrays, replication index fastest.
 struct RunBuffers {
-    double *y;            // [R]              (KEEP_PATHS)
+    double *y;            // [R]              (KEEP_PATHS or outcomes only)
     double *fck;          // [n_ckpt][R]      always: the epilogue reads it back for RSE
     uint32_t *cnt;        // [(d+1)][R]       (KEEP_PATHS)
     uint64_t *wsum;       // [d][R]           (KEEP_PATHS)
@@ -100,6 +112,7 @@ struct RunBuffers {
     uint32_t n_streams;
     // dense correlated returns: sqrt(2 ln 2) L and its transpose, columns permuted and laid out in
     // the order the matrix-core instruction consumes them, and L itself in FP64 (row-major)
+    float *feat;          // [(d+2)][R]       (CV_FEATURES)
     const float *dense_g;
     const float *dense_v;
     const double *dense_l64;

@@ -14,13 +14,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsim.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 MAX_D = 64
 MAX_CKPT = 8
 TAU_NONE = 0xFFFFFFFF
 NOISE_GAUSS, NOISE_T = 0, 1
 FP32, FP64 = 0, 1
-KEEP_PATHS, DECISION_LOG = 1, 2
+KEEP_PATHS, DECISION_LOG, CV_FEATURES = 1, 2, 4
 STATUS = {0: "ok", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EUNSUPPORTED"}
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -57,7 +57,8 @@ class SimPathView(ctypes.Structure):
                 ("f_ckpt", ctypes.c_void_p), ("cnt", ctypes.c_void_p), ("wsum", ctypes.c_void_p),
                 ("tau", ctypes.c_void_p), ("decisions", ctypes.c_void_p),
                 ("log_rep_begin", ctypes.c_uint64), ("log_rep_count", ctypes.c_uint64),
-                ("f_ckpt_stride", ctypes.c_uint64)]
+                ("f_ckpt_stride", ctypes.c_uint64), ("x", ctypes.c_void_p),
+                ("n_features", ctypes.c_uint32), ("pad_", ctypes.c_uint32)]
 
 
 class SimBatchConfig(ctypes.Structure):
@@ -65,10 +66,44 @@ class SimBatchConfig(ctypes.Structure):
                 ("heavy_factor", ctypes.c_double), ("lanes_per_rep", ctypes.POINTER(ctypes.c_uint8))]
 
 
+class SimCvOpts(ctypes.Structure):
+    _fields_ = [("n_runs", ctypes.c_uint32), ("epochs", ctypes.c_uint32), ("R_train", ctypes.c_uint64),
+                ("R_pilot", ctypes.c_uint64), ("batch", ctypes.c_uint32), ("reinit", ctypes.c_uint32),
+                ("lr", ctypes.c_double)]
+
+
+class SimCvFitOut(ctypes.Structure):
+    _fields_ = [("n_train", ctypes.c_uint64), ("steps", ctypes.c_uint64), ("y_mean", ctypes.c_double),
+                ("y_sd", ctypes.c_double), ("loss_first_epoch", ctypes.c_double),
+                ("loss_last_epoch", ctypes.c_double), ("beta", ctypes.c_double), ("rho2", ctypes.c_double),
+                ("pilot_var_y", ctypes.c_double), ("sim_ms", ctypes.c_double), ("train_ms", ctypes.c_double),
+                ("pilot_ms", ctypes.c_double)]
+
+
+class SimCvStats(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_uint64), ("R_aux", ctypes.c_uint64), ("beta", ctypes.c_double),
+                ("mean_plain", ctypes.c_double), ("var_plain", ctypes.c_double), ("ci95_plain", ctypes.c_double),
+                ("mean_resid", ctypes.c_double), ("var_resid", ctypes.c_double), ("mean_h_aux", ctypes.c_double),
+                ("var_h_aux", ctypes.c_double), ("mean_cv", ctypes.c_double), ("var_est", ctypes.c_double),
+                ("ci95_cv", ctypes.c_double), ("rho2", ctypes.c_double), ("aux_gamma_failures", ctypes.c_uint64),
+                ("kernel_ms", ctypes.c_double)]
+
+
+class SimCvView(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_uint64), ("n_aux", ctypes.c_uint64), ("F", ctypes.c_uint32),
+                ("pad_", ctypes.c_uint32), ("y", ctypes.c_void_p), ("h", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("x_aux", ctypes.c_void_p), ("h_aux", ctypes.c_void_p)]
+
+
+def mlp_param_count(F: int) -> int:
+    return 64 * F + 4289
+
+
 #: every symbol include/sim.h declares
 EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_run_batch",
            "sim_plan_batch", "sim_batch_stats", "sim_batch_paths", "sim_stats", "sim_paths", "sim_copy_to_host",
-           "sim_strerror", "sim_last_error", "sim_destroy")
+           "sim_strerror", "sim_last_error", "sim_destroy", "sim_cv_fit", "sim_run_cv", "sim_cv_paths",
+           "sim_mlp_set_params", "sim_mlp_get_params", "sim_mlp_forward", "sim_mlp_grad", "sim_cv_aux_draws")
 
 _lib = None
 
@@ -106,6 +141,17 @@ def load():
         L.sim_last_error.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
         L.sim_destroy.argtypes = [vp]
         L.sim_destroy.restype = None
+        u64, fp = ctypes.c_uint64, ctypes.POINTER(ctypes.c_float)
+        L.sim_cv_fit.argtypes = [vp, ctypes.POINTER(SimParams), u64, u64, ctypes.POINTER(SimCvOpts),
+                                 ctypes.POINTER(SimCvFitOut)]
+        L.sim_run_cv.argtypes = [vp, ctypes.POINTER(SimParams), u64, u64, u64, u64, ctypes.POINTER(SimCvStats)]
+        L.sim_cv_paths.argtypes = [vp, ctypes.POINTER(SimCvView)]
+        L.sim_mlp_set_params.argtypes = [vp, ctypes.c_uint32, fp]
+        L.sim_mlp_get_params.argtypes = [vp, ctypes.c_uint32, fp]
+        L.sim_mlp_forward.argtypes = [vp, fp, u64, fp]
+        L.sim_mlp_grad.argtypes = [vp, fp, fp, u64, fp, ctypes.POINTER(ctypes.c_double)]
+        L.sim_cv_aux_draws.argtypes = [vp, ctypes.POINTER(SimParams), u64, u64, u64, u64, fp,
+                                       ctypes.POINTER(ctypes.c_uint64)]
         _lib = L
     return _lib
 
@@ -133,6 +179,7 @@ class Problem:
     gap_eps: float = 1e-2
     keep_paths: bool = False
     log_reps: tuple | None = None      # (begin, count) of replications whose decisions are logged
+    cv_features: bool = False          # write each path's d+2 control-variate features
     instance_id: int = 0
 
 
@@ -238,7 +285,8 @@ class Sim:
         for i, c in enumerate(p.checkpoints[:MAX_CKPT]):
             sp.checkpoints[i] = int(c)
         sp.gap_eps = p.gap_eps
-        sp.flags = (KEEP_PATHS if p.keep_paths else 0) | (DECISION_LOG if p.log_reps else 0)
+        sp.flags = ((KEEP_PATHS if p.keep_paths else 0) | (DECISION_LOG if p.log_reps else 0) |
+                    (CV_FEATURES if p.cv_features else 0))
         sp.instance_id = p.instance_id
         if p.log_reps:
             sp.log_rep_begin, sp.log_rep_count = int(p.log_reps[0]), int(p.log_reps[1])
@@ -285,6 +333,72 @@ class Sim:
         out["n_tiles"] = nt.value
         return out
 
+    # ---- control variate ------------------------------------------------------------------
+    @staticmethod
+    def _f32(a):
+        return np.ascontiguousarray(a, dtype=np.float32)
+
+    def mlp_set_params(self, F: int, theta):
+        t = self._f32(theta)
+        assert t.size == mlp_param_count(F)
+        self._check(self.L.sim_mlp_set_params(self.h, F, t.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def mlp_get_params(self, F: int) -> np.ndarray:
+        t = np.zeros(mlp_param_count(F), dtype=np.float32)
+        self._check(self.L.sim_mlp_get_params(self.h, F, t.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return t
+
+    def mlp_forward(self, x) -> np.ndarray:
+        """Raw network outputs for features x [F][n] (feature-major)."""
+        x = self._f32(x)
+        out = np.zeros(x.shape[1], dtype=np.float32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        self._check(self.L.sim_mlp_forward(self.h, x.ctypes.data_as(fp), x.shape[1], out.ctypes.data_as(fp)))
+        return out
+
+    def mlp_grad(self, x, y):
+        """(mean squared error, gradient [P]) at the current parameters; x [F][n], y [n]."""
+        x, y = self._f32(x), self._f32(y)
+        F, n = x.shape
+        g = np.zeros(mlp_param_count(F), dtype=np.float32)
+        loss = ctypes.c_double()
+        fp = ctypes.POINTER(ctypes.c_float)
+        self._check(self.L.sim_mlp_grad(self.h, x.ctypes.data_as(fp), y.ctypes.data_as(fp), n,
+                                        g.ctypes.data_as(fp), ctypes.byref(loss)))
+        return loss.value, g
+
+    def cv_aux_draws(self, p: Problem, T: int, seed: int, k0: int, n: int):
+        sp, keep = self.params(p)
+        x = np.zeros((len(p.mu) + 2, n), dtype=np.float32)
+        nf = ctypes.c_uint64()
+        self._check(self.L.sim_cv_aux_draws(self.h, ctypes.byref(sp), T, seed, k0, n,
+                                            x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(nf)))
+        return x, nf.value
+
+    def cv_fit(self, p: Problem, T: int, seed: int, n_runs=1, epochs=1, R_train=65536, R_pilot=65536,
+               batch=4096, lr=1e-3, reinit=True) -> SimCvFitOut:
+        sp, keep = self.params(p)
+        o = SimCvOpts(n_runs=n_runs, epochs=epochs, R_train=R_train, R_pilot=R_pilot, batch=batch,
+                      reinit=int(reinit), lr=lr)
+        out = SimCvFitOut()
+        self._check(self.L.sim_cv_fit(self.h, ctypes.byref(sp), T, seed, ctypes.byref(o), ctypes.byref(out)))
+        return out
+
+    def run_cv(self, p: Problem, R: int, T: int, seed: int, R_aux: int) -> SimCvStats:
+        sp, keep = self.params(p)
+        out = SimCvStats()
+        self._check(self.L.sim_run_cv(self.h, ctypes.byref(sp), R, T, seed, R_aux, ctypes.byref(out)))
+        return out
+
+    def cv_paths(self) -> dict:
+        v = SimCvView()
+        self._check(self.L.sim_cv_paths(self.h, ctypes.byref(v)))
+        R, n, F = v.R, v.n_aux, v.F
+        return {"y": self._copy(v.y, np.float64, R), "h": self._copy(v.h, np.float32, R),
+                "x": self._copy(v.x, np.float32, F * R).reshape(F, R),
+                "x_aux": self._copy(v.x_aux, np.float32, F * n).reshape(F, n),
+                "h_aux": self._copy(v.h_aux, np.float32, n)}
+
     def paths(self) -> dict:
         v = SimPathView()
         self._check(self.L.sim_paths(self.h, ctypes.byref(v)))
@@ -305,4 +419,6 @@ class Sim:
             n = v.log_rep_count
             out["decisions"] = self._copy(v.decisions, np.uint8, v.T * n).reshape(v.T, n)
             out["log_rep_begin"] = v.log_rep_begin
+        if v.x:
+            out["x"] = self._copy(v.x, np.float32, v.n_features * R).reshape(v.n_features, R)
         return out

@@ -1,0 +1,200 @@
+"""Control-variate pieces on the device vs the CPU oracle through the C ABI (needs an MI355X).
+
+Features: each path's d+2 features against the oracle's (same noise stream, replayed decisions)
+to 5e-5 absolute -- binary32 normals and per-epoch binary32 sums against FP64 -- and, at sizes
+the oracle cannot follow, their exact law (KS tests and correlations).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import scipy.stats as ss
+
+import oracle
+from paper_2404_11631_amd import sim, workloads
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+FEAT_ATOL = 5e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    s = sim.Sim(0)
+    yield s
+    s.close()
+
+
+@pytest.mark.parametrize("case", [
+    dict(d=10, N=10, M=1, T=200, R=300, noise=sim.NOISE_GAUSS),
+    dict(d=3, N=4, M=3, T=100, R=200, noise=sim.NOISE_GAUSS),
+    dict(d=6, N=5, M=1, T=120, R=150, noise=sim.NOISE_T),
+    dict(d=20, N=3, M=2, T=61, R=130, noise=sim.NOISE_GAUSS),
+], ids=lambda c: f"d{c['d']}N{c['N']}M{c['M']}{'t' if c['noise'] else 'g'}")
+def test_features_match_oracle(ctx, case):
+    d, R, T = case["d"], case["R"], case["T"]
+    mu, sigma = workloads.diag_instance(9, d, d)
+    p = sim.Problem(mu=mu, sigma=sigma, N=case["N"], M=case["M"], noise=case["noise"], nu=4,
+                    checkpoints=(T,), gap_eps=0.05, instance_id=30 + d, keep_paths=True,
+                    log_reps=(0, R), cv_features=True)
+    say(f"[cv] features d={d} N={case['N']} M={case['M']} noise={case['noise']} R={R} T={T}")
+    ctx.run(p, R, T, 77)
+    g = ctx.paths()
+    assert g["x"].shape == (d + 2, R)
+    P = parity.oracle_problem(p, 77)
+    err = 0.0
+    for r in range(R):
+        o = parity.check_rep(P, g, r, T, oracle.U32, decisions=g["decisions"][:, r])
+        ref = np.array([o.feat[j] for j in range(d + 2)])
+        e = np.max(np.abs(g["x"][:, r].astype(np.float64) - ref))
+        err = max(err, e)
+        assert e <= FEAT_ATOL, f"rep {r}: feature error {e}"
+    say(f"[cv] max feature error {err:.2e}")
+
+
+def test_features_do_not_change_the_paths(ctx):
+    d, R, T = 10, 2000, 300
+    mu, sigma = workloads.diag_instance(1, 2, d)
+    base = dict(mu=mu, sigma=sigma, N=10, checkpoints=(100, T), keep_paths=True)
+    ctx.run(sim.Problem(**base), R, T, 5)
+    a = ctx.paths()
+    ctx.run(sim.Problem(**base, cv_features=True), R, T, 5)
+    b = ctx.paths()
+    assert np.array_equal(a["y"], b["y"]) and np.array_equal(a["wsum"], b["wsum"])
+    assert "x" not in a and "x" in b
+
+
+def test_feature_law_at_scale(ctx):
+    """The control-variate workload's shape (d = 10, N = 10) at R = 2e5, T = 1000: the device's
+    features follow their exact law."""
+    d, R, T = 10, 200_000, 1000
+    mu, sigma = workloads.diag_instance(100, 0, d)
+    p = sim.Problem(mu=mu, sigma=sigma, N=10, checkpoints=(T,), cv_features=True)
+    ctx.run(p, R, T, 100)
+    X = ctx.paths()["x"].astype(np.float64)
+    for j in range(d + 1):
+        assert ss.kstest(X[j], "norm").pvalue > 1e-4, f"feature {j}"
+    k = T * d * 9
+    assert ss.kstest(X[d + 1] * math.sqrt(2 * k) + k, ss.chi2(k).cdf).pvalue > 1e-4
+    a = oracle.cv_eta_corr(T, 1, d)
+    se = 5.0 / math.sqrt(R)
+    C = np.corrcoef(X)
+    for j in range(d):
+        assert abs(C[j, d] - a) < se and abs(C[j, d + 1]) < se
+    say(f"[cv] law ok, corr(xi, eta) {C[0, d]:.4f} vs {a:.4f}")
+
+
+# ---- surrogate primitives ------------------------------------------------------------------
+# The device rounds the operands of each matrix product to bfloat16 where the oracle (quantize)
+# does, but accumulates in FP32: an activation whose FP32 and FP64 values straddle a bfloat16
+# rounding boundary rounds differently (one bfloat16 ulp, 2^-8 relative), so a few elements per
+# batch differ at the 1e-3 level. Tolerances: forward, median relative error 1e-5 and every row
+# within 5e-3 of the output scale; gradient, 1e-3 relative Frobenius error per tensor.
+
+def _theta(F, seed, scale=0.3):
+    g = np.random.default_rng(seed)
+    return g.normal(0.0, scale, sim.mlp_param_count(F)).astype(np.float32)
+
+
+def _tensors(F):
+    o = 0
+    out = {}
+    for name, size in (("W1", 64 * F), ("b1", 64), ("W2", 4096), ("b2", 64), ("w3", 64), ("b3", 1)):
+        out[name] = slice(o, o + size)
+        o += size
+    return out
+
+
+def test_cv_run_needs_a_fit(ctx):
+    mu, sigma = workloads.diag_instance(0, 0, 4)
+    with pytest.raises(sim.SimError) as e:
+        ctx.run_cv(sim.Problem(mu=mu, sigma=sigma, N=4), 100, 10, 1, 100)
+    assert e.value.code == -4
+
+
+@pytest.mark.parametrize("F,n", [(12, 300), (66, 257), (3, 128), (17, 1000)])
+def test_mlp_forward_matches_oracle(ctx, F, n):
+    th = _theta(F, F)
+    x = np.random.default_rng(F + 1).normal(size=(F, n)).astype(np.float32)
+    ctx.mlp_set_params(F, th)
+    assert np.array_equal(ctx.mlp_get_params(F), th)
+    out = ctx.mlp_forward(x).astype(np.float64)
+    ref = oracle.mlp_forward(th.astype(np.float64), F, x.T.astype(np.float64), quantize=True)
+    err = np.abs(out - ref)
+    scale = np.sqrt(np.mean(ref ** 2))
+    say(f"[cv] forward F={F} n={n}: max err {err.max():.2e}, median rel {np.median(err / np.abs(ref)):.2e}")
+    assert np.median(err / np.abs(ref)) <= 1e-5
+    assert err.max() <= 5e-3 * scale
+
+
+@pytest.mark.parametrize("F,n", [(12, 300), (66, 200), (12, 4096)])
+def test_mlp_grad_matches_oracle(ctx, F, n):
+    g = np.random.default_rng(100 + F)
+    th = _theta(F, 200 + F)
+    x = g.normal(size=(F, n)).astype(np.float32)
+    y = g.normal(size=n).astype(np.float32)
+    ctx.mlp_set_params(F, th)
+    loss, grad = ctx.mlp_grad(x, y)
+    loss2, grad2 = ctx.mlp_grad(x, y)
+    assert loss == loss2 and np.array_equal(grad, grad2)          # fixed reduction order
+    lref, gref = oracle.mlp_grad(th.astype(np.float64), F, x.T.astype(np.float64), y.astype(np.float64),
+                                 quantize=True)
+    assert abs(loss - lref) <= 1e-4 * lref
+    for name, sl in _tensors(F).items():
+        rel = np.linalg.norm(grad[sl] - gref[sl]) / np.linalg.norm(gref[sl])
+        say(f"[cv] grad F={F} n={n} {name}: rel Frobenius error {rel:.2e}")
+        assert rel <= 1e-3, name
+
+
+@pytest.mark.parametrize("d,N,M,T", [(10, 10, 1, 10_000), (1, 2, 1, 1), (3, 5, 2, 41), (64, 100, 1, 1000)])
+def test_aux_draws_match_oracle(ctx, d, N, M, T):
+    mu, sigma = workloads.diag_instance(4, d, d)
+    p = sim.Problem(mu=mu, sigma=sigma, N=N, M=M, instance_id=5)
+    x, nf = ctx.cv_aux_draws(p, T, 123, 1000, 2000)
+    P = oracle.OracleProblem(mu, sigma, N=N, M=M, seed=123, instance=5)
+    ref, tries = oracle.cv_aux(P, T, 1000, 2000)
+    assert nf == 0 and np.all(tries >= 1)
+    err = np.abs(x.T.astype(np.float64) - ref)
+    say(f"[cv] aux d={d} k={(-(-T // M)) * d * (N - 1)}: max err {err.max():.2e}")
+    assert np.all(err <= 2e-6 + 1e-6 * np.abs(ref))
+
+
+def test_cv_fit_and_estimate(ctx):
+    """Train on the device, fit beta on a pilot, estimate: the estimator's arithmetic matches the
+    oracle's on the same arrays, h matches the oracle's surrogate on the same features, the estimate
+    agrees with the plain mean of the same paths, and its variance is smaller."""
+    d, N, T = 10, 10, 300
+    mu, sigma = workloads.diag_instance(100, 0, d)
+    p = sim.Problem(mu=mu, sigma=sigma, N=N)
+    fit = ctx.cv_fit(p, T, 1, n_runs=2, epochs=4, R_train=1 << 16, R_pilot=1 << 15, batch=4096, lr=2e-3)
+    say(f"[cv] fit: loss {fit.loss_first_epoch:.4f} -> {fit.loss_last_epoch:.4f}, beta {fit.beta:.3f}, "
+        f"rho2 {fit.rho2:.3f}, sim {fit.sim_ms:.0f} ms, train {fit.train_ms:.0f} ms ({fit.steps} steps)")
+    assert fit.n_train == 2 << 16 and fit.steps == 4 * 32
+    assert fit.loss_last_epoch < fit.loss_first_epoch
+    R, R_aux = 20_000, 400_000
+    st = ctx.run_cv(p, R, T, 100, R_aux)
+    v = ctx.cv_paths()
+    assert st.aux_gamma_failures == 0 and v["h_aux"].shape == (R_aux,)
+    ost = oracle.cv_estimate(v["y"], v["h"].astype(np.float64), v["h_aux"].astype(np.float64), st.beta)
+    for a, b, tol in ((st.mean_plain, ost.mean_plain, 1e-12), (st.var_plain, ost.var_plain, 1e-9),
+                      (st.mean_resid, ost.mean_resid, 1e-12), (st.var_resid, ost.var_resid, 1e-8),
+                      (st.mean_h_aux, ost.mean_h_aux, 1e-12), (st.var_h_aux, ost.var_h_aux, 1e-9),
+                      (st.mean_cv, ost.mean_cv, 1e-12), (st.var_est, ost.var_est, 1e-8)):
+        assert abs(a - b) <= tol * max(abs(a), abs(b), 1e-300), (a, b)
+    theta = ctx.mlp_get_params(d + 2).astype(np.float64)
+    href = fit.y_mean + fit.y_sd * oracle.mlp_forward(theta, d + 2, v["x"][:, :512].T.astype(np.float64),
+                                                      quantize=True)
+    assert np.max(np.abs(v["h"][:512] - href)) <= 2e-3 * fit.y_sd
+    joint = math.sqrt(st.ci95_plain ** 2 + st.ci95_cv ** 2) / 1.96
+    gain = (st.var_plain / R) / st.var_est
+    say(f"[cv] plain {st.mean_plain:.6f} +- {st.ci95_plain:.2e}, cv {st.mean_cv:.6f} +- {st.ci95_cv:.2e}, "
+        f"variance gain {gain:.2f}, rho2 {st.rho2:.3f}, {st.kernel_ms:.1f} ms")
+    assert abs(st.mean_cv - st.mean_plain) <= 4.5 * joint
+    assert gain > 1.2

@@ -134,3 +134,31 @@ def test_stress_reduced(ctx):
     for r in (R - 130, R - 129, R - 2, R - 1):
         parity.check_rep(P, g, r, T, oracle.U32, decisions=g["decisions"][:, r - (R - 130)])
         say(f"[dense] stress rep {r} matches the oracle")
+
+
+@pytest.mark.timeout(600)
+def test_stress_full_size(ctx):
+    """The stress workload at full size (R = 1e7, one launch): the decisions of the last 40
+    replications (the end of the last workgroup) are logged and replayed by the oracle for a few
+    of them, with their checkpoint values; every replication by exact properties of the totals."""
+    w = workloads.WORKLOADS["stress"]
+    mu, L = workloads.dense_instance(w["seed"], 0, w["d"], "unit")
+    R, T = w["R"], w["T"]
+    p = sim.Problem(mu=mu, chol=L, N=w["N"], noise=sim.NOISE_T, nu=w["nu"], checkpoints=w["checkpoints"],
+                    log_reps=(R - 40, 40))
+    say(f"[dense] stress full size R={R} T={T}")
+    ctx.run(p, R, T, w["seed"])
+    st = ctx.stats()
+    say(f"[dense] stress full: {st.kernel_ms:.1f} ms, {st.path_steps_per_s:.3e} path-steps/s")
+    g = ctx.paths()
+    assert st.R == R and sum(st.decision_total) == R * T
+    y = g["f_ckpt"][-1]                      # the last checkpoint is T: Y of every replication
+    assert math.isclose(st.mean, math.fsum(y) / R, rel_tol=1e-12)
+    assert st.min == y.min() and st.max == y.max()
+    P = parity.oracle_problem(p, w["seed"])
+    for r in (R - 40, R - 25, R - 1):
+        o = P.path(r, T, replay=g["decisions"][:, r - (R - 40)], uroff=oracle.U32)
+        assert o.n_mismatch == 0, f"rep {r}: first mismatch at {o.first_mismatch}"
+        for c in range(len(w["checkpoints"])):
+            assert abs(g["f_ckpt"][c, r] - o.f_ckpt[c]) <= parity.Y_RTOL * abs(o.f_ckpt[c]) + parity.Y_ATOL
+        say(f"[dense] stress rep {r} matches the oracle ({o.n_replayed} replayed)")
