@@ -81,6 +81,14 @@ inline float __builtin_amdgcn_logf(float x) { return std::log2(x); }
 inline float __builtin_amdgcn_cosf(float x) { return (float)std::cos(6.283185307179586 * x); }
 inline float __builtin_amdgcn_sinf(float x) { return (float)std::sin(6.283185307179586 * x); }
 inline float __builtin_amdgcn_rsqf(float x) { return 1.0f / std::sqrt(x); }
+// three-input bitwise function given by its 8-entry truth table, row index 4 a + 2 b + c
+inline uint32_t __builtin_amdgcn_bitop3_b32(uint32_t a, uint32_t b, uint32_t c, uint32_t lut)
+{
+    uint32_t r = 0;
+    for (int i = 0; i < 8; ++i)
+        if ((lut >> i) & 1u) r |= ((i & 4) ? a : ~a) & ((i & 2) ? b : ~b) & ((i & 1) ? c : ~c);
+    return r;
+}
 inline void sincospi(double x, double *s, double *c) { *s = std::sin(M_PI * x); *c = std::cos(M_PI * x); }
 using std::fma; using std::fmin; using std::fmax; using std::sqrt; using std::log;
 inline float fmaf(float a, float b, float c) { return std::fma(a, b, c); }
