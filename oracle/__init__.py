@@ -45,7 +45,8 @@ class Problem(ctypes.Structure):
                 ("instance", ctypes.c_uint32), ("pad_", ctypes.c_uint32),
                 ("seed", ctypes.c_uint64), ("lam", ctypes.c_double), ("gap_eps", ctypes.c_double),
                 ("mu", ctypes.POINTER(ctypes.c_double)), ("chol", ctypes.POINTER(ctypes.c_double)),
-                ("w0", ctypes.POINTER(ctypes.c_double)), ("ckpt", ctypes.c_int64 * MAX_CKPT)]
+                ("w0", ctypes.POINTER(ctypes.c_double)), ("ckpt", ctypes.c_int64 * MAX_CKPT),
+                ("cv_ref", ctypes.POINTER(ctypes.c_double))]
 
 
 class PathOut(ctypes.Structure):
@@ -55,7 +56,8 @@ class PathOut(ctypes.Structure):
                 ("n_ambiguous", ctypes.c_uint64), ("n_replayed", ctypes.c_uint64),
                 ("n_mismatch", ctypes.c_uint64), ("first_mismatch", ctypes.c_int64),
                 ("identity_err", ctypes.c_double), ("min_margin", ctypes.c_double),
-                ("feat", ctypes.c_double * (MAX_D + 2))]
+                ("cv_count", ctypes.c_double * (MAX_D + 1)), ("cv_q", ctypes.c_double),
+                ("cv_amb", ctypes.c_double)]
 
 
 class CvStats(ctypes.Structure):
@@ -105,13 +107,12 @@ def lib():
         L.or_reduce.argtypes = [ctypes.POINTER(Problem), ctypes.c_uint64, ctypes.POINTER(PathOut),
                                 ctypes.c_uint64, ctypes.POINTER(Stats)]
         u64 = ctypes.c_uint64
-        L.or_cv_late_epochs.argtypes = [u64]
-        L.or_cv_late_epochs.restype = u64
-        L.or_cv_weight_norm.argtypes = [u64, ctypes.c_int]
-        L.or_cv_weight_norm.restype = ctypes.c_double
-        L.or_cv_eta_corr.argtypes = [u64, ctypes.c_int, ctypes.c_int]
-        L.or_cv_eta_corr.restype = ctypes.c_double
-        L.or_cv_aux.argtypes = [ctypes.POINTER(Problem), u64, u64, dp]
+        L.or_cv_pick_probs.argtypes = [ctypes.c_int, dp, dp, dp]
+        L.or_cv_pick_probs.restype = ctypes.c_double
+        L.or_cv_weights.argtypes = [u64, ctypes.c_int, dp, dp]
+        L.or_cv_features.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp,
+                                     ctypes.c_double, dp]
+        L.or_cv_aux.argtypes = [ctypes.POINTER(Problem), u64, dp, u64, dp, dp]
         L.or_cv_aux.restype = ctypes.c_int
         L.or_bf16.argtypes = [ctypes.c_double]
         L.or_bf16.restype = ctypes.c_double
@@ -134,7 +135,7 @@ class OracleProblem:
     """Keeps the numpy buffers of one problem alive next to its ctypes struct."""
 
     def __init__(self, mu, sigma=None, chol=None, *, N, M=1, lam=0.5, w0=None, noise=NOISE_GAUSS,
-                 nu=3, seed=0, instance=0, ckpt=(), gap_eps=1e-2):
+                 nu=3, seed=0, instance=0, ckpt=(), gap_eps=1e-2, cv_ref=None):
         self.mu = np.ascontiguousarray(mu, dtype=np.float64)
         d = self.mu.shape[0]
         if chol is None:
@@ -149,6 +150,8 @@ class OracleProblem:
         p.instance, p.seed, p.lam, p.gap_eps = instance, seed, lam, gap_eps
         p.mu, p.chol = _dptr(self.mu), _dptr(self.chol)
         p.w0 = _dptr(self.w0) if self.w0 is not None else ctypes.POINTER(ctypes.c_double)()
+        self.cv_ref = None if cv_ref is None else np.ascontiguousarray(cv_ref, dtype=np.float64)
+        p.cv_ref = _dptr(self.cv_ref) if self.cv_ref is not None else ctypes.POINTER(ctypes.c_double)()
         for i, c in enumerate(ck):
             p.ckpt[i] = int(c)
         self.p = p
@@ -233,27 +236,53 @@ def _arr(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def cv_aux(P: OracleProblem, T: int, k0: int, n: int):
-    """Draws k0 .. k0+n-1 from the exact law of the path features: (n, d+2), and the tries."""
-    out = np.zeros((n, P.d + 2))
-    tries = np.zeros(n, dtype=np.int64)
-    row = np.zeros(P.d + 2)
-    for i in range(n):
-        tries[i] = lib().or_cv_aux(ctypes.byref(P.p), T, k0 + i, _dptr(row))
-        out[i] = row
-    return out, tries
+def cv_pick_probs(b, s):
+    """(p, sum): probabilities of the reference decision, p[0] the origin, p[j+1] vertex e_j."""
+    b, s = _arr(b), _arr(s)
+    p = np.zeros(b.shape[0] + 1)
+    tot = lib().or_cv_pick_probs(b.shape[0], _dptr(b), _dptr(s), _dptr(p))
+    return p, tot
 
 
-def cv_eta_corr(T: int, M: int, d: int) -> float:
-    return lib().or_cv_eta_corr(T, M, d)
+def cv_weights(T: int, M: int):
+    s2, s4 = ctypes.c_double(), ctypes.c_double()
+    lib().or_cv_weights(T, M, ctypes.byref(s2), ctypes.byref(s4))
+    return s2.value, s4.value
 
 
-def cv_weight_norm(T: int, M: int) -> float:
-    return lib().or_cv_weight_norm(T, M)
+class CvLaw:
+    """The features' law for a problem (diagonal L) with reference gradient cv_ref and T iterations."""
 
+    def __init__(self, P: OracleProblem, T: int):
+        sig = np.diag(P.chol).copy()
+        self.P, self.T, self.d = P, T, P.d
+        self.probs, self.total = cv_pick_probs(P.cv_ref, sig / np.sqrt(P.N))
+        self.S2, self.S4 = cv_weights(T, P.p.M)
+        E = -(-T // P.p.M)
+        self.kdof = float(E * P.d * (P.N - 1))
 
-def cv_late_epochs(E: int) -> int:
-    return lib().or_cv_late_epochs(E)
+    def standardize(self, count, q):
+        x = np.zeros(self.d + 2)
+        c = _arr(count)
+        lib().or_cv_features(self.d, _dptr(self.probs), self.S2, self.S4, self.kdof, _dptr(c), float(q), _dptr(x))
+        return x
+
+    def path_features(self, o):
+        return self.standardize([o.cv_count[c] for c in range(self.d + 1)], o.cv_q)
+
+    def aux(self, k0: int, n: int):
+        """Draws k0 .. k0+n-1 from the exact law: (standardized (n, d+2), raw counts (n, d+1), tries)."""
+        X = np.zeros((n, self.d + 2))
+        C = np.zeros((n, self.d + 1))
+        tries = np.zeros(n, dtype=np.int64)
+        cnt = np.zeros(self.d + 1)
+        q = ctypes.c_double()
+        for i in range(n):
+            tries[i] = lib().or_cv_aux(ctypes.byref(self.P.p), self.T, _dptr(self.probs), k0 + i, _dptr(cnt),
+                                       ctypes.byref(q))
+            C[i] = cnt
+            X[i] = self.standardize(cnt, q.value)
+        return X, C, tries
 
 
 def bf16(v: float) -> float:

@@ -4,15 +4,17 @@
  * (forward and backward written as plain loops), and the control-variate estimator.
  *
  * The surrogate is not part of the paper's method; it is a variance-reduction layer over the
- * Monte Carlo estimate of E f(w_T) from Algorithm 1. Its features are summaries of the Gaussian
- * noise each path consumed, chosen so that their joint law is known exactly:
- *   u_{e,j} = sum_i z_{e,i,j} / sqrt(N)         ~ N(0,1), i.i.d. over epochs e and assets j,
- *   q_e     = sum_j sum_i (z_{e,i,j} - zbar)^2  ~ chi-square(d (N-1)), independent of u,
- *   xi_j    = sum_t (t+1) u_{e(t),j} / sqrt(sum_e C_e^2),  C_e = sum of (t+1) over epoch e,
- *   eta     = sum over the last W epochs of sum_j u_{e,j} / sqrt(W d),  W = ceil(E / 10),
- *   zeta    = (sum_e q_e - k) / sqrt(2 k),  k = E d (N-1),  E = ceil(T / M) epochs.
- * So xi ~ N(0, I_d), eta ~ N(0,1) with Cov(xi_j, eta) = a (or_cv_eta_corr), and zeta is a
- * standardized chi-square(k) independent of both.
+ * Monte Carlo estimate of E f(w_T) from Algorithm 1. Its features summarize the noise each path
+ * consumed so that their joint law is known exactly. Per epoch e (E = ceil(T/M) epochs), with
+ * zbar_e the sample mean of the epoch's Gaussian numerators:
+ *   J_e = the vertex the linear subproblem over W picks for the fixed gradient b - L zbar_e (b a
+ *         reference gradient fixed before the run): lowest index among equal minima, the origin
+ *         when the minimum is >= 0. zbar_e ~ N(0, I/N) i.i.d. over epochs, so for diagonal
+ *         L = diag(sigma) the J_e are i.i.d. categorical with probabilities p_c given by one-
+ *         dimensional integrals (or_cv_pick_probs);
+ *   q_e = sum_j sum_i (z_eij - zbar_ej)^2 ~ chi-square(d (N-1)), independent of zbar_e.
+ * The summaries are count_c = sum_t (t+1)^2 [J_e(t) = c] (the late iterations weigh most, as in
+ * w_T) and q = sum_e q_e ~ chi-square(k), k = E d (N-1), independent of the counts.
  */
 #include "oracle.h"
 
@@ -20,50 +22,75 @@
 #include <stdlib.h>
 #include <string.h>
 
-uint64_t or_cv_late_epochs(uint64_t n_epochs)
-{
-    uint64_t w = (n_epochs + 9) / 10;
-    return w < 1 ? 1 : w;
-}
+static double std_normal_cdf(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
 
-/* C_e = sum of (t+1) over the iterations t of epoch e (the last epoch may be short). */
-static double epoch_weight(uint64_t e, uint64_t T, int M)
+/* p_0 = prod_k P(b_k - s_k Z_k >= 0) = prod_k Phi(b_k / s_k);
+ * p_{a+1} = P(b_a - s_a Z_a < 0 and below every other value)
+ *         = integral over z > b_a / s_a of phi(z) prod_{k != a} Phi((b_k - b_a + s_a z) / s_k) dz,
+ * by composite Simpson's rule on [max(b_a/s_a, -12), 12] with 24,000 intervals. */
+double or_cv_pick_probs(int d, const double *b, const double *s, double *p)
 {
-    const uint64_t t0 = e * (uint64_t)M;
-    uint64_t t1 = t0 + (uint64_t)M;
-    if (t1 > T) t1 = T;
-    double c = 0.0;
-    for (uint64_t t = t0; t < t1; ++t) c += (double)(t + 1);
-    return c;
-}
-
-double or_cv_weight_norm(uint64_t T, int M)
-{
-    const uint64_t E = (T + (uint64_t)M - 1) / (uint64_t)M;
-    double s = 0.0;
-    for (uint64_t e = 0; e < E; ++e) {
-        const double c = epoch_weight(e, T, M);
-        s += c * c;
+    const double inv_sqrt_2pi = 0.39894228040143267793994605993438;
+    double p0 = 1.0;
+    for (int k = 0; k < d; ++k) p0 *= std_normal_cdf(b[k] / s[k]);
+    p[0] = p0;
+    double total = p0;
+    for (int a = 0; a < d; ++a) {
+        double lo = b[a] / s[a];
+        if (lo < -12.0) lo = -12.0;
+        const double hi = 12.0;
+        double acc = 0.0;
+        if (lo < hi) {
+            const int n = 24000;
+            const double h = (hi - lo) / n;
+            for (int i = 0; i <= n; ++i) {
+                const double z = lo + h * i;
+                double f = inv_sqrt_2pi * exp(-0.5 * z * z);
+                for (int k = 0; k < d; ++k)
+                    if (k != a) f *= std_normal_cdf((b[k] - b[a] + s[a] * z) / s[k]);
+                const double wgt = (i == 0 || i == n) ? 1.0 : ((i % 2) ? 4.0 : 2.0);
+                acc += wgt * f;
+            }
+            acc *= h / 3.0;
+        }
+        p[a + 1] = acc;
+        total += acc;
     }
-    return sqrt(s);
+    return total;
 }
 
-double or_cv_eta_corr(uint64_t T, int M, int d)
+void or_cv_weights(uint64_t T, int M, double *S2, double *S4)
 {
-    const uint64_t E = (T + (uint64_t)M - 1) / (uint64_t)M;
-    const uint64_t W = or_cv_late_epochs(E);
-    double late = 0.0;
-    for (uint64_t e = E - W; e < E; ++e) late += epoch_weight(e, T, M);
-    return late / (or_cv_weight_norm(T, M) * sqrt((double)W * (double)d));
+    double s2 = 0.0, s4 = 0.0;
+    for (uint64_t t0 = 0; t0 < T; t0 += (uint64_t)M) {
+        double we = 0.0;
+        for (uint64_t t = t0; t < t0 + (uint64_t)M && t < T; ++t) we += (double)(t + 1) * (double)(t + 1);
+        s2 += we;
+        s4 += we * we;
+    }
+    *S2 = s2;
+    *S4 = s4;
+}
+
+void or_cv_features(int d, const double *probs, double S2, double S4, double kdof, const double *count,
+                    double q, double *x)
+{
+    for (int c = 0; c <= d; ++c) {
+        double v = probs[c] * (1.0 - probs[c]);
+        if (v < 1e-4) v = 1e-4;
+        const double f = (count[c] - probs[c] * S2) / sqrt(S4 * v);
+        x[c == 0 ? d : c - 1] = f;
+    }
+    x[d + 1] = (q - kdof) / sqrt(2.0 * kdof);
 }
 
 /* Gamma(alpha, 1) by Marsaglia and Tsang, "A simple method for generating gamma variables",
  * ACM TOMS 26(3), 2000: for shape a >= 1, d = a - 1/3, c = 1/sqrt(9 d); with x ~ N(0,1) and
  * v = (1 + c x)^3 > 0, accept d v when log U < x^2/2 + d - d v + d log v. A shape alpha < 1 runs
  * with a = alpha + 1 and scales the result by V^(1/alpha), V uniform (same paper, Section 6).
- * Try i uses Philox block 64 + i of the draw's stream: its first pair gives x by Box-Muller (cosine
- * branch), word 2 gives U and word 3 gives V. Returns the number of tries used, or -1 if none of
- * 64 accepted (then *g = d). */
+ * Try i uses Philox block 64 + i of the draw's stream (epoch word 0): its first pair gives x by
+ * Box-Muller (cosine branch), word 2 gives U and word 3 gives V. Returns the number of tries used,
+ * or -1 if none of 64 accepted (then *g = d). */
 static int gamma_mt(double alpha, uint64_t seed, uint32_t instance, uint64_t k, double *g)
 {
     const int boost = alpha < 1.0;
@@ -91,23 +118,41 @@ static int gamma_mt(double alpha, uint64_t seed, uint32_t instance, uint64_t k, 
     return -1;
 }
 
-int or_cv_aux(const or_problem *p, uint64_t T, uint64_t k, double *x)
+/* A uniform in (0,1) with 53 random bits from two words: ((a >> 5) 2^26 + (b >> 6) + 1/2) 2^-53. */
+static double uniform53(uint32_t a, uint32_t b)
 {
-    const int d = p->d;
-    double z[OR_MAX_D + 1];
-    or_normals(p->seed, OR_DOMAIN_CV_AUX, p->instance, k, 0, 0, (uint64_t)d + 1, z);
-    const double a = or_cv_eta_corr(T, p->M, d);
-    double s = 0.0;
-    for (int j = 0; j < d; ++j) {
-        x[j] = z[j];
-        s += z[j];
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+int or_cv_aux(const or_problem *p, uint64_t T, const double *probs, uint64_t k, double *count, double *q)
+{
+    const int d = p->d, M = p->M;
+    uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
+    for (int c = 0; c <= d; ++c) count[c] = 0.0;
+    uint64_t e = 0;
+    for (uint64_t t0 = 0; t0 < T; t0 += (uint64_t)M, ++e) {
+        /* epoch e: words (2 (e mod 2), 2 (e mod 2) + 1) of block e / 2, epoch word 1 */
+        uint32_t ctr[4] = {(uint32_t)(e / 2), 1u, (uint32_t)k, (OR_DOMAIN_CV_AUX << 24) | (p->instance & 0xFFFFFFu)};
+        uint32_t w[4];
+        or_philox4x32_10(ctr, key, w);
+        const double u = (e % 2 == 0) ? uniform53(w[0], w[1]) : uniform53(w[2], w[3]);
+        int cat = d;                       /* the smallest c with u < p_0 + ... + p_c */
+        double cum = 0.0;
+        for (int c = 0; c < d; ++c) {
+            cum += probs[c];
+            if (u < cum) {
+                cat = c;
+                break;
+            }
+        }
+        double we = 0.0;
+        for (uint64_t t = t0; t < t0 + (uint64_t)M && t < T; ++t) we += (double)(t + 1) * (double)(t + 1);
+        count[cat] += we;
     }
-    x[d] = a * s + sqrt(1.0 - (double)d * a * a) * z[d];
-    const uint64_t E = (T + (uint64_t)p->M - 1) / (uint64_t)p->M;
-    const double kdof = (double)E * (double)d * (double)(p->N - 1);
+    const double kdof = (double)e * (double)d * (double)(p->N - 1);
     double g = 0.0;
     const int tries = gamma_mt(0.5 * kdof, p->seed, p->instance, k, &g);
-    x[d + 1] = (2.0 * g - kdof) / sqrt(2.0 * kdof);
+    *q = 2.0 * g;
     return tries;
 }
 

@@ -164,25 +164,41 @@ double or_objective(const or_problem *p, const double *w)
     return p->lambda * quad - lin;
 }
 
-/* Per-epoch noise summaries for the control-variate features: u_j = sum_i z_ij / sqrt(N), which
- * is N(0,1), and q = sum_j sum_i (z_ij - zbar_j)^2, which is chi-square with d (N-1) degrees of
- * freedom and independent of u (sample mean and sample variance of a Gaussian sample). */
-static void cv_epoch_summaries(int d, int N, const double *z, double *u, double *q)
+/* Per-epoch summaries for the control-variate features (see cv.c): the reference decision -- the
+ * vertex the linear subproblem picks for the fixed gradient cv_ref perturbed by this epoch's
+ * sample-mean noise, cv_ref - L zbar (lowest index among equal minima, the origin when the
+ * minimum is >= 0) -- with the gap between its value and the next best, and the pooled
+ * within-asset sum of squares sum_j sum_i (z_ij - zbar_j)^2. */
+static int cv_epoch_summaries(const or_problem *p, const double *z, double *zbar, double *vals,
+                              double *q, double *margin)
 {
+    const int d = p->d, N = p->N;
     double qs = 0.0;
     for (int j = 0; j < d; ++j) {
         double s = 0.0;
         for (int i = 0; i < N; ++i) s += z[(size_t)i * d + j];
-        const double mean = s / (double)N;
-        double ss = 0.0;
+        zbar[j] = s / (double)N;
         for (int i = 0; i < N; ++i) {
-            const double e = z[(size_t)i * d + j] - mean;
-            ss += e * e;
+            const double e = z[(size_t)i * d + j] - zbar[j];
+            qs += e * e;
         }
-        u[j] = s / sqrt((double)N);
-        qs += ss;
     }
     *q = qs;
+    vals[0] = 0.0;                                   /* the origin */
+    for (int j = 0; j < d; ++j) {
+        double lz = 0.0;
+        for (int k = 0; k <= j; ++k) lz += p->chol[j * d + k] * zbar[k];
+        vals[j + 1] = p->cv_ref[j] - lz;
+    }
+    int best = 1;
+    for (int c = 2; c <= d; ++c)
+        if (vals[c] < vals[best]) best = c;
+    const int pick = (vals[best] < 0.0) ? best : 0;
+    double second = INFINITY;
+    for (int c = 0; c <= d; ++c)
+        if (c != pick && vals[c] < second) second = vals[c];
+    *margin = second - vals[pick];
+    return pick;
 }
 
 /* ---------------------------------------------------------------------------------------------
@@ -208,11 +224,10 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
     double *habs = (double *)malloc(sizeof(double) * (size_t)d);
     double *pabs = (double *)malloc(sizeof(double) * (size_t)N);
     double *zraw = (double *)malloc(sizeof(double) * (size_t)N * d);
-    double *u_e = (double *)malloc(sizeof(double) * (size_t)d);
-    double *xi = (double *)calloc((size_t)d, sizeof(double));
-    double q_e = 0.0, eta = 0.0, zeta = 0.0;
-    const uint64_t n_epochs = (T + (uint64_t)M - 1) / (uint64_t)M;
-    const uint64_t late = or_cv_late_epochs(n_epochs);
+    double *zbar = (double *)malloc(sizeof(double) * (size_t)d);
+    double *rvals = (double *)malloc(sizeof(double) * (size_t)(d + 1));
+    int ref_pick = 0;
+    double ref_margin = INFINITY;
 
     memset(out, 0, sizeof(*out));
     out->tau = out->tau_lo = out->tau_hi = OR_TAU_NONE;
@@ -226,13 +241,17 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
         const uint64_t epoch = t / (uint64_t)M;        /* k = t div M, m = t mod M */
         if (t % (uint64_t)M == 0) {                    /* resample */
             draw_returns(p, rep, epoch, Rmat, noise, zraw);
-            cv_epoch_summaries(d, N, zraw, u_e, &q_e);
-            if (epoch >= n_epochs - late) {
-                for (int j = 0; j < d; ++j) eta += u_e[j];
+            if (p->cv_ref) {
+                double q_e = 0.0;
+                ref_pick = cv_epoch_summaries(p, zraw, zbar, rvals, &q_e, &ref_margin);
+                out->cv_q += q_e;
             }
-            zeta += q_e;
         }
-        for (int j = 0; j < d; ++j) xi[j] += (double)(t + 1) * u_e[j];
+        if (p->cv_ref) {                               /* weight (t+1)^2 on this epoch's pick */
+            const double wt = (double)(t + 1) * (double)(t + 1);
+            out->cv_count[ref_pick] += wt;
+            if (ref_margin < OR_CV_AMBIGUOUS) out->cv_amb += wt;
+        }
 
         /* gradient of the sample objective at w_m */
         sample_statistics(p, Rmat, w, rbar, sw);
@@ -328,22 +347,13 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
     }
     out->y = or_objective(p, w);   /* return w: the outcome is f at the last iterate */
 
-    /* control-variate features (noise summaries with a known joint law) */
-    {
-        const double xnorm = or_cv_weight_norm(T, M);
-        for (int j = 0; j < d; ++j) out->feat[j] = xi[j] / xnorm;
-        out->feat[d] = eta / sqrt((double)late * (double)d);
-        const double k = (double)n_epochs * (double)d * (double)(N - 1);
-        out->feat[d + 1] = (zeta - k) / sqrt(2.0 * k);
-    }
-
     double tt = (double)T * (double)(T + 1);
     for (int j = 0; j < d; ++j) {
         double closed = 2.0 * (double)out->wsum[j] / tt;
         double e = fabs(w[j] - closed);
         if (e > out->identity_err) out->identity_err = e;
     }
-    free(xi); free(u_e); free(zraw);
+    free(rvals); free(zbar); free(zraw);
     free(pabs); free(habs); free(vabs);
     free(vals); free(sw); free(rbar); free(g); free(w); free(noise); free(Rmat);
     return 0;

@@ -50,7 +50,11 @@ typedef struct {
     const double *chol;     /* d*d row-major lower-triangular L, Sigma = L L' */
     const double *w0;       /* d starting point in W, or NULL for the origin */
     int64_t ckpt[OR_MAX_CKPT]; /* iterate counts in [1, T] at which f(w_t) is recorded */
+    const double *cv_ref;   /* d reference gradient of the control-variate features, or NULL */
 } or_problem;
+
+/* reference decisions whose margin is below this are reported as ambiguous (cv_amb) */
+#define OR_CV_AMBIGUOUS 1e-4
 
 /* Everything one replication produces. */
 typedef struct {
@@ -66,7 +70,13 @@ typedef struct {
     int64_t first_mismatch;         /* step of the first mismatch, or -1 */
     double identity_err;            /* max_j |w_T - 2 wsum/(T(T+1))| (recurrence vs closed form) */
     double min_margin;              /* smallest LMO margin seen along the path */
-    double feat[OR_MAX_D + 2];      /* control-variate features xi_0..xi_{d-1}, eta, zeta */
+    /* control-variate raw summaries (cv_ref set): per category c (0 origin, j+1 vertex e_j) the sum
+     * of (t+1)^2 over iterations whose epoch's reference decision is c; the pooled within-asset
+     * sum of squares over epochs; the (t+1)^2 weight of iterations whose reference margin is below
+     * OR_CV_AMBIGUOUS */
+    double cv_count[OR_MAX_D + 1];
+    double cv_q;
+    double cv_amb;
 } or_path_out;
 
 typedef struct {
@@ -130,15 +140,19 @@ typedef struct {
     double mean_cv, var_est, ci95_cv;           /* the estimate, its variance, 95% half-width */
 } or_cv_stats;
 
-/* Epochs E = ceil(T/M); the late window holds the last ceil(E/10) epochs. */
-uint64_t or_cv_late_epochs(uint64_t n_epochs);
-/* sqrt(sum_e C_e^2), C_e = sum of (t+1) over the iterations of epoch e. */
-double or_cv_weight_norm(uint64_t T, int M);
-/* Cov(xi_j, eta) of the path features. */
-double or_cv_eta_corr(uint64_t T, int M, int d);
-/* Draw k (stream domain 2) from the exact joint law of the d+2 path features; returns the
- * gamma sampler's tries, or -1 if it did not accept within 64. */
-int or_cv_aux(const or_problem *p, uint64_t T, uint64_t k, double *x);
+/* Probabilities of the reference decision, p[0] the origin and p[j+1] vertex e_j, for a gradient
+ * b - s .* Z with Z ~ N(0, I_d) (s > 0: the standard deviations of the sample-mean noise, sigma / sqrt(N)). */
+double or_cv_pick_probs(int d, const double *b, const double *s, double *p);
+/* S2 = sum_t (t+1)^2 and S4 = sum_e (sum of (t+1)^2 over epoch e)^2 for T iterations, epochs of M. */
+void or_cv_weights(uint64_t T, int M, double *S2, double *S4);
+/* Standardized features x[0..d+1] from raw summaries: x_j (j < d) for category j+1, x_d for the
+ * origin, (count_c - p_c S2) / sqrt(S4 max(p_c (1 - p_c), 1e-4)); x_{d+1} = (q - k) / sqrt(2 k). */
+void or_cv_features(int d, const double *probs, double S2, double S4, double kdof, const double *count,
+                    double q, double *x);
+/* Draw k (stream domain 2) from the exact joint law of the raw summaries: per epoch a category
+ * from probs (one 53-bit uniform), and q ~ chi-square(E d (N-1)). Returns the gamma sampler's
+ * tries, or -1 if it did not accept within 64. */
+int or_cv_aux(const or_problem *p, uint64_t T, const double *probs, uint64_t k, double *count, double *q);
 
 /* bfloat16 rounding (to nearest even, through binary32). */
 double or_bf16(double v);

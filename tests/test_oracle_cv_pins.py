@@ -1,12 +1,12 @@
 """Pins of the oracle's control-variate pieces against what mathematics fixes.
 
-* Path features: their joint law is exact by construction (sample means and sample variances of
-  Gaussian samples): xi ~ N(0, I_d), eta ~ N(0, 1) with Cov(xi_j, eta) = a, zeta a standardized
-  chi-square(E d (N-1)) independent of both. Checked by KS tests and correlation bounds over
-  oracle paths, for M = 1, for M = 3 with a short last epoch, and with t noise (whose Gaussian
-  numerators carry the features).
-* Aux draws: the same law (KS per coordinate, correlations), including the gamma sampler at
-  shapes below, at and above one, and a two-sample KS against path features.
+* Reference-decision probabilities: they sum to one, reduce to normal CDFs for one asset and to
+  equal shares for a symmetric instance, and match brute-force Monte Carlo of the argmin.
+* Path features: the raw summaries' exact moments (E count_c = p_c S2, Cov = S4 (p_c [c = c'] -
+  p_c p_c')), the chi-square law of the pooled sum of squares and its independence, for M = 1,
+  M = 3 with a short last epoch, and t noise; the T = 1 case against the argmin of the raw normals.
+* Aux draws: category frequencies against p (chi-square goodness of fit), the same moments, the
+  gamma sampler's chi-square law at shapes 1/2, 1, 3 and 4.5e5, and agreement with path features.
 * Surrogate gradient: central finite differences of the unrounded network, and torch's autograd
   (float64) on an independent formulation of the rounded network.
 * bfloat16 rounding: torch's float32 -> bfloat16 conversion, ties included.
@@ -21,87 +21,171 @@ import scipy.stats as ss
 import oracle
 
 
-def _features(d, N, M, T, R, noise=oracle.NOISE_GAUSS, nu=3, seed=3):
-    mu = np.linspace(0.1, 0.4, d)
-    sigma = np.linspace(0.3, 0.6, d)
-    P = oracle.OracleProblem(mu, sigma, N=N, M=M, noise=noise, nu=nu, seed=seed, instance=2)
+def _instance(d, seed=3):
+    g = np.random.default_rng(seed)
+    mu = g.uniform(0.1, 0.6, d)
+    sigma = g.uniform(0.2, 0.7, d)
+    return mu, sigma
+
+
+def _ref(mu, sigma, N, scale=0.6):
+    """A reference gradient near the problem's: 2 lambda Sigma w - mu at an interior point."""
+    d = mu.shape[0]
+    w = np.full(d, scale / d)
+    return sigma ** 2 * w - mu
+
+
+@pytest.mark.parametrize("d", [1, 3, 10, 32])
+def test_pick_probs_sum_to_one(d):
+    g = np.random.default_rng(d)
+    for _ in range(3):
+        b = g.uniform(-0.8, 0.3, d)
+        s = g.uniform(0.05, 0.5, d)
+        p, tot = oracle.cv_pick_probs(b, s)
+        assert abs(tot - 1.0) < 1e-11 and np.all(p >= 0)
+
+
+def test_pick_probs_closed_forms():
+    p, _ = oracle.cv_pick_probs([-0.3], [0.4])
+    assert math.isclose(p[0], ss.norm.cdf(-0.75), rel_tol=1e-12)
+    assert math.isclose(p[1], ss.norm.sf(-0.75), rel_tol=1e-12)
+    d = 5
+    p, _ = oracle.cv_pick_probs(np.full(d, -0.2), np.full(d, 0.3))
+    p0 = ss.norm.cdf(-0.2 / 0.3) ** d
+    assert math.isclose(p[0], p0, rel_tol=1e-12)
+    assert np.allclose(p[1:], (1 - p0) / d, rtol=1e-11)
+
+
+def test_pick_probs_monte_carlo():
+    g = np.random.default_rng(11)
+    d = 6
+    b = g.uniform(-0.5, 0.1, d)
+    s = g.uniform(0.1, 0.4, d)
+    p, _ = oracle.cv_pick_probs(b, s)
+    n = 2_000_000
+    V = b - s * g.standard_normal((n, d))
+    j = V.argmin(1)
+    cat = np.where(V[np.arange(n), j] < 0, j + 1, 0)
+    freq = np.bincount(cat, minlength=d + 1) / n
+    se = np.sqrt(p * (1 - p) / n)
+    assert np.all(np.abs(freq - p) < 5 * se + 1e-12)
+
+
+def _paths(d, N, M, T, R, noise=oracle.NOISE_GAUSS, seed=3):
+    mu, sigma = _instance(d)
+    P = oracle.OracleProblem(mu, sigma, N=N, M=M, noise=noise, nu=4, seed=seed, instance=2,
+                             cv_ref=_ref(mu, sigma, N))
     outs = P.run(R, T)
-    X = np.array([[o.feat[j] for j in range(d + 2)] for o in outs])
-    return P, X
+    C = np.array([[o.cv_count[c] for c in range(d + 1)] for o in outs])
+    q = np.array([o.cv_q for o in outs])
+    return P, C, q
 
 
-def _check_law(X, d, N, M, T, alpha=1e-3):
-    n = X.shape[0]
-    for j in range(d):
-        assert ss.kstest(X[:, j], "norm").pvalue > alpha, f"xi_{j}"
-    assert ss.kstest(X[:, d], "norm").pvalue > alpha, "eta"
-    E = -(-T // M)
-    k = E * d * (N - 1)
-    chi = X[:, d + 1] * math.sqrt(2 * k) + k
-    assert ss.kstest(chi, ss.chi2(k).cdf).pvalue > alpha, "zeta"
-    a = oracle.cv_eta_corr(T, M, d)
-    se = 4.5 / math.sqrt(n)
-    for j in range(d):
-        assert abs(np.corrcoef(X[:, j], X[:, d])[0, 1] - a) < se, f"corr(xi_{j}, eta)"
-        assert abs(np.corrcoef(X[:, j], X[:, d + 1])[0, 1]) < se, f"corr(xi_{j}, zeta)"
-        for i in range(j):
-            assert abs(np.corrcoef(X[:, j], X[:, i])[0, 1]) < se
-    assert abs(np.corrcoef(X[:, d], X[:, d + 1])[0, 1]) < se
+def _check_moments(C, q, law, tol=5.0):
+    n = C.shape[0]
+    p, S2, S4 = law.probs, law.S2, law.S4
+    mean = p * S2
+    var = p * (1 - p) * S4
+    ok = var > 0
+    z = (C.mean(0) - mean)[ok] / np.sqrt(var[ok] / n)
+    assert np.all(np.abs(z) < tol), z
+    # variances of the categories that are neither rare nor dominant (sums of many weighted
+    # indicators, close to normal): the sample variance scatters by about sqrt(2/n) (relative)
+    mid = (p > 0.05) & (p < 0.95)
+    rv = C.var(0, ddof=1)[mid] / var[mid]
+    assert np.all(np.abs(rv - 1) < tol * math.sqrt(2.0 / n) + 0.02), rv
+    # the covariance of two categories is -p_c p_c' S4
+    big = np.argsort(p)[-2:]
+    a, b = big
+    cov = np.cov(C[:, a], C[:, b])[0, 1]
+    assert abs(cov + p[a] * p[b] * S4) < tol * math.sqrt(var[a] * var[b] / n) * 1.5
+    k = law.kdof
+    assert ss.kstest(q, ss.chi2(k).cdf).pvalue > 1e-3
+    for c in big:
+        assert abs(np.corrcoef(C[:, c], q)[0, 1]) < tol / math.sqrt(n)
 
 
 @pytest.mark.parametrize("d,N,M,T,noise", [
     (3, 5, 1, 40, oracle.NOISE_GAUSS),
     (2, 4, 3, 40, oracle.NOISE_GAUSS),      # 14 epochs, the last one a single iteration
-    (3, 3, 1, 30, oracle.NOISE_T),
+    (3, 3, 1, 30, oracle.NOISE_T),          # the features use the Gaussian numerators
 ])
 def test_path_feature_law(d, N, M, T, noise):
-    P, X = _features(d, N, M, T, 3000, noise=noise)
-    _check_law(X, d, N, M, T)
+    P, C, q = _paths(d, N, M, T, 3000, noise=noise)
+    law = oracle.CvLaw(P, T)
+    assert abs(law.total - 1) < 1e-11
+    assert np.allclose(C.sum(1), law.S2)
+    _check_moments(C, q, law)
 
 
-def test_feature_constants():
-    # M = 1, T = 4: weights 1..4, norm sqrt(30); the late window is one epoch (the last)
-    assert math.isclose(oracle.cv_weight_norm(4, 1), math.sqrt(30.0), rel_tol=1e-15)
-    assert oracle.cv_late_epochs(4) == 1 and oracle.cv_late_epochs(10) == 1 and oracle.cv_late_epochs(11) == 2
-    assert math.isclose(oracle.cv_eta_corr(4, 1, 2), 4.0 / (math.sqrt(30.0) * math.sqrt(2.0)), rel_tol=1e-15)
-    # M = 3, T = 7: epochs {0,1,2}, {3,4,5}, {6} with weights 6, 15, 7
-    assert math.isclose(oracle.cv_weight_norm(7, 3), math.sqrt(36 + 225 + 49), rel_tol=1e-15)
-    # Cauchy-Schwarz keeps the eta mixture valid: d a^2 <= 1
-    for T, M, d in [(10_000, 1, 10), (1000, 1, 64), (7, 3, 1), (1, 1, 1)]:
-        assert d * oracle.cv_eta_corr(T, M, d) ** 2 <= 1.0 + 1e-15
+def test_weights_closed_form():
+    S2, S4 = oracle.cv_weights(4, 1)
+    assert S2 == 1 + 4 + 9 + 16 and S4 == 1 + 16 + 81 + 256
+    S2, S4 = oracle.cv_weights(7, 3)        # epochs {1,2,3}, {4,5,6}, {7}
+    assert S2 == 140 and S4 == 14 ** 2 + 77 ** 2 + 49 ** 2
 
 
-def test_single_iteration_features_are_sample_summaries():
-    """T = 1: xi is sqrt(N) times the sample mean of the one draw and zeta is the standardized
-    pooled within-asset sum of squares; eta (one late epoch) is the sum of xi over sqrt(d)."""
-    d, N = 3, 6
-    P = oracle.OracleProblem(np.zeros(d), np.ones(d), N=N, seed=11, instance=0)
-    o = P.path(5, 1)
-    Z = oracle.normals(11, 0, 0, 5, 0, 0, N * d).reshape(N, d)
-    xi = Z.mean(axis=0) * math.sqrt(N)
-    k = d * (N - 1)
-    ssq = ((Z - Z.mean(axis=0)) ** 2).sum()
-    assert np.allclose([o.feat[j] for j in range(d)], xi, rtol=1e-13, atol=1e-14)
-    assert math.isclose(o.feat[d], xi.sum() / math.sqrt(d), rel_tol=1e-13)
-    assert math.isclose(o.feat[d + 1], (ssq - k) / math.sqrt(2 * k), rel_tol=1e-12, abs_tol=1e-14)
+def test_single_iteration_pick_is_the_argmin_of_the_sample_mean():
+    d, N = 4, 6
+    mu, sigma = _instance(d)
+    b = _ref(mu, sigma, N)
+    P = oracle.OracleProblem(mu, sigma, N=N, seed=11, instance=0, cv_ref=b)
+    for r in range(20):
+        o = P.path(r, 1)
+        Z = oracle.normals(11, 0, 0, r, 0, 0, N * d).reshape(N, d)
+        v = b - sigma * Z.mean(axis=0)
+        cat = int(v.argmin()) + 1 if v.min() < 0 else 0
+        expect = np.zeros(d + 1)
+        expect[cat] = 1.0
+        assert np.array_equal([o.cv_count[c] for c in range(d + 1)], expect)
+        ssq = ((Z - Z.mean(axis=0)) ** 2).sum()
+        assert math.isclose(o.cv_q, ssq, rel_tol=1e-13)
 
 
-@pytest.mark.parametrize("d,N,M,T", [(3, 5, 1, 40), (1, 2, 1, 1), (1, 3, 1, 1), (1, 2, 1, 6), (10, 10, 1, 10_000)])
+def test_aux_categories_follow_the_probabilities():
+    d, N = 4, 5
+    mu, sigma = _instance(d)
+    P = oracle.OracleProblem(mu, sigma, N=N, seed=21, instance=4, cv_ref=_ref(mu, sigma, N, 0.3))
+    law = oracle.CvLaw(P, 1)
+    X, C, tries = law.aux(0, 20000)
+    obs = C.sum(0)
+    exp = law.probs * C.shape[0]
+    keep = exp > 5
+    chi = (((obs - exp) ** 2) / exp)[keep].sum()
+    assert ss.chi2(keep.sum() - 1).sf(chi) > 1e-3
+
+
+@pytest.mark.parametrize("d,N,M,T", [(3, 5, 1, 40), (1, 2, 1, 1), (1, 3, 1, 1), (1, 2, 1, 6), (2, 4, 3, 40)])
 def test_aux_law(d, N, M, T):
-    """k = E d (N-1) of 1, 2 and 6 run the gamma sampler at shapes 1/2, 1 and 3; 9e5 at the
-    control-variate workload's size."""
-    P = oracle.OracleProblem(np.zeros(d), np.ones(d), N=N, M=M, seed=21, instance=4)
-    X, tries = oracle.cv_aux(P, T, 0, 4000)
+    """k = E d (N-1) of 1, 2 and 6 run the gamma sampler at shapes 1/2, 1 and 3."""
+    mu, sigma = _instance(d)
+    P = oracle.OracleProblem(mu, sigma, N=N, M=M, seed=21, instance=4, cv_ref=_ref(mu, sigma, N))
+    law = oracle.CvLaw(P, T)
+    X, C, tries = law.aux(0, 4000)
     assert np.all(tries >= 1)
-    _check_law(X, d, N, M, T)
+    _check_moments(C, law.kdof * 0 + (X[:, d + 1] * math.sqrt(2 * law.kdof) + law.kdof), law)
+
+
+def test_aux_gamma_at_the_control_variate_size():
+    d, N, T = 10, 10, 10_000
+    mu, sigma = _instance(d)
+    P = oracle.OracleProblem(mu, sigma, N=N, seed=21, instance=4, cv_ref=_ref(mu, sigma, N))
+    law = oracle.CvLaw(P, 1)
+    law.T, law.kdof = T, float(T * d * (N - 1))          # the gamma part only (one epoch of picks)
+    X, C, tries = law.aux(0, 3000)
+    q = X[:, d + 1] * math.sqrt(2 * law.kdof) + law.kdof
+    assert ss.kstest(q, ss.chi2(law.kdof).cdf).pvalue > 1e-3
 
 
 def test_aux_matches_path_features():
     d, N, M, T = 2, 4, 3, 40
-    P, Xp = _features(d, N, M, T, 3000)
-    Xa, _ = oracle.cv_aux(P, T, 0, 3000)
+    P, C, q = _paths(d, N, M, T, 3000)
+    law = oracle.CvLaw(P, T)
+    Xa, Ca, _ = law.aux(0, 3000)
+    Xp = np.array([law.standardize(C[i], q[i]) for i in range(C.shape[0])])
     for j in range(d + 2):
         assert ss.ks_2samp(Xp[:, j], Xa[:, j]).pvalue > 1e-3
+    assert np.allclose(Xp[:, :d + 1].mean(0), 0.0, atol=0.15)
 
 
 def _theta(F, seed, scale=0.4):
