@@ -253,12 +253,16 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
                      "sim_ms": fit.sim_ms, "train_ms": fit.train_ms, "loss_first_epoch": fit.loss_first_epoch,
                      "loss_last_epoch": fit.loss_last_epoch, "beta": fit.beta, "pilot_rho2": fit.rho2},
            "pilot_paths": pilot_R, "sd_plain": s_plain, "sd_resid": s_resid,
-           "variance_ratio": ps.var / max(cs.var_resid, 1e-300), "targets": []}
+           "variance_ratio": ps.var / max(cs.var_resid, 1e-300), "aux_per_path": None, "targets": []}
+    # aux draws per path: the variance-per-cost optimum sqrt(beta^2 var(h) / (c var(Y - beta h))), c the
+    # cost of one draw relative to one path (one uniform per epoch against N d normals per iteration)
+    c_aux = 1.0 / 60.0
+    ratio = min(100.0, max(1.0, math.sqrt(beta2_vh / (c_aux * max(cs.var_resid, 1e-300)))))
     for h in (1e-3, 1.96 * s_plain / 1000.0):
         r_plain = max(2, math.ceil((1.96 * s_plain / h) ** 2))
-        r_cv = max(2, math.ceil((1.96 * s_resid / h) ** 2))
-        r_aux = max(1 << 20, 50 * r_cv)
-        r_aux = min(r_aux, 1 << 31)
+        r_cv = max(2, math.ceil((1.96 / h) ** 2 * (cs.var_resid + beta2_vh / ratio)))
+        r_aux = min(max(2, math.ceil(ratio * r_cv)), 1 << 31)
+        out["aux_per_path"] = ratio
         pm, plain_s = timed(lambda: plain_run(r_plain, eval_seed + 3))
         cm, cv_s = timed(lambda: cv_run(r_cv, eval_seed + 4, r_aux))
         out["targets"].append({

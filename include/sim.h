@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define SIM_ABI_VERSION 2u
+#define SIM_ABI_VERSION 3u
 #define SIM_MAX_D 64u          /* assets per instance */
 #define SIM_MAX_CKPT 8u        /* checkpoints per run */
 #define SIM_TAU_NONE 0xFFFFFFFFu
@@ -84,6 +84,7 @@ typedef struct {
     uint32_t instance_id;       /* stream domain of this instance, < 2^24 */
     uint64_t log_rep_begin;     /* SIM_DECISION_LOG: first logged replication */
     uint64_t log_rep_count;     /* SIM_DECISION_LOG: number of logged replications (<= 65536) */
+    const double *cv_ref;       /* SIM_CV_FEATURES: [d] reference gradient b of the features */
 } sim_params;
 
 /* FP64 statistics of one run. Means, variances and sums use compensated (double-double)
@@ -106,16 +107,19 @@ typedef struct {
 } sim_stats_out;
 
 /* Control-variate features (SIM_CV_FEATURES). A variance-reduction layer over the Monte Carlo
- * estimate of E f(w_T); not part of the paper's method. With z the Gaussian numerators a path draws
- * (for t noise, before the chi-square scaling), per epoch e of E = ceil(T/M):
- *   u_ej = sum_i z_eij / sqrt(N) and q_e = sum_j sum_i (z_eij - zbar_ej)^2;
- *   xi_j = sum_e C_e u_ej / sqrt(sum_e C_e^2), C_e = sum of (t+1) over the iterations of epoch e
- *          (the weights the step rule 2/(t+2) gives each iteration in w_T);
- *   eta  = sum of u_ej over the last W = ceil(E/10) epochs and all j, over sqrt(W d);
- *   zeta = (sum_e q_e - k) / sqrt(2k), k = E d (N-1).
- * Their joint law is exact: xi ~ N(0, I_d), eta ~ N(0,1) with Cov(xi_j, eta) = sum of C_e over the
- * late epochs / (sqrt(sum_e C_e^2) sqrt(W d)), zeta a standardized chi-square(k) independent of both.
- * Supported with FP32 state, diagonal Sigma and T <= 92681. */
+ * estimate of E f(w_T); not part of the paper's method. With zbar_e the sample mean of the Gaussian
+ * numerators a path draws in epoch e (for t noise, before the chi-square scaling), E = ceil(T/M):
+ *   J_e  = the vertex the linear subproblem over W picks for the gradient b - sigma .* zbar_e, with
+ *          b = cv_ref fixed before the run (lowest index among equal minima, the origin when the
+ *          minimum is >= 0): i.i.d. categorical over epochs with probabilities p_c (c = 0 origin,
+ *          c = j+1 vertex e_j), p_c one-dimensional normal integrals;
+ *   K_c  = sum over iterations t of (t+1)^2 [J_e(t) = c];  S2 = sum_t (t+1)^2,
+ *          S4 = sum_e (sum of (t+1)^2 over epoch e)^2;
+ *   q    = sum_e sum_j sum_i (z_eij - zbar_ej)^2 ~ chi-square(k), k = E d (N-1), independent of J.
+ * Features: x_j = (K_{j+1} - p_{j+1} S2) / sqrt(S4 max(p(1-p), 1e-4)) for j < d, x_d the same for
+ * the origin, x_{d+1} = (q - k) / sqrt(2k). Their joint law is exact for exact normals; binary32
+ * normals move it by their rounding only. Supported with FP32 state, diagonal Sigma with every
+ * sigma_j > 0, d <= 32 and T <= 92681. */
 
 /* Device pointers (owned by the context) to the per-path records of the last run, structure of
  * arrays indexed [field][r]. Fields not produced by the run are NULL. */
@@ -214,6 +218,8 @@ typedef struct {
 
 typedef struct {
     uint64_t n_train, steps;
+    double ref[SIM_MAX_D];  /* the reference gradient b used for the features: 2 lambda Sigma wbar - mu,
+                               wbar the mean of w_T over a plain pilot run (seed + n_runs + 1) */
     double y_mean, y_sd;    /* standardization of the training target */
     double loss_first_epoch, loss_last_epoch;   /* mean squared error of the standardized target */
     double beta, rho2;      /* Cov(Y, h) / Var(h) and Corr(Y, h)^2 on the pilot */
@@ -233,15 +239,17 @@ typedef struct {
     double kernel_ms;                           /* device time: paths, features, h, aux, reductions */
 } sim_cv_stats_out;
 
-/* Trains the surrogate for problem p (with T iterations) on the device: runs n_runs simulations
- * of R_train replications with features, standardizes Y, takes epochs x (n / batch) Adam steps
+/* Trains the surrogate for problem p (with T iterations) on the device: fixes the features'
+ * reference gradient from a plain pilot run, runs n_runs simulations of R_train replications with
+ * features, standardizes Y, takes epochs x (n / batch) Adam steps
  * over minibatches in a fresh affine permutation of the pairs per epoch, then fits beta on a
  * held-out pilot run. Synchronous. Supported problems: those SIM_CV_FEATURES supports. */
 int sim_cv_fit(sim_ctx *ctx, const sim_params *p, uint64_t T, uint64_t seed, const sim_cv_opts *o,
                sim_cv_fit_out *out);
 
 /* Control-variate estimate of E f(w_T) from R replications (seed `seed`) and R_aux draws from the
- * features' law (stream domain 2 of `seed`), with the fitted surrogate and beta. Synchronous. */
+ * features' law (stream domain 2 of `seed`), with the fitted surrogate, beta and reference gradient
+ * (p->cv_ref is not read). Synchronous. */
 int sim_run_cv(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed, uint64_t R_aux,
                sim_cv_stats_out *out);
 
@@ -263,11 +271,18 @@ int sim_mlp_get_params(sim_ctx *ctx, uint32_t F, float *theta);
 int sim_mlp_forward(sim_ctx *ctx, const float *x, uint64_t n, float *out);
 int sim_mlp_grad(sim_ctx *ctx, const float *x, const float *y, uint64_t n, float *grad, double *loss);
 
-/* Draws k0 .. k0+n-1 from the exact law of the features of problem p with T iterations (stream
- * domain 2 of seed) into host x [F][n]; failures (may be NULL): draws whose gamma sampler did not
- * accept within 64 tries. */
+/* Draws k0 .. k0+n-1 from the exact law of the features of problem p (reference gradient
+ * p->cv_ref) with T iterations into host x [F][n]: per epoch one 53-bit uniform from Philox block
+ * (e/2, 1, k, domain 2 | instance) picks the category by the cumulative p_0, p_1, ...; q by
+ * Marsaglia-Tsang gamma sampling on blocks (64+i, 0, k, ...). failures (may be NULL): draws whose
+ * gamma sampler did not accept within 64 tries. */
 int sim_cv_aux_draws(sim_ctx *ctx, const sim_params *p, uint64_t T, uint64_t seed, uint64_t k0, uint64_t n,
                      float *x, uint64_t *failures);
+
+/* The features' law for problem p (reference gradient p->cv_ref) with T iterations, without a
+ * device: probs [d+1] (0 origin, j+1 vertex e_j), S2 and S4 (may be NULL). Returns 0 or the code
+ * sim_run with SIM_CV_FEATURES would return. */
+int sim_cv_law(const sim_params *p, uint64_t T, double *probs, double *S2, double *S4, char *msg, size_t len);
 
 /* Statistics of the last run; synchronises the stream. */
 int sim_stats(sim_ctx *ctx, sim_stats_out *out);

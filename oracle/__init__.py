@@ -254,6 +254,8 @@ class CvLaw:
     """The features' law for a problem (diagonal L) with reference gradient cv_ref and T iterations."""
 
     def __init__(self, P: OracleProblem, T: int):
+        if P.cv_ref is None:
+            raise ValueError("the features' law needs a reference gradient (cv_ref)")
         sig = np.diag(P.chol).copy()
         self.P, self.T, self.d = P, T, P.d
         self.probs, self.total = cv_pick_probs(P.cv_ref, sig / np.sqrt(P.N))

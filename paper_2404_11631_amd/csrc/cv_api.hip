@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -16,6 +17,7 @@ using namespace fw::host;
 namespace {
 
 constexpr uint64_t kAuxChunk = 1ull << 22;
+constexpr uint64_t kRefPilot = 1ull << 14;   // replications of the run that fixes the reference gradient
 constexpr uint32_t kMomentBlocks = 512;
 
 // host double-double accumulation of chunk sums
@@ -120,15 +122,20 @@ MeanVar mean_var(double s, double s2, double shift, uint64_t n)
 
 fw::AuxLaw aux_law(const sim_params *p, uint64_t T, uint64_t seed)
 {
-    const CvConstants c = cv_constants(T, p->resample_every, p->d, p->n_samples);
+    const CvLaw L = cv_law(p, T);
     fw::AuxLaw law{};
     law.seed = seed;
     law.instance = p->instance_id;
     law.d = (int)p->d;
-    law.eta_a = c.eta_corr;
-    law.eta_b = std::sqrt(std::max(0.0, 1.0 - (double)p->d * c.eta_corr * c.eta_corr));
-    law.kdof = c.k;
-    law.alpha = 0.5 * c.k;
+    law.T = T;
+    law.M = p->resample_every;
+    law.kdof = L.k;
+    law.alpha = 0.5 * L.k;
+    for (uint32_t c = 0; c <= p->d; ++c) {
+        law.cum[c] = L.cum[c];
+        law.mean[c] = L.mean[c];
+        law.inv[c] = L.inv[c];
+    }
     return law;
 }
 
@@ -150,6 +157,22 @@ float elapsed(hipEvent_t a, hipEvent_t b)
 }  // namespace
 
 extern "C" {
+
+int sim_cv_law(const sim_params *p, uint64_t T, double *probs, double *S2, double *S4, char *msg, size_t len)
+{
+    char err[kErrLen] = {0};
+    if (!p || !probs) return SIM_EINVAL;
+    sim_params q = *p;
+    q.flags = SIM_CV_FEATURES;
+    const int rc = validate(err, &q, 1, T);
+    if (msg && len) std::snprintf(msg, len, "%s", rc ? err : "");
+    if (rc) return rc;
+    const CvLaw L = cv_law(&q, T);
+    for (uint32_t c = 0; c <= q.d; ++c) probs[c] = L.p[c];
+    if (S2) *S2 = L.S2;
+    if (S4) *S4 = L.S4;
+    return SIM_OK;
+}
 
 int sim_mlp_set_params(sim_ctx *ctx, uint32_t F, const float *theta)
 {
@@ -270,17 +293,39 @@ int sim_cv_fit(sim_ctx *ctx, const sim_params *p, uint64_t T, uint64_t seed, con
     if (o->reinit > 1) return set_err(ctx, SIM_EINVAL, "reinit must be 0 or 1");
     const uint64_t n = (uint64_t)o->n_runs * o->R_train;
     if (n > (1ull << 31)) return set_err(ctx, SIM_EINVAL, "more than 2^31 training pairs");
-    sim_params q = *p;
-    q.flags = SIM_CV_FEATURES;
-    int rc = validate(ctx->err, &q, std::max<uint64_t>(o->R_train, o->R_pilot), T);
+    // the features' reference gradient: 2 lambda Sigma wbar - mu, wbar the mean of w_T over a plain
+    // pilot run with its own seed
+    sim_params qp = *p;
+    qp.flags = SIM_KEEP_PATHS;
+    qp.n_checkpoints = 0;
+    qp.cv_ref = nullptr;
+    int rc = validate(ctx->err, &qp, kRefPilot, T);
     if (rc) return rc;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
+    CvState &cv = ctx->cv;
+    {
+        if ((rc = run_impl(ctx, &qp, kRefPilot, T, seed + o->n_runs + 1, 0u))) return rc;
+        std::vector<uint64_t> ws((size_t)p->d * kRefPilot);
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_TRY(ctx, hipMemcpy(ws.data(), ctx->wsum.ptr, sizeof(uint64_t) * ws.size(), hipMemcpyDeviceToHost));
+        const double c = 2.0 / ((double)T * (double)(T + 1));
+        for (uint32_t j = 0; j < p->d; ++j) {
+            double acc = 0.0;
+            for (uint64_t r = 0; r < kRefPilot; ++r) acc += (double)ws[j * kRefPilot + r];
+            const double wbar = c * acc / (double)kRefPilot;
+            cv.ref[j] = 2.0 * p->risk_coef * p->sigma[j] * p->sigma[j] * wbar - p->mu[j];
+        }
+    }
+    sim_params q = *p;
+    q.flags = SIM_CV_FEATURES;
+    q.cv_ref = cv.ref;
+    if ((rc = validate(ctx->err, &q, std::max<uint64_t>(o->R_train, o->R_pilot), T))) return rc;
     const int F = (int)q.d + 2;
     if ((rc = ensure_mlp(ctx, F))) return rc;
     if ((rc = ensure_events(ctx))) return rc;
-    CvState &cv = ctx->cv;
     const fw::MlpDev m = mlp_dev(cv);
     std::memset(out, 0, sizeof(*out));
+    for (uint32_t j = 0; j < q.d; ++j) out->ref[j] = cv.ref[j];
 
     // training pairs
     if ((rc = ensure(ctx, cv.xtrain, sizeof(float) * F * n))) return rc;
@@ -400,9 +445,10 @@ int sim_run_cv(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64
     if (R_aux > (1ull << 32)) return set_err(ctx, SIM_EINVAL, "R_aux above 2^32");
     sim_params q = *p;
     q.flags = SIM_CV_FEATURES;
+    q.cv_ref = cv.ref;
+    if ((int)q.d + 2 != cv.F) return set_err(ctx, SIM_EINVAL, "the surrogate was fitted for d=%d", cv.F - 2);
     int rc = validate(ctx->err, &q, R, T);
     if (rc) return rc;
-    if ((int)q.d + 2 != cv.F) return set_err(ctx, SIM_EINVAL, "the surrogate was fitted for d=%d", cv.F - 2);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if ((rc = ensure_events(ctx))) return rc;
     const fw::MlpDev m = mlp_dev(cv);

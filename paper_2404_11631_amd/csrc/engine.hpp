@@ -55,6 +55,7 @@ struct CvState {
     DevBuf xaux, haux, mpart, mout, mdone, fails;
     uint64_t n_train = 0, n_steps = 0, R = 0, n_aux_last = 0;
     double y_mean = 0.0, y_sd = 1.0, beta = 0.0, rho2 = 0.0;
+    double ref[SIM_MAX_D] = {0};          // the features' reference gradient of the fitted surrogate
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 

@@ -108,11 +108,13 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
     uint32_t ck = 0;
     uint64_t next_ckpt = n_ckpt ? P->ckpt[0] : 0;
     uint32_t epoch = 0, m_in_epoch = 0;   // t = epoch * M + m_in_epoch
-    // control-variate feature accumulators (FP64): sum_e C_e u_ej, late-window sum of u, sum_e q_e
-    double fxi[D];
-    double feta = 0.0, fzeta = 0.0;
+    // control-variate summaries: per category (0 origin, j+1 vertex e_j) the sum of (t+1)^2 over
+    // iterations whose epoch's reference decision is that category (integers < 2^53, exact in
+    // FP64 in any order), and the pooled within-asset sum of squares
+    double fcnt[D + 1];
+    double fzeta = 0.0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) fxi[j] = 0.0;
+    for (int j = 0; j <= D; ++j) fcnt[j] = 0.0;
 
     for (uint64_t t = 0; t < T; ++t) {
         // iterate w_t (scale factor of the signature) and v = sigma .* w_t
@@ -229,22 +231,29 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
 
         if constexpr (FEAT) {
             if (feat_epoch) {
-                // C_e = sum of (t+1) over the iterations of this epoch, [t, min(t + M, T))
+                // the reference decision for b - sigma .* zbar (FP64; lowest index among equal
+                // minima, the origin when the minimum is >= 0), weighted by the epoch's
+                // sum of (t+1)^2 over [t, min(t + M, T))
                 const uint64_t t1 = (t + M < T) ? t + M : T;
-                const double ce = 0.5 * (static_cast<double>(t1) * static_cast<double>(t1 + 1) -
-                                         static_cast<double>(t) * static_cast<double>(t + 1));
-                Real qsum = Real(0), usum = Real(0);
+                const double we = static_cast<double>(t1 * (t1 + 1) * (2 * t1 + 1) / 6 - t * (t + 1) * (2 * t + 1) / 6);
+                double vmin = 0.0;
+                int pick = 0;
+                Real qsum = Real(0);
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
                     if (j < d) {
                         const Real u = (NOISE == 1) ? g1[j] : s1[j];
-                        fxi[j] = fma(ce, static_cast<double>(u), fxi[j]);
+                        const double v = P->cv_b[j] - P->cv_s[j] * static_cast<double>(u);
+                        if (v < vmin) {
+                            vmin = v;
+                            pick = j + 1;
+                        }
                         qsum += sq[j] - u * u * C.inv_n();
-                        usum += u;
                     }
                 }
+#pragma unroll
+                for (int c = 0; c <= D; ++c) fcnt[c] += (c == pick) ? we : 0.0;
                 fzeta += static_cast<double>(qsum);
-                if (epoch >= P->cv_late_begin) feta += static_cast<double>(usum);
             }
         }
 
@@ -297,10 +306,14 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
         P, S, 2.0 / (static_cast<double>(T) * static_cast<double>(T + 1)));
     res.tau = tau;
     if constexpr (FEAT) {
+        // x_j for vertex e_j (category j+1), x_d for the origin, x_{d+1} the chi-square summary
 #pragma unroll
-        for (int j = 0; j < D; ++j)
-            if (j < d) B.feat[static_cast<uint64_t>(j) * R + r] = static_cast<float>(fxi[j] * P->cv_xi_scale);
-        B.feat[static_cast<uint64_t>(d) * R + r] = static_cast<float>(feta * P->cv_eta_scale);
+        for (int c = 0; c <= D; ++c) {
+            if (c <= d) {
+                const uint64_t row = (c == 0) ? static_cast<uint64_t>(d) : static_cast<uint64_t>(c - 1);
+                B.feat[row * R + r] = static_cast<float>((fcnt[c] - P->cv_mean[c]) * P->cv_inv[c]);
+            }
+        }
         B.feat[static_cast<uint64_t>(d + 1) * R + r] =
             static_cast<float>((fzeta * P->cv_kappa2 - P->cv_k) * P->cv_zeta_inv);
     }

@@ -89,8 +89,15 @@ int validate(char *err, const sim_params *p, uint64_t R, uint64_t T)
         if (p->state_precision != SIM_FP32)
             return fail(err, SIM_EUNSUPPORTED, "control-variate features need FP32 state");
         if (p->chol) return fail(err, SIM_EUNSUPPORTED, "control-variate features need diagonal Sigma");
+        if (p->d > 32) return fail(err, SIM_EUNSUPPORTED, "control-variate features need d <= 32");
         if (T > kMaxNarrowT)
             return fail(err, SIM_EUNSUPPORTED, "control-variate features need T <= %llu", (unsigned long long)kMaxNarrowT);
+        if (!p->cv_ref) return fail(err, SIM_EINVAL, "control-variate features need cv_ref");
+        for (uint32_t j = 0; j < p->d; ++j) {
+            if (!finite(p->cv_ref[j])) return fail(err, SIM_EINVAL, "cv_ref[%u] not finite", j);
+            if (!(p->sigma[j] > 0.0))
+                return fail(err, SIM_EUNSUPPORTED, "control-variate features need every sigma_j > 0");
+        }
     }
     if (p->instance_id >= (1u << 24)) return fail(err, SIM_EINVAL, "instance_id must be < 2^24");
     if (p->flags & SIM_DECISION_LOG) {
@@ -131,13 +138,18 @@ void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uin
     D.tscale_f = (float)(tnu / kappa);
     D.inv_n_f = (float)(1.0 / N);
     if (p->flags & SIM_CV_FEATURES) {
-        const CvConstants c = cv_constants(T, p->resample_every, p->d, p->n_samples);
-        D.cv_xi_scale = kappa / (std::sqrt(N) * c.weight_norm);
-        D.cv_eta_scale = kappa / (std::sqrt(N) * std::sqrt((double)c.late * (double)p->d));
+        const CvLaw law = cv_law(p, T);
+        for (uint32_t j = 0; j < p->d; ++j) {
+            D.cv_b[j] = p->cv_ref[j];
+            D.cv_s[j] = p->sigma[j] * kappa / N;
+        }
+        for (uint32_t c = 0; c <= p->d; ++c) {
+            D.cv_mean[c] = law.mean[c];
+            D.cv_inv[c] = law.inv[c];
+        }
         D.cv_kappa2 = kappa * kappa;
-        D.cv_k = c.k;
-        D.cv_zeta_inv = 1.0 / std::sqrt(2.0 * c.k);
-        D.cv_late_begin = (uint32_t)(c.epochs - c.late);
+        D.cv_k = law.k;
+        D.cv_zeta_inv = 1.0 / std::sqrt(2.0 * law.k);
     }
     for (uint32_t j = 0; j < p->d; ++j) {
         // with a dense L the per-asset scale is the marginal standard deviation |row j of L|
@@ -222,23 +234,103 @@ Moments moments(const double *f)
 // min over W of lambda sum sigma_j^2 w_j^2 - mu'w (KKT water-filling), diagonal Sigma with every
 // sigma_j > 0: w_j(nu) = max(0, (mu_j - nu) / (2 lambda sigma_j^2)) with nu >= 0 chosen so that
 // sum_j w_j <= 1 holds with complementary slackness. NaN when some sigma_j is zero.
-CvConstants cv_constants(uint64_t T, uint32_t M, uint32_t d, uint32_t N)
+namespace {
+
+double normal_cdf(double x) { return 0.5 * std::erfc(-x / std::sqrt(2.0)); }
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on P_n (three-term recurrence)
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
 {
-    CvConstants c;
-    c.epochs = (T + M - 1) / M;
-    c.late = (c.epochs + 9) / 10;
-    if (c.late < 1) c.late = 1;
-    double s = 0.0, late = 0.0;
-    for (uint64_t e = 0; e < c.epochs; ++e) {
-        const uint64_t t0 = e * M, t1 = std::min<uint64_t>(t0 + M, T);
-        const double w = 0.5 * ((double)t1 * (double)(t1 + 1) - (double)t0 * (double)(t0 + 1));
-        s += w * w;
-        if (e >= c.epochs - c.late) late += w;
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = pk;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            const double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = pk;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
     }
-    c.weight_norm = std::sqrt(s);
-    c.eta_corr = late / (c.weight_norm * std::sqrt((double)c.late * (double)d));
-    c.k = (double)c.epochs * (double)d * (double)(N - 1);
-    return c;
+}
+
+}  // namespace
+
+void cv_pick_probs(uint32_t d, const double *b, const double *s, double *p)
+{
+    // origin: every b_k - s_k Z_k >= 0; vertex a: b_a - s_a z < 0 and below every other value,
+    // integrated over z > b_a / s_a with 16-point Gauss-Legendre panels of width <= 1/8
+    static std::vector<double> gx, gw;
+    if (gx.empty()) gauss_legendre(16, gx, gw);
+    double p0 = 1.0;
+    for (uint32_t k = 0; k < d; ++k) p0 *= normal_cdf(b[k] / s[k]);
+    p[0] = p0;
+    const double inv_sqrt_2pi = 0.39894228040143267793994605993438;
+    for (uint32_t a = 0; a < d; ++a) {
+        const double lo = std::max(b[a] / s[a], -13.0), hi = 13.0;
+        double acc = 0.0;
+        if (lo < hi) {
+            const int panels = (int)std::ceil((hi - lo) * 8.0);
+            const double h = (hi - lo) / panels;
+            for (int q = 0; q < panels; ++q) {
+                const double c = lo + (q + 0.5) * h;
+                for (int i = 0; i < 16; ++i) {
+                    const double z = c + 0.5 * h * gx[i];
+                    double f = inv_sqrt_2pi * std::exp(-0.5 * z * z);
+                    for (uint32_t k = 0; k < d; ++k)
+                        if (k != a) f *= normal_cdf((b[k] - b[a] + s[a] * z) / s[k]);
+                    acc += 0.5 * h * gw[i] * f;
+                }
+            }
+        }
+        p[a + 1] = acc;
+    }
+}
+
+CvLaw cv_law(const sim_params *p, uint64_t T)
+{
+    CvLaw L;
+    const uint32_t d = p->d, M = p->resample_every;
+    std::vector<double> s(d);
+    for (uint32_t j = 0; j < d; ++j) s[j] = p->sigma[j] / std::sqrt((double)p->n_samples);
+    cv_pick_probs(d, p->cv_ref, s.data(), L.p);
+    // S2 = sum_t (t+1)^2; S4 = sum over epochs of (sum of (t+1)^2 over the epoch)^2
+    auto sq_sum = [](uint64_t n) { return (double)(n * (n + 1) * (2 * n + 1) / 6); };
+    L.S2 = sq_sum(T);
+    L.S4 = 0.0;
+    L.epochs = 0;
+    for (uint64_t t0 = 0; t0 < T; t0 += M, ++L.epochs) {
+        const uint64_t t1 = std::min<uint64_t>(t0 + M, T);
+        const double we = sq_sum(t1) - sq_sum(t0);
+        L.S4 += we * we;
+    }
+    double cum = 0.0;
+    for (uint32_t c = 0; c <= d; ++c) {
+        L.mean[c] = L.p[c] * L.S2;
+        L.inv[c] = 1.0 / std::sqrt(L.S4 * std::max(L.p[c] * (1.0 - L.p[c]), 1e-4));
+        cum += L.p[c];
+        L.cum[c] = cum;
+    }
+    L.cum[d] = 2.0;   // every uniform falls below the last bound
+    L.k = (double)L.epochs * (double)d * (double)(p->n_samples - 1);
+    return L;
 }
 
 int dense_asset_of(int p, int k) { return (k >> 2) * 8 + 4 * p + (k & 3); }

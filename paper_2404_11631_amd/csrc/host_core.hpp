@@ -19,15 +19,17 @@ constexpr uint64_t kMaxDenseT = 65535;
 int fail(char *err, int code, const char *fmt, ...);
 int validate(char *err, const sim_params *p, uint64_t R, uint64_t T);
 void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed);
-// Constants of the control-variate features' law for a run of T iterations, resampling every M.
-struct CvConstants {
-    uint64_t epochs;       // E = ceil(T / M)
-    uint64_t late;         // W = ceil(E / 10), at least 1
-    double weight_norm;    // sqrt(sum_e C_e^2), C_e = sum of (t+1) over epoch e
-    double eta_corr;       // Cov(xi_j, eta)
-    double k;              // E d (N-1), degrees of freedom of the pooled sum of squares
+// Law of the control-variate features of a run (diagonal Sigma, reference gradient p->cv_ref):
+// reference-decision probabilities p (0 origin, j+1 vertex e_j) and their running sums, the
+// weights S2 = sum_t (t+1)^2 and S4 = sum_e (epoch sum of (t+1)^2)^2, the standardization of the
+// counts, and the chi-square degrees of freedom k = E d (N-1).
+struct CvLaw {
+    double p[kMaxD + 1], cum[kMaxD + 1], mean[kMaxD + 1], inv[kMaxD + 1];
+    double S2, S4, k;
+    uint64_t epochs;
 };
-CvConstants cv_constants(uint64_t T, uint32_t M, uint32_t d, uint32_t N);
+void cv_pick_probs(uint32_t d, const double *b, const double *s, double *p);
+CvLaw cv_law(const sim_params *p, uint64_t T);
 
 // The two FP32 operands of the dense-L kernels, sqrt(2 ln 2) L (for g = L h) and its transpose
 // (for v = L'w), each [d/32][d/2][64] in the lane order of v_mfma_f32_32x32x2f32 (row 32 mt +

@@ -362,35 +362,53 @@ __global__ __launch_bounds__(256) void mlp_init_kernel(MlpDev m, uint64_t seed, 
     m.theta[i] = static_cast<float>(w);
 }
 
-// Draws k0 .. k0+n-1 from the exact joint law of the path features (stream domain 2): xi from
-// normals 0..d-1, eta = a sum(xi) + b eps with eps normal d, and zeta = (2 G - k) / sqrt(2 k) with
-// G ~ Gamma(k/2) by Marsaglia and Tsang (ACM TOMS 26(3), 2000; shapes below one through
-// G = G' V^(1/alpha), G' of shape alpha + 1). Try i uses Philox block 64 + i: its first pair gives
-// the normal (cosine branch), word 2 the acceptance uniform, word 3 V. FP64 throughout.
+// Draws k0 .. k0+n-1 from the exact joint law of the path features (stream domain 2 of the seed):
+// per epoch e a category from the 53-bit uniform ((a >> 5) 2^26 + (b >> 6) + 1/2) 2^-53 of words
+// (a, b) = (x0, x1) for even e, (x2, x3) for odd e of Philox block (e/2, 1, k, ...), weighted by the
+// epoch's sum of (t+1)^2; and q = 2 G, G ~ Gamma(k/2) by Marsaglia and Tsang (ACM TOMS 26(3), 2000;
+// shapes below one through G = G' V^(1/alpha), G' of shape alpha + 1), try i on Philox block
+// (64 + i, 0, k, ...): its first pair gives the normal (cosine branch), word 2 the acceptance
+// uniform, word 3 V. FP64 throughout. D bounds d (categories 0..d).
+template <int D>
 __global__ __launch_bounds__(256) void cv_aux_kernel(AuxLaw law, uint64_t k0, uint64_t n, float *x, uint64_t ldx,
                                                      uint32_t *failures)
 {
-    const uint64_t idx = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
+    constexpr int LEN = D + 1;                 // categories 0..D; entries beyond d hold 2 (never <= u)
+    constexpr int TOP = (LEN > 32) ? 64 : (LEN > 16) ? 32 : (LEN > 8) ? 16 : (LEN > 4) ? 8 : 4;
+    __shared__ double s_cum[LEN];
+    __shared__ uint64_t s_cnt[LEN * 256];      // [category][thread]: integer sums of (t+1)^2
+    const int tid = threadIdx.x;
+    const int d = law.d;
+    if (tid < LEN) s_cum[tid] = (tid <= d) ? law.cum[tid] : 2.0;
+#pragma unroll
+    for (int c = 0; c < LEN; ++c) s_cnt[c * 256 + tid] = 0;
+    __syncthreads();
+    const uint64_t idx = static_cast<uint64_t>(blockIdx.x) * 256 + tid;
     if (idx >= n) return;
     const uint32_t k = static_cast<uint32_t>(k0 + idx);
     const uint32_t dom = (2u << 24) | (law.instance & 0xFFFFFFu);
     const uint32_t s0 = static_cast<uint32_t>(law.seed), s1 = static_cast<uint32_t>(law.seed >> 32);
-    const int d = law.d;
-    double sum = 0.0, eps = 0.0;
-    for (int b = 0; 4 * b <= d; ++b) {
-        const Block4<double> q = normals_block<double>(static_cast<uint32_t>(b), 0u, k, dom, s0, s1);
+    const uint64_t T = law.T, M = law.M;
+
+    Words4 w{0u, 0u, 0u, 0u};
+    uint32_t e = 0;
+    for (uint64_t t0 = 0; t0 < T; t0 += M, ++e) {
+        if ((e & 1u) == 0) w = philox4x32_10(e >> 1, 1u, k, dom, s0, s1);
+        const uint32_t a = (e & 1u) ? w.x2 : w.x0, b = (e & 1u) ? w.x3 : w.x1;
+        const double u = (static_cast<double>(a >> 5) * 67108864.0 + static_cast<double>(b >> 6) + 0.5) *
+                         (1.0 / 9007199254740992.0);
+        // category = the number of cumulative bounds <= u (the smallest c with u < cum[c])
+        int c = 0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int jj = 4 * b + c;
-            if (jj < d) {
-                x[static_cast<uint64_t>(jj) * ldx + idx] = static_cast<float>(q.z[c]);
-                sum += q.z[c];
-            } else if (jj == d) {
-                eps = q.z[c];
-            }
-        }
+        for (int step = TOP; step >= 1; step >>= 1)
+            if (c + step <= LEN && s_cum[c + step - 1] <= u) c += step;
+        const uint64_t t1 = (t0 + M < T) ? t0 + M : T;
+        s_cnt[c * 256 + tid] += t1 * (t1 + 1) * (2 * t1 + 1) / 6 - t0 * (t0 + 1) * (2 * t0 + 1) / 6;
     }
-    x[static_cast<uint64_t>(d) * ldx + idx] = static_cast<float>(law.eta_a * sum + law.eta_b * eps);
+    for (int c = 0; c <= d; ++c) {
+        const uint64_t row = (c == 0) ? static_cast<uint64_t>(d) : static_cast<uint64_t>(c - 1);
+        x[row * ldx + idx] = static_cast<float>((static_cast<double>(s_cnt[c * 256 + tid]) - law.mean[c]) * law.inv[c]);
+    }
 
     const bool boost = law.alpha < 1.0;
     const double alpha = boost ? law.alpha + 1.0 : law.alpha;
@@ -399,15 +417,15 @@ __global__ __launch_bounds__(256) void cv_aux_kernel(AuxLaw law, uint64_t k0, ui
     double g = dd;
     bool ok = false;
     for (uint32_t i = 0; i < 64 && !ok; ++i) {
-        const Words4 w = philox4x32_10(64u + i, 0u, k, dom, s0, s1);
-        const double z = box_muller64(w.x0, w.x1).c;
-        const double u = static_cast<double>(uniform_open01(w.x2));
+        const Words4 v4 = philox4x32_10(64u + i, 0u, k, dom, s0, s1);
+        const double z = box_muller64(v4.x0, v4.x1).c;
+        const double uu = static_cast<double>(uniform_open01(v4.x2));
         const double bb = 1.0 + cc * z;
         if (bb > 0.0) {
             const double v = bb * bb * bb;
-            if (log(u) < 0.5 * z * z + dd - dd * v + dd * log(v)) {
+            if (log(uu) < 0.5 * z * z + dd - dd * v + dd * log(v)) {
                 g = dd * v;
-                if (boost) g *= pow(static_cast<double>(uniform_open01(w.x3)), 1.0 / law.alpha);
+                if (boost) g *= pow(static_cast<double>(uniform_open01(v4.x3)), 1.0 / law.alpha);
                 ok = true;
             }
         }
@@ -531,8 +549,12 @@ int launch_cv_aux(const AuxLaw &law, uint64_t k0, uint64_t n, float *x, uint64_t
                   hipStream_t st)
 {
     if (n == 0) return 0;
-    hipLaunchKernelGGL(cv_aux_kernel, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0, st, law, k0, n, x,
-                       ldx, failures);
+    const dim3 g(static_cast<uint32_t>((n + 255) / 256)), b(256);
+    if (law.d <= 4) hipLaunchKernelGGL(cv_aux_kernel<4>, g, b, 0, st, law, k0, n, x, ldx, failures);
+    else if (law.d <= 8) hipLaunchKernelGGL(cv_aux_kernel<8>, g, b, 0, st, law, k0, n, x, ldx, failures);
+    else if (law.d <= 16) hipLaunchKernelGGL(cv_aux_kernel<16>, g, b, 0, st, law, k0, n, x, ldx, failures);
+    else if (law.d <= 32) hipLaunchKernelGGL(cv_aux_kernel<32>, g, b, 0, st, law, k0, n, x, ldx, failures);
+    else return -5;
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

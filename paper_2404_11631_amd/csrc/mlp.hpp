@@ -35,13 +35,17 @@ struct AdamStep {
     float lr, beta1, beta2, eps, bc1, bc2;
 };
 
-// Law of the path features for the aux draws (stream domain 2 of `seed`, `instance`).
+// Law of the path features for the aux draws (stream domain 2 of `seed`, `instance`): reference
+// decisions i.i.d. over epochs with cumulative probabilities cum (origin first, last entry 2),
+// standardized by mean and inv; the chi-square summary with kdof degrees of freedom.
 struct AuxLaw {
     uint64_t seed;
     uint32_t instance;
     int d;
-    double eta_a, eta_b;   // eta = eta_a sum(xi) + eta_b eps
-    double kdof, alpha;    // zeta: chi-square(kdof), alpha = kdof / 2
+    uint64_t T;
+    uint32_t M, pad_;
+    double kdof, alpha;    // alpha = kdof / 2
+    double cum[65], mean[65], inv[65];
 };
 
 int launch_mlp_forward(const MlpDev &m, const float *x, uint64_t ldx, uint64_t n, float shift, float scale,

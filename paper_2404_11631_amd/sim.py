@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsim.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 MAX_D = 64
 MAX_CKPT = 8
 TAU_NONE = 0xFFFFFFFF
@@ -34,7 +34,7 @@ class SimParams(ctypes.Structure):
                 ("state_precision", ctypes.c_uint32), ("n_checkpoints", ctypes.c_uint32),
                 ("checkpoints", ctypes.c_uint64 * MAX_CKPT), ("gap_eps", ctypes.c_double),
                 ("flags", ctypes.c_uint32), ("instance_id", ctypes.c_uint32),
-                ("log_rep_begin", ctypes.c_uint64), ("log_rep_count", ctypes.c_uint64)]
+                ("log_rep_begin", ctypes.c_uint64), ("log_rep_count", ctypes.c_uint64), ("cv_ref", _dp)]
 
 
 class SimStats(ctypes.Structure):
@@ -73,7 +73,8 @@ class SimCvOpts(ctypes.Structure):
 
 
 class SimCvFitOut(ctypes.Structure):
-    _fields_ = [("n_train", ctypes.c_uint64), ("steps", ctypes.c_uint64), ("y_mean", ctypes.c_double),
+    _fields_ = [("n_train", ctypes.c_uint64), ("steps", ctypes.c_uint64), ("ref", ctypes.c_double * MAX_D),
+                ("y_mean", ctypes.c_double),
                 ("y_sd", ctypes.c_double), ("loss_first_epoch", ctypes.c_double),
                 ("loss_last_epoch", ctypes.c_double), ("beta", ctypes.c_double), ("rho2", ctypes.c_double),
                 ("pilot_var_y", ctypes.c_double), ("sim_ms", ctypes.c_double), ("train_ms", ctypes.c_double),
@@ -103,7 +104,8 @@ def mlp_param_count(F: int) -> int:
 EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_run_batch",
            "sim_plan_batch", "sim_batch_stats", "sim_batch_paths", "sim_stats", "sim_paths", "sim_copy_to_host",
            "sim_strerror", "sim_last_error", "sim_destroy", "sim_cv_fit", "sim_run_cv", "sim_cv_paths",
-           "sim_mlp_set_params", "sim_mlp_get_params", "sim_mlp_forward", "sim_mlp_grad", "sim_cv_aux_draws")
+           "sim_mlp_set_params", "sim_mlp_get_params", "sim_mlp_forward", "sim_mlp_grad", "sim_cv_aux_draws",
+           "sim_cv_law")
 
 _lib = None
 
@@ -152,6 +154,7 @@ def load():
         L.sim_mlp_grad.argtypes = [vp, fp, fp, u64, fp, ctypes.POINTER(ctypes.c_double)]
         L.sim_cv_aux_draws.argtypes = [vp, ctypes.POINTER(SimParams), u64, u64, u64, u64, fp,
                                        ctypes.POINTER(ctypes.c_uint64)]
+        L.sim_cv_law.argtypes = [ctypes.POINTER(SimParams), u64, _dp, _dp, _dp, ctypes.c_char_p, ctypes.c_size_t]
         _lib = L
     return _lib
 
@@ -180,6 +183,7 @@ class Problem:
     keep_paths: bool = False
     log_reps: tuple | None = None      # (begin, count) of replications whose decisions are logged
     cv_features: bool = False          # write each path's d+2 control-variate features
+    cv_ref: np.ndarray | None = None   # the features' reference gradient b
     instance_id: int = 0
 
 
@@ -189,6 +193,18 @@ def validate(p: Problem, R: int, T: int):
     buf = ctypes.create_string_buffer(512)
     rc = load().sim_validate(ctypes.byref(sp), R, T, buf, 512)
     return rc, buf.value.decode()
+
+
+def cv_law(p: Problem, T: int):
+    """(probs [d+1], S2, S4) of the features' law, without a device."""
+    sp, keep = Sim.params(p)
+    probs = np.zeros(len(p.mu) + 1)
+    s2, s4 = ctypes.c_double(), ctypes.c_double()
+    buf = ctypes.create_string_buffer(512)
+    rc = load().sim_cv_law(ctypes.byref(sp), T, probs.ctypes.data_as(_dp), ctypes.byref(s2), ctypes.byref(s4), buf, 512)
+    if rc:
+        raise SimError(rc, buf.value.decode())
+    return probs, s2.value, s4.value
 
 
 def _batch_args(problems, R, T, heavy_factor=0.0, lanes_per_rep=None, keep_paths=False):
@@ -290,6 +306,10 @@ class Sim:
         sp.instance_id = p.instance_id
         if p.log_reps:
             sp.log_rep_begin, sp.log_rep_count = int(p.log_reps[0]), int(p.log_reps[1])
+        if p.cv_ref is not None:
+            b = np.ascontiguousarray(p.cv_ref, dtype=np.float64)
+            keep.append(b)
+            sp.cv_ref = b.ctypes.data_as(_dp)
         return sp, keep
 
     def run(self, p: Problem, R: int, T: int, seed: int):

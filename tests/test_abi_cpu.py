@@ -1,6 +1,7 @@
 """The C-ABI library without a GPU: it loads, exports every symbol include/sim.h declares, the
 ctypes layouts match the header, and host-side validation rejects what the header says it does."""
 import ctypes
+import math
 import os
 import re
 import subprocess
@@ -41,13 +42,11 @@ def test_exports_every_declared_symbol(lib):
 
 def test_struct_layout_matches_header():
     """sizeof/offsetof from a C compile of the header equal the ctypes mirrors."""
-    fields = {
-        "sim_params": [f[0] for f in sim.SimParams._fields_],
-        "sim_stats_out": [f[0] for f in sim.SimStats._fields_],
-        "sim_path_view": [f[0] for f in sim.SimPathView._fields_],
-    }
     mirrors = {"sim_params": sim.SimParams, "sim_stats_out": sim.SimStats,
-               "sim_path_view": sim.SimPathView}
+               "sim_path_view": sim.SimPathView, "sim_batch_config": sim.SimBatchConfig,
+               "sim_cv_opts": sim.SimCvOpts, "sim_cv_fit_out": sim.SimCvFitOut,
+               "sim_cv_stats_out": sim.SimCvStats, "sim_cv_view": sim.SimCvView}
+    fields = {name: [f[0] for f in cls._fields_] for name, cls in mirrors.items()}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for st, fs in fields.items():
         lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
@@ -144,3 +143,34 @@ def test_create_without_gpu_fails_cleanly(lib):
     h = ctypes.c_void_p()
     assert lib.sim_create(0, None, ctypes.byref(h)) == -3
     assert not h.value
+
+
+@pytest.mark.parametrize("d,N,M,T", [(10, 10, 1, 10_000), (1, 2, 1, 7), (5, 4, 3, 100), (32, 6, 1, 500)])
+def test_cv_law_matches_oracle(lib, d, N, M, T):
+    """The library's reference-decision probabilities (Gauss-Legendre) against the oracle's
+    (Simpson): two independent quadratures of the same integrals."""
+    import oracle
+    g = np.random.default_rng(d)
+    mu = g.uniform(0.1, 0.9, d)
+    sigma = g.uniform(0.1, 0.9, d)
+    b = sigma ** 2 * np.full(d, 0.8 / d) - mu
+    p = sim.Problem(mu=mu, sigma=sigma, N=N, M=M, cv_ref=b)
+    probs, S2, S4 = sim.cv_law(p, T)
+    ref, tot = oracle.cv_pick_probs(b, sigma / np.sqrt(N))
+    assert abs(probs.sum() - 1) < 1e-12 and abs(tot - 1) < 1e-11
+    assert np.max(np.abs(probs - ref)) < 1e-12
+    oS2, oS4 = oracle.cv_weights(T, M)
+    assert S2 == oS2 and math.isclose(S4, oS4, rel_tol=1e-13)
+
+
+def test_cv_feature_validation(lib):
+    mu, sigma = workloads.diag_instance(0, 0, 4)
+    b = sigma ** 2 * 0.2 - mu
+    assert sim.validate(sim.Problem(mu=mu, sigma=sigma, N=4, cv_features=True, cv_ref=b), 10, 100)[0] == 0
+    assert sim.validate(sim.Problem(mu=mu, sigma=sigma, N=4, cv_features=True), 10, 100)[0] == -1
+    z = sigma.copy()
+    z[1] = 0.0
+    assert sim.validate(sim.Problem(mu=mu, sigma=z, N=4, cv_features=True, cv_ref=b), 10, 100)[0] == -5
+    assert sim.validate(sim.Problem(mu=mu, sigma=sigma, N=4, cv_features=True, cv_ref=b,
+                                    precision=sim.FP64), 10, 100)[0] == -5
+    assert sim.validate(sim.Problem(mu=mu, sigma=sigma, N=4, cv_features=True, cv_ref=b), 10, 100_000)[0] == -5

@@ -1,8 +1,11 @@
 """Control-variate pieces on the device vs the CPU oracle through the C ABI (needs an MI355X).
 
-Features: each path's d+2 features against the oracle's (same noise stream, replayed decisions)
-to 5e-5 absolute -- binary32 normals and per-epoch binary32 sums against FP64 -- and, at sizes
-the oracle cannot follow, their exact law (KS tests and correlations).
+Features: each path's d+2 features against the oracle's (same noise stream, replayed decisions).
+The reference decisions are taken from binary32 sample means on the device and FP64 ones in the
+oracle, so an epoch whose reference margin is below 1e-4 may fall in another category; the
+tolerance is that weight (the oracle reports it) times the standardization, plus 5e-5 for the
+binary32 chi-square summary and storage. At sizes the oracle cannot follow: the exact moments of
+the features' law.
 """
 import math
 import sys
@@ -32,6 +35,11 @@ def ctx():
     s.close()
 
 
+def _ref(mu, sigma, scale=0.8):
+    d = mu.shape[0]
+    return sigma ** 2 * np.full(d, scale / d) - mu
+
+
 @pytest.mark.parametrize("case", [
     dict(d=10, N=10, M=1, T=200, R=300, noise=sim.NOISE_GAUSS),
     dict(d=3, N=4, M=3, T=100, R=200, noise=sim.NOISE_GAUSS),
@@ -41,22 +49,28 @@ def ctx():
 def test_features_match_oracle(ctx, case):
     d, R, T = case["d"], case["R"], case["T"]
     mu, sigma = workloads.diag_instance(9, d, d)
+    b = _ref(mu, sigma)
     p = sim.Problem(mu=mu, sigma=sigma, N=case["N"], M=case["M"], noise=case["noise"], nu=4,
                     checkpoints=(T,), gap_eps=0.05, instance_id=30 + d, keep_paths=True,
-                    log_reps=(0, R), cv_features=True)
+                    log_reps=(0, R), cv_features=True, cv_ref=b)
     say(f"[cv] features d={d} N={case['N']} M={case['M']} noise={case['noise']} R={R} T={T}")
     ctx.run(p, R, T, 77)
     g = ctx.paths()
     assert g["x"].shape == (d + 2, R)
     P = parity.oracle_problem(p, 77)
-    err = 0.0
+    law = oracle.CvLaw(P, T)
+    inv = 1.0 / np.sqrt(law.S4 * np.maximum(law.probs * (1 - law.probs), 1e-4))
+    err, amb = 0.0, 0
     for r in range(R):
         o = parity.check_rep(P, g, r, T, oracle.U32, decisions=g["decisions"][:, r])
-        ref = np.array([o.feat[j] for j in range(d + 2)])
-        e = np.max(np.abs(g["x"][:, r].astype(np.float64) - ref))
-        err = max(err, e)
-        assert e <= FEAT_ATOL, f"rep {r}: feature error {e}"
-    say(f"[cv] max feature error {err:.2e}")
+        ref = law.path_features(o)
+        e = np.abs(g["x"][:, r].astype(np.float64) - ref)
+        tol = FEAT_ATOL + 1e-6 * np.abs(ref)
+        tol[: d + 1] += o.cv_amb * inv.max()
+        amb += o.cv_amb > 0
+        err = max(err, e.max())
+        assert np.all(e <= tol), f"rep {r}: feature errors {e}"
+    say(f"[cv] max feature error {err:.2e}; replications with a near-tie reference decision: {amb}")
 
 
 def test_features_do_not_change_the_paths(ctx):
@@ -65,7 +79,7 @@ def test_features_do_not_change_the_paths(ctx):
     base = dict(mu=mu, sigma=sigma, N=10, checkpoints=(100, T), keep_paths=True)
     ctx.run(sim.Problem(**base), R, T, 5)
     a = ctx.paths()
-    ctx.run(sim.Problem(**base, cv_features=True), R, T, 5)
+    ctx.run(sim.Problem(**base, cv_features=True, cv_ref=_ref(mu, sigma)), R, T, 5)
     b = ctx.paths()
     assert np.array_equal(a["y"], b["y"]) and np.array_equal(a["wsum"], b["wsum"])
     assert "x" not in a and "x" in b
@@ -73,22 +87,24 @@ def test_features_do_not_change_the_paths(ctx):
 
 def test_feature_law_at_scale(ctx):
     """The control-variate workload's shape (d = 10, N = 10) at R = 2e5, T = 1000: the device's
-    features follow their exact law."""
+    features have their law's exact means and variances, and the chi-square summary its law."""
     d, R, T = 10, 200_000, 1000
-    mu, sigma = workloads.diag_instance(100, 0, d)
-    p = sim.Problem(mu=mu, sigma=sigma, N=10, checkpoints=(T,), cv_features=True)
+    mu, sigma = workloads.diag_instance(0, 0, d)
+    b = _ref(mu, sigma)
+    p = sim.Problem(mu=mu, sigma=sigma, N=10, checkpoints=(T,), cv_features=True, cv_ref=b)
     ctx.run(p, R, T, 100)
     X = ctx.paths()["x"].astype(np.float64)
+    probs, S2, S4 = sim.cv_law(p, T)
+    cat = np.concatenate([probs[1:], probs[:1]])       # feature order: vertices, then the origin
+    v = cat * (1 - cat) / np.maximum(cat * (1 - cat), 1e-4)
     for j in range(d + 1):
-        assert ss.kstest(X[j], "norm").pvalue > 1e-4, f"feature {j}"
+        if v[j] > 0:
+            assert abs(X[j].mean()) < 5 * math.sqrt(v[j] / R), f"feature {j} mean"
+        if 0.05 < cat[j] < 0.95:
+            assert abs(X[j].var() / v[j] - 1) < 5 * math.sqrt(2 / R) + 0.01, f"feature {j} variance"
     k = T * d * 9
     assert ss.kstest(X[d + 1] * math.sqrt(2 * k) + k, ss.chi2(k).cdf).pvalue > 1e-4
-    a = oracle.cv_eta_corr(T, 1, d)
-    se = 5.0 / math.sqrt(R)
-    C = np.corrcoef(X)
-    for j in range(d):
-        assert abs(C[j, d] - a) < se and abs(C[j, d + 1]) < se
-    say(f"[cv] law ok, corr(xi, eta) {C[0, d]:.4f} vs {a:.4f}")
+    say(f"[cv] law ok at R={R}: probabilities {np.round(probs, 3)}")
 
 
 # ---- surrogate primitives ------------------------------------------------------------------
@@ -153,16 +169,18 @@ def test_mlp_grad_matches_oracle(ctx, F, n):
         assert rel <= 1e-3, name
 
 
-@pytest.mark.parametrize("d,N,M,T", [(10, 10, 1, 10_000), (1, 2, 1, 1), (3, 5, 2, 41), (64, 100, 1, 1000)])
-def test_aux_draws_match_oracle(ctx, d, N, M, T):
+@pytest.mark.parametrize("d,N,M,T,n", [(10, 10, 1, 10_000, 300), (1, 2, 1, 1, 2000), (3, 5, 2, 41, 2000),
+                                       (32, 100, 1, 1000, 300)])
+def test_aux_draws_match_oracle(ctx, d, N, M, T, n):
     mu, sigma = workloads.diag_instance(4, d, d)
-    p = sim.Problem(mu=mu, sigma=sigma, N=N, M=M, instance_id=5)
-    x, nf = ctx.cv_aux_draws(p, T, 123, 1000, 2000)
-    P = oracle.OracleProblem(mu, sigma, N=N, M=M, seed=123, instance=5)
-    ref, tries = oracle.cv_aux(P, T, 1000, 2000)
+    b = _ref(mu, sigma)
+    p = sim.Problem(mu=mu, sigma=sigma, N=N, M=M, instance_id=5, cv_ref=b)
+    x, nf = ctx.cv_aux_draws(p, T, 123, 1000, n)
+    P = oracle.OracleProblem(mu, sigma, N=N, M=M, seed=123, instance=5, cv_ref=b)
+    ref, counts, tries = oracle.CvLaw(P, T).aux(1000, n)
     assert nf == 0 and np.all(tries >= 1)
     err = np.abs(x.T.astype(np.float64) - ref)
-    say(f"[cv] aux d={d} k={(-(-T // M)) * d * (N - 1)}: max err {err.max():.2e}")
+    say(f"[cv] aux d={d} T={T}: max err {err.max():.2e}")
     assert np.all(err <= 2e-6 + 1e-6 * np.abs(ref))
 
 
