@@ -56,7 +56,7 @@ class PathOut(ctypes.Structure):
                 ("n_ambiguous", ctypes.c_uint64), ("n_replayed", ctypes.c_uint64),
                 ("n_mismatch", ctypes.c_uint64), ("first_mismatch", ctypes.c_int64),
                 ("identity_err", ctypes.c_double), ("min_margin", ctypes.c_double),
-                ("cv_count", ctypes.c_double * (MAX_D + 1)), ("cv_q", ctypes.c_double),
+                ("cv_count", ctypes.c_double * (MAX_D + 1)), ("cv_count1", ctypes.c_double * (MAX_D + 1)),
                 ("cv_amb", ctypes.c_double)]
 
 
@@ -109,11 +109,12 @@ def lib():
         u64 = ctypes.c_uint64
         L.or_cv_pick_probs.argtypes = [ctypes.c_int, dp, dp, dp]
         L.or_cv_pick_probs.restype = ctypes.c_double
-        L.or_cv_weights.argtypes = [u64, ctypes.c_int, dp, dp]
-        L.or_cv_features.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp,
-                                     ctypes.c_double, dp]
+        L.or_cv_weights.argtypes = [u64, ctypes.c_int, dp]
+        L.or_cv_top.argtypes = [ctypes.c_int, dp]
+        L.or_cv_top.restype = ctypes.c_int
+        L.or_cv_features.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp]
         L.or_cv_aux.argtypes = [ctypes.POINTER(Problem), u64, dp, u64, dp, dp]
-        L.or_cv_aux.restype = ctypes.c_int
+        L.or_cv_aux.restype = None
         L.or_bf16.argtypes = [ctypes.c_double]
         L.or_bf16.restype = ctypes.c_double
         L.or_mlp_param_count.argtypes = [ctypes.c_int]
@@ -245,9 +246,10 @@ def cv_pick_probs(b, s):
 
 
 def cv_weights(T: int, M: int):
-    s2, s4 = ctypes.c_double(), ctypes.c_double()
-    lib().or_cv_weights(T, M, ctypes.byref(s2), ctypes.byref(s4))
-    return s2.value, s4.value
+    """(S2, S4, S1, S11, S12): sums over epochs of W2_e, W2_e^2, W1_e, W1_e^2, W1_e W2_e."""
+    w = np.zeros(5)
+    lib().or_cv_weights(T, M, _dptr(w))
+    return tuple(w)
 
 
 class CvLaw:
@@ -259,32 +261,31 @@ class CvLaw:
         sig = np.diag(P.chol).copy()
         self.P, self.T, self.d = P, T, P.d
         self.probs, self.total = cv_pick_probs(P.cv_ref, sig / np.sqrt(P.N))
-        self.S2, self.S4 = cv_weights(T, P.p.M)
-        E = -(-T // P.p.M)
-        self.kdof = float(E * P.d * (P.N - 1))
+        self.w = np.array(cv_weights(T, P.p.M))
+        self.S2, self.S4, self.S1, self.S11, self.S12 = self.w
+        self.top = lib().or_cv_top(self.d, _dptr(self.probs))
 
-    def standardize(self, count, q):
+    def standardize(self, count, count1):
         x = np.zeros(self.d + 2)
-        c = _arr(count)
-        lib().or_cv_features(self.d, _dptr(self.probs), self.S2, self.S4, self.kdof, _dptr(c), float(q), _dptr(x))
+        c, c1 = _arr(count), _arr(count1)
+        lib().or_cv_features(self.d, _dptr(self.probs), _dptr(self.w), _dptr(c), _dptr(c1), _dptr(x))
         return x
 
     def path_features(self, o):
-        return self.standardize([o.cv_count[c] for c in range(self.d + 1)], o.cv_q)
+        return self.standardize([o.cv_count[c] for c in range(self.d + 1)],
+                                [o.cv_count1[c] for c in range(self.d + 1)])
 
     def aux(self, k0: int, n: int):
-        """Draws k0 .. k0+n-1 from the exact law: (standardized (n, d+2), raw counts (n, d+1), tries)."""
+        """Draws k0 .. k0+n-1 from the exact law: (standardized (n, d+2), counts (n, d+1), counts1 (n, d+1))."""
         X = np.zeros((n, self.d + 2))
         C = np.zeros((n, self.d + 1))
-        tries = np.zeros(n, dtype=np.int64)
-        cnt = np.zeros(self.d + 1)
-        q = ctypes.c_double()
+        C1 = np.zeros((n, self.d + 1))
+        cnt, cnt1 = np.zeros(self.d + 1), np.zeros(self.d + 1)
         for i in range(n):
-            tries[i] = lib().or_cv_aux(ctypes.byref(self.P.p), self.T, _dptr(self.probs), k0 + i, _dptr(cnt),
-                                       ctypes.byref(q))
-            C[i] = cnt
-            X[i] = self.standardize(cnt, q.value)
-        return X, C, tries
+            lib().or_cv_aux(ctypes.byref(self.P.p), self.T, _dptr(self.probs), k0 + i, _dptr(cnt), _dptr(cnt1))
+            C[i], C1[i] = cnt, cnt1
+            X[i] = self.standardize(cnt, cnt1)
+        return X, C, C1
 
 
 def bf16(v: float) -> float:

@@ -14,7 +14,8 @@
  *         dimensional integrals (or_cv_pick_probs);
  *   q_e = sum_j sum_i (z_eij - zbar_ej)^2 ~ chi-square(d (N-1)), independent of zbar_e.
  * The summaries are count_c = sum_t (t+1)^2 [J_e(t) = c] (the late iterations weigh most, as in
- * w_T) and q = sum_e q_e ~ chi-square(k), k = E d (N-1), independent of the counts.
+ * w_T) and count1_c = sum_t (t+1) [J_e(t) = c]; their joint law is that of weighted sums of i.i.d.
+ * categorical indicators.
  */
 #include "oracle.h"
 
@@ -59,63 +60,44 @@ double or_cv_pick_probs(int d, const double *b, const double *s, double *p)
     return total;
 }
 
-void or_cv_weights(uint64_t T, int M, double *S2, double *S4)
+void or_cv_weights(uint64_t T, int M, double *w)
 {
-    double s2 = 0.0, s4 = 0.0;
+    for (int i = 0; i < 5; ++i) w[i] = 0.0;
     for (uint64_t t0 = 0; t0 < T; t0 += (uint64_t)M) {
-        double we = 0.0;
-        for (uint64_t t = t0; t < t0 + (uint64_t)M && t < T; ++t) we += (double)(t + 1) * (double)(t + 1);
-        s2 += we;
-        s4 += we * we;
-    }
-    *S2 = s2;
-    *S4 = s4;
-}
-
-void or_cv_features(int d, const double *probs, double S2, double S4, double kdof, const double *count,
-                    double q, double *x)
-{
-    for (int c = 0; c <= d; ++c) {
-        double v = probs[c] * (1.0 - probs[c]);
-        if (v < 1e-4) v = 1e-4;
-        const double f = (count[c] - probs[c] * S2) / sqrt(S4 * v);
-        x[c == 0 ? d : c - 1] = f;
-    }
-    x[d + 1] = (q - kdof) / sqrt(2.0 * kdof);
-}
-
-/* Gamma(alpha, 1) by Marsaglia and Tsang, "A simple method for generating gamma variables",
- * ACM TOMS 26(3), 2000: for shape a >= 1, d = a - 1/3, c = 1/sqrt(9 d); with x ~ N(0,1) and
- * v = (1 + c x)^3 > 0, accept d v when log U < x^2/2 + d - d v + d log v. A shape alpha < 1 runs
- * with a = alpha + 1 and scales the result by V^(1/alpha), V uniform (same paper, Section 6).
- * Try i uses Philox block 64 + i of the draw's stream (epoch word 0): its first pair gives x by
- * Box-Muller (cosine branch), word 2 gives U and word 3 gives V. Returns the number of tries used,
- * or -1 if none of 64 accepted (then *g = d). */
-static int gamma_mt(double alpha, uint64_t seed, uint32_t instance, uint64_t k, double *g)
-{
-    const int boost = alpha < 1.0;
-    if (boost) alpha += 1.0;
-    const double dd = alpha - 1.0 / 3.0;
-    const double c = 1.0 / sqrt(9.0 * dd);
-    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    for (int i = 0; i < 64; ++i) {
-        uint32_t ctr[4] = {64u + (uint32_t)i, 0u, (uint32_t)k, (OR_DOMAIN_CV_AUX << 24) | (instance & 0xFFFFFFu)};
-        uint32_t w[4];
-        or_philox4x32_10(ctr, key, w);
-        double x;
-        or_normals(seed, OR_DOMAIN_CV_AUX, instance, k, 0, 4u * (64u + (uint32_t)i), 1, &x);
-        const double u = or_uniform(w[2]);
-        const double b = 1.0 + c * x;
-        if (b <= 0.0) continue;
-        const double v = b * b * b;
-        if (log(u) < 0.5 * x * x + dd - dd * v + dd * log(v)) {
-            *g = dd * v;
-            if (boost) *g *= pow(or_uniform(w[3]), 1.0 / (alpha - 1.0));
-            return i + 1;
+        double w2 = 0.0, w1 = 0.0;
+        for (uint64_t t = t0; t < t0 + (uint64_t)M && t < T; ++t) {
+            w2 += (double)(t + 1) * (double)(t + 1);
+            w1 += (double)(t + 1);
         }
+        w[0] += w2;
+        w[1] += w2 * w2;
+        w[2] += w1;
+        w[3] += w1 * w1;
+        w[4] += w1 * w2;
     }
-    *g = dd;
-    return -1;
+}
+
+int or_cv_top(int d, const double *probs)
+{
+    int top = 0;
+    for (int c = 1; c <= d; ++c)
+        if (probs[c] > probs[top]) top = c;
+    return top;
+}
+
+static double standardized(double count, double p, double mean_w, double var_w)
+{
+    double v = p * (1.0 - p);
+    if (v < 1e-4) v = 1e-4;
+    return (count - p * mean_w) / sqrt(var_w * v);
+}
+
+void or_cv_features(int d, const double *probs, const double *w, const double *count, const double *count1,
+                    double *x)
+{
+    for (int c = 0; c <= d; ++c) x[c == 0 ? d : c - 1] = standardized(count[c], probs[c], w[0], w[1]);
+    const int top = or_cv_top(d, probs);
+    x[d + 1] = standardized(count1[top], probs[top], w[2], w[3]);
 }
 
 /* A uniform in (0,1) with 53 random bits from two words: ((a >> 5) 2^26 + (b >> 6) + 1/2) 2^-53. */
@@ -124,11 +106,11 @@ static double uniform53(uint32_t a, uint32_t b)
     return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6) + 0.5) * (1.0 / 9007199254740992.0);
 }
 
-int or_cv_aux(const or_problem *p, uint64_t T, const double *probs, uint64_t k, double *count, double *q)
+void or_cv_aux(const or_problem *p, uint64_t T, const double *probs, uint64_t k, double *count, double *count1)
 {
     const int d = p->d, M = p->M;
     uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
-    for (int c = 0; c <= d; ++c) count[c] = 0.0;
+    for (int c = 0; c <= d; ++c) count[c] = count1[c] = 0.0;
     uint64_t e = 0;
     for (uint64_t t0 = 0; t0 < T; t0 += (uint64_t)M, ++e) {
         /* epoch e: words (2 (e mod 2), 2 (e mod 2) + 1) of block e / 2, epoch word 1 */
@@ -145,15 +127,11 @@ int or_cv_aux(const or_problem *p, uint64_t T, const double *probs, uint64_t k, 
                 break;
             }
         }
-        double we = 0.0;
-        for (uint64_t t = t0; t < t0 + (uint64_t)M && t < T; ++t) we += (double)(t + 1) * (double)(t + 1);
-        count[cat] += we;
+        for (uint64_t t = t0; t < t0 + (uint64_t)M && t < T; ++t) {
+            count[cat] += (double)(t + 1) * (double)(t + 1);
+            count1[cat] += (double)(t + 1);
+        }
     }
-    const double kdof = (double)e * (double)d * (double)(p->N - 1);
-    double g = 0.0;
-    const int tries = gamma_mt(0.5 * kdof, p->seed, p->instance, k, &g);
-    *q = 2.0 * g;
-    return tries;
 }
 
 /* ---------------------------------------------------------------------------------------------

@@ -164,26 +164,19 @@ double or_objective(const or_problem *p, const double *w)
     return p->lambda * quad - lin;
 }
 
-/* Per-epoch summaries for the control-variate features (see cv.c): the reference decision -- the
- * vertex the linear subproblem picks for the fixed gradient cv_ref perturbed by this epoch's
- * sample-mean noise, cv_ref - L zbar (lowest index among equal minima, the origin when the
- * minimum is >= 0) -- with the gap between its value and the next best, and the pooled
- * within-asset sum of squares sum_j sum_i (z_ij - zbar_j)^2. */
-static int cv_epoch_summaries(const or_problem *p, const double *z, double *zbar, double *vals,
-                              double *q, double *margin)
+/* The epoch's reference decision for the control-variate features (see cv.c): the vertex the
+ * linear subproblem picks for the fixed gradient cv_ref perturbed by this epoch's sample-mean noise,
+ * cv_ref - L zbar (lowest index among equal minima, the origin when the minimum is >= 0), and the
+ * gap between its value and the next best. */
+static int cv_reference_decision(const or_problem *p, const double *z, double *zbar, double *vals,
+                                 double *margin)
 {
     const int d = p->d, N = p->N;
-    double qs = 0.0;
     for (int j = 0; j < d; ++j) {
         double s = 0.0;
         for (int i = 0; i < N; ++i) s += z[(size_t)i * d + j];
         zbar[j] = s / (double)N;
-        for (int i = 0; i < N; ++i) {
-            const double e = z[(size_t)i * d + j] - zbar[j];
-            qs += e * e;
-        }
     }
-    *q = qs;
     vals[0] = 0.0;                                   /* the origin */
     for (int j = 0; j < d; ++j) {
         double lz = 0.0;
@@ -241,15 +234,12 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
         const uint64_t epoch = t / (uint64_t)M;        /* k = t div M, m = t mod M */
         if (t % (uint64_t)M == 0) {                    /* resample */
             draw_returns(p, rep, epoch, Rmat, noise, zraw);
-            if (p->cv_ref) {
-                double q_e = 0.0;
-                ref_pick = cv_epoch_summaries(p, zraw, zbar, rvals, &q_e, &ref_margin);
-                out->cv_q += q_e;
-            }
+            if (p->cv_ref) ref_pick = cv_reference_decision(p, zraw, zbar, rvals, &ref_margin);
         }
-        if (p->cv_ref) {                               /* weight (t+1)^2 on this epoch's pick */
+        if (p->cv_ref) {                       /* weights (t+1)^2 and (t+1) on this epoch's pick */
             const double wt = (double)(t + 1) * (double)(t + 1);
             out->cv_count[ref_pick] += wt;
+            out->cv_count1[ref_pick] += (double)(t + 1);
             if (ref_margin < OR_CV_AMBIGUOUS) out->cv_amb += wt;
         }
 

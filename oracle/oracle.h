@@ -70,12 +70,11 @@ typedef struct {
     int64_t first_mismatch;         /* step of the first mismatch, or -1 */
     double identity_err;            /* max_j |w_T - 2 wsum/(T(T+1))| (recurrence vs closed form) */
     double min_margin;              /* smallest LMO margin seen along the path */
-    /* control-variate raw summaries (cv_ref set): per category c (0 origin, j+1 vertex e_j) the sum
-     * of (t+1)^2 over iterations whose epoch's reference decision is c; the pooled within-asset
-     * sum of squares over epochs; the (t+1)^2 weight of iterations whose reference margin is below
-     * OR_CV_AMBIGUOUS */
+    /* control-variate raw summaries (cv_ref set): per category c (0 origin, j+1 vertex e_j) the sums
+     * of (t+1)^2 and of (t+1) over iterations whose epoch's reference decision is c; the (t+1)^2
+     * weight of iterations whose reference margin is below OR_CV_AMBIGUOUS */
     double cv_count[OR_MAX_D + 1];
-    double cv_q;
+    double cv_count1[OR_MAX_D + 1];
     double cv_amb;
 } or_path_out;
 
@@ -143,16 +142,20 @@ typedef struct {
 /* Probabilities of the reference decision, p[0] the origin and p[j+1] vertex e_j, for a gradient
  * b - s .* Z with Z ~ N(0, I_d) (s > 0: the standard deviations of the sample-mean noise, sigma / sqrt(N)). */
 double or_cv_pick_probs(int d, const double *b, const double *s, double *p);
-/* S2 = sum_t (t+1)^2 and S4 = sum_e (sum of (t+1)^2 over epoch e)^2 for T iterations, epochs of M. */
-void or_cv_weights(uint64_t T, int M, double *S2, double *S4);
-/* Standardized features x[0..d+1] from raw summaries: x_j (j < d) for category j+1, x_d for the
- * origin, (count_c - p_c S2) / sqrt(S4 max(p_c (1 - p_c), 1e-4)); x_{d+1} = (q - k) / sqrt(2 k). */
-void or_cv_features(int d, const double *probs, double S2, double S4, double kdof, const double *count,
-                    double q, double *x);
-/* Draw k (stream domain 2) from the exact joint law of the raw summaries: per epoch a category
- * from probs (one 53-bit uniform), and q ~ chi-square(E d (N-1)). Returns the gamma sampler's
- * tries, or -1 if it did not accept within 64. */
-int or_cv_aux(const or_problem *p, uint64_t T, const double *probs, uint64_t k, double *count, double *q);
+/* Weights of T iterations in epochs of M: W2_e, W1_e = sums of (t+1)^2 and (t+1) over epoch e;
+ * w[0] = S2 = sum_e W2_e, w[1] = S4 = sum_e W2_e^2, w[2] = S1 = sum_e W1_e, w[3] = S11 = sum_e W1_e^2,
+ * w[4] = S12 = sum_e W1_e W2_e. */
+void or_cv_weights(uint64_t T, int M, double *w);
+/* The most probable category (lowest index among equal probabilities). */
+int or_cv_top(int d, const double *probs);
+/* Standardized features x[0..d+1] from raw summaries: x_j (j < d) for category j+1 and x_d for the
+ * origin, (count_c - p_c S2) / sqrt(S4 max(p_c (1 - p_c), 1e-4)); x_{d+1} for the most probable
+ * category c*, (count1_c* - p_c* S1) / sqrt(S11 max(p_c* (1 - p_c*), 1e-4)). */
+void or_cv_features(int d, const double *probs, const double *w, const double *count, const double *count1,
+                    double *x);
+/* Draw k (stream domain 2) from the exact joint law of the raw summaries: per epoch a category from
+ * probs (one 53-bit uniform). */
+void or_cv_aux(const or_problem *p, uint64_t T, const double *probs, uint64_t k, double *count, double *count1);
 
 /* bfloat16 rounding (to nearest even, through binary32). */
 double or_bf16(double v);

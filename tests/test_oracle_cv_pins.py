@@ -3,10 +3,10 @@
 * Reference-decision probabilities: they sum to one, reduce to normal CDFs for one asset and to
   equal shares for a symmetric instance, and match brute-force Monte Carlo of the argmin.
 * Path features: the raw summaries' exact moments (E count_c = p_c S2, Cov = S4 (p_c [c = c'] -
-  p_c p_c')), the chi-square law of the pooled sum of squares and its independence, for M = 1,
+  p_c p_c'), the same with (t+1) weights, and the correlation of the two weightings), for M = 1,
   M = 3 with a short last epoch, and t noise; the T = 1 case against the argmin of the raw normals.
-* Aux draws: category frequencies against p (chi-square goodness of fit), the same moments, the
-  gamma sampler's chi-square law at shapes 1/2, 1, 3 and 4.5e5, and agreement with path features.
+* Aux draws: category frequencies against p (chi-square goodness of fit), the same moments, and
+  agreement with path features.
 * Surrogate gradient: central finite differences of the unrounded network, and torch's autograd
   (float64) on an independent formulation of the rounded network.
 * bfloat16 rounding: torch's float32 -> bfloat16 conversion, ties included.
@@ -77,32 +77,34 @@ def _paths(d, N, M, T, R, noise=oracle.NOISE_GAUSS, seed=3):
                              cv_ref=_ref(mu, sigma, N))
     outs = P.run(R, T)
     C = np.array([[o.cv_count[c] for c in range(d + 1)] for o in outs])
-    q = np.array([o.cv_q for o in outs])
-    return P, C, q
+    C1 = np.array([[o.cv_count1[c] for c in range(d + 1)] for o in outs])
+    return P, C, C1
 
 
-def _check_moments(C, q, law, tol=5.0):
+def _check_moments(C, C1, law, tol=5.0):
+    """Weighted sums of i.i.d. categorical indicators: E count_c = p_c S2, Var = p_c (1 - p_c) S4,
+    Cov(count_c, count_c') = -p_c p_c' S4; for the (t+1) weights S1, S11, and
+    Cov(count1_c, count_c) = p_c (1 - p_c) S12."""
     n = C.shape[0]
-    p, S2, S4 = law.probs, law.S2, law.S4
-    mean = p * S2
-    var = p * (1 - p) * S4
-    ok = var > 0
-    z = (C.mean(0) - mean)[ok] / np.sqrt(var[ok] / n)
-    assert np.all(np.abs(z) < tol), z
-    # variances of the categories that are neither rare nor dominant (sums of many weighted
-    # indicators, close to normal): the sample variance scatters by about sqrt(2/n) (relative)
-    mid = (p > 0.05) & (p < 0.95)
-    rv = C.var(0, ddof=1)[mid] / var[mid]
-    assert np.all(np.abs(rv - 1) < tol * math.sqrt(2.0 / n) + 0.02), rv
-    # the covariance of two categories is -p_c p_c' S4
-    big = np.argsort(p)[-2:]
-    a, b = big
+    p, S2, S4, S1, S11, S12 = law.probs, law.S2, law.S4, law.S1, law.S11, law.S12
+    for cnt, mw, vw in ((C, S2, S4), (C1, S1, S11)):
+        mean = p * mw
+        var = p * (1 - p) * vw
+        ok = var > 0
+        z = (cnt.mean(0) - mean)[ok] / np.sqrt(var[ok] / n)
+        assert np.all(np.abs(z) < tol), z
+        # variances of the categories that are neither rare nor dominant (sums of many weighted
+        # indicators, close to normal): the sample variance scatters by about sqrt(2/n) (relative)
+        mid = (p > 0.05) & (p < 0.95)
+        rv = cnt.var(0, ddof=1)[mid] / var[mid]
+        assert np.all(np.abs(rv - 1) < tol * math.sqrt(2.0 / n) + 0.02), rv
+    a, b = np.argsort(p)[-2:]
     cov = np.cov(C[:, a], C[:, b])[0, 1]
-    assert abs(cov + p[a] * p[b] * S4) < tol * math.sqrt(var[a] * var[b] / n) * 1.5
-    k = law.kdof
-    assert ss.kstest(q, ss.chi2(k).cdf).pvalue > 1e-3
-    for c in big:
-        assert abs(np.corrcoef(C[:, c], q)[0, 1]) < tol / math.sqrt(n)
+    assert abs(cov + p[a] * p[b] * S4) < tol * math.sqrt(p[a] * (1 - p[a]) * p[b] * (1 - p[b])) * S4 / math.sqrt(n) * 1.5
+    c = law.top
+    corr = np.corrcoef(C[:, c], C1[:, c])[0, 1]
+    exact = S12 / math.sqrt(S4 * S11)
+    assert abs(corr - exact) < tol * (1 - exact ** 2) / math.sqrt(n) + 0.01, (corr, exact)
 
 
 @pytest.mark.parametrize("d,N,M,T,noise", [
@@ -111,18 +113,20 @@ def _check_moments(C, q, law, tol=5.0):
     (3, 3, 1, 30, oracle.NOISE_T),          # the features use the Gaussian numerators
 ])
 def test_path_feature_law(d, N, M, T, noise):
-    P, C, q = _paths(d, N, M, T, 3000, noise=noise)
+    P, C, C1 = _paths(d, N, M, T, 3000, noise=noise)
     law = oracle.CvLaw(P, T)
     assert abs(law.total - 1) < 1e-11
-    assert np.allclose(C.sum(1), law.S2)
-    _check_moments(C, q, law)
+    assert np.allclose(C.sum(1), law.S2) and np.allclose(C1.sum(1), law.S1)
+    _check_moments(C, C1, law)
 
 
 def test_weights_closed_form():
-    S2, S4 = oracle.cv_weights(4, 1)
+    S2, S4, S1, S11, S12 = oracle.cv_weights(4, 1)
     assert S2 == 1 + 4 + 9 + 16 and S4 == 1 + 16 + 81 + 256
-    S2, S4 = oracle.cv_weights(7, 3)        # epochs {1,2,3}, {4,5,6}, {7}
+    assert S1 == 10 and S11 == 30 and S12 == 1 + 8 + 27 + 64
+    S2, S4, S1, S11, S12 = oracle.cv_weights(7, 3)       # epochs {1,2,3}, {4,5,6}, {7}
     assert S2 == 140 and S4 == 14 ** 2 + 77 ** 2 + 49 ** 2
+    assert S1 == 28 and S11 == 6 ** 2 + 15 ** 2 + 7 ** 2 and S12 == 6 * 14 + 15 * 77 + 7 * 49
 
 
 def test_single_iteration_pick_is_the_argmin_of_the_sample_mean():
@@ -138,8 +142,7 @@ def test_single_iteration_pick_is_the_argmin_of_the_sample_mean():
         expect = np.zeros(d + 1)
         expect[cat] = 1.0
         assert np.array_equal([o.cv_count[c] for c in range(d + 1)], expect)
-        ssq = ((Z - Z.mean(axis=0)) ** 2).sum()
-        assert math.isclose(o.cv_q, ssq, rel_tol=1e-13)
+        assert np.array_equal([o.cv_count1[c] for c in range(d + 1)], expect)
 
 
 def test_aux_categories_follow_the_probabilities():
@@ -147,7 +150,7 @@ def test_aux_categories_follow_the_probabilities():
     mu, sigma = _instance(d)
     P = oracle.OracleProblem(mu, sigma, N=N, seed=21, instance=4, cv_ref=_ref(mu, sigma, N, 0.3))
     law = oracle.CvLaw(P, 1)
-    X, C, tries = law.aux(0, 20000)
+    X, C, C1 = law.aux(0, 20000)
     obs = C.sum(0)
     exp = law.probs * C.shape[0]
     keep = exp > 5
@@ -155,37 +158,47 @@ def test_aux_categories_follow_the_probabilities():
     assert ss.chi2(keep.sum() - 1).sf(chi) > 1e-3
 
 
-@pytest.mark.parametrize("d,N,M,T", [(3, 5, 1, 40), (1, 2, 1, 1), (1, 3, 1, 1), (1, 2, 1, 6), (2, 4, 3, 40)])
+@pytest.mark.parametrize("d,N,M,T", [(3, 5, 1, 40), (1, 2, 1, 6), (2, 4, 3, 40), (6, 3, 1, 25)])
 def test_aux_law(d, N, M, T):
-    """k = E d (N-1) of 1, 2 and 6 run the gamma sampler at shapes 1/2, 1 and 3."""
     mu, sigma = _instance(d)
     P = oracle.OracleProblem(mu, sigma, N=N, M=M, seed=21, instance=4, cv_ref=_ref(mu, sigma, N))
     law = oracle.CvLaw(P, T)
-    X, C, tries = law.aux(0, 4000)
-    assert np.all(tries >= 1)
-    _check_moments(C, law.kdof * 0 + (X[:, d + 1] * math.sqrt(2 * law.kdof) + law.kdof), law)
+    X, C, C1 = law.aux(0, 4000)
+    assert np.allclose(C.sum(1), law.S2) and np.allclose(C1.sum(1), law.S1)
+    _check_moments(C, C1, law)
 
 
-def test_aux_gamma_at_the_control_variate_size():
-    d, N, T = 10, 10, 10_000
+def test_standardized_features_have_unit_variance():
+    """Slot by slot: x_j is vertex e_j's count, x_d the origin's, x_{d+1} the (t+1)-weighted count of
+    the most probable category; each has mean 0 and, away from rare categories, variance 1. The
+    reference gradient leaves the origin a large share here."""
+    d, N, T = 3, 4, 30
     mu, sigma = _instance(d)
-    P = oracle.OracleProblem(mu, sigma, N=N, seed=21, instance=4, cv_ref=_ref(mu, sigma, N))
-    law = oracle.CvLaw(P, 1)
-    law.T, law.kdof = T, float(T * d * (N - 1))          # the gamma part only (one epoch of picks)
-    X, C, tries = law.aux(0, 3000)
-    q = X[:, d + 1] * math.sqrt(2 * law.kdof) + law.kdof
-    assert ss.kstest(q, ss.chi2(law.kdof).cdf).pvalue > 1e-3
+    b = _ref(mu, sigma, N) + 0.9 * mu
+    P = oracle.OracleProblem(mu, sigma, N=N, seed=5, instance=1, cv_ref=b)
+    law = oracle.CvLaw(P, T)
+    assert 0.1 < law.probs[0] < 0.9
+    X, _, _ = law.aux(0, 6000)
+    cat = np.concatenate([law.probs[1:], law.probs[:1], [law.probs[law.top]]])
+    for j in range(d + 2):
+        assert abs(X[:, j].mean()) < 5 / math.sqrt(6000)
+        if 0.05 < cat[j] < 0.95:
+            assert abs(X[:, j].var() - 1) < 0.1, j
+
+
+def test_top_category():
+    assert oracle.lib().or_cv_top(3, oracle._dptr(np.array([0.1, 0.4, 0.4, 0.1]))) == 1
 
 
 def test_aux_matches_path_features():
     d, N, M, T = 2, 4, 3, 40
-    P, C, q = _paths(d, N, M, T, 3000)
+    P, C, C1 = _paths(d, N, M, T, 3000)
     law = oracle.CvLaw(P, T)
-    Xa, Ca, _ = law.aux(0, 3000)
-    Xp = np.array([law.standardize(C[i], q[i]) for i in range(C.shape[0])])
+    Xa, _, _ = law.aux(0, 3000)
+    Xp = np.array([law.standardize(C[i], C1[i]) for i in range(C.shape[0])])
     for j in range(d + 2):
         assert ss.ks_2samp(Xp[:, j], Xa[:, j]).pvalue > 1e-3
-    assert np.allclose(Xp[:, :d + 1].mean(0), 0.0, atol=0.15)
+    assert np.allclose(Xp.mean(0), 0.0, atol=0.15)
 
 
 def _theta(F, seed, scale=0.4):
