@@ -248,16 +248,17 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
     s_plain = math.sqrt(ps.var)
     s_resid = math.sqrt(max(cs.var_resid, 0.0))
     beta2_vh = cs.beta ** 2 * cs.var_h_aux
+    # aux draws per path: the variance-per-cost optimum sqrt(beta^2 var(h) / (c var(Y - beta h))), c the
+    # cost of one draw relative to one path, measured on the pilot
+    c_aux = (cs.aux_ms / (1 << 20)) / (cs.paths_ms / pilot_R)
+    ratio = min(100.0, max(1.0, math.sqrt(beta2_vh / (c_aux * max(cs.var_resid, 1e-300)))))
     out = {"workload": "control_variate", "instance": "paper_scale (seed 0)", "T": T, "d": len(mu), "N": N,
            "train": {"pairs": fit.n_train, "steps": fit.steps, "epochs": args.cv_epochs, "wall_s": train_wall,
                      "sim_ms": fit.sim_ms, "train_ms": fit.train_ms, "loss_first_epoch": fit.loss_first_epoch,
                      "loss_last_epoch": fit.loss_last_epoch, "beta": fit.beta, "pilot_rho2": fit.rho2},
            "pilot_paths": pilot_R, "sd_plain": s_plain, "sd_resid": s_resid,
-           "variance_ratio": ps.var / max(cs.var_resid, 1e-300), "aux_per_path": None, "targets": []}
-    # aux draws per path: the variance-per-cost optimum sqrt(beta^2 var(h) / (c var(Y - beta h))), c the
-    # cost of one draw relative to one path (one uniform per epoch against N d normals per iteration)
-    c_aux = 1.0 / 60.0
-    ratio = min(100.0, max(1.0, math.sqrt(beta2_vh / (c_aux * max(cs.var_resid, 1e-300)))))
+           "variance_ratio": ps.var / max(cs.var_resid, 1e-300), "aux_per_path": None,
+           "aux_cost_per_path": c_aux, "targets": []}
     for h in (1e-3, 1.96 * s_plain / 1000.0):
         r_plain = max(2, math.ceil((1.96 * s_plain / h) ** 2))
         r_cv = max(2, math.ceil((1.96 / h) ** 2 * (cs.var_resid + beta2_vh / ratio)))

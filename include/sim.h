@@ -113,12 +113,13 @@ typedef struct {
  *          b = cv_ref fixed before the run (lowest index among equal minima, the origin when the
  *          minimum is >= 0): i.i.d. categorical over epochs with probabilities p_c (c = 0 origin,
  *          c = j+1 vertex e_j), p_c one-dimensional normal integrals;
- *   K_c  = sum over iterations t of (t+1)^2 [J_e(t) = c];  S2 = sum_t (t+1)^2,
- *          S4 = sum_e (sum of (t+1)^2 over epoch e)^2;
- *   q    = sum_e sum_j sum_i (z_eij - zbar_ej)^2 ~ chi-square(k), k = E d (N-1), independent of J.
+ *   K_c  = sum over iterations t of (t+1)^2 [J_e(t) = c],  K1 = sum_t (t+1) [J_e(t) = c*], c* the
+ *          most probable category;  per epoch W2_e, W1_e = sums of (t+1)^2, (t+1) over it;
+ *          S2 = sum W2_e, S4 = sum W2_e^2, S1 = sum W1_e, S11 = sum W1_e^2.
  * Features: x_j = (K_{j+1} - p_{j+1} S2) / sqrt(S4 max(p(1-p), 1e-4)) for j < d, x_d the same for
- * the origin, x_{d+1} = (q - k) / sqrt(2k). Their joint law is exact for exact normals; binary32
- * normals move it by their rounding only. Supported with FP32 state, diagonal Sigma with every
+ * the origin, x_{d+1} = (K1 - p_c* S1) / sqrt(S11 max(p_c* (1 - p_c*), 1e-4)). The law is exact
+ * for exact arithmetic; the device takes J_e from binary32 sample means, which moves it only by
+ * near-ties at the rounding level. Supported with FP32 state, diagonal Sigma with every
  * sigma_j > 0, d <= 32 and T <= 92681. */
 
 /* Device pointers (owned by the context) to the per-path records of the last run, structure of
@@ -235,8 +236,8 @@ typedef struct {
     double mean_h_aux, var_h_aux;               /* h over the aux draws */
     double mean_cv, var_est, ci95_cv;           /* estimate, its variance, 95% half-width */
     double rho2;                                /* Corr(Y, h)^2 on this run */
-    uint64_t aux_gamma_failures;                /* aux draws whose gamma sampler did not accept (0) */
     double kernel_ms;                           /* device time: paths, features, h, aux, reductions */
+    double paths_ms, aux_ms;                    /* of which the path kernel, and the aux draws with h */
 } sim_cv_stats_out;
 
 /* Trains the surrogate for problem p (with T iterations) on the device: fixes the features'
@@ -273,11 +274,9 @@ int sim_mlp_grad(sim_ctx *ctx, const float *x, const float *y, uint64_t n, float
 
 /* Draws k0 .. k0+n-1 from the exact law of the features of problem p (reference gradient
  * p->cv_ref) with T iterations into host x [F][n]: per epoch one 53-bit uniform from Philox block
- * (e/2, 1, k, domain 2 | instance) picks the category by the cumulative p_0, p_1, ...; q by
- * Marsaglia-Tsang gamma sampling on blocks (64+i, 0, k, ...). failures (may be NULL): draws whose
- * gamma sampler did not accept within 64 tries. */
+ * (e/2, 1, k, domain 2 | instance) picks the category by the cumulative p_0, p_1, .... */
 int sim_cv_aux_draws(sim_ctx *ctx, const sim_params *p, uint64_t T, uint64_t seed, uint64_t k0, uint64_t n,
-                     float *x, uint64_t *failures);
+                     float *x);
 
 /* The features' law for problem p (reference gradient p->cv_ref) with T iterations, without a
  * device: probs [d+1] (0 origin, j+1 vertex e_j), S2 and S4 (may be NULL). Returns 0 or the code

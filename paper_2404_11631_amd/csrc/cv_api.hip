@@ -129,8 +129,9 @@ fw::AuxLaw aux_law(const sim_params *p, uint64_t T, uint64_t seed)
     law.d = (int)p->d;
     law.T = T;
     law.M = p->resample_every;
-    law.kdof = L.k;
-    law.alpha = 0.5 * L.k;
+    law.top = L.top;
+    law.mean1 = L.mean1;
+    law.inv1 = L.inv1;
     for (uint32_t c = 0; c <= p->d; ++c) {
         law.cum[c] = L.cum[c];
         law.mean[c] = L.mean[c];
@@ -144,6 +145,8 @@ int ensure_events(sim_ctx *ctx)
     CvState &cv = ctx->cv;
     if (!cv.ev0) HIP_TRY(ctx, hipEventCreate(&cv.ev0));
     if (!cv.ev1) HIP_TRY(ctx, hipEventCreate(&cv.ev1));
+    if (!cv.ev_a) HIP_TRY(ctx, hipEventCreate(&cv.ev_a));
+    if (!cv.ev_b) HIP_TRY(ctx, hipEventCreate(&cv.ev_b));
     return SIM_OK;
 }
 
@@ -257,10 +260,12 @@ int sim_mlp_grad(sim_ctx *ctx, const float *x, const float *y, uint64_t n, float
 }
 
 int sim_cv_aux_draws(sim_ctx *ctx, const sim_params *p, uint64_t T, uint64_t seed, uint64_t k0, uint64_t n,
-                     float *x, uint64_t *failures)
+                     float *x)
 {
     if (!ctx || !p || (n && !x)) return SIM_EINVAL;
-    int rc = validate(ctx->err, p, 1, T);
+    sim_params q = *p;
+    q.flags = SIM_CV_FEATURES;
+    int rc = validate(ctx->err, &q, 1, T);
     if (rc) return rc;
     if (k0 + n > (1ull << 32)) return set_err(ctx, SIM_EINVAL, "draw index beyond 2^32");
     if (n == 0) return SIM_OK;
@@ -268,15 +273,10 @@ int sim_cv_aux_draws(sim_ctx *ctx, const sim_params *p, uint64_t T, uint64_t see
     CvState &cv = ctx->cv;
     const uint32_t F = p->d + 2;
     if ((rc = ensure(ctx, cv.xaux, sizeof(float) * F * n))) return rc;
-    if ((rc = ensure(ctx, cv.fails, 64))) return rc;
-    HIP_TRY(ctx, hipMemsetAsync(cv.fails.ptr, 0, 4, ctx->stream));
-    if (fw::launch_cv_aux(aux_law(p, T, seed), k0, n, (float *)cv.xaux.ptr, n, (uint32_t *)cv.fails.ptr, ctx->stream))
+    if (fw::launch_cv_aux(aux_law(&q, T, seed), k0, n, (float *)cv.xaux.ptr, n, ctx->stream))
         return set_err(ctx, SIM_EDEVICE, "aux launch failed");
-    uint32_t nf = 0;
     HIP_TRY(ctx, hipMemcpyAsync(x, cv.xaux.ptr, sizeof(float) * F * n, hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(&nf, cv.fails.ptr, 4, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize());
-    if (failures) *failures = nf;
     return SIM_OK;
 }
 
@@ -456,6 +456,7 @@ int sim_run_cv(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64
 
     HIP_TRY(ctx, hipEventRecord(cv.ev0, ctx->stream));
     if ((rc = run_impl(ctx, &q, R, T, seed, fw::kFlagYOnly))) return rc;
+    const hipEvent_t path_start = ctx->ev_start, path_stop = ctx->ev_stop;
     if ((rc = ensure(ctx, cv.hout, sizeof(float) * R))) return rc;
     if (fw::launch_mlp_forward(m, (const float *)ctx->feat.ptr, R, R, (float)cv.y_mean, (float)cv.y_sd,
                                (float *)cv.hout.ptr, ctx->stream))
@@ -468,25 +469,25 @@ int sim_run_cv(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64
     const uint64_t chunk = std::min<uint64_t>(R_aux, kAuxChunk);
     if ((rc = ensure(ctx, cv.xaux, sizeof(float) * cv.F * chunk))) return rc;
     if ((rc = ensure(ctx, cv.haux, sizeof(float) * chunk))) return rc;
-    if ((rc = ensure(ctx, cv.fails, 64))) return rc;
-    HIP_TRY(ctx, hipMemsetAsync(cv.fails.ptr, 0, 4, ctx->stream));
     Acc sb, sb2;
+    float aux_ms = 0.0f;
     for (uint64_t k0 = 0; k0 < R_aux; k0 += chunk) {
         const uint64_t nk = std::min(chunk, R_aux - k0);
-        if (fw::launch_cv_aux(law, k0, nk, (float *)cv.xaux.ptr, nk, (uint32_t *)cv.fails.ptr, ctx->stream))
+        HIP_TRY(ctx, hipEventRecord(cv.ev_a, ctx->stream));
+        if (fw::launch_cv_aux(law, k0, nk, (float *)cv.xaux.ptr, nk, ctx->stream))
             return set_err(ctx, SIM_EDEVICE, "aux launch failed");
         if (fw::launch_mlp_forward(m, (const float *)cv.xaux.ptr, nk, nk, (float)cv.y_mean, (float)cv.y_sd,
                                    (float *)cv.haux.ptr, ctx->stream))
             return set_err(ctx, SIM_EDEVICE, "surrogate forward launch failed");
+        HIP_TRY(ctx, hipEventRecord(cv.ev_b, ctx->stream));
         double ma[5];
         if ((rc = moments(ctx, nullptr, (const float *)cv.haux.ptr, nk, 0.0, cv.y_mean, ma))) return rc;
+        aux_ms += elapsed(cv.ev_a, cv.ev_b);
         sb.add(ma[1], 0.0);
         sb2.add(ma[3], 0.0);
         cv.n_aux_last = nk;
     }
     HIP_TRY(ctx, hipEventRecord(cv.ev1, ctx->stream));
-    uint32_t nf = 0;
-    HIP_TRY(ctx, hipMemcpyAsync(&nf, cv.fails.ptr, 4, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
 
     const MeanVar y = mean_var(mo[0], mo[2], cv.y_mean, R), hv = mean_var(mo[1], mo[3], cv.y_mean, R);
@@ -507,8 +508,9 @@ int sim_run_cv(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64
     out->var_est = out->var_resid / (double)R + b * b * ha.var / (double)R_aux;
     out->ci95_cv = 1.96 * std::sqrt(out->var_est);
     out->rho2 = (hv.var > 0.0 && y.var > 0.0) ? cov * cov / (hv.var * y.var) : 0.0;
-    out->aux_gamma_failures = nf;
     out->kernel_ms = elapsed(cv.ev0, cv.ev1);
+    out->paths_ms = elapsed(path_start, path_stop);
+    out->aux_ms = aux_ms;
     cv.R = R;
     return SIM_OK;
 }

@@ -52,11 +52,11 @@ struct CvState {
     DevBuf theta, w1a, w2a, w2t, mom1, mom2, part, grad, loss_hist;
     DevBuf xtrain, ytrain, ttrain;        // training pairs: [F][n] features, Y (FP64), target (FP32)
     DevBuf xio, yio, hout;                // staging of sim_mlp_forward / sim_mlp_grad, and h(x) of a run
-    DevBuf xaux, haux, mpart, mout, mdone, fails;
+    DevBuf xaux, haux, mpart, mout, mdone;
     uint64_t n_train = 0, n_steps = 0, R = 0, n_aux_last = 0;
     double y_mean = 0.0, y_sd = 1.0, beta = 0.0, rho2 = 0.0;
     double ref[SIM_MAX_D] = {0};          // the features' reference gradient of the fitted surrogate
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_a = nullptr, ev_b = nullptr;
 };
 
 struct sim_ctx {

@@ -88,7 +88,7 @@ struct LaneResult {
 template <int D, bool EXACT, typename Real, int NOISE, typename WS, bool FEAT>
 __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, const RunBuffers &B,
                                          uint32_t r, uint32_t (&cnt)[D + 1], WS (&S)[D],
-                                         LaneResult &res)
+                                         LaneResult &res, uint64_t *feat_cnt)
 {
     const Coef<Real> C{P};
     const int d = EXACT ? D : static_cast<int>(P->d);
@@ -108,27 +108,28 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
     uint32_t ck = 0;
     uint64_t next_ckpt = n_ckpt ? P->ckpt[0] : 0;
     uint32_t epoch = 0, m_in_epoch = 0;   // t = epoch * M + m_in_epoch
-    // control-variate summaries: per category (0 origin, j+1 vertex e_j) the sum of (t+1)^2 over
-    // iterations whose epoch's reference decision is that category (integers < 2^53, exact in
-    // FP64 in any order), and the pooled within-asset sum of squares
-    double fcnt[D + 1];
-    double fzeta = 0.0;
+    // control-variate summaries: per category (0 origin, j+1 vertex e_j) the integer sum of (t+1)^2
+    // over iterations whose epoch's reference decision is that category, in this thread's column
+    // of LDS (feat_cnt[c * kBlock]); the (t+1)-weighted count of the most probable category
+    uint64_t fcnt1 = 0;
+    const uint32_t ftop = FEAT ? P->cv_top : 0u;
+    if constexpr (FEAT) {
 #pragma unroll
-    for (int j = 0; j <= D; ++j) fcnt[j] = 0.0;
+        for (int c = 0; c <= D; ++c) feat_cnt[c * kBlock] = 0;
+    }
 
     for (uint64_t t = 0; t < T; ++t) {
         // iterate w_t (scale factor of the signature) and v = sigma .* w_t
         const double cw = t == 0 ? 0.0 : 2.0 / (static_cast<double>(t) * static_cast<double>(t + 1));
         const Real cwr = static_cast<Real>(cw);
         Real v[D], s1[D], s2[D];
-        Real sq[D], g1[D];   // FEAT: sum of squares and (t noise) sum of the Gaussian numerators
+        Real g1[D];          // FEAT with t noise: sum of the Gaussian numerators
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             const Real w = (t == 0) ? (P->has_w0 ? C.w0(j) : Real(0)) : static_cast<Real>(S[j]) * cwr;
             v[j] = (j < d) ? C.sz(j) * w : Real(0);
             s1[j] = Real(0);
             s2[j] = Real(0);
-            sq[j] = Real(0);
             g1[j] = Real(0);
         }
         const bool feat_epoch = FEAT && m_in_epoch == 0;   // draws repeat within an epoch
@@ -158,7 +159,6 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
                     for (int j = 0; j < D; ++j) {
                         s1[j] += z[s * D + j];
                         s2[j] = fma(z[s * D + j], dot, s2[j]);
-                        if constexpr (FEAT) sq[j] = fma(z[s * D + j], z[s * D + j], sq[j]);
                     }
                 }
             }
@@ -187,8 +187,7 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
                         for (int j = 0; j < D; ++j) {
                             s1[j] += z[s * D + j];
                             s2[j] = fma(z[s * D + j], dot, s2[j]);
-                            if constexpr (FEAT) sq[j] = fma(z[s * D + j], z[s * D + j], sq[j]);
-                        }
+                            }
                     }
                 }
             }
@@ -201,12 +200,9 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
                 Real z[D];
 #pragma unroll
                 for (int j = 0; j < D; ++j) z[j] = (j < d) ? cur.next(epoch, r, dom, k0, k1) : Real(0);
-                if constexpr (FEAT) {
+                if constexpr (FEAT && NOISE == 1) {
 #pragma unroll
-                    for (int j = 0; j < D; ++j) {
-                        sq[j] = fma(z[j], z[j], sq[j]);
-                        if constexpr (NOISE == 1) g1[j] += z[j];
-                    }
+                    for (int j = 0; j < D; ++j) g1[j] += z[j];
                 }
                 if constexpr (NOISE == 1) {
                     Real ss = Real(0);
@@ -231,29 +227,28 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
 
         if constexpr (FEAT) {
             if (feat_epoch) {
-                // the reference decision for b - sigma .* zbar (FP64; lowest index among equal
-                // minima, the origin when the minimum is >= 0), weighted by the epoch's
-                // sum of (t+1)^2 over [t, min(t + M, T))
+                // the reference decision for b - sigma .* zbar (lowest index among equal minima,
+                // the origin when the minimum is >= 0), weighted by the epoch's sums of (t+1)^2
+                // and (t+1) over [t, min(t + M, T))
                 const uint64_t t1 = (t + M < T) ? t + M : T;
-                const double we = static_cast<double>(t1 * (t1 + 1) * (2 * t1 + 1) / 6 - t * (t + 1) * (2 * t + 1) / 6);
-                double vmin = 0.0;
-                int pick = 0;
-                Real qsum = Real(0);
+                const uint64_t w2 = (M == 1) ? (t + 1) * (t + 1)
+                                             : t1 * (t1 + 1) * (2 * t1 + 1) / 6 - t * (t + 1) * (2 * t + 1) / 6;
+                const uint64_t w1 = (M == 1) ? t + 1 : t1 * (t1 + 1) / 2 - t * (t + 1) / 2;
+                float vmin = 0.0f;
+                uint32_t pick = 0;
 #pragma unroll
                 for (int j = 0; j < D; ++j) {
                     if (j < d) {
-                        const Real u = (NOISE == 1) ? g1[j] : s1[j];
-                        const double v = P->cv_b[j] - P->cv_s[j] * static_cast<double>(u);
+                        const float u = static_cast<float>((NOISE == 1) ? g1[j] : s1[j]);
+                        const float v = fmaf(-P->cv_s[j], u, P->cv_b[j]);
                         if (v < vmin) {
                             vmin = v;
-                            pick = j + 1;
+                            pick = static_cast<uint32_t>(j + 1);
                         }
-                        qsum += sq[j] - u * u * C.inv_n();
                     }
                 }
-#pragma unroll
-                for (int c = 0; c <= D; ++c) fcnt[c] += (c == pick) ? we : 0.0;
-                fzeta += static_cast<double>(qsum);
+                feat_cnt[pick * kBlock] += w2;
+                fcnt1 += (pick == ftop) ? w1 : 0u;
             }
         }
 
@@ -306,16 +301,18 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
         P, S, 2.0 / (static_cast<double>(T) * static_cast<double>(T + 1)));
     res.tau = tau;
     if constexpr (FEAT) {
-        // x_j for vertex e_j (category j+1), x_d for the origin, x_{d+1} the chi-square summary
+        // x_j for vertex e_j (category j+1), x_d for the origin, x_{d+1} the (t+1)-weighted count of
+        // the most probable category; the integer counts are exact in FP64 (< 2^53)
 #pragma unroll
         for (int c = 0; c <= D; ++c) {
             if (c <= d) {
                 const uint64_t row = (c == 0) ? static_cast<uint64_t>(d) : static_cast<uint64_t>(c - 1);
-                B.feat[row * R + r] = static_cast<float>((fcnt[c] - P->cv_mean[c]) * P->cv_inv[c]);
+                B.feat[row * R + r] =
+                    static_cast<float>((static_cast<double>(feat_cnt[c * kBlock]) - P->cv_mean[c]) * P->cv_inv[c]);
             }
         }
         B.feat[static_cast<uint64_t>(d + 1) * R + r] =
-            static_cast<float>((fzeta * P->cv_kappa2 - P->cv_k) * P->cv_zeta_inv);
+            static_cast<float>((static_cast<double>(fcnt1) - P->cv_mean1) * P->cv_inv1);
     }
 }
 
@@ -329,6 +326,8 @@ __global__ __launch_bounds__(kBlock) void fw_paths_kernel(const InstanceDesc *__
     __shared__ double sm_f[2 * (kBlock / 64)];
     __shared__ uint64_t sm_i[kBlock / 64];
     __shared__ uint32_t sm_last;
+    // control-variate counts, [category][thread]: each thread owns its column
+    __shared__ uint64_t sm_feat[FEAT ? (D + 1) * kBlock : 1];
 
     const uint64_t R = P->R;
     const uint64_t r = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -339,7 +338,8 @@ __global__ __launch_bounds__(kBlock) void fw_paths_kernel(const InstanceDesc *__
     WS S[D];
     LaneResult res{0.0, kTauNone};
     if (active) {
-        run_path<D, EXACT, Real, NOISE, WS, FEAT>(P, B, static_cast<uint32_t>(r), cnt, S, res);
+        run_path<D, EXACT, Real, NOISE, WS, FEAT>(P, B, static_cast<uint32_t>(r), cnt, S, res,
+                                                  sm_feat + threadIdx.x);
         if ((P->flags & 8u) && !(P->flags & 1u)) B.y[r] = res.y;   // outcomes only
         if (P->flags & 1u) {
             B.y[r] = res.y;

@@ -140,16 +140,16 @@ void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uin
     if (p->flags & SIM_CV_FEATURES) {
         const CvLaw law = cv_law(p, T);
         for (uint32_t j = 0; j < p->d; ++j) {
-            D.cv_b[j] = p->cv_ref[j];
-            D.cv_s[j] = p->sigma[j] * kappa / N;
+            D.cv_b[j] = (float)p->cv_ref[j];
+            D.cv_s[j] = (float)(p->sigma[j] * kappa / N);
         }
         for (uint32_t c = 0; c <= p->d; ++c) {
             D.cv_mean[c] = law.mean[c];
             D.cv_inv[c] = law.inv[c];
         }
-        D.cv_kappa2 = kappa * kappa;
-        D.cv_k = law.k;
-        D.cv_zeta_inv = 1.0 / std::sqrt(2.0 * law.k);
+        D.cv_mean1 = law.mean1;
+        D.cv_inv1 = law.inv1;
+        D.cv_top = law.top;
     }
     for (uint32_t j = 0; j < p->d; ++j) {
         // with a dense L the per-asset scale is the marginal standard deviation |row j of L|
@@ -311,25 +311,32 @@ CvLaw cv_law(const sim_params *p, uint64_t T)
     std::vector<double> s(d);
     for (uint32_t j = 0; j < d; ++j) s[j] = p->sigma[j] / std::sqrt((double)p->n_samples);
     cv_pick_probs(d, p->cv_ref, s.data(), L.p);
-    // S2 = sum_t (t+1)^2; S4 = sum over epochs of (sum of (t+1)^2 over the epoch)^2
-    auto sq_sum = [](uint64_t n) { return (double)(n * (n + 1) * (2 * n + 1) / 6); };
-    L.S2 = sq_sum(T);
-    L.S4 = 0.0;
+    // per epoch e: W2_e, W1_e = sums of (t+1)^2 and (t+1) over its iterations;
+    // S2 = sum W2_e, S4 = sum W2_e^2, S1 = sum W1_e, S11 = sum W1_e^2
+    L.S2 = L.S4 = L.S1 = L.S11 = 0.0;
     L.epochs = 0;
     for (uint64_t t0 = 0; t0 < T; t0 += M, ++L.epochs) {
         const uint64_t t1 = std::min<uint64_t>(t0 + M, T);
-        const double we = sq_sum(t1) - sq_sum(t0);
-        L.S4 += we * we;
+        const double w2 = (double)(t1 * (t1 + 1) * (2 * t1 + 1) / 6 - t0 * (t0 + 1) * (2 * t0 + 1) / 6);
+        const double w1 = (double)(t1 * (t1 + 1) / 2 - t0 * (t0 + 1) / 2);
+        L.S2 += w2;
+        L.S4 += w2 * w2;
+        L.S1 += w1;
+        L.S11 += w1 * w1;
     }
+    auto inv_sd = [](double S, double p) { return 1.0 / std::sqrt(S * std::max(p * (1.0 - p), 1e-4)); };
     double cum = 0.0;
+    L.top = 0;
     for (uint32_t c = 0; c <= d; ++c) {
         L.mean[c] = L.p[c] * L.S2;
-        L.inv[c] = 1.0 / std::sqrt(L.S4 * std::max(L.p[c] * (1.0 - L.p[c]), 1e-4));
+        L.inv[c] = inv_sd(L.S4, L.p[c]);
         cum += L.p[c];
         L.cum[c] = cum;
+        if (L.p[c] > L.p[L.top]) L.top = c;
     }
     L.cum[d] = 2.0;   // every uniform falls below the last bound
-    L.k = (double)L.epochs * (double)d * (double)(p->n_samples - 1);
+    L.mean1 = L.p[L.top] * L.S1;
+    L.inv1 = inv_sd(L.S11, L.p[L.top]);
     return L;
 }
 

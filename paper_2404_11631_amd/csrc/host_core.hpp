@@ -21,11 +21,12 @@ int validate(char *err, const sim_params *p, uint64_t R, uint64_t T);
 void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed);
 // Law of the control-variate features of a run (diagonal Sigma, reference gradient p->cv_ref):
 // reference-decision probabilities p (0 origin, j+1 vertex e_j) and their running sums, the
-// weights S2 = sum_t (t+1)^2 and S4 = sum_e (epoch sum of (t+1)^2)^2, the standardization of the
-// counts, and the chi-square degrees of freedom k = E d (N-1).
+// weights S2 = sum_e W2_e, S4 = sum_e W2_e^2, S1 = sum_e W1_e, S11 = sum_e W1_e^2 (W2_e, W1_e the
+// epoch sums of (t+1)^2 and (t+1)), the standardization of the counts, the most probable category.
 struct CvLaw {
     double p[kMaxD + 1], cum[kMaxD + 1], mean[kMaxD + 1], inv[kMaxD + 1];
-    double S2, S4, k;
+    double S2, S4, S1, S11, mean1, inv1;
+    uint32_t top;
     uint64_t epochs;
 };
 void cv_pick_probs(uint32_t d, const double *b, const double *s, double *p);

@@ -365,13 +365,9 @@ __global__ __launch_bounds__(256) void mlp_init_kernel(MlpDev m, uint64_t seed, 
 // Draws k0 .. k0+n-1 from the exact joint law of the path features (stream domain 2 of the seed):
 // per epoch e a category from the 53-bit uniform ((a >> 5) 2^26 + (b >> 6) + 1/2) 2^-53 of words
 // (a, b) = (x0, x1) for even e, (x2, x3) for odd e of Philox block (e/2, 1, k, ...), weighted by the
-// epoch's sum of (t+1)^2; and q = 2 G, G ~ Gamma(k/2) by Marsaglia and Tsang (ACM TOMS 26(3), 2000;
-// shapes below one through G = G' V^(1/alpha), G' of shape alpha + 1), try i on Philox block
-// (64 + i, 0, k, ...): its first pair gives the normal (cosine branch), word 2 the acceptance
-// uniform, word 3 V. FP64 throughout. D bounds d (categories 0..d).
+// epoch's sums of (t+1)^2 (every category) and (t+1) (category `top`). D bounds d.
 template <int D>
-__global__ __launch_bounds__(256) void cv_aux_kernel(AuxLaw law, uint64_t k0, uint64_t n, float *x, uint64_t ldx,
-                                                     uint32_t *failures)
+__global__ __launch_bounds__(256) void cv_aux_kernel(AuxLaw law, uint64_t k0, uint64_t n, float *x, uint64_t ldx)
 {
     constexpr int LEN = D + 1;                 // categories 0..D; entries beyond d hold 2 (never <= u)
     constexpr int TOP = (LEN > 32) ? 64 : (LEN > 16) ? 32 : (LEN > 8) ? 16 : (LEN > 4) ? 8 : 4;
@@ -389,7 +385,9 @@ __global__ __launch_bounds__(256) void cv_aux_kernel(AuxLaw law, uint64_t k0, ui
     const uint32_t dom = (2u << 24) | (law.instance & 0xFFFFFFu);
     const uint32_t s0 = static_cast<uint32_t>(law.seed), s1 = static_cast<uint32_t>(law.seed >> 32);
     const uint64_t T = law.T, M = law.M;
+    const int top = static_cast<int>(law.top);
 
+    uint64_t cnt1 = 0;
     Words4 w{0u, 0u, 0u, 0u};
     uint32_t e = 0;
     for (uint64_t t0 = 0; t0 < T; t0 += M, ++e) {
@@ -403,35 +401,17 @@ __global__ __launch_bounds__(256) void cv_aux_kernel(AuxLaw law, uint64_t k0, ui
         for (int step = TOP; step >= 1; step >>= 1)
             if (c + step <= LEN && s_cum[c + step - 1] <= u) c += step;
         const uint64_t t1 = (t0 + M < T) ? t0 + M : T;
-        s_cnt[c * 256 + tid] += t1 * (t1 + 1) * (2 * t1 + 1) / 6 - t0 * (t0 + 1) * (2 * t0 + 1) / 6;
+        const uint64_t w2 = (M == 1) ? (t0 + 1) * (t0 + 1)
+                                     : t1 * (t1 + 1) * (2 * t1 + 1) / 6 - t0 * (t0 + 1) * (2 * t0 + 1) / 6;
+        const uint64_t w1 = (M == 1) ? t0 + 1 : t1 * (t1 + 1) / 2 - t0 * (t0 + 1) / 2;
+        s_cnt[c * 256 + tid] += w2;
+        cnt1 += (c == top) ? w1 : 0u;
     }
     for (int c = 0; c <= d; ++c) {
         const uint64_t row = (c == 0) ? static_cast<uint64_t>(d) : static_cast<uint64_t>(c - 1);
         x[row * ldx + idx] = static_cast<float>((static_cast<double>(s_cnt[c * 256 + tid]) - law.mean[c]) * law.inv[c]);
     }
-
-    const bool boost = law.alpha < 1.0;
-    const double alpha = boost ? law.alpha + 1.0 : law.alpha;
-    const double dd = alpha - 1.0 / 3.0;
-    const double cc = 1.0 / sqrt(9.0 * dd);
-    double g = dd;
-    bool ok = false;
-    for (uint32_t i = 0; i < 64 && !ok; ++i) {
-        const Words4 v4 = philox4x32_10(64u + i, 0u, k, dom, s0, s1);
-        const double z = box_muller64(v4.x0, v4.x1).c;
-        const double uu = static_cast<double>(uniform_open01(v4.x2));
-        const double bb = 1.0 + cc * z;
-        if (bb > 0.0) {
-            const double v = bb * bb * bb;
-            if (log(uu) < 0.5 * z * z + dd - dd * v + dd * log(v)) {
-                g = dd * v;
-                if (boost) g *= pow(static_cast<double>(uniform_open01(v4.x3)), 1.0 / law.alpha);
-                ok = true;
-            }
-        }
-    }
-    if (!ok) atomicAdd(failures, 1u);
-    x[static_cast<uint64_t>(d + 1) * ldx + idx] = static_cast<float>((2.0 * g - law.kdof) / sqrt(2.0 * law.kdof));
+    x[static_cast<uint64_t>(d + 1) * ldx + idx] = static_cast<float>((static_cast<double>(cnt1) - law.mean1) * law.inv1);
 }
 
 // Double-double sums of a = A - sa, b = B - sb, a^2, b^2, a b over n pairs (A FP64 or absent,
@@ -545,15 +525,14 @@ int launch_mlp_init(const MlpDev &m, uint64_t seed, uint32_t instance, hipStream
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
-int launch_cv_aux(const AuxLaw &law, uint64_t k0, uint64_t n, float *x, uint64_t ldx, uint32_t *failures,
-                  hipStream_t st)
+int launch_cv_aux(const AuxLaw &law, uint64_t k0, uint64_t n, float *x, uint64_t ldx, hipStream_t st)
 {
     if (n == 0) return 0;
     const dim3 g(static_cast<uint32_t>((n + 255) / 256)), b(256);
-    if (law.d <= 4) hipLaunchKernelGGL(cv_aux_kernel<4>, g, b, 0, st, law, k0, n, x, ldx, failures);
-    else if (law.d <= 8) hipLaunchKernelGGL(cv_aux_kernel<8>, g, b, 0, st, law, k0, n, x, ldx, failures);
-    else if (law.d <= 16) hipLaunchKernelGGL(cv_aux_kernel<16>, g, b, 0, st, law, k0, n, x, ldx, failures);
-    else if (law.d <= 32) hipLaunchKernelGGL(cv_aux_kernel<32>, g, b, 0, st, law, k0, n, x, ldx, failures);
+    if (law.d <= 4) hipLaunchKernelGGL(cv_aux_kernel<4>, g, b, 0, st, law, k0, n, x, ldx);
+    else if (law.d <= 8) hipLaunchKernelGGL(cv_aux_kernel<8>, g, b, 0, st, law, k0, n, x, ldx);
+    else if (law.d <= 16) hipLaunchKernelGGL(cv_aux_kernel<16>, g, b, 0, st, law, k0, n, x, ldx);
+    else if (law.d <= 32) hipLaunchKernelGGL(cv_aux_kernel<32>, g, b, 0, st, law, k0, n, x, ldx);
     else return -5;
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }

@@ -36,15 +36,15 @@ struct AdamStep {
 };
 
 // Law of the path features for the aux draws (stream domain 2 of `seed`, `instance`): reference
-// decisions i.i.d. over epochs with cumulative probabilities cum (origin first, last entry 2),
-// standardized by mean and inv; the chi-square summary with kdof degrees of freedom.
+// decisions i.i.d. over epochs with cumulative probabilities cum (origin first, last entry 2), the
+// counts standardized by mean and inv, and the (t+1)-weighted count of category `top` by mean1, inv1.
 struct AuxLaw {
     uint64_t seed;
     uint32_t instance;
     int d;
     uint64_t T;
-    uint32_t M, pad_;
-    double kdof, alpha;    // alpha = kdof / 2
+    uint32_t M, top;
+    double mean1, inv1;
     double cum[65], mean[65], inv[65];
 };
 
@@ -56,8 +56,7 @@ int launch_mlp_reduce(const MlpDev &m, const float *part, uint32_t n_parts, int 
                       float *mom2, float *grad_out, float *loss_out, hipStream_t st);
 int launch_mlp_copies(const MlpDev &m, hipStream_t st);
 int launch_mlp_init(const MlpDev &m, uint64_t seed, uint32_t instance, hipStream_t st);
-int launch_cv_aux(const AuxLaw &law, uint64_t k0, uint64_t n, float *x, uint64_t ldx, uint32_t *failures,
-                  hipStream_t st);
+int launch_cv_aux(const AuxLaw &law, uint64_t k0, uint64_t n, float *x, uint64_t ldx, hipStream_t st);
 int launch_cv_moments(const double *A, const float *B, uint64_t n, double sa, double sb, double *part, uint32_t nb,
                       double *out, uint32_t *done, hipStream_t st);
 int launch_cv_target(const double *Y, uint64_t n, double mean, double inv_sd, float *t, hipStream_t st);

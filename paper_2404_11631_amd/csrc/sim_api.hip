@@ -154,10 +154,10 @@ void sim_destroy(sim_ctx *ctx)
     CvState &cv = ctx->cv;
     for (DevBuf *x : {&cv.theta, &cv.w1a, &cv.w2a, &cv.w2t, &cv.mom1, &cv.mom2, &cv.part, &cv.grad, &cv.loss_hist,
                       &cv.xtrain, &cv.ytrain, &cv.ttrain, &cv.xio, &cv.yio, &cv.hout, &cv.xaux, &cv.haux, &cv.mpart,
-                      &cv.mout, &cv.mdone, &cv.fails})
+                      &cv.mout, &cv.mdone})
         free_buf(*x);
-    if (cv.ev0) (void)hipEventDestroy(cv.ev0);
-    if (cv.ev1) (void)hipEventDestroy(cv.ev1);
+    for (hipEvent_t e : {cv.ev0, cv.ev1, cv.ev_a, cv.ev_b})
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 

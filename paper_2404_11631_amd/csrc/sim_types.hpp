@@ -43,13 +43,12 @@ struct InstanceDesc {
     uint64_t wsum_base;      // into signatures ([d][R] block of this instance)
     uint64_t dlog_base;      // into the decision log ([T][log_count] block)
     // control-variate features (flag 4): reference decisions and their law
-    double cv_b[kMaxD];          // reference gradient b
-    double cv_s[kMaxD];          // sigma_j sqrt(2 ln 2) / N: times the binary32 sum s1_j gives sigma_j zbar_j
+    float cv_b[kMaxD];           // reference gradient b
+    float cv_s[kMaxD];           // sigma_j sqrt(2 ln 2) / N: times the binary32 sum s1_j gives sigma_j zbar_j
     double cv_mean[kMaxD + 1];   // p_c S2, category c (0 origin, j+1 vertex e_j)
     double cv_inv[kMaxD + 1];    // 1 / sqrt(S4 max(p_c (1 - p_c), 1e-4))
-    double cv_kappa2;            // kappa^2: squares of binary32 normals back to unit scale
-    double cv_k;                 // E d (N-1)
-    double cv_zeta_inv;          // 1 / sqrt(2 k)
+    double cv_mean1, cv_inv1;    // the same for the (t+1)-weighted count of category cv_top
+    uint32_t cv_top, cv_pad_;
 };
 
 // One wavefront's unit of work in a batched run: `nrep` replications of one instance starting at

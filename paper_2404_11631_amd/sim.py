@@ -86,8 +86,8 @@ class SimCvStats(ctypes.Structure):
                 ("mean_plain", ctypes.c_double), ("var_plain", ctypes.c_double), ("ci95_plain", ctypes.c_double),
                 ("mean_resid", ctypes.c_double), ("var_resid", ctypes.c_double), ("mean_h_aux", ctypes.c_double),
                 ("var_h_aux", ctypes.c_double), ("mean_cv", ctypes.c_double), ("var_est", ctypes.c_double),
-                ("ci95_cv", ctypes.c_double), ("rho2", ctypes.c_double), ("aux_gamma_failures", ctypes.c_uint64),
-                ("kernel_ms", ctypes.c_double)]
+                ("ci95_cv", ctypes.c_double), ("rho2", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("paths_ms", ctypes.c_double), ("aux_ms", ctypes.c_double)]
 
 
 class SimCvView(ctypes.Structure):
@@ -152,8 +152,7 @@ def load():
         L.sim_mlp_get_params.argtypes = [vp, ctypes.c_uint32, fp]
         L.sim_mlp_forward.argtypes = [vp, fp, u64, fp]
         L.sim_mlp_grad.argtypes = [vp, fp, fp, u64, fp, ctypes.POINTER(ctypes.c_double)]
-        L.sim_cv_aux_draws.argtypes = [vp, ctypes.POINTER(SimParams), u64, u64, u64, u64, fp,
-                                       ctypes.POINTER(ctypes.c_uint64)]
+        L.sim_cv_aux_draws.argtypes = [vp, ctypes.POINTER(SimParams), u64, u64, u64, u64, fp]
         L.sim_cv_law.argtypes = [ctypes.POINTER(SimParams), u64, _dp, _dp, _dp, ctypes.c_char_p, ctypes.c_size_t]
         _lib = L
     return _lib
@@ -388,12 +387,12 @@ class Sim:
         return loss.value, g
 
     def cv_aux_draws(self, p: Problem, T: int, seed: int, k0: int, n: int):
+        """Draws k0 .. k0+n-1 from the features' law: [F][n]."""
         sp, keep = self.params(p)
         x = np.zeros((len(p.mu) + 2, n), dtype=np.float32)
-        nf = ctypes.c_uint64()
         self._check(self.L.sim_cv_aux_draws(self.h, ctypes.byref(sp), T, seed, k0, n,
-                                            x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(nf)))
-        return x, nf.value
+                                            x.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return x
 
     def cv_fit(self, p: Problem, T: int, seed: int, n_runs=1, epochs=1, R_train=65536, R_pilot=65536,
                batch=4096, lr=1e-3, reinit=True) -> SimCvFitOut:

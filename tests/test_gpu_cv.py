@@ -59,14 +59,19 @@ def test_features_match_oracle(ctx, case):
     assert g["x"].shape == (d + 2, R)
     P = parity.oracle_problem(p, 77)
     law = oracle.CvLaw(P, T)
-    inv = 1.0 / np.sqrt(law.S4 * np.maximum(law.probs * (1 - law.probs), 1e-4))
+    inv = np.concatenate([1.0 / np.sqrt(law.S4 * np.maximum(law.probs * (1 - law.probs), 1e-4)),
+                          [1.0 / np.sqrt(law.S11 * max(law.probs[law.top] * (1 - law.probs[law.top]), 1e-4))]])
+    amb1 = 1.0 / math.sqrt(law.S11 * max(law.probs[law.top] * (1 - law.probs[law.top]), 1e-4))
     err, amb = 0.0, 0
     for r in range(R):
         o = parity.check_rep(P, g, r, T, oracle.U32, decisions=g["decisions"][:, r])
         ref = law.path_features(o)
         e = np.abs(g["x"][:, r].astype(np.float64) - ref)
         tol = FEAT_ATOL + 1e-6 * np.abs(ref)
-        tol[: d + 1] += o.cv_amb * inv.max()
+        # a flipped epoch moves its (t+1)^2 weight between two counts, and at most its (t+1)
+        # weight (<= the square root of the former) into or out of the top category's count
+        tol[: d + 1] += o.cv_amb * inv[: d + 1].max()
+        tol[d + 1] += math.sqrt(o.cv_amb) * amb1 * 4
         amb += o.cv_amb > 0
         err = max(err, e.max())
         assert np.all(e <= tol), f"rep {r}: feature errors {e}"
@@ -95,15 +100,14 @@ def test_feature_law_at_scale(ctx):
     ctx.run(p, R, T, 100)
     X = ctx.paths()["x"].astype(np.float64)
     probs, S2, S4 = sim.cv_law(p, T)
-    cat = np.concatenate([probs[1:], probs[:1]])       # feature order: vertices, then the origin
+    top = int(np.argmax(probs))
+    cat = np.concatenate([probs[1:], probs[:1], [probs[top]]])   # vertices, the origin, the top count
     v = cat * (1 - cat) / np.maximum(cat * (1 - cat), 1e-4)
-    for j in range(d + 1):
+    for j in range(d + 2):
         if v[j] > 0:
             assert abs(X[j].mean()) < 5 * math.sqrt(v[j] / R), f"feature {j} mean"
         if 0.05 < cat[j] < 0.95:
             assert abs(X[j].var() / v[j] - 1) < 5 * math.sqrt(2 / R) + 0.01, f"feature {j} variance"
-    k = T * d * 9
-    assert ss.kstest(X[d + 1] * math.sqrt(2 * k) + k, ss.chi2(k).cdf).pvalue > 1e-4
     say(f"[cv] law ok at R={R}: probabilities {np.round(probs, 3)}")
 
 
@@ -175,10 +179,9 @@ def test_aux_draws_match_oracle(ctx, d, N, M, T, n):
     mu, sigma = workloads.diag_instance(4, d, d)
     b = _ref(mu, sigma)
     p = sim.Problem(mu=mu, sigma=sigma, N=N, M=M, instance_id=5, cv_ref=b)
-    x, nf = ctx.cv_aux_draws(p, T, 123, 1000, n)
+    x = ctx.cv_aux_draws(p, T, 123, 1000, n)
     P = oracle.OracleProblem(mu, sigma, N=N, M=M, seed=123, instance=5, cv_ref=b)
-    ref, counts, tries = oracle.CvLaw(P, T).aux(1000, n)
-    assert nf == 0 and np.all(tries >= 1)
+    ref, _, _ = oracle.CvLaw(P, T).aux(1000, n)
     err = np.abs(x.T.astype(np.float64) - ref)
     say(f"[cv] aux d={d} T={T}: max err {err.max():.2e}")
     assert np.all(err <= 2e-6 + 1e-6 * np.abs(ref))
@@ -199,7 +202,7 @@ def test_cv_fit_and_estimate(ctx):
     R, R_aux = 20_000, 400_000
     st = ctx.run_cv(p, R, T, 100, R_aux)
     v = ctx.cv_paths()
-    assert st.aux_gamma_failures == 0 and v["h_aux"].shape == (R_aux,)
+    assert v["h_aux"].shape == (R_aux,) and 0 < st.paths_ms < st.kernel_ms and 0 < st.aux_ms < st.kernel_ms
     ost = oracle.cv_estimate(v["y"], v["h"].astype(np.float64), v["h_aux"].astype(np.float64), st.beta)
     for a, b, tol in ((st.mean_plain, ost.mean_plain, 1e-12), (st.var_plain, ost.var_plain, 1e-9),
                       (st.mean_resid, ost.mean_resid, 1e-12), (st.var_resid, ost.var_resid, 1e-8),
