@@ -16,7 +16,8 @@ int launch_fw_paths(const InstanceDesc &host_desc, const InstanceDesc *dev_desc,
 int launch_fw_batch(const BatchBuffers &B, const uint32_t *class_begin, hipStream_t stream);
 int launch_fw_dense(const InstanceDesc &host_desc, const InstanceDesc *dev_desc, const RunBuffers &B,
                     hipStream_t stream);
-constexpr int kDenseRepsPerBlock = kBlock / 2;   // dense-L kernels: two lanes per replication
+constexpr int kDenseLanesPerRep = 4;                       // dense-L kernels: four lanes per replication
+constexpr int kDenseRepsPerBlock = kBlock / kDenseLanesPerRep;
 }  // namespace fw
 
 using fw::InstanceDesc;

@@ -1,22 +1,23 @@
 // fw_dense.hip -- Algorithm 1 (Section 3.1) with correlated returns R_i = mu + L y_i (dense
 // lower-triangular L, Sigma = L L'), Gaussian or elliptical-t noise, d in {32, 64}, FP32 state.
 //
-// Mapping: two lanes per replication. Lane (r, p) of a wavefront (r = lane mod 32, p = lane / 32)
-// owns the d/2 assets a(p, k) = 8 (k div 4) + 4p + (k mod 4), k < d/2 -- alternate blocks of four,
-// so each lane draws exactly the Philox blocks of its own assets (block i d/4 + 2m + p holds
-// assets 8m + 4p .. 8m + 4p + 3 of sample i), accumulates s1 = sum_i y_i and s2 = sum_i y_i (y_i'v)
-// for its assets without any cross-lane sum, and needs one xor-32 exchange per sample for the dot
-// product y_i'v.
+// Mapping: four lanes per replication. Lane (r, p) of a wavefront (r = lane mod 16, p = lane / 16)
+// owns the d/4 assets a(p, k) = 16 (k div 4) + 4p + (k mod 4), k < d/4 -- every fourth block of four
+// -- so each lane draws exactly the Philox blocks of its own assets (block i d/4 + 4m + p holds
+// assets 16m + 4p .. 16m + 4p + 3 of sample i), accumulates s1 = sum_i y_i and s2 = sum_i y_i
+// (y_i'v) for its assets without any cross-lane sum, and needs two xor exchanges (16, 32) per sample
+// for the dot product.
 //
 // In noise coordinates the sample statistics factor through L (Eq. (4)-(5)):
 //   Rbar = mu + L s1 / N,   (N-1) Sigma_hat w = L (s2 - s1 (s1'v) / N),   v = L'w,
 // so the gradient is g = L h - mu with h = 2 lambda/(N-1) (s2 - s1 (s1'v)/N) - s1/N. The two
-// d x d products per iteration (v = L'w and g = L h) are, over the 32 replications of a wavefront,
-// (d x d) x (d x 32) products on v_mfma_f32_32x32x2f32: the B operand of step kk is register kk
-// of every lane (K index 2kk + p), the result lands in the same per-lane asset layout, and the
+// d x d products per iteration (v = L'w and g = L h) are, over the 16 replications of a wavefront,
+// (d x d) x (d x 16) products on v_mfma_f32_16x16x4f32: the B operand of step kk is register kk
+// of every lane (K index 4kk + p), the result lands in the same per-lane asset layout, and the
 // A operand (L or L' with its columns permuted once on the host) is read from global memory (L2
-// resident: every wavefront reads the same d^2 values) in the order the instruction consumes it. Binary32 normals are scaled by 1/sqrt(2 ln 2); the host folds that
-// constant into the FP32 copies of L.
+// resident: every wavefront reads the same d^2 values) in the order the instruction consumes it.
+// Binary32 normals are scaled by 1/sqrt(2 ln 2); the host folds that constant into the FP32
+// copies of L. With t noise y_i = a_i z_i enters as s1 += a_i z_i, s2 += a_i^2 (z_i'v) z_i.
 #include <hip/hip_runtime.h>
 
 #include "device_reduce.hpp"
@@ -26,42 +27,53 @@
 
 namespace fw {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ int dense_asset(int p, int k) { return (k >> 2) * 8 + 4 * p + (k & 3); }
+constexpr int kRepsPerWave = 64 / kDenseLanesPerRep;
+constexpr int kRB = kDenseRepsPerBlock;   // replications per workgroup
 
-// out = A x B over the 32 replications of this wavefront; A (D x D) in MFMA order
-// (A_mfma[(mt * D/2 + kk) * 64 + lane] = A[32 mt + lane mod 32][a(lane / 32, kk)]), read from
+__device__ __forceinline__ int dense_asset(int p, int k) { return (k >> 2) * 16 + 4 * p + (k & 3); }
+
+// Sum over the four lanes of a replication (lanes r, r+16, r+32, r+48).
+template <typename V>
+__device__ __forceinline__ V rep_sum(V x)
+{
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
+    return x;
+}
+
+// out = A x B over the 16 replications of this wavefront; A (D x D) in MFMA order
+// (A_mfma[(mt * D/4 + kk) * 64 + lane] = A[16 mt + lane mod 16][a(lane / 16, kk)]), read from
 // global memory: every wavefront of the grid reads the same D x D values, which stay in L2.
 template <int D>
-__device__ __forceinline__ void dense_product(const float *A_mfma, const float (&b)[D / 2],
-                                              float (&out)[D / 2], int lane)
+__device__ __forceinline__ void dense_product(const float *A_mfma, const float (&b)[D / 4],
+                                              float (&out)[D / 4], int lane)
 {
     // an opaque per-call lane offset keeps the compiler from precomputing (and holding) one
     // 64-bit address per operand: each load is base + 32-bit offset
     uint32_t off = static_cast<uint32_t>(lane);
     asm volatile("" : "+v"(off));
 #pragma unroll
-    for (int mt = 0; mt < D / 32; ++mt) {
-        f32x16 acc = {0.0f};
+    for (int mt = 0; mt < D / 16; ++mt) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int kk = 0; kk < D / 2; ++kk)
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(A_mfma[off + (mt * (D / 2) + kk) * 64], b[kk], acc, 0, 0, 0);
+        for (int kk = 0; kk < D / 4; ++kk)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A_mfma[off + (mt * (D / 4) + kk) * 64], b[kk], acc, 0, 0, 0);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) out[16 * mt + q] = acc[q];
+        for (int q = 0; q < 4; ++q) out[4 * mt + q] = acc[q];
     }
 }
 
-// f(w) = lambda |L'w|^2 - mu'w at w = c S, FP64 (Eq. (3)); both lanes of a replication return it.
-// sS[asset][replication] holds the signatures of the workgroup, so each lane forms
+// f(w) = lambda |L'w|^2 - mu'w at w = c S, FP64 (Eq. (3)); all four lanes of a replication return
+// it. sS[asset][replication] holds the signatures of the workgroup, so each lane forms
 // (L'w)_m = sum_j L_jm w_j for its own assets m. Every thread of the workgroup calls this at the
 // same iterations (checkpoints and the end).
 template <int D>
 __device__ __forceinline__ double dense_objective(const InstanceDesc *P, const double *L64,
                                                   int p, int rep, double c, const uint32_t *sS)
 {
-    constexpr int H = D / 2;
-    constexpr int RB = kBlock / 2;
+    constexpr int H = D / 4;
     __syncthreads();
     double quad = 0.0, lin = 0.0;
 #pragma unroll 1
@@ -69,24 +81,23 @@ __device__ __forceinline__ double dense_objective(const InstanceDesc *P, const d
         const int m = dense_asset(p, k);
         double v = 0.0;
 #pragma unroll 8
-        for (int j = m; j < D; ++j) v += L64[j * D + m] * static_cast<double>(sS[j * RB + rep]);
+        for (int j = m; j < D; ++j) v += L64[j * D + m] * static_cast<double>(sS[j * kRB + rep]);
         v *= c;
         quad += v * v;
-        lin += P->mu_d[m] * (static_cast<double>(sS[m * RB + rep]) * c);
+        lin += P->mu_d[m] * (static_cast<double>(sS[m * kRB + rep]) * c);
     }
     __syncthreads();
-    quad += __shfl_xor(quad, 32, 64);
-    lin += __shfl_xor(lin, 32, 64);
+    quad = rep_sum(quad);
+    lin = rep_sum(lin);
     return P->lambda * quad - lin;
 }
 
 template <int D, int NOISE>
 __global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P, RunBuffers B)
 {
-    constexpr int H = D / 2;
-    constexpr int RB = kBlock / 2;
-    __shared__ uint32_t sS[D * RB];          // signature S_j of each replication, [asset][replication]
-    __shared__ uint16_t sC[(D + 1) * RB];    // decision counts (T <= 65535), origin first
+    constexpr int H = D / 4;
+    __shared__ uint32_t sS[D * kRB];          // signature S_j of each replication, [asset][replication]
+    __shared__ uint16_t sC[(D + 1) * kRB];    // decision counts (T <= 65535), origin first
     __shared__ double sm_f[2 * (kBlock / 64)];
     __shared__ uint64_t sm_i[kBlock / 64];
     __shared__ uint32_t sm_last;
@@ -94,10 +105,10 @@ __global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P,
     const float *Av = B.dense_v;   // sqrt(2 ln 2) L', MFMA order: v = L'w
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int p = lane >> 5;
+    const int p = lane >> 4;
     const uint64_t R = P->R;
-    const int rep = wave * 32 + (lane & 31);   // replication within the workgroup
-    const uint64_t r64 = static_cast<uint64_t>(blockIdx.x) * (kBlock / 2) + rep;
+    const int rep = wave * kRepsPerWave + (lane & 15);   // replication within the workgroup
+    const uint64_t r64 = static_cast<uint64_t>(blockIdx.x) * kRB + rep;
     const bool active = r64 < R;
     const uint32_t r = static_cast<uint32_t>(r64);
     const uint32_t N = P->N, M = P->M;
@@ -111,8 +122,8 @@ __global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P,
 
 #pragma unroll
     for (int k = 0; k < H; ++k) {
-        sS[dense_asset(p, k) * RB + rep] = 0u;
-        sC[(dense_asset(p, k) + 1) * RB + rep] = 0;
+        sS[dense_asset(p, k) * kRB + rep] = 0u;
+        sC[(dense_asset(p, k) + 1) * kRB + rep] = 0;
     }
     if (p == 0) sC[rep] = 0;
     uint32_t tau = kTauNone;
@@ -132,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P,
 #pragma unroll
             for (int k = 0; k < H; ++k) {
                 w[k] = (t == 0) ? (P->has_w0 ? P->w0_f[dense_asset(p, k)] : 0.0f)
-                                : static_cast<float>(sS[dense_asset(p, k) * RB + rep]) * cw;
+                                : static_cast<float>(sS[dense_asset(p, k) * kRB + rep]) * cw;
                 s1[k] = 0.0f;
                 s2[k] = 0.0f;
             }
@@ -146,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P,
             float z[H];
 #pragma unroll
             for (int m = 0; m < H / 4; ++m) {
-                const Block4<float> q = normals_block<float>(i * (D / 4) + 2 * m + p, epoch, r, dom, k0, k1);
+                const Block4<float> q = normals_block<float>(i * (D / 4) + 4 * m + p, epoch, r, dom, k0, k1);
                 z[4 * m + 0] = q.z[0];
                 z[4 * m + 1] = q.z[1];
                 z[4 * m + 2] = q.z[2];
@@ -154,6 +165,7 @@ __global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P,
                 // two Philox chains in flight at most: bounds the live temporaries
                 if (m & 1) __builtin_amdgcn_sched_barrier(0);
             }
+            float a = 1.0f;
             if constexpr (NOISE == 1) {
                 float ss = 0.0f;
 #pragma unroll 1
@@ -161,32 +173,32 @@ __global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P,
                     const float e = ext.next(epoch, r, dom, k0, k1);
                     ss = fmaf(e, e, ss);
                 }
-                const float a = P->tscale_f * __builtin_amdgcn_rsqf(ss);
-#pragma unroll
-                for (int k = 0; k < H; ++k) z[k] *= a;
+                a = P->tscale_f * __builtin_amdgcn_rsqf(ss);
             }
             float dot = 0.0f;
 #pragma unroll
             for (int k = 0; k < H; ++k) dot = fmaf(z[k], v[k], dot);
-            dot += __shfl_xor(dot, 32, 64);
+            dot = rep_sum(dot);
+            const float a2dot = (NOISE == 1) ? a * a * dot : dot;
 #pragma unroll
             for (int k = 0; k < H; ++k) {
-                s1[k] += z[k];
-                s2[k] = fmaf(z[k], dot, s2[k]);
+                if constexpr (NOISE == 1) s1[k] = fmaf(a, z[k], s1[k]);
+                else s1[k] += z[k];
+                s2[k] = fmaf(z[k], a2dot, s2[k]);
             }
         }
 
         float dot1 = 0.0f;
 #pragma unroll
         for (int k = 0; k < H; ++k) dot1 = fmaf(s1[k], v[k], dot1);
-        dot1 += __shfl_xor(dot1, 32, 64);
+        dot1 = rep_sum(dot1);
         const float qn = dot1 * inv_n;
 #pragma unroll
         for (int k = 0; k < H; ++k) s2[k] = cu * (s2[k] - s1[k] * qn) - s1[k] * inv_n;   // h
         float g[H];
         dense_product<D>(Ag, s2, g, lane);
 
-        // vertex search: lowest asset index among equal minima, across both lanes
+        // vertex search: lowest asset index among equal minima, across the four lanes
         float gmin = 0.0f, gw = 0.0f;
         int jmin = -1;
 #pragma unroll
@@ -197,16 +209,19 @@ __global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P,
                 gmin = gj;
                 jmin = j;
             }
-            const float wk = (t == 0) ? (P->has_w0 ? P->w0_f[j] : 0.0f) : static_cast<float>(sS[j * RB + rep]) * cw;
+            const float wk = (t == 0) ? (P->has_w0 ? P->w0_f[j] : 0.0f) : static_cast<float>(sS[j * kRB + rep]) * cw;
             gw = fmaf(gj, wk, gw);
         }
-        const float og = __shfl_xor(gmin, 32, 64);
-        const int oj = __shfl_xor(jmin, 32, 64);
-        if (og < gmin || (og == gmin && oj < jmin)) {
-            gmin = og;
-            jmin = oj;
+#pragma unroll
+        for (int x = 16; x <= 32; x <<= 1) {
+            const float og = __shfl_xor(gmin, x, 64);
+            const int oj = __shfl_xor(jmin, x, 64);
+            if (og < gmin || (og == gmin && oj < jmin)) {
+                gmin = og;
+                jmin = oj;
+            }
         }
-        gw += __shfl_xor(gw, 32, 64);
+        gw = rep_sum(gw);
         const int a = (gmin < 0.0f) ? jmin + 1 : 0;
         const float gap = gw - (gmin < 0.0f ? gmin : 0.0f);
         if (tau == kTauNone && gap <= static_cast<float>(P->gap_eps)) tau = static_cast<uint32_t>(t);
@@ -214,10 +229,10 @@ __global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P,
 
         // the lane that owns the chosen vertex updates its signature and count
         const int ja = a - 1;
-        const bool mine = (a == 0) ? (p == 0) : (((ja >> 2) & 1) == p);
+        const bool mine = (a == 0) ? (p == 0) : (((ja >> 2) & 3) == p);
         if (mine) {
-            sC[a * RB + rep] += 1;
-            if (a > 0) sS[ja * RB + rep] += static_cast<uint32_t>(t + 1);
+            sC[a * kRB + rep] += 1;
+            if (a > 0) sS[ja * kRB + rep] += static_cast<uint32_t>(t + 1);
         }
         if (t + 1 == next_ckpt) {
             const double c = 2.0 / (static_cast<double>(t + 1) * static_cast<double>(t + 2));
@@ -235,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P,
                                         2.0 / (static_cast<double>(T) * static_cast<double>(T + 1)), sS);
     const bool leader = active && p == 0;
 
-    if (active && p == 0 && (P->flags & 8u) && !(P->flags & 1u)) B.y[r64] = y;   // outcomes only
+    if (leader && (P->flags & 8u) && !(P->flags & 1u)) B.y[r64] = y;   // outcomes only
     if (active && (P->flags & 1u)) {
         if (p == 0) {
             B.y[r64] = y;
@@ -245,8 +260,8 @@ __global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P,
 #pragma unroll 1
         for (int k = 0; k < H; ++k) {
             const int j = dense_asset(p, k);
-            B.cnt[static_cast<uint64_t>(j + 1) * R + r64] = sC[(j + 1) * RB + rep];
-            B.wsum[static_cast<uint64_t>(j) * R + r64] = sS[j * RB + rep];
+            B.cnt[static_cast<uint64_t>(j + 1) * R + r64] = sC[(j + 1) * kRB + rep];
+            B.wsum[static_cast<uint64_t>(j) * R + r64] = sS[j * kRB + rep];
         }
     }
 
@@ -294,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P,
         }
     }
     for (int j = 0; j <= D; ++j) {
-        const uint32_t cj = leader ? sC[j * RB + rep] : 0u;
+        const uint32_t cj = leader ? sC[j * kRB + rep] : 0u;
         const uint64_t tot = block_sum_u64(cj, sm_i);
         if (threadIdx.x == 0) store_agent(B.part_i + static_cast<uint64_t>(j) * nb + blockIdx.x, tot);
     }

@@ -340,18 +340,18 @@ CvLaw cv_law(const sim_params *p, uint64_t T)
     return L;
 }
 
-int dense_asset_of(int p, int k) { return (k >> 2) * 8 + 4 * p + (k & 3); }
+int dense_asset_of(int p, int k) { return (k >> 2) * 16 + 4 * p + (k & 3); }
 
 void dense_operands(const double *L, uint32_t d, float *Ag, float *Av, double *L64)
 {
     const double kappa = fw::kBoxMullerScale;
-    const uint32_t H = d / 2;
-    for (uint32_t mt = 0; mt < d / 32; ++mt)
-        for (uint32_t kk = 0; kk < H; ++kk)
+    const uint32_t K = d / 4;
+    for (uint32_t mt = 0; mt < d / 16; ++mt)
+        for (uint32_t kk = 0; kk < K; ++kk)
             for (uint32_t lane = 0; lane < 64; ++lane) {
-                const uint32_t row = 32 * mt + (lane & 31);
-                const uint32_t col = (uint32_t)dense_asset_of((int)(lane >> 5), (int)kk);
-                const size_t at = ((size_t)mt * H + kk) * 64 + lane;
+                const uint32_t row = 16 * mt + (lane & 15);
+                const uint32_t col = (uint32_t)dense_asset_of((int)(lane >> 4), (int)kk);
+                const size_t at = ((size_t)mt * K + kk) * 64 + lane;
                 Ag[at] = (float)(kappa * L[row * d + col]);   // g = L h
                 Av[at] = (float)(kappa * L[col * d + row]);   // v = L'w
             }

@@ -33,8 +33,8 @@ void cv_pick_probs(uint32_t d, const double *b, const double *s, double *p);
 CvLaw cv_law(const sim_params *p, uint64_t T);
 
 // The two FP32 operands of the dense-L kernels, sqrt(2 ln 2) L (for g = L h) and its transpose
-// (for v = L'w), each [d/32][d/2][64] in the lane order of v_mfma_f32_32x32x2f32 (row 32 mt +
-// lane mod 32, column the asset that lane lane/32 holds in register kk), and L copied in FP64.
+// (for v = L'w), each [d/16][d/4][64] in the lane order of v_mfma_f32_16x16x4f32 (row 16 mt +
+// lane mod 16, column the asset that lane lane/16 holds in register kk), and L copied in FP64.
 void dense_operands(const double *L, uint32_t d, float *Ag, float *Av, double *L64);
 double kkt_fstar(const double *mu, const double *sigma, uint32_t d, double lambda);
 // statistics from the reduced stream layout (per stream: sum hi/lo, squares hi/lo, count)
