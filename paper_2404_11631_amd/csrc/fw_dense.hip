@@ -92,8 +92,11 @@ __device__ __forceinline__ double dense_objective(const InstanceDesc *P, const d
     return P->lambda * quad - lin;
 }
 
+// Three wavefronts per SIMD: the register budget (<= 168) that still holds the per-lane state
+// (16 assets x z, s1, s2, v at d = 64) without spilling in the sample loop.
 template <int D, int NOISE>
-__global__ __launch_bounds__(kBlock) void fw_dense_kernel(const InstanceDesc *P, RunBuffers B)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3)))
+void fw_dense_kernel(const InstanceDesc *P, RunBuffers B)
 {
     constexpr int H = D / 4;
     __shared__ uint32_t sS[D * kRB];          // signature S_j of each replication, [asset][replication]
