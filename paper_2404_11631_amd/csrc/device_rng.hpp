@@ -19,6 +19,12 @@
 
 #include "sim_types.hpp"
 
+// Makes a value opaque to the optimiser without emitting an instruction, so that it stays in a
+// vector register instead of being recomputed where it is used.
+#ifndef FW_PIN_VGPR
+#define FW_PIN_VGPR(x) asm volatile("" : "+v"(x))
+#endif
+
 namespace fw {
 
 struct Words4 {
@@ -33,6 +39,63 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
         const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
         const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
         // three-input xors in one v_bitop3_b32 each (truth table 0x96: odd parity)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p0 >> 32), c3, k1, 0x96);
+        c1 = static_cast<uint32_t>(p1);
+        c3 = static_cast<uint32_t>(p0);
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Words4{c0, c1, c2, c3};
+}
+
+// The same generator over counters (b, e, r, s) of which only the block word b changes along a
+// stream: round 1's product of word 2 (= r) and round 2's product of word 0 depend on (e, r) and
+// the key alone, so a stream computes them once and each block starts from them.
+struct PhiloxRow {
+    uint32_t w1;     // word 1 after round 1: low half of M1 r
+    uint32_t p_hi;   // round 2 product of word 0 (hi(M1 r) ^ e ^ k0) with M0: high half
+    uint32_t p_lo;   //                                                      low half
+};
+
+__device__ __forceinline__ PhiloxRow philox_row(uint32_t e, uint32_t r, uint32_t k0)
+{
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * r;
+    const uint32_t x = static_cast<uint32_t>(p1 >> 32) ^ e ^ k0;
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * x;
+    PhiloxRow row{static_cast<uint32_t>(p1), static_cast<uint32_t>(p0 >> 32), static_cast<uint32_t>(p0)};
+    // keep the row live in registers: left to itself the compiler recomputes the two products
+    // in every block
+    FW_PIN_VGPR(row.w1);
+    FW_PIN_VGPR(row.p_hi);
+    FW_PIN_VGPR(row.p_lo);
+    return row;
+}
+
+// Philox4x32-10 of counter (b, e, r, s) from the row of (e, r); equal to philox4x32_10(b, e, r, s).
+__device__ __forceinline__ Words4 philox_block(const PhiloxRow &row, uint32_t b, uint32_t s, uint32_t k0,
+                                               uint32_t k1)
+{
+    // round 1, block word only
+    const uint64_t q = static_cast<uint64_t>(0xD2511F53u) * b;
+    const uint32_t a2 = static_cast<uint32_t>(q >> 32) ^ s ^ k1;
+    const uint32_t a3 = static_cast<uint32_t>(q);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+    // round 2: word 0's product comes from the row
+    const uint64_t q2 = static_cast<uint64_t>(0xCD9E8D57u) * a2;
+    uint32_t c0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(q2 >> 32), row.w1, k0, 0x96);
+    uint32_t c2 = __builtin_amdgcn_bitop3_b32(row.p_hi, a3, k1, 0x96);
+    uint32_t c1 = static_cast<uint32_t>(q2);
+    uint32_t c3 = row.p_lo;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+#pragma unroll
+    for (int round = 2; round < 10; ++round) {
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
         const uint32_t n0 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p1 >> 32), c1, k0, 0x96);
         const uint32_t n2 = __builtin_amdgcn_bitop3_b32(static_cast<uint32_t>(p0 >> 32), c3, k1, 0x96);
         c1 = static_cast<uint32_t>(p1);
@@ -95,6 +158,16 @@ __device__ __forceinline__ Block4<float> normals_block<float>(uint32_t block, ui
                                                               uint32_t k0, uint32_t k1)
 {
     const Words4 x = philox4x32_10(block, epoch, rep, dom, k0, k1);
+    const Pair32 a = box_muller_scaled(x.x0, x.x1);
+    const Pair32 b = box_muller_scaled(x.x2, x.x3);
+    return Block4<float>{{a.c, a.s, b.c, b.s}};
+}
+
+// Block b of the stream of row (e, r), binary32.
+__device__ __forceinline__ Block4<float> normals_block_row(const PhiloxRow &row, uint32_t block, uint32_t dom,
+                                                           uint32_t k0, uint32_t k1)
+{
+    const Words4 x = philox_block(row, block, dom, k0, k1);
     const Pair32 a = box_muller_scaled(x.x0, x.x1);
     const Pair32 b = box_muller_scaled(x.x2, x.x3);
     return Block4<float>{{a.c, a.s, b.c, b.s}};

@@ -24,6 +24,8 @@
 #include "device_rng.hpp"
 #include "sim_types.hpp"
 
+#include <type_traits>
+
 namespace fw {
 
 // ---------------------------------------------------------------------------------------------
@@ -57,6 +59,18 @@ struct Coef<double> {
     __device__ double tscale() const { return P->tscale_d; }
     __device__ static double rsqrt(double x) { return 1.0 / sqrt(x); }
 };
+
+// Block `block` of the noise stream (epoch, r): binary32 starts from the stream's Philox row,
+// binary64 runs the whole generator.
+template <typename Real>
+__device__ __forceinline__ Block4<Real> block_of_row(const PhiloxRow &row, uint32_t block, uint32_t epoch,
+                                                     uint32_t r, uint32_t dom, uint32_t k0, uint32_t k1)
+{
+    if constexpr (std::is_same<Real, float>::value)
+        return normals_block_row(row, block, dom, k0, k1);
+    else
+        return normals_block<Real>(block, epoch, r, dom, k0, k1);
+}
 
 constexpr int gcd_const(int a, int b) { return b == 0 ? a : gcd_const(b, a % b); }
 
@@ -124,13 +138,19 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
         const Real cwr = static_cast<Real>(cw);
         Real v[D], s1[D], s2[D];
         Real g1[D];          // FEAT with t noise: sum of the Gaussian numerators
+        // w_t = cw S except at t = 0 with a given start point (S = 0 and cw = 0 there, so the
+        // origin needs no special case); one uniform branch instead of a select per asset
+        const bool from_w0 = (t == 0) && P->has_w0;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-            const Real w = (t == 0) ? (P->has_w0 ? C.w0(j) : Real(0)) : static_cast<Real>(S[j]) * cwr;
-            v[j] = (j < d) ? C.sz(j) * w : Real(0);
+            v[j] = (j < d) ? C.sz(j) * (static_cast<Real>(S[j]) * cwr) : Real(0);
             s1[j] = Real(0);
             s2[j] = Real(0);
             g1[j] = Real(0);
+        }
+        if (from_w0) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) v[j] = (j < d) ? C.sz(j) * C.w0(j) : Real(0);
         }
         const bool feat_epoch = FEAT && m_in_epoch == 0;   // draws repeat within an epoch
 
@@ -140,11 +160,13 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
             constexpr int NZ = G * D;
             constexpr int NB = NZ / 4;
             const uint32_t full = N / G, rem = N % G;
+            PhiloxRow row{};
+            if constexpr (std::is_same<Real, float>::value) row = philox_row(epoch, r, k0);
             for (uint32_t gi = 0; gi < full; ++gi) {
                 Real z[NZ];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    const Block4<Real> q = normals_block<Real>(gi * NB + b, epoch, r, dom, k0, k1);
+                    const Block4<Real> q = block_of_row<Real>(row, gi * NB + b, epoch, r, dom, k0, k1);
                     z[4 * b + 0] = q.z[0];
                     z[4 * b + 1] = q.z[1];
                     z[4 * b + 2] = q.z[2];
@@ -168,7 +190,7 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     if (static_cast<uint32_t>(b) < nb_needed) {
-                        const Block4<Real> q = normals_block<Real>(full * NB + b, epoch, r, dom, k0, k1);
+                        const Block4<Real> q = block_of_row<Real>(row, full * NB + b, epoch, r, dom, k0, k1);
                         z[4 * b + 0] = q.z[0];
                         z[4 * b + 1] = q.z[1];
                         z[4 * b + 2] = q.z[2];
@@ -260,17 +282,25 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
         Real gmin = Real(0);
         int jmin = -1;
         Real gw = Real(0);
+        Real gv[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
+            gv[j] = Real(0);
             if (j < d) {
                 const Real g = C.c2(j) * (s2[j] - s1[j] * qn) - C.mu(j) - C.c1(j) * s1[j];
                 if (jmin < 0 || g < gmin) {
                     gmin = g;
                     jmin = j;
                 }
-                const Real w = (t == 0) ? (P->has_w0 ? C.w0(j) : Real(0)) : static_cast<Real>(S[j]) * cwr;
-                gw = fma(g, w, gw);
+                gv[j] = g;
+                gw = fma(g, static_cast<Real>(S[j]) * cwr, gw);
             }
+        }
+        if (from_w0) {
+            gw = Real(0);
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+                if (j < d) gw = fma(gv[j], C.w0(j), gw);
         }
         const int a = (gmin < Real(0)) ? jmin + 1 : 0;
         const Real gap = gw - (gmin < Real(0) ? gmin : Real(0));

@@ -113,3 +113,37 @@ extern "C" int emu_batch_paths(uint32_t i, sim_path_view *out, uint32_t *P, uint
     *nt = g_plan.tiles_of[i];
     return 0;
 }
+
+// Philox4x32-10 started from a stream's row (philox_row / philox_block) against the generator run
+// in full, on n counters from a SplitMix64 sequence; returns the number of differing words.
+extern "C" int emu_philox_row_check(uint64_t seed, int n)
+{
+    uint64_t x = seed;
+    auto next = [&x]() {
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    int bad = 0;
+    for (int i = 0; i < n; ++i) {
+        const uint64_t a = next(), b = next(), c = next();
+        const uint32_t blk = (uint32_t)a, e = (uint32_t)(a >> 32), r = (uint32_t)b, s = (uint32_t)(b >> 32);
+        const uint32_t k0 = (uint32_t)c, k1 = (uint32_t)(c >> 32);
+        const Words4 full = philox4x32_10(blk, e, r, s, k0, k1);
+        const Words4 fast = philox_block(philox_row(e, r, k0), blk, s, k0, k1);
+        bad += (full.x0 != fast.x0) + (full.x1 != fast.x1) + (full.x2 != fast.x2) + (full.x3 != fast.x3);
+    }
+    return bad;
+}
+
+// The device generator for one counter and key, for comparison with the oracle's.
+extern "C" void emu_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out)
+{
+    const Words4 w = philox4x32_10(ctr[0], ctr[1], ctr[2], ctr[3], key[0], key[1]);
+    out[0] = w.x0;
+    out[1] = w.x1;
+    out[2] = w.x2;
+    out[3] = w.x3;
+}

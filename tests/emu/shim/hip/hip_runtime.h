@@ -82,6 +82,9 @@ inline float __builtin_amdgcn_cosf(float x) { return (float)std::cos(6.283185307
 inline float __builtin_amdgcn_sinf(float x) { return (float)std::sin(6.283185307179586 * x); }
 inline float __builtin_amdgcn_rsqf(float x) { return 1.0f / std::sqrt(x); }
 // three-input bitwise function given by its 8-entry truth table, row index 4 a + 2 b + c
+// register pinning is an optimiser hint on the device; nothing to do on the host
+#define FW_PIN_VGPR(x) ((void)(x))
+
 inline uint32_t __builtin_amdgcn_bitop3_b32(uint32_t a, uint32_t b, uint32_t c, uint32_t lut)
 {
     uint32_t r = 0;

@@ -47,6 +47,8 @@ def emu():
                                 ctypes.POINTER(ctypes.c_uint64), ctypes.c_uint64,
                                 ctypes.POINTER(sim.SimBatchConfig), ctypes.c_int]
     L.emu_batch_stats.argtypes = [ctypes.c_uint32, ctypes.POINTER(sim.SimStats)]
+    L.emu_philox_row_check.argtypes = [ctypes.c_uint64, ctypes.c_int]
+    L.emu_philox.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
     L.emu_batch_paths.argtypes = [ctypes.c_uint32, ctypes.POINTER(sim.SimPathView),
                                   ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)]
     yield L
@@ -95,6 +97,21 @@ def test_tile_kernels_match_oracle(emu):
         for r in range(R[i]):
             outs[r] = parity.check_rep(op, g, r, T[i], oracle.U32, decisions=g["decisions"][:, r])
         parity.check_stats(st, op.reduce(outs, T[i]), len(p.checkpoints), len(p.mu), g["tau"])
+
+
+def test_philox_row_equals_full_generator(emu):
+    """The per-stream shortcut of the device generator (rounds 1-2 shared by the blocks of one
+    (epoch, replication) row) gives the words of Philox4x32-10 run in full, and the full device
+    generator gives the oracle's words."""
+    assert emu.emu_philox_row_check(12345, 200000) == 0
+    assert emu.emu_philox_row_check(2**64 - 99, 200000) == 0
+    rng = np.random.default_rng(7)
+    for _ in range(200):
+        ctr = [int(v) for v in rng.integers(0, 2**32, 4)]
+        key = [int(v) for v in rng.integers(0, 2**32, 2)]
+        out = (ctypes.c_uint32 * 4)()
+        emu.emu_philox((ctypes.c_uint32 * 4)(*ctr), (ctypes.c_uint32 * 2)(*key), out)
+        assert list(out) == list(oracle.philox(ctr, key))
 
 
 def test_plan_without_device():
