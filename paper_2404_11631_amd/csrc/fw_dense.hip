@@ -43,6 +43,19 @@ __device__ __forceinline__ V rep_sum(V x)
     return x;
 }
 
+// Binary32 form on the gfx950 lane-swap instructions, without a trip through LDS: swapping the
+// upper 32 lanes of one copy of x with the lower 32 of another leaves (x_lo, x_lo) and
+// (x_hi, x_hi), whose sum is x + x[lane ^ 32] in every lane; the 16-lane swap does the same for
+// lane ^ 16. Addition is commutative, so all four lanes hold the same bits.
+template <>
+__device__ __forceinline__ float rep_sum<float>(float x)
+{
+    const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = __uint_as_float(h[0]) + __uint_as_float(h[1]);
+    const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+
 // out = A x B over the 16 replications of this wavefront; A (D x D) in MFMA order
 // (A_mfma[(mt * D/4 + kk) * 64 + lane] = A[16 mt + lane mod 16][a(lane / 16, kk)]), read from
 // global memory: every wavefront of the grid reads the same D x D values, which stay in L2.
@@ -153,10 +166,31 @@ void fw_dense_kernel(const InstanceDesc *P, RunBuffers B)
             dense_product<D>(Av, w, v, lane);
         }
 
-        NormalCursor<float> ext;
-        if constexpr (NOISE == 1) ext.seek(N * static_cast<uint32_t>(D), epoch, r, dom, k0, k1);
+        // t noise: the chi-square normals of sample i are normals N D + nu i + q, q < nu. In each group
+        // of 16 samples lane p draws those of samples 16g + 4p .. 16g + 4p + 3 (nu whole Philox blocks
+        // from N D + nu (16g + 4p)), once for the replication instead of once per lane, and sample i
+        // takes its scale from lane (i mod 16) div 4 of the replication.
+        float a_own[4] = {1.0f, 1.0f, 1.0f, 1.0f};
 #pragma unroll 1
         for (uint32_t i = 0; i < N; ++i) {
+            if constexpr (NOISE == 1) {
+                if ((i & 15u) == 0u) {
+                    const uint32_t nu = P->nu;
+                    NormalCursor<float> chi;
+                    chi.seek(N * static_cast<uint32_t>(D) + nu * (i + 4u * static_cast<uint32_t>(p)), epoch, r, dom,
+                             k0, k1);
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) {
+                        float ss = 0.0f;
+#pragma unroll 1
+                        for (uint32_t q = 0; q < nu; ++q) {
+                            const float e = chi.next(epoch, r, dom, k0, k1);
+                            ss = fmaf(e, e, ss);
+                        }
+                        a_own[s4] = P->tscale_f * __builtin_amdgcn_rsqf(ss);
+                    }
+                }
+            }
             float z[H];
 #pragma unroll
             for (int m = 0; m < H / 4; ++m) {
@@ -170,13 +204,13 @@ void fw_dense_kernel(const InstanceDesc *P, RunBuffers B)
             }
             float a = 1.0f;
             if constexpr (NOISE == 1) {
-                float ss = 0.0f;
-#pragma unroll 1
-                for (uint32_t q = 0; q < P->nu; ++q) {
-                    const float e = ext.next(epoch, r, dom, k0, k1);
-                    ss = fmaf(e, e, ss);
-                }
-                a = P->tscale_f * __builtin_amdgcn_rsqf(ss);
+                // slot i mod 4 is a_own[0] after i mod 4 rotations (all lanes rotate in step)
+                a = __shfl(a_own[0], (lane & 15) + 16 * static_cast<int>((i >> 2) & 3u), 64);
+                const float a0 = a_own[0];
+                a_own[0] = a_own[1];
+                a_own[1] = a_own[2];
+                a_own[2] = a_own[3];
+                a_own[3] = a0;
             }
             float dot = 0.0f;
 #pragma unroll
