@@ -27,8 +27,9 @@ U64 = 2.0 ** -53
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c and cv.c into liboracle.so (plain gcc, no fast-math, no FMA contraction)."""
-    srcs = [os.path.join(HERE, f) for f in ("oracle.c", "cv.c")]
+    """Compile oracle.c, wide.c and cv.c into liboracle.so (plain gcc, no fast-math, no FMA
+    contraction)."""
+    srcs = [os.path.join(HERE, f) for f in ("oracle.c", "wide.c", "cv.c")]
     stale = any(os.path.getmtime(LIB_PATH) < os.path.getmtime(f) for f in srcs) if os.path.exists(LIB_PATH) else True
     if force or stale:
         tmp = LIB_PATH + ".tmp"
@@ -58,6 +59,23 @@ class PathOut(ctypes.Structure):
                 ("identity_err", ctypes.c_double), ("min_margin", ctypes.c_double),
                 ("cv_count", ctypes.c_double * (MAX_D + 1)), ("cv_count1", ctypes.c_double * (MAX_D + 1)),
                 ("cv_amb", ctypes.c_double)]
+
+
+class WideProblem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int64), ("N", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("instance", ctypes.c_uint32), ("n_ckpt", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("lam", ctypes.c_double), ("gap_eps", ctypes.c_double),
+                ("mu", ctypes.POINTER(ctypes.c_double)), ("sigma", ctypes.POINTER(ctypes.c_double)),
+                ("w0", ctypes.POINTER(ctypes.c_double)), ("ckpt", ctypes.c_int64 * MAX_CKPT)]
+
+
+class WideOut(ctypes.Structure):
+    _fields_ = [("y", ctypes.c_double), ("f_ckpt", ctypes.c_double * MAX_CKPT),
+                ("cnt", ctypes.POINTER(ctypes.c_uint32)), ("wsum", ctypes.POINTER(ctypes.c_uint64)),
+                ("tau", ctypes.c_uint32), ("tau_lo", ctypes.c_uint32), ("tau_hi", ctypes.c_uint32),
+                ("pad_", ctypes.c_uint32), ("n_ambiguous", ctypes.c_uint64), ("n_replayed", ctypes.c_uint64),
+                ("n_mismatch", ctypes.c_uint64), ("first_mismatch", ctypes.c_int64),
+                ("identity_err", ctypes.c_double), ("min_margin", ctypes.c_double)]
 
 
 class CvStats(ctypes.Structure):
@@ -122,6 +140,12 @@ def lib():
         L.or_mlp_forward.argtypes = [dp, ctypes.c_int, dp, u64, ctypes.c_int, dp]
         L.or_mlp_grad.argtypes = [dp, ctypes.c_int, dp, dp, u64, ctypes.c_int, dp]
         L.or_mlp_grad.restype = ctypes.c_double
+        L.or_wide_path.argtypes = [ctypes.POINTER(WideProblem), u64, u64, ctypes.POINTER(ctypes.c_uint32),
+                                   ctypes.c_double, ctypes.POINTER(WideOut), ctypes.POINTER(ctypes.c_uint32)]
+        L.or_wide_gradient.argtypes = [ctypes.POINTER(WideProblem), u64, u64, dp, dp, ctypes.c_double, dp]
+        L.or_wide_gradient.restype = None
+        L.or_wide_objective.argtypes = [ctypes.POINTER(WideProblem), dp]
+        L.or_wide_objective.restype = ctypes.c_double
         L.or_cv_beta.argtypes = [dp, dp, u64, dp, dp]
         L.or_cv_estimate.argtypes = [dp, dp, u64, dp, u64, ctypes.c_double, ctypes.POINTER(CvStats)]
         _lib = L
@@ -199,6 +223,62 @@ class OracleProblem:
     def objective(self, w):
         w = np.ascontiguousarray(w, dtype=np.float64)
         return lib().or_objective(ctypes.byref(self.p), _dptr(w))
+
+
+class WideOracle:
+    """Algorithm 1 at the paper's experimental shape (many assets, diagonal Sigma): wide.c."""
+
+    def __init__(self, mu, sigma, *, N, M=1, lam=0.5, w0=None, seed=0, instance=0, ckpt=(), gap_eps=1e-2):
+        self.mu = np.ascontiguousarray(mu, dtype=np.float64)
+        self.sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+        d = self.mu.shape[0]
+        self.w0 = None if w0 is None else np.ascontiguousarray(w0, dtype=np.float64)
+        ck = list(ckpt)
+        if len(ck) > MAX_CKPT:
+            raise ValueError("at most 8 checkpoints")
+        p = WideProblem()
+        p.d, p.N, p.M, p.instance, p.n_ckpt, p.seed = d, N, M, instance, len(ck), seed
+        p.lam, p.gap_eps = lam, gap_eps
+        p.mu, p.sigma = _dptr(self.mu), _dptr(self.sigma)
+        p.w0 = _dptr(self.w0) if self.w0 is not None else ctypes.POINTER(ctypes.c_double)()
+        for i, c in enumerate(ck):
+            p.ckpt[i] = int(c)
+        self.p = p
+        self.d, self.N, self.M, self.ckpt = d, N, M, ck
+
+    def path(self, rep, T, replay=None, uroff=0.0):
+        """One replication: a dict of y, f_ckpt, cnt, wsum, tau (and its bound range), the replay
+        counters, identity_err and the decisions taken."""
+        cnt = np.zeros(self.d + 1, dtype=np.uint32)
+        wsum = np.zeros(self.d, dtype=np.uint64)
+        dec = np.zeros(T, dtype=np.uint32)
+        out = WideOut()
+        out.cnt = cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        out.wsum = wsum.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        rp = None
+        if replay is not None:
+            replay = np.ascontiguousarray(replay, dtype=np.uint32)
+            assert replay.shape[0] >= T
+            rp = replay.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        rc = lib().or_wide_path(ctypes.byref(self.p), rep, T, rp, uroff, ctypes.byref(out),
+                                dec.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+        if rc:
+            raise ValueError("or_wide_path rejected the problem")
+        return dict(y=out.y, f_ckpt=np.array(out.f_ckpt[:len(self.ckpt)]), cnt=cnt, wsum=wsum, tau=out.tau,
+                    tau_lo=out.tau_lo, tau_hi=out.tau_hi, n_ambiguous=out.n_ambiguous,
+                    n_replayed=out.n_replayed, n_mismatch=out.n_mismatch, first_mismatch=out.first_mismatch,
+                    identity_err=out.identity_err, min_margin=out.min_margin, decisions=dec)
+
+    def gradient(self, rep, epoch, w, uroff=0.0):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        g = np.zeros(self.d)
+        b = ctypes.c_double(0.0)
+        lib().or_wide_gradient(ctypes.byref(self.p), rep, epoch, _dptr(w), _dptr(g), uroff, ctypes.byref(b))
+        return g, b.value
+
+    def objective(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        return lib().or_wide_objective(ctypes.byref(self.p), _dptr(w))
 
 
 def philox(ctr, key):

@@ -128,6 +128,45 @@ int or_run_range(const or_problem *p, uint64_t r0, uint64_t r1, uint64_t T, or_p
 void or_reduce(const or_problem *p, uint64_t T, const or_path_out *paths, uint64_t n,
                or_stats *st);
 
+/* ---- Algorithm 1 at the paper's experimental shape (wide.c) ----------------------------
+ * Many assets (Section 4.1: d up to 1e5), diagonal Sigma = diag(sigma^2), Gaussian noise; the
+ * same method and noise streams as or_path, with per-path arrays sized by the caller. */
+typedef struct {
+    int64_t d;              /* assets, >= 1 */
+    int32_t N, M;           /* samples per resample (>= 2), iterations between resamples (>= 1) */
+    uint32_t instance;      /* stream domain, < 2^24 */
+    int32_t n_ckpt;         /* checkpoints, 0..8 */
+    uint64_t seed;          /* Philox key */
+    double lambda, gap_eps;
+    const double *mu;       /* [d] */
+    const double *sigma;    /* [d] */
+    const double *w0;       /* [d] or NULL */
+    int64_t ckpt[OR_MAX_CKPT];
+} or_wide_problem;
+
+typedef struct {
+    double y;
+    double f_ckpt[OR_MAX_CKPT];
+    uint32_t *cnt;          /* caller-allocated [d+1]: [0] origin, [j+1] vertex e_j */
+    uint64_t *wsum;         /* caller-allocated [d]: sum of (t+1) over the steps choosing e_j */
+    uint32_t tau, tau_lo, tau_hi;
+    uint32_t pad_;
+    uint64_t n_ambiguous, n_replayed, n_mismatch;
+    int64_t first_mismatch;
+    double identity_err, min_margin;
+} or_wide_out;
+
+/* One replication (see or_path for replay, uroff and decisions; decisions here are 32-bit). */
+int or_wide_path(const or_wide_problem *p, uint64_t rep, uint64_t T, const uint32_t *replay, double uroff,
+                 or_wide_out *out, uint32_t *decisions);
+
+/* The sample gradient of (rep, epoch) at w, and the rounding bound of a system with unit
+ * roundoff uroff at that point (NULL to skip). */
+void or_wide_gradient(const or_wide_problem *p, uint64_t rep, uint64_t epoch, const double *w, double *g,
+                      double uroff, double *bound);
+
+double or_wide_objective(const or_wide_problem *p, const double *w);
+
 /* ---- control-variate pieces (cv.c) ------------------------------------------------------ */
 
 typedef struct {
