@@ -42,6 +42,9 @@ extern "C" {
 #define SIM_MAX_D 64u          /* assets per instance */
 #define SIM_MAX_CKPT 8u        /* checkpoints per run */
 #define SIM_TAU_NONE 0xFFFFFFFFu
+#define SIM_WIDE_MAX_D 4194304u    /* assets per instance on the wide path (sim_run_wide) */
+#define SIM_WIDE_MAX_R 64u         /* replications per wide run */
+#define SIM_WIDE_MAX_N 1024u       /* samples per resample on the wide path */
 
 typedef struct sim_ctx sim_ctx;
 
@@ -282,6 +285,42 @@ int sim_cv_aux_draws(sim_ctx *ctx, const sim_params *p, uint64_t T, uint64_t see
  * device: probs [d+1] (0 origin, j+1 vertex e_j), S2 and S4 (may be NULL). Returns 0 or the code
  * sim_run with SIM_CV_FEATURES would return. */
 int sim_cv_law(const sim_params *p, uint64_t T, double *probs, double *S2, double *S4, char *msg, size_t len);
+
+/* ---- Algorithm 1 at the paper's experimental shape -------------------------------------------
+ * Section 4.1 runs Algorithm 1 on a single replication of an instance with many assets: d from 5e2
+ * to 1e5, N = 25 (50 at d = 1e5) samples per gradient, K = 1500 iterations, mu_j ~ U(-1,1),
+ * sigma_j ~ U(0, 0.025), Sigma diagonal. The wide path runs that shape with the parallelism inside a
+ * replication: each iteration is four launches (samples and their dot products with v = sigma .* w,
+ * the cross-workgroup sums, the gradient of Eq. (4)-(5) with the per-workgroup vertex search, and
+ * the global vertex with the update), all sums in a fixed order. The noise is the stream of sim_run:
+ * standard normal i d + j of (replication, epoch) for sample i and asset j.
+ * Supported: 4 <= d <= SIM_WIDE_MAX_D with d a multiple of 4, diagonal Sigma (chol NULL), Gaussian
+ * noise, FP32 state, 2 <= N <= SIM_WIDE_MAX_N, any M, 1 <= R <= SIM_WIDE_MAX_R, R T <= 2^30; flags
+ * may hold SIM_KEEP_PATHS and SIM_DECISION_LOG, and the run keeps every per-path record and
+ * decision either way. Asynchronous on the context's stream; the host enqueues 4 T (+ checkpoint)
+ * launches before returning. */
+int sim_run_wide(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed);
+
+/* Checks a parameter set exactly as sim_run_wide does, without a device. */
+int sim_validate_wide(const sim_params *p, uint64_t R, uint64_t T, char *msg, size_t len);
+
+/* Statistics of the last wide run (as sim_stats; decision_total holds only the origin's total, the
+ * per-asset counts are in sim_wide_paths); synchronises the stream. */
+int sim_wide_stats(sim_ctx *ctx, sim_stats_out *out);
+
+/* Device pointers (owned by the context) to the records of the last wide run, replication-major. */
+typedef struct {
+    uint64_t R, T;
+    uint32_t d, n_checkpoints;
+    const double *y;            /* [R] f(w_T) */
+    const double *f_ckpt;       /* [n_checkpoints][R] */
+    const uint32_t *cnt;        /* [R][d+1] decision counts, origin first */
+    const uint64_t *wsum;       /* [R][d] sum of (t+1) over the steps choosing e_j */
+    const uint32_t *tau;        /* [R] hitting step or SIM_TAU_NONE */
+    const uint32_t *decisions;  /* [R][T] decisions, 0 = origin, j+1 = e_j */
+} sim_wide_view;
+
+int sim_wide_paths(sim_ctx *ctx, sim_wide_view *out);
 
 /* Statistics of the last run; synchronises the stream. */
 int sim_stats(sim_ctx *ctx, sim_stats_out *out);

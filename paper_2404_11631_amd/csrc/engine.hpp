@@ -60,6 +60,18 @@ struct CvState {
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev_a = nullptr, ev_b = nullptr;
 };
 
+// Buffers and description of the last wide run (sim_run_wide).
+struct WideState {
+    bool have = false;
+    sim_params params{};                  // pointers cleared
+    uint64_t R = 0, T = 0;
+    uint32_t nwg = 0;
+    double fstar = 0.0;
+    DevBuf asset_f, asset_d, S, cnt, tau, dec, s1, part_dot, part_qn, dot, qn, wg_g, wg_j, wg_gw, fval,
+        stats, origin;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
 struct sim_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -80,6 +92,7 @@ struct sim_ctx {
     int kernel_width = 0;
     BatchState batch;
     CvState cv;
+    WideState wide;
 };
 
 

@@ -110,6 +110,52 @@ int validate(char *err, const sim_params *p, uint64_t R, uint64_t T)
     return SIM_OK;
 }
 
+int validate_wide(char *err, const sim_params *p, uint64_t R, uint64_t T)
+{
+    if (!p) return fail(err, SIM_EINVAL, "params is NULL");
+    if (p->abi_version != SIM_ABI_VERSION)
+        return fail(err, SIM_EINVAL, "abi_version %u != %u", p->abi_version, SIM_ABI_VERSION);
+    if (p->d < 4 || p->d > SIM_WIDE_MAX_D || p->d % 4 != 0)
+        return fail(err, SIM_EINVAL, "d=%u: the wide path needs a multiple of 4 in [4, %u]", p->d, SIM_WIDE_MAX_D);
+    if (R < 1 || R > SIM_WIDE_MAX_R)
+        return fail(err, SIM_EINVAL, "R=%llu outside [1, %u]", (unsigned long long)R, SIM_WIDE_MAX_R);
+    if (T < 1 || T > 0xFFFFFFFEull) return fail(err, SIM_EINVAL, "T=%llu outside [1, 2^32-2]", (unsigned long long)T);
+    if (R * T > (1ull << 30)) return fail(err, SIM_EINVAL, "R T above 2^30 (the decision record)");
+    if (p->chol) return fail(err, SIM_EUNSUPPORTED, "the wide path takes a diagonal Sigma (chol must be NULL)");
+    if (!p->mu || !p->sigma) return fail(err, SIM_EINVAL, "mu and sigma are required");
+    for (uint32_t j = 0; j < p->d; ++j) {
+        if (!finite(p->mu[j])) return fail(err, SIM_EINVAL, "mu[%u] not finite", j);
+        if (!finite(p->sigma[j]) || p->sigma[j] < 0.0) return fail(err, SIM_EINVAL, "sigma[%u] must be finite and >= 0", j);
+    }
+    if (!(p->risk_coef > 0.0) || !finite(p->risk_coef))
+        return fail(err, SIM_EINVAL, "risk_coef must be finite and > 0");
+    if (p->w0) {
+        double s = 0.0;
+        for (uint32_t j = 0; j < p->d; ++j) {
+            if (!finite(p->w0[j]) || p->w0[j] < 0.0) return fail(err, SIM_EINVAL, "w0[%u] outside W", j);
+            s += p->w0[j];
+        }
+        if (s > 1.0 + 1e-12) return fail(err, SIM_EINVAL, "w0 sums to %g > 1", s);
+    }
+    if (p->n_samples < 2 || p->n_samples > SIM_WIDE_MAX_N)
+        return fail(err, SIM_EINVAL, "n_samples must be in [2, %u]", SIM_WIDE_MAX_N);
+    if (p->resample_every < 1) return fail(err, SIM_EINVAL, "resample_every must be >= 1");
+    if (p->noise != SIM_NOISE_GAUSS) return fail(err, SIM_EUNSUPPORTED, "the wide path draws Gaussian noise only");
+    if (p->state_precision != SIM_FP32) return fail(err, SIM_EUNSUPPORTED, "the wide path runs in FP32 state");
+    if (p->n_checkpoints > SIM_MAX_CKPT) return fail(err, SIM_EINVAL, "more than 8 checkpoints");
+    for (uint32_t k = 0; k < p->n_checkpoints; ++k) {
+        if (p->checkpoints[k] < 1 || p->checkpoints[k] > T)
+            return fail(err, SIM_EINVAL, "checkpoint %u outside [1, T]", k);
+        if (k && p->checkpoints[k] <= p->checkpoints[k - 1])
+            return fail(err, SIM_EINVAL, "checkpoints must increase strictly");
+    }
+    if (!finite(p->gap_eps) || p->gap_eps < 0.0) return fail(err, SIM_EINVAL, "gap_eps must be finite and >= 0");
+    if (p->flags & ~(uint32_t)(SIM_KEEP_PATHS | SIM_DECISION_LOG))
+        return fail(err, SIM_EINVAL, "the wide path takes no flag but SIM_KEEP_PATHS and SIM_DECISION_LOG");
+    if (p->instance_id >= (1u << 24)) return fail(err, SIM_EINVAL, "instance_id must be < 2^24");
+    return SIM_OK;
+}
+
 void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed)
 {
     std::memset(&D, 0, sizeof(D));

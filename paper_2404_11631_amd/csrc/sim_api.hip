@@ -158,6 +158,12 @@ void sim_destroy(sim_ctx *ctx)
         free_buf(*x);
     for (hipEvent_t e : {cv.ev0, cv.ev1, cv.ev_a, cv.ev_b})
         if (e) (void)hipEventDestroy(e);
+    WideState &wd = ctx->wide;
+    for (DevBuf *x : {&wd.asset_f, &wd.asset_d, &wd.S, &wd.cnt, &wd.tau, &wd.dec, &wd.s1, &wd.part_dot, &wd.part_qn,
+                      &wd.dot, &wd.qn, &wd.wg_g, &wd.wg_j, &wd.wg_gw, &wd.fval, &wd.stats, &wd.origin})
+        free_buf(*x);
+    for (hipEvent_t e : {wd.ev0, wd.ev1})
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 

@@ -1,0 +1,53 @@
+// wide.hpp -- Algorithm 1 at the paper's experimental shape (Section 4.1: d up to 1e5 assets,
+// N = 25-50 samples per gradient, K = 1500 iterations, one or a few replications): the device
+// arguments shared by the kernels (fw_wide.hip) and the host driver (wide_api.hip).
+#pragma once
+
+#include <stdint.h>
+
+namespace fw {
+
+constexpr int kWideBlock = 256;                 // threads per workgroup
+constexpr int kWideChunks = 8;                  // sample chunks per workgroup (i = c, c + 8, ...)
+constexpr int kWideQuads = kWideBlock / kWideChunks;   // asset quads per workgroup (128 assets)
+constexpr uint32_t kWideMaxR = 64;
+constexpr uint32_t kWideMaxN = 1024;
+constexpr uint64_t kWideMaxD = 1ull << 22;
+
+struct WideArgs {
+    // instance: d assets in nq = d/4 quads, nwg workgroups per replication
+    uint32_t d, nq, N, nwg, R;
+    uint32_t k0, k1, dom;                       // Philox key, stream domain (path noise)
+    float inv_n, gap_eps;
+    double lambda;
+    const float *mu_f, *sz_f, *c1_f, *c2_f, *w0_f;   // per asset; sz = sqrt(2 ln 2) sigma
+    const double *mu_d, *sig_d;
+    // state of each replication r
+    uint64_t *S;                                // [R][d] signature: sum of (t+1) over steps choosing e_j
+    uint32_t *cnt;                              // [R][d+1] decision counts, origin first
+    uint32_t *tau;                              // [R] first step with FW gap <= eps
+    uint32_t *dec;                              // [R][T] decisions (0 origin, j+1 vertex e_j)
+    uint64_t T;
+    // per-step scratch
+    float *s1;                                  // [R][d] sum of the step's normals per asset
+    float *part_dot;                            // [R][N][nwg] workgroup partials of z_i'v
+    float *part_qn;                             // [R][nwg] workgroup partials of s1'v
+    float *dot;                                 // [R][N] z_i'v
+    float *qn;                                  // [R] s1'v
+    float *wg_g;                                // [R][nwg] workgroup minimum of the gradient
+    uint32_t *wg_j;                             // [R][nwg] its asset
+    float *wg_gw;                               // [R][nwg] workgroup partial of g'w
+    // outcomes
+    double *fval;                               // [n_ckpt + 1][R] f(w_c) per checkpoint, then f(w_T)
+    double *stats;                              // kMaxStreams x kStreamFields + 2 (min, max of Y)
+    uint64_t *origin_total;                     // [1] decisions for the origin over all replications
+};
+
+// One iteration: w_t = cw S (or w_0 at t = 0 when from_w0), epoch = t div M.
+int launch_wide_step(const WideArgs &A, uint64_t t, uint32_t epoch, float cw, bool from_w0, hipStream_t s);
+// f(w) at w = c S into fval[slot][r].
+int launch_wide_objective(const WideArgs &A, double c, uint32_t slot, hipStream_t s);
+// Cross-replication statistics of Y and of the n_ckpt checkpoints into stats.
+int launch_wide_finalize(const WideArgs &A, uint32_t n_ckpt, hipStream_t s);
+
+}  // namespace fw

@@ -96,6 +96,13 @@ class SimCvView(ctypes.Structure):
                 ("x_aux", ctypes.c_void_p), ("h_aux", ctypes.c_void_p)]
 
 
+class SimWideView(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_uint64), ("T", ctypes.c_uint64), ("d", ctypes.c_uint32),
+                ("n_checkpoints", ctypes.c_uint32), ("y", ctypes.c_void_p), ("f_ckpt", ctypes.c_void_p),
+                ("cnt", ctypes.c_void_p), ("wsum", ctypes.c_void_p), ("tau", ctypes.c_void_p),
+                ("decisions", ctypes.c_void_p)]
+
+
 def mlp_param_count(F: int) -> int:
     return 64 * F + 4289
 
@@ -105,7 +112,7 @@ EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_run_b
            "sim_plan_batch", "sim_batch_stats", "sim_batch_paths", "sim_stats", "sim_paths", "sim_copy_to_host",
            "sim_strerror", "sim_last_error", "sim_destroy", "sim_cv_fit", "sim_run_cv", "sim_cv_paths",
            "sim_mlp_set_params", "sim_mlp_get_params", "sim_mlp_forward", "sim_mlp_grad", "sim_cv_aux_draws",
-           "sim_cv_law")
+           "sim_cv_law", "sim_run_wide", "sim_validate_wide", "sim_wide_stats", "sim_wide_paths")
 
 _lib = None
 
@@ -154,6 +161,10 @@ def load():
         L.sim_mlp_grad.argtypes = [vp, fp, fp, u64, fp, ctypes.POINTER(ctypes.c_double)]
         L.sim_cv_aux_draws.argtypes = [vp, ctypes.POINTER(SimParams), u64, u64, u64, u64, fp]
         L.sim_cv_law.argtypes = [ctypes.POINTER(SimParams), u64, _dp, _dp, _dp, ctypes.c_char_p, ctypes.c_size_t]
+        L.sim_run_wide.argtypes = [vp, ctypes.POINTER(SimParams), u64, u64, u64]
+        L.sim_validate_wide.argtypes = [ctypes.POINTER(SimParams), u64, u64, ctypes.c_char_p, ctypes.c_size_t]
+        L.sim_wide_stats.argtypes = [vp, ctypes.POINTER(SimStats)]
+        L.sim_wide_paths.argtypes = [vp, ctypes.POINTER(SimWideView)]
         _lib = L
     return _lib
 
@@ -191,6 +202,14 @@ def validate(p: Problem, R: int, T: int):
     sp, keep = Sim.params(p)
     buf = ctypes.create_string_buffer(512)
     rc = load().sim_validate(ctypes.byref(sp), R, T, buf, 512)
+    return rc, buf.value.decode()
+
+
+def validate_wide(p: Problem, R: int, T: int):
+    """(code, message) of the checks sim_run_wide applies, without a device."""
+    sp, keep = Sim.params(p)
+    buf = ctypes.create_string_buffer(512)
+    rc = load().sim_validate_wide(ctypes.byref(sp), R, T, buf, 512)
     return rc, buf.value.decode()
 
 
@@ -320,6 +339,32 @@ class Sim:
         st = SimStats()
         self._check(self.L.sim_stats(self.h, ctypes.byref(st)))
         return st
+
+    def run_wide(self, p: Problem, R: int, T: int, seed: int):
+        """Algorithm 1 at the paper's experimental shape (sim_run_wide): many assets, few replications."""
+        sp, keep = self.params(p)
+        self._keep = keep
+        self._check(self.L.sim_run_wide(self.h, ctypes.byref(sp), R, T, seed))
+
+    def wide_stats(self) -> SimStats:
+        st = SimStats()
+        self._check(self.L.sim_wide_stats(self.h, ctypes.byref(st)))
+        return st
+
+    def wide_paths(self) -> dict:
+        """Host copies of the last wide run's records: y [R], f_ckpt [nc][R], cnt [R][d+1], wsum [R][d],
+        tau [R], decisions [R][T]."""
+        v = SimWideView()
+        self._check(self.L.sim_wide_paths(self.h, ctypes.byref(v)))
+        R, T, d, nc = v.R, v.T, v.d, v.n_checkpoints
+        out = dict(R=R, T=T, d=d)
+        out["y"] = self._copy(v.y, np.float64, R)
+        out["f_ckpt"] = self._copy(v.f_ckpt, np.float64, nc * R).reshape(nc, R) if nc else np.zeros((0, R))
+        out["cnt"] = self._copy(v.cnt, np.uint32, R * (d + 1)).reshape(R, d + 1)
+        out["wsum"] = self._copy(v.wsum, np.uint64, R * d).reshape(R, d)
+        out["tau"] = self._copy(v.tau, np.uint32, R)
+        out["decisions"] = self._copy(v.decisions, np.uint32, R * T).reshape(R, T)
+        return out
 
     def _copy(self, ptr, dtype, count):
         out = np.empty(count, dtype=dtype)

@@ -45,7 +45,8 @@ def test_struct_layout_matches_header():
     mirrors = {"sim_params": sim.SimParams, "sim_stats_out": sim.SimStats,
                "sim_path_view": sim.SimPathView, "sim_batch_config": sim.SimBatchConfig,
                "sim_cv_opts": sim.SimCvOpts, "sim_cv_fit_out": sim.SimCvFitOut,
-               "sim_cv_stats_out": sim.SimCvStats, "sim_cv_view": sim.SimCvView}
+               "sim_cv_stats_out": sim.SimCvStats, "sim_cv_view": sim.SimCvView,
+               "sim_wide_view": sim.SimWideView}
     fields = {name: [f[0] for f in cls._fields_] for name, cls in mirrors.items()}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for st, fs in fields.items():
@@ -134,6 +135,29 @@ def test_dense_validation(lib):
 def test_validation_d_range(lib):
     rc, _ = sim.validate(sim.Problem(mu=np.zeros(65), sigma=np.ones(65)), 10, 10)
     assert rc == -1
+
+
+def test_wide_validation(lib):
+    """The wide path (sim_run_wide): d a multiple of 4 up to SIM_WIDE_MAX_D, diagonal Sigma, Gaussian
+    noise, FP32, R <= 64, N <= 1024, R T <= 2^30."""
+    d = 100_000
+    mu, sig = workloads.diag_instance(0, 0, d, "paper")
+    ok = dict(mu=mu, sigma=sig, N=50)
+    assert sim.validate_wide(sim.Problem(**ok), 1, 1500)[0] == 0
+    assert sim.validate_wide(sim.Problem(**ok), 64, 1500)[0] == 0
+    assert sim.validate_wide(sim.Problem(**ok), 65, 10)[0] == -1
+    assert sim.validate_wide(sim.Problem(**ok), 64, 2 ** 25)[0] == -1          # decision record
+    assert sim.validate_wide(sim.Problem(mu=mu[:102], sigma=sig[:102], N=25), 1, 10)[0] == -1
+    assert sim.validate_wide(sim.Problem(mu=mu[:4], sigma=sig[:4], N=2), 1, 10)[0] == 0
+    assert sim.validate_wide(sim.Problem(**ok, noise=sim.NOISE_T), 1, 10)[0] == -5
+    assert sim.validate_wide(sim.Problem(**ok, precision=sim.FP64), 1, 10)[0] == -5
+    assert sim.validate_wide(sim.Problem(mu=mu[:64], chol=np.diag(sig[:64]), N=5), 1, 10)[0] == -5
+    assert sim.validate_wide(sim.Problem(mu=mu, sigma=sig, N=1025), 1, 10)[0] == -1
+    assert sim.validate_wide(sim.Problem(**ok, cv_features=True), 1, 10)[0] == -1
+    neg = sig.copy()
+    neg[7] = -1.0
+    assert sim.validate_wide(sim.Problem(mu=mu, sigma=neg, N=50), 1, 10)[0] == -1
+    assert sim.validate_wide(sim.Problem(**ok, checkpoints=(10, 5)), 1, 20)[0] == -1
 
 
 def test_create_without_gpu_fails_cleanly(lib):
