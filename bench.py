@@ -7,8 +7,13 @@ fused with its cross-path reduction, followed by sim_stats; every step draws fre
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--cpu-seconds 20] [--no-cpu-baseline]
 
+The line also carries the control-variate leg ("cv", skip with --no-cv) and the sweep over the
+Section 4.1 shape ("paper_shape", skip with --no-paper-shape).
+
 Other measurements (not the headline line):
     --workload stress [--reps R]   the dense-L, t(3) stress workload (d = 64, N = 100, T = 1e3)
+    --workload paper_shape         Section 4.1's shape alone: one replication, d = 5e2 .. 1e5,
+                                   K = 1500, on the wide path (--steps runs per size)
     --copy-probe BYTES             one plain device-to-device copy of BYTES, for calibrating the
                                    FETCH_SIZE / WRITE_SIZE counters against known traffic
 """
@@ -125,7 +130,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="paper_scale", choices=("paper_scale", "stress"))
+    ap.add_argument("--workload", default="paper_scale", choices=("paper_scale", "stress", "paper_shape"))
+    ap.add_argument("--no-paper-shape", action="store_true", help="skip the Section 4.1 shape sweep")
     ap.add_argument("--reps", type=int, default=0, help="replications (stress only; 0: the full 1e7)")
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--no-cv", action="store_true", help="skip the control-variate leg")
@@ -142,6 +148,16 @@ def main():
         return
     if args.workload == "stress":
         stress(args)
+        return
+    if args.workload == "paper_shape":
+        import torch
+
+        from paper_2404_11631_amd import sim
+
+        torch.cuda.init()
+        ctx = sim.Sim(0, torch.cuda.current_stream().cuda_stream)
+        print(json.dumps(paper_shape_leg(ctx, sim, max(1, args.steps), args.warmup)), flush=True)
+        ctx.close()
         return
 
     import torch
@@ -170,6 +186,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     cv = None if args.no_cv else cv_leg(ctx, sim, w, mu, sigma, args)
+    shape = None if args.no_paper_shape else paper_shape_leg(ctx, sim, 2, 1)
     ctx.close()
 
     ms_step = 1e3 * wall / args.steps
@@ -199,6 +216,8 @@ def main():
     }
     if cv is not None:
         line["cv"] = cv
+    if shape is not None:
+        line["paper_shape"] = shape
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, mu, sigma, args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -276,6 +295,43 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
         })
         print(f"[cv] h={h:.2e}: plain R={r_plain} {plain_pilot_s + plain_s:.3f} s, cv R={r_cv} "
               f"{cv_pilot_s + cv_s:.3f} s", file=sys.stderr, flush=True)
+    return out
+
+
+def paper_shape_leg(ctx, sim, runs: int, warmup: int):
+    """Algorithm 1 at the shape of Section 4.1 (Task 1): one replication of d assets, mu ~ U(-1,1),
+    sigma ~ U(0, 0.025), K = 1500 iterations, N = 25 samples per gradient (50 at d = 1e5), on the
+    wide path (sim_run_wide). Per size: device time of the whole run (HIP events around its 4 K
+    launches), the wall time of the call and its statistics read-back, and the ALU roofline of the
+    method's algorithmic work (23 lane-ops per normal, N d normals and ~15 d further operations per
+    iteration; the device draws each normal twice, which is not counted). The paper reports about
+    6 h on a Threadripper 3970X and 1 h on an RTX 3090 for the d = 1e5 run (context, other hardware)."""
+    from paper_2404_11631_amd import workloads
+
+    w = workloads.WORKLOADS["paper_shape"]
+    T, seed = w["T"], w["seed"]
+    out = {"workload": "paper_shape", "T": T, "R": w["R"], "regime": w["regime"], "runs": runs, "sizes": [],
+           "paper_reported_s_at_1e5": {"rtx_3090": 3600, "threadripper_3970x": 21600}}
+    for d in w["sizes"]:
+        N = w["N"][d]
+        mu, sig = workloads.diag_instance(seed, 0, d, w["regime"])
+        p = sim.Problem(mu=mu, sigma=sig, N=N, M=w["M"], checkpoints=w["checkpoints"])
+        for k in range(warmup):
+            ctx.run_wide(p, w["R"], T, seed + 1000 + k)
+            ctx.wide_stats()
+        kms, walls = [], []
+        for k in range(runs):
+            t0 = time.perf_counter()
+            ctx.run_wide(p, w["R"], T, seed + k)
+            st = ctx.wide_stats()
+            walls.append(time.perf_counter() - t0)
+            kms.append(st.kernel_ms)
+        kavg = sum(kms) / len(kms)
+        ops = (23.0 * N * d + 15.0 * d) * T * w["R"]
+        out["sizes"].append({"d": d, "N": N, "device_ms": kavg, "wall_ms": 1e3 * sum(walls) / len(walls),
+                             "iterations_per_s": T / (kavg * 1e-3), "normals_per_s": N * d * T / (kavg * 1e-3),
+                             "alu_frac": ops / (kavg * 1e-3) / PEAK_OPS, "Y": st.mean})
+        print(f"[paper_shape] d={d} N={N}: {kavg:.1f} ms per run", file=sys.stderr, flush=True)
     return out
 
 

@@ -92,4 +92,10 @@ WORKLOADS = {
                             train_pairs=10_000_000, hidden=64, seed=100),
     "stress": dict(R=10_000_000, T=1_000, d=64, N=100, M=1, precision="fp32", noise="t", nu=3,
                    dense=True, checkpoints=(50, 100, 500, 1000), seed=0),
+    # Section 4.1, Task 1: one replication per size, K = 1500 iterations, N = 25 samples per
+    # gradient (50 at d = 1e5), the "paper" parameter regime
+    "paper_shape": dict(R=1, T=1_500, sizes=(500, 5_000, 10_000, 50_000, 100_000),
+                        N={500: 25, 5_000: 25, 10_000: 25, 50_000: 25, 100_000: 50}, M=1,
+                        precision="fp32", noise="gauss", regime="paper",
+                        checkpoints=(50, 100, 500, 1000, 1500), seed=0),
 }
