@@ -152,7 +152,10 @@ int sim_set_stream(sim_ctx *ctx, void *hip_stream);
 
 /* Runs R replications of Algorithm 1 for T iterations (Section 3.1) with noise seed `seed`,
  * fused with the cross-path reduction in one launch. Asynchronous on the context's stream.
- * Ranges: 1 <= R < 2^32, 1 <= T <= 2^32 - 2. */
+ * Ranges: 1 <= R < 2^32, 1 <= T <= 2^32 - 2. One lane (diagonal Sigma) or four lanes (dense L) hold
+ * a replication's state, so the shapes are: diagonal Sigma with d <= 32 in FP32 state or d <= 16 in
+ * FP64; a dense factor with d = 32 or 64, FP32, T <= 65535. Others return SIM_EUNSUPPORTED (many
+ * assets on a few replications: sim_run_wide). */
 int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed);
 
 /* Checks a parameter set exactly as sim_run does, without a device. Returns 0 or the code sim_run

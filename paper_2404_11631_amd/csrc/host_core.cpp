@@ -56,6 +56,11 @@ int validate(char *err, const sim_params *p, uint64_t R, uint64_t T)
         for (uint32_t j = 0; j < p->d; ++j)
             if (!finite(p->sigma[j]) || p->sigma[j] < 0.0)
                 return fail(err, SIM_EINVAL, "sigma[%u] must be finite and >= 0", j);
+        // one lane per replication holds the state of at most 32 (FP32) or 16 (FP64) assets
+        const uint32_t dmax = p->state_precision == SIM_FP64 ? 16u : 32u;
+        if (p->d > dmax)
+            return fail(err, SIM_EUNSUPPORTED, "diagonal Sigma with d=%u: the per-lane kernels hold d <= %u in this "
+                        "precision (sim_run_wide takes many assets on a few replications)", p->d, dmax);
     }
     if (!(p->risk_coef > 0.0) || !finite(p->risk_coef))
         return fail(err, SIM_EINVAL, "risk_coef must be finite and > 0");

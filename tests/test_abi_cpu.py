@@ -135,6 +135,12 @@ def test_dense_validation(lib):
 def test_validation_d_range(lib):
     rc, _ = sim.validate(sim.Problem(mu=np.zeros(65), sigma=np.ones(65)), 10, 10)
     assert rc == -1
+    # per-lane kernels: diagonal d <= 32 in FP32, d <= 16 in FP64
+    assert sim.validate(sim.Problem(mu=np.zeros(32), sigma=np.ones(32)), 10, 10)[0] == 0
+    rc, msg = sim.validate(sim.Problem(mu=np.zeros(33), sigma=np.ones(33)), 10, 10)
+    assert rc == -5 and "sim_run_wide" in msg
+    assert sim.validate(sim.Problem(mu=np.zeros(16), sigma=np.ones(16), precision=sim.FP64), 10, 10)[0] == 0
+    assert sim.validate(sim.Problem(mu=np.zeros(17), sigma=np.ones(17), precision=sim.FP64), 10, 10)[0] == -5
 
 
 def test_wide_validation(lib):
