@@ -27,9 +27,9 @@ U64 = 2.0 ** -53
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c, wide.c and cv.c into liboracle.so (plain gcc, no fast-math, no FMA
-    contraction)."""
-    srcs = [os.path.join(HERE, f) for f in ("oracle.c", "wide.c", "cv.c")]
+    """Compile oracle.c, wide.c, newsvendor.c and cv.c into liboracle.so (plain gcc, no fast-math,
+    no FMA contraction)."""
+    srcs = [os.path.join(HERE, f) for f in ("oracle.c", "wide.c", "newsvendor.c", "cv.c")]
     stale = any(os.path.getmtime(LIB_PATH) < os.path.getmtime(f) for f in srcs) if os.path.exists(LIB_PATH) else True
     if force or stale:
         tmp = LIB_PATH + ".tmp"
@@ -70,6 +70,23 @@ class WideProblem(ctypes.Structure):
 
 
 class WideOut(ctypes.Structure):
+    _fields_ = [("y", ctypes.c_double), ("f_ckpt", ctypes.c_double * MAX_CKPT),
+                ("cnt", ctypes.POINTER(ctypes.c_uint32)), ("wsum", ctypes.POINTER(ctypes.c_uint64)),
+                ("tau", ctypes.c_uint32), ("tau_lo", ctypes.c_uint32), ("tau_hi", ctypes.c_uint32),
+                ("pad_", ctypes.c_uint32), ("n_ambiguous", ctypes.c_uint64), ("n_replayed", ctypes.c_uint64),
+                ("n_mismatch", ctypes.c_uint64), ("first_mismatch", ctypes.c_int64),
+                ("identity_err", ctypes.c_double), ("min_margin", ctypes.c_double)]
+
+
+class NvProblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("S", ctypes.c_int32), ("M", ctypes.c_int32), ("instance", ctypes.c_uint32),
+                ("n_ckpt", ctypes.c_int32), ("seed", ctypes.c_uint64), ("C", ctypes.c_double),
+                ("gap_eps", ctypes.c_double)] + [(f, ctypes.POINTER(ctypes.c_double)) for f in
+                                                 ("mu", "sigma", "k", "h", "v", "c", "x0")] + \
+               [("ckpt", ctypes.c_int64 * MAX_CKPT)]
+
+
+class NvOut(ctypes.Structure):
     _fields_ = [("y", ctypes.c_double), ("f_ckpt", ctypes.c_double * MAX_CKPT),
                 ("cnt", ctypes.POINTER(ctypes.c_uint32)), ("wsum", ctypes.POINTER(ctypes.c_uint64)),
                 ("tau", ctypes.c_uint32), ("tau_lo", ctypes.c_uint32), ("tau_hi", ctypes.c_uint32),
@@ -146,6 +163,12 @@ def lib():
         L.or_wide_gradient.restype = None
         L.or_wide_objective.argtypes = [ctypes.POINTER(WideProblem), dp]
         L.or_wide_objective.restype = ctypes.c_double
+        L.or_nv_path.argtypes = [ctypes.POINTER(NvProblem), u64, u64, ctypes.POINTER(ctypes.c_uint32),
+                                 ctypes.c_double, ctypes.POINTER(NvOut), ctypes.POINTER(ctypes.c_uint32)]
+        L.or_nv_gradient.argtypes = [ctypes.POINTER(NvProblem), u64, u64, dp, dp, ctypes.POINTER(ctypes.c_uint32)]
+        L.or_nv_gradient.restype = None
+        L.or_nv_cost.argtypes = [ctypes.POINTER(NvProblem), dp]
+        L.or_nv_cost.restype = ctypes.c_double
         L.or_cv_beta.argtypes = [dp, dp, u64, dp, dp]
         L.or_cv_estimate.argtypes = [dp, dp, u64, dp, u64, ctypes.c_double, ctypes.POINTER(CvStats)]
         _lib = L
@@ -279,6 +302,63 @@ class WideOracle:
     def objective(self, w):
         w = np.ascontiguousarray(w, dtype=np.float64)
         return lib().or_wide_objective(ctypes.byref(self.p), _dptr(w))
+
+
+class NvOracle:
+    """Algorithm 2, the multi-product newsvendor with one resource row (newsvendor.c)."""
+
+    FIELDS = ("mu", "sigma", "k", "h", "v", "c")
+
+    def __init__(self, inst: dict, *, S, M=1, x0=None, seed=0, instance=0, ckpt=(), gap_eps=1e-2):
+        self.arrays = {f: np.ascontiguousarray(inst[f], dtype=np.float64) for f in self.FIELDS}
+        n = self.arrays["mu"].shape[0]
+        self.x0 = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+        ck = list(ckpt)
+        if len(ck) > MAX_CKPT:
+            raise ValueError("at most 8 checkpoints")
+        p = NvProblem()
+        p.n, p.S, p.M, p.instance, p.n_ckpt, p.seed = n, S, M, instance, len(ck), seed
+        p.C, p.gap_eps = float(inst["C"]), gap_eps
+        for f in self.FIELDS:
+            setattr(p, f, _dptr(self.arrays[f]))
+        p.x0 = _dptr(self.x0) if self.x0 is not None else ctypes.POINTER(ctypes.c_double)()
+        for i, c in enumerate(ck):
+            p.ckpt[i] = int(c)
+        self.p = p
+        self.n, self.S, self.M, self.ckpt, self.C = n, S, M, ck, float(inst["C"])
+
+    def path(self, rep, T, replay=None, uroff=0.0):
+        cnt = np.zeros(self.n + 1, dtype=np.uint32)
+        wsum = np.zeros(self.n, dtype=np.uint64)
+        dec = np.zeros(T, dtype=np.uint32)
+        out = NvOut()
+        out.cnt = cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        out.wsum = wsum.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        rp = None
+        if replay is not None:
+            replay = np.ascontiguousarray(replay, dtype=np.uint32)
+            assert replay.shape[0] >= T
+            rp = replay.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+        rc = lib().or_nv_path(ctypes.byref(self.p), rep, T, rp, uroff, ctypes.byref(out),
+                              dec.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+        if rc:
+            raise ValueError("or_nv_path rejected the problem")
+        return dict(y=out.y, f_ckpt=np.array(out.f_ckpt[:len(self.ckpt)]), cnt=cnt, wsum=wsum, tau=out.tau,
+                    tau_lo=out.tau_lo, tau_hi=out.tau_hi, n_ambiguous=out.n_ambiguous,
+                    n_replayed=out.n_replayed, n_mismatch=out.n_mismatch, first_mismatch=out.first_mismatch,
+                    identity_err=out.identity_err, min_margin=out.min_margin, decisions=dec)
+
+    def gradient(self, rep, epoch, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        g = np.zeros(self.n)
+        cnt = np.zeros(self.n, dtype=np.uint32)
+        lib().or_nv_gradient(ctypes.byref(self.p), rep, epoch, _dptr(x), _dptr(g),
+                             cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+        return g, cnt
+
+    def cost(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().or_nv_cost(ctypes.byref(self.p), _dptr(x))
 
 
 def philox(ctr, key):

@@ -31,7 +31,7 @@ extern "C" {
 #define OR_TAU_NONE 0xFFFFFFFFu
 
 enum { OR_NOISE_GAUSS = 0, OR_NOISE_T = 1 };
-enum { OR_DOMAIN_PATH = 0, OR_DOMAIN_PARAM = 1, OR_DOMAIN_CV_AUX = 2, OR_DOMAIN_MLP = 3 };
+enum { OR_DOMAIN_PATH = 0, OR_DOMAIN_PARAM = 1, OR_DOMAIN_CV_AUX = 2, OR_DOMAIN_MLP = 3, OR_DOMAIN_NEWSVENDOR = 4 };
 
 /* One instance of problem Eq. (3) plus the sampling knobs of Algorithm 1. */
 typedef struct {
@@ -166,6 +166,46 @@ void or_wide_gradient(const or_wide_problem *p, uint64_t rep, uint64_t epoch, co
                       double uroff, double *bound);
 
 double or_wide_objective(const or_wide_problem *p, const double *w);
+
+/* ---- Algorithm 2: the multi-product newsvendor (newsvendor.c) ---------------------------
+ * Section 3.2: products j with demand N(mu_j, sigma_j^2), costs k_j, h_j, v_j (Eq. (6)), one
+ * resource row c'x <= C with c > 0 (Eq. (7)), gradient estimate Eq. (9) from S demand samples per
+ * product, resampled every M iterations. */
+typedef struct {
+    int64_t n;              /* products */
+    int32_t S, M;           /* samples per product, iterations between resamples */
+    uint32_t instance;      /* stream domain, < 2^24 */
+    int32_t n_ckpt;
+    uint64_t seed;
+    double C, gap_eps;      /* resource level, Frank-Wolfe gap threshold */
+    const double *mu, *sigma, *k, *h, *v, *c;   /* [n] each */
+    const double *x0;       /* [n] starting point in X, or NULL for the origin */
+    int64_t ckpt[OR_MAX_CKPT];
+} or_nv_problem;
+
+typedef struct {
+    double y;               /* f(x_T), Eq. (7) with Eq. (6) in closed form for normal demand */
+    double f_ckpt[OR_MAX_CKPT];
+    uint32_t *cnt;          /* caller-allocated [n+1]: [0] origin, [j+1] vertex (C/c_j) e_j */
+    uint64_t *wsum;         /* caller-allocated [n]: sum of (t+1) over the steps choosing vertex j */
+    uint32_t tau, tau_lo, tau_hi;
+    uint32_t pad_;
+    uint64_t n_ambiguous, n_replayed, n_mismatch;
+    int64_t first_mismatch;
+    double identity_err, min_margin;
+} or_nv_out;
+
+/* One replication of Algorithm 2 (replay, uroff and decisions as in or_path; the bound covers a
+ * system that draws the normals and forms x in binary32). */
+int or_nv_path(const or_nv_problem *p, uint64_t rep, uint64_t T, const uint32_t *replay, double uroff,
+               or_nv_out *out, uint32_t *decisions);
+
+/* Eq. (9) at x for (rep, epoch): the gradient estimate and (count may be NULL) the sample counts. */
+void or_nv_gradient(const or_nv_problem *p, uint64_t rep, uint64_t epoch, const double *x, double *g,
+                    uint32_t *count);
+
+/* f(x) = sum_j f_j(x_j), Eq. (6) in closed form for normal demand. */
+double or_nv_cost(const or_nv_problem *p, const double *x);
 
 /* ---- control-variate pieces (cv.c) ------------------------------------------------------ */
 

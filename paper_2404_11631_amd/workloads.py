@@ -54,6 +54,20 @@ def dense_instance(seed: int, instance: int, d: int, regime: str = "unit"):
     return mu, L
 
 
+def newsvendor_instance(seed: int, instance: int, n: int):
+    """Algorithm 2's products (Section 3.2): demand mu_j ~ U(20, 50), sigma_j ~ U(10, 20) (Section 4.1);
+    the costs and the resource row, which the paper does not give: unit cost k_j ~ U(1, 2), selling
+    value v_j = k_j U(1.5, 3), holding cost h_j = k_j U(0.1, 0.5), one resource row c = k (a budget in
+    money) with level C = 0.5 sum_j k_j mu_j (half of stocking every product at its mean demand)."""
+    g = _rng(seed, instance, 4)
+    mu = g.uniform(20.0, 50.0, n)
+    sigma = g.uniform(10.0, 20.0, n)
+    k = g.uniform(1.0, 2.0, n)
+    v = k * g.uniform(1.5, 3.0, n)
+    h = k * g.uniform(0.1, 0.5, n)
+    return dict(mu=mu, sigma=sigma, k=k, h=h, v=v, c=k.copy(), C=0.5 * float(np.dot(k, mu)))
+
+
 @dataclass
 class BatchInstance:
     instance: int
