@@ -45,6 +45,8 @@ extern "C" {
 #define SIM_WIDE_MAX_D 4194304u    /* assets per instance on the wide path (sim_run_wide) */
 #define SIM_WIDE_MAX_R 64u         /* replications per wide run */
 #define SIM_WIDE_MAX_N 1024u       /* samples per resample on the wide path */
+#define SIM_NV_MAX_N 16777216u     /* products of a newsvendor instance (sim_run_newsvendor) */
+#define SIM_NV_MAX_S 1024u         /* demand samples per product and resample */
 
 typedef struct sim_ctx sim_ctx;
 
@@ -324,6 +326,47 @@ typedef struct {
 } sim_wide_view;
 
 int sim_wide_paths(sim_ctx *ctx, sim_wide_view *out);
+
+/* ---- Algorithm 2: the multi-product newsvendor (Section 3.2, Task 2) -------------------------
+ * Products j = 1..n with demand N(mu_j, sigma_j^2), unit cost k_j, holding cost h_j (negative: a
+ * scrap value) and selling value v_j; cost Eq. (6) f_j(x) = k x + h E(x - xi)^+ + v E(xi - x)^+;
+ * problem Eq. (7) over X = {c'x <= C, x >= 0} (one resource row, c > 0), whose vertices are the
+ * origin and (C/c_j) e_j; gradient Eq. (9): k_j - v_j + (h_j + v_j) #{s : d_j^(s) <= x_j} / S from S
+ * demand samples per product, d_j^(s) = mu_j + sigma_j z with z the standard normal s n + j of the
+ * (replication, epoch) stream in domain 4; Algorithm 2 with the vertex of smallest g_j / c_j when it
+ * is negative (else the origin, lowest index among equal values), step 2/(t+2). Y = f(x_T) and the
+ * checkpoints f(x_c) in FP64 from Eq. (6) in closed form. The parallelism is inside a replication
+ * (a thread per four products), two launches per iteration. */
+typedef struct {
+    uint32_t abi_version;       /* SIM_ABI_VERSION */
+    uint32_t n;                 /* products, a multiple of 4 in [4, SIM_NV_MAX_N] */
+    const double *mu;           /* [n] demand means */
+    const double *sigma;        /* [n] demand standard deviations >= 0 */
+    const double *k;            /* [n] unit costs */
+    const double *h;            /* [n] holding costs per unit */
+    const double *v;            /* [n] selling values per unit */
+    const double *c;            /* [n] resource use per unit, > 0 */
+    double C;                   /* resource level, > 0 */
+    const double *x0;           /* [n] starting point in X, or NULL for the origin */
+    uint32_t n_samples;         /* S: demand samples per product and resample, 1..SIM_NV_MAX_S */
+    uint32_t resample_every;    /* M >= 1 */
+    uint32_t n_checkpoints;     /* 0..SIM_MAX_CKPT */
+    uint32_t instance_id;       /* stream instance, < 2^24 */
+    uint64_t checkpoints[SIM_MAX_CKPT]; /* strictly increasing iterate counts in [1, T] */
+    double gap_eps;             /* Frank-Wolfe gap threshold of tau, >= 0 */
+} sim_nv_params;
+
+/* Runs R replications (1 <= R <= SIM_WIDE_MAX_R, R T <= 2^30) of Algorithm 2 for T iterations with
+ * noise seed `seed`. Asynchronous on the context's stream. Results: sim_nv_stats (f_star NaN,
+ * decision_total holds the origin's total only) and sim_nv_paths (the records of sim_wide_view, with
+ * products in place of assets: cnt [R][n+1], wsum [R][n], x_T = (C/c) .* 2 wsum / (T (T+1))). */
+int sim_run_newsvendor(sim_ctx *ctx, const sim_nv_params *p, uint64_t R, uint64_t T, uint64_t seed);
+
+/* Checks a parameter set exactly as sim_run_newsvendor does, without a device. */
+int sim_validate_newsvendor(const sim_nv_params *p, uint64_t R, uint64_t T, char *msg, size_t len);
+
+int sim_nv_stats(sim_ctx *ctx, sim_stats_out *out);
+int sim_nv_paths(sim_ctx *ctx, sim_wide_view *out);
 
 /* Statistics of the last run; synchronises the stream. */
 int sim_stats(sim_ctx *ctx, sim_stats_out *out);

@@ -72,6 +72,16 @@ struct WideState {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
+// Buffers and description of the last newsvendor run (sim_run_newsvendor).
+struct NvState {
+    bool have = false;
+    sim_nv_params params{};               // pointers cleared
+    uint64_t R = 0, T = 0;
+    uint32_t nwg = 0;
+    DevBuf prod_f, prod_d, S, cnt, tau, dec, wg_r, wg_j, wg_gx, fval, stats, origin;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
 struct sim_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -93,6 +103,7 @@ struct sim_ctx {
     BatchState batch;
     CvState cv;
     WideState wide;
+    NvState nv;
 };
 
 

@@ -1,0 +1,261 @@
+// fw_newsvendor.hip -- Algorithm 2 (Section 3.2, Task 2): the multi-product newsvendor with one
+// resource row c'x <= C, by stochastic Frank-Wolfe, at the paper's shape (Section 4.1: 1e2 to 1e6
+// products, S = 25-50 demand samples per product, K = 1500 iterations, one or a few replications).
+//
+// The gradient is separable (Eq. (8)-(9)): g_j = k_j - v_j + (h_j + v_j) #{s : d_j^(s) <= x_j} / S,
+// so an iteration is two launches:
+//   sample    a thread owns four consecutive products (one Philox block per sample), draws their S
+//             demand samples, counts those at or below x_j -- as standard normals against the
+//             threshold (x_j - mu_j)/sigma_j, in binary32 -- forms g_j and the ratio g_j / c_j, and
+//             the workgroup keeps its smallest ratio (lowest index among equal values) and its part
+//             of g'x;
+//   step      the vertex over all workgroups: (C/c_j) e_j for the smallest ratio when it is negative,
+//             else the origin; the Frank-Wolfe gap g'x - min(0, C min_j g_j/c_j) and tau; the
+//             integer update S_a += t + 1 (x_{t+1} = (C/c) .* 2 S / ((t+1)(t+2)), Algorithm 2's
+//             recurrence in exact arithmetic).
+// The demand normals are standard normal s n + j of the (replication, epoch) stream in domain 4,
+// scaled by 1/sqrt(2 ln 2) like every binary32 normal here; the host folds that into the threshold.
+#include <hip/hip_runtime.h>
+
+#include "device_reduce.hpp"
+#include "device_rng.hpp"
+#include "newsvendor.hpp"
+#include "sim_types.hpp"
+
+namespace fw {
+
+namespace {
+
+// (value, index) minimum over a wavefront, lowest index among equal values; every lane gets it.
+__device__ __forceinline__ void wave_argmin(float &g, uint32_t &j)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const float og = __shfl_xor(g, m, 64);
+        const uint32_t oj = __shfl_xor(j, m, 64);
+        if (og < g || (og == g && oj < j)) {
+            g = og;
+            j = oj;
+        }
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float x)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kNvBlock) void nv_sample_kernel(NvArgs A, uint32_t epoch, float cw, int from_x0)
+{
+    __shared__ float sm_r[kNvBlock / 64], sm_gx[kNvBlock / 64];
+    __shared__ uint32_t sm_j[kNvBlock / 64];
+    const uint32_t tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+    const uint32_t r = blockIdx.y, g = blockIdx.x;
+    const uint32_t q = g * kNvBlock + tid;
+    const bool active = q < A.nq;
+    const uint32_t j0 = 4 * q;
+
+    float x[4], thr[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        x[k] = 0.0f;
+        thr[k] = 0.0f;
+        if (active) {
+            const uint32_t j = j0 + k;
+            x[k] = from_x0 ? A.x0_f[j]
+                           : A.xs_f[j] * (static_cast<float>(static_cast<double>(A.S_sig[static_cast<uint64_t>(r) * A.n + j])) * cw);
+            // sigma_j = 0 stores an infinite scale: the threshold is then +-infinity, and +infinity
+            // (every sample counted) where x_j equals the demand exactly
+            thr[k] = (x[k] - A.mu_f[j]) * A.isk_f[j];
+            if (thr[k] != thr[k]) thr[k] = INFINITY;
+        }
+    }
+    const PhiloxRow row = philox_row(epoch, r, A.k0);
+    uint32_t count[4] = {0u, 0u, 0u, 0u};
+    for (uint32_t s = 0; s < A.S; ++s) {
+        const Block4<float> z = normals_block_row(row, s * A.nq + q, A.dom, A.k0, A.k1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) count[k] += (z.z[k] <= thr[k]) ? 1u : 0u;
+    }
+    float rmin = INFINITY, gx = 0.0f;
+    uint32_t jmin = 0xFFFFFFFFu;
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t j = j0 + k;
+            const float gj = A.a_f[j] + A.b_f[j] * static_cast<float>(count[k]);
+            const float rj = gj * A.ic_f[j];
+            if (rj < rmin) {
+                rmin = rj;
+                jmin = j;
+            }
+            gx = fmaf(gj, x[k], gx);
+        }
+    }
+    wave_argmin(rmin, jmin);
+    gx = wave_sum(gx);
+    if (lane == 0) {
+        sm_r[wave] = rmin;
+        sm_j[wave] = jmin;
+        sm_gx[wave] = gx;
+    }
+    __syncthreads();
+    if (tid == 0) {   // the wavefronts cover ascending product ranges: strict < keeps the lowest index
+        float rm = sm_r[0], gs = sm_gx[0];
+        uint32_t jm = sm_j[0];
+        for (int w = 1; w < kNvBlock / 64; ++w) {
+            if (sm_r[w] < rm) {
+                rm = sm_r[w];
+                jm = sm_j[w];
+            }
+            gs += sm_gx[w];
+        }
+        const uint64_t o = static_cast<uint64_t>(r) * A.nwg + g;
+        A.wg_r[o] = rm;
+        A.wg_j[o] = jm;
+        A.wg_gx[o] = gs;
+    }
+}
+
+// The vertex over the workgroups of replication blockIdx.x, the gap, tau and the update.
+__global__ __launch_bounds__(kNvBlock) void nv_step_kernel(NvArgs A, uint64_t t)
+{
+    __shared__ float smr[kNvBlock], smx[kNvBlock];
+    __shared__ uint32_t smj[kNvBlock];
+    const uint32_t r = blockIdx.x, tid = threadIdx.x;
+    const uint64_t base = static_cast<uint64_t>(r) * A.nwg;
+    float rm = INFINITY, gs = 0.0f;
+    uint32_t jm = 0xFFFFFFFFu;
+    for (uint32_t g = tid; g < A.nwg; g += kNvBlock) {
+        const float x = A.wg_r[base + g];
+        if (x < rm) {
+            rm = x;
+            jm = A.wg_j[base + g];
+        }
+        gs += A.wg_gx[base + g];
+    }
+    smr[tid] = rm;
+    smj[tid] = jm;
+    smx[tid] = gs;
+    __syncthreads();
+    for (int h = kNvBlock / 2; h > 0; h >>= 1) {
+        if (tid < static_cast<uint32_t>(h)) {
+            const float o = smr[tid + h];
+            const uint32_t oj = smj[tid + h];
+            if (o < smr[tid] || (o == smr[tid] && oj < smj[tid])) {
+                smr[tid] = o;
+                smj[tid] = oj;
+            }
+            smx[tid] += smx[tid + h];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const float best = smr[0];
+        const uint32_t a = (best < 0.0f) ? smj[0] + 1u : 0u;
+        const float gap = smx[0] - (best < 0.0f ? A.C * best : 0.0f);
+        if (A.tau[r] == kTauNone && gap <= A.gap_eps) A.tau[r] = static_cast<uint32_t>(t);
+        A.dec[static_cast<uint64_t>(r) * A.T + t] = a;
+        A.cnt[static_cast<uint64_t>(r) * (A.n + 1) + a] += 1u;
+        if (a > 0) A.S_sig[static_cast<uint64_t>(r) * A.n + (a - 1)] += t + 1;
+    }
+}
+
+// f(x) = sum_j k x + h E(x - xi)^+ + v E(xi - x)^+ (Eq. (6), normal demand, closed form) at
+// x = (C/c) .* c S, FP64, one workgroup per replication.
+__global__ __launch_bounds__(kBlock) void nv_cost_kernel(NvArgs A, double c, uint32_t slot)
+{
+    __shared__ double sm[2 * (kBlock / 64)];
+    const uint32_t r = blockIdx.x, tid = threadIdx.x;
+    const uint64_t *S = A.S_sig + static_cast<uint64_t>(r) * A.n;
+    double total = 0.0;
+    for (uint32_t j = tid; j < A.n; j += kBlock) {
+        const double x = A.xs_d[j] * (static_cast<double>(S[j]) * c);
+        const double mu = A.mu_d[j], sg = A.sig_d[j];
+        double over, under;
+        if (sg > 0.0) {
+            const double z = (x - mu) / sg;
+            const double pdf = 0.39894228040143267794 * exp(-0.5 * z * z);
+            const double cdf = 0.5 * erfc(-z * 0.70710678118654752440);
+            const double upper = 0.5 * erfc(z * 0.70710678118654752440);
+            over = sg * (z * cdf + pdf);
+            under = sg * (pdf - z * upper);
+        } else {
+            over = x > mu ? x - mu : 0.0;
+            under = mu > x ? mu - x : 0.0;
+        }
+        total += A.k_d[j] * x + A.h_d[j] * over + A.v_d[j] * under;
+    }
+    double h = total, l = 0.0;
+    block_sum_dd(h, l, sm);
+    if (tid == 0) A.fval[static_cast<uint64_t>(slot) * A.R + r] = h + l;
+}
+
+// Streams of Y, f(x_c) and RSE_c over the replications in order, in the layout of the per-lane
+// kernels (sum hi/lo, squares hi/lo, count), min and max of Y, and the origin's total.
+__global__ void nv_finalize_kernel(NvArgs A, uint32_t n_ckpt)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double *Y = A.fval + static_cast<uint64_t>(n_ckpt) * A.R;
+    const uint32_t n_streams = 1 + 2 * n_ckpt;
+    for (uint32_t s = 0; s < n_streams; ++s) {
+        double h = 0.0, l = 0.0, qh = 0.0, ql = 0.0, n = 0.0;
+        for (uint32_t r = 0; r < A.R; ++r) {
+            double x;
+            if (s == 0) {
+                x = Y[r];
+            } else if (s <= n_ckpt) {
+                x = A.fval[static_cast<uint64_t>(s - 1) * A.R + r];
+            } else {
+                const double f = A.fval[static_cast<uint64_t>(s - 1 - n_ckpt) * A.R + r];
+                if (f == 0.0) continue;
+                const double e = (f - Y[r]) / f;
+                x = e * e;
+            }
+            dd_add(h, l, x, 0.0);
+            dd_add(qh, ql, x * x, fma(x, x, -(x * x)));
+            n += 1.0;
+        }
+        double *o = A.stats + s * kStreamFields;
+        o[0] = h;
+        o[1] = l;
+        o[2] = qh;
+        o[3] = ql;
+        o[4] = n;
+    }
+    double mn = INFINITY, mx = -INFINITY;
+    uint64_t origin = 0;
+    for (uint32_t r = 0; r < A.R; ++r) {
+        mn = fmin(mn, Y[r]);
+        mx = fmax(mx, Y[r]);
+        origin += A.cnt[static_cast<uint64_t>(r) * (A.n + 1)];
+    }
+    A.stats[n_streams * kStreamFields] = mn;
+    A.stats[n_streams * kStreamFields + 1] = mx;
+    *A.origin_total = origin;
+}
+
+int launch_nv_step(const NvArgs &A, uint64_t t, uint32_t epoch, float cw, bool from_x0, hipStream_t s)
+{
+    hipLaunchKernelGGL(nv_sample_kernel, dim3(A.nwg, A.R), dim3(kNvBlock), 0, s, A, epoch, cw, from_x0 ? 1 : 0);
+    hipLaunchKernelGGL(nv_step_kernel, dim3(A.R), dim3(kNvBlock), 0, s, A, t);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_nv_cost(const NvArgs &A, double c, uint32_t slot, hipStream_t s)
+{
+    hipLaunchKernelGGL(nv_cost_kernel, dim3(A.R), dim3(kBlock), 0, s, A, c, slot);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_nv_finalize(const NvArgs &A, uint32_t n_ckpt, hipStream_t s)
+{
+    hipLaunchKernelGGL(nv_finalize_kernel, dim3(1), dim3(64), 0, s, A, n_ckpt);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace fw

@@ -161,6 +161,49 @@ int validate_wide(char *err, const sim_params *p, uint64_t R, uint64_t T)
     return SIM_OK;
 }
 
+int validate_newsvendor(char *err, const sim_nv_params *p, uint64_t R, uint64_t T)
+{
+    if (!p) return fail(err, SIM_EINVAL, "params is NULL");
+    if (p->abi_version != SIM_ABI_VERSION)
+        return fail(err, SIM_EINVAL, "abi_version %u != %u", p->abi_version, SIM_ABI_VERSION);
+    if (p->n < 4 || p->n > SIM_NV_MAX_N || p->n % 4 != 0)
+        return fail(err, SIM_EINVAL, "n=%u: products must be a multiple of 4 in [4, %u]", p->n, SIM_NV_MAX_N);
+    if (R < 1 || R > SIM_WIDE_MAX_R)
+        return fail(err, SIM_EINVAL, "R=%llu outside [1, %u]", (unsigned long long)R, SIM_WIDE_MAX_R);
+    if (T < 1 || T > 0xFFFFFFFEull) return fail(err, SIM_EINVAL, "T=%llu outside [1, 2^32-2]", (unsigned long long)T);
+    if (R * T > (1ull << 30)) return fail(err, SIM_EINVAL, "R T above 2^30 (the decision record)");
+    if (!p->mu || !p->sigma || !p->k || !p->h || !p->v || !p->c)
+        return fail(err, SIM_EINVAL, "mu, sigma, k, h, v and c are required");
+    if (!finite(p->C) || !(p->C > 0.0)) return fail(err, SIM_EINVAL, "C must be finite and > 0");
+    for (uint32_t j = 0; j < p->n; ++j) {
+        if (!finite(p->mu[j]) || !finite(p->k[j]) || !finite(p->h[j]) || !finite(p->v[j]))
+            return fail(err, SIM_EINVAL, "product %u: mu, k, h, v must be finite", j);
+        if (!finite(p->sigma[j]) || p->sigma[j] < 0.0) return fail(err, SIM_EINVAL, "sigma[%u] must be finite and >= 0", j);
+        if (!finite(p->c[j]) || !(p->c[j] > 0.0)) return fail(err, SIM_EINVAL, "c[%u] must be finite and > 0", j);
+    }
+    if (p->x0) {
+        double used = 0.0;
+        for (uint32_t j = 0; j < p->n; ++j) {
+            if (!finite(p->x0[j]) || p->x0[j] < 0.0) return fail(err, SIM_EINVAL, "x0[%u] outside X", j);
+            used += p->c[j] * p->x0[j];
+        }
+        if (used > p->C * (1.0 + 1e-12)) return fail(err, SIM_EINVAL, "x0 uses %g > C", used);
+    }
+    if (p->n_samples < 1 || p->n_samples > SIM_NV_MAX_S)
+        return fail(err, SIM_EINVAL, "n_samples must be in [1, %u]", SIM_NV_MAX_S);
+    if (p->resample_every < 1) return fail(err, SIM_EINVAL, "resample_every must be >= 1");
+    if (p->n_checkpoints > SIM_MAX_CKPT) return fail(err, SIM_EINVAL, "more than 8 checkpoints");
+    for (uint32_t k = 0; k < p->n_checkpoints; ++k) {
+        if (p->checkpoints[k] < 1 || p->checkpoints[k] > T)
+            return fail(err, SIM_EINVAL, "checkpoint %u outside [1, T]", k);
+        if (k && p->checkpoints[k] <= p->checkpoints[k - 1])
+            return fail(err, SIM_EINVAL, "checkpoints must increase strictly");
+    }
+    if (!finite(p->gap_eps) || p->gap_eps < 0.0) return fail(err, SIM_EINVAL, "gap_eps must be finite and >= 0");
+    if (p->instance_id >= (1u << 24)) return fail(err, SIM_EINVAL, "instance_id must be < 2^24");
+    return SIM_OK;
+}
+
 void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed)
 {
     std::memset(&D, 0, sizeof(D));

@@ -1,0 +1,200 @@
+// nv_api.hip -- host side of Algorithm 2 (sim_run_newsvendor): validation, device buffers, the
+// per-iteration launch sequence, and the statistics and records of the last newsvendor run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "engine.hpp"
+#include "newsvendor.hpp"
+
+using namespace fw::host;
+
+namespace {
+
+fw::NvArgs nv_args(NvState &w, const sim_nv_params *p, uint64_t R, uint64_t T, uint64_t seed)
+{
+    fw::NvArgs A{};
+    const uint32_t n = p->n;
+    const size_t N = n;
+    A.n = n;
+    A.nq = n / 4;
+    A.S = p->n_samples;
+    A.nwg = w.nwg;
+    A.R = static_cast<uint32_t>(R);
+    A.k0 = static_cast<uint32_t>(seed);
+    A.k1 = static_cast<uint32_t>(seed >> 32);
+    A.dom = (fw::kNvDomain << 24) | (p->instance_id & 0xFFFFFFu);
+    A.C = static_cast<float>(p->C);
+    A.gap_eps = static_cast<float>(p->gap_eps);
+    const float *f = static_cast<const float *>(w.prod_f.ptr);
+    A.mu_f = f;
+    A.isk_f = f + N;
+    A.a_f = f + 2 * N;
+    A.b_f = f + 3 * N;
+    A.ic_f = f + 4 * N;
+    A.xs_f = f + 5 * N;
+    A.x0_f = f + 6 * N;
+    const double *d = static_cast<const double *>(w.prod_d.ptr);
+    A.mu_d = d;
+    A.sig_d = d + N;
+    A.k_d = d + 2 * N;
+    A.h_d = d + 3 * N;
+    A.v_d = d + 4 * N;
+    A.xs_d = d + 5 * N;
+    A.S_sig = static_cast<uint64_t *>(w.S.ptr);
+    A.cnt = static_cast<uint32_t *>(w.cnt.ptr);
+    A.tau = static_cast<uint32_t *>(w.tau.ptr);
+    A.dec = static_cast<uint32_t *>(w.dec.ptr);
+    A.T = T;
+    A.wg_r = static_cast<float *>(w.wg_r.ptr);
+    A.wg_j = static_cast<uint32_t *>(w.wg_j.ptr);
+    A.wg_gx = static_cast<float *>(w.wg_gx.ptr);
+    A.fval = static_cast<double *>(w.fval.ptr);
+    A.stats = static_cast<double *>(w.stats.ptr);
+    A.origin_total = static_cast<uint64_t *>(w.origin.ptr);
+    return A;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_validate_newsvendor(const sim_nv_params *p, uint64_t R, uint64_t T, char *msg, size_t len)
+{
+    char err[kErrLen] = {0};
+    const int rc = validate_newsvendor(err, p, R, T);
+    if (msg && len) std::snprintf(msg, len, "%s", rc ? err : "");
+    return rc;
+}
+
+int sim_run_newsvendor(sim_ctx *ctx, const sim_nv_params *p, uint64_t R, uint64_t T, uint64_t seed)
+{
+    if (!ctx) return SIM_EINVAL;
+    if (int rc = validate_newsvendor(ctx->err, p, R, T)) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    NvState &w = ctx->nv;
+    w.have = false;
+    if (!w.ev0) HIP_TRY(ctx, hipEventCreate(&w.ev0));
+    if (!w.ev1) HIP_TRY(ctx, hipEventCreate(&w.ev1));
+    const uint32_t n = p->n, nc = p->n_checkpoints;
+    const uint32_t nq = n / 4;
+    w.nwg = (nq + fw::kNvBlock - 1) / fw::kNvBlock;
+    const size_t N = n;
+
+    // per product: binary32 coefficients (the normals carry the factor 1/sqrt(2 ln 2)), binary64 for Eq. (6)
+    const double kappa = fw::kBoxMullerScale;
+    std::vector<float> pf(7 * N);
+    std::vector<double> pd(6 * N);
+    for (size_t j = 0; j < N; ++j) {
+        const double xs = p->C / p->c[j];
+        pf[j] = static_cast<float>(p->mu[j]);
+        pf[N + j] = p->sigma[j] > 0.0 ? static_cast<float>(1.0 / (kappa * p->sigma[j])) : INFINITY;
+        pf[2 * N + j] = static_cast<float>(p->k[j] - p->v[j]);
+        pf[3 * N + j] = static_cast<float>((p->h[j] + p->v[j]) / p->n_samples);
+        pf[4 * N + j] = static_cast<float>(1.0 / p->c[j]);
+        pf[5 * N + j] = static_cast<float>(xs);
+        pf[6 * N + j] = p->x0 ? static_cast<float>(p->x0[j]) : 0.0f;
+        pd[j] = p->mu[j];
+        pd[N + j] = p->sigma[j];
+        pd[2 * N + j] = p->k[j];
+        pd[3 * N + j] = p->h[j];
+        pd[4 * N + j] = p->v[j];
+        pd[5 * N + j] = xs;
+    }
+    int rc;
+    if ((rc = ensure(ctx, w.prod_f, sizeof(float) * pf.size())) || (rc = ensure(ctx, w.prod_d, sizeof(double) * pd.size())) ||
+        (rc = ensure(ctx, w.S, sizeof(uint64_t) * R * N)) || (rc = ensure(ctx, w.cnt, sizeof(uint32_t) * R * (N + 1))) ||
+        (rc = ensure(ctx, w.tau, sizeof(uint32_t) * R)) || (rc = ensure(ctx, w.dec, sizeof(uint32_t) * R * T)) ||
+        (rc = ensure(ctx, w.wg_r, sizeof(float) * R * w.nwg)) || (rc = ensure(ctx, w.wg_j, sizeof(uint32_t) * R * w.nwg)) ||
+        (rc = ensure(ctx, w.wg_gx, sizeof(float) * R * w.nwg)) || (rc = ensure(ctx, w.fval, sizeof(double) * R * (nc + 1))) ||
+        (rc = ensure(ctx, w.stats, sizeof(double) * (fw::kMaxStreams * fw::kStreamFields + 2))) ||
+        (rc = ensure(ctx, w.origin, sizeof(uint64_t))))
+        return rc;
+    hipStream_t st = ctx->stream;
+    HIP_TRY(ctx, hipMemcpyAsync(w.prod_f.ptr, pf.data(), sizeof(float) * pf.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(w.prod_d.ptr, pd.data(), sizeof(double) * pd.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipMemsetAsync(w.S.ptr, 0, sizeof(uint64_t) * R * N, st));
+    HIP_TRY(ctx, hipMemsetAsync(w.cnt.ptr, 0, sizeof(uint32_t) * R * (N + 1), st));
+    HIP_TRY(ctx, hipMemsetAsync(w.tau.ptr, 0xFF, sizeof(uint32_t) * R, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));   // the host vectors must outlive the copies
+
+    const fw::NvArgs A = nv_args(w, p, R, T, seed);
+    const uint64_t M = p->resample_every;
+    HIP_TRY(ctx, hipEventRecord(w.ev0, st));
+    uint32_t ck = 0;
+    for (uint64_t t = 0; t < T; ++t) {
+        const float cw = t == 0 ? 0.0f : static_cast<float>(2.0 / (static_cast<double>(t) * static_cast<double>(t + 1)));
+        if (fw::launch_nv_step(A, t, static_cast<uint32_t>(t / M), cw, t == 0 && p->x0 != nullptr, st))
+            return set_err(ctx, SIM_EDEVICE, "newsvendor step launch failed at t=%llu", (unsigned long long)t);
+        while (ck < nc && p->checkpoints[ck] == t + 1) {
+            const double c = 2.0 / (static_cast<double>(t + 1) * static_cast<double>(t + 2));
+            if (fw::launch_nv_cost(A, c, ck, st)) return set_err(ctx, SIM_EDEVICE, "newsvendor cost launch failed");
+            ++ck;
+        }
+    }
+    if (fw::launch_nv_cost(A, 2.0 / (static_cast<double>(T) * static_cast<double>(T + 1)), nc, st) ||
+        fw::launch_nv_finalize(A, nc, st))
+        return set_err(ctx, SIM_EDEVICE, "newsvendor finalize launch failed");
+    HIP_TRY(ctx, hipEventRecord(w.ev1, st));
+
+    w.params = *p;
+    w.params.mu = w.params.sigma = w.params.k = w.params.h = w.params.v = w.params.c = w.params.x0 = nullptr;
+    w.R = R;
+    w.T = T;
+    w.have = true;
+    return SIM_OK;
+}
+
+int sim_nv_stats(sim_ctx *ctx, sim_stats_out *out)
+{
+    if (!ctx || !out) return SIM_EINVAL;
+    NvState &w = ctx->nv;
+    if (!w.have) return set_err(ctx, SIM_ESTATE, "no newsvendor run yet");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipEventSynchronize(w.ev1));
+    const uint32_t nc = w.params.n_checkpoints, n_streams = 1 + 2 * nc;
+    double F[fw::kMaxStreams * fw::kStreamFields + 2];
+    uint64_t origin = 0;
+    std::vector<uint32_t> tau(w.R);
+    HIP_TRY(ctx, hipMemcpy(F, w.stats.ptr, sizeof(double) * (n_streams * fw::kStreamFields + 2), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(&origin, w.origin.ptr, sizeof(uint64_t), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(tau.data(), w.tau.ptr, sizeof(uint32_t) * w.R, hipMemcpyDeviceToHost));
+    float ms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, w.ev0, w.ev1));
+    uint64_t tc = 0, ts = 0;
+    for (uint32_t x : tau)
+        if (x != SIM_TAU_NONE) {
+            ++tc;
+            ts += x;
+        }
+    fill_stats(out, F, nc, w.params.checkpoints, F[n_streams * fw::kStreamFields], F[n_streams * fw::kStreamFields + 1],
+               &origin, 0, tc, ts, w.R, w.T, NAN, ms, static_cast<double>(w.R) * static_cast<double>(w.T));
+    return SIM_OK;
+}
+
+int sim_nv_paths(sim_ctx *ctx, sim_wide_view *out)
+{
+    if (!ctx || !out) return SIM_EINVAL;
+    NvState &w = ctx->nv;
+    if (!w.have) return set_err(ctx, SIM_ESTATE, "no newsvendor run yet");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipEventSynchronize(w.ev1));
+    std::memset(out, 0, sizeof(*out));
+    out->R = w.R;
+    out->T = w.T;
+    out->d = w.params.n;
+    out->n_checkpoints = w.params.n_checkpoints;
+    const double *fv = static_cast<const double *>(w.fval.ptr);
+    out->y = fv + static_cast<size_t>(w.params.n_checkpoints) * w.R;
+    out->f_ckpt = w.params.n_checkpoints ? fv : nullptr;
+    out->cnt = static_cast<const uint32_t *>(w.cnt.ptr);
+    out->wsum = static_cast<const uint64_t *>(w.S.ptr);
+    out->tau = static_cast<const uint32_t *>(w.tau.ptr);
+    out->decisions = static_cast<const uint32_t *>(w.dec.ptr);
+    return SIM_OK;
+}
+
+}  // extern "C"

@@ -103,6 +103,48 @@ class SimWideView(ctypes.Structure):
                 ("decisions", ctypes.c_void_p)]
 
 
+class SimNvParams(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("n", ctypes.c_uint32)] + \
+               [(f, _dp) for f in ("mu", "sigma", "k", "h", "v", "c")] + \
+               [("C", ctypes.c_double), ("x0", _dp), ("n_samples", ctypes.c_uint32),
+                ("resample_every", ctypes.c_uint32), ("n_checkpoints", ctypes.c_uint32),
+                ("instance_id", ctypes.c_uint32), ("checkpoints", ctypes.c_uint64 * MAX_CKPT),
+                ("gap_eps", ctypes.c_double)]
+
+
+def nv_params(inst: dict, S: int, M: int = 1, x0=None, checkpoints=(), gap_eps: float = 1e-2, instance_id: int = 0):
+    """sim_nv_params over the arrays of a newsvendor instance (dict of mu, sigma, k, h, v, c and C); returns the
+    struct and the arrays it points into."""
+    keep = []
+    sp = SimNvParams()
+    sp.abi_version = ABI_VERSION
+    for f in ("mu", "sigma", "k", "h", "v", "c"):
+        a = np.ascontiguousarray(inst[f], dtype=np.float64)
+        keep.append(a)
+        setattr(sp, f, a.ctypes.data_as(_dp))
+    sp.n = keep[0].shape[0]
+    sp.C = float(inst["C"])
+    if x0 is not None:
+        a = np.ascontiguousarray(x0, dtype=np.float64)
+        keep.append(a)
+        sp.x0 = a.ctypes.data_as(_dp)
+    sp.n_samples, sp.resample_every = S, M
+    sp.n_checkpoints = len(checkpoints)
+    for i, c in enumerate(checkpoints[:MAX_CKPT]):
+        sp.checkpoints[i] = int(c)
+    sp.gap_eps = gap_eps
+    sp.instance_id = instance_id
+    return sp, keep
+
+
+def validate_newsvendor(inst: dict, R: int, T: int, **kw):
+    """(code, message) of the checks sim_run_newsvendor applies, without a device."""
+    sp, keep = nv_params(inst, **kw)
+    buf = ctypes.create_string_buffer(512)
+    rc = load().sim_validate_newsvendor(ctypes.byref(sp), R, T, buf, 512)
+    return rc, buf.value.decode()
+
+
 def mlp_param_count(F: int) -> int:
     return 64 * F + 4289
 
@@ -112,7 +154,8 @@ EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_run_b
            "sim_plan_batch", "sim_batch_stats", "sim_batch_paths", "sim_stats", "sim_paths", "sim_copy_to_host",
            "sim_strerror", "sim_last_error", "sim_destroy", "sim_cv_fit", "sim_run_cv", "sim_cv_paths",
            "sim_mlp_set_params", "sim_mlp_get_params", "sim_mlp_forward", "sim_mlp_grad", "sim_cv_aux_draws",
-           "sim_cv_law", "sim_run_wide", "sim_validate_wide", "sim_wide_stats", "sim_wide_paths")
+           "sim_cv_law", "sim_run_wide", "sim_validate_wide", "sim_wide_stats", "sim_wide_paths",
+           "sim_run_newsvendor", "sim_validate_newsvendor", "sim_nv_stats", "sim_nv_paths")
 
 _lib = None
 
@@ -165,6 +208,10 @@ def load():
         L.sim_validate_wide.argtypes = [ctypes.POINTER(SimParams), u64, u64, ctypes.c_char_p, ctypes.c_size_t]
         L.sim_wide_stats.argtypes = [vp, ctypes.POINTER(SimStats)]
         L.sim_wide_paths.argtypes = [vp, ctypes.POINTER(SimWideView)]
+        L.sim_run_newsvendor.argtypes = [vp, ctypes.POINTER(SimNvParams), u64, u64, u64]
+        L.sim_validate_newsvendor.argtypes = [ctypes.POINTER(SimNvParams), u64, u64, ctypes.c_char_p, ctypes.c_size_t]
+        L.sim_nv_stats.argtypes = [vp, ctypes.POINTER(SimStats)]
+        L.sim_nv_paths.argtypes = [vp, ctypes.POINTER(SimWideView)]
         _lib = L
     return _lib
 
@@ -351,11 +398,31 @@ class Sim:
         self._check(self.L.sim_wide_stats(self.h, ctypes.byref(st)))
         return st
 
+    def run_newsvendor(self, inst: dict, R: int, T: int, seed: int, **kw):
+        """Algorithm 2 (sim_run_newsvendor) on the products of `inst`; kw as nv_params."""
+        sp, keep = nv_params(inst, **kw)
+        self._keep = keep
+        self._check(self.L.sim_run_newsvendor(self.h, ctypes.byref(sp), R, T, seed))
+
+    def nv_stats(self) -> SimStats:
+        st = SimStats()
+        self._check(self.L.sim_nv_stats(self.h, ctypes.byref(st)))
+        return st
+
+    def nv_paths(self) -> dict:
+        """Host copies of the last newsvendor run's records (as wide_paths, products in place of assets)."""
+        v = SimWideView()
+        self._check(self.L.sim_nv_paths(self.h, ctypes.byref(v)))
+        return self._wide_view(v)
+
     def wide_paths(self) -> dict:
         """Host copies of the last wide run's records: y [R], f_ckpt [nc][R], cnt [R][d+1], wsum [R][d],
         tau [R], decisions [R][T]."""
         v = SimWideView()
         self._check(self.L.sim_wide_paths(self.h, ctypes.byref(v)))
+        return self._wide_view(v)
+
+    def _wide_view(self, v) -> dict:
         R, T, d, nc = v.R, v.T, v.d, v.n_checkpoints
         out = dict(R=R, T=T, d=d)
         out["y"] = self._copy(v.y, np.float64, R)

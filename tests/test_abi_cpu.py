@@ -46,7 +46,7 @@ def test_struct_layout_matches_header():
                "sim_path_view": sim.SimPathView, "sim_batch_config": sim.SimBatchConfig,
                "sim_cv_opts": sim.SimCvOpts, "sim_cv_fit_out": sim.SimCvFitOut,
                "sim_cv_stats_out": sim.SimCvStats, "sim_cv_view": sim.SimCvView,
-               "sim_wide_view": sim.SimWideView}
+               "sim_wide_view": sim.SimWideView, "sim_nv_params": sim.SimNvParams}
     fields = {name: [f[0] for f in cls._fields_] for name, cls in mirrors.items()}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for st, fs in fields.items():
@@ -164,6 +164,28 @@ def test_wide_validation(lib):
     neg[7] = -1.0
     assert sim.validate_wide(sim.Problem(mu=mu, sigma=neg, N=50), 1, 10)[0] == -1
     assert sim.validate_wide(sim.Problem(**ok, checkpoints=(10, 5)), 1, 20)[0] == -1
+
+
+def test_newsvendor_validation(lib):
+    """Algorithm 2 (sim_run_newsvendor): n a multiple of 4, c > 0, C > 0, sigma >= 0, x0 in X,
+    1 <= S <= 1024, R <= 64, R T <= 2^30."""
+    inst = workloads.newsvendor_instance(0, 0, 1000)
+    assert sim.validate_newsvendor(inst, 1, 1500, S=25)[0] == 0
+    assert sim.validate_newsvendor(inst, 65, 10, S=25)[0] == -1
+    assert sim.validate_newsvendor(inst, 64, 2 ** 25, S=25)[0] == -1
+    assert sim.validate_newsvendor(dict(inst, C=0.0), 1, 10, S=25)[0] == -1
+    assert sim.validate_newsvendor(inst, 1, 10, S=0)[0] == -1
+    assert sim.validate_newsvendor(inst, 1, 10, S=1025)[0] == -1
+    bad = {f: (inst[f][:998] if f != "C" else inst[f]) for f in inst}
+    assert sim.validate_newsvendor(bad, 1, 10, S=25)[0] == -1            # not a multiple of 4
+    c0 = dict(inst, c=np.where(np.arange(1000) == 3, 0.0, inst["c"]))
+    assert sim.validate_newsvendor(c0, 1, 10, S=25)[0] == -1
+    x0 = np.zeros(1000)
+    x0[5] = 1.01 * inst["C"] / inst["c"][5]
+    assert sim.validate_newsvendor(inst, 1, 10, S=25, x0=x0)[0] == -1     # outside the budget
+    x0[5] = 0.5 * inst["C"] / inst["c"][5]
+    assert sim.validate_newsvendor(inst, 1, 10, S=25, x0=x0)[0] == 0
+    assert sim.validate_newsvendor(inst, 1, 20, S=25, checkpoints=(20, 30))[0] == -1
 
 
 def test_create_without_gpu_fails_cleanly(lib):

@@ -1,0 +1,143 @@
+"""Algorithm 2, the multi-product newsvendor (sim_run_newsvendor), vs the CPU oracle through the C ABI
+(needs an MI355X).
+
+Protocol: the oracle (oracle/newsvendor.c) replays the device's decisions. A decision may differ from
+the oracle's own only where the interval of another vertex's value reaches the chosen one's -- the
+intervals widen by one count wherever a demand sample's normal lies within binary32 reach of the
+threshold (x_j - mu_j)/sigma_j; everywhere else it must be the oracle's vertex. Counts and
+signatures then match exactly, f(x_T) and f(x_c) to 1e-11 relative (Eq. (6) in FP64 from the exact
+signature on both sides), tau inside the bound's range, statistics to 1e-10 / 1e-8. At Section 4.1's
+largest shape (1e6 products, S = 50, K = 1500) the oracle checks sampled iterations.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_11631_amd import sim, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    s = sim.Sim(0)
+    yield s
+    s.close()
+
+
+def close(a, b, rtol, atol):
+    return abs(a - b) <= atol + rtol * abs(b)
+
+
+def run_and_compare(ctx, inst, R, T, seed, S, M=1, x0=None, ckpt=(), instance=0):
+    n = len(inst["mu"])
+    say(f"[nv] n={n} S={S} M={M} x0={x0 is not None} R={R} T={T} seed={seed}")
+    ctx.run_newsvendor(inst, R, T, seed, S=S, M=M, x0=x0, checkpoints=ckpt, instance_id=instance)
+    st = ctx.nv_stats()
+    g = ctx.nv_paths()
+    O = oracle.NvOracle(inst, S=S, M=M, x0=x0, seed=seed, instance=instance, ckpt=ckpt)
+    ys, fcs, replayed = [], [], 0
+    for r in range(R):
+        o = O.path(r, T, replay=g["decisions"][r], uroff=oracle.U32)
+        assert o["n_mismatch"] == 0, f"rep {r}: {o['n_mismatch']} mismatches, first at {o['first_mismatch']}"
+        replayed += o["n_replayed"]
+        assert np.array_equal(g["decisions"][r], o["decisions"])
+        assert np.array_equal(g["cnt"][r], o["cnt"]) and np.array_equal(g["wsum"][r], o["wsum"])
+        assert close(g["y"][r], o["y"], 1e-11, 1e-9), (g["y"][r], o["y"])
+        for c in range(len(ckpt)):
+            assert close(g["f_ckpt"][c, r], o["f_ckpt"][c], 1e-11, 1e-9)
+        assert o["tau_lo"] <= int(g["tau"][r]) <= o["tau_hi"], (g["tau"][r], o["tau_lo"], o["tau_hi"])
+        ys.append(o["y"])
+        fcs.append(o["f_ckpt"])
+    ys = np.array(ys)
+    assert close(st.mean, ys.mean(), 1e-10, 1e-9)
+    if R > 1:
+        assert close(st.var, ys.var(ddof=1), 1e-8, 1e-15 * ys.mean() ** 2)
+    assert st.min == g["y"].min() and st.max == g["y"].max()
+    assert int(g["cnt"].sum()) == R * T and st.decision_total[0] == int(g["cnt"][:, 0].sum())
+    for c in range(len(ckpt)):
+        assert close(st.f_mean[c], np.mean([f[c] for f in fcs]), 1e-10, 1e-9)
+    say(f"[nv] ok, replayed ambiguous decisions: {replayed} of {R * T}; {st.kernel_ms:.2f} ms")
+    return st, g
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=4, S=25, T=120, R=3, ckpt=(1, 120)),
+    dict(n=100, S=25, T=300, R=2, ckpt=(50, 300)),
+    dict(n=1000, S=7, M=3, T=150, R=2, ckpt=(150,)),          # 250 quads: a ragged workgroup
+    dict(n=4096, S=50, T=100, R=1, ckpt=(100,), x0=True),
+    dict(n=20000, S=25, T=60, R=1, ckpt=()),
+])
+def test_newsvendor_against_oracle(ctx, case):
+    c = dict(case)
+    n = c.pop("n")
+    inst = workloads.newsvendor_instance(1, 0, n)
+    x0 = None
+    if c.pop("x0", False):
+        x0 = np.zeros(n)
+        x0[7] = 0.25 * inst["C"] / inst["c"][7]
+        x0[n - 1] = 0.5 * inst["C"] / inst["c"][n - 1]
+    run_and_compare(ctx, inst, c.pop("R"), c.pop("T"), 13, c.pop("S"), M=c.pop("M", 1), x0=x0, ckpt=c.pop("ckpt"))
+
+
+def test_newsvendor_zero_noise(ctx):
+    """sigma = 0: every sample is mu, so the device's counts are exact (all or none) and the path is the
+    oracle's without any ambiguity."""
+    n = 64
+    inst = dict(workloads.newsvendor_instance(2, 0, n), sigma=np.zeros(n))
+    st, g = run_and_compare(ctx, inst, 1, 80, 3, 5, ckpt=(80,))
+    O = oracle.NvOracle(inst, S=5, seed=3)
+    assert O.path(0, 80, uroff=oracle.U32)["n_ambiguous"] == 0
+
+
+def test_newsvendor_deterministic(ctx):
+    inst = workloads.newsvendor_instance(3, 0, 2000)
+    ctx.run_newsvendor(inst, 2, 100, 4, S=25, checkpoints=(100,))
+    a = ctx.nv_paths()
+    ctx.run_newsvendor(inst, 2, 100, 4, S=25, checkpoints=(100,))
+    b = ctx.nv_paths()
+    assert np.array_equal(a["decisions"], b["decisions"]) and np.array_equal(a["y"], b["y"])
+
+
+def test_paper_shape_sampled(ctx):
+    """Section 4.1's largest Task 2 run: 1e6 products, S = 50, K = 1500, mu ~ U(20,50), sigma ~ U(10,20).
+    At sampled iterations the oracle recomputes the gradient at the device's iterate (rebuilt exactly
+    from the device's decisions) and checks the vertex against its own up to count-level ambiguity;
+    f(x_T) against the oracle's cost at the device's final iterate."""
+    n, S, T, seed = 1_000_000, 50, 1500, 0
+    inst = workloads.newsvendor_instance(0, 0, n)
+    say(f"[nv] paper shape n={n} S={S} T={T}")
+    ctx.run_newsvendor(inst, 1, T, seed, S=S, checkpoints=(50, 100, 500, 1000, 1500))
+    st = ctx.nv_stats()
+    g = ctx.nv_paths()
+    say(f"[nv] paper shape: {st.kernel_ms:.1f} ms for {T} iterations, Y = {g['y'][0]:.6f}")
+    dec = g["decisions"][0].astype(np.int64)
+    assert int(g["cnt"].sum()) == T
+    O = oracle.NvOracle(inst, S=S, seed=seed)
+    xs = inst["C"] / inst["c"]
+    Ssig = np.zeros(n)
+    for t in range(T):
+        if t in (0, 1, 2, 10, 100, 777, 1499):
+            x = np.zeros(n) if t == 0 else xs * Ssig * (2.0 / (t * (t + 1.0)))
+            grad, _ = O.gradient(0, t, x)
+            r = grad / inst["c"]
+            a = int(dec[t])
+            best = min(float(r.min()), 0.0)
+            chosen = 0.0 if a == 0 else float(r[a - 1])
+            # one count of slack on the chosen and the best product covers binary32 near-ties
+            slack = 2 * float(np.max((inst["h"] + inst["v"]) / (S * inst["c"])))
+            assert chosen <= best + slack, (t, a, chosen, best)
+            own = int(np.argmin(r)) + 1 if r.min() < 0 else 0
+            say(f"[nv] t={t}: vertex {a}, oracle {own}, value {chosen:.6f}, best {best:.6f}")
+        if dec[t] > 0:
+            Ssig[dec[t] - 1] += t + 1
+    assert np.array_equal(g["wsum"][0].astype(np.float64), Ssig)
+    xT = xs * Ssig * (2.0 / (T * (T + 1.0)))
+    assert close(g["y"][0], O.cost(xT), 1e-11, 1e-9)
