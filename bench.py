@@ -7,13 +7,16 @@ fused with its cross-path reduction, followed by sim_stats; every step draws fre
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--cpu-seconds 20] [--no-cpu-baseline]
 
-The line also carries the control-variate leg ("cv", skip with --no-cv) and the sweep over the
-Section 4.1 shape ("paper_shape", skip with --no-paper-shape).
+The line also carries the control-variate leg ("cv", skip with --no-cv) and the sweeps over the
+Section 4.1 shapes of Task 1 ("paper_shape") and Task 2 ("newsvendor_shape"), skipped with
+--no-paper-shape.
 
 Other measurements (not the headline line):
     --workload stress [--reps R]   the dense-L, t(3) stress workload (d = 64, N = 100, T = 1e3)
     --workload paper_shape         Section 4.1's shape alone: one replication, d = 5e2 .. 1e5,
                                    K = 1500, on the wide path (--steps runs per size)
+    --workload newsvendor_shape    Task 2 (Algorithm 2) at Section 4.1's shape: n = 1e2 .. 1e6
+                                   products, K = 1500
     --copy-probe BYTES             one plain device-to-device copy of BYTES, for calibrating the
                                    FETCH_SIZE / WRITE_SIZE counters against known traffic
 """
@@ -130,8 +133,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="paper_scale", choices=("paper_scale", "stress", "paper_shape"))
-    ap.add_argument("--no-paper-shape", action="store_true", help="skip the Section 4.1 shape sweep")
+    ap.add_argument("--workload", default="paper_scale", choices=("paper_scale", "stress", "paper_shape", "newsvendor_shape"))
+    ap.add_argument("--no-paper-shape", action="store_true", help="skip the Section 4.1 shape sweeps")
     ap.add_argument("--reps", type=int, default=0, help="replications (stress only; 0: the full 1e7)")
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--no-cv", action="store_true", help="skip the control-variate leg")
@@ -149,14 +152,15 @@ def main():
     if args.workload == "stress":
         stress(args)
         return
-    if args.workload == "paper_shape":
+    if args.workload in ("paper_shape", "newsvendor_shape"):
         import torch
 
         from paper_2404_11631_amd import sim
 
         torch.cuda.init()
         ctx = sim.Sim(0, torch.cuda.current_stream().cuda_stream)
-        print(json.dumps(paper_shape_leg(ctx, sim, max(1, args.steps), args.warmup)), flush=True)
+        leg = paper_shape_leg if args.workload == "paper_shape" else newsvendor_shape_leg
+        print(json.dumps(leg(ctx, sim, max(1, args.steps), args.warmup)), flush=True)
         ctx.close()
         return
 
@@ -187,6 +191,7 @@ def main():
     wall = time.perf_counter() - t0
     cv = None if args.no_cv else cv_leg(ctx, sim, w, mu, sigma, args)
     shape = None if args.no_paper_shape else paper_shape_leg(ctx, sim, 2, 1)
+    nv_shape = None if args.no_paper_shape else newsvendor_shape_leg(ctx, sim, 2, 1)
     ctx.close()
 
     ms_step = 1e3 * wall / args.steps
@@ -218,6 +223,8 @@ def main():
         line["cv"] = cv
     if shape is not None:
         line["paper_shape"] = shape
+    if nv_shape is not None:
+        line["newsvendor_shape"] = nv_shape
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, mu, sigma, args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -332,6 +339,41 @@ def paper_shape_leg(ctx, sim, runs: int, warmup: int):
                              "iterations_per_s": T / (kavg * 1e-3), "normals_per_s": N * d * T / (kavg * 1e-3),
                              "alu_frac": ops / (kavg * 1e-3) / PEAK_OPS, "Y": st.mean})
         print(f"[paper_shape] d={d} N={N}: {kavg:.1f} ms per run", file=sys.stderr, flush=True)
+    return out
+
+
+def newsvendor_shape_leg(ctx, sim, runs: int, warmup: int):
+    """Algorithm 2 (Task 2) at the shape of Section 4.1: one replication of n products, K = 1500, S = 25
+    demand samples per product (50 at n = 1e6), mu ~ U(20, 50), sigma ~ U(10, 20), on
+    sim_run_newsvendor. Per size: device time of the run (HIP events around its 2 K launches), the
+    wall time of the call and its read-back, and the sample throughput (S n demand samples per
+    iteration). The gradient is an integer count, so the ALU fraction counts 23 lane-ops per normal and
+    2 per comparison."""
+    from paper_2404_11631_amd import workloads
+
+    w = workloads.WORKLOADS["newsvendor_shape"]
+    T, seed = w["T"], w["seed"]
+    out = {"workload": "newsvendor_shape", "T": T, "R": w["R"], "runs": runs, "sizes": []}
+    for n in w["sizes"]:
+        S = w["S"][n]
+        inst = workloads.newsvendor_instance(seed, 0, n)
+        kw = dict(S=S, M=w["M"], checkpoints=w["checkpoints"])
+        for k in range(warmup):
+            ctx.run_newsvendor(inst, w["R"], T, seed + 1000 + k, **kw)
+            ctx.nv_stats()
+        kms, walls = [], []
+        for k in range(runs):
+            t0 = time.perf_counter()
+            ctx.run_newsvendor(inst, w["R"], T, seed + k, **kw)
+            st = ctx.nv_stats()
+            walls.append(time.perf_counter() - t0)
+            kms.append(st.kernel_ms)
+        kavg = sum(kms) / len(kms)
+        ops = 25.0 * S * n * T * w["R"]
+        out["sizes"].append({"n": n, "S": S, "device_ms": kavg, "wall_ms": 1e3 * sum(walls) / len(walls),
+                             "iterations_per_s": T / (kavg * 1e-3), "samples_per_s": S * n * T / (kavg * 1e-3),
+                             "alu_frac": ops / (kavg * 1e-3) / PEAK_OPS, "Y": st.mean})
+        print(f"[newsvendor_shape] n={n} S={S}: {kavg:.1f} ms per run", file=sys.stderr, flush=True)
     return out
 
 

@@ -166,14 +166,16 @@ __global__ __launch_bounds__(kNvBlock) void nv_step_kernel(NvArgs A, uint64_t t)
 }
 
 // f(x) = sum_j k x + h E(x - xi)^+ + v E(xi - x)^+ (Eq. (6), normal demand, closed form) at
-// x = (C/c) .* c S, FP64, one workgroup per replication.
-__global__ __launch_bounds__(kBlock) void nv_cost_kernel(NvArgs A, double c, uint32_t slot)
+// x = (C/c) .* c S, FP64: workgroup blockIdx.x of replication blockIdx.y sums products
+// [kNvCostChunk blockIdx.x, +kNvCostChunk) into a double-double partial.
+__global__ __launch_bounds__(kBlock) void nv_cost_kernel(NvArgs A, double c)
 {
     __shared__ double sm[2 * (kBlock / 64)];
-    const uint32_t r = blockIdx.x, tid = threadIdx.x;
+    const uint32_t r = blockIdx.y, tid = threadIdx.x;
     const uint64_t *S = A.S_sig + static_cast<uint64_t>(r) * A.n;
+    const uint32_t j1 = min(A.n, (blockIdx.x + 1) * kNvCostChunk);
     double total = 0.0;
-    for (uint32_t j = tid; j < A.n; j += kBlock) {
+    for (uint32_t j = blockIdx.x * kNvCostChunk + tid; j < j1; j += kBlock) {
         const double x = A.xs_d[j] * (static_cast<double>(S[j]) * c);
         const double mu = A.mu_d[j], sg = A.sig_d[j];
         double over, under;
@@ -191,6 +193,24 @@ __global__ __launch_bounds__(kBlock) void nv_cost_kernel(NvArgs A, double c, uin
         total += A.k_d[j] * x + A.h_d[j] * over + A.v_d[j] * under;
     }
     double h = total, l = 0.0;
+    block_sum_dd(h, l, sm);
+    if (tid == 0) {
+        const uint32_t nc = (A.n + kNvCostChunk - 1) / kNvCostChunk;
+        double *o = A.cost_part + 2 * (static_cast<uint64_t>(r) * nc + blockIdx.x);
+        o[0] = h;
+        o[1] = l;
+    }
+}
+
+// The partials of replication blockIdx.x in order, into fval[slot][r].
+__global__ __launch_bounds__(kBlock) void nv_cost_sum_kernel(NvArgs A, uint32_t slot)
+{
+    __shared__ double sm[2 * (kBlock / 64)];
+    const uint32_t r = blockIdx.x, tid = threadIdx.x;
+    const uint32_t nc = (A.n + kNvCostChunk - 1) / kNvCostChunk;
+    const double *p = A.cost_part + 2 * static_cast<uint64_t>(r) * nc;
+    double h = 0.0, l = 0.0;
+    for (uint32_t b = tid; b < nc; b += kBlock) dd_add(h, l, p[2 * b], p[2 * b + 1]);
     block_sum_dd(h, l, sm);
     if (tid == 0) A.fval[static_cast<uint64_t>(slot) * A.R + r] = h + l;
 }
@@ -248,7 +268,9 @@ int launch_nv_step(const NvArgs &A, uint64_t t, uint32_t epoch, float cw, bool f
 
 int launch_nv_cost(const NvArgs &A, double c, uint32_t slot, hipStream_t s)
 {
-    hipLaunchKernelGGL(nv_cost_kernel, dim3(A.R), dim3(kBlock), 0, s, A, c, slot);
+    const uint32_t nc = (A.n + kNvCostChunk - 1) / kNvCostChunk;
+    hipLaunchKernelGGL(nv_cost_kernel, dim3(nc, A.R), dim3(kBlock), 0, s, A, c);
+    hipLaunchKernelGGL(nv_cost_sum_kernel, dim3(A.R), dim3(kBlock), 0, s, A, slot);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

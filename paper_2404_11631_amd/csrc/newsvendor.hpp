@@ -12,6 +12,7 @@ constexpr uint32_t kNvMaxR = 64;
 constexpr uint32_t kNvMaxS = 1024;
 constexpr uint64_t kNvMaxN = 1ull << 24;
 constexpr uint32_t kNvDomain = 4u;              // Philox stream domain of the demand samples
+constexpr uint32_t kNvCostChunk = 4096;         // products per workgroup of the cost evaluation
 
 struct NvArgs {
     uint32_t n, nq, S, nwg, R;                  // products, quads, samples per product, workgroups
@@ -32,6 +33,7 @@ struct NvArgs {
     uint32_t *wg_j;                             // [R][nwg] its product
     float *wg_gx;                               // [R][nwg] the workgroup's part of g'x
     // outcomes
+    double *cost_part;                          // [R][ceil(n / kNvCostChunk)][2] double-double partials
     double *fval;                               // [n_ckpt + 1][R]
     double *stats;                              // kMaxStreams x kStreamFields + 2
     uint64_t *origin_total;

@@ -52,6 +52,7 @@ fw::NvArgs nv_args(NvState &w, const sim_nv_params *p, uint64_t R, uint64_t T, u
     A.wg_r = static_cast<float *>(w.wg_r.ptr);
     A.wg_j = static_cast<uint32_t *>(w.wg_j.ptr);
     A.wg_gx = static_cast<float *>(w.wg_gx.ptr);
+    A.cost_part = static_cast<double *>(w.cost_part.ptr);
     A.fval = static_cast<double *>(w.fval.ptr);
     A.stats = static_cast<double *>(w.stats.ptr);
     A.origin_total = static_cast<uint64_t *>(w.origin.ptr);
@@ -111,7 +112,8 @@ int sim_run_newsvendor(sim_ctx *ctx, const sim_nv_params *p, uint64_t R, uint64_
         (rc = ensure(ctx, w.wg_r, sizeof(float) * R * w.nwg)) || (rc = ensure(ctx, w.wg_j, sizeof(uint32_t) * R * w.nwg)) ||
         (rc = ensure(ctx, w.wg_gx, sizeof(float) * R * w.nwg)) || (rc = ensure(ctx, w.fval, sizeof(double) * R * (nc + 1))) ||
         (rc = ensure(ctx, w.stats, sizeof(double) * (fw::kMaxStreams * fw::kStreamFields + 2))) ||
-        (rc = ensure(ctx, w.origin, sizeof(uint64_t))))
+        (rc = ensure(ctx, w.origin, sizeof(uint64_t))) ||
+        (rc = ensure(ctx, w.cost_part, sizeof(double) * 2 * R * ((N + fw::kNvCostChunk - 1) / fw::kNvCostChunk))))
         return rc;
     hipStream_t st = ctx->stream;
     HIP_TRY(ctx, hipMemcpyAsync(w.prod_f.ptr, pf.data(), sizeof(float) * pf.size(), hipMemcpyHostToDevice, st));

@@ -165,8 +165,8 @@ void sim_destroy(sim_ctx *ctx)
     for (hipEvent_t e : {wd.ev0, wd.ev1})
         if (e) (void)hipEventDestroy(e);
     NvState &nv = ctx->nv;
-    for (DevBuf *x : {&nv.prod_f, &nv.prod_d, &nv.S, &nv.cnt, &nv.tau, &nv.dec, &nv.wg_r, &nv.wg_j, &nv.wg_gx, &nv.fval,
-                      &nv.stats, &nv.origin})
+    for (DevBuf *x : {&nv.prod_f, &nv.prod_d, &nv.S, &nv.cnt, &nv.tau, &nv.dec, &nv.wg_r, &nv.wg_j, &nv.wg_gx,
+                      &nv.cost_part, &nv.fval, &nv.stats, &nv.origin})
         free_buf(*x);
     for (hipEvent_t e : {nv.ev0, nv.ev1})
         if (e) (void)hipEventDestroy(e);

@@ -112,4 +112,9 @@ WORKLOADS = {
                         N={500: 25, 5_000: 25, 10_000: 25, 50_000: 25, 100_000: 50}, M=1,
                         precision="fp32", noise="gauss", regime="paper",
                         checkpoints=(50, 100, 500, 1000, 1500), seed=0),
+    # Section 4.1, Task 2 (Algorithm 2): one replication per size, K = 1500, S = 25 demand samples
+    # per product (50 at 1e6), mu ~ U(20, 50), sigma ~ U(10, 20); costs and budget as newsvendor_instance
+    "newsvendor_shape": dict(R=1, T=1_500, sizes=(100, 1_000, 10_000, 100_000, 1_000_000),
+                             S={100: 25, 1_000: 25, 10_000: 25, 100_000: 25, 1_000_000: 50}, M=1,
+                             checkpoints=(50, 100, 500, 1000, 1500), seed=0),
 }
