@@ -27,9 +27,9 @@ U64 = 2.0 ** -53
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c, wide.c, newsvendor.c and cv.c into liboracle.so (plain gcc, no fast-math,
-    no FMA contraction)."""
-    srcs = [os.path.join(HERE, f) for f in ("oracle.c", "wide.c", "newsvendor.c", "cv.c")]
+    """Compile oracle.c, wide.c, newsvendor.c, sqn.c and cv.c into liboracle.so (plain gcc, no
+    fast-math, no FMA contraction)."""
+    srcs = [os.path.join(HERE, f) for f in ("oracle.c", "wide.c", "newsvendor.c", "sqn.c", "cv.c")]
     stale = any(os.path.getmtime(LIB_PATH) < os.path.getmtime(f) for f in srcs) if os.path.exists(LIB_PATH) else True
     if force or stale:
         tmp = LIB_PATH + ".tmp"
@@ -93,6 +93,19 @@ class NvOut(ctypes.Structure):
                 ("pad_", ctypes.c_uint32), ("n_ambiguous", ctypes.c_uint64), ("n_replayed", ctypes.c_uint64),
                 ("n_mismatch", ctypes.c_uint64), ("first_mismatch", ctypes.c_int64),
                 ("identity_err", ctypes.c_double), ("min_margin", ctypes.c_double)]
+
+
+class SqnProblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("N", ctypes.c_int64), ("L", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("b", ctypes.c_int32), ("bH", ctypes.c_int32), ("beta", ctypes.c_double),
+                ("instance", ctypes.c_uint32), ("n_ckpt", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("X", ctypes.POINTER(ctypes.c_uint8)), ("z", ctypes.POINTER(ctypes.c_uint8)),
+                ("ckpt", ctypes.c_int64 * MAX_CKPT)]
+
+
+class SqnOut(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_double), ("F_ckpt", ctypes.c_double * MAX_CKPT),
+                ("w", ctypes.POINTER(ctypes.c_double)), ("pairs", ctypes.c_int64)]
 
 
 class CvStats(ctypes.Structure):
@@ -169,6 +182,18 @@ def lib():
         L.or_nv_gradient.restype = None
         L.or_nv_cost.argtypes = [ctypes.POINTER(NvProblem), dp]
         L.or_nv_cost.restype = ctypes.c_double
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.or_sqn_indices.argtypes = [ctypes.POINTER(SqnProblem), u64, u64, ctypes.c_uint32, ctypes.c_uint32, u32p]
+        L.or_sqn_indices.restype = None
+        L.or_sqn_loss.argtypes = [ctypes.POINTER(SqnProblem), dp]
+        L.or_sqn_loss.restype = ctypes.c_double
+        L.or_sqn_gradient.argtypes = [ctypes.POINTER(SqnProblem), u32p, ctypes.c_uint32, dp, dp]
+        L.or_sqn_gradient.restype = None
+        L.or_sqn_hessian_vector.argtypes = [ctypes.POINTER(SqnProblem), u32p, ctypes.c_uint32, dp, dp, dp]
+        L.or_sqn_hessian_vector.restype = None
+        L.or_sqn_hessian_approx.argtypes = [ctypes.c_int64, ctypes.c_int, dp, dp, dp]
+        L.or_sqn_hessian_approx.restype = None
+        L.or_sqn_run.argtypes = [ctypes.POINTER(SqnProblem), u64, u64, ctypes.POINTER(SqnOut)]
         L.or_cv_beta.argtypes = [dp, dp, u64, dp, dp]
         L.or_cv_estimate.argtypes = [dp, dp, u64, dp, u64, ctypes.c_double, ctypes.POINTER(CvStats)]
         _lib = L
@@ -359,6 +384,70 @@ class NvOracle:
     def cost(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64)
         return lib().or_nv_cost(ctypes.byref(self.p), _dptr(x))
+
+
+class SqnOracle:
+    """Algorithms 3-4, stochastic quasi-Newton for the logistic loss (sqn.c)."""
+
+    DOMAIN_GRAD, DOMAIN_HESS = 5, 6
+
+    def __init__(self, X, z, *, L=10, M=25, b=50, bH=300, beta=2.0, seed=0, instance=0, ckpt=()):
+        self.X = np.ascontiguousarray(X, dtype=np.uint8)
+        self.z = np.ascontiguousarray(z, dtype=np.uint8)
+        N, n = self.X.shape
+        ck = list(ckpt)
+        p = SqnProblem()
+        p.n, p.N, p.L, p.M, p.b, p.bH, p.beta = n, N, L, M, b, bH, beta
+        p.instance, p.n_ckpt, p.seed = instance, len(ck), seed
+        p.X = self.X.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        p.z = self.z.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        for i, c in enumerate(ck):
+            p.ckpt[i] = int(c)
+        self.p, self.n, self.N, self.ckpt = p, n, N, ck
+
+    def indices(self, rep, k, domain, count):
+        idx = np.zeros(count, dtype=np.uint32)
+        lib().or_sqn_indices(ctypes.byref(self.p), rep, k, domain, count,
+                             idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+        return idx
+
+    def loss(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        return lib().or_sqn_loss(ctypes.byref(self.p), _dptr(w))
+
+    def gradient(self, idx, w):
+        idx = np.ascontiguousarray(idx, dtype=np.uint32)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        g = np.zeros(self.n)
+        lib().or_sqn_gradient(ctypes.byref(self.p), idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                              len(idx), _dptr(w), _dptr(g))
+        return g
+
+    def hessian_vector(self, idx, w, v):
+        idx = np.ascontiguousarray(idx, dtype=np.uint32)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        out = np.zeros(self.n)
+        lib().or_sqn_hessian_vector(ctypes.byref(self.p), idx.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                    len(idx), _dptr(w), _dptr(v), _dptr(out))
+        return out
+
+    @staticmethod
+    def hessian_approx(S, Y):
+        S = np.ascontiguousarray(S, dtype=np.float64)
+        Y = np.ascontiguousarray(Y, dtype=np.float64)
+        m, n = S.shape
+        H = np.zeros((n, n))
+        lib().or_sqn_hessian_approx(n, m, _dptr(S), _dptr(Y), _dptr(H))
+        return H
+
+    def run(self, rep, K):
+        w = np.zeros(self.n)
+        out = SqnOut()
+        out.w = _dptr(w)
+        if lib().or_sqn_run(ctypes.byref(self.p), rep, K, ctypes.byref(out)):
+            raise ValueError("or_sqn_run rejected the problem")
+        return dict(F=out.F, F_ckpt=np.array(out.F_ckpt[:len(self.ckpt)]), w=w, pairs=out.pairs)
 
 
 def philox(ctr, key):

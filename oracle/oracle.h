@@ -11,6 +11,11 @@
  * counter-based generator (Philox4x32-10, Salmon et al., SC'11) from its
  * published definition.
  *
+ * The same library holds the oracles of the paper's other tasks: the wide
+ * (one replication, many assets) form of Algorithm 1 (wide.c), Algorithm 2,
+ * the multi-product newsvendor (newsvendor.c), Algorithms 3-4, stochastic
+ * quasi-Newton classification (sqn.c), and the control-variate pieces (cv.c).
+ *
  * Everything here is slow on purpose: one replication at a time, the sample
  * matrix R_i = mu + L y_i formed explicitly, the sample mean and the centred
  * sample covariance applied to w exactly as Eq. (4)-(5) write them, and the
@@ -31,7 +36,8 @@ extern "C" {
 #define OR_TAU_NONE 0xFFFFFFFFu
 
 enum { OR_NOISE_GAUSS = 0, OR_NOISE_T = 1 };
-enum { OR_DOMAIN_PATH = 0, OR_DOMAIN_PARAM = 1, OR_DOMAIN_CV_AUX = 2, OR_DOMAIN_MLP = 3, OR_DOMAIN_NEWSVENDOR = 4 };
+enum { OR_DOMAIN_PATH = 0, OR_DOMAIN_PARAM = 1, OR_DOMAIN_CV_AUX = 2, OR_DOMAIN_MLP = 3, OR_DOMAIN_NEWSVENDOR = 4,
+       OR_DOMAIN_SQN_GRAD = 5, OR_DOMAIN_SQN_HESS = 6 };
 
 /* One instance of problem Eq. (3) plus the sampling knobs of Algorithm 1. */
 typedef struct {
@@ -206,6 +212,41 @@ void or_nv_gradient(const or_nv_problem *p, uint64_t rep, uint64_t epoch, const 
 
 /* f(x) = sum_j f_j(x_j), Eq. (6) in closed form for normal demand. */
 double or_nv_cost(const or_nv_problem *p, const double *x);
+
+/* ---- Algorithms 3-4: stochastic quasi-Newton classification (sqn.c) ---------------------
+ * Section 3.3: logistic loss Eq. (10)-(11) over N rows of n binary features, mini-batch gradient
+ * Eq. (12), sub-sampled Hessian Eq. (13), SQN (Algorithm 3) with the explicit BFGS matrix of
+ * Algorithm 4. */
+typedef struct {
+    int64_t n, N;           /* features, rows */
+    int32_t L, M, b, bH;    /* window, pair memory, gradient and Hessian sample sizes */
+    double beta;            /* step alpha_k = beta / k */
+    uint32_t instance;      /* stream instance, < 2^24 */
+    int32_t n_ckpt;
+    uint64_t seed;
+    const uint8_t *X;       /* [N][n] features in {0, 1} */
+    const uint8_t *z;       /* [N] labels in {0, 1} */
+    int64_t ckpt[OR_MAX_CKPT];   /* iterations k after which F(w^{k+1}) is recorded */
+} or_sqn_problem;
+
+typedef struct {
+    double F;               /* F(w^{K+1}) */
+    double F_ckpt[OR_MAX_CKPT];
+    double *w;              /* caller-allocated [n]: w^{K+1} */
+    int64_t pairs;          /* correction pairs computed */
+} or_sqn_out;
+
+/* The sampled rows of iteration k: domain OR_DOMAIN_SQN_GRAD (gradient) or OR_DOMAIN_SQN_HESS. */
+void or_sqn_indices(const or_sqn_problem *p, uint64_t rep, uint64_t k, uint32_t domain, uint32_t count,
+                    uint32_t *idx);
+double or_sqn_loss(const or_sqn_problem *p, const double *w);
+void or_sqn_gradient(const or_sqn_problem *p, const uint32_t *idx, uint32_t b, const double *w, double *g);
+void or_sqn_hessian_vector(const or_sqn_problem *p, const uint32_t *idx, uint32_t bh, const double *w,
+                           const double *v, double *out);
+/* Algorithm 4's H_t (n x n, row-major) from m pairs S, Y [m][n], oldest first. */
+void or_sqn_hessian_approx(int64_t n, int m, const double *S, const double *Y, double *H);
+/* One run of Algorithm 3 for K iterations (replication rep picks the sample streams). */
+int or_sqn_run(const or_sqn_problem *p, uint64_t rep, uint64_t K, or_sqn_out *out);
 
 /* ---- control-variate pieces (cv.c) ------------------------------------------------------ */
 

@@ -68,6 +68,22 @@ def newsvendor_instance(seed: int, instance: int, n: int):
     return dict(mu=mu, sigma=sigma, k=k, h=h, v=v, c=k.copy(), C=0.5 * float(np.dot(k, mu)))
 
 
+def sqn_dataset(seed: int, n: int, N: int | None = None):
+    """Task 3's synthetic classification data (Section 4.1): N = 30 n rows of n binary features, labels
+    from a random linear combination of the features with 10% label noise. Here: features i.i.d.
+    Bernoulli(1/2), weights a_j ~ N(0, 1), label 1 when x'a exceeds its mean a'1/2, each label flipped
+    with probability 0.1. Returns (X uint8 [N][n], z uint8 [N])."""
+    N = 30 * n if N is None else N
+    g = _rng(seed, 0, 5)
+    X = (g.random((N, n)) < 0.5).astype(np.uint8)
+    a = g.standard_normal(n)
+    score = X @ a - 0.5 * a.sum()
+    z = (score > 0).astype(np.uint8)
+    flip = g.random(N) < 0.1
+    z[flip] ^= 1
+    return X, z
+
+
 @dataclass
 class BatchInstance:
     instance: int

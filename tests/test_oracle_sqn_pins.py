@@ -1,0 +1,259 @@
+"""Pins of the oracle for Algorithms 3-4, stochastic quasi-Newton classification (Section 3.3,
+oracle/sqn.c).
+
+The loss Eq. (10)-(11) against its definition written with logarithms of c and 1 - c and its value
+log 2 at the origin; the mini-batch gradient Eq. (12) and the sub-sampled Hessian Eq. (13) against
+central differences; Algorithm 4's matrix against the product form of one BFGS update, the secant
+equation, symmetry and definiteness, the compact representation of Byrd, Nocedal and Schnabel (a
+different formula for the same matrix), and quadratic termination on conjugate pairs; the sampled
+rows against the counter layout and a uniformity test; Algorithm 3 reduced to plain SGD when no
+window closes early enough, its pair count, and its long-run loss against the minimum of
+Eq. (10) found by a deterministic solver.
+"""
+import numpy as np
+import pytest
+from scipy import optimize, stats
+
+import oracle
+from paper_2404_11631_amd import workloads
+
+
+def data(n, seed=0, N=None):
+    return workloads.sqn_dataset(seed, n, N)
+
+
+def loss_by_definition(X, z, w):
+    """Eq. (10) as written: -(1/N) sum z log c + (1 - z) log(1 - c), c = 1/(1 + exp(-x'w))."""
+    c = 1.0 / (1.0 + np.exp(-(X.astype(np.float64) @ w)))
+    return -np.mean(z * np.log(c) + (1 - z) * np.log(1 - c))
+
+
+def test_dataset_recipe():
+    X, z = data(40)
+    assert X.shape == (1200, 40) and z.shape == (1200,)
+    assert set(np.unique(X)) <= {0, 1} and set(np.unique(z)) <= {0, 1}
+    assert abs(X.mean() - 0.5) < 0.02
+    assert 0.3 < z.mean() < 0.7
+    X2, z2 = data(40)
+    assert np.array_equal(X, X2) and np.array_equal(z, z2)
+
+
+def test_loss_definition_and_origin():
+    X, z = data(20, seed=1)
+    O = oracle.SqnOracle(X, z)
+    assert O.loss(np.zeros(20)) == pytest.approx(np.log(2.0), rel=1e-15)
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        w = rng.normal(0, 0.3, 20)
+        assert O.loss(w) == pytest.approx(loss_by_definition(X, z, w), rel=1e-12)
+
+
+def test_loss_no_overflow_for_large_margins():
+    """The softplus form stays finite where the definition's log(1 - c) would take log 0."""
+    X, z = data(8, seed=2)
+    O = oracle.SqnOracle(X, z)
+    v = O.loss(np.full(8, 200.0))
+    assert np.isfinite(v)
+    rows = X.sum(axis=1).astype(np.float64) * 200.0
+    # -log(1 - c) = a + log(1 + e^{-a}) for z = 0, log(1 + e^{-a}) for z = 1
+    ref = np.mean(np.where(z == 1, np.log1p(np.exp(-rows)), rows + np.log1p(np.exp(-rows))))
+    assert v == pytest.approx(ref, rel=1e-12)
+
+
+def test_sampled_rows_counter_layout_and_uniformity():
+    X, z = data(10, seed=3)
+    N = X.shape[0]
+    O = oracle.SqnOracle(X, z, seed=0x1234_5678_9ABC, instance=7)
+    idx = O.indices(5, 42, O.DOMAIN_GRAD, 10)
+    key = (0x5678_9ABC, 0x1234)
+    for q in range(10):
+        u = oracle.philox((q // 4, 42, 5, (5 << 24) | 7), key)[q % 4]
+        assert idx[q] == (u * N) >> 32
+    big = O.indices(0, 1, O.DOMAIN_HESS, 60000)
+    assert big.max() < N
+    counts = np.bincount(big * 10 // N, minlength=10)
+    assert stats.chisquare(counts).pvalue > 1e-4
+    assert not np.array_equal(O.indices(0, 1, O.DOMAIN_GRAD, 50), O.indices(0, 2, O.DOMAIN_GRAD, 50))
+    assert not np.array_equal(O.indices(0, 1, O.DOMAIN_GRAD, 50), O.indices(1, 1, O.DOMAIN_GRAD, 50))
+    assert not np.array_equal(O.indices(0, 1, O.DOMAIN_GRAD, 50), O.indices(0, 1, O.DOMAIN_HESS, 50))
+
+
+def test_gradient_is_the_derivative_of_the_batch_loss():
+    """Eq. (12) with the full data set as the batch is the gradient of Eq. (10): central differences."""
+    n = 12
+    X, z = data(n, seed=4)
+    O = oracle.SqnOracle(X, z)
+    idx = np.arange(X.shape[0], dtype=np.uint32)
+    w = np.random.default_rng(1).normal(0, 0.4, n)
+    g = O.gradient(idx, w)
+    eps = 1e-6
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = eps
+        fd = (O.loss(w + e) - O.loss(w - e)) / (2 * eps)
+        assert g[j] == pytest.approx(fd, abs=1e-8)
+
+
+def test_minibatch_gradient_uses_the_sampled_rows_with_repeats():
+    """A repeated index counts twice: the batch estimate equals the full gradient over a data set made
+    of the sampled rows."""
+    n = 9
+    X, z = data(n, seed=5)
+    O = oracle.SqnOracle(X, z)
+    idx = np.array([3, 3, 17, 40, 3, 99], dtype=np.uint32)
+    w = np.random.default_rng(2).normal(0, 0.5, n)
+    sub = oracle.SqnOracle(X[idx], z[idx])
+    full = sub.gradient(np.arange(len(idx), dtype=np.uint32), w)
+    assert np.allclose(O.gradient(idx, w), full, rtol=1e-14, atol=1e-16)
+    eps = 1e-6
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = eps
+        fd = (loss_by_definition(X[idx], z[idx], w + e) - loss_by_definition(X[idx], z[idx], w - e)) / (2 * eps)
+        assert full[j] == pytest.approx(fd, abs=1e-8)
+
+
+def test_hessian_vector_is_the_derivative_of_the_gradient():
+    """Eq. (13) applied to v equals the directional derivative of Eq. (12) on the same rows."""
+    n = 10
+    X, z = data(n, seed=6)
+    O = oracle.SqnOracle(X, z)
+    idx = O.indices(0, 10, O.DOMAIN_HESS, 300)
+    rng = np.random.default_rng(3)
+    w, v = rng.normal(0, 0.4, n), rng.normal(0, 1.0, n)
+    hv = O.hessian_vector(idx, w, v)
+    eps = 1e-5
+    fd = (O.gradient(idx, w + eps * v) - O.gradient(idx, w - eps * v)) / (2 * eps)
+    assert np.allclose(hv, fd, rtol=1e-6, atol=1e-9)
+    # and it is linear in v, symmetric (u'Hv = v'Hu) and non-negative (v'Hv >= 0)
+    u = rng.normal(0, 1.0, n)
+    assert np.allclose(O.hessian_vector(idx, w, 2 * v - u), 2 * hv - O.hessian_vector(idx, w, u), atol=1e-14)
+    assert u @ hv == pytest.approx(v @ O.hessian_vector(idx, w, u), rel=1e-12)
+    assert v @ hv >= 0.0
+
+
+def random_pairs(n, m, seed):
+    """Pairs (s, y = A s) for a random SPD A, so every curvature s'y is positive."""
+    rng = np.random.default_rng(seed)
+    B = rng.normal(size=(n, n))
+    A = B @ B.T / n + 0.5 * np.eye(n)
+    S = rng.normal(size=(m, n))
+    return S, S @ A, A
+
+
+def test_one_pair_equals_the_product_form():
+    """Algorithm 4 with one pair: H = (I - rho s y')(gamma I)(I - rho y s') + rho s s', gamma = s'y/y'y,
+    evaluated with explicit matrix products."""
+    n = 7
+    S, Y, _ = random_pairs(n, 1, 0)
+    s, y = S[0], Y[0]
+    rho = 1.0 / (y @ s)
+    gamma = (s @ y) / (y @ y)
+    I = np.eye(n)
+    ref = (I - rho * np.outer(s, y)) @ (gamma * I) @ (I - rho * np.outer(y, s)) + rho * np.outer(s, s)
+    assert np.allclose(oracle.SqnOracle.hessian_approx(S, Y), ref, rtol=1e-13, atol=1e-14)
+
+
+def test_chain_applies_pairs_oldest_first_in_product_form():
+    n, m = 6, 4
+    S, Y, _ = random_pairs(n, m, 1)
+    gamma = (S[-1] @ Y[-1]) / (Y[-1] @ Y[-1])
+    H = gamma * np.eye(n)
+    I = np.eye(n)
+    for s, y in zip(S, Y):
+        rho = 1.0 / (y @ s)
+        H = (I - rho * np.outer(s, y)) @ H @ (I - rho * np.outer(y, s)) + rho * np.outer(s, s)
+    assert np.allclose(oracle.SqnOracle.hessian_approx(S, Y), H, rtol=1e-12, atol=1e-13)
+    # the reversed order is a different matrix, so the order is pinned
+    assert not np.allclose(oracle.SqnOracle.hessian_approx(S[::-1], Y[::-1]), H, rtol=1e-6)
+
+
+def test_secant_symmetry_definiteness():
+    n, m = 15, 6
+    S, Y, _ = random_pairs(n, m, 2)
+    H = oracle.SqnOracle.hessian_approx(S, Y)
+    assert np.allclose(H @ Y[-1], S[-1], rtol=1e-12, atol=1e-12)      # secant equation of the newest pair
+    assert np.allclose(H, H.T, atol=1e-13 * np.abs(H).max())
+    assert np.linalg.eigvalsh(0.5 * (H + H.T)).min() > 0.0
+
+
+def test_compact_representation():
+    """Byrd-Nocedal-Schnabel: H = gamma I + [S gamma Y] [[R^-T (D + gamma Y'Y) R^-1, -R^-T], [-R^-1, 0]]
+    [S'; gamma Y'], R the upper triangle of S'Y and D its diagonal, for pairs as columns oldest first."""
+    n, m = 20, 8
+    S, Y, _ = random_pairs(n, m, 3)
+    gamma = (S[-1] @ Y[-1]) / (Y[-1] @ Y[-1])
+    Sm, Ym = S.T, Y.T
+    SY = Sm.T @ Ym
+    R = np.triu(SY)
+    D = np.diag(np.diag(SY))
+    Ri = np.linalg.inv(R)
+    mid = np.block([[Ri.T @ (D + gamma * Ym.T @ Ym) @ Ri, -Ri.T], [-Ri, np.zeros((m, m))]])
+    U = np.hstack([Sm, gamma * Ym])
+    ref = gamma * np.eye(n) + U @ mid @ U.T
+    assert np.allclose(oracle.SqnOracle.hessian_approx(S, Y), ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+def test_quadratic_termination_on_conjugate_pairs():
+    """For y_j = A s_j with A-conjugate s_1..s_n, n BFGS updates reproduce A^{-1} exactly (the
+    hereditary secant property), whatever the initial scaling."""
+    n = 6
+    rng = np.random.default_rng(4)
+    B = rng.normal(size=(n, n))
+    A = B @ B.T + n * np.eye(n)
+    V = rng.normal(size=(n, n))
+    S = []
+    for v in V:                                  # Gram-Schmidt in the A inner product
+        for s in S:
+            v = v - (s @ A @ v) / (s @ A @ s) * s
+        S.append(v)
+    S = np.array(S)
+    Y = S @ A
+    H = oracle.SqnOracle.hessian_approx(S, Y)
+    assert np.allclose(H, np.linalg.inv(A), rtol=1e-9, atol=1e-11)
+
+
+def test_run_is_sgd_while_no_window_closes():
+    """With 2L >= K every step is the plain stochastic gradient step of Algorithm 3's first phase,
+    alpha_k = beta/k, and no correction pair is formed before the window count reaches two."""
+    n, K = 7, 30
+    X, z = data(n, seed=7)
+    O = oracle.SqnOracle(X, z, L=15, b=20, beta=2.0, seed=3)
+    out = O.run(2, K)
+    w = np.zeros(n)
+    for k in range(1, K + 1):
+        w = w - (2.0 / k) * O.gradient(O.indices(2, k, O.DOMAIN_GRAD, 20), w)
+    assert np.array_equal(out["w"], w)
+    assert out["pairs"] == 1                           # k = 30 closes the second window (t = 1)
+    assert out["F"] == pytest.approx(O.loss(w), rel=1e-15)
+
+
+def test_pair_count_and_checkpoints():
+    n = 11
+    X, z = data(n, seed=8)
+    O = oracle.SqnOracle(X, z, L=10, M=5, b=30, bH=100, ckpt=(25, 90))
+    out = O.run(0, 95)
+    assert out["pairs"] == 95 // 10 - 1
+    assert out["F_ckpt"][0] > out["F_ckpt"][1] > 0
+    again = O.run(0, 90)
+    assert out["F_ckpt"][1] == again["F"]
+
+
+def test_long_run_reaches_the_minimum():
+    """Section 4.1's parameters (M = 25, L = 10, b = 50, beta = 2, b_H = 300) at n = 50: after 2000
+    iterations the loss is within a small margin of the minimum of Eq. (10), found by a deterministic
+    quasi-Newton solver on the full data."""
+    n = 50
+    X, z = data(n, seed=9)
+    O = oracle.SqnOracle(X, z, L=10, M=25, b=50, bH=300, beta=2.0, seed=1, ckpt=(50, 500))
+    out = O.run(0, 2000)
+    Xd = X.astype(np.float64)
+
+    def f(w):
+        a = Xd @ w
+        return np.mean(np.logaddexp(0, a) - z * a), Xd.T @ (1 / (1 + np.exp(-a)) - z) / len(z)
+
+    best = optimize.minimize(f, np.zeros(n), jac=True, method="L-BFGS-B", options=dict(gtol=1e-10)).fun
+    assert best < out["F"] < best + 0.02
+    assert out["F_ckpt"][0] > out["F_ckpt"][1] > out["F"] - 1e-3
+    assert out["pairs"] == 199
