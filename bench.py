@@ -8,8 +8,8 @@ fused with its cross-path reduction, followed by sim_stats; every step draws fre
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--cpu-seconds 20] [--no-cpu-baseline]
 
 The line also carries the control-variate leg ("cv", skip with --no-cv) and the sweeps over the
-Section 4.1 shapes of Task 1 ("paper_shape") and Task 2 ("newsvendor_shape"), skipped with
---no-paper-shape.
+Section 4.1 shapes of Task 1 ("paper_shape"), Task 2 ("newsvendor_shape") and Task 3
+("sqn_shape"), skipped with --no-paper-shape.
 
 Other measurements (not the headline line):
     --workload stress [--reps R]   the dense-L, t(3) stress workload (d = 64, N = 100, T = 1e3)
@@ -17,6 +17,8 @@ Other measurements (not the headline line):
                                    K = 1500, on the wide path (--steps runs per size)
     --workload newsvendor_shape    Task 2 (Algorithm 2) at Section 4.1's shape: n = 1e2 .. 1e6
                                    products, K = 1500
+    --workload sqn_shape           Task 3 (Algorithms 3-4) at Section 4.1's settings: n = 50 .. 5000
+                                   features, N = 30 n, K = 2000, b_H = 300 / 600
     --copy-probe BYTES             one plain device-to-device copy of BYTES, for calibrating the
                                    FETCH_SIZE / WRITE_SIZE counters against known traffic
 """
@@ -45,6 +47,8 @@ OPS_PER_NORMAL = 15 + 2 + 3 + 3
 OPS_PER_ASSET_STEP = 15
 # 256 CUs x 2.4 GHz x 128 lane-ops/clock: the FP32 vector rate 157.3 TFLOP/s at 2 flops per FMA
 PEAK_OPS = 256 * 2.4e9 * 128
+# HBM3E bandwidth of one MI355X, bytes/s
+PEAK_HBM = 8.0e12
 
 
 def ops_per_path_step(d: int, N: int) -> float:
@@ -133,9 +137,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="paper_scale", choices=("paper_scale", "stress", "paper_shape", "newsvendor_shape"))
+    ap.add_argument("--workload", default="paper_scale",
+                    choices=("paper_scale", "stress", "paper_shape", "newsvendor_shape", "sqn_shape"))
     ap.add_argument("--no-paper-shape", action="store_true", help="skip the Section 4.1 shape sweeps")
     ap.add_argument("--reps", type=int, default=0, help="replications (stress only; 0: the full 1e7)")
+    ap.add_argument("--sqn-sizes", default="", help="feature counts of the sqn_shape workload (comma list; "
+                    "default: all of Section 4.1's)")
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--no-cv", action="store_true", help="skip the control-variate leg")
     ap.add_argument("--cv-train-runs", type=int, default=10, help="training simulations of 1e6 paths")
@@ -152,15 +159,19 @@ def main():
     if args.workload == "stress":
         stress(args)
         return
-    if args.workload in ("paper_shape", "newsvendor_shape"):
+    if args.workload in ("paper_shape", "newsvendor_shape", "sqn_shape"):
         import torch
 
         from paper_2404_11631_amd import sim
 
         torch.cuda.init()
         ctx = sim.Sim(0, torch.cuda.current_stream().cuda_stream)
-        leg = paper_shape_leg if args.workload == "paper_shape" else newsvendor_shape_leg
-        print(json.dumps(leg(ctx, sim, max(1, args.steps), args.warmup)), flush=True)
+        leg = {"paper_shape": paper_shape_leg, "newsvendor_shape": newsvendor_shape_leg,
+               "sqn_shape": sqn_shape_leg}[args.workload]
+        kw = {}
+        if args.workload == "sqn_shape" and args.sqn_sizes:
+            kw["sizes"] = tuple(int(x) for x in args.sqn_sizes.split(","))
+        print(json.dumps(leg(ctx, sim, max(1, args.steps), args.warmup, **kw)), flush=True)
         ctx.close()
         return
 
@@ -192,6 +203,7 @@ def main():
     cv = None if args.no_cv else cv_leg(ctx, sim, w, mu, sigma, args)
     shape = None if args.no_paper_shape else paper_shape_leg(ctx, sim, 2, 1)
     nv_shape = None if args.no_paper_shape else newsvendor_shape_leg(ctx, sim, 2, 1)
+    sqn_shape = None if args.no_paper_shape else sqn_shape_leg(ctx, sim, 2, 1)
     ctx.close()
 
     ms_step = 1e3 * wall / args.steps
@@ -225,6 +237,8 @@ def main():
         line["paper_shape"] = shape
     if nv_shape is not None:
         line["newsvendor_shape"] = nv_shape
+    if sqn_shape is not None:
+        line["sqn_shape"] = sqn_shape
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, mu, sigma, args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -374,6 +388,85 @@ def newsvendor_shape_leg(ctx, sim, runs: int, warmup: int):
                              "iterations_per_s": T / (kavg * 1e-3), "samples_per_s": S * n * T / (kavg * 1e-3),
                              "alu_frac": ops / (kavg * 1e-3) / PEAK_OPS, "Y": st.mean})
         print(f"[newsvendor_shape] n={n} S={S}: {kavg:.1f} ms per run", file=sys.stderr, flush=True)
+    return out
+
+
+def sqn_bytes(n: int, K: int, L: int, M: int, b: int, bH: int) -> float:
+    """HBM bytes one replication of the SQN kernel must move over K iterations: per iteration the two
+    passes over the stored pairs (S'g, Y'g, then S a + Y c: 2 x 2 m n doubles), the b sampled rows'
+    bits twice (the dot products, then the gradient) and the window sum (read and written); per window
+    the new pair (s and y written, the previous average read and written), the b_H Hessian rows' bits
+    three times (x'wbar, x's, then y) and the pair's dot products with the m stored pairs
+    (S_i, Y_i, and Y_i again: 3 m n doubles)."""
+    row = 4 * (((n + 31) // 32 + 3) // 4 * 4)
+    total, m, t = 0.0, 0, -1
+    for k in range(1, K + 1):
+        total += 2 * b * row + 16 * n
+        if k > 2 * L:
+            total += 32 * m * n
+        if k % L == 0:
+            t += 1
+            if t > 0:
+                m = min(m + 1, M)
+                total += 8 * 4 * n + 3 * bH * row + 24 * m * n
+    return total
+
+
+def sqn_shape_leg(ctx, sim, runs: int, warmup: int, throughput_sizes=(5_000,), sizes=None):
+    """Task 3 (Algorithms 3-4) at Section 4.1's settings on sim_run_sqn: per feature count n (N = 30 n
+    rows, M = 25, L = 10, b = 50, beta = 2, K = 2000) and b_H in {300, 600}, the device time of one
+    run (the paper's single replication), and at the sizes in `throughput_sizes` the throughput of
+    R = 1024 replications in one launch (replication-iterations per second) against HBM bandwidth,
+    with sqn_bytes as the algorithmic traffic. The loss evaluations at the checkpoints are timed
+    apart (loss_ms)."""
+    from paper_2404_11631_amd import workloads
+
+    w = workloads.WORKLOADS["sqn_shape"]
+    K, seed = w["K"], w["seed"]
+    kw0 = dict(L=w["L"], M=w["M"], b=w["b"], beta=w["beta"], checkpoints=w["checkpoints"])
+    out = {"workload": "sqn_shape", "K": K, "L": w["L"], "M": w["M"], "b": w["b"], "beta": w["beta"],
+           "runs": runs, "precision": "f64", "sizes": []}
+    for n in (sizes or w["sizes"]):
+        X, z = workloads.sqn_dataset(seed, n)
+        ctx.sqn_load(X, z)
+        del X, z
+        for bH in w["bH"]:
+            kw = dict(kw0, bH=bH)
+            for k in range(warmup):
+                ctx.run_sqn(1, K, seed + 1000 + k, **kw)
+                ctx.sqn_stats()
+            kms, walls = [], []
+            for k in range(runs):
+                t0 = time.perf_counter()
+                ctx.run_sqn(1, K, seed + k, **kw)
+                st = ctx.sqn_stats()
+                walls.append(time.perf_counter() - t0)
+                kms.append(st.kernel_ms)
+            kavg = sum(kms) / len(kms)
+            entry = {"n": n, "N": 30 * n, "bH": bH, "device_ms": kavg, "wall_ms": 1e3 * sum(walls) / len(walls),
+                     "iterations_per_s": K / (kavg * 1e-3), "F": st.mean,
+                     "F_ckpt": [st.f_mean[c] for c in range(len(w["checkpoints"]))]}
+            if n in throughput_sizes and bH == w["bH"][0]:
+                R = w["R_batch"]
+                ctx.run_sqn(R, K, seed + 2000, **kw)
+                ctx.sqn_stats()
+                bms = []
+                for k in range(runs):
+                    ctx.run_sqn(R, K, seed + 3000 + k, **kw)
+                    stb = ctx.sqn_stats()
+                    bms.append(stb.kernel_ms)
+                bavg = sum(bms) / len(bms)
+                alg = sqn_bytes(n, K, w["L"], w["M"], w["b"], bH) * R
+                entry["batch"] = {"R": R, "device_ms": bavg, "rep_iterations_per_s": R * K / (bavg * 1e-3),
+                                  "F_mean": stb.mean, "F_ci95_halfwidth": stb.ci95_halfwidth,
+                                  "roofline": {"bound": "hbm", "achieved": alg / (bavg * 1e-3) / 1e9,
+                                               "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                                               "frac": alg / (bavg * 1e-3) / PEAK_HBM,
+                                               "bytes_per_rep": alg / R}}
+            out["sizes"].append(entry)
+            print(f"[sqn_shape] n={n} bH={bH}: {kavg:.1f} ms per run"
+                  + (f", R={entry['batch']['R']}: {entry['batch']['device_ms']:.1f} ms" if "batch" in entry else ""),
+                  file=sys.stderr, flush=True)
     return out
 
 

@@ -47,6 +47,10 @@ extern "C" {
 #define SIM_WIDE_MAX_N 1024u       /* samples per resample on the wide path */
 #define SIM_NV_MAX_N 16777216u     /* products of a newsvendor instance (sim_run_newsvendor) */
 #define SIM_NV_MAX_S 1024u         /* demand samples per product and resample */
+#define SIM_SQN_MAX_N 8192u        /* features of the classification data (sim_sqn_load) */
+#define SIM_SQN_MAX_M 32u          /* stored correction pairs */
+#define SIM_SQN_MAX_B 1024u        /* gradient and Hessian sample sizes b, b_H */
+#define SIM_SQN_MAX_R 4096u        /* replications of sim_run_sqn */
 
 typedef struct sim_ctx sim_ctx;
 
@@ -367,6 +371,66 @@ int sim_validate_newsvendor(const sim_nv_params *p, uint64_t R, uint64_t T, char
 
 int sim_nv_stats(sim_ctx *ctx, sim_stats_out *out);
 int sim_nv_paths(sim_ctx *ctx, sim_wide_view *out);
+
+/* ---- Algorithms 3-4: stochastic quasi-Newton classification (Section 3.3, Task 3) ------------
+ * Logistic loss Eq. (10)-(11), F(w) = (1/N) sum_i log(1 + e^{-x_i'w}) + (1 - z_i) x_i'w, over N rows
+ * of n binary features; mini-batch gradient Eq. (12) over b rows; sub-sampled Hessian Eq. (13) over
+ * b_H rows, applied to s; Algorithm 3 with alpha_k = beta / k, plain gradient steps for k <= 2L,
+ * steps along -H_t g after that, a correction pair (s_t, y_t) every L iterations from the second
+ * window on, the M newest kept; H_t is Algorithm 4's BFGS matrix from gamma I, gamma = s_t'y_t /
+ * y_t'y_t (applied to g through its compact representation, never formed). Rows are drawn
+ * uniformly with replacement: index floor(u N / 2^32) for the 32-bit Philox words u of counter
+ * (q/4, k, replication, 5 << 24 | instance) for the gradient rows of iteration k and
+ * (q/4, k, replication, 6 << 24 | instance) for the Hessian rows of the pair closed at iteration k.
+ * w^1 = 0. FP64 throughout. */
+
+/* Uploads the data set (host memory, copied; the previous one is replaced): X [N][n] row-major
+ * features, each 0 or 1, and z [N] labels, each 0 or 1. 1 <= n <= SIM_SQN_MAX_N, 1 <= N < 2^31,
+ * N n < 2^40. Errors: SIM_EINVAL for sizes or any other byte value (nothing is uploaded),
+ * SIM_ENOMEM, SIM_EDEVICE. Synchronous. */
+int sim_sqn_load(sim_ctx *ctx, const uint8_t *X, const uint8_t *z, uint64_t N, uint32_t n);
+
+typedef struct {
+    uint32_t abi_version;       /* SIM_ABI_VERSION */
+    uint32_t L;                 /* iterations per window, >= 1 */
+    uint32_t M;                 /* pairs kept, 1..SIM_SQN_MAX_M */
+    uint32_t b, b_H;            /* sample sizes, 1..SIM_SQN_MAX_B */
+    uint32_t n_checkpoints;     /* 0..SIM_MAX_CKPT */
+    uint32_t instance_id;       /* stream instance, < 2^24 */
+    uint32_t pad_;
+    double beta;                /* step alpha_k = beta / k, finite and > 0 */
+    uint64_t checkpoints[SIM_MAX_CKPT]; /* strictly increasing iterations k in [1, K]: F(w^{k+1}) */
+} sim_sqn_params;
+
+/* Runs R replications (1 <= R <= SIM_SQN_MAX_R) of Algorithm 3 for K iterations (1 <= K < 2^32) on
+ * the loaded data with sample seed `seed`, then evaluates F at every checkpoint and at w^{K+1}.
+ * Asynchronous on the context's stream. SIM_ESTATE without data. */
+int sim_run_sqn(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, uint64_t seed);
+
+/* Checks a parameter set exactly as sim_run_sqn does for data of N rows and n features, without a
+ * device. */
+int sim_validate_sqn(const sim_sqn_params *p, uint64_t N, uint32_t n, uint64_t R, uint64_t K, char *msg,
+                     size_t len);
+
+/* Statistics of the last SQN run over replications: Y = F(w^{K+1}), f_mean / f_sd at the
+ * checkpoints, rse of Table 2 ((F_c - Y) / F_c)^2; T holds K, f_star is NaN, kernel_ms the
+ * iterations' device time (the loss evaluations excluded), path_steps_per_s R K / that time.
+ * Synchronises the stream. */
+int sim_sqn_stats(sim_ctx *ctx, sim_stats_out *out);
+
+/* Device pointers (owned by the context) to the records of the last SQN run. */
+typedef struct {
+    uint64_t R, K;
+    uint32_t n, ld;             /* features; stride of w (a multiple of 4, entries n..ld-1 are 0) */
+    uint32_t n_checkpoints, pad_;
+    const double *F;            /* [R] F(w^{K+1}) */
+    const double *F_ckpt;       /* [n_checkpoints][R] */
+    const double *w;            /* [R][ld] w^{K+1} */
+    const double *w_ckpt;       /* [n_checkpoints][R][ld] */
+    const uint32_t *pairs;      /* [R] correction pairs computed */
+} sim_sqn_view;
+
+int sim_sqn_paths(sim_ctx *ctx, sim_sqn_view *out);
 
 /* Statistics of the last run; synchronises the stream. */
 int sim_stats(sim_ctx *ctx, sim_stats_out *out);

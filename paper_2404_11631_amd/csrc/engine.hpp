@@ -82,6 +82,18 @@ struct NvState {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
+// Data set and buffers of the last stochastic quasi-Newton run (sim_sqn_load, sim_run_sqn).
+struct SqnState {
+    bool have_data = false, have = false;
+    uint64_t N = 0;
+    uint32_t n = 0, ld = 0, xw = 0;       // features; vector stride; bitmap words per row
+    sim_sqn_params params{};
+    uint64_t R = 0, K = 0;
+    uint32_t nblk = 0;
+    DevBuf X, z, S, Y, wprev, acc, wsnap, pairs, loss_part, fval, stats;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+};
+
 struct sim_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -104,6 +116,7 @@ struct sim_ctx {
     CvState cv;
     WideState wide;
     NvState nv;
+    SqnState sqn;
 };
 
 

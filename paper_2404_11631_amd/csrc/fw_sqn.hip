@@ -1,0 +1,559 @@
+// fw_sqn.hip -- Algorithms 3-4 (Section 3.3, Task 3): stochastic quasi-Newton (SQN) for the
+// logistic loss Eq. (10)-(11) over N rows of n binary features, many independent replications.
+//
+// One workgroup of 1024 threads runs one replication through all K iterations (no grid-wide
+// synchronisation). Two mappings share the work:
+//   element owner   thread t owns the feature quads t (and t + 1024 when n > 4096): w in registers,
+//                   the gradient Eq. (12) and y = Eq. (13) s summed over the sampled rows in order,
+//                   the direction and the step, the window sum (in HBM, own features only);
+//   groups          G lanes (a power of two) take one row or one stored vector at a time for the dot
+//                   products x_i'v and s_i'v / y_i'v, against a copy of v staged in LDS; a butterfly
+//                   over the G lanes, no workgroup reduction; only the set bits of a row touch LDS.
+// The features are a bitmap in HBM (bit j of row i = x_ij, rows padded to 16 bytes), an eighth of
+// the bytes and a single 16-byte load per 128 features.
+// An iteration:
+//   rows       b rows drawn uniformly with replacement (Philox domain 5, counter (q/4, k, rep));
+//   gradient   x_i'w, c(x_i'w) - z_i, then Eq. (12) divided by b;
+//   direction  for k <= 2L the gradient; after that H_t g by the compact representation of the
+//              BFGS matrix (Byrd, Nocedal and Schnabel): with S, Y the stored pairs (oldest first),
+//              R the upper triangle of S'Y, D its diagonal and gamma = s_t'y_t / y_t'y_t,
+//                H g = gamma g + S (C S'g - gamma R^-T Y'g) - gamma Y R^-1 S'g,
+//                C = R^-T (D + gamma Y'Y) R^-1,
+//              which equals Algorithm 4's chain of rank-two updates from gamma I applied to g, in
+//              O(M n) per iteration instead of forming the n x n matrix;
+//   step       w -= (beta / k) direction;
+//   window     every L iterations the average of the window's iterates; from the second window on
+//              the pair s = wbar_t - wbar_{t-1}, y = Eq. (13) at wbar_t applied to s over b_H rows
+//              (Philox domain 6, counter (q/4, k, rep)), stored in the replication's ring of M
+//              slots; the new row and column of S'Y and Y'Y, then R^-1 and C, rebuilt in LDS.
+// Everything is FP64. The stored pairs live in HBM ([R][M][ld] per array). The loss Eq. (10) at the
+// checkpoints and at w^{K+1} is a separate launch over the whole data set.
+#include <hip/hip_runtime.h>
+
+#include "device_reduce.hpp"
+#include "device_rng.hpp"
+#include "sim_types.hpp"
+#include "sqn.hpp"
+
+namespace fw {
+
+namespace {
+
+constexpr int kRunBlock = 1024;
+
+__device__ __forceinline__ double sigmoid(double a) { return 1.0 / (1.0 + exp(-a)); }
+
+// The b (or b_H) rows of iteration k: floor(u N / 2^32) for the words u of counter (q/4, k, rep,
+// domain | instance). The caller synchronises before the rows are read.
+__device__ __forceinline__ void draw_rows(const SqnArgs &A, uint32_t rep, uint64_t k, uint32_t dom, uint32_t count,
+                                          uint32_t *idx)
+{
+    const uint32_t nb = (count + 3) / 4;
+    for (uint32_t q = threadIdx.x; q < nb; q += blockDim.x) {
+        const Words4 x = philox4x32_10(q, static_cast<uint32_t>(k), rep, (dom << 24) | A.inst, A.k0, A.k1);
+        const uint32_t u[4] = {x.x0, x.x1, x.x2, x.x3};
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (4 * q + c < count) idx[4 * q + c] = __umulhi(u[c], A.N);
+    }
+}
+
+// The four feature bits of quad q of a row (bit c = feature 4q + c).
+__device__ __forceinline__ uint32_t quad_bits(const uint32_t *X, uint32_t row, uint32_t xw, uint32_t q)
+{
+    return (X[static_cast<size_t>(row) * xw + (q >> 3)] >> (4 * (q & 7))) & 0xFu;
+}
+
+// v summed over the set bits of a 32-feature word starting at feature j0, lowest bit first.
+__device__ __forceinline__ double word_dot(uint32_t bits, const double *v, uint32_t j0)
+{
+    double a = 0.0;
+    while (bits) {
+        a += v[j0 + __builtin_ctz(bits)];
+        bits &= bits - 1;
+    }
+    return a;
+}
+
+__device__ __forceinline__ void load4(const double *p, double (&v)[4])
+{
+    const double2 a = reinterpret_cast<const double2 *>(p)[0];
+    const double2 b = reinterpret_cast<const double2 *>(p)[1];
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+    v[3] = b.y;
+}
+
+__device__ __forceinline__ void store4(double *p, const double (&v)[4])
+{
+    reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
+    reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+}
+
+// Sum over the G lanes of a group (G a power of two <= 64, groups aligned in the wavefront); every
+// lane of the wavefront must take part.
+__device__ __forceinline__ double group_sum(double a, uint32_t G)
+{
+    for (uint32_t off = G >> 1; off >= 1; off >>= 1) a += __shfl_xor(a, static_cast<int>(off), 64);
+    return a;
+}
+
+// out[i] = x_{idx[i]}'v for i < count, v staged in LDS, G lanes per row, each lane four words (128
+// features) per load. Ends with a barrier.
+__device__ __forceinline__ void row_dots(const SqnArgs &A, const uint32_t *idx, uint32_t count, const double *v,
+                                         double *out, uint32_t G)
+{
+    const uint32_t sub = threadIdx.x & (G - 1), group = threadIdx.x / G, ngroups = blockDim.x / G;
+    const uint32_t n4 = A.xw / 4;
+    for (uint32_t i0 = 0; i0 < count; i0 += ngroups) {
+        const uint32_t i = i0 + group;
+        double a = 0.0;
+        if (i < count) {
+            const uint4 *row = reinterpret_cast<const uint4 *>(A.X + static_cast<size_t>(idx[i]) * A.xw);
+#pragma unroll 4
+            for (uint32_t k4 = sub; k4 < n4; k4 += G) {
+                const uint4 x = row[k4];
+                const uint32_t j0 = 128u * k4;
+                a += word_dot(x.x, v, j0);
+                a += word_dot(x.y, v, j0 + 32);
+                a += word_dot(x.z, v, j0 + 64);
+                a += word_dot(x.w, v, j0 + 96);
+            }
+        }
+        a = group_sum(a, G);
+        if (sub == 0 && i < count) out[i] = a;
+    }
+    __syncthreads();
+}
+
+// *out(u) = vec(u)'v for u < count, vec(u) a stored vector in HBM, v staged in LDS, G lanes per
+// vector. Ends with a barrier.
+template <class VecOf, class OutOf>
+__device__ __forceinline__ void vec_dots(const SqnArgs &A, uint32_t count, VecOf vec, const double *v, OutOf out,
+                                         uint32_t G)
+{
+    const uint32_t sub = threadIdx.x & (G - 1), group = threadIdx.x / G, ngroups = blockDim.x / G;
+    for (uint32_t u0 = 0; u0 < count; u0 += ngroups) {
+        const uint32_t u = u0 + group;
+        double a = 0.0;
+        if (u < count) {
+            const double *p = vec(u);
+#pragma unroll 4
+            for (uint32_t qq = sub; qq < A.nq; qq += G) {
+                double x[4];
+                load4(p + 4 * qq, x);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) a += x[c] * v[4 * qq + c];
+            }
+        }
+        a = group_sum(a, G);
+        if (sub == 0 && u < count) *out(u) = a;
+    }
+    __syncthreads();
+}
+
+}  // namespace
+
+template <int EQ>
+__global__ __launch_bounds__(kRunBlock) void sqn_run_kernel(SqnArgs A)
+{
+    __shared__ double s_stage[kSqnMaxN];                 // the vector the group dot products read
+    __shared__ uint32_t s_idx[kSqnMaxB];
+    __shared__ double s_v[kSqnMaxB];                     // row dots x_i'w, x_i'wbar
+    __shared__ double s_coef[kSqnMaxB];                  // residuals / curvature weights; matrix scratch
+    __shared__ double s_dots[3 * kSqnMaxM];
+    __shared__ double s_SY[kSqnMaxM * kSqnMaxM];         // s_i'y_j, chronological
+    __shared__ double s_YY[kSqnMaxM * kSqnMaxM];         // y_i'y_j
+    __shared__ double s_Ri[kSqnMaxM * kSqnMaxM];         // R^-1 (upper triangular)
+    __shared__ double s_C[kSqnMaxM * kSqnMaxM];          // R^-T (D + gamma Y'Y) R^-1
+    __shared__ double s_cs[kSqnMaxM], s_cy[kSqnMaxM];    // coefficients of S and Y in H g
+
+    const uint32_t rep = blockIdx.x;
+    const uint32_t tid = threadIdx.x, T = blockDim.x;
+    const uint32_t ld = A.ld, M = A.M, G = A.G, xw = A.xw;
+    const size_t vs = static_cast<size_t>(ld);
+    double *Srep = A.S + static_cast<size_t>(rep) * M * ld;
+    double *Yrep = A.Y + static_cast<size_t>(rep) * M * ld;
+    double *wprev = A.wprev + static_cast<size_t>(rep) * ld;
+    double *acc = A.acc + static_cast<size_t>(rep) * ld;
+
+    uint32_t q[EQ];
+    bool own[EQ];
+    double w[EQ][4];
+#pragma unroll
+    for (int e = 0; e < EQ; ++e) {
+        q[e] = tid + e * T;
+        own[e] = q[e] < A.nq;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) w[e][c] = 0.0;
+        if (own[e]) store4(acc + 4 * q[e], w[e]);
+    }
+
+    uint32_t m = 0, head = 0, pairs = 0, ck = 0;
+    int64_t t = -1;
+    double gamma = 0.0;
+
+    for (uint64_t k = 1; k <= A.K; ++k) {
+        __syncthreads();                                   // the previous rows and coefficients are read
+        // rows and x_i'w (w staged)
+#pragma unroll
+        for (int e = 0; e < EQ; ++e)
+            if (own[e]) store4(s_stage + 4 * q[e], w[e]);
+        draw_rows(A, rep, k, kSqnDomGrad, A.b, s_idx);
+        __syncthreads();
+        row_dots(A, s_idx, A.b, s_stage, s_v, G);
+        for (uint32_t i = tid; i < A.b; i += T) s_coef[i] = sigmoid(s_v[i]) - static_cast<double>(A.z[s_idx[i]]);
+        __syncthreads();
+
+        // Eq. (12), and the window sum
+        double g[EQ][4];
+#pragma unroll
+        for (int e = 0; e < EQ; ++e) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) g[e][c] = 0.0;
+            if (!own[e]) continue;
+#pragma unroll 8
+            for (uint32_t i = 0; i < A.b; ++i) {
+                const uint32_t x = quad_bits(A.X, s_idx[i], xw, q[e]);
+                const double r = s_coef[i];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if ((x >> c) & 1u) g[e][c] += r;
+            }
+            double a4[4];
+            load4(acc + 4 * q[e], a4);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                g[e][c] /= static_cast<double>(A.b);
+                a4[c] += w[e][c];
+            }
+            store4(acc + 4 * q[e], a4);
+        }
+        const double alpha = A.beta / static_cast<double>(k);
+
+        if (k <= 2ull * A.L) {
+#pragma unroll
+            for (int e = 0; e < EQ; ++e)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) w[e][c] -= alpha * g[e][c];
+        } else {
+            // S'g and Y'g (g staged), interleaved: 2i is s_i'g, 2i + 1 is y_i'g, pair i oldest first
+#pragma unroll
+            for (int e = 0; e < EQ; ++e)
+                if (own[e]) store4(s_stage + 4 * q[e], g[e]);
+            __syncthreads();
+            const uint32_t hd = head, mm = m;
+            vec_dots(A, 2 * m, [&](uint32_t u) { return ((u & 1) ? Yrep : Srep) + ((hd + (u >> 1)) % M) * vs; },
+                     s_stage, [&](uint32_t u) { return s_dots + u; }, A.GV);
+            if (tid < mm) {
+                const uint32_t i = tid;
+                double a = 0.0, r = 0.0;
+                for (uint32_t l = 0; l < mm; ++l) a += s_C[i * kSqnMaxM + l] * s_dots[2 * l];
+                for (uint32_t l = 0; l <= i; ++l) r += s_Ri[l * kSqnMaxM + i] * s_dots[2 * l + 1];
+                s_cs[i] = a - gamma * r;
+            } else if (tid < 2 * mm) {
+                const uint32_t i = tid - mm;
+                double r = 0.0;
+                for (uint32_t l = i; l < mm; ++l) r += s_Ri[i * kSqnMaxM + l] * s_dots[2 * l];
+                s_cy[i] = -gamma * r;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < EQ; ++e) {
+                if (!own[e]) continue;
+                double dir[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) dir[c] = gamma * g[e][c];
+#pragma unroll 4
+                for (uint32_t i = 0; i < mm; ++i) {
+                    const size_t off = ((hd + i) % M) * vs + 4 * q[e];
+                    double sv[4], yv[4];
+                    load4(Srep + off, sv);
+                    load4(Yrep + off, yv);
+                    const double cs = s_cs[i], cy = s_cy[i];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) dir[c] += sv[c] * cs + yv[c] * cy;
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) w[e][c] -= alpha * dir[c];
+            }
+        }
+
+        if (k % A.L == 0) {
+            ++t;
+            const bool pair = t > 0;
+            const bool full = m == M;
+            const uint32_t slot = full ? head : (head + m) % M;
+            // wbar (staged), s = wbar - wbar_prev into the ring, wbar_prev = wbar, the window sum cleared
+#pragma unroll
+            for (int e = 0; e < EQ; ++e)
+                if (own[e]) {
+                    double wb[4], pv[4], sv[4];
+                    load4(acc + 4 * q[e], wb);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) wb[c] /= static_cast<double>(A.L);
+                    if (pair) {
+                        load4(wprev + 4 * q[e], pv);
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) sv[c] = wb[c] - pv[c];
+                        store4(Srep + slot * vs + 4 * q[e], sv);
+                    }
+                    store4(wprev + 4 * q[e], wb);
+                    store4(s_stage + 4 * q[e], wb);
+                    double zero[4] = {0.0, 0.0, 0.0, 0.0};
+                    store4(acc + 4 * q[e], zero);
+                }
+            if (pair) {
+                __syncthreads();                               // the gradient rows are read
+                draw_rows(A, rep, k, kSqnDomHess, A.bH, s_idx);
+                __syncthreads();
+                row_dots(A, s_idx, A.bH, s_stage, s_v, G);                 // x_i'wbar
+#pragma unroll
+                for (int e = 0; e < EQ; ++e)
+                    if (own[e]) {
+                        double sv[4];
+                        load4(Srep + slot * vs + 4 * q[e], sv);
+                        store4(s_stage + 4 * q[e], sv);
+                    }
+                __syncthreads();
+                row_dots(A, s_idx, A.bH, s_stage, s_coef, G);              // x_i's
+                for (uint32_t i = tid; i < A.bH; i += T) {
+                    const double c = sigmoid(s_v[i]);
+                    s_coef[i] = c * (1.0 - c) * s_coef[i];
+                }
+                __syncthreads();
+                // Eq. (13) applied to s, into the ring and staged
+#pragma unroll
+                for (int e = 0; e < EQ; ++e) {
+                    if (!own[e]) continue;
+                    double y[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+                    for (uint32_t i = 0; i < A.bH; ++i) {
+                        const uint32_t x = quad_bits(A.X, s_idx[i], xw, q[e]);
+                        const double cf = s_coef[i];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            if ((x >> c) & 1u) y[c] += cf;
+                    }
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) y[c] /= static_cast<double>(A.bH);
+                    store4(Yrep + slot * vs + 4 * q[e], y);
+                    store4(s_stage + 4 * q[e], y);
+                }
+                if (full) head = (head + 1) % M;
+                else ++m;
+                __syncthreads();
+                // the new row and column of S'Y and Y'Y: 3i = s_i'y, 3i + 1 = s'y_i, 3i + 2 = y_i'y
+                const uint32_t hd = head;
+                vec_dots(A, 2 * m, [&](uint32_t u) { return ((u & 1) ? Yrep : Srep) + ((hd + (u >> 1)) % M) * vs; },
+                         s_stage, [&](uint32_t u) { return s_dots + 3 * (u >> 1) + ((u & 1) ? 2 : 0); }, A.GV);
+#pragma unroll
+                for (int e = 0; e < EQ; ++e)
+                    if (own[e]) {
+                        double sv[4];
+                        load4(Srep + slot * vs + 4 * q[e], sv);
+                        store4(s_stage + 4 * q[e], sv);
+                    }
+                __syncthreads();
+                vec_dots(A, m, [&](uint32_t u) { return Yrep + ((hd + u) % M) * vs; }, s_stage,
+                         [&](uint32_t u) { return s_dots + 3 * u + 1; }, A.GV);
+                // drop the oldest pair's row and column when the ring was full (through s_v, free here)
+                if (full) {
+                    const uint32_t mm = m - 1;
+                    for (uint32_t u = tid; u < mm * mm; u += T) {
+                        const uint32_t i = u / mm, j = u % mm;
+                        s_v[u] = s_SY[(i + 1) * kSqnMaxM + j + 1];
+                    }
+                    for (uint32_t u = tid; u < mm * mm; u += T) {
+                        const uint32_t i = u / mm, j = u % mm;
+                        s_coef[u] = s_YY[(i + 1) * kSqnMaxM + j + 1];
+                    }
+                    __syncthreads();
+                    for (uint32_t u = tid; u < mm * mm; u += T) {
+                        const uint32_t i = u / mm, j = u % mm;
+                        s_SY[i * kSqnMaxM + j] = s_v[u];
+                        s_YY[i * kSqnMaxM + j] = s_coef[u];
+                    }
+                    __syncthreads();
+                }
+                if (tid < m) {
+                    const uint32_t i = tid, n1 = m - 1;
+                    s_SY[n1 * kSqnMaxM + i] = s_dots[3 * i + 1];
+                    s_YY[i * kSqnMaxM + n1] = s_dots[3 * i + 2];
+                    s_YY[n1 * kSqnMaxM + i] = s_dots[3 * i + 2];
+                }
+                __syncthreads();
+                if (tid < m) s_SY[tid * kSqnMaxM + (m - 1)] = s_dots[3 * tid];
+                __syncthreads();
+                gamma = s_SY[(m - 1) * kSqnMaxM + (m - 1)] / s_YY[(m - 1) * kSqnMaxM + (m - 1)];
+                // R^-1 by columns: R x = e_c, back substitution
+                if (tid < m) {
+                    const uint32_t c = tid;
+                    for (uint32_t i = c + 1; i < m; ++i) s_Ri[i * kSqnMaxM + c] = 0.0;
+                    s_Ri[c * kSqnMaxM + c] = 1.0 / s_SY[c * kSqnMaxM + c];
+                    for (int i = static_cast<int>(c) - 1; i >= 0; --i) {
+                        double acc_r = 0.0;
+                        for (uint32_t l = i + 1; l <= c; ++l) acc_r += s_SY[i * kSqnMaxM + l] * s_Ri[l * kSqnMaxM + c];
+                        s_Ri[i * kSqnMaxM + c] = -acc_r / s_SY[i * kSqnMaxM + i];
+                    }
+                }
+                __syncthreads();
+                // T1 = (D + gamma Y'Y) R^-1 into s_coef, then C = R^-T T1
+                for (uint32_t u = tid; u < m * m; u += T) {
+                    const uint32_t i = u / m, c = u % m;
+                    double acc_t = 0.0;
+                    for (uint32_t l = 0; l <= c; ++l) {
+                        const double dl = gamma * s_YY[i * kSqnMaxM + l] + (i == l ? s_SY[i * kSqnMaxM + i] : 0.0);
+                        acc_t += dl * s_Ri[l * kSqnMaxM + c];
+                    }
+                    s_coef[i * kSqnMaxM + c] = acc_t;
+                }
+                __syncthreads();
+                for (uint32_t u = tid; u < m * m; u += T) {
+                    const uint32_t i = u / m, c = u % m;
+                    double acc_c = 0.0;
+                    for (uint32_t l = 0; l <= i; ++l) acc_c += s_Ri[l * kSqnMaxM + i] * s_coef[l * kSqnMaxM + c];
+                    s_C[i * kSqnMaxM + c] = acc_c;
+                }
+                ++pairs;
+            }
+            __syncthreads();
+        }
+
+        while (ck < A.n_ckpt && A.ckpt[ck] == k) {
+            double *dst = A.wsnap + (static_cast<size_t>(ck) * A.R + rep) * ld;
+#pragma unroll
+            for (int e = 0; e < EQ; ++e)
+                if (own[e]) store4(dst + 4 * q[e], w[e]);
+            ++ck;
+        }
+    }
+    double *dst = A.wsnap + (static_cast<size_t>(A.n_ckpt) * A.R + rep) * ld;
+#pragma unroll
+    for (int e = 0; e < EQ; ++e)
+        if (own[e]) store4(dst + 4 * q[e], w[e]);
+    if (tid == 0) A.pairs[rep] = pairs;
+}
+
+// Eq. (10) at one stored iterate (blockIdx.y = checkpoint * R + replication) over kSqnLossRows rows:
+// a wavefront per row, lanes over 128-feature blocks of the row's bits, the terms log(1 + e^{-a}) + (1 - z) a summed in
+// double-double, wavefront partials in order.
+__global__ __launch_bounds__(kSqnLossBlock) void sqn_loss_kernel(SqnArgs A)
+{
+    __shared__ double s_w[kSqnMaxN];
+    __shared__ double s_part[2 * kSqnLossBlock / 64];
+    const uint32_t snap = blockIdx.y;
+    const double *wv = A.wsnap + static_cast<size_t>(snap) * A.ld;
+    for (uint32_t j = threadIdx.x; j < A.ld; j += blockDim.x) s_w[j] = wv[j];
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t r0 = blockIdx.x * kSqnLossRows;
+    const uint32_t r1 = min(A.N, r0 + kSqnLossRows);
+    double h = 0.0, l = 0.0;
+    for (uint32_t row = r0 + wave; row < r1; row += nw) {
+        double a = 0.0;
+        const uint4 *xr = reinterpret_cast<const uint4 *>(A.X + static_cast<size_t>(row) * A.xw);
+#pragma unroll 2
+        for (uint32_t k4 = lane; k4 < A.xw / 4; k4 += 64) {
+            const uint4 x = xr[k4];
+            const uint32_t j0 = 128u * k4;
+            a += word_dot(x.x, s_w, j0);
+            a += word_dot(x.y, s_w, j0 + 32);
+            a += word_dot(x.z, s_w, j0 + 64);
+            a += word_dot(x.w, s_w, j0 + 96);
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
+        if (lane == 0) {
+            const double sp = a > 0.0 ? log1p(exp(-a)) : log1p(exp(a)) - a;
+            dd_add(h, l, sp + (A.z[row] ? 0.0 : a), 0.0);
+        }
+    }
+    if (lane == 0) {
+        s_part[2 * wave] = h;
+        s_part[2 * wave + 1] = l;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        h = s_part[0];
+        l = s_part[1];
+        for (uint32_t k = 1; k < nw; ++k) dd_add(h, l, s_part[2 * k], s_part[2 * k + 1]);
+        double *o = A.loss_part + (static_cast<size_t>(snap) * A.nblk + blockIdx.x) * 2;
+        o[0] = h;
+        o[1] = l;
+    }
+}
+
+// F per stored iterate: the workgroups' partials in order, divided by N.
+__global__ void sqn_loss_final_kernel(SqnArgs A, uint32_t n_snap)
+{
+    const uint32_t snap = blockIdx.x * blockDim.x + threadIdx.x;
+    if (snap >= n_snap) return;
+    const double *p = A.loss_part + static_cast<size_t>(snap) * A.nblk * 2;
+    double h = 0.0, l = 0.0;
+    for (uint32_t b = 0; b < A.nblk; ++b) dd_add(h, l, p[2 * b], p[2 * b + 1]);
+    A.fval[snap] = (h + l) / static_cast<double>(A.N);
+}
+
+// Statistics across replications: streams F(w^{K+1}), F at each checkpoint, and the relative
+// squared error ((F_c - F_K) / F_c)^2 of Table 2, each as double-double sums of values and squares.
+__global__ void sqn_stats_kernel(SqnArgs A)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t nc = A.n_ckpt;
+    const double *Yv = A.fval + static_cast<size_t>(nc) * A.R;
+    const uint32_t n_streams = 1 + 2 * nc;
+    for (uint32_t s = 0; s < n_streams; ++s) {
+        double h = 0.0, l = 0.0, qh = 0.0, ql = 0.0, cnt = 0.0;
+        for (uint32_t r = 0; r < A.R; ++r) {
+            double x;
+            if (s == 0) {
+                x = Yv[r];
+            } else if (s <= nc) {
+                x = A.fval[static_cast<size_t>(s - 1) * A.R + r];
+            } else {
+                const double f = A.fval[static_cast<size_t>(s - 1 - nc) * A.R + r];
+                if (f == 0.0) continue;
+                const double e = (f - Yv[r]) / f;
+                x = e * e;
+            }
+            dd_add(h, l, x, 0.0);
+            dd_add(qh, ql, x * x, fma(x, x, -(x * x)));
+            cnt += 1.0;
+        }
+        double *o = A.stats + s * kStreamFields;
+        o[0] = h;
+        o[1] = l;
+        o[2] = qh;
+        o[3] = ql;
+        o[4] = cnt;
+    }
+    double mn = INFINITY, mx = -INFINITY;
+    for (uint32_t r = 0; r < A.R; ++r) {
+        mn = fmin(mn, Yv[r]);
+        mx = fmax(mx, Yv[r]);
+    }
+    A.stats[n_streams * kStreamFields] = mn;
+    A.stats[n_streams * kStreamFields + 1] = mx;
+}
+
+int launch_sqn_run(const SqnArgs &A, hipStream_t s)
+{
+    if (A.nq <= static_cast<uint32_t>(kRunBlock))
+        hipLaunchKernelGGL(sqn_run_kernel<1>, dim3(A.R), dim3(kRunBlock), 0, s, A);
+    else
+        hipLaunchKernelGGL(sqn_run_kernel<2>, dim3(A.R), dim3(kRunBlock), 0, s, A);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_sqn_loss(const SqnArgs &A, hipStream_t s)
+{
+    const uint32_t n_snap = (A.n_ckpt + 1) * A.R;
+    hipLaunchKernelGGL(sqn_loss_kernel, dim3(A.nblk, n_snap), dim3(kSqnLossBlock), 0, s, A);
+    hipLaunchKernelGGL(sqn_loss_final_kernel, dim3((n_snap + 63) / 64), dim3(64), 0, s, A, n_snap);
+    hipLaunchKernelGGL(sqn_stats_kernel, dim3(1), dim3(64), 0, s, A);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace fw

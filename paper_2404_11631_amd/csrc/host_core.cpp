@@ -204,6 +204,33 @@ int validate_newsvendor(char *err, const sim_nv_params *p, uint64_t R, uint64_t 
     return SIM_OK;
 }
 
+int validate_sqn(char *err, const sim_sqn_params *p, uint64_t N, uint32_t n, uint64_t R, uint64_t K)
+{
+    if (!p) return fail(err, SIM_EINVAL, "params is NULL");
+    if (p->abi_version != SIM_ABI_VERSION)
+        return fail(err, SIM_EINVAL, "abi_version %u != %u", p->abi_version, SIM_ABI_VERSION);
+    if (n < 1 || n > SIM_SQN_MAX_N) return fail(err, SIM_EINVAL, "n=%u outside [1, %u]", n, SIM_SQN_MAX_N);
+    if (N < 1 || N >= (1ull << 31)) return fail(err, SIM_EINVAL, "N=%llu outside [1, 2^31)", (unsigned long long)N);
+    if (R < 1 || R > SIM_SQN_MAX_R)
+        return fail(err, SIM_EINVAL, "R=%llu outside [1, %u]", (unsigned long long)R, SIM_SQN_MAX_R);
+    if (K < 1 || K > 0xFFFFFFFFull) return fail(err, SIM_EINVAL, "K=%llu outside [1, 2^32-1]", (unsigned long long)K);
+    if (p->L < 1) return fail(err, SIM_EINVAL, "L must be >= 1");
+    if (p->M < 1 || p->M > SIM_SQN_MAX_M) return fail(err, SIM_EINVAL, "M=%u outside [1, %u]", p->M, SIM_SQN_MAX_M);
+    if (p->b < 1 || p->b > SIM_SQN_MAX_B) return fail(err, SIM_EINVAL, "b=%u outside [1, %u]", p->b, SIM_SQN_MAX_B);
+    if (p->b_H < 1 || p->b_H > SIM_SQN_MAX_B)
+        return fail(err, SIM_EINVAL, "b_H=%u outside [1, %u]", p->b_H, SIM_SQN_MAX_B);
+    if (!finite(p->beta) || !(p->beta > 0.0)) return fail(err, SIM_EINVAL, "beta must be finite and > 0");
+    if (p->n_checkpoints > SIM_MAX_CKPT) return fail(err, SIM_EINVAL, "more than 8 checkpoints");
+    for (uint32_t k = 0; k < p->n_checkpoints; ++k) {
+        if (p->checkpoints[k] < 1 || p->checkpoints[k] > K)
+            return fail(err, SIM_EINVAL, "checkpoint %u outside [1, K]", k);
+        if (k && p->checkpoints[k] <= p->checkpoints[k - 1])
+            return fail(err, SIM_EINVAL, "checkpoints must increase strictly");
+    }
+    if (p->instance_id >= (1u << 24)) return fail(err, SIM_EINVAL, "instance_id must be < 2^24");
+    return SIM_OK;
+}
+
 void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed)
 {
     std::memset(&D, 0, sizeof(D));

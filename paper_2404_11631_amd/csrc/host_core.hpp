@@ -22,6 +22,7 @@ int validate(char *err, const sim_params *p, uint64_t R, uint64_t T);
 int validate_wide(char *err, const sim_params *p, uint64_t R, uint64_t T);
 // Algorithm 2, the newsvendor (sim_run_newsvendor)
 int validate_newsvendor(char *err, const sim_nv_params *p, uint64_t R, uint64_t T);
+int validate_sqn(char *err, const sim_sqn_params *p, uint64_t N, uint32_t n, uint64_t R, uint64_t K);
 void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed);
 // Law of the control-variate features of a run (diagonal Sigma, reference gradient p->cv_ref):
 // reference-decision probabilities p (0 origin, j+1 vertex e_j) and their running sums, the

@@ -1,0 +1,48 @@
+// sqn.hpp -- Algorithms 3-4 (Section 3.3, Task 3): stochastic quasi-Newton for the logistic loss
+// Eq. (10)-(11). Device arguments shared by the kernels (fw_sqn.hip) and the host driver
+// (sqn_api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fw {
+
+constexpr uint32_t kSqnDomGrad = 5u;        // Philox domain of the gradient rows of iteration k
+constexpr uint32_t kSqnDomHess = 6u;        // Philox domain of the Hessian rows of the pair closed at k
+constexpr int kSqnMaxM = 32;                // stored pairs
+constexpr int kSqnMaxB = 1024;              // b and b_H
+constexpr uint32_t kSqnMaxN = 8192;         // features (two quads per thread at 1024 threads)
+constexpr int kSqnChunk = 8;                // values per workgroup reduction
+constexpr int kSqnLossBlock = 256;          // threads of the loss kernel
+constexpr uint32_t kSqnLossRows = 512;      // rows per workgroup of the loss kernel
+
+struct SqnArgs {
+    uint32_t n, ld, nq;                     // features; row stride (a multiple of 4); quads ld / 4
+    uint32_t N;                             // rows of the data set
+    uint32_t L, M, b, bH;
+    uint32_t k0, k1, inst;                  // Philox key (seed lo, hi); stream instance
+    uint32_t R, n_ckpt;
+    uint32_t G;                             // lanes per row in the row dot products (a power of two)
+    uint32_t GV;                            // lanes per stored vector in the vector dot products
+    uint64_t K;
+    double beta;
+    uint64_t ckpt[8];
+    const uint32_t *X;                      // [N][xw] feature bits, bit j % 32 of word j / 32; zero padded
+    uint32_t xw;                            // words per row, a multiple of 4
+    const uint8_t *z;                       // [N] labels in {0, 1}
+    double *S, *Y;                          // [R][M][ld] the stored pairs, a ring per replication
+    double *wprev;                          // [R][ld] the previous window's average
+    double *acc;                            // [R][ld] the current window's sum of iterates
+    double *wsnap;                          // [n_ckpt + 1][R][ld] w after each checkpoint; the last is w^{K+1}
+    uint32_t *pairs;                        // [R] correction pairs computed
+    double *loss_part;                      // [n_ckpt + 1][R][nblk][2] double-double partial sums
+    uint32_t nblk;                          // loss workgroups per snapshot
+    double *fval;                           // [n_ckpt + 1][R] F at the checkpoints, then F(w^{K+1})
+    double *stats;                          // kMaxStreams x kStreamFields + 2
+};
+
+int launch_sqn_run(const SqnArgs &A, hipStream_t s);
+int launch_sqn_loss(const SqnArgs &A, hipStream_t s);
+
+}  // namespace fw

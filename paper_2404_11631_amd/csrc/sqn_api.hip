@@ -1,0 +1,184 @@
+// sqn_api.hip -- host side of Algorithms 3-4 (sim_sqn_load, sim_run_sqn): the data set upload,
+// validation, device buffers, the launches, and the statistics and records of the last run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "engine.hpp"
+#include "sqn.hpp"
+
+using namespace fw::host;
+
+extern "C" {
+
+int sim_sqn_load(sim_ctx *ctx, const uint8_t *X, const uint8_t *z, uint64_t N, uint32_t n)
+{
+    if (!ctx) return SIM_EINVAL;
+    if (!X || !z) return set_err(ctx, SIM_EINVAL, "X and z are required");
+    if (n < 1 || n > SIM_SQN_MAX_N) return set_err(ctx, SIM_EINVAL, "n=%u outside [1, %u]", n, SIM_SQN_MAX_N);
+    if (N < 1 || N >= (1ull << 31)) return set_err(ctx, SIM_EINVAL, "N=%llu outside [1, 2^31)", (unsigned long long)N);
+    if (N * n >= (1ull << 40)) return set_err(ctx, SIM_EINVAL, "N n above 2^40");
+    for (uint64_t i = 0; i < N; ++i) {
+        if (z[i] > 1) return set_err(ctx, SIM_EINVAL, "label z[%llu] = %u is not 0 or 1", (unsigned long long)i, z[i]);
+        const uint8_t *row = X + i * n;
+        uint8_t any = 0;
+        for (uint32_t j = 0; j < n; ++j) any |= row[j];
+        if (any > 1)
+            for (uint32_t j = 0; j < n; ++j)
+                if (row[j] > 1)
+                    return set_err(ctx, SIM_EINVAL, "X[%llu][%u] = %u is not 0 or 1", (unsigned long long)i, j, row[j]);
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    SqnState &q = ctx->sqn;
+    q.have_data = q.have = false;
+    // bitmap rows: bit j % 32 of word j / 32, rows padded to a multiple of four words (16 bytes)
+    const uint32_t xw = ((n + 31) / 32 + 3) / 4 * 4;
+    std::vector<uint32_t> bits(static_cast<size_t>(N) * xw, 0u);
+    for (uint64_t i = 0; i < N; ++i) {
+        const uint8_t *row = X + i * n;
+        uint32_t *dst = bits.data() + i * xw;
+        for (uint32_t j = 0; j < n; ++j) dst[j >> 5] |= static_cast<uint32_t>(row[j]) << (j & 31);
+    }
+    int rc;
+    if ((rc = ensure(ctx, q.X, sizeof(uint32_t) * bits.size())) || (rc = ensure(ctx, q.z, N))) return rc;
+    hipStream_t st = ctx->stream;
+    HIP_TRY(ctx, hipMemcpyAsync(q.X.ptr, bits.data(), sizeof(uint32_t) * bits.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipMemcpyAsync(q.z.ptr, z, N, hipMemcpyHostToDevice, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    q.xw = xw;
+    const uint32_t ld = (n + 3) / 4 * 4;
+    q.N = N;
+    q.n = n;
+    q.ld = ld;
+    q.have_data = true;
+    return SIM_OK;
+}
+
+int sim_validate_sqn(const sim_sqn_params *p, uint64_t N, uint32_t n, uint64_t R, uint64_t K, char *msg, size_t len)
+{
+    char err[kErrLen] = {0};
+    const int rc = validate_sqn(err, p, N, n, R, K);
+    if (msg && len) std::snprintf(msg, len, "%s", rc ? err : "");
+    return rc;
+}
+
+int sim_run_sqn(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, uint64_t seed)
+{
+    if (!ctx) return SIM_EINVAL;
+    SqnState &q = ctx->sqn;
+    if (!q.have_data) return set_err(ctx, SIM_ESTATE, "no data set loaded (sim_sqn_load)");
+    if (int rc = validate_sqn(ctx->err, p, q.N, q.n, R, K)) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    q.have = false;
+    for (hipEvent_t *e : {&q.ev0, &q.ev1, &q.ev2})
+        if (!*e) HIP_TRY(ctx, hipEventCreate(e));
+    const uint32_t nc = p->n_checkpoints;
+    const size_t ld = q.ld;
+    const uint32_t nblk = static_cast<uint32_t>((q.N + fw::kSqnLossRows - 1) / fw::kSqnLossRows);
+    const size_t n_snap = static_cast<size_t>(nc + 1) * R;
+    int rc;
+    if ((rc = ensure(ctx, q.S, sizeof(double) * R * p->M * ld)) || (rc = ensure(ctx, q.Y, sizeof(double) * R * p->M * ld)) ||
+        (rc = ensure(ctx, q.wprev, sizeof(double) * R * ld)) || (rc = ensure(ctx, q.acc, sizeof(double) * R * ld)) || (rc = ensure(ctx, q.wsnap, sizeof(double) * n_snap * ld)) ||
+        (rc = ensure(ctx, q.pairs, sizeof(uint32_t) * R)) ||
+        (rc = ensure(ctx, q.loss_part, sizeof(double) * 2 * n_snap * nblk)) ||
+        (rc = ensure(ctx, q.fval, sizeof(double) * n_snap)) ||
+        (rc = ensure(ctx, q.stats, sizeof(double) * (fw::kMaxStreams * fw::kStreamFields + 2))))
+        return rc;
+
+    fw::SqnArgs A{};
+    A.n = q.n;
+    A.ld = q.ld;
+    A.nq = q.ld / 4;
+    A.N = static_cast<uint32_t>(q.N);
+    A.L = p->L;
+    A.M = p->M;
+    A.b = p->b;
+    A.bH = p->b_H;
+    A.k0 = static_cast<uint32_t>(seed);
+    A.k1 = static_cast<uint32_t>(seed >> 32);
+    A.inst = p->instance_id & 0xFFFFFFu;
+    A.R = static_cast<uint32_t>(R);
+    A.n_ckpt = nc;
+    A.xw = q.xw;
+    uint32_t G = 1;                                     // at most four 16-byte loads per lane and row
+    while (G < 64 && G * 4 < A.xw / 4) G *= 2;
+    A.G = G;
+    uint32_t GV = 1;                                    // at most 32 quads per lane and stored vector
+    while (GV < 64 && GV * 32 < A.nq) GV *= 2;
+    A.GV = GV;
+    A.K = K;
+    A.beta = p->beta;
+    for (uint32_t c = 0; c < nc; ++c) A.ckpt[c] = p->checkpoints[c];
+    A.X = static_cast<const uint32_t *>(q.X.ptr);
+    A.z = static_cast<const uint8_t *>(q.z.ptr);
+    A.S = static_cast<double *>(q.S.ptr);
+    A.Y = static_cast<double *>(q.Y.ptr);
+    A.wprev = static_cast<double *>(q.wprev.ptr);
+    A.acc = static_cast<double *>(q.acc.ptr);
+    A.wsnap = static_cast<double *>(q.wsnap.ptr);
+    A.pairs = static_cast<uint32_t *>(q.pairs.ptr);
+    A.loss_part = static_cast<double *>(q.loss_part.ptr);
+    A.nblk = nblk;
+    A.fval = static_cast<double *>(q.fval.ptr);
+    A.stats = static_cast<double *>(q.stats.ptr);
+
+    hipStream_t st = ctx->stream;
+    HIP_TRY(ctx, hipEventRecord(q.ev0, st));
+    if (fw::launch_sqn_run(A, st)) return set_err(ctx, SIM_EDEVICE, "SQN launch failed");
+    HIP_TRY(ctx, hipEventRecord(q.ev1, st));
+    if (fw::launch_sqn_loss(A, st)) return set_err(ctx, SIM_EDEVICE, "SQN loss launch failed");
+    HIP_TRY(ctx, hipEventRecord(q.ev2, st));
+    q.params = *p;
+    q.R = R;
+    q.K = K;
+    q.nblk = nblk;
+    q.have = true;
+    return SIM_OK;
+}
+
+int sim_sqn_stats(sim_ctx *ctx, sim_stats_out *out)
+{
+    if (!ctx || !out) return SIM_EINVAL;
+    SqnState &q = ctx->sqn;
+    if (!q.have) return set_err(ctx, SIM_ESTATE, "no SQN run yet");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipEventSynchronize(q.ev2));
+    const uint32_t nc = q.params.n_checkpoints, n_streams = 1 + 2 * nc;
+    double F[fw::kMaxStreams * fw::kStreamFields + 2];
+    HIP_TRY(ctx, hipMemcpy(F, q.stats.ptr, sizeof(double) * (n_streams * fw::kStreamFields + 2), hipMemcpyDeviceToHost));
+    float ms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, q.ev0, q.ev1));
+    const uint64_t none = 0;
+    fill_stats(out, F, nc, q.params.checkpoints, F[n_streams * fw::kStreamFields], F[n_streams * fw::kStreamFields + 1],
+               &none, 0, 0, 0, q.R, q.K, NAN, ms, static_cast<double>(q.R) * static_cast<double>(q.K));
+    return SIM_OK;
+}
+
+int sim_sqn_paths(sim_ctx *ctx, sim_sqn_view *out)
+{
+    if (!ctx || !out) return SIM_EINVAL;
+    SqnState &q = ctx->sqn;
+    if (!q.have) return set_err(ctx, SIM_ESTATE, "no SQN run yet");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipEventSynchronize(q.ev2));
+    std::memset(out, 0, sizeof(*out));
+    const uint32_t nc = q.params.n_checkpoints;
+    out->R = q.R;
+    out->K = q.K;
+    out->n = q.n;
+    out->ld = q.ld;
+    out->n_checkpoints = nc;
+    const double *fv = static_cast<const double *>(q.fval.ptr);
+    const double *ws = static_cast<const double *>(q.wsnap.ptr);
+    out->F = fv + static_cast<size_t>(nc) * q.R;
+    out->F_ckpt = nc ? fv : nullptr;
+    out->w = ws + static_cast<size_t>(nc) * q.R * q.ld;
+    out->w_ckpt = nc ? ws : nullptr;
+    out->pairs = static_cast<const uint32_t *>(q.pairs.ptr);
+    return SIM_OK;
+}
+
+}  // extern "C"

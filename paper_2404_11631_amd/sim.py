@@ -145,6 +145,41 @@ def validate_newsvendor(inst: dict, R: int, T: int, **kw):
     return rc, buf.value.decode()
 
 
+class SimSqnParams(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("L", ctypes.c_uint32), ("M", ctypes.c_uint32),
+                ("b", ctypes.c_uint32), ("b_H", ctypes.c_uint32), ("n_checkpoints", ctypes.c_uint32),
+                ("instance_id", ctypes.c_uint32), ("pad_", ctypes.c_uint32), ("beta", ctypes.c_double),
+                ("checkpoints", ctypes.c_uint64 * MAX_CKPT)]
+
+
+class SimSqnView(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_uint64), ("K", ctypes.c_uint64), ("n", ctypes.c_uint32), ("ld", ctypes.c_uint32),
+                ("n_checkpoints", ctypes.c_uint32), ("pad_", ctypes.c_uint32), ("F", ctypes.c_void_p),
+                ("F_ckpt", ctypes.c_void_p), ("w", ctypes.c_void_p), ("w_ckpt", ctypes.c_void_p),
+                ("pairs", ctypes.c_void_p)]
+
+
+def sqn_params(L: int = 10, M: int = 25, b: int = 50, bH: int = 300, beta: float = 2.0, checkpoints=(),
+               instance_id: int = 0) -> SimSqnParams:
+    """sim_sqn_params; the defaults are Section 4.1's Task 3 settings (b_H = 300)."""
+    sp = SimSqnParams()
+    sp.abi_version = ABI_VERSION
+    sp.L, sp.M, sp.b, sp.b_H, sp.beta = L, M, b, bH, beta
+    sp.n_checkpoints = len(checkpoints)
+    for i, c in enumerate(checkpoints[:MAX_CKPT]):
+        sp.checkpoints[i] = int(c)
+    sp.instance_id = instance_id
+    return sp
+
+
+def validate_sqn(N: int, n: int, R: int, K: int, **kw):
+    """(code, message) of the checks sim_run_sqn applies, without a device."""
+    sp = sqn_params(**kw)
+    buf = ctypes.create_string_buffer(512)
+    rc = load().sim_validate_sqn(ctypes.byref(sp), N, n, R, K, buf, 512)
+    return rc, buf.value.decode()
+
+
 def mlp_param_count(F: int) -> int:
     return 64 * F + 4289
 
@@ -155,7 +190,8 @@ EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_run_b
            "sim_strerror", "sim_last_error", "sim_destroy", "sim_cv_fit", "sim_run_cv", "sim_cv_paths",
            "sim_mlp_set_params", "sim_mlp_get_params", "sim_mlp_forward", "sim_mlp_grad", "sim_cv_aux_draws",
            "sim_cv_law", "sim_run_wide", "sim_validate_wide", "sim_wide_stats", "sim_wide_paths",
-           "sim_run_newsvendor", "sim_validate_newsvendor", "sim_nv_stats", "sim_nv_paths")
+           "sim_run_newsvendor", "sim_validate_newsvendor", "sim_nv_stats", "sim_nv_paths",
+           "sim_sqn_load", "sim_run_sqn", "sim_validate_sqn", "sim_sqn_stats", "sim_sqn_paths")
 
 _lib = None
 
@@ -212,6 +248,13 @@ def load():
         L.sim_validate_newsvendor.argtypes = [ctypes.POINTER(SimNvParams), u64, u64, ctypes.c_char_p, ctypes.c_size_t]
         L.sim_nv_stats.argtypes = [vp, ctypes.POINTER(SimStats)]
         L.sim_nv_paths.argtypes = [vp, ctypes.POINTER(SimWideView)]
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        L.sim_sqn_load.argtypes = [vp, u8p, u8p, u64, ctypes.c_uint32]
+        L.sim_run_sqn.argtypes = [vp, ctypes.POINTER(SimSqnParams), u64, u64, u64]
+        L.sim_validate_sqn.argtypes = [ctypes.POINTER(SimSqnParams), u64, ctypes.c_uint32, u64, u64, ctypes.c_char_p,
+                                       ctypes.c_size_t]
+        L.sim_sqn_stats.argtypes = [vp, ctypes.POINTER(SimStats)]
+        L.sim_sqn_paths.argtypes = [vp, ctypes.POINTER(SimSqnView)]
         _lib = L
     return _lib
 
@@ -414,6 +457,41 @@ class Sim:
         v = SimWideView()
         self._check(self.L.sim_nv_paths(self.h, ctypes.byref(v)))
         return self._wide_view(v)
+
+    def sqn_load(self, X, z):
+        """Uploads the classification data set: X [N][n] and z [N], bytes 0 or 1 (sim_sqn_load)."""
+        X = np.ascontiguousarray(X, dtype=np.uint8)
+        z = np.ascontiguousarray(z, dtype=np.uint8)
+        if X.ndim != 2 or z.shape != (X.shape[0],):
+            raise ValueError("X must be [N][n] and z [N]")
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        self._check(self.L.sim_sqn_load(self.h, X.ctypes.data_as(u8p), z.ctypes.data_as(u8p), X.shape[0], X.shape[1]))
+
+    def run_sqn(self, R: int, K: int, seed: int, **kw):
+        """Algorithms 3-4 (sim_run_sqn) on the loaded data; kw as sqn_params."""
+        sp = sqn_params(**kw)
+        self._check(self.L.sim_run_sqn(self.h, ctypes.byref(sp), R, K, seed))
+
+    def sqn_stats(self) -> SimStats:
+        st = SimStats()
+        self._check(self.L.sim_sqn_stats(self.h, ctypes.byref(st)))
+        return st
+
+    def sqn_paths(self) -> dict:
+        """Host copies of the last SQN run's records: F [R], F_ckpt [nc][R], w [R][n], w_ckpt [nc][R][n],
+        pairs [R]."""
+        v = SimSqnView()
+        self._check(self.L.sim_sqn_paths(self.h, ctypes.byref(v)))
+        R, n, ld, nc = v.R, v.n, v.ld, v.n_checkpoints
+        out = dict(R=R, K=v.K, n=n)
+        out["F"] = self._copy(v.F, np.float64, R)
+        out["F_ckpt"] = self._copy(v.F_ckpt, np.float64, nc * R).reshape(nc, R) if nc else np.zeros((0, R))
+        out["w"] = self._copy(v.w, np.float64, R * ld).reshape(R, ld)[:, :n]
+        out["w_pad"] = self._copy(v.w, np.float64, R * ld).reshape(R, ld)[:, n:]
+        out["w_ckpt"] = (self._copy(v.w_ckpt, np.float64, nc * R * ld).reshape(nc, R, ld)[:, :, :n] if nc
+                         else np.zeros((0, R, n)))
+        out["pairs"] = self._copy(v.pairs, np.uint32, R)
+        return out
 
     def wide_paths(self) -> dict:
         """Host copies of the last wide run's records: y [R], f_ckpt [nc][R], cnt [R][d+1], wsum [R][d],

@@ -68,17 +68,24 @@ def newsvendor_instance(seed: int, instance: int, n: int):
     return dict(mu=mu, sigma=sigma, k=k, h=h, v=v, c=k.copy(), C=0.5 * float(np.dot(k, mu)))
 
 
-def sqn_dataset(seed: int, n: int, N: int | None = None):
+def sqn_dataset(seed: int, n: int, N: int | None = None, density: float | None = None):
     """Task 3's synthetic classification data (Section 4.1): N = 30 n rows of n binary features, labels
     from a random linear combination of the features with 10% label noise. Here: features i.i.d.
-    Bernoulli(1/2), weights a_j ~ N(0, 1), label 1 when x'a exceeds its mean a'1/2, each label flipped
-    with probability 0.1. Returns (X uint8 [N][n], z uint8 [N])."""
+    Bernoulli(p) with p = min(1/2, 25/n) (about 25 ones per row at every n >= 50, so the curvature of
+    the loss, and with it the meaning of the step parameter beta, does not grow with n); weights
+    a_j ~ N(0, 1); label 1 when x'a exceeds its mean p a'1; each label flipped with probability 0.1.
+    Returns (X uint8 [N][n], z uint8 [N])."""
     N = 30 * n if N is None else N
+    p = min(0.5, 25.0 / n) if density is None else density
     g = _rng(seed, 0, 5)
-    X = (g.random((N, n)) < 0.5).astype(np.uint8)
+    X = np.empty((N, n), dtype=np.uint8)
+    for i in range(0, N, 4096):                      # in row blocks, so no N x n float array is formed
+        X[i:i + 4096] = g.random((min(4096, N - i), n)) < p
     a = g.standard_normal(n)
-    score = X @ a - 0.5 * a.sum()
-    z = (score > 0).astype(np.uint8)
+    mean = p * a.sum()
+    z = np.empty(N, dtype=np.uint8)
+    for i in range(0, N, 8192):
+        z[i:i + 8192] = (X[i:i + 8192].astype(np.float64) @ a - mean) > 0
     flip = g.random(N) < 0.1
     z[flip] ^= 1
     return X, z
@@ -133,4 +140,7 @@ WORKLOADS = {
     "newsvendor_shape": dict(R=1, T=1_500, sizes=(100, 1_000, 10_000, 100_000, 1_000_000),
                              S={100: 25, 1_000: 25, 10_000: 25, 100_000: 25, 1_000_000: 50}, M=1,
                              checkpoints=(50, 100, 500, 1000, 1500), seed=0),
+    # Task 3 (Algorithms 3-4) at Section 4.1's settings: n features, N = 30 n rows, K = 2000
+    "sqn_shape": dict(K=2_000, sizes=(50, 500, 1_000, 5_000), L=10, M=25, b=50, bH=(300, 600), beta=2.0,
+                      checkpoints=(50, 100, 500, 1000, 2000), R_batch=1024, seed=0),
 }

@@ -46,7 +46,8 @@ def test_struct_layout_matches_header():
                "sim_path_view": sim.SimPathView, "sim_batch_config": sim.SimBatchConfig,
                "sim_cv_opts": sim.SimCvOpts, "sim_cv_fit_out": sim.SimCvFitOut,
                "sim_cv_stats_out": sim.SimCvStats, "sim_cv_view": sim.SimCvView,
-               "sim_wide_view": sim.SimWideView, "sim_nv_params": sim.SimNvParams}
+               "sim_wide_view": sim.SimWideView, "sim_nv_params": sim.SimNvParams,
+               "sim_sqn_params": sim.SimSqnParams, "sim_sqn_view": sim.SimSqnView}
     fields = {name: [f[0] for f in cls._fields_] for name, cls in mirrors.items()}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for st, fs in fields.items():
@@ -186,6 +187,29 @@ def test_newsvendor_validation(lib):
     x0[5] = 0.5 * inst["C"] / inst["c"][5]
     assert sim.validate_newsvendor(inst, 1, 10, S=25, x0=x0)[0] == 0
     assert sim.validate_newsvendor(inst, 1, 20, S=25, checkpoints=(20, 30))[0] == -1
+
+
+def test_sqn_validation(lib):
+    """Algorithms 3-4 (sim_run_sqn): 1 <= n <= 8192, 1 <= N < 2^31, R <= 4096, 1 <= K < 2^32, L >= 1,
+    1 <= M <= 32, 1 <= b, b_H <= 1024, beta > 0, checkpoints increasing in [1, K]."""
+    assert sim.validate_sqn(1500, 50, 1, 2000)[0] == 0
+    assert sim.validate_sqn(150000, 5000, 512, 2000, bH=600, checkpoints=(50, 100, 500, 1000))[0] == 0
+    assert sim.validate_sqn(1500, 0, 1, 10)[0] == -1
+    assert sim.validate_sqn(1500, 8193, 1, 10)[0] == -1
+    assert sim.validate_sqn(0, 50, 1, 10)[0] == -1
+    assert sim.validate_sqn(1500, 50, 4097, 10)[0] == -1
+    assert sim.validate_sqn(1500, 50, 1, 0)[0] == -1
+    assert sim.validate_sqn(1500, 50, 1, 2 ** 32)[0] == -1
+    assert sim.validate_sqn(1500, 50, 1, 10, L=0)[0] == -1
+    assert sim.validate_sqn(1500, 50, 1, 10, M=33)[0] == -1
+    assert sim.validate_sqn(1500, 50, 1, 10, M=0)[0] == -1
+    assert sim.validate_sqn(1500, 50, 1, 10, b=1025)[0] == -1
+    assert sim.validate_sqn(1500, 50, 1, 10, bH=0)[0] == -1
+    assert sim.validate_sqn(1500, 50, 1, 10, beta=0.0)[0] == -1
+    assert sim.validate_sqn(1500, 50, 1, 10, beta=float("nan"))[0] == -1
+    assert sim.validate_sqn(1500, 50, 1, 10, checkpoints=(5, 5))[0] == -1
+    assert sim.validate_sqn(1500, 50, 1, 10, checkpoints=(11,))[0] == -1
+    assert sim.validate_sqn(1500, 50, 1, 10, instance_id=1 << 24)[0] == -1
 
 
 def test_create_without_gpu_fails_cleanly(lib):

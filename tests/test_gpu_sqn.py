@@ -1,0 +1,149 @@
+"""Algorithms 3-4, stochastic quasi-Newton classification (sim_run_sqn), vs the CPU oracle through the
+C ABI (needs an MI355X).
+
+There are no discrete decisions besides the sampled rows, which both sides draw from the same Philox
+counters (bit-exact). The iterates differ only by rounding: the device sums dot products in a tree,
+and applies H_t through the compact representation instead of Algorithm 4's explicit chain (the
+oracle's pins show the two are the same matrix). Tolerances, in FP64: w^{K+1} and the checkpoint
+iterates to 1e-9 relative in the 2-norm, F to 1e-10 relative; the loss kernel alone (F at the
+device's own iterate) to 1e-12. Pair counts exact. At Section 4.1's largest shape (n = 5000,
+N = 30 n, b_H = 600, K = 2000) the oracle checks the first iterations exactly that way and the full
+run through properties: the loss at every checkpoint recomputed by the oracle at the device's iterate,
+a decreasing loss, the pair count.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_11631_amd import sim, workloads
+
+pytestmark = pytest.mark.gpu
+
+W_RTOL = 1e-9
+F_RTOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    s = sim.Sim(0)
+    yield s
+    s.close()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def run_and_compare(ctx, X, z, R, K, seed, L=10, M=25, b=50, bH=300, beta=2.0, ckpt=(), instance=0, load=True):
+    N, n = X.shape
+    say(f"[sqn] n={n} N={N} R={R} K={K} L={L} M={M} b={b} bH={bH} seed={seed} ckpt={ckpt}")
+    if load:
+        ctx.sqn_load(X, z)
+    ctx.run_sqn(R, K, seed, L=L, M=M, b=b, bH=bH, beta=beta, checkpoints=ckpt, instance_id=instance)
+    st = ctx.sqn_stats()
+    g = ctx.sqn_paths()
+    assert np.all(g["w_pad"] == 0.0)
+    O = oracle.SqnOracle(X, z, L=L, M=M, b=b, bH=bH, beta=beta, seed=seed, instance=instance, ckpt=ckpt)
+    Fs, worst_w, worst_f = [], 0.0, 0.0
+    for r in range(R):
+        o = O.run(r, K)
+        assert int(g["pairs"][r]) == o["pairs"]
+        ew = rel(g["w"][r], o["w"])
+        ef = abs(g["F"][r] - o["F"]) / o["F"]
+        worst_w, worst_f = max(worst_w, ew), max(worst_f, ef)
+        assert ew <= W_RTOL, (r, ew)
+        assert ef <= F_RTOL, (r, g["F"][r], o["F"])
+        assert abs(g["F"][r] - O.loss(g["w"][r])) <= 1e-12 * o["F"]
+        for c in range(len(ckpt)):
+            assert abs(g["F_ckpt"][c, r] - o["F_ckpt"][c]) <= F_RTOL * o["F_ckpt"][c]
+            assert abs(g["F_ckpt"][c, r] - O.loss(g["w_ckpt"][c, r])) <= 1e-12 * o["F_ckpt"][c]
+        Fs.append(o["F"])
+    Fs = np.array(Fs)
+    assert abs(st.mean - Fs.mean()) <= 1e-10 * Fs.mean()
+    if R > 1:
+        assert abs(st.var - Fs.var(ddof=1)) <= 1e-6 * Fs.var(ddof=1) + 1e-20
+    assert st.min == g["F"].min() and st.max == g["F"].max()
+    assert st.T == K and st.R == R
+    say(f"[sqn] ok: max rel err w {worst_w:.2e}, F {worst_f:.2e}; {st.kernel_ms:.2f} ms")
+    return st, g
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=50, R=3, K=200, ckpt=(50, 100, 200)),                              # 19 pairs, ring not full
+    dict(n=50, R=2, K=400, M=5, ckpt=(400,)),                                 # the ring wraps 34 times
+    dict(n=37, N=1110, R=2, K=120, L=5, M=4, b=17, bH=33, ckpt=(7, 60)),      # ragged quads and chunks
+    dict(n=24, N=700, R=2, K=60, L=1, M=1, b=9, bH=5),                        # a pair every iteration
+    dict(n=1000, N=30000, R=2, K=60, M=3, bH=600, ckpt=(30,)),                # 256 threads
+    dict(n=4100, N=5000, R=1, K=40, M=3, ckpt=(25,)),                         # two quads per thread
+])
+def test_sqn_against_oracle(ctx, case):
+    c = dict(case)
+    n = c.pop("n")
+    X, z = workloads.sqn_dataset(11, n, c.pop("N", None))
+    run_and_compare(ctx, X, z, c.pop("R"), c.pop("K"), 21, **c)
+
+
+def test_sqn_instance_and_seed_streams(ctx):
+    X, z = workloads.sqn_dataset(12, 40)
+    run_and_compare(ctx, X, z, 2, 90, 0x1234_5678_9ABC, M=6, ckpt=(45,), instance=77)
+
+
+def test_sqn_deterministic_and_reload(ctx):
+    X, z = workloads.sqn_dataset(13, 64)
+    ctx.sqn_load(X, z)
+    ctx.run_sqn(3, 150, 5, checkpoints=(100,))
+    a = ctx.sqn_paths()
+    ctx.run_sqn(3, 150, 5, checkpoints=(100,))
+    b = ctx.sqn_paths()
+    assert np.array_equal(a["w"], b["w"]) and np.array_equal(a["F"], b["F"])
+    # another data set replaces the first one; the first one again gives the first results
+    X2, z2 = workloads.sqn_dataset(14, 30)
+    ctx.sqn_load(X2, z2)
+    ctx.run_sqn(1, 20, 5)
+    assert ctx.sqn_paths()["w"].shape == (1, 30)
+    ctx.sqn_load(X, z)
+    ctx.run_sqn(3, 150, 5, checkpoints=(100,))
+    assert np.array_equal(ctx.sqn_paths()["w"], a["w"])
+
+
+def test_sqn_rejects_bad_data(ctx):
+    X, z = workloads.sqn_dataset(15, 8)
+    bad = X.copy()
+    bad[3, 2] = 2
+    with pytest.raises(sim.SimError):
+        ctx.sqn_load(bad, z)
+    zb = z.copy()
+    zb[0] = 7
+    with pytest.raises(sim.SimError):
+        ctx.sqn_load(X, zb)
+
+
+def test_paper_shape_sampled(ctx):
+    """Section 4.1's largest Task 3 run: n = 5000, N = 30 n, b = 50, b_H = 600, M = 25, L = 10, beta = 2,
+    K = 2000. The first 35 iterations (three pairs) against the oracle; the full run through the loss
+    at every checkpoint recomputed by the oracle at the device's iterate, its decrease and the pair
+    count."""
+    n = 5000
+    X, z = workloads.sqn_dataset(0, n)
+    say(f"[sqn] paper shape n={n} N={X.shape[0]}")
+    ctx.sqn_load(X, z)
+    run_and_compare(ctx, X, z, 1, 35, 0, bH=600, ckpt=(20,), load=False)
+    ck = (50, 100, 500, 1000, 2000)
+    ctx.run_sqn(1, 2000, 0, bH=600, checkpoints=ck)
+    st = ctx.sqn_stats()
+    g = ctx.sqn_paths()
+    say(f"[sqn] paper shape: {st.kernel_ms:.1f} ms for 2000 iterations, F = {g['F'][0]:.6f}")
+    assert int(g["pairs"][0]) == 199
+    O = oracle.SqnOracle(X, z)
+    for c, k in enumerate(ck):
+        f = O.loss(g["w_ckpt"][c, 0])
+        assert abs(g["F_ckpt"][c, 0] - f) <= 1e-12 * f, (k, g["F_ckpt"][c, 0], f)
+    assert g["F_ckpt"][-1, 0] == g["F"][0]
+    assert np.all(np.diff(g["F_ckpt"][1:, 0]) < 0) and g["F"][0] < np.log(2.0)

@@ -36,6 +36,8 @@ def test_dataset_recipe():
     assert 0.3 < z.mean() < 0.7
     X2, z2 = data(40)
     assert np.array_equal(X, X2) and np.array_equal(z, z2)
+    Xs, zs = data(500, N=2000)                       # about 25 ones per row beyond n = 50
+    assert abs(Xs.sum(axis=1).mean() - 25.0) < 0.5 and 0.3 < zs.mean() < 0.7
 
 
 def test_loss_definition_and_origin():
