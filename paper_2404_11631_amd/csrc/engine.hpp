@@ -90,7 +90,7 @@ struct SqnState {
     sim_sqn_params params{};
     uint64_t R = 0, K = 0;
     uint32_t nblk = 0;
-    DevBuf X, z, S, Y, wprev, acc, wsnap, pairs, loss_part, fval, stats;
+    DevBuf X, z, S, Y, wprev, acc, wsnap, wt, pairs, loss_part, fval, stats;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
 };
 

@@ -485,6 +485,63 @@ __global__ __launch_bounds__(kSqnLossBlock) void sqn_loss_kernel(SqnArgs A)
     }
 }
 
+// wt[j][s] = wsnap[s][j]: the stored iterates feature-major, for sqn_loss_many_kernel. 32 x 32 tiles.
+__global__ __launch_bounds__(256) void sqn_transpose_kernel(SqnArgs A, uint32_t n_snap)
+{
+    __shared__ double tile[32][33];
+    const uint32_t j0 = blockIdx.x * 32, s0 = blockIdx.y * 32;
+    const uint32_t tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (uint32_t r = ty; r < 32; r += 8) {
+        const uint32_t sn = s0 + r, j = j0 + tx;
+        tile[r][tx] = (sn < n_snap && j < A.ld) ? A.wsnap[static_cast<size_t>(sn) * A.ld + j] : 0.0;
+    }
+    __syncthreads();
+    for (uint32_t r = ty; r < 32; r += 8) {
+        const uint32_t j = j0 + r, sn = s0 + tx;
+        if (j < A.ld && sn < n_snap) A.wt[static_cast<size_t>(j) * n_snap + sn] = tile[tx][r];
+    }
+}
+
+// Eq. (10) at many stored iterates at once: a lane per iterate (64 per workgroup, blockIdx.y picks
+// them), the four wavefronts over the rows of the block (row r0 + wave, + 4, ...). Each row's set
+// bits are walked once per wavefront from scalar registers and every lane adds its iterate's w_j,
+// lowest j first; the terms in double-double, the wavefronts' partials in order.
+__global__ __launch_bounds__(kSqnLossBlock) void sqn_loss_many_kernel(SqnArgs A, uint32_t n_snap)
+{
+    __shared__ double s_part[2 * kSqnLossBlock];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t snap = blockIdx.y * 64 + lane;
+    const bool act = snap < n_snap;
+    const double *wt = A.wt + (act ? snap : 0);
+    const uint32_t r0 = blockIdx.x * kSqnLossRows;
+    const uint32_t r1 = min(A.N, r0 + kSqnLossRows);
+    double h = 0.0, l = 0.0;
+    for (uint32_t row = r0 + wave; row < r1; row += nw) {
+        const uint32_t rr = __builtin_amdgcn_readfirstlane(row);
+        const uint32_t *xr = A.X + static_cast<size_t>(rr) * A.xw;
+        double a = 0.0;
+        for (uint32_t wi = 0; wi < A.xw; ++wi) {
+            uint32_t bits = __builtin_amdgcn_readfirstlane(xr[wi]);
+            while (bits) {
+                const uint32_t j = 32u * wi + static_cast<uint32_t>(__builtin_ctz(bits));
+                a += wt[static_cast<size_t>(j) * n_snap];
+                bits &= bits - 1;
+            }
+        }
+        const double sp = a > 0.0 ? log1p(exp(-a)) : log1p(exp(a)) - a;
+        dd_add(h, l, sp + (A.z[rr] ? 0.0 : a), 0.0);
+    }
+    s_part[2 * threadIdx.x] = h;
+    s_part[2 * threadIdx.x + 1] = l;
+    __syncthreads();
+    if (wave == 0 && act) {
+        for (uint32_t k = 1; k < nw; ++k) dd_add(h, l, s_part[2 * (k * 64 + lane)], s_part[2 * (k * 64 + lane) + 1]);
+        double *o = A.loss_part + (static_cast<size_t>(snap) * A.nblk + blockIdx.x) * 2;
+        o[0] = h;
+        o[1] = l;
+    }
+}
+
 // F per stored iterate: the workgroups' partials in order, divided by N.
 __global__ void sqn_loss_final_kernel(SqnArgs A, uint32_t n_snap)
 {
@@ -550,7 +607,12 @@ int launch_sqn_run(const SqnArgs &A, hipStream_t s)
 int launch_sqn_loss(const SqnArgs &A, hipStream_t s)
 {
     const uint32_t n_snap = (A.n_ckpt + 1) * A.R;
-    hipLaunchKernelGGL(sqn_loss_kernel, dim3(A.nblk, n_snap), dim3(kSqnLossBlock), 0, s, A);
+    if (n_snap >= kSqnManySnap) {
+        hipLaunchKernelGGL(sqn_transpose_kernel, dim3((A.ld + 31) / 32, (n_snap + 31) / 32), dim3(256), 0, s, A, n_snap);
+        hipLaunchKernelGGL(sqn_loss_many_kernel, dim3(A.nblk, (n_snap + 63) / 64), dim3(kSqnLossBlock), 0, s, A, n_snap);
+    } else {
+        hipLaunchKernelGGL(sqn_loss_kernel, dim3(A.nblk, n_snap), dim3(kSqnLossBlock), 0, s, A);
+    }
     hipLaunchKernelGGL(sqn_loss_final_kernel, dim3((n_snap + 63) / 64), dim3(64), 0, s, A, n_snap);
     hipLaunchKernelGGL(sqn_stats_kernel, dim3(1), dim3(64), 0, s, A);
     return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -15,7 +15,8 @@ constexpr int kSqnMaxB = 1024;              // b and b_H
 constexpr uint32_t kSqnMaxN = 8192;         // features (two quads per thread at 1024 threads)
 constexpr int kSqnChunk = 8;                // values per workgroup reduction
 constexpr int kSqnLossBlock = 256;          // threads of the loss kernel
-constexpr uint32_t kSqnLossRows = 512;      // rows per workgroup of the loss kernel
+constexpr uint32_t kSqnLossRows = 512;      // rows per workgroup of the loss kernels
+constexpr uint32_t kSqnManySnap = 64;       // stored iterates from which the loss runs a lane per iterate
 
 struct SqnArgs {
     uint32_t n, ld, nq;                     // features; row stride (a multiple of 4); quads ld / 4
@@ -35,6 +36,7 @@ struct SqnArgs {
     double *wprev;                          // [R][ld] the previous window's average
     double *acc;                            // [R][ld] the current window's sum of iterates
     double *wsnap;                          // [n_ckpt + 1][R][ld] w after each checkpoint; the last is w^{K+1}
+    double *wt;                             // [ld][(n_ckpt + 1) R] the same, feature-major (many iterates)
     uint32_t *pairs;                        // [R] correction pairs computed
     double *loss_part;                      // [n_ckpt + 1][R][nblk][2] double-double partial sums
     uint32_t nblk;                          // loss workgroups per snapshot

@@ -83,6 +83,7 @@ int sim_run_sqn(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, u
     if ((rc = ensure(ctx, q.S, sizeof(double) * R * p->M * ld)) || (rc = ensure(ctx, q.Y, sizeof(double) * R * p->M * ld)) ||
         (rc = ensure(ctx, q.wprev, sizeof(double) * R * ld)) || (rc = ensure(ctx, q.acc, sizeof(double) * R * ld)) || (rc = ensure(ctx, q.wsnap, sizeof(double) * n_snap * ld)) ||
         (rc = ensure(ctx, q.pairs, sizeof(uint32_t) * R)) ||
+        (n_snap >= fw::kSqnManySnap && (rc = ensure(ctx, q.wt, sizeof(double) * n_snap * ld))) ||
         (rc = ensure(ctx, q.loss_part, sizeof(double) * 2 * n_snap * nblk)) ||
         (rc = ensure(ctx, q.fval, sizeof(double) * n_snap)) ||
         (rc = ensure(ctx, q.stats, sizeof(double) * (fw::kMaxStreams * fw::kStreamFields + 2))))
@@ -119,6 +120,7 @@ int sim_run_sqn(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, u
     A.wprev = static_cast<double *>(q.wprev.ptr);
     A.acc = static_cast<double *>(q.acc.ptr);
     A.wsnap = static_cast<double *>(q.wsnap.ptr);
+    A.wt = static_cast<double *>(q.wt.ptr);
     A.pairs = static_cast<uint32_t *>(q.pairs.ptr);
     A.loss_part = static_cast<double *>(q.loss_part.ptr);
     A.nblk = nblk;

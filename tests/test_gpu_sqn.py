@@ -90,6 +90,30 @@ def test_sqn_against_oracle(ctx, case):
     run_and_compare(ctx, X, z, c.pop("R"), c.pop("K"), 21, **c)
 
 
+def test_sqn_many_replications(ctx):
+    """140 stored iterates (70 replications, one checkpoint) take the loss kernel with a lane per
+    iterate: every F against the oracle's loss at the device's iterate, three replications against the
+    oracle's run, the statistics against those F."""
+    X, z = workloads.sqn_dataset(16, 52)
+    R, K = 70, 60
+    say(f"[sqn] many replications R={R}")
+    ctx.sqn_load(X, z)
+    ctx.run_sqn(R, K, 9, M=4, checkpoints=(30,))
+    st = ctx.sqn_stats()
+    g = ctx.sqn_paths()
+    O = oracle.SqnOracle(X, z, M=4, seed=9, ckpt=(30,))
+    for r in range(R):
+        f = O.loss(g["w"][r])
+        assert abs(g["F"][r] - f) <= 1e-12 * f, (r, g["F"][r], f)
+        fc = O.loss(g["w_ckpt"][0, r])
+        assert abs(g["F_ckpt"][0, r] - fc) <= 1e-12 * fc
+    for r in (0, 33, R - 1):
+        o = O.run(r, K)
+        assert rel(g["w"][r], o["w"]) <= W_RTOL and abs(g["F"][r] - o["F"]) <= F_RTOL * o["F"]
+    assert abs(st.mean - g["F"].mean()) <= 1e-13 * g["F"].mean()
+    assert abs(st.f_mean[0] - g["F_ckpt"][0].mean()) <= 1e-13 * g["F_ckpt"][0].mean()
+
+
 def test_sqn_instance_and_seed_streams(ctx):
     X, z = workloads.sqn_dataset(12, 40)
     run_and_compare(ctx, X, z, 2, 90, 0x1234_5678_9ABC, M=6, ckpt=(45,), instance=77)
