@@ -66,7 +66,8 @@ class WideProblem(ctypes.Structure):
                 ("instance", ctypes.c_uint32), ("n_ckpt", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("lam", ctypes.c_double), ("gap_eps", ctypes.c_double),
                 ("mu", ctypes.POINTER(ctypes.c_double)), ("sigma", ctypes.POINTER(ctypes.c_double)),
-                ("w0", ctypes.POINTER(ctypes.c_double)), ("ckpt", ctypes.c_int64 * MAX_CKPT)]
+                ("w0", ctypes.POINTER(ctypes.c_double)), ("ckpt", ctypes.c_int64 * MAX_CKPT),
+                ("n_sched", ctypes.POINTER(ctypes.c_int32))]
 
 
 class WideOut(ctypes.Structure):
@@ -276,7 +277,8 @@ class OracleProblem:
 class WideOracle:
     """Algorithm 1 at the paper's experimental shape (many assets, diagonal Sigma): wide.c."""
 
-    def __init__(self, mu, sigma, *, N, M=1, lam=0.5, w0=None, seed=0, instance=0, ckpt=(), gap_eps=1e-2):
+    def __init__(self, mu, sigma, *, N, M=1, lam=0.5, w0=None, seed=0, instance=0, ckpt=(), gap_eps=1e-2,
+                 n_sched=None):
         self.mu = np.ascontiguousarray(mu, dtype=np.float64)
         self.sigma = np.ascontiguousarray(sigma, dtype=np.float64)
         d = self.mu.shape[0]
@@ -291,6 +293,9 @@ class WideOracle:
         p.w0 = _dptr(self.w0) if self.w0 is not None else ctypes.POINTER(ctypes.c_double)()
         for i, c in enumerate(ck):
             p.ckpt[i] = int(c)
+        self.n_sched = None if n_sched is None else np.ascontiguousarray(n_sched, dtype=np.int32)
+        p.n_sched = (self.n_sched.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if self.n_sched is not None
+                     else ctypes.POINTER(ctypes.c_int32)())
         self.p = p
         self.d, self.N, self.M, self.ckpt = d, N, M, ck
 

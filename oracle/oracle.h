@@ -148,6 +148,9 @@ typedef struct {
     const double *sigma;    /* [d] */
     const double *w0;       /* [d] or NULL */
     int64_t ckpt[OR_MAX_CKPT];
+    /* Algorithm 1 lets the sample size N_k of epoch k adapt to k: n_sched[k] (>= 2) for every
+     * epoch k < ceil(T / M) of a run, or NULL for N in every epoch */
+    const int32_t *n_sched;
 } or_wide_problem;
 
 typedef struct {

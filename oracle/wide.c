@@ -10,7 +10,9 @@
  * or_path in oracle.c: returns R_i = mu + sigma .* z_i with z_i the standard normals
  * i d + j of the (replication, epoch) stream, the sample mean Eq. (5), the centred sample
  * covariance Eq. (4) applied to w, the gradient 2 lambda Sigma_hat w - Rbar, the vertex search
- * over W, the step 2/(t+2) and the update w + gamma (s - w).
+ * over W, the step 2/(t+2) and the update w + gamma (s - w). With a schedule n_sched, epoch k
+ * draws N_k = n_sched[k] returns (the comment of Algorithm 1's resampling step) and its statistics
+ * divide by N_k and N_k - 1.
  */
 #include "oracle.h"
 
@@ -20,10 +22,11 @@
 
 /* The returns R_i = mu + sigma .* z_i of one (replication, epoch), N x d row-major, and the
  * standard normals z behind them. */
-static void wide_returns(const or_wide_problem *p, uint64_t rep, uint64_t epoch, double *Rmat, double *z)
+static int wide_n(const or_wide_problem *p, uint64_t epoch) { return p->n_sched ? p->n_sched[epoch] : p->N; }
+
+static void wide_returns(const or_wide_problem *p, int N, uint64_t rep, uint64_t epoch, double *Rmat, double *z)
 {
     const int64_t d = p->d;
-    const int N = p->N;
     or_normals(p->seed, OR_DOMAIN_PATH, p->instance, rep, epoch, 0, (uint64_t)N * (uint64_t)d, z);
     for (int i = 0; i < N; ++i)
         for (int64_t j = 0; j < d; ++j) Rmat[(size_t)i * d + j] = p->mu[j] + p->sigma[j] * z[(size_t)i * d + j];
@@ -31,11 +34,10 @@ static void wide_returns(const or_wide_problem *p, uint64_t rep, uint64_t epoch,
 
 /* Eq. (5) and Eq. (4): Rbar and Sigma_hat w = (1/(N-1)) sum_i D_i (D_i' w), D_i = R_i - Rbar; the
  * gradient 2 lambda Sigma_hat w - Rbar. */
-static void wide_statistics(const or_wide_problem *p, const double *Rmat, const double *w, double *rbar,
+static void wide_statistics(const or_wide_problem *p, int N, const double *Rmat, const double *w, double *rbar,
                             double *sw, double *g)
 {
     const int64_t d = p->d;
-    const int N = p->N;
     for (int64_t j = 0; j < d; ++j) {
         double acc = 0.0;
         for (int i = 0; i < N; ++i) acc += Rmat[(size_t)i * d + j];
@@ -69,11 +71,10 @@ double or_wide_objective(const or_wide_problem *p, const double *w)
  * in absolute values through the noise coordinates (as or_path does with L = diag(sigma)), times
  * an accumulation depth N + ceil(log2 d) + 16 -- sums over the N samples run in order, sums over
  * the d assets as trees -- and a safety factor of 8. */
-static double wide_bound(const or_wide_problem *p, const double *z, const double *w, const double *g,
+static double wide_bound(const or_wide_problem *p, int N, const double *z, const double *w, const double *g,
                          double uroff, double *vabs, double *pabs)
 {
     const int64_t d = p->d;
-    const int N = p->N;
     double wabs = 0.0, amax = 0.0;
     for (int64_t m = 0; m < d; ++m) {
         vabs[m] = fabs(p->sigma[m]) * fabs(w[m]);
@@ -104,16 +105,16 @@ void or_wide_gradient(const or_wide_problem *p, uint64_t rep, uint64_t epoch, co
                       double uroff, double *bound)
 {
     const int64_t d = p->d;
-    const int N = p->N;
+    const int N = wide_n(p, epoch);
     double *Rmat = (double *)malloc(sizeof(double) * (size_t)N * d);
     double *z = (double *)malloc(sizeof(double) * (size_t)N * d);
     double *rbar = (double *)malloc(sizeof(double) * (size_t)d);
     double *sw = (double *)malloc(sizeof(double) * (size_t)d);
     double *vabs = (double *)malloc(sizeof(double) * (size_t)d);
     double *pabs = (double *)malloc(sizeof(double) * (size_t)N);
-    wide_returns(p, rep, epoch, Rmat, z);
-    wide_statistics(p, Rmat, w, rbar, sw, g);
-    if (bound) *bound = uroff > 0.0 ? wide_bound(p, z, w, g, uroff, vabs, pabs) : 0.0;
+    wide_returns(p, N, rep, epoch, Rmat, z);
+    wide_statistics(p, N, Rmat, w, rbar, sw, g);
+    if (bound) *bound = uroff > 0.0 ? wide_bound(p, N, z, w, g, uroff, vabs, pabs) : 0.0;
     free(pabs); free(vabs); free(sw); free(rbar); free(z); free(Rmat);
 }
 
@@ -121,19 +122,26 @@ int or_wide_path(const or_wide_problem *p, uint64_t rep, uint64_t T, const uint3
                  or_wide_out *out, uint32_t *decisions)
 {
     const int64_t d = p->d;
-    const int N = p->N, M = p->M;
-    if (d < 1 || N < 2 || M < 1 || T < 1 || T > 0xFFFFFFFEull || p->n_ckpt < 0 || p->n_ckpt > OR_MAX_CKPT ||
+    const int M = p->M;
+    if (d < 1 || M < 1 || T < 1 || T > 0xFFFFFFFEull || p->n_ckpt < 0 || p->n_ckpt > OR_MAX_CKPT ||
         !(p->lambda > 0.0) || !out->cnt || !out->wsum)
         return -1;
+    int Nmax = 0;                        /* the largest sample size of the run's epochs */
+    for (uint64_t e = 0; e * (uint64_t)M < T; ++e) {
+        const int Ne = wide_n(p, e);
+        if (Ne < 2) return -1;
+        if (Ne > Nmax) Nmax = Ne;
+    }
+    int N = p->N;
 
-    double *Rmat = (double *)malloc(sizeof(double) * (size_t)N * d);
-    double *z = (double *)malloc(sizeof(double) * (size_t)N * d);
+    double *Rmat = (double *)malloc(sizeof(double) * (size_t)Nmax * d);
+    double *z = (double *)malloc(sizeof(double) * (size_t)Nmax * d);
     double *w = (double *)malloc(sizeof(double) * (size_t)d);
     double *g = (double *)malloc(sizeof(double) * (size_t)d);
     double *rbar = (double *)malloc(sizeof(double) * (size_t)d);
     double *sw = (double *)malloc(sizeof(double) * (size_t)d);
     double *vabs = (double *)malloc(sizeof(double) * (size_t)d);
-    double *pabs = (double *)malloc(sizeof(double) * (size_t)N);
+    double *pabs = (double *)malloc(sizeof(double) * (size_t)Nmax);
 
     uint32_t *cnt = out->cnt;
     uint64_t *wsum = out->wsum;
@@ -150,8 +158,11 @@ int or_wide_path(const or_wide_problem *p, uint64_t rep, uint64_t T, const uint3
     int ck = 0;
     for (uint64_t t = 0; t < T; ++t) {
         const uint64_t epoch = t / (uint64_t)M;
-        if (t % (uint64_t)M == 0) wide_returns(p, rep, epoch, Rmat, z);   /* resample */
-        wide_statistics(p, Rmat, w, rbar, sw, g);
+        if (t % (uint64_t)M == 0) {                                     /* resample N_k returns */
+            N = wide_n(p, epoch);
+            wide_returns(p, N, rep, epoch, Rmat, z);
+        }
+        wide_statistics(p, N, Rmat, w, rbar, sw, g);
 
         /* the vertex search over W: e_j for the smallest g_j when it is negative, else the origin;
          * equal minima go to the lowest index */
@@ -166,7 +177,7 @@ int or_wide_path(const or_wide_problem *p, uint64_t rep, uint64_t T, const uint3
         const double margin = second - best;
         if (margin < out->min_margin) out->min_margin = margin;
 
-        const double bound = uroff > 0.0 ? wide_bound(p, z, w, g, uroff, vabs, pabs) : 0.0;
+        const double bound = uroff > 0.0 ? wide_bound(p, N, z, w, g, uroff, vabs, pabs) : 0.0;
         const int ambiguous = margin <= 2.0 * bound;
         if (ambiguous) out->n_ambiguous++;
         if (replay && replay[t] != a) {

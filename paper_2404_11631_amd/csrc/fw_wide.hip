@@ -68,7 +68,8 @@ __device__ __forceinline__ void wide_iterate(const WideArgs &A, uint32_t r, uint
 
 }  // namespace
 
-__global__ __launch_bounds__(kWideBlock) void wide_sample_kernel(WideArgs A, uint32_t epoch, float cw, int from_w0)
+__global__ __launch_bounds__(kWideBlock) void wide_sample_kernel(WideArgs A, uint32_t epoch, uint32_t Nk, float cw,
+                                                                 int from_w0)
 {
     __shared__ float sm[kWideBlock * 4];
     const uint32_t tid = threadIdx.x, c = tid / kWideQuads, aq = tid % kWideQuads;
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(kWideBlock) void wide_sample_kernel(WideArgs A, uin
 
     const PhiloxRow row = philox_row(epoch, r, A.k0);
     float s1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (uint32_t i = c; i < A.N; i += kWideChunks) {
+    for (uint32_t i = c; i < Nk; i += kWideChunks) {
         const Block4<float> z = normals_block_row(row, i * A.nq + q, A.dom, A.k0, A.k1);
         float p = 0.0f;
 #pragma unroll
@@ -113,12 +114,12 @@ __global__ __launch_bounds__(kWideBlock) void wide_sample_kernel(WideArgs A, uin
     }
 }
 
-// block i < N: dot_i = sum over the workgroups of z_i'v; block N: s1'v. One workgroup each.
-__global__ __launch_bounds__(kWideBlock) void wide_dot_kernel(WideArgs A)
+// block i < N_k: dot_i = sum over the workgroups of z_i'v; block N_k: s1'v. One workgroup each.
+__global__ __launch_bounds__(kWideBlock) void wide_dot_kernel(WideArgs A, uint32_t Nk)
 {
     __shared__ float sm[kWideBlock];
     const uint32_t i = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
-    const float *src = (i < A.N) ? A.part_dot + (static_cast<uint64_t>(r) * A.N + i) * A.nwg
+    const float *src = (i < Nk) ? A.part_dot + (static_cast<uint64_t>(r) * A.N + i) * A.nwg
                                  : A.part_qn + static_cast<uint64_t>(r) * A.nwg;
     float x = 0.0f;
     for (uint32_t g = tid; g < A.nwg; g += kWideBlock) x += src[g];
@@ -129,12 +130,13 @@ __global__ __launch_bounds__(kWideBlock) void wide_dot_kernel(WideArgs A)
         __syncthreads();
     }
     if (tid == 0) {
-        if (i < A.N) A.dot[static_cast<uint64_t>(r) * A.N + i] = sm[0];
+        if (i < Nk) A.dot[static_cast<uint64_t>(r) * A.N + i] = sm[0];
         else A.qn[r] = sm[0];
     }
 }
 
-__global__ __launch_bounds__(kWideBlock) void wide_gradient_kernel(WideArgs A, uint32_t epoch, float cw, int from_w0)
+__global__ __launch_bounds__(kWideBlock) void wide_gradient_kernel(WideArgs A, uint32_t epoch, WideEpoch E, float cw,
+                                                                   int from_w0)
 {
     __shared__ float sm[kWideBlock * 4];
     const uint32_t tid = threadIdx.x, c = tid / kWideQuads, aq = tid % kWideQuads;
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(kWideBlock) void wide_gradient_kernel(WideArgs A, u
     const PhiloxRow row = philox_row(epoch, r, A.k0);
     const float *dot = A.dot + static_cast<uint64_t>(r) * A.N;
     float s2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    for (uint32_t i = c; i < A.N; i += kWideChunks) {
+    for (uint32_t i = c; i < E.n; i += kWideChunks) {
         const Block4<float> z = normals_block_row(row, i * A.nq + q, A.dom, A.k0, A.k1);
         const float di = dot[i];
 #pragma unroll
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(kWideBlock) void wide_gradient_kernel(WideArgs A, u
     if (c == 0) {
         float w[4], v[4];
         wide_iterate(A, r, j0, active, cw, from_w0 != 0, w, v);
-        const float qn = A.qn[r] * A.inv_n;
+        const float qn = A.qn[r] * E.inv_n;
         float gmin = INFINITY, gw = 0.0f;
         uint32_t jmin = 0xFFFFFFFFu;
 #pragma unroll
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(kWideBlock) void wide_gradient_kernel(WideArgs A, u
             if (active) {
                 const uint32_t j = j0 + k;
                 const float s1k = A.s1[static_cast<uint64_t>(r) * A.d + j];
-                const float gj = A.c2_f[j] * (s2k - s1k * qn) - A.mu_f[j] - A.c1_f[j] * s1k;
+                const float gj = (A.c2_f[j] * E.sc2) * (s2k - s1k * qn) - A.mu_f[j] - (A.c1_f[j] * E.sc1) * s1k;
                 if (gj < gmin) {
                     gmin = gj;
                     jmin = j;
@@ -294,12 +296,13 @@ __global__ void wide_finalize_kernel(WideArgs A, uint32_t n_ckpt)
     *A.origin_total = origin;
 }
 
-int launch_wide_step(const WideArgs &A, uint64_t t, uint32_t epoch, float cw, bool from_w0, hipStream_t s)
+int launch_wide_step(const WideArgs &A, uint64_t t, uint32_t epoch, const WideEpoch &E, float cw, bool from_w0,
+                     hipStream_t s)
 {
     const dim3 grid(A.nwg, A.R);
-    hipLaunchKernelGGL(wide_sample_kernel, grid, dim3(kWideBlock), 0, s, A, epoch, cw, from_w0 ? 1 : 0);
-    hipLaunchKernelGGL(wide_dot_kernel, dim3(A.N + 1, A.R), dim3(kWideBlock), 0, s, A);
-    hipLaunchKernelGGL(wide_gradient_kernel, grid, dim3(kWideBlock), 0, s, A, epoch, cw, from_w0 ? 1 : 0);
+    hipLaunchKernelGGL(wide_sample_kernel, grid, dim3(kWideBlock), 0, s, A, epoch, E.n, cw, from_w0 ? 1 : 0);
+    hipLaunchKernelGGL(wide_dot_kernel, dim3(E.n + 1, A.R), dim3(kWideBlock), 0, s, A, E.n);
+    hipLaunchKernelGGL(wide_gradient_kernel, grid, dim3(kWideBlock), 0, s, A, epoch, E, cw, from_w0 ? 1 : 0);
     hipLaunchKernelGGL(wide_step_kernel, dim3(A.R), dim3(kWideBlock), 0, s, A, t);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -32,6 +32,8 @@ int validate(char *err, const sim_params *p, uint64_t R, uint64_t T)
     if (p->abi_version != SIM_ABI_VERSION)
         return fail(err, SIM_EINVAL, "abi_version %u != %u", p->abi_version, SIM_ABI_VERSION);
     if (p->d < 1 || p->d > SIM_MAX_D) return fail(err, SIM_EINVAL, "d=%u outside [1, 64]", p->d);
+    if (p->n_schedule)
+        return fail(err, SIM_EUNSUPPORTED, "n_schedule: per-epoch sample sizes run on sim_run_wide only");
     if (R < 1 || R > 0xFFFFFFFFull) return fail(err, SIM_EINVAL, "R=%llu outside [1, 2^32)", (unsigned long long)R);
     if (T < 1 || T > 0xFFFFFFFEull) return fail(err, SIM_EINVAL, "T=%llu outside [1, 2^32-2]", (unsigned long long)T);
     if (!p->mu) return fail(err, SIM_EINVAL, "mu is NULL");
@@ -145,6 +147,13 @@ int validate_wide(char *err, const sim_params *p, uint64_t R, uint64_t T)
     if (p->n_samples < 2 || p->n_samples > SIM_WIDE_MAX_N)
         return fail(err, SIM_EINVAL, "n_samples must be in [2, %u]", SIM_WIDE_MAX_N);
     if (p->resample_every < 1) return fail(err, SIM_EINVAL, "resample_every must be >= 1");
+    if (p->n_schedule) {
+        const uint64_t epochs = (T + p->resample_every - 1) / p->resample_every;
+        for (uint64_t e = 0; e < epochs; ++e)
+            if (p->n_schedule[e] < 2 || p->n_schedule[e] > SIM_WIDE_MAX_N)
+                return fail(err, SIM_EINVAL, "n_schedule[%llu] = %u outside [2, %u]", (unsigned long long)e,
+                            p->n_schedule[e], SIM_WIDE_MAX_N);
+    }
     if (p->noise != SIM_NOISE_GAUSS) return fail(err, SIM_EUNSUPPORTED, "the wide path draws Gaussian noise only");
     if (p->state_precision != SIM_FP32) return fail(err, SIM_EUNSUPPORTED, "the wide path runs in FP32 state");
     if (p->n_checkpoints > SIM_MAX_CKPT) return fail(err, SIM_EINVAL, "more than 8 checkpoints");

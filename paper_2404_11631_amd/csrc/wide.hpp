@@ -16,11 +16,12 @@ constexpr uint64_t kWideMaxD = 1ull << 22;
 
 struct WideArgs {
     // instance: d assets in nq = d/4 quads, nwg workgroups per replication
-    uint32_t d, nq, N, nwg, R;
+    uint32_t d, nq, N, nwg, R;                  // N: the largest sample size of the run (buffer stride)
     uint32_t k0, k1, dom;                       // Philox key, stream domain (path noise)
-    float inv_n, gap_eps;
+    float gap_eps;
     double lambda;
-    const float *mu_f, *sz_f, *c1_f, *c2_f, *w0_f;   // per asset; sz = sqrt(2 ln 2) sigma
+    // per asset; sz = sqrt(2 ln 2) sigma, c1 = sz / N0, c2 = 2 lambda sz / (N0 - 1) for the base size N0
+    const float *mu_f, *sz_f, *c1_f, *c2_f, *w0_f;
     const double *mu_d, *sig_d;
     // state of each replication r
     uint64_t *S;                                // [R][d] signature: sum of (t+1) over steps choosing e_j
@@ -43,8 +44,16 @@ struct WideArgs {
     uint64_t *origin_total;                     // [1] decisions for the origin over all replications
 };
 
-// One iteration: w_t = cw S (or w_0 at t = 0 when from_w0), epoch = t div M.
-int launch_wide_step(const WideArgs &A, uint64_t t, uint32_t epoch, float cw, bool from_w0, hipStream_t s);
+// The sample size of one epoch: N_k returns, 1/N_k, and the factors N0/N_k and (N0-1)/(N_k-1) that
+// turn the base coefficients c1, c2 into those of N_k (exactly 1 when N_k = N0).
+struct WideEpoch {
+    uint32_t n;
+    float inv_n, sc1, sc2;
+};
+
+// One iteration: w_t = cw S (or w_0 at t = 0 when from_w0), epoch = t div M of size E.
+int launch_wide_step(const WideArgs &A, uint64_t t, uint32_t epoch, const WideEpoch &E, float cw, bool from_w0,
+                     hipStream_t s);
 // f(w) at w = c S into fval[slot][r].
 int launch_wide_objective(const WideArgs &A, double c, uint32_t slot, hipStream_t s);
 // Cross-replication statistics of Y and of the n_ckpt checkpoints into stats.

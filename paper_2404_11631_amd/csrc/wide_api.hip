@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -21,6 +22,17 @@ int ensure_events(sim_ctx *ctx, WideState &w)
     return SIM_OK;
 }
 
+// The largest sample size over the run's epochs.
+uint32_t wide_nmax(const sim_params *p, uint64_t T)
+{
+    uint32_t n = p->n_samples;
+    if (p->n_schedule) {
+        const uint64_t epochs = (T + p->resample_every - 1) / p->resample_every;
+        for (uint64_t e = 0; e < epochs; ++e) n = std::max(n, p->n_schedule[e]);
+    }
+    return n;
+}
+
 // Device arguments over the context's wide buffers for problem p.
 fw::WideArgs wide_args(WideState &w, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed)
 {
@@ -28,13 +40,12 @@ fw::WideArgs wide_args(WideState &w, const sim_params *p, uint64_t R, uint64_t T
     const uint32_t d = p->d;
     A.d = d;
     A.nq = d / 4;
-    A.N = p->n_samples;
+    A.N = wide_nmax(p, T);
     A.nwg = w.nwg;
     A.R = static_cast<uint32_t>(R);
     A.k0 = static_cast<uint32_t>(seed);
     A.k1 = static_cast<uint32_t>(seed >> 32);
     A.dom = p->instance_id & 0xFFFFFFu;
-    A.inv_n = static_cast<float>(1.0 / p->n_samples);
     A.gap_eps = static_cast<float>(p->gap_eps);
     A.lambda = p->risk_coef;
     const float *af = static_cast<const float *>(w.asset_f.ptr);
@@ -86,6 +97,7 @@ int sim_run_wide(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint
     w.have = false;
     if (int rc = ensure_events(ctx, w)) return rc;
     const uint32_t d = p->d, N = p->n_samples, nc = p->n_checkpoints;
+    const uint32_t Nmax = wide_nmax(p, T);
     const uint32_t nq = d / 4;
     w.nwg = (nq + fw::kWideQuads - 1) / fw::kWideQuads;
     const size_t D = d;
@@ -109,8 +121,8 @@ int sim_run_wide(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint
         (rc = ensure(ctx, w.S, sizeof(uint64_t) * R * D)) || (rc = ensure(ctx, w.cnt, sizeof(uint32_t) * R * (D + 1))) ||
         (rc = ensure(ctx, w.tau, sizeof(uint32_t) * R)) || (rc = ensure(ctx, w.dec, sizeof(uint32_t) * R * T)) ||
         (rc = ensure(ctx, w.s1, sizeof(float) * R * D)) ||
-        (rc = ensure(ctx, w.part_dot, sizeof(float) * R * N * w.nwg)) ||
-        (rc = ensure(ctx, w.part_qn, sizeof(float) * R * w.nwg)) || (rc = ensure(ctx, w.dot, sizeof(float) * R * N)) ||
+        (rc = ensure(ctx, w.part_dot, sizeof(float) * R * Nmax * w.nwg)) ||
+        (rc = ensure(ctx, w.part_qn, sizeof(float) * R * w.nwg)) || (rc = ensure(ctx, w.dot, sizeof(float) * R * Nmax)) ||
         (rc = ensure(ctx, w.qn, sizeof(float) * R)) || (rc = ensure(ctx, w.wg_g, sizeof(float) * R * w.nwg)) ||
         (rc = ensure(ctx, w.wg_j, sizeof(uint32_t) * R * w.nwg)) || (rc = ensure(ctx, w.wg_gw, sizeof(float) * R * w.nwg)) ||
         (rc = ensure(ctx, w.fval, sizeof(double) * R * (nc + 1))) ||
@@ -132,7 +144,11 @@ int sim_run_wide(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint
     uint32_t ck = 0;
     for (uint64_t t = 0; t < T; ++t) {
         const float cw = t == 0 ? 0.0f : static_cast<float>(2.0 / (static_cast<double>(t) * static_cast<double>(t + 1)));
-        if (fw::launch_wide_step(A, t, static_cast<uint32_t>(t / M), cw, t == 0 && p->w0 != nullptr, st))
+        const uint64_t e = t / M;
+        const uint32_t Ne = p->n_schedule ? p->n_schedule[e] : N;
+        const fw::WideEpoch E{Ne, static_cast<float>(1.0 / Ne), static_cast<float>(static_cast<double>(N) / Ne),
+                              static_cast<float>((N - 1.0) / (Ne - 1.0))};
+        if (fw::launch_wide_step(A, t, static_cast<uint32_t>(e), E, cw, t == 0 && p->w0 != nullptr, st))
             return set_err(ctx, SIM_EDEVICE, "wide step launch failed at t=%llu", (unsigned long long)t);
         while (ck < nc && p->checkpoints[ck] == t + 1) {
             const double c = 2.0 / (static_cast<double>(t + 1) * static_cast<double>(t + 2));
@@ -147,6 +163,7 @@ int sim_run_wide(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint
 
     w.params = *p;
     w.params.mu = w.params.sigma = w.params.chol = w.params.w0 = w.params.cv_ref = nullptr;
+    w.params.n_schedule = nullptr;
     w.R = R;
     w.T = T;
     w.fstar = kkt_fstar(p->mu, p->sigma, d, p->risk_coef);

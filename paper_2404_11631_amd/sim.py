@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsim.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAX_D = 64
 MAX_CKPT = 8
 TAU_NONE = 0xFFFFFFFF
@@ -34,7 +34,8 @@ class SimParams(ctypes.Structure):
                 ("state_precision", ctypes.c_uint32), ("n_checkpoints", ctypes.c_uint32),
                 ("checkpoints", ctypes.c_uint64 * MAX_CKPT), ("gap_eps", ctypes.c_double),
                 ("flags", ctypes.c_uint32), ("instance_id", ctypes.c_uint32),
-                ("log_rep_begin", ctypes.c_uint64), ("log_rep_count", ctypes.c_uint64), ("cv_ref", _dp)]
+                ("log_rep_begin", ctypes.c_uint64), ("log_rep_count", ctypes.c_uint64), ("cv_ref", _dp),
+                ("n_schedule", ctypes.POINTER(ctypes.c_uint32))]
 
 
 class SimStats(ctypes.Structure):
@@ -285,6 +286,7 @@ class Problem:
     cv_features: bool = False          # write each path's d+2 control-variate features
     cv_ref: np.ndarray | None = None   # the features' reference gradient b
     instance_id: int = 0
+    n_schedule: tuple | None = None    # sim_run_wide: sample size N_k of every epoch
 
 
 def validate(p: Problem, R: int, T: int):
@@ -418,6 +420,10 @@ class Sim:
             b = np.ascontiguousarray(p.cv_ref, dtype=np.float64)
             keep.append(b)
             sp.cv_ref = b.ctypes.data_as(_dp)
+        if p.n_schedule is not None:
+            ns = np.ascontiguousarray(p.n_schedule, dtype=np.uint32)
+            keep.append(ns)
+            sp.n_schedule = ns.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
         return sp, keep
 
     def run(self, p: Problem, R: int, T: int, seed: int):

@@ -167,6 +167,22 @@ def test_wide_validation(lib):
     assert sim.validate_wide(sim.Problem(**ok, checkpoints=(10, 5)), 1, 20)[0] == -1
 
 
+def test_sample_size_schedule_validation(lib):
+    """Per-epoch sample sizes N_k: every entry of the ceil(T/M) epochs in [2, 1024] on the wide path;
+    every other entry point rejects a schedule as unsupported."""
+    mu, sig = workloads.diag_instance(0, 0, 64, "paper")
+    sch = [2 + k for k in range(50)]
+    assert sim.validate_wide(sim.Problem(mu=mu, sigma=sig, N=10, n_schedule=sch), 1, 50)[0] == 0
+    assert sim.validate_wide(sim.Problem(mu=mu, sigma=sig, N=10, M=3, n_schedule=sch[:17]), 1, 50)[0] == 0
+    bad = list(sch)
+    bad[49] = 1
+    assert sim.validate_wide(sim.Problem(mu=mu, sigma=sig, N=10, n_schedule=bad), 1, 50)[0] == -1
+    bad[49] = 1025
+    assert sim.validate_wide(sim.Problem(mu=mu, sigma=sig, N=10, n_schedule=bad), 1, 50)[0] == -1
+    assert sim.validate_wide(sim.Problem(mu=mu, sigma=sig, N=10, n_schedule=bad), 1, 49)[0] == 0   # 49 epochs
+    assert sim.validate(sim.Problem(mu=mu[:8], sigma=sig[:8], N=10, n_schedule=sch), 10, 50)[0] == -5
+
+
 def test_newsvendor_validation(lib):
     """Algorithm 2 (sim_run_newsvendor): n a multiple of 4, c > 0, C > 0, sigma >= 0, x0 in X,
     1 <= S <= 1024, R <= 64, R T <= 2^30."""

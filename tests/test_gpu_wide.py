@@ -45,12 +45,13 @@ def problem(d, N, M=1, seed=0, regime="paper", w0=False, ckpt=(), lam=0.5, insta
 
 def wide_oracle(p, seed):
     return oracle.WideOracle(p.mu, p.sigma, N=p.N, M=p.M, lam=p.lam, w0=p.w0, seed=seed, instance=p.instance_id,
-                             ckpt=p.checkpoints, gap_eps=p.gap_eps)
+                             ckpt=p.checkpoints, gap_eps=p.gap_eps, n_sched=p.n_schedule)
 
 
 def run_and_compare(ctx, p, R, T, seed):
     d = len(p.mu)
-    say(f"[wide] d={d} N={p.N} M={p.M} lam={p.lam} w0={p.w0 is not None} R={R} T={T} seed={seed}")
+    say(f"[wide] d={d} N={p.N} M={p.M} lam={p.lam} w0={p.w0 is not None} R={R} T={T} seed={seed} "
+        f"schedule={None if p.n_schedule is None else (min(p.n_schedule), max(p.n_schedule))}")
     ctx.run_wide(p, R, T, seed)
     st = ctx.wide_stats()
     g = ctx.wide_paths()
@@ -169,3 +170,29 @@ def test_paper_shape_sampled(ctx):
     wT = S * (2.0 / (T * (T + 1.0)))
     assert close(g["y"][0], W.objective(wT), 1e-11, 1e-14)
     assert close(g["f_ckpt"][-1, 0], g["y"][0], 1e-15, 0.0)
+
+
+@pytest.mark.parametrize("case", [
+    dict(d=64, N=10, M=1, T=120, R=2, sched="grow"),        # N_k = 2 + k / 4: 2 .. 31
+    dict(d=500, N=25, M=3, T=150, R=2, sched="geom"),       # N_k = ceil(4 * 1.1^k) capped at 300, M = 3
+    dict(d=1000, N=25, M=1, T=80, R=1, sched="same"),       # a constant schedule equal to N
+])
+def test_wide_sample_size_schedule(ctx, case):
+    """Algorithm 1 with per-epoch sample sizes N_k (the adaptive N_k its resampling step allows): the
+    same replay protocol against the oracle run with the same schedule; a constant schedule equal to
+    N reproduces the plain run bit for bit."""
+    d, N, M, T, R = case["d"], case["N"], case["M"], case["T"], case["R"]
+    E = (T + M - 1) // M
+    if case["sched"] == "grow":
+        sch = [2 + k // 4 for k in range(E)]
+    elif case["sched"] == "geom":
+        sch = [min(300, int(np.ceil(4 * 1.1 ** k))) for k in range(E)]
+    else:
+        sch = [N] * E
+    base = problem(d, N, M=M, seed=5, ckpt=(T // 2, T))
+    p = sim.Problem(**{**base.__dict__, "n_schedule": tuple(sch)})
+    st, g = run_and_compare(ctx, p, R, T, 17)
+    if case["sched"] == "same":
+        ctx.run_wide(base, R, T, 17)
+        plain = ctx.wide_paths()
+        assert np.array_equal(plain["decisions"], g["decisions"]) and np.array_equal(plain["y"], g["y"])

@@ -112,3 +112,73 @@ def test_bound_covers_a_binary32_evaluation(d, N):
         err = np.abs(g32.astype(np.float64) - g64).max()
         assert err <= bound, (err, bound)
         assert bound < 1e-2 * np.abs(g64).max()
+
+
+# ---- adaptive sample sizes N_k (Algorithm 1 lets the resample size depend on the epoch) ----------
+
+def test_constant_schedule_is_the_plain_run():
+    mu, sig = workloads.diag_instance(4, 0, 30)
+    plain = oracle.WideOracle(mu, sig, N=7, M=2, seed=4, ckpt=(9, 40))
+    sched = oracle.WideOracle(mu, sig, N=7, M=2, seed=4, ckpt=(9, 40), n_sched=[7] * 20)
+    for rep in (0, 3):
+        a, b = plain.path(rep, 40), sched.path(rep, 40)
+        assert np.array_equal(a["decisions"], b["decisions"]) and a["y"] == b["y"]
+        assert np.array_equal(a["f_ckpt"], b["f_ckpt"])
+
+
+def test_schedule_applies_each_epochs_size():
+    """The gradient of epoch k with a schedule is the plain gradient with N = N_k (same stream: the
+    first N_k returns of the (replication, epoch) draw), and the path's decisions are those of a
+    path whose epochs are run with their own N."""
+    d = 20
+    mu, sig = workloads.diag_instance(5, 0, d)
+    sch = [2, 9, 3, 30, 4]
+    S = oracle.WideOracle(mu, sig, N=5, M=3, seed=6, n_sched=sch)
+    w = np.random.default_rng(0).dirichlet(np.ones(d)) * 0.8
+    for k, Nk in enumerate(sch):
+        g, _ = S.gradient(1, k, w)
+        ref, _ = oracle.WideOracle(mu, sig, N=Nk, M=3, seed=6).gradient(1, k, w)
+        assert np.array_equal(g, ref)
+    full = S.path(1, 15)
+    for k, Nk in enumerate(sch):
+        # epoch k alone, from the iterate the schedule's path reached, with the plain oracle at N_k:
+        # the first decision of the epoch is the vertex of that gradient
+        t = 3 * k
+        dec = full["decisions"][:t]
+        wt = np.zeros(d)
+        for s, a in enumerate(dec):
+            gamma = 2.0 / (s + 2.0)
+            wt = (1 - gamma) * wt
+            if a:
+                wt[a - 1] += gamma
+        g, _ = oracle.WideOracle(mu, sig, N=Nk, M=3, seed=6).gradient(1, k, wt)
+        own = int(np.argmin(g)) + 1 if g.min() < 0 else 0
+        assert full["decisions"][t] == own
+
+
+def test_schedule_sample_mean_variance_and_covariance_bias():
+    """At w = 0 the gradient is -Rbar with Rbar_j ~ N(mu_j, sigma_j^2 / N_k): the spread over epochs
+    scales with 1/N_k (chi-square bounds); at w != 0, (g + Rbar)/(2 lambda) = Sigma_hat w averages to
+    Sigma w for every N_k (the 1/(N_k - 1) of Eq. (4)), here with N_k = 3 where 1/N_k would be off by 1/3."""
+    from scipy import stats
+    d = 6
+    mu, sig = workloads.diag_instance(7, 0, d)
+    E = 600
+    sch = [4 if k % 2 == 0 else 64 for k in range(E)]
+    S = oracle.WideOracle(mu, sig, N=4, seed=8, n_sched=sch)
+    g = np.array([S.gradient(0, k, np.zeros(d))[0] for k in range(E)])
+    for par, Nk in ((0, 4), (1, 64)):
+        x = g[par::2]
+        q = ((x + mu) ** 2 / (sig ** 2 / Nk)).sum(axis=0)          # sum of E/2 chi2(1) per asset
+        lo, hi = stats.chi2.ppf([1e-4, 1 - 1e-4], E // 2)
+        assert np.all((q > lo) & (q < hi)), (Nk, q)
+    w = np.full(d, 1.0 / d)
+    S3 = oracle.WideOracle(mu, sig, N=3, seed=9, n_sched=[3] * 4000)
+    est = []
+    for k in range(4000):
+        gk, _ = S3.gradient(0, k, w)
+        est.append(gk)
+    # E g = 2 lambda Sigma w - mu with lambda = 1/2
+    m = np.mean(est, axis=0)
+    se = np.std(est, axis=0, ddof=1) / np.sqrt(4000)
+    assert np.all(np.abs(m - (sig ** 2 * w - mu)) < 5 * se)
