@@ -49,6 +49,8 @@ OPS_PER_ASSET_STEP = 15
 PEAK_OPS = 256 * 2.4e9 * 128
 # HBM3E bandwidth of one MI355X, bytes/s
 PEAK_HBM = 8.0e12
+# dense FP64 matrix-core rate of one MI355X, flop/s
+PEAK_F64 = 78.6e12
 
 
 def ops_per_path_step(d: int, N: int) -> float:
@@ -447,6 +449,17 @@ def sqn_shape_leg(ctx, sim, runs: int, warmup: int, throughput_sizes=(5_000,), s
                      "iterations_per_s": K / (kavg * 1e-3), "F": st.mean,
                      "F_ckpt": [st.f_mean[c] for c in range(len(w["checkpoints"]))]}
             if n in throughput_sizes and bH == w["bH"][0]:
+                # Algorithm 4's matrix formed from the pairs of that run (sim_sqn_hessian): the n x n
+                # product on the FP64 matrix cores, 2 n^2 Kp flops (Kp = 2m rounded up to 4) and the
+                # 8 n^2 bytes of H written
+                hs = [ctx.sqn_hessian(0, copy=False) for _ in range(runs + 1)][1:]
+                hms = sum(h["device_ms"] for h in hs) / len(hs)
+                m = hs[0]["m"]
+                Kp = (2 * m + 3) // 4 * 4
+                entry["hessian"] = {"m": m, "device_ms": hms,
+                                    "tflops": 2.0 * n * n * Kp / (hms * 1e-3) / 1e12,
+                                    "frac_fp64_mfma": 2.0 * n * n * Kp / (hms * 1e-3) / PEAK_F64,
+                                    "write_GBps": 8.0 * n * n / (hms * 1e-3) / 1e9}
                 R = w["R_batch"]
                 ctx.run_sqn(R, K, seed + 2000, **kw)
                 ctx.sqn_stats()

@@ -432,9 +432,28 @@ typedef struct {
     const double *w;            /* [R][ld] w^{K+1} */
     const double *w_ckpt;       /* [n_checkpoints][R][ld] */
     const uint32_t *pairs;      /* [R] correction pairs computed */
+    uint32_t M, pad2_;          /* ring slots per replication */
+    const double *S, *Y;        /* [R][M][ld] the stored pairs; with P = pairs[r], the min(P, M) newest,
+                                   the oldest at slot (P >= M ? P mod M : 0), then cyclically */
 } sim_sqn_view;
 
 int sim_sqn_paths(sim_ctx *ctx, sim_sqn_view *out);
+
+/* Algorithm 4's matrix H_t formed explicitly: gamma I and the BFGS updates over the m = min(P, M)
+ * pairs that replication `rep` of the last SQN run holds (the matrix its next iteration would
+ * apply), as H = gamma I + U W U' with U = [S, gamma Y] and the 2m x 2m middle matrix W of the
+ * compact representation, the n x n product on the FP64 matrix cores. Synchronous. Errors:
+ * SIM_ESTATE without a run or when the replication has no pair yet, SIM_EINVAL for rep >= R. */
+typedef struct {
+    uint32_t n, m;
+    uint32_t ld, pad_;          /* row stride of H: n rounded up to a multiple of 16 (128-byte rows) */
+    double gamma;               /* s_t'y_t / y_t'y_t of the newest pair */
+    const double *H;            /* device, [n][ld] row-major (columns n..ld-1 unset), owned by the
+                                   context until the next call */
+    double device_ms;           /* the four launches, HIP events */
+} sim_sqn_hessian_view;
+
+int sim_sqn_hessian(sim_ctx *ctx, uint64_t rep, sim_sqn_hessian_view *out);
 
 /* Statistics of the last run; synchronises the stream. */
 int sim_stats(sim_ctx *ctx, sim_stats_out *out);

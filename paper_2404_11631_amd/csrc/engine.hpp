@@ -91,7 +91,8 @@ struct SqnState {
     uint64_t R = 0, K = 0;
     uint32_t nblk = 0;
     DevBuf X, z, S, Y, wprev, acc, wsnap, wt, pairs, loss_part, fval, stats;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+    DevBuf H, hscratch;                   // sim_sqn_hessian: the n x n matrix and its work space
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr;
 };
 
 struct sim_ctx {

@@ -542,6 +542,202 @@ __global__ __launch_bounds__(kSqnLossBlock) void sqn_loss_many_kernel(SqnArgs A,
     }
 }
 
+// ---- Algorithm 4's matrix, formed (sim_sqn_hessian) ---------------------------------------------
+// H_t = gamma I + U W U' with U = [S, gamma Y] (n x 2m, pairs oldest first) and
+// W = [[C, -R^-T], [-R^-1, 0]] from the compact representation; four launches: the Gram entries
+// s_i'y_j and y_i'y_j, the 2m x 2m middle matrix, V = U W and U' feature-major, and the n x n
+// product V U' on the FP64 matrix cores.
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// SY[i][j] = s_i'y_j, YY[i][j] = y_i'y_j (chronological i, j < m) of replication rep: a workgroup
+// per (i, j), a fixed-order tree over the features.
+__global__ __launch_bounds__(256) void sqn_gram_kernel(SqnArgs A, uint32_t rep, uint32_t head, uint32_t m, double *SY,
+                                                       double *YY)
+{
+    __shared__ double s_a[256], s_b[256];
+    const uint32_t i = blockIdx.x, j = blockIdx.y, M = A.M;
+    const size_t base = static_cast<size_t>(rep) * M * A.ld;
+    const double *si = A.S + base + static_cast<size_t>((head + i) % M) * A.ld;
+    const double *yi = A.Y + base + static_cast<size_t>((head + i) % M) * A.ld;
+    const double *yj = A.Y + base + static_cast<size_t>((head + j) % M) * A.ld;
+    double a = 0.0, b = 0.0;
+    for (uint32_t k = threadIdx.x; k < A.ld; k += blockDim.x) {
+        a += si[k] * yj[k];
+        b += yi[k] * yj[k];
+    }
+    s_a[threadIdx.x] = a;
+    s_b[threadIdx.x] = b;
+    __syncthreads();
+    for (uint32_t h = blockDim.x / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            s_a[threadIdx.x] += s_a[threadIdx.x + h];
+            s_b[threadIdx.x] += s_b[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        SY[i * m + j] = s_a[0];
+        YY[i * m + j] = s_b[0];
+    }
+}
+
+// W (Kp x Kp, zero beyond 2m) and gamma from SY, YY: R^-1 by column back substitution, then
+// C = R^-T (D + gamma Y'Y) R^-1. One workgroup.
+__global__ __launch_bounds__(256) void sqn_middle_kernel(uint32_t m, uint32_t Kp, const double *SYg, const double *YYg,
+                                                         double *W, double *gamma_out)
+{
+    __shared__ double SY[kSqnMaxM * kSqnMaxM], YY[kSqnMaxM * kSqnMaxM];
+    __shared__ double s_Ri[kSqnMaxM * kSqnMaxM], s_T[kSqnMaxM * kSqnMaxM];
+    const uint32_t tid = threadIdx.x, T = blockDim.x;
+    for (uint32_t u = tid; u < m * m; u += T) {
+        SY[u] = SYg[u];
+        YY[u] = YYg[u];
+    }
+    __syncthreads();
+    const double gamma = SY[(m - 1) * m + (m - 1)] / YY[(m - 1) * m + (m - 1)];
+    if (tid < m) {
+        const uint32_t c = tid;
+        for (uint32_t i = c + 1; i < m; ++i) s_Ri[i * kSqnMaxM + c] = 0.0;
+        s_Ri[c * kSqnMaxM + c] = 1.0 / SY[c * m + c];
+        for (int i = static_cast<int>(c) - 1; i >= 0; --i) {
+            double acc = 0.0;
+            for (uint32_t l = i + 1; l <= c; ++l) acc += SY[i * m + l] * s_Ri[l * kSqnMaxM + c];
+            s_Ri[i * kSqnMaxM + c] = -acc / SY[i * m + i];
+        }
+    }
+    __syncthreads();
+    for (uint32_t u = tid; u < m * m; u += T) {
+        const uint32_t i = u / m, c = u % m;
+        double acc = 0.0;
+        for (uint32_t l = 0; l <= c; ++l) acc += (gamma * YY[i * m + l] + (i == l ? SY[i * m + i] : 0.0)) * s_Ri[l * kSqnMaxM + c];
+        s_T[i * kSqnMaxM + c] = acc;
+    }
+    __syncthreads();
+    for (uint32_t u = tid; u < Kp * Kp; u += T) {
+        const uint32_t r = u / Kp, c = u % Kp;
+        double v = 0.0;
+        if (r < m && c < m) {
+            for (uint32_t l = 0; l <= r; ++l) v += s_Ri[l * kSqnMaxM + r] * s_T[l * kSqnMaxM + c];
+        } else if (r < m && c < 2 * m) {
+            v = -s_Ri[(c - m) * kSqnMaxM + r];            // -R^-T
+        } else if (r < 2 * m && c < m) {
+            v = -s_Ri[(r - m) * kSqnMaxM + c];            // -R^-1
+        }
+        W[u] = v;
+    }
+    if (tid == 0) *gamma_out = gamma;
+}
+
+// Ut[a][k] = U[a][k] and V[a][c] = sum_k U[a][k] W[k][c], feature-major (Kp per feature, zero
+// padded): a wavefront per feature a, a lane per column c.
+__global__ __launch_bounds__(256) void sqn_uv_kernel(SqnArgs A, uint32_t rep, uint32_t head, uint32_t m, uint32_t Kp,
+                                                     const double *W, const double *gamma_p, double *V, double *Ut)
+{
+    __shared__ double s_W[2 * kSqnMaxM * 2 * kSqnMaxM];
+    __shared__ double s_u[4][2 * kSqnMaxM];
+    for (uint32_t u = threadIdx.x; u < Kp * Kp; u += blockDim.x) s_W[u] = W[u];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t a = blockIdx.x * 4 + wave;
+    const double gamma = *gamma_p;
+    const uint32_t M = A.M;
+    const size_t base = static_cast<size_t>(rep) * M * A.ld;
+    double x = 0.0;
+    if (a < A.n) {
+        if (lane < m) x = A.S[base + static_cast<size_t>((head + lane) % M) * A.ld + a];
+        else if (lane < 2 * m) x = gamma * A.Y[base + static_cast<size_t>((head + lane - m) % M) * A.ld + a];
+    }
+    s_u[wave][lane] = x;
+    __syncthreads();
+    if (a >= A.n || lane >= Kp) return;
+    Ut[static_cast<size_t>(a) * Kp + lane] = x;
+    double v = 0.0;
+    for (uint32_t k = 0; k < 2 * m; ++k) v += s_u[wave][k] * s_W[k * Kp + lane];
+    V[static_cast<size_t>(a) * Kp + lane] = v;
+}
+
+// H[a][b] = gamma [a == b] + sum_k V[a][k] Ut[b][k] over a 64 x 64 tile per workgroup: each wavefront
+// a 32 x 32 quarter as 2 x 2 tiles of v_mfma_f64_16x16x4f64 (A operand: row lane % 16, k lane / 16;
+// B operand: k lane / 16, column lane % 16; result register i: row lane / 16 + 4 i, column lane % 16,
+// as measured on gfx950 -- unlike the 4 (lane / 16) + i rows of the binary32 16x16x4 form).
+__global__ __launch_bounds__(256) void sqn_hessian_mfma_kernel(uint32_t n, uint32_t ldh, uint32_t Kp, const double *V,
+                                                               const double *Ut, const double *gamma_p, double *H)
+{
+    // the workgroup's 64 rows of V and of Ut are contiguous (64 Kp doubles each): 16-byte loads into LDS
+    __shared__ double s_A[64 * 2 * kSqnMaxM], s_B[64 * 2 * kSqnMaxM];
+    const uint32_t ra = blockIdx.y * 64, rb = blockIdx.x * 64;
+    const uint32_t na = min(64u, n - ra) * Kp, nb = min(64u, n - rb) * Kp;
+    const double2 *ga = reinterpret_cast<const double2 *>(V + static_cast<size_t>(ra) * Kp);
+    const double2 *gb = reinterpret_cast<const double2 *>(Ut + static_cast<size_t>(rb) * Kp);
+    for (uint32_t u = threadIdx.x; u < 32 * Kp; u += blockDim.x) {
+        const double2 x = 2 * u < na ? ga[u] : make_double2(0.0, 0.0);
+        const double2 y = 2 * u < nb ? gb[u] : make_double2(0.0, 0.0);
+        s_A[2 * u] = x.x;
+        s_A[2 * u + 1] = x.y;
+        s_B[2 * u] = y.x;
+        s_B[2 * u + 1] = y.y;
+    }
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t ta = (wave >> 1) * 32, tb = (wave & 1) * 32;      // the wavefront's quarter of the tile
+    const uint32_t lr = lane & 15, lk = lane >> 4;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (uint32_t kb = 0; kb < Kp; kb += 4) {
+        double av[2], bv[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            av[x] = s_A[(ta + 16 * x + lr) * Kp + kb + lk];
+            bv[x] = s_B[(tb + 16 * x + lr) * Kp + kb + lk];
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+    }
+    // the tile through LDS (s_A is free once every wavefront is past its last product), then whole
+    // 512-byte row segments per store
+    __syncthreads();
+    double *tile = s_A;                                              // [64][64]
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) tile[(ta + 16 * x + lk + 4 * i) * 64 + tb + 16 * y + lr] = acc[x][y][i];
+    __syncthreads();
+    const double gamma = *gamma_p;
+    const uint32_t c2 = 2 * (threadIdx.x & 31), r8 = threadIdx.x >> 5;
+    for (uint32_t r = r8; r < 64; r += 8) {
+        const uint32_t row = ra + r, col = rb + c2;
+        if (row >= n) break;
+        double2 v = make_double2(tile[r * 64 + c2], tile[r * 64 + c2 + 1]);
+        if (row == col) v.x += gamma;
+        if (row == col + 1) v.y += gamma;
+        double *dst = H + static_cast<size_t>(row) * ldh + col;
+        if (col + 1 < n) *reinterpret_cast<double2 *>(dst) = v;
+        else if (col < n) dst[0] = v.x;
+    }
+}
+
+int launch_sqn_hessian(const SqnArgs &A, uint32_t rep, uint32_t head, uint32_t m, double *scratch, double *H,
+                       uint32_t ldh, hipStream_t s)
+{
+    const uint32_t Kp = (2 * m + 3) / 4 * 4;
+    double *SY = scratch, *YY = SY + kSqnMaxM * kSqnMaxM, *W = YY + kSqnMaxM * kSqnMaxM;
+    double *gamma = W + 4 * kSqnMaxM * kSqnMaxM;
+    double *V = gamma + 4, *Ut = V + static_cast<size_t>(A.n) * Kp;
+    hipLaunchKernelGGL(sqn_gram_kernel, dim3(m, m), dim3(256), 0, s, A, rep, head, m, SY, YY);
+    hipLaunchKernelGGL(sqn_middle_kernel, dim3(1), dim3(256), 0, s, m, Kp, SY, YY, W, gamma);
+    hipLaunchKernelGGL(sqn_uv_kernel, dim3((A.n + 3) / 4), dim3(256), 0, s, A, rep, head, m, Kp, W, gamma, V, Ut);
+    const uint32_t nt = (A.n + 63) / 64;
+    hipLaunchKernelGGL(sqn_hessian_mfma_kernel, dim3(nt, nt), dim3(256), 0, s, A.n, ldh, Kp, V, Ut, gamma, H);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // F per stored iterate: the workgroups' partials in order, divided by N.
 __global__ void sqn_loss_final_kernel(SqnArgs A, uint32_t n_snap)
 {

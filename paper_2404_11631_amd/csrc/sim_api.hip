@@ -171,9 +171,9 @@ void sim_destroy(sim_ctx *ctx)
     for (hipEvent_t e : {nv.ev0, nv.ev1})
         if (e) (void)hipEventDestroy(e);
     SqnState &sq = ctx->sqn;
-    for (DevBuf *x : {&sq.X, &sq.z, &sq.S, &sq.Y, &sq.wprev, &sq.acc, &sq.wsnap, &sq.wt, &sq.pairs, &sq.loss_part, &sq.fval, &sq.stats})
+    for (DevBuf *x : {&sq.X, &sq.z, &sq.S, &sq.Y, &sq.wprev, &sq.acc, &sq.wsnap, &sq.wt, &sq.H, &sq.hscratch, &sq.pairs, &sq.loss_part, &sq.fval, &sq.stats})
         free_buf(*x);
-    for (hipEvent_t e : {sq.ev0, sq.ev1, sq.ev2})
+    for (hipEvent_t e : {sq.ev0, sq.ev1, sq.ev2, sq.ev3, sq.ev4})
         if (e) (void)hipEventDestroy(e);
     delete ctx;
 }

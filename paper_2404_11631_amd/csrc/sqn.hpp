@@ -46,5 +46,11 @@ struct SqnArgs {
 
 int launch_sqn_run(const SqnArgs &A, hipStream_t s);
 int launch_sqn_loss(const SqnArgs &A, hipStream_t s);
+// Algorithm 4's H_t (n x n, row stride ldh, a multiple of 16) of replication rep from its m newest
+// pairs (the oldest at ring slot head). scratch holds at least sqn_hessian_scratch(n) doubles.
+int launch_sqn_hessian(const SqnArgs &A, uint32_t rep, uint32_t head, uint32_t m, double *scratch, double *H,
+                       uint32_t ldh, hipStream_t s);
+inline uint32_t sqn_hessian_ld(uint32_t n) { return (n + 15) / 16 * 16; }
+inline size_t sqn_hessian_scratch(uint32_t n) { return 6 * kSqnMaxM * kSqnMaxM + 4 + 2 * static_cast<size_t>(n) * 2 * kSqnMaxM; }
 
 }  // namespace fw

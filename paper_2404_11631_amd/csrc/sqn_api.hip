@@ -180,6 +180,56 @@ int sim_sqn_paths(sim_ctx *ctx, sim_sqn_view *out)
     out->w = ws + static_cast<size_t>(nc) * q.R * q.ld;
     out->w_ckpt = nc ? ws : nullptr;
     out->pairs = static_cast<const uint32_t *>(q.pairs.ptr);
+    out->M = q.params.M;
+    out->S = static_cast<const double *>(q.S.ptr);
+    out->Y = static_cast<const double *>(q.Y.ptr);
+    return SIM_OK;
+}
+
+int sim_sqn_hessian(sim_ctx *ctx, uint64_t rep, sim_sqn_hessian_view *out)
+{
+    if (!ctx || !out) return SIM_EINVAL;
+    SqnState &q = ctx->sqn;
+    if (!q.have) return set_err(ctx, SIM_ESTATE, "no SQN run yet");
+    if (rep >= q.R) return set_err(ctx, SIM_EINVAL, "rep=%llu outside [0, %llu)", (unsigned long long)rep, (unsigned long long)q.R);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipEventSynchronize(q.ev2));
+    uint32_t P = 0;
+    HIP_TRY(ctx, hipMemcpy(&P, static_cast<const uint32_t *>(q.pairs.ptr) + rep, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    const uint32_t M = q.params.M;
+    const uint32_t m = P < M ? P : M, head = P >= M ? P % M : 0;
+    if (m == 0) return set_err(ctx, SIM_ESTATE, "replication %llu has no correction pair yet", (unsigned long long)rep);
+    for (hipEvent_t *e : {&q.ev3, &q.ev4})
+        if (!*e) HIP_TRY(ctx, hipEventCreate(e));
+    int rc;
+    const uint32_t ldh = fw::sqn_hessian_ld(q.n);
+    if ((rc = ensure(ctx, q.H, sizeof(double) * q.n * ldh)) ||
+        (rc = ensure(ctx, q.hscratch, sizeof(double) * fw::sqn_hessian_scratch(q.n))))
+        return rc;
+    fw::SqnArgs A{};
+    A.n = q.n;
+    A.ld = q.ld;
+    A.M = M;
+    A.S = static_cast<double *>(q.S.ptr);
+    A.Y = static_cast<double *>(q.Y.ptr);
+    hipStream_t st = ctx->stream;
+    HIP_TRY(ctx, hipEventRecord(q.ev3, st));
+    if (fw::launch_sqn_hessian(A, static_cast<uint32_t>(rep), head, m, static_cast<double *>(q.hscratch.ptr),
+                               static_cast<double *>(q.H.ptr), ldh, st))
+        return set_err(ctx, SIM_EDEVICE, "Hessian launch failed");
+    HIP_TRY(ctx, hipEventRecord(q.ev4, st));
+    HIP_TRY(ctx, hipEventSynchronize(q.ev4));
+    double gamma = 0.0;
+    const double *gp = static_cast<const double *>(q.hscratch.ptr) + 6 * fw::kSqnMaxM * fw::kSqnMaxM;
+    HIP_TRY(ctx, hipMemcpy(&gamma, gp, sizeof(double), hipMemcpyDeviceToHost));
+    float ms = 0.0f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ms, q.ev3, q.ev4));
+    out->n = q.n;
+    out->ld = ldh;
+    out->m = m;
+    out->gamma = gamma;
+    out->H = static_cast<const double *>(q.H.ptr);
+    out->device_ms = ms;
     return SIM_OK;
 }
 

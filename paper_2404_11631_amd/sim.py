@@ -157,7 +157,13 @@ class SimSqnView(ctypes.Structure):
     _fields_ = [("R", ctypes.c_uint64), ("K", ctypes.c_uint64), ("n", ctypes.c_uint32), ("ld", ctypes.c_uint32),
                 ("n_checkpoints", ctypes.c_uint32), ("pad_", ctypes.c_uint32), ("F", ctypes.c_void_p),
                 ("F_ckpt", ctypes.c_void_p), ("w", ctypes.c_void_p), ("w_ckpt", ctypes.c_void_p),
-                ("pairs", ctypes.c_void_p)]
+                ("pairs", ctypes.c_void_p), ("M", ctypes.c_uint32), ("pad2_", ctypes.c_uint32),
+                ("S", ctypes.c_void_p), ("Y", ctypes.c_void_p)]
+
+
+class SimSqnHessianView(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("m", ctypes.c_uint32), ("ld", ctypes.c_uint32), ("pad_", ctypes.c_uint32),
+                ("gamma", ctypes.c_double), ("H", ctypes.c_void_p), ("device_ms", ctypes.c_double)]
 
 
 def sqn_params(L: int = 10, M: int = 25, b: int = 50, bH: int = 300, beta: float = 2.0, checkpoints=(),
@@ -192,7 +198,7 @@ EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_run_b
            "sim_mlp_set_params", "sim_mlp_get_params", "sim_mlp_forward", "sim_mlp_grad", "sim_cv_aux_draws",
            "sim_cv_law", "sim_run_wide", "sim_validate_wide", "sim_wide_stats", "sim_wide_paths",
            "sim_run_newsvendor", "sim_validate_newsvendor", "sim_nv_stats", "sim_nv_paths",
-           "sim_sqn_load", "sim_run_sqn", "sim_validate_sqn", "sim_sqn_stats", "sim_sqn_paths")
+           "sim_sqn_load", "sim_run_sqn", "sim_validate_sqn", "sim_sqn_stats", "sim_sqn_paths", "sim_sqn_hessian")
 
 _lib = None
 
@@ -256,6 +262,7 @@ def load():
                                        ctypes.c_size_t]
         L.sim_sqn_stats.argtypes = [vp, ctypes.POINTER(SimStats)]
         L.sim_sqn_paths.argtypes = [vp, ctypes.POINTER(SimSqnView)]
+        L.sim_sqn_hessian.argtypes = [vp, u64, ctypes.POINTER(SimSqnHessianView)]
         _lib = L
     return _lib
 
@@ -497,6 +504,26 @@ class Sim:
         out["w_ckpt"] = (self._copy(v.w_ckpt, np.float64, nc * R * ld).reshape(nc, R, ld)[:, :, :n] if nc
                          else np.zeros((0, R, n)))
         out["pairs"] = self._copy(v.pairs, np.uint32, R)
+        M = v.M
+        S = self._copy(v.S, np.float64, R * M * ld).reshape(R, M, ld)[:, :, :n]
+        Y = self._copy(v.Y, np.float64, R * M * ld).reshape(R, M, ld)[:, :, :n]
+        out["S"], out["Y"] = [], []
+        for r in range(R):                      # each replication's pairs, oldest first
+            P = int(out["pairs"][r])
+            m, head = min(P, M), (P % M if P >= M else 0)
+            order = [(head + i) % M for i in range(m)]
+            out["S"].append(S[r, order])
+            out["Y"].append(Y[r, order])
+        return out
+
+    def sqn_hessian(self, rep: int, copy: bool = True) -> dict:
+        """Algorithm 4's H_t of replication rep of the last SQN run (sim_sqn_hessian): n, m, gamma,
+        device_ms and, with copy, H [n][n] on the host."""
+        v = SimSqnHessianView()
+        self._check(self.L.sim_sqn_hessian(self.h, rep, ctypes.byref(v)))
+        out = dict(n=v.n, m=v.m, gamma=v.gamma, device_ms=v.device_ms)
+        if copy:
+            out["H"] = self._copy(v.H, np.float64, v.n * v.ld).reshape(v.n, v.ld)[:, :v.n].copy()
         return out
 
     def wide_paths(self) -> dict:

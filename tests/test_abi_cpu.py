@@ -47,7 +47,8 @@ def test_struct_layout_matches_header():
                "sim_cv_opts": sim.SimCvOpts, "sim_cv_fit_out": sim.SimCvFitOut,
                "sim_cv_stats_out": sim.SimCvStats, "sim_cv_view": sim.SimCvView,
                "sim_wide_view": sim.SimWideView, "sim_nv_params": sim.SimNvParams,
-               "sim_sqn_params": sim.SimSqnParams, "sim_sqn_view": sim.SimSqnView}
+               "sim_sqn_params": sim.SimSqnParams, "sim_sqn_view": sim.SimSqnView,
+               "sim_sqn_hessian_view": sim.SimSqnHessianView}
     fields = {name: [f[0] for f in cls._fields_] for name, cls in mirrors.items()}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
     for st, fs in fields.items():

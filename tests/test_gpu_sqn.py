@@ -114,6 +114,36 @@ def test_sqn_many_replications(ctx):
     assert abs(st.f_mean[0] - g["F_ckpt"][0].mean()) <= 1e-13 * g["F_ckpt"][0].mean()
 
 
+@pytest.mark.parametrize("n,M,K", [(37, 4, 120), (300, 25, 200), (1000, 7, 150), (4100, 3, 60)])
+def test_sqn_explicit_hessian(ctx, n, M, K):
+    """Algorithm 4's matrix formed on the device (sim_sqn_hessian) from the pairs each replication
+    holds, against the oracle's explicit chain of BFGS updates over the same pairs (read back from
+    the device's ring, oldest first): Frobenius-relative 1e-10, gamma of the newest pair, the secant
+    equation H y_t = s_t, symmetry."""
+    X, z = workloads.sqn_dataset(17, n, min(30 * n, 6000))
+    say(f"[sqn] explicit H n={n} M={M} K={K}")
+    ctx.sqn_load(X, z)
+    ctx.run_sqn(2, K, 3, M=M)
+    g = ctx.sqn_paths()
+    for r in range(2):
+        h = ctx.sqn_hessian(r)
+        S, Y = g["S"][r], g["Y"][r]
+        assert h["m"] == len(S) == min(int(g["pairs"][r]), M) and h["n"] == n
+        ref = oracle.SqnOracle.hessian_approx(S, Y)
+        err = np.linalg.norm(h["H"] - ref) / np.linalg.norm(ref)
+        say(f"[sqn] rep {r}: m={h['m']} rel err {err:.2e}, {h['device_ms']:.3f} ms")
+        assert err <= 1e-10
+        gam = (S[-1] @ Y[-1]) / (Y[-1] @ Y[-1])
+        assert abs(h["gamma"] - gam) <= 1e-12 * abs(gam)
+        assert np.linalg.norm(h["H"] @ Y[-1] - S[-1]) <= 1e-8 * np.linalg.norm(S[-1])
+        assert np.allclose(h["H"], h["H"].T, rtol=0, atol=1e-12 * np.abs(h["H"]).max())
+    with pytest.raises(sim.SimError):
+        ctx.sqn_hessian(2)
+    ctx.run_sqn(1, 15, 3, M=M)                     # k = 15 < 2L: no pair yet
+    with pytest.raises(sim.SimError):
+        ctx.sqn_hessian(0)
+
+
 def test_sqn_instance_and_seed_streams(ctx):
     X, z = workloads.sqn_dataset(12, 40)
     run_and_compare(ctx, X, z, 2, 90, 0x1234_5678_9ABC, M=6, ckpt=(45,), instance=77)
@@ -171,3 +201,6 @@ def test_paper_shape_sampled(ctx):
         assert abs(g["F_ckpt"][c, 0] - f) <= 1e-12 * f, (k, g["F_ckpt"][c, 0], f)
     assert g["F_ckpt"][-1, 0] == g["F"][0]
     assert np.all(np.diff(g["F_ckpt"][1:, 0]) < 0) and g["F"][0] < np.log(2.0)
+    h = ctx.sqn_hessian(0, copy=False)
+    say(f"[sqn] paper shape: H_t with m={h['m']} pairs formed in {h['device_ms']:.3f} ms")
+    assert h["m"] == 25
