@@ -90,6 +90,40 @@ def test_sqn_against_oracle(ctx, case):
     run_and_compare(ctx, X, z, c.pop("R"), c.pop("K"), 21, **c)
 
 
+@pytest.mark.parametrize("case", [
+    dict(n=9, N=1, R=2, K=40, L=4, M=3, b=3, bH=2),            # one row: every sample is that row
+    dict(n=16, N=200, R=2, K=1),                                # a single gradient step
+    dict(n=16, N=200, R=2, K=25, L=30),                         # no window closes: plain SGD, no pair
+    dict(n=20, N=600, R=1, K=400, L=2, M=32, b=1024, bH=1024),  # largest M, b and b_H
+    dict(n=8192, N=300, R=1, K=25, L=5, M=3, b=40, bH=60),      # largest n: two quads in every thread
+])
+def test_sqn_edge_cases(ctx, case):
+    c = dict(case)
+    n = c.pop("n")
+    X, z = workloads.sqn_dataset(30, n, c.pop("N"))
+    st, g = run_and_compare(ctx, X, z, c.pop("R"), c.pop("K"), 2, **c)
+    if case.get("L", 10) * 2 >= case["K"]:
+        assert np.all(g["pairs"] <= 1)
+
+
+def test_sqn_single_feature(ctx):
+    """One feature: a window whose Hessian rows all have x = 0 gives y = 0, so gamma = s'y / y'y is
+    0/0 and the method (which uses every pair as formed) breaks down; the device must break down in
+    the same replication as the oracle, with the same pair count, and agree where it does not."""
+    X, z = workloads.sqn_dataset(30, 1, 40)
+    ctx.sqn_load(X, z)
+    O = oracle.SqnOracle(X, z, L=3, M=2, b=5, bH=7, seed=2)
+    ctx.run_sqn(2, 50, 2, L=3, M=2, b=5, bH=7)
+    g = ctx.sqn_paths()
+    for r in range(2):
+        o = O.run(r, 50)
+        assert int(g["pairs"][r]) == o["pairs"]
+        if np.isnan(o["F"]):
+            assert np.isnan(g["F"][r])
+        else:
+            assert rel(g["w"][r], o["w"]) <= W_RTOL
+
+
 def test_sqn_many_replications(ctx):
     """140 stored iterates (70 replications, one checkpoint) take the loss kernel with a lane per
     iterate: every F against the oracle's loss at the device's iterate, three replications against the
