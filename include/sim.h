@@ -60,7 +60,7 @@ typedef enum {
     SIM_ENOMEM = -2,        /* device or host allocation failed */
     SIM_EDEVICE = -3,       /* a HIP call failed; sim_last_error has its message */
     SIM_ESTATE = -4,        /* call out of order (e.g. results before any run) */
-    SIM_EUNSUPPORTED = -5   /* a combination this build does not implement */
+    SIM_EUNSUPPORTED = -5   /* a combination the library does not implement */
 } sim_status;
 
 typedef enum { SIM_NOISE_GAUSS = 0, SIM_NOISE_T = 1 } sim_noise;
@@ -217,7 +217,7 @@ int sim_batch_paths(sim_ctx *ctx, uint32_t instance, sim_path_view *out, uint32_
  * on pairs the simulation generates, and the estimator
  *   Y_cv = mean_r (Y_r - beta h(x_r)) + beta mean_k h(x'_k),
  * with x'_k drawn from the features' exact law. Y_cv is unbiased for E Y whatever h and beta
- * (both fixed before the run); the plain mean stays the fallback and the judge of its bias.
+ * (both fixed before the run); the plain mean stays the fallback and the check on its bias.
  * The surrogate: F = d + 2 inputs -> 64 -> 64 -> 1, exact GELU (x Phi(x)), parameters flat
  * theta = W1 [64][F], b1 [64], W2 [64][64], b2 [64], w3 [64], b3 (P = 64 F + 4289 floats), matrix
  * products on the matrix cores with bfloat16 operands and FP32 accumulation, FP32 master weights,

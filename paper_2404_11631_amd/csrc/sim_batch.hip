@@ -42,7 +42,7 @@ int sim_run_batch(sim_ctx *ctx, uint32_t n_inst, const sim_params *p, const uint
     // kernels below reproduce the oracle in a CPU emulation of the device code; they are not run on a
     // device until that cause is understood.
     if (!batch_on_device_enabled())
-        return set_err(ctx, SIM_EUNSUPPORTED, "batched runs are switched off on the device in this build");
+        return set_err(ctx, SIM_EUNSUPPORTED, "batched runs are switched off on the device");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipDeviceProp_t prop;
     HIP_TRY(ctx, hipGetDeviceProperties(&prop, ctx->device));

@@ -1,6 +1,6 @@
 """Batched runs of uneven instances vs the CPU oracle.
 
-Skipped: the batched device path is switched off in this build (sim_run_batch returns
+Skipped: the batched device path is switched off (sim_run_batch returns
 SIM_EUNSUPPORTED). Its first device run, an earlier persistent-kernel design launched from a captured
 graph, stopped responding and the cause has not been shown; the tile kernels that replaced it pass
 the same parity checks in a CPU emulation of the device code (tests/test_batch_emulated.py) but are
