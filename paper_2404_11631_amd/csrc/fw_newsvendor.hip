@@ -3,7 +3,7 @@
 // products, S = 25-50 demand samples per product, K = 1500 iterations, one or a few replications).
 //
 // The gradient is separable (Eq. (8)-(9)): g_j = k_j - v_j + (h_j + v_j) #{s : d_j^(s) <= x_j} / S,
-// so an iteration is two launches:
+// so an iteration is a sample launch and a step:
 //   sample    a thread owns four consecutive products (one Philox block per sample), draws their S
 //             demand samples, counts those at or below x_j -- as standard normals against the
 //             threshold (x_j - mu_j)/sigma_j, in binary32 -- forms g_j and the ratio g_j / c_j, and
@@ -12,7 +12,11 @@
 //   step      the vertex over all workgroups: (C/c_j) e_j for the smallest ratio when it is negative,
 //             else the origin; the Frank-Wolfe gap g'x - min(0, C min_j g_j/c_j) and tau; the
 //             integer update S_a += t + 1 (x_{t+1} = (C/c) .* 2 S / ((t+1)(t+2)), Algorithm 2's
-//             recurrence in exact arithmetic).
+//             recurrence in exact arithmetic). The step of iteration t normally runs at the start of
+//             iteration t + 1's sample launch: every workgroup reduces the same partials in the same
+//             order (so all get the same vertex), workgroup 0 records it and the thread owning the
+//             chosen product updates its signature; a launch of its own remains only before a cost
+//             evaluation and after the last iteration. The partials alternate between two buffers.
 // The demand normals are standard normal s n + j of the (replication, epoch) stream in domain 4,
 // scaled by 1/sqrt(2 ln 2) like every binary32 normal here; the host folds that into the threshold.
 #include <hip/hip_runtime.h>
@@ -47,17 +51,83 @@ __device__ __forceinline__ float wave_sum(float x)
     return x;
 }
 
+// The step of iteration t over the workgroup partials of replication r (buffer par): the smallest
+// ratio (lowest product among equal values; the workgroups cover ascending product ranges, so strict
+// < over them in order keeps the lowest), the sum of the g'x parts, then the vertex a (0: the
+// origin). Every thread of the kNvBlock-thread workgroup takes part and gets a; thread 0 also gets
+// the gap. The order of the sums is fixed, so every workgroup that calls it gets the same bits.
+__device__ __forceinline__ uint32_t nv_reduce_step(const NvArgs &A, uint32_t r, uint32_t par, float *smr, float *smx,
+                                                   uint32_t *smj, float &gap)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint64_t base = (static_cast<uint64_t>(par) * A.R + r) * A.nwg;
+    float rm = INFINITY, gs = 0.0f;
+    uint32_t jm = 0xFFFFFFFFu;
+    for (uint32_t g = tid; g < A.nwg; g += kNvBlock) {
+        const float x = A.wg_r[base + g];
+        if (x < rm) {
+            rm = x;
+            jm = A.wg_j[base + g];
+        }
+        gs += A.wg_gx[base + g];
+    }
+    smr[tid] = rm;
+    smj[tid] = jm;
+    smx[tid] = gs;
+    __syncthreads();
+    for (int h = kNvBlock / 2; h > 0; h >>= 1) {
+        if (tid < static_cast<uint32_t>(h)) {
+            const float o = smr[tid + h];
+            const uint32_t oj = smj[tid + h];
+            if (o < smr[tid] || (o == smr[tid] && oj < smj[tid])) {
+                smr[tid] = o;
+                smj[tid] = oj;
+            }
+            smx[tid] += smx[tid + h];
+        }
+        __syncthreads();
+    }
+    const float best = smr[0];
+    const uint32_t a = (best < 0.0f) ? smj[0] + 1u : 0u;
+    gap = smx[0] - (best < 0.0f ? A.C * best : 0.0f);
+    __syncthreads();                                    // smr/smj/smx may be reused after this
+    return a;
+}
+
+// The records of the step of iteration t with vertex a (one thread).
+__device__ __forceinline__ void nv_record_step(const NvArgs &A, uint32_t r, uint64_t t, uint32_t a, float gap)
+{
+    if (A.tau[r] == kTauNone && gap <= A.gap_eps) A.tau[r] = static_cast<uint32_t>(t);
+    A.dec[static_cast<uint64_t>(r) * A.T + t] = a;
+    A.cnt[static_cast<uint64_t>(r) * (A.n + 1) + a] += 1u;
+}
+
 }  // namespace
 
-__global__ __launch_bounds__(kNvBlock) void nv_sample_kernel(NvArgs A, uint32_t epoch, float cw, int from_x0)
+// Iteration t (partials into buffer par = t & 1). With prev_t >= 0 the launch first takes the step of
+// iteration prev_t = t - 1 from the other buffer (every workgroup computes the same vertex; workgroup 0
+// records it, and the thread owning that product adds t to its signature before reading it), which
+// saves the separate step launch between the two iterations.
+__global__ __launch_bounds__(kNvBlock) void nv_sample_kernel(NvArgs A, uint32_t epoch, float cw, int from_x0,
+                                                             int64_t prev_t, uint32_t par)
 {
     __shared__ float sm_r[kNvBlock / 64], sm_gx[kNvBlock / 64];
     __shared__ uint32_t sm_j[kNvBlock / 64];
+    __shared__ float st_r[kNvBlock], st_x[kNvBlock];
+    __shared__ uint32_t st_j[kNvBlock];
     const uint32_t tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const uint32_t r = blockIdx.y, g = blockIdx.x;
     const uint32_t q = g * kNvBlock + tid;
     const bool active = q < A.nq;
     const uint32_t j0 = 4 * q;
+
+    if (prev_t >= 0) {
+        float gap;
+        const uint32_t a = nv_reduce_step(A, r, par ^ 1u, st_r, st_x, st_j, gap);
+        if (g == 0 && tid == 0) nv_record_step(A, r, static_cast<uint64_t>(prev_t), a, gap);
+        if (a > 0 && active && a - 1 >= j0 && a - 1 < j0 + 4)
+            A.S_sig[static_cast<uint64_t>(r) * A.n + (a - 1)] += static_cast<uint64_t>(prev_t) + 1;
+    }
 
     float x[4], thr[4];
 #pragma unroll
@@ -114,53 +184,24 @@ __global__ __launch_bounds__(kNvBlock) void nv_sample_kernel(NvArgs A, uint32_t 
             }
             gs += sm_gx[w];
         }
-        const uint64_t o = static_cast<uint64_t>(r) * A.nwg + g;
+        const uint64_t o = (static_cast<uint64_t>(par) * A.R + r) * A.nwg + g;
         A.wg_r[o] = rm;
         A.wg_j[o] = jm;
         A.wg_gx[o] = gs;
     }
 }
 
-// The vertex over the workgroups of replication blockIdx.x, the gap, tau and the update.
-__global__ __launch_bounds__(kNvBlock) void nv_step_kernel(NvArgs A, uint64_t t)
+// The step of iteration t from buffer par on its own (before a cost evaluation and after the last
+// iteration): the vertex, the gap, tau and the update.
+__global__ __launch_bounds__(kNvBlock) void nv_step_kernel(NvArgs A, uint64_t t, uint32_t par)
 {
     __shared__ float smr[kNvBlock], smx[kNvBlock];
     __shared__ uint32_t smj[kNvBlock];
-    const uint32_t r = blockIdx.x, tid = threadIdx.x;
-    const uint64_t base = static_cast<uint64_t>(r) * A.nwg;
-    float rm = INFINITY, gs = 0.0f;
-    uint32_t jm = 0xFFFFFFFFu;
-    for (uint32_t g = tid; g < A.nwg; g += kNvBlock) {
-        const float x = A.wg_r[base + g];
-        if (x < rm) {
-            rm = x;
-            jm = A.wg_j[base + g];
-        }
-        gs += A.wg_gx[base + g];
-    }
-    smr[tid] = rm;
-    smj[tid] = jm;
-    smx[tid] = gs;
-    __syncthreads();
-    for (int h = kNvBlock / 2; h > 0; h >>= 1) {
-        if (tid < static_cast<uint32_t>(h)) {
-            const float o = smr[tid + h];
-            const uint32_t oj = smj[tid + h];
-            if (o < smr[tid] || (o == smr[tid] && oj < smj[tid])) {
-                smr[tid] = o;
-                smj[tid] = oj;
-            }
-            smx[tid] += smx[tid + h];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        const float best = smr[0];
-        const uint32_t a = (best < 0.0f) ? smj[0] + 1u : 0u;
-        const float gap = smx[0] - (best < 0.0f ? A.C * best : 0.0f);
-        if (A.tau[r] == kTauNone && gap <= A.gap_eps) A.tau[r] = static_cast<uint32_t>(t);
-        A.dec[static_cast<uint64_t>(r) * A.T + t] = a;
-        A.cnt[static_cast<uint64_t>(r) * (A.n + 1) + a] += 1u;
+    const uint32_t r = blockIdx.x;
+    float gap;
+    const uint32_t a = nv_reduce_step(A, r, par, smr, smx, smj, gap);
+    if (threadIdx.x == 0) {
+        nv_record_step(A, r, t, a, gap);
         if (a > 0) A.S_sig[static_cast<uint64_t>(r) * A.n + (a - 1)] += t + 1;
     }
 }
@@ -259,10 +300,17 @@ __global__ void nv_finalize_kernel(NvArgs A, uint32_t n_ckpt)
     *A.origin_total = origin;
 }
 
-int launch_nv_step(const NvArgs &A, uint64_t t, uint32_t epoch, float cw, bool from_x0, hipStream_t s)
+int launch_nv_sample(const NvArgs &A, uint64_t t, uint32_t epoch, float cw, bool from_x0, bool fold_prev, hipStream_t s)
 {
-    hipLaunchKernelGGL(nv_sample_kernel, dim3(A.nwg, A.R), dim3(kNvBlock), 0, s, A, epoch, cw, from_x0 ? 1 : 0);
-    hipLaunchKernelGGL(nv_step_kernel, dim3(A.R), dim3(kNvBlock), 0, s, A, t);
+    const int64_t prev = fold_prev ? static_cast<int64_t>(t) - 1 : -1;
+    hipLaunchKernelGGL(nv_sample_kernel, dim3(A.nwg, A.R), dim3(kNvBlock), 0, s, A, epoch, cw, from_x0 ? 1 : 0, prev,
+                       static_cast<uint32_t>(t & 1));
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_nv_step(const NvArgs &A, uint64_t t, hipStream_t s)
+{
+    hipLaunchKernelGGL(nv_step_kernel, dim3(A.R), dim3(kNvBlock), 0, s, A, t, static_cast<uint32_t>(t & 1));
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -29,9 +29,10 @@ struct NvArgs {
     uint32_t *dec;                              // [R][T]
     uint64_t T;
     // per-iteration scratch
-    float *wg_r;                                // [R][nwg] smallest g_j / c_j of the workgroup
-    uint32_t *wg_j;                             // [R][nwg] its product
-    float *wg_gx;                               // [R][nwg] the workgroup's part of g'x
+    // two buffers by iteration parity: a sample launch may read the previous iteration's partials
+    float *wg_r;                                // [2][R][nwg] smallest g_j / c_j of the workgroup
+    uint32_t *wg_j;                             // [2][R][nwg] its product
+    float *wg_gx;                               // [2][R][nwg] the workgroup's part of g'x
     // outcomes
     double *cost_part;                          // [R][ceil(n / kNvCostChunk)][2] double-double partials
     double *fval;                               // [n_ckpt + 1][R]
@@ -39,7 +40,11 @@ struct NvArgs {
     uint64_t *origin_total;
 };
 
-int launch_nv_step(const NvArgs &A, uint64_t t, uint32_t epoch, float cw, bool from_x0, hipStream_t s);
+// Iteration t's samples and workgroup partials; with fold_prev it first takes the step of iteration
+// t - 1 (whose partials the previous launch left in the other buffer).
+int launch_nv_sample(const NvArgs &A, uint64_t t, uint32_t epoch, float cw, bool from_x0, bool fold_prev, hipStream_t s);
+// The step of iteration t on its own.
+int launch_nv_step(const NvArgs &A, uint64_t t, hipStream_t s);
 int launch_nv_cost(const NvArgs &A, double c, uint32_t slot, hipStream_t s);
 int launch_nv_finalize(const NvArgs &A, uint32_t n_ckpt, hipStream_t s);
 

@@ -109,8 +109,9 @@ int sim_run_newsvendor(sim_ctx *ctx, const sim_nv_params *p, uint64_t R, uint64_
     if ((rc = ensure(ctx, w.prod_f, sizeof(float) * pf.size())) || (rc = ensure(ctx, w.prod_d, sizeof(double) * pd.size())) ||
         (rc = ensure(ctx, w.S, sizeof(uint64_t) * R * N)) || (rc = ensure(ctx, w.cnt, sizeof(uint32_t) * R * (N + 1))) ||
         (rc = ensure(ctx, w.tau, sizeof(uint32_t) * R)) || (rc = ensure(ctx, w.dec, sizeof(uint32_t) * R * T)) ||
-        (rc = ensure(ctx, w.wg_r, sizeof(float) * R * w.nwg)) || (rc = ensure(ctx, w.wg_j, sizeof(uint32_t) * R * w.nwg)) ||
-        (rc = ensure(ctx, w.wg_gx, sizeof(float) * R * w.nwg)) || (rc = ensure(ctx, w.fval, sizeof(double) * R * (nc + 1))) ||
+        (rc = ensure(ctx, w.wg_r, sizeof(float) * 2 * R * w.nwg)) ||
+        (rc = ensure(ctx, w.wg_j, sizeof(uint32_t) * 2 * R * w.nwg)) ||
+        (rc = ensure(ctx, w.wg_gx, sizeof(float) * 2 * R * w.nwg)) || (rc = ensure(ctx, w.fval, sizeof(double) * R * (nc + 1))) ||
         (rc = ensure(ctx, w.stats, sizeof(double) * (fw::kMaxStreams * fw::kStreamFields + 2))) ||
         (rc = ensure(ctx, w.origin, sizeof(uint64_t))) ||
         (rc = ensure(ctx, w.cost_part, sizeof(double) * 2 * R * ((N + fw::kNvCostChunk - 1) / fw::kNvCostChunk))))
@@ -126,10 +127,17 @@ int sim_run_newsvendor(sim_ctx *ctx, const sim_nv_params *p, uint64_t R, uint64_
     const fw::NvArgs A = nv_args(w, p, R, T, seed);
     const uint64_t M = p->resample_every;
     HIP_TRY(ctx, hipEventRecord(w.ev0, st));
+    // The step of iteration t runs inside the next iteration's sample launch unless a cost
+    // evaluation needs the updated signature first or t is the last iteration.
     uint32_t ck = 0;
+    bool pending = false;
     for (uint64_t t = 0; t < T; ++t) {
         const float cw = t == 0 ? 0.0f : static_cast<float>(2.0 / (static_cast<double>(t) * static_cast<double>(t + 1)));
-        if (fw::launch_nv_step(A, t, static_cast<uint32_t>(t / M), cw, t == 0 && p->x0 != nullptr, st))
+        if (fw::launch_nv_sample(A, t, static_cast<uint32_t>(t / M), cw, t == 0 && p->x0 != nullptr, pending, st))
+            return set_err(ctx, SIM_EDEVICE, "newsvendor sample launch failed at t=%llu", (unsigned long long)t);
+        const bool cost_next = ck < nc && p->checkpoints[ck] == t + 1;
+        pending = !(cost_next || t + 1 == T);
+        if (!pending && fw::launch_nv_step(A, t, st))
             return set_err(ctx, SIM_EDEVICE, "newsvendor step launch failed at t=%llu", (unsigned long long)t);
         while (ck < nc && p->checkpoints[ck] == t + 1) {
             const double c = 2.0 / (static_cast<double>(t + 1) * static_cast<double>(t + 2));
