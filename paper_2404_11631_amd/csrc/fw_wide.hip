@@ -4,7 +4,7 @@
 //
 // Parallelism is inside a replication: a workgroup owns 128 assets (32 quads of four consecutive
 // assets, one Philox block per quad and sample) and splits the N samples over 8 chunks. One
-// iteration is four launches on the stream:
+// iteration is three launches and a step:
 //   sample    z_i for the workgroup's assets; z_i'v summed over the workgroup (per sample) and
 //             s1 = sum_i z_i per asset; workgroup partials of s1'v,
 //   dot       z_i'v and s1'v over the workgroups of the replication (fixed order),
@@ -13,7 +13,10 @@
 //             workgroup's smallest g_j (lowest index among equal values) and its part of g'w,
 //   step      the vertex over all workgroups, the Frank-Wolfe gap and tau, and the integer update
 //             S_a += t + 1 of the chosen vertex (w_{t+1} = 2 S / ((t+1)(t+2)), Algorithm 1's
-//             recurrence in exact arithmetic).
+//             recurrence in exact arithmetic). It runs at the start of the next iteration's sample
+//             launch (every workgroup reduces the same partials in the same order; the partials
+//             alternate between two buffers), and in a launch of its own only before an objective
+//             evaluation and after the last iteration.
 // Every sum runs in a fixed order, so a run is reproducible bit for bit. The normals are those of
 // the per-lane path kernels (standard normal q = i d + j of the (replication, epoch) stream),
 // scaled by 1/sqrt(2 ln 2), which the host folds into sz = sqrt(2 ln 2) sigma.
@@ -66,17 +69,81 @@ __device__ __forceinline__ void wide_iterate(const WideArgs &A, uint32_t r, uint
     }
 }
 
+// The vertex over the workgroup partials of replication r (buffer par): the smallest gradient entry
+// (lowest asset among equal values: the workgroups cover ascending asset ranges, so strict < over
+// them in order keeps the lowest), the sum of the g'w parts, then the vertex a (0: the origin) and the
+// Frank-Wolfe gap. Every thread of the kWideBlock-thread workgroup takes part and gets a; the order
+// of the sums is fixed, so every workgroup that calls it gets the same bits.
+__device__ __forceinline__ uint32_t wide_reduce_step(const WideArgs &A, uint32_t r, uint32_t par, float *smg, float *smw,
+                                                     uint32_t *smj, float &gap)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint64_t base = (static_cast<uint64_t>(par) * A.R + r) * A.nwg;
+    float gmin = INFINITY, gw = 0.0f;
+    uint32_t jmin = 0xFFFFFFFFu;
+    for (uint32_t g = tid; g < A.nwg; g += kWideBlock) {
+        const float x = A.wg_g[base + g];
+        if (x < gmin) {
+            gmin = x;
+            jmin = A.wg_j[base + g];
+        }
+        gw += A.wg_gw[base + g];
+    }
+    smg[tid] = gmin;
+    smj[tid] = jmin;
+    smw[tid] = gw;
+    __syncthreads();
+    for (int h = kWideBlock / 2; h > 0; h >>= 1) {
+        if (tid < static_cast<uint32_t>(h)) {
+            const float og = smg[tid + h];
+            const uint32_t oj = smj[tid + h];
+            if (og < smg[tid] || (og == smg[tid] && oj < smj[tid])) {
+                smg[tid] = og;
+                smj[tid] = oj;
+            }
+            smw[tid] += smw[tid + h];
+        }
+        __syncthreads();
+    }
+    const float gm = smg[0];
+    const uint32_t a = (gm < 0.0f) ? smj[0] + 1u : 0u;
+    gap = smw[0] - (gm < 0.0f ? gm : 0.0f);
+    __syncthreads();                                    // smg/smj/smw may be reused after this
+    return a;
+}
+
+// The records of the step of iteration t with vertex a (one thread).
+__device__ __forceinline__ void wide_record_step(const WideArgs &A, uint32_t r, uint64_t t, uint32_t a, float gap)
+{
+    if (A.tau[r] == kTauNone && gap <= A.gap_eps) A.tau[r] = static_cast<uint32_t>(t);
+    A.dec[static_cast<uint64_t>(r) * A.T + t] = a;
+    A.cnt[static_cast<uint64_t>(r) * (A.d + 1) + a] += 1u;
+}
+
 }  // namespace
 
+// With prev_t >= 0 the launch first takes the step of iteration prev_t = t - 1 from the partials the
+// previous gradient launch left in buffer par ^ 1 (every workgroup computes the same vertex;
+// workgroup 0 records it, and the workgroup owning that asset adds t to its signature before any
+// thread reads it), which saves the separate step launch between the two iterations.
 __global__ __launch_bounds__(kWideBlock) void wide_sample_kernel(WideArgs A, uint32_t epoch, uint32_t Nk, float cw,
-                                                                 int from_w0)
+                                                                 int from_w0, int64_t prev_t, uint32_t par)
 {
     __shared__ float sm[kWideBlock * 4];
+    __shared__ uint32_t st_j[kWideBlock];
     const uint32_t tid = threadIdx.x, c = tid / kWideQuads, aq = tid % kWideQuads;
     const uint32_t r = blockIdx.y, g = blockIdx.x;
     const uint32_t q = g * kWideQuads + aq;
     const bool active = q < A.nq;
     const uint32_t j0 = 4 * q;
+    if (prev_t >= 0) {
+        float gap;
+        const uint32_t a = wide_reduce_step(A, r, par ^ 1u, sm, sm + kWideBlock, st_j, gap);
+        if (g == 0 && tid == 0) wide_record_step(A, r, static_cast<uint64_t>(prev_t), a, gap);
+        if (a > 0 && c == 0 && active && a - 1 >= j0 && a - 1 < j0 + 4)
+            A.S[static_cast<uint64_t>(r) * A.d + (a - 1)] += static_cast<uint64_t>(prev_t) + 1;
+        __syncthreads();                                // the signature is read below by all chunks
+    }
     float w[4], v[4];
     wide_iterate(A, r, j0, active, cw, from_w0 != 0, w, v);
 
@@ -181,7 +248,7 @@ __global__ __launch_bounds__(kWideBlock) void wide_gradient_kernel(WideArgs A, u
         half_argmin(gmin, jmin);
         gw = half_sum(gw);
         if (aq == 0) {
-            const uint64_t o = static_cast<uint64_t>(r) * A.nwg + g;
+            const uint64_t o = (static_cast<uint64_t>(E.par) * A.R + r) * A.nwg + g;
             A.wg_g[o] = gmin;
             A.wg_j[o] = jmin;
             A.wg_gw[o] = gw;
@@ -189,46 +256,17 @@ __global__ __launch_bounds__(kWideBlock) void wide_gradient_kernel(WideArgs A, u
     }
 }
 
-// The vertex over all workgroups of replication blockIdx.x, the gap, tau and the update.
-__global__ __launch_bounds__(kWideBlock) void wide_step_kernel(WideArgs A, uint64_t t)
+// The step of iteration t from buffer par on its own (before an objective evaluation and after the
+// last iteration): the vertex, the gap, tau and the update.
+__global__ __launch_bounds__(kWideBlock) void wide_step_kernel(WideArgs A, uint64_t t, uint32_t par)
 {
     __shared__ float smg[kWideBlock], smw[kWideBlock];
     __shared__ uint32_t smj[kWideBlock];
-    const uint32_t r = blockIdx.x, tid = threadIdx.x;
-    const uint64_t base = static_cast<uint64_t>(r) * A.nwg;
-    float gmin = INFINITY, gw = 0.0f;
-    uint32_t jmin = 0xFFFFFFFFu;
-    for (uint32_t g = tid; g < A.nwg; g += kWideBlock) {   // ascending asset ranges: strict < keeps the lowest
-        const float x = A.wg_g[base + g];
-        if (x < gmin) {
-            gmin = x;
-            jmin = A.wg_j[base + g];
-        }
-        gw += A.wg_gw[base + g];
-    }
-    smg[tid] = gmin;
-    smj[tid] = jmin;
-    smw[tid] = gw;
-    __syncthreads();
-    for (int h = kWideBlock / 2; h > 0; h >>= 1) {
-        if (tid < static_cast<uint32_t>(h)) {
-            const float og = smg[tid + h];
-            const uint32_t oj = smj[tid + h];
-            if (og < smg[tid] || (og == smg[tid] && oj < smj[tid])) {
-                smg[tid] = og;
-                smj[tid] = oj;
-            }
-            smw[tid] += smw[tid + h];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        const float gm = smg[0];
-        const uint32_t a = (gm < 0.0f) ? smj[0] + 1u : 0u;
-        const float gap = smw[0] - (gm < 0.0f ? gm : 0.0f);
-        if (A.tau[r] == kTauNone && gap <= A.gap_eps) A.tau[r] = static_cast<uint32_t>(t);
-        A.dec[static_cast<uint64_t>(r) * A.T + t] = a;
-        A.cnt[static_cast<uint64_t>(r) * (A.d + 1) + a] += 1u;
+    const uint32_t r = blockIdx.x;
+    float gap;
+    const uint32_t a = wide_reduce_step(A, r, par, smg, smw, smj, gap);
+    if (threadIdx.x == 0) {
+        wide_record_step(A, r, t, a, gap);
         if (a > 0) A.S[static_cast<uint64_t>(r) * A.d + (a - 1)] += t + 1;
     }
 }
@@ -296,14 +334,20 @@ __global__ void wide_finalize_kernel(WideArgs A, uint32_t n_ckpt)
     *A.origin_total = origin;
 }
 
-int launch_wide_step(const WideArgs &A, uint64_t t, uint32_t epoch, const WideEpoch &E, float cw, bool from_w0,
-                     hipStream_t s)
+int launch_wide_iteration(const WideArgs &A, uint64_t t, uint32_t epoch, const WideEpoch &E, float cw, bool from_w0,
+                          bool fold_prev, hipStream_t s)
 {
     const dim3 grid(A.nwg, A.R);
-    hipLaunchKernelGGL(wide_sample_kernel, grid, dim3(kWideBlock), 0, s, A, epoch, E.n, cw, from_w0 ? 1 : 0);
+    const int64_t prev = fold_prev ? static_cast<int64_t>(t) - 1 : -1;
+    hipLaunchKernelGGL(wide_sample_kernel, grid, dim3(kWideBlock), 0, s, A, epoch, E.n, cw, from_w0 ? 1 : 0, prev, E.par);
     hipLaunchKernelGGL(wide_dot_kernel, dim3(E.n + 1, A.R), dim3(kWideBlock), 0, s, A, E.n);
     hipLaunchKernelGGL(wide_gradient_kernel, grid, dim3(kWideBlock), 0, s, A, epoch, E, cw, from_w0 ? 1 : 0);
-    hipLaunchKernelGGL(wide_step_kernel, dim3(A.R), dim3(kWideBlock), 0, s, A, t);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_wide_step(const WideArgs &A, uint64_t t, hipStream_t s)
+{
+    hipLaunchKernelGGL(wide_step_kernel, dim3(A.R), dim3(kWideBlock), 0, s, A, t, static_cast<uint32_t>(t & 1));
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -35,9 +35,10 @@ struct WideArgs {
     float *part_qn;                             // [R][nwg] workgroup partials of s1'v
     float *dot;                                 // [R][N] z_i'v
     float *qn;                                  // [R] s1'v
-    float *wg_g;                                // [R][nwg] workgroup minimum of the gradient
-    uint32_t *wg_j;                             // [R][nwg] its asset
-    float *wg_gw;                               // [R][nwg] workgroup partial of g'w
+    // two buffers by iteration parity: a sample launch may read the previous iteration's partials
+    float *wg_g;                                // [2][R][nwg] workgroup minimum of the gradient
+    uint32_t *wg_j;                             // [2][R][nwg] its asset
+    float *wg_gw;                               // [2][R][nwg] workgroup partial of g'w
     // outcomes
     double *fval;                               // [n_ckpt + 1][R] f(w_c) per checkpoint, then f(w_T)
     double *stats;                              // kMaxStreams x kStreamFields + 2 (min, max of Y)
@@ -49,11 +50,15 @@ struct WideArgs {
 struct WideEpoch {
     uint32_t n;
     float inv_n, sc1, sc2;
+    uint32_t par;                               // buffer of the iteration's workgroup partials (t & 1)
 };
 
-// One iteration: w_t = cw S (or w_0 at t = 0 when from_w0), epoch = t div M of size E.
-int launch_wide_step(const WideArgs &A, uint64_t t, uint32_t epoch, const WideEpoch &E, float cw, bool from_w0,
-                     hipStream_t s);
+// One iteration without its step (sample, dot, gradient): w_t = cw S (or w_0 at t = 0 when from_w0),
+// epoch = t div M of size E; with fold_prev the sample launch first takes the step of iteration t - 1.
+int launch_wide_iteration(const WideArgs &A, uint64_t t, uint32_t epoch, const WideEpoch &E, float cw, bool from_w0,
+                          bool fold_prev, hipStream_t s);
+// The step of iteration t on its own.
+int launch_wide_step(const WideArgs &A, uint64_t t, hipStream_t s);
 // f(w) at w = c S into fval[slot][r].
 int launch_wide_objective(const WideArgs &A, double c, uint32_t slot, hipStream_t s);
 // Cross-replication statistics of Y and of the n_ckpt checkpoints into stats.

@@ -123,8 +123,9 @@ int sim_run_wide(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint
         (rc = ensure(ctx, w.s1, sizeof(float) * R * D)) ||
         (rc = ensure(ctx, w.part_dot, sizeof(float) * R * Nmax * w.nwg)) ||
         (rc = ensure(ctx, w.part_qn, sizeof(float) * R * w.nwg)) || (rc = ensure(ctx, w.dot, sizeof(float) * R * Nmax)) ||
-        (rc = ensure(ctx, w.qn, sizeof(float) * R)) || (rc = ensure(ctx, w.wg_g, sizeof(float) * R * w.nwg)) ||
-        (rc = ensure(ctx, w.wg_j, sizeof(uint32_t) * R * w.nwg)) || (rc = ensure(ctx, w.wg_gw, sizeof(float) * R * w.nwg)) ||
+        (rc = ensure(ctx, w.qn, sizeof(float) * R)) || (rc = ensure(ctx, w.wg_g, sizeof(float) * 2 * R * w.nwg)) ||
+        (rc = ensure(ctx, w.wg_j, sizeof(uint32_t) * 2 * R * w.nwg)) ||
+        (rc = ensure(ctx, w.wg_gw, sizeof(float) * 2 * R * w.nwg)) ||
         (rc = ensure(ctx, w.fval, sizeof(double) * R * (nc + 1))) ||
         (rc = ensure(ctx, w.stats, sizeof(double) * (fw::kMaxStreams * fw::kStreamFields + 2))) ||
         (rc = ensure(ctx, w.origin, sizeof(uint64_t))))
@@ -141,14 +142,21 @@ int sim_run_wide(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint
     const fw::WideArgs A = wide_args(w, p, R, T, seed);
     const uint64_t M = p->resample_every;
     HIP_TRY(ctx, hipEventRecord(w.ev0, st));
+    // The step of iteration t runs inside the next iteration's sample launch unless an objective
+    // evaluation needs the updated signature first or t is the last iteration.
     uint32_t ck = 0;
+    bool pending = false;
     for (uint64_t t = 0; t < T; ++t) {
         const float cw = t == 0 ? 0.0f : static_cast<float>(2.0 / (static_cast<double>(t) * static_cast<double>(t + 1)));
         const uint64_t e = t / M;
         const uint32_t Ne = p->n_schedule ? p->n_schedule[e] : N;
         const fw::WideEpoch E{Ne, static_cast<float>(1.0 / Ne), static_cast<float>(static_cast<double>(N) / Ne),
-                              static_cast<float>((N - 1.0) / (Ne - 1.0))};
-        if (fw::launch_wide_step(A, t, static_cast<uint32_t>(e), E, cw, t == 0 && p->w0 != nullptr, st))
+                              static_cast<float>((N - 1.0) / (Ne - 1.0)), static_cast<uint32_t>(t & 1)};
+        if (fw::launch_wide_iteration(A, t, static_cast<uint32_t>(e), E, cw, t == 0 && p->w0 != nullptr, pending, st))
+            return set_err(ctx, SIM_EDEVICE, "wide launch failed at t=%llu", (unsigned long long)t);
+        const bool objective_next = ck < nc && p->checkpoints[ck] == t + 1;
+        pending = !(objective_next || t + 1 == T);
+        if (!pending && fw::launch_wide_step(A, t, st))
             return set_err(ctx, SIM_EDEVICE, "wide step launch failed at t=%llu", (unsigned long long)t);
         while (ck < nc && p->checkpoints[ck] == t + 1) {
             const double c = 2.0 / (static_cast<double>(t + 1) * static_cast<double>(t + 2));
