@@ -393,24 +393,24 @@ def newsvendor_shape_leg(ctx, sim, runs: int, warmup: int):
     return out
 
 
-def sqn_bytes(n: int, K: int, L: int, M: int, b: int, bH: int) -> float:
+def sqn_bytes(n: int, K: int, L: int, M: int, b: int, bH: int, pair_bytes: int = 8) -> float:
     """HBM bytes one replication of the SQN kernel must move over K iterations: per iteration the two
     passes over the stored pairs (S'g, Y'g, then S a + Y c: 2 x 2 m n doubles), the b sampled rows'
     bits twice (the dot products, then the gradient) and the window sum (read and written); per window
     the new pair (s and y written, the previous average read and written), the b_H Hessian rows' bits
     three times (x'wbar, x's, then y) and the pair's dot products with the m stored pairs
-    (S_i, Y_i, and Y_i again: 3 m n doubles)."""
+    (S_i, Y_i, and Y_i again: 3 m n values). The pairs take pair_bytes per value (8, or 4 in binary32)."""
     row = 4 * (((n + 31) // 32 + 3) // 4 * 4)
     total, m, t = 0.0, 0, -1
     for k in range(1, K + 1):
         total += 2 * b * row + 16 * n
         if k > 2 * L:
-            total += 32 * m * n
+            total += 4 * pair_bytes * m * n
         if k % L == 0:
             t += 1
             if t > 0:
                 m = min(m + 1, M)
-                total += 8 * 4 * n + 3 * bH * row + 24 * m * n
+                total += 2 * pair_bytes * n + 8 * 2 * n + 3 * bH * row + 3 * pair_bytes * m * n
     return total
 
 
@@ -476,6 +476,21 @@ def sqn_shape_leg(ctx, sim, runs: int, warmup: int, throughput_sizes=(5_000,), s
                                                "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                                                "frac": alg / (bavg * 1e-3) / PEAK_HBM,
                                                "bytes_per_rep": alg / R}}
+                # the same launch with the pairs kept in binary32
+                kw32 = dict(kw, pairs_fp32=True)
+                ctx.run_sqn(R, K, seed + 2000, **kw32)
+                ctx.sqn_stats()
+                fms = []
+                for k in range(runs):
+                    ctx.run_sqn(R, K, seed + 3000 + k, **kw32)
+                    stf = ctx.sqn_stats()
+                    fms.append(stf.kernel_ms)
+                favg = sum(fms) / len(fms)
+                alg32 = sqn_bytes(n, K, w["L"], w["M"], w["b"], bH, pair_bytes=4) * R
+                entry["batch_fp32_pairs"] = {
+                    "R": R, "device_ms": favg, "rep_iterations_per_s": R * K / (favg * 1e-3), "F_mean": stf.mean,
+                    "roofline": {"bound": "hbm", "achieved": alg32 / (favg * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                                 "unit": "GB/s", "frac": alg32 / (favg * 1e-3) / PEAK_HBM, "bytes_per_rep": alg32 / R}}
             out["sizes"].append(entry)
             print(f"[sqn_shape] n={n} bH={bH}: {kavg:.1f} ms per run"
                   + (f", R={entry['batch']['R']}: {entry['batch']['device_ms']:.1f} ms" if "batch" in entry else ""),

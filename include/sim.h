@@ -401,7 +401,9 @@ typedef struct {
     uint32_t b, b_H;            /* sample sizes, 1..SIM_SQN_MAX_B */
     uint32_t n_checkpoints;     /* 0..SIM_MAX_CKPT */
     uint32_t instance_id;       /* stream instance, < 2^24 */
-    uint32_t pad_;
+    uint32_t pairs_fp32;        /* 1: keep the correction pairs in binary32 (s rounded before y is
+                                   formed from it, y rounded when stored; half the bytes of the two
+                                   passes over them per iteration), 0: binary64 */
     double beta;                /* step alpha_k = beta / k, finite and > 0 */
     uint64_t checkpoints[SIM_MAX_CKPT]; /* strictly increasing iterations k in [1, K]: F(w^{k+1}) */
 } sim_sqn_params;
@@ -432,8 +434,9 @@ typedef struct {
     const double *w;            /* [R][ld] w^{K+1} */
     const double *w_ckpt;       /* [n_checkpoints][R][ld] */
     const uint32_t *pairs;      /* [R] correction pairs computed */
-    uint32_t M, pad2_;          /* ring slots per replication */
-    const double *S, *Y;        /* [R][M][ld] the stored pairs; with P = pairs[r], the min(P, M) newest,
+    uint32_t M;                 /* ring slots per replication */
+    uint32_t pairs_fp32;        /* element type of S and Y: 1 float, 0 double */
+    const void *S, *Y;          /* [R][M][ld] the stored pairs; with P = pairs[r], the min(P, M) newest,
                                    the oldest at slot (P >= M ? P mod M : 0), then cyclically */
 } sim_sqn_view;
 

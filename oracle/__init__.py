@@ -101,7 +101,7 @@ class SqnProblem(ctypes.Structure):
                 ("b", ctypes.c_int32), ("bH", ctypes.c_int32), ("beta", ctypes.c_double),
                 ("instance", ctypes.c_uint32), ("n_ckpt", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("X", ctypes.POINTER(ctypes.c_uint8)), ("z", ctypes.POINTER(ctypes.c_uint8)),
-                ("ckpt", ctypes.c_int64 * MAX_CKPT)]
+                ("ckpt", ctypes.c_int64 * MAX_CKPT), ("pairs_fp32", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class SqnOut(ctypes.Structure):
@@ -396,7 +396,7 @@ class SqnOracle:
 
     DOMAIN_GRAD, DOMAIN_HESS = 5, 6
 
-    def __init__(self, X, z, *, L=10, M=25, b=50, bH=300, beta=2.0, seed=0, instance=0, ckpt=()):
+    def __init__(self, X, z, *, L=10, M=25, b=50, bH=300, beta=2.0, seed=0, instance=0, ckpt=(), pairs_fp32=False):
         self.X = np.ascontiguousarray(X, dtype=np.uint8)
         self.z = np.ascontiguousarray(z, dtype=np.uint8)
         N, n = self.X.shape
@@ -408,6 +408,7 @@ class SqnOracle:
         p.z = self.z.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         for i, c in enumerate(ck):
             p.ckpt[i] = int(c)
+        p.pairs_fp32 = 1 if pairs_fp32 else 0
         self.p, self.n, self.N, self.ckpt = p, n, N, ck
 
     def indices(self, rep, k, domain, count):

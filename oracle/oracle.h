@@ -230,6 +230,9 @@ typedef struct {
     const uint8_t *X;       /* [N][n] features in {0, 1} */
     const uint8_t *z;       /* [N] labels in {0, 1} */
     int64_t ckpt[OR_MAX_CKPT];   /* iterations k after which F(w^{k+1}) is recorded */
+    int32_t pairs_fp32;     /* 1: every stored pair is rounded to binary32 (s before y is formed
+                               from it, then y); 0: binary64 */
+    int32_t pad_;
 } or_sqn_problem;
 
 typedef struct {

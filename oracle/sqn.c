@@ -14,6 +14,8 @@
  * Sampled rows: index floor(u N / 2^32) for the 32-bit Philox words u of counter
  * (q/4, k, replication, domain | instance), q = 0, 1, ...; domain 5 for the gradient samples of
  * iteration k, domain 6 for the Hessian samples of the pair closed at iteration k.
+ * With pairs_fp32 the stored pairs are rounded to binary32: s, then y = Hessian(wbar_t) applied to
+ * the rounded s, then y itself; everything else stays binary64.
  */
 #include "oracle.h"
 
@@ -174,9 +176,14 @@ int or_sqn_run(const or_sqn_problem *p, uint64_t rep, uint64_t K, or_sqn_out *ou
                     --m;
                 }
                 double *s = S + (size_t)m * n, *y = Y + (size_t)m * n;
-                for (int64_t j = 0; j < n; ++j) s[j] = wbar[j] - wbar_prev[j];
+                for (int64_t j = 0; j < n; ++j) {
+                    s[j] = wbar[j] - wbar_prev[j];
+                    if (p->pairs_fp32) s[j] = (double)(float)s[j];
+                }
                 or_sqn_indices(p, rep, k, OR_DOMAIN_SQN_HESS, (uint32_t)p->bH, idx);
                 or_sqn_hessian_vector(p, idx, (uint32_t)p->bH, wbar, s, y);
+                if (p->pairs_fp32)
+                    for (int64_t j = 0; j < n; ++j) y[j] = (double)(float)y[j];
                 ++m;
                 ++out->pairs;
                 H_ready = 0;

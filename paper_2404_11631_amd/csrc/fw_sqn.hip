@@ -26,8 +26,10 @@
 //              the pair s = wbar_t - wbar_{t-1}, y = Eq. (13) at wbar_t applied to s over b_H rows
 //              (Philox domain 6, counter (q/4, k, rep)), stored in the replication's ring of M
 //              slots; the new row and column of S'Y and Y'Y, then R^-1 and C, rebuilt in LDS.
-// Everything is FP64. The stored pairs live in HBM ([R][M][ld] per array). The loss Eq. (10) at the
-// checkpoints and at w^{K+1} is a separate launch over the whole data set.
+// Everything is FP64; the stored pairs live in HBM ([R][M][ld] per array), in binary64 or, on
+// request, binary32 (s rounded before y is formed from it, y rounded when stored: half the bytes of
+// the two passes over them). The loss Eq. (10) at the checkpoints and at w^{K+1} is a separate
+// launch over the whole data set.
 #include <hip/hip_runtime.h>
 
 #include "device_reduce.hpp"
@@ -91,6 +93,22 @@ __device__ __forceinline__ void store4(double *p, const double (&v)[4])
     reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
 }
 
+// the same for pairs stored in binary32: one 16-byte access, rounded to nearest on the way out
+__device__ __forceinline__ void load4(const float *p, double (&v)[4])
+{
+    const float4 a = *reinterpret_cast<const float4 *>(p);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+}
+
+__device__ __forceinline__ void store4(float *p, const double (&v)[4])
+{
+    *reinterpret_cast<float4 *>(p) = make_float4(static_cast<float>(v[0]), static_cast<float>(v[1]),
+                                                 static_cast<float>(v[2]), static_cast<float>(v[3]));
+}
+
 // Sum over the G lanes of a group (G a power of two <= 64, groups aligned in the wavefront); every
 // lane of the wavefront must take part.
 __device__ __forceinline__ double group_sum(double a, uint32_t G)
@@ -138,7 +156,7 @@ __device__ __forceinline__ void vec_dots(const SqnArgs &A, uint32_t count, VecOf
         const uint32_t u = u0 + group;
         double a = 0.0;
         if (u < count) {
-            const double *p = vec(u);
+            const auto *p = vec(u);
 #pragma unroll 4
             for (uint32_t qq = sub; qq < A.nq; qq += G) {
                 double x[4];
@@ -155,7 +173,8 @@ __device__ __forceinline__ void vec_dots(const SqnArgs &A, uint32_t count, VecOf
 
 }  // namespace
 
-template <int EQ>
+// PT: the storage type of the pairs (double, or float when they are kept in binary32)
+template <int EQ, typename PT>
 __global__ __launch_bounds__(kRunBlock) void sqn_run_kernel(SqnArgs A)
 {
     __shared__ double s_stage[kSqnMaxN];                 // the vector the group dot products read
@@ -173,8 +192,8 @@ __global__ __launch_bounds__(kRunBlock) void sqn_run_kernel(SqnArgs A)
     const uint32_t tid = threadIdx.x, T = blockDim.x;
     const uint32_t ld = A.ld, M = A.M, G = A.G, xw = A.xw;
     const size_t vs = static_cast<size_t>(ld);
-    double *Srep = A.S + static_cast<size_t>(rep) * M * ld;
-    double *Yrep = A.Y + static_cast<size_t>(rep) * M * ld;
+    PT *Srep = static_cast<PT *>(A.S) + static_cast<size_t>(rep) * M * ld;
+    PT *Yrep = static_cast<PT *>(A.Y) + static_cast<size_t>(rep) * M * ld;
     double *wprev = A.wprev + static_cast<size_t>(rep) * ld;
     double *acc = A.acc + static_cast<size_t>(rep) * ld;
 
@@ -337,7 +356,7 @@ __global__ __launch_bounds__(kRunBlock) void sqn_run_kernel(SqnArgs A)
                             if ((x >> c) & 1u) y[c] += cf;
                     }
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) y[c] /= static_cast<double>(A.bH);
+                    for (int c = 0; c < 4; ++c) y[c] = static_cast<double>(static_cast<PT>(y[c] / static_cast<double>(A.bH)));
                     store4(Yrep + slot * vs + 4 * q[e], y);
                     store4(s_stage + 4 * q[e], y);
                 }
@@ -552,19 +571,20 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // SY[i][j] = s_i'y_j, YY[i][j] = y_i'y_j (chronological i, j < m) of replication rep: a workgroup
 // per (i, j), a fixed-order tree over the features.
+template <typename PT>
 __global__ __launch_bounds__(256) void sqn_gram_kernel(SqnArgs A, uint32_t rep, uint32_t head, uint32_t m, double *SY,
                                                        double *YY)
 {
     __shared__ double s_a[256], s_b[256];
     const uint32_t i = blockIdx.x, j = blockIdx.y, M = A.M;
     const size_t base = static_cast<size_t>(rep) * M * A.ld;
-    const double *si = A.S + base + static_cast<size_t>((head + i) % M) * A.ld;
-    const double *yi = A.Y + base + static_cast<size_t>((head + i) % M) * A.ld;
-    const double *yj = A.Y + base + static_cast<size_t>((head + j) % M) * A.ld;
+    const PT *si = static_cast<const PT *>(A.S) + base + static_cast<size_t>((head + i) % M) * A.ld;
+    const PT *yi = static_cast<const PT *>(A.Y) + base + static_cast<size_t>((head + i) % M) * A.ld;
+    const PT *yj = static_cast<const PT *>(A.Y) + base + static_cast<size_t>((head + j) % M) * A.ld;
     double a = 0.0, b = 0.0;
     for (uint32_t k = threadIdx.x; k < A.ld; k += blockDim.x) {
-        a += si[k] * yj[k];
-        b += yi[k] * yj[k];
+        a += static_cast<double>(si[k]) * static_cast<double>(yj[k]);
+        b += static_cast<double>(yi[k]) * static_cast<double>(yj[k]);
     }
     s_a[threadIdx.x] = a;
     s_b[threadIdx.x] = b;
@@ -631,6 +651,7 @@ __global__ __launch_bounds__(256) void sqn_middle_kernel(uint32_t m, uint32_t Kp
 
 // Ut[a][k] = U[a][k] and V[a][c] = sum_k U[a][k] W[k][c], feature-major (Kp per feature, zero
 // padded): a wavefront per feature a, a lane per column c.
+template <typename PT>
 __global__ __launch_bounds__(256) void sqn_uv_kernel(SqnArgs A, uint32_t rep, uint32_t head, uint32_t m, uint32_t Kp,
                                                      const double *W, const double *gamma_p, double *V, double *Ut)
 {
@@ -644,8 +665,9 @@ __global__ __launch_bounds__(256) void sqn_uv_kernel(SqnArgs A, uint32_t rep, ui
     const size_t base = static_cast<size_t>(rep) * M * A.ld;
     double x = 0.0;
     if (a < A.n) {
-        if (lane < m) x = A.S[base + static_cast<size_t>((head + lane) % M) * A.ld + a];
-        else if (lane < 2 * m) x = gamma * A.Y[base + static_cast<size_t>((head + lane - m) % M) * A.ld + a];
+        const PT *S = static_cast<const PT *>(A.S), *Y = static_cast<const PT *>(A.Y);
+        if (lane < m) x = S[base + static_cast<size_t>((head + lane) % M) * A.ld + a];
+        else if (lane < 2 * m) x = gamma * static_cast<double>(Y[base + static_cast<size_t>((head + lane - m) % M) * A.ld + a]);
     }
     s_u[wave][lane] = x;
     __syncthreads();
@@ -730,9 +752,15 @@ int launch_sqn_hessian(const SqnArgs &A, uint32_t rep, uint32_t head, uint32_t m
     double *SY = scratch, *YY = SY + kSqnMaxM * kSqnMaxM, *W = YY + kSqnMaxM * kSqnMaxM;
     double *gamma = W + 4 * kSqnMaxM * kSqnMaxM;
     double *V = gamma + 4, *Ut = V + static_cast<size_t>(A.n) * Kp;
-    hipLaunchKernelGGL(sqn_gram_kernel, dim3(m, m), dim3(256), 0, s, A, rep, head, m, SY, YY);
+    if (A.pairs_fp32)
+        hipLaunchKernelGGL(sqn_gram_kernel<float>, dim3(m, m), dim3(256), 0, s, A, rep, head, m, SY, YY);
+    else
+        hipLaunchKernelGGL(sqn_gram_kernel<double>, dim3(m, m), dim3(256), 0, s, A, rep, head, m, SY, YY);
     hipLaunchKernelGGL(sqn_middle_kernel, dim3(1), dim3(256), 0, s, m, Kp, SY, YY, W, gamma);
-    hipLaunchKernelGGL(sqn_uv_kernel, dim3((A.n + 3) / 4), dim3(256), 0, s, A, rep, head, m, Kp, W, gamma, V, Ut);
+    if (A.pairs_fp32)
+        hipLaunchKernelGGL(sqn_uv_kernel<float>, dim3((A.n + 3) / 4), dim3(256), 0, s, A, rep, head, m, Kp, W, gamma, V, Ut);
+    else
+        hipLaunchKernelGGL(sqn_uv_kernel<double>, dim3((A.n + 3) / 4), dim3(256), 0, s, A, rep, head, m, Kp, W, gamma, V, Ut);
     const uint32_t nt = (A.n + 63) / 64;
     hipLaunchKernelGGL(sqn_hessian_mfma_kernel, dim3(nt, nt), dim3(256), 0, s, A.n, ldh, Kp, V, Ut, gamma, H);
     return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -793,10 +821,14 @@ __global__ void sqn_stats_kernel(SqnArgs A)
 
 int launch_sqn_run(const SqnArgs &A, hipStream_t s)
 {
-    if (A.nq <= static_cast<uint32_t>(kRunBlock))
-        hipLaunchKernelGGL(sqn_run_kernel<1>, dim3(A.R), dim3(kRunBlock), 0, s, A);
-    else
-        hipLaunchKernelGGL(sqn_run_kernel<2>, dim3(A.R), dim3(kRunBlock), 0, s, A);
+    const bool one = A.nq <= static_cast<uint32_t>(kRunBlock);
+    if (A.pairs_fp32) {
+        if (one) hipLaunchKernelGGL((sqn_run_kernel<1, float>), dim3(A.R), dim3(kRunBlock), 0, s, A);
+        else hipLaunchKernelGGL((sqn_run_kernel<2, float>), dim3(A.R), dim3(kRunBlock), 0, s, A);
+    } else {
+        if (one) hipLaunchKernelGGL((sqn_run_kernel<1, double>), dim3(A.R), dim3(kRunBlock), 0, s, A);
+        else hipLaunchKernelGGL((sqn_run_kernel<2, double>), dim3(A.R), dim3(kRunBlock), 0, s, A);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

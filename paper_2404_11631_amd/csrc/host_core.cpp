@@ -237,6 +237,7 @@ int validate_sqn(char *err, const sim_sqn_params *p, uint64_t N, uint32_t n, uin
             return fail(err, SIM_EINVAL, "checkpoints must increase strictly");
     }
     if (p->instance_id >= (1u << 24)) return fail(err, SIM_EINVAL, "instance_id must be < 2^24");
+    if (p->pairs_fp32 > 1) return fail(err, SIM_EINVAL, "pairs_fp32 must be 0 or 1");
     return SIM_OK;
 }
 

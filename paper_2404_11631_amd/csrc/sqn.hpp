@@ -32,7 +32,8 @@ struct SqnArgs {
     const uint32_t *X;                      // [N][xw] feature bits, bit j % 32 of word j / 32; zero padded
     uint32_t xw;                            // words per row, a multiple of 4
     const uint8_t *z;                       // [N] labels in {0, 1}
-    double *S, *Y;                          // [R][M][ld] the stored pairs, a ring per replication
+    void *S, *Y;                            // [R][M][ld] the stored pairs (double, or float with pairs_fp32)
+    uint32_t pairs_fp32;
     double *wprev;                          // [R][ld] the previous window's average
     double *acc;                            // [R][ld] the current window's sum of iterates
     double *wsnap;                          // [n_ckpt + 1][R][ld] w after each checkpoint; the last is w^{K+1}

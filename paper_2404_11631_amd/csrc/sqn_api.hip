@@ -80,7 +80,8 @@ int sim_run_sqn(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, u
     const uint32_t nblk = static_cast<uint32_t>((q.N + fw::kSqnLossRows - 1) / fw::kSqnLossRows);
     const size_t n_snap = static_cast<size_t>(nc + 1) * R;
     int rc;
-    if ((rc = ensure(ctx, q.S, sizeof(double) * R * p->M * ld)) || (rc = ensure(ctx, q.Y, sizeof(double) * R * p->M * ld)) ||
+    const size_t pb = p->pairs_fp32 ? sizeof(float) : sizeof(double);
+    if ((rc = ensure(ctx, q.S, pb * R * p->M * ld)) || (rc = ensure(ctx, q.Y, pb * R * p->M * ld)) ||
         (rc = ensure(ctx, q.wprev, sizeof(double) * R * ld)) || (rc = ensure(ctx, q.acc, sizeof(double) * R * ld)) || (rc = ensure(ctx, q.wsnap, sizeof(double) * n_snap * ld)) ||
         (rc = ensure(ctx, q.pairs, sizeof(uint32_t) * R)) ||
         (n_snap >= fw::kSqnManySnap && (rc = ensure(ctx, q.wt, sizeof(double) * n_snap * ld))) ||
@@ -115,8 +116,9 @@ int sim_run_sqn(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, u
     for (uint32_t c = 0; c < nc; ++c) A.ckpt[c] = p->checkpoints[c];
     A.X = static_cast<const uint32_t *>(q.X.ptr);
     A.z = static_cast<const uint8_t *>(q.z.ptr);
-    A.S = static_cast<double *>(q.S.ptr);
-    A.Y = static_cast<double *>(q.Y.ptr);
+    A.S = q.S.ptr;
+    A.Y = q.Y.ptr;
+    A.pairs_fp32 = p->pairs_fp32 ? 1u : 0u;
     A.wprev = static_cast<double *>(q.wprev.ptr);
     A.acc = static_cast<double *>(q.acc.ptr);
     A.wsnap = static_cast<double *>(q.wsnap.ptr);
@@ -181,8 +183,9 @@ int sim_sqn_paths(sim_ctx *ctx, sim_sqn_view *out)
     out->w_ckpt = nc ? ws : nullptr;
     out->pairs = static_cast<const uint32_t *>(q.pairs.ptr);
     out->M = q.params.M;
-    out->S = static_cast<const double *>(q.S.ptr);
-    out->Y = static_cast<const double *>(q.Y.ptr);
+    out->pairs_fp32 = q.params.pairs_fp32 ? 1u : 0u;
+    out->S = q.S.ptr;
+    out->Y = q.Y.ptr;
     return SIM_OK;
 }
 
@@ -210,8 +213,9 @@ int sim_sqn_hessian(sim_ctx *ctx, uint64_t rep, sim_sqn_hessian_view *out)
     A.n = q.n;
     A.ld = q.ld;
     A.M = M;
-    A.S = static_cast<double *>(q.S.ptr);
-    A.Y = static_cast<double *>(q.Y.ptr);
+    A.S = q.S.ptr;
+    A.Y = q.Y.ptr;
+    A.pairs_fp32 = q.params.pairs_fp32 ? 1u : 0u;
     hipStream_t st = ctx->stream;
     HIP_TRY(ctx, hipEventRecord(q.ev3, st));
     if (fw::launch_sqn_hessian(A, static_cast<uint32_t>(rep), head, m, static_cast<double *>(q.hscratch.ptr),

@@ -149,7 +149,7 @@ def validate_newsvendor(inst: dict, R: int, T: int, **kw):
 class SimSqnParams(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_uint32), ("L", ctypes.c_uint32), ("M", ctypes.c_uint32),
                 ("b", ctypes.c_uint32), ("b_H", ctypes.c_uint32), ("n_checkpoints", ctypes.c_uint32),
-                ("instance_id", ctypes.c_uint32), ("pad_", ctypes.c_uint32), ("beta", ctypes.c_double),
+                ("instance_id", ctypes.c_uint32), ("pairs_fp32", ctypes.c_uint32), ("beta", ctypes.c_double),
                 ("checkpoints", ctypes.c_uint64 * MAX_CKPT)]
 
 
@@ -157,7 +157,7 @@ class SimSqnView(ctypes.Structure):
     _fields_ = [("R", ctypes.c_uint64), ("K", ctypes.c_uint64), ("n", ctypes.c_uint32), ("ld", ctypes.c_uint32),
                 ("n_checkpoints", ctypes.c_uint32), ("pad_", ctypes.c_uint32), ("F", ctypes.c_void_p),
                 ("F_ckpt", ctypes.c_void_p), ("w", ctypes.c_void_p), ("w_ckpt", ctypes.c_void_p),
-                ("pairs", ctypes.c_void_p), ("M", ctypes.c_uint32), ("pad2_", ctypes.c_uint32),
+                ("pairs", ctypes.c_void_p), ("M", ctypes.c_uint32), ("pairs_fp32", ctypes.c_uint32),
                 ("S", ctypes.c_void_p), ("Y", ctypes.c_void_p)]
 
 
@@ -167,7 +167,7 @@ class SimSqnHessianView(ctypes.Structure):
 
 
 def sqn_params(L: int = 10, M: int = 25, b: int = 50, bH: int = 300, beta: float = 2.0, checkpoints=(),
-               instance_id: int = 0) -> SimSqnParams:
+               instance_id: int = 0, pairs_fp32: bool = False) -> SimSqnParams:
     """sim_sqn_params; the defaults are Section 4.1's Task 3 settings (b_H = 300)."""
     sp = SimSqnParams()
     sp.abi_version = ABI_VERSION
@@ -176,6 +176,7 @@ def sqn_params(L: int = 10, M: int = 25, b: int = 50, bH: int = 300, beta: float
     for i, c in enumerate(checkpoints[:MAX_CKPT]):
         sp.checkpoints[i] = int(c)
     sp.instance_id = instance_id
+    sp.pairs_fp32 = 1 if pairs_fp32 else 0
     return sp
 
 
@@ -505,8 +506,9 @@ class Sim:
                          else np.zeros((0, R, n)))
         out["pairs"] = self._copy(v.pairs, np.uint32, R)
         M = v.M
-        S = self._copy(v.S, np.float64, R * M * ld).reshape(R, M, ld)[:, :, :n]
-        Y = self._copy(v.Y, np.float64, R * M * ld).reshape(R, M, ld)[:, :, :n]
+        pt = np.float32 if v.pairs_fp32 else np.float64
+        S = self._copy(v.S, pt, R * M * ld).reshape(R, M, ld)[:, :, :n].astype(np.float64)
+        Y = self._copy(v.Y, pt, R * M * ld).reshape(R, M, ld)[:, :, :n].astype(np.float64)
         out["S"], out["Y"] = [], []
         for r in range(R):                      # each replication's pairs, oldest first
             P = int(out["pairs"][r])

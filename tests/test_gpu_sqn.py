@@ -41,16 +41,22 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def run_and_compare(ctx, X, z, R, K, seed, L=10, M=25, b=50, bH=300, beta=2.0, ckpt=(), instance=0, load=True):
+def run_and_compare(ctx, X, z, R, K, seed, L=10, M=25, b=50, bH=300, beta=2.0, ckpt=(), instance=0, load=True,
+                    pairs_fp32=False):
     N, n = X.shape
-    say(f"[sqn] n={n} N={N} R={R} K={K} L={L} M={M} b={b} bH={bH} seed={seed} ckpt={ckpt}")
+    say(f"[sqn] n={n} N={N} R={R} K={K} L={L} M={M} b={b} bH={bH} seed={seed} ckpt={ckpt} fp32 pairs={pairs_fp32}")
     if load:
         ctx.sqn_load(X, z)
-    ctx.run_sqn(R, K, seed, L=L, M=M, b=b, bH=bH, beta=beta, checkpoints=ckpt, instance_id=instance)
+    ctx.run_sqn(R, K, seed, L=L, M=M, b=b, bH=bH, beta=beta, checkpoints=ckpt, instance_id=instance,
+                pairs_fp32=pairs_fp32)
     st = ctx.sqn_stats()
     g = ctx.sqn_paths()
     assert np.all(g["w_pad"] == 0.0)
-    O = oracle.SqnOracle(X, z, L=L, M=M, b=b, bH=bH, beta=beta, seed=seed, instance=instance, ckpt=ckpt)
+    O = oracle.SqnOracle(X, z, L=L, M=M, b=b, bH=bH, beta=beta, seed=seed, instance=instance, ckpt=ckpt,
+                         pairs_fp32=pairs_fp32)
+    # binary32 pairs: both sides round at the same points, but a value within 1e-15 of a binary32
+    # rounding boundary may round differently on the two sides (one ulp, 6e-8 of one entry)
+    w_rtol, f_rtol = (1e-7, 1e-9) if pairs_fp32 else (W_RTOL, F_RTOL)
     Fs, worst_w, worst_f = [], 0.0, 0.0
     for r in range(R):
         o = O.run(r, K)
@@ -58,11 +64,11 @@ def run_and_compare(ctx, X, z, R, K, seed, L=10, M=25, b=50, bH=300, beta=2.0, c
         ew = rel(g["w"][r], o["w"])
         ef = abs(g["F"][r] - o["F"]) / o["F"]
         worst_w, worst_f = max(worst_w, ew), max(worst_f, ef)
-        assert ew <= W_RTOL, (r, ew)
-        assert ef <= F_RTOL, (r, g["F"][r], o["F"])
+        assert ew <= w_rtol, (r, ew)
+        assert ef <= f_rtol, (r, g["F"][r], o["F"])
         assert abs(g["F"][r] - O.loss(g["w"][r])) <= 1e-12 * o["F"]
         for c in range(len(ckpt)):
-            assert abs(g["F_ckpt"][c, r] - o["F_ckpt"][c]) <= F_RTOL * o["F_ckpt"][c]
+            assert abs(g["F_ckpt"][c, r] - o["F_ckpt"][c]) <= f_rtol * o["F_ckpt"][c]
             assert abs(g["F_ckpt"][c, r] - O.loss(g["w_ckpt"][c, r])) <= 1e-12 * o["F_ckpt"][c]
         Fs.append(o["F"])
     Fs = np.array(Fs)
@@ -122,6 +128,26 @@ def test_sqn_single_feature(ctx):
             assert np.isnan(g["F"][r])
         else:
             assert rel(g["w"][r], o["w"]) <= W_RTOL
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=50, R=2, K=400, M=5, ckpt=(200, 400)),
+    dict(n=37, N=1110, R=2, K=120, L=5, M=4, b=17, bH=33),
+    dict(n=1000, N=30000, R=2, K=60, M=3, bH=600, ckpt=(30,)),
+    dict(n=4100, N=5000, R=1, K=40, M=3),
+])
+def test_sqn_binary32_pairs(ctx, case):
+    """The pairs kept in binary32 (pairs_fp32): against the oracle run with the same rounding points;
+    Algorithm 4's matrix from the float pairs against the oracle's chain over the same pairs."""
+    c = dict(case)
+    n = c.pop("n")
+    X, z = workloads.sqn_dataset(18, n, c.pop("N", None))
+    st, g = run_and_compare(ctx, X, z, c.pop("R"), c.pop("K"), 23, pairs_fp32=True, **c)
+    S, Y = g["S"][0], g["Y"][0]
+    assert np.array_equal(S, S.astype(np.float32).astype(np.float64))
+    h = ctx.sqn_hessian(0)
+    ref = oracle.SqnOracle.hessian_approx(S, Y)
+    assert np.linalg.norm(h["H"] - ref) <= 1e-10 * np.linalg.norm(ref)
 
 
 def test_sqn_many_replications(ctx):

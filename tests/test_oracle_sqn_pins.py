@@ -259,3 +259,21 @@ def test_long_run_reaches_the_minimum():
     assert best < out["F"] < best + 0.02
     assert out["F_ckpt"][0] > out["F_ckpt"][1] > out["F"] - 1e-3
     assert out["pairs"] == 199
+
+
+def test_binary32_pairs_stay_close_and_round_where_stated():
+    """With the pairs stored in binary32 the run follows the binary64 run closely (the rounding of s
+    and y perturbs H_t by about 2^-24 relatively), pairs and the loss's descent unchanged; at K <= 2L
+    (no pair used yet) the two runs are identical bit for bit."""
+    n = 30
+    X, z = data(n, seed=10)
+    kw = dict(L=10, M=8, b=40, bH=200, seed=4, ckpt=(100,))
+    a = oracle.SqnOracle(X, z, **kw).run(0, 300)
+    b = oracle.SqnOracle(X, z, pairs_fp32=True, **kw).run(0, 300)
+    assert a["pairs"] == b["pairs"] == 29
+    err = np.linalg.norm(a["w"] - b["w"]) / np.linalg.norm(a["w"])
+    assert 0.0 < err < 1e-5
+    assert abs(a["F"] - b["F"]) < 1e-7 * a["F"]
+    early_a = oracle.SqnOracle(X, z, **kw).run(0, 20)
+    early_b = oracle.SqnOracle(X, z, pairs_fp32=True, **kw).run(0, 20)
+    assert np.array_equal(early_a["w"], early_b["w"])
