@@ -324,7 +324,7 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
 def paper_shape_leg(ctx, sim, runs: int, warmup: int):
     """Algorithm 1 at the shape of Section 4.1 (Task 1): one replication of d assets, mu ~ U(-1,1),
     sigma ~ U(0, 0.025), K = 1500 iterations, N = 25 samples per gradient (50 at d = 1e5), on the
-    wide path (sim_run_wide). Per size: device time of the whole run (HIP events around its 4 K
+    wide path (sim_run_wide). Per size: device time of the whole run (HIP events around its ~3 K
     launches), the wall time of the call and its statistics read-back, and the ALU roofline of the
     method's algorithmic work (23 lane-ops per normal, N d normals and ~15 d further operations per
     iteration; the device draws each normal twice, which is not counted). The paper reports about
@@ -361,7 +361,7 @@ def paper_shape_leg(ctx, sim, runs: int, warmup: int):
 def newsvendor_shape_leg(ctx, sim, runs: int, warmup: int):
     """Algorithm 2 (Task 2) at the shape of Section 4.1: one replication of n products, K = 1500, S = 25
     demand samples per product (50 at n = 1e6), mu ~ U(20, 50), sigma ~ U(10, 20), on
-    sim_run_newsvendor. Per size: device time of the run (HIP events around its 2 K launches), the
+    sim_run_newsvendor. Per size: device time of the run (HIP events around its launches), the
     wall time of the call and its read-back, and the sample throughput (S n demand samples per
     iteration). The gradient is an integer count, so the ALU fraction counts 23 lane-ops per normal and
     2 per comparison."""
