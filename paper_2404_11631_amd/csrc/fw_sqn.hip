@@ -685,8 +685,11 @@ __global__ __launch_bounds__(256) void sqn_uv_kernel(SqnArgs A, uint32_t rep, ui
 __global__ __launch_bounds__(256) void sqn_hessian_mfma_kernel(uint32_t n, uint32_t ldh, uint32_t Kp, const double *V,
                                                                const double *Ut, const double *gamma_p, double *H)
 {
-    // the workgroup's 64 rows of V and of Ut are contiguous (64 Kp doubles each): 16-byte loads into LDS
-    __shared__ double s_A[64 * 2 * kSqnMaxM], s_B[64 * 2 * kSqnMaxM];
+    // The workgroup's 64 rows of V and of Ut are contiguous (64 Kp doubles each): 16-byte loads, stored
+    // k-major in LDS with a pitch of 65 doubles, so the 16 rows an operand read spans fall in
+    // consecutive banks (a row-major tile at pitch Kp puts them in 4 bank groups).
+    constexpr uint32_t P = 65;
+    __shared__ double s_A[2 * kSqnMaxM * P], s_B[2 * kSqnMaxM * P];
     const uint32_t ra = blockIdx.y * 64, rb = blockIdx.x * 64;
     const uint32_t na = min(64u, n - ra) * Kp, nb = min(64u, n - rb) * Kp;
     const double2 *ga = reinterpret_cast<const double2 *>(V + static_cast<size_t>(ra) * Kp);
@@ -694,10 +697,11 @@ __global__ __launch_bounds__(256) void sqn_hessian_mfma_kernel(uint32_t n, uint3
     for (uint32_t u = threadIdx.x; u < 32 * Kp; u += blockDim.x) {
         const double2 x = 2 * u < na ? ga[u] : make_double2(0.0, 0.0);
         const double2 y = 2 * u < nb ? gb[u] : make_double2(0.0, 0.0);
-        s_A[2 * u] = x.x;
-        s_A[2 * u + 1] = x.y;
-        s_B[2 * u] = y.x;
-        s_B[2 * u + 1] = y.y;
+        const uint32_t row = (2 * u) / Kp, k = (2 * u) % Kp;     // Kp is a multiple of 4: k, k + 1 share the row
+        s_A[k * P + row] = x.x;
+        s_A[(k + 1) * P + row] = x.y;
+        s_B[k * P + row] = y.x;
+        s_B[(k + 1) * P + row] = y.y;
     }
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -712,8 +716,8 @@ __global__ __launch_bounds__(256) void sqn_hessian_mfma_kernel(uint32_t n, uint3
         double av[2], bv[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
-            av[x] = s_A[(ta + 16 * x + lr) * Kp + kb + lk];
-            bv[x] = s_B[(tb + 16 * x + lr) * Kp + kb + lk];
+            av[x] = s_A[(kb + lk) * P + ta + 16 * x + lr];
+            bv[x] = s_B[(kb + lk) * P + tb + 16 * x + lr];
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x)
