@@ -7,9 +7,10 @@ fused with its cross-path reduction, followed by sim_stats; every step draws fre
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--cpu-seconds 20] [--no-cpu-baseline]
 
-The line also carries the control-variate leg ("cv", skip with --no-cv) and the sweeps over the
+The line also carries the control-variate leg ("cv", skip with --no-cv), the sweeps over the
 Section 4.1 shapes of Task 1 ("paper_shape"), Task 2 ("newsvendor_shape") and Task 3
-("sqn_shape"), skipped with --no-paper-shape.
+("sqn_shape"), and Table 2's RSE statistic over seven replications of each task ("table2"), all
+skipped with --no-paper-shape.
 
 Other measurements (not the headline line):
     --workload stress [--reps R]   the dense-L, t(3) stress workload (d = 64, N = 100, T = 1e3)
@@ -206,6 +207,7 @@ def main():
     shape = None if args.no_paper_shape else paper_shape_leg(ctx, sim, 2, 1)
     nv_shape = None if args.no_paper_shape else newsvendor_shape_leg(ctx, sim, 2, 1)
     sqn_shape = None if args.no_paper_shape else sqn_shape_leg(ctx, sim, 2, 1)
+    table2 = None if args.no_paper_shape else table2_leg(ctx, sim)
     ctx.close()
 
     ms_step = 1e3 * wall / args.steps
@@ -241,6 +243,8 @@ def main():
         line["newsvendor_shape"] = nv_shape
     if sqn_shape is not None:
         line["sqn_shape"] = sqn_shape
+    if table2 is not None:
+        line["table2"] = table2
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, mu, sigma, args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -495,6 +499,46 @@ def sqn_shape_leg(ctx, sim, runs: int, warmup: int, throughput_sizes=(5_000,), s
             print(f"[sqn_shape] n={n} bH={bH}: {kavg:.1f} ms per run"
                   + (f", R={entry['batch']['R']}: {entry['batch']['device_ms']:.1f} ms" if "batch" in entry else ""),
                   file=sys.stderr, flush=True)
+    return out
+
+
+# Table 2 of the paper (GPU column): mean RSE in percent at iterations 50, 100, 500, 1000 over seven
+# runs, on the paper's own instances and hardware (context only: instances, seeds and start points
+# differ here)
+TABLE2_PAPER_GPU = {"asset_5k": [85.07, 62.41, 24.07, 13.39], "inventory_10k": [89.92, 76.25, 40.94, 20.58],
+                    "classification_1k": [72.16, 51.06, 31.29, 15.59]}
+
+
+def table2_leg(ctx, sim):
+    """Table 2's statistic on this library: RSE_c = ((f_c - f_K) / f_c)^2 at c in {50, 100, 500, 1000},
+    mean and standard deviation over R = 7 replications, in percent, for Task 1 at d = 5000 (wide
+    path, paper regime, N = 25, K = 1500), Task 2 at n = 1e4 (S = 25, K = 1500) and Task 3 at
+    n = 1000 (N = 30 n, K = 2000, b_H = 300), beside the paper's GPU column."""
+    from paper_2404_11631_amd import workloads
+
+    ck = (50, 100, 500, 1000)
+    out = {"R": 7, "checkpoints": list(ck), "unit": "percent", "rows": {}}
+
+    def row(name, st, device_ms):
+        out["rows"][name] = {"rse_mean": [100.0 * st.rse_mean[c] for c in range(len(ck))],
+                             "rse_sd": [100.0 * st.rse_sd[c] for c in range(len(ck))],
+                             "paper_gpu_mean": TABLE2_PAPER_GPU[name], "device_ms": device_ms}
+
+    mu, sig = workloads.diag_instance(0, 0, 5000, "paper")
+    ctx.run_wide(sim.Problem(mu=mu, sigma=sig, N=25, checkpoints=ck), 7, 1500, 11)
+    st = ctx.wide_stats()
+    row("asset_5k", st, st.kernel_ms)
+    inst = workloads.newsvendor_instance(0, 0, 10_000)
+    ctx.run_newsvendor(inst, 7, 1500, 12, S=25, checkpoints=ck)
+    st = ctx.nv_stats()
+    row("inventory_10k", st, st.kernel_ms)
+    X, z = workloads.sqn_dataset(0, 1000)
+    ctx.sqn_load(X, z)
+    ctx.run_sqn(7, 2000, 13, bH=300, checkpoints=ck)
+    st = ctx.sqn_stats()
+    row("classification_1k", st, st.kernel_ms)
+    print("[table2] " + "; ".join(f"{k}: {[round(x, 2) for x in v['rse_mean']]}" for k, v in out["rows"].items()),
+          file=sys.stderr, flush=True)
     return out
 
 
