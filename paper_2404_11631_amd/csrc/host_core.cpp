@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <numeric>
 
 namespace fw {
@@ -580,8 +581,8 @@ double lane_cost(const sim_params &p, uint64_t T, uint32_t P)
     return (double)T * (20.0 * normals + 15.0 * p.d + 6.0 * p.d * stages);
 }
 
-int plan_batch(char *err, uint32_t n_inst, const sim_params *p, const uint64_t *R, const uint64_t *T,
-               uint64_t seed, const sim_batch_config *cfg, uint32_t n_cu, BatchPlan &out)
+static int plan_batch_impl(char *err, uint32_t n_inst, const sim_params *p, const uint64_t *R, const uint64_t *T,
+                           uint64_t seed, const sim_batch_config *cfg, uint32_t n_cu, BatchPlan &out)
 {
     if (n_inst < 1 || n_inst > 65536 || !p || !R || !T)
         return fail(err, SIM_EINVAL, "need 1 <= n_inst <= 65536 and non-NULL p, R, T");
@@ -707,6 +708,18 @@ int plan_batch(char *err, uint32_t n_inst, const sim_params *p, const uint64_t *
     }
     for (uint32_t c = 0; c < 8; ++c) out.class_begin[c + 1] += out.class_begin[c];
     return SIM_OK;
+}
+
+int plan_batch(char *err, uint32_t n_inst, const sim_params *p, const uint64_t *R, const uint64_t *T,
+               uint64_t seed, const sim_batch_config *cfg, uint32_t n_cu, BatchPlan &out)
+{
+    // the plan's tables grow with the number of tiles (up to 2^32 - 1): a failed host allocation is
+    // an error code, never an exception through the C interface
+    try {
+        return plan_batch_impl(err, n_inst, p, R, T, seed, cfg, n_cu, out);
+    } catch (const std::bad_alloc &) {
+        return fail(err, SIM_ENOMEM, "host memory for the batch plan");
+    }
 }
 
 }  // namespace host

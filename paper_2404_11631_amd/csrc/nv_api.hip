@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "engine.hpp"
@@ -87,8 +88,14 @@ int sim_run_newsvendor(sim_ctx *ctx, const sim_nv_params *p, uint64_t R, uint64_
 
     // per product: binary32 coefficients (the normals carry the factor 1/sqrt(2 ln 2)), binary64 for Eq. (6)
     const double kappa = fw::kBoxMullerScale;
-    std::vector<float> pf(7 * N);
-    std::vector<double> pd(6 * N);
+    std::vector<float> pf;
+    std::vector<double> pd;
+    try {
+        pf.resize(7 * N);
+        pd.resize(6 * N);
+    } catch (const std::bad_alloc &) {
+        return set_err(ctx, SIM_ENOMEM, "host staging of the product coefficients");
+    }
     for (size_t j = 0; j < N; ++j) {
         const double xs = p->C / p->c[j];
         pf[j] = static_cast<float>(p->mu[j]);

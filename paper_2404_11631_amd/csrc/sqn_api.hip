@@ -2,9 +2,11 @@
 // validation, device buffers, the launches, and the statistics and records of the last run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "engine.hpp"
@@ -34,18 +36,31 @@ int sim_sqn_load(sim_ctx *ctx, const uint8_t *X, const uint8_t *z, uint64_t N, u
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     SqnState &q = ctx->sqn;
     q.have_data = q.have = false;
-    // bitmap rows: bit j % 32 of word j / 32, rows padded to a multiple of four words (16 bytes)
+    // bitmap rows: bit j % 32 of word j / 32, rows padded to a multiple of four words (16 bytes);
+    // packed on the host a block of rows at a time (at most 64 MB of staging) and copied up
     const uint32_t xw = ((n + 31) / 32 + 3) / 4 * 4;
-    std::vector<uint32_t> bits(static_cast<size_t>(N) * xw, 0u);
-    for (uint64_t i = 0; i < N; ++i) {
-        const uint8_t *row = X + i * n;
-        uint32_t *dst = bits.data() + i * xw;
-        for (uint32_t j = 0; j < n; ++j) dst[j >> 5] |= static_cast<uint32_t>(row[j]) << (j & 31);
+    const uint64_t block = 65536;
+    std::vector<uint32_t> bits;
+    try {
+        bits.resize(static_cast<size_t>(std::min<uint64_t>(N, block)) * xw);
+    } catch (const std::bad_alloc &) {
+        return set_err(ctx, SIM_ENOMEM, "host staging for the feature bitmap");
     }
     int rc;
-    if ((rc = ensure(ctx, q.X, sizeof(uint32_t) * bits.size())) || (rc = ensure(ctx, q.z, N))) return rc;
+    if ((rc = ensure(ctx, q.X, sizeof(uint32_t) * static_cast<size_t>(N) * xw)) || (rc = ensure(ctx, q.z, N))) return rc;
     hipStream_t st = ctx->stream;
-    HIP_TRY(ctx, hipMemcpyAsync(q.X.ptr, bits.data(), sizeof(uint32_t) * bits.size(), hipMemcpyHostToDevice, st));
+    for (uint64_t i0 = 0; i0 < N; i0 += block) {
+        const uint64_t rows = std::min<uint64_t>(block, N - i0);
+        std::fill(bits.begin(), bits.end(), 0u);
+        for (uint64_t i = 0; i < rows; ++i) {
+            const uint8_t *row = X + (i0 + i) * n;
+            uint32_t *dst = bits.data() + i * xw;
+            for (uint32_t j = 0; j < n; ++j) dst[j >> 5] |= static_cast<uint32_t>(row[j]) << (j & 31);
+        }
+        HIP_TRY(ctx, hipStreamSynchronize(st));     // the previous block's copy has read the staging
+        HIP_TRY(ctx, hipMemcpyAsync(static_cast<uint32_t *>(q.X.ptr) + i0 * xw, bits.data(),
+                                    sizeof(uint32_t) * rows * xw, hipMemcpyHostToDevice, st));
+    }
     HIP_TRY(ctx, hipMemcpyAsync(q.z.ptr, z, N, hipMemcpyHostToDevice, st));
     HIP_TRY(ctx, hipStreamSynchronize(st));
     q.xw = xw;

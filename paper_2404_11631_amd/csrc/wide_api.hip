@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "engine.hpp"
@@ -104,8 +105,14 @@ int sim_run_wide(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint
 
     // per-asset coefficients (FP32 in units of the scaled normals, FP64 for the objective)
     const double kappa = fw::kBoxMullerScale;
-    std::vector<float> af(5 * D);
-    std::vector<double> ad(2 * D);
+    std::vector<float> af;
+    std::vector<double> ad;
+    try {
+        af.resize(5 * D);
+        ad.resize(2 * D);
+    } catch (const std::bad_alloc &) {
+        return set_err(ctx, SIM_ENOMEM, "host staging of the asset coefficients");
+    }
     for (size_t j = 0; j < D; ++j) {
         const double sz = kappa * p->sigma[j];
         af[j] = static_cast<float>(p->mu[j]);
