@@ -20,6 +20,8 @@ Other measurements (not the headline line):
                                    products, K = 1500
     --workload sqn_shape           Task 3 (Algorithms 3-4) at Section 4.1's settings: n = 50 .. 5000
                                    features, N = 30 n, K = 2000, b_H = 300 / 600
+    --workload uneven              the 256 uneven instances on the plain path, instance by instance
+                                   over four streams
     --copy-probe BYTES             one plain device-to-device copy of BYTES, for calibrating the
                                    FETCH_SIZE / WRITE_SIZE counters against known traffic
 """
@@ -141,7 +143,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="paper_scale",
-                    choices=("paper_scale", "stress", "paper_shape", "newsvendor_shape", "sqn_shape"))
+                    choices=("paper_scale", "stress", "paper_shape", "newsvendor_shape", "sqn_shape", "uneven"))
     ap.add_argument("--no-paper-shape", action="store_true", help="skip the Section 4.1 shape sweeps")
     ap.add_argument("--reps", type=int, default=0, help="replications (stress only; 0: the full 1e7)")
     ap.add_argument("--sqn-sizes", default="", help="feature counts of the sqn_shape workload (comma list; "
@@ -161,6 +163,9 @@ def main():
         return
     if args.workload == "stress":
         stress(args)
+        return
+    if args.workload == "uneven":
+        uneven_plain(args)
         return
     if args.workload in ("paper_shape", "newsvendor_shape", "sqn_shape"):
         import torch
@@ -540,6 +545,64 @@ def table2_leg(ctx, sim):
     print("[table2] " + "; ".join(f"{k}: {[round(x, 2) for x in v['rse_mean']]}" for k, v in out["rows"].items()),
           file=sys.stderr, flush=True)
     return out
+
+
+def uneven_plain(args):
+    """The uneven workload (256 instances: d ~ U{2..32}, N ~ U{2..50}, T log-uniform in [100, 1e5],
+    4096 replications each) on the plain fused path, instance by instance: four contexts on four
+    streams of default priority, instances longest first, round robin, each context reading its
+    statistics before it takes the next instance. The batched device path (one launch for all
+    instances) is switched off; this measures the workload without it."""
+    import torch
+
+    from paper_2404_11631_amd import sim, workloads
+
+    w = workloads.WORKLOADS["uneven"]
+    batch = workloads.uneven_batch(w["seed"], w["n_instances"], w["R"], w["d_range"], w["n_range"], w["t_range"])
+    torch.cuda.init()
+    n_ctx = 4
+    streams = [torch.cuda.Stream() for _ in range(n_ctx)]
+    ctxs = [sim.Sim(0, s.cuda_stream) for s in streams]
+    order = sorted(range(len(batch)), key=lambda i: -batch[i].T * batch[i].N * batch[i].d)
+    problems = {i: sim.Problem(mu=batch[i].mu, sigma=batch[i].sigma, N=batch[i].N, M=1, precision=sim.FP32)
+                for i in order}
+    # one small run per context first (library set-up, buffers)
+    for c in ctxs:
+        c.run(problems[order[-1]], 64, 100, 1)
+        c.stats()
+    torch.cuda.synchronize()
+    pending = [None] * n_ctx
+    kms = {}
+    t0 = time.perf_counter()
+    for k, i in enumerate(order):
+        c = k % n_ctx
+        if pending[c] is not None:
+            kms[pending[c]] = ctxs[c].stats().kernel_ms
+        ctxs[c].run(problems[i], batch[i].R, batch[i].T, w["seed"] + 1 + i)
+        pending[c] = i
+        if k % 32 == 0:
+            print(f"[uneven] {k} of {len(order)} instances launched", file=sys.stderr, flush=True)
+    for c in range(n_ctx):
+        if pending[c] is not None:
+            kms[pending[c]] = ctxs[c].stats().kernel_ms
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for c in ctxs:
+        c.close()
+    steps = sum(b.R * b.T for b in batch)
+    ops = sum(b.R * b.T * ops_per_path_step(b.d, b.N) for b in batch)
+    line = {
+        "metric": "path-steps/s, uneven workload on the plain path (instance by instance, 4 streams)",
+        "value": steps / wall, "unit": "path-steps/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1e3 * wall, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "uneven", "instances": len(batch), "R": w["R"], "d": list(w["d_range"]),
+                   "N": list(w["n_range"]), "T": list(w["t_range"]), "streams": n_ctx},
+        "roofline": {"bound": "alu", "achieved": ops / wall / 1e12, "peak": PEAK_OPS / 1e12, "unit": "TOP/s",
+                     "frac": ops / wall / PEAK_OPS, "traffic": None},
+        "path_steps": steps, "wall_s": wall, "sum_kernel_ms": sum(kms.values()),
+        "longest_instance_ms": max(kms.values()),
+    }
+    print(json.dumps(line), flush=True)
 
 
 def stress(args):
