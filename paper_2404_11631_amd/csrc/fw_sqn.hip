@@ -60,10 +60,19 @@ __device__ __forceinline__ void draw_rows(const SqnArgs &A, uint32_t rep, uint64
     }
 }
 
-// The four feature bits of quad q of a row (bit c = feature 4q + c).
-__device__ __forceinline__ uint32_t quad_bits(const uint32_t *X, uint32_t row, uint32_t xw, uint32_t q)
+// Rows idx[i0 .. i0 + cnt) of the bitmap (cnt <= kStageRows) into rows[r][xw] of LDS, 16-byte loads
+// spread over the workgroup. The caller synchronises before and after.
+constexpr uint32_t kStageRows = 32;
+
+__device__ __forceinline__ void stage_rows(const SqnArgs &A, const uint32_t *idx, uint32_t i0, uint32_t cnt,
+                                           uint32_t *rows)
 {
-    return (X[static_cast<size_t>(row) * xw + (q >> 3)] >> (4 * (q & 7))) & 0xFu;
+    const uint32_t q4 = A.xw / 4, total = cnt * q4;
+    for (uint32_t u = threadIdx.x; u < total; u += blockDim.x) {
+        const uint32_t r = u / q4, wq = u % q4;
+        reinterpret_cast<uint4 *>(rows + r * A.xw)[wq] =
+            reinterpret_cast<const uint4 *>(A.X + static_cast<size_t>(idx[i0 + r]) * A.xw)[wq];
+    }
 }
 
 // v summed over the set bits of a 32-feature word starting at feature j0, lowest bit first.
@@ -187,6 +196,7 @@ __global__ __launch_bounds__(kRunBlock) void sqn_run_kernel(SqnArgs A)
     __shared__ double s_Ri[kSqnMaxM * kSqnMaxM];         // R^-1 (upper triangular)
     __shared__ double s_C[kSqnMaxM * kSqnMaxM];          // R^-T (D + gamma Y'Y) R^-1
     __shared__ double s_cs[kSqnMaxM], s_cy[kSqnMaxM];    // coefficients of S and Y in H g
+    __shared__ uint32_t s_rows[kStageRows * (kSqnMaxN / 32)];   // a chunk of sampled rows' bits
 
     const uint32_t rep = blockIdx.x;
     const uint32_t tid = threadIdx.x, T = blockDim.x;
@@ -231,15 +241,29 @@ __global__ __launch_bounds__(kRunBlock) void sqn_run_kernel(SqnArgs A)
         for (int e = 0; e < EQ; ++e) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) g[e][c] = 0.0;
-            if (!own[e]) continue;
-#pragma unroll 8
-            for (uint32_t i = 0; i < A.b; ++i) {
-                const uint32_t x = quad_bits(A.X, s_idx[i], xw, q[e]);
-                const double r = s_coef[i];
+        }
+        // Eq. (12): the rows in order, staged through LDS kStageRows at a time
+        for (uint32_t i0 = 0; i0 < A.b; i0 += kStageRows) {
+            const uint32_t cnt = min(kStageRows, A.b - i0);
+            __syncthreads();
+            stage_rows(A, s_idx, i0, cnt, s_rows);
+            __syncthreads();
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if ((x >> c) & 1u) g[e][c] += r;
+            for (int e = 0; e < EQ; ++e) {
+                if (!own[e]) continue;
+                const uint32_t wq = q[e] >> 3, sh = 4 * (q[e] & 7);
+                for (uint32_t i = 0; i < cnt; ++i) {
+                    const uint32_t x = (s_rows[i * xw + wq] >> sh) & 0xFu;
+                    const double r = s_coef[i0 + i];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if ((x >> c) & 1u) g[e][c] += r;
+                }
             }
+        }
+#pragma unroll
+        for (int e = 0; e < EQ; ++e) {
+            if (!own[e]) continue;
             double a4[4];
             load4(acc + 4 * q[e], a4);
 #pragma unroll
@@ -342,23 +366,39 @@ __global__ __launch_bounds__(kRunBlock) void sqn_run_kernel(SqnArgs A)
                     s_coef[i] = c * (1.0 - c) * s_coef[i];
                 }
                 __syncthreads();
-                // Eq. (13) applied to s, into the ring and staged
+                // Eq. (13) applied to s (the rows in order, staged through LDS kStageRows at a time),
+                // into the ring and staged
+                double y[EQ][4];
+#pragma unroll
+                for (int e = 0; e < EQ; ++e)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) y[e][c] = 0.0;
+                for (uint32_t i0 = 0; i0 < A.bH; i0 += kStageRows) {
+                    const uint32_t cnt = min(kStageRows, A.bH - i0);
+                    __syncthreads();
+                    stage_rows(A, s_idx, i0, cnt, s_rows);
+                    __syncthreads();
+#pragma unroll
+                    for (int e = 0; e < EQ; ++e) {
+                        if (!own[e]) continue;
+                        const uint32_t wq = q[e] >> 3, sh = 4 * (q[e] & 7);
+                        for (uint32_t i = 0; i < cnt; ++i) {
+                            const uint32_t x = (s_rows[i * xw + wq] >> sh) & 0xFu;
+                            const double cf = s_coef[i0 + i];
+#pragma unroll
+                            for (int c = 0; c < 4; ++c)
+                                if ((x >> c) & 1u) y[e][c] += cf;
+                        }
+                    }
+                }
 #pragma unroll
                 for (int e = 0; e < EQ; ++e) {
                     if (!own[e]) continue;
-                    double y[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-                    for (uint32_t i = 0; i < A.bH; ++i) {
-                        const uint32_t x = quad_bits(A.X, s_idx[i], xw, q[e]);
-                        const double cf = s_coef[i];
 #pragma unroll
-                        for (int c = 0; c < 4; ++c)
-                            if ((x >> c) & 1u) y[c] += cf;
-                    }
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) y[c] = static_cast<double>(static_cast<PT>(y[c] / static_cast<double>(A.bH)));
-                    store4(Yrep + slot * vs + 4 * q[e], y);
-                    store4(s_stage + 4 * q[e], y);
+                    for (int c = 0; c < 4; ++c)
+                        y[e][c] = static_cast<double>(static_cast<PT>(y[e][c] / static_cast<double>(A.bH)));
+                    store4(Yrep + slot * vs + 4 * q[e], y[e]);
+                    store4(s_stage + 4 * q[e], y[e]);
                 }
                 if (full) head = (head + 1) % M;
                 else ++m;
