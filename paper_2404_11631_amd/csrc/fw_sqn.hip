@@ -60,9 +60,9 @@ __device__ __forceinline__ void draw_rows(const SqnArgs &A, uint32_t rep, uint64
     }
 }
 
-// Rows idx[i0 .. i0 + cnt) of the bitmap (cnt <= kStageRows) into rows[r][xw] of LDS, 16-byte loads
-// spread over the workgroup. The caller synchronises before and after.
-constexpr uint32_t kStageRows = 32;
+// Rows idx[i0 .. i0 + cnt) of the bitmap into rows[r][xw] of LDS (cnt xw <= kStageWords), 16-byte
+// loads spread over the workgroup. The caller synchronises before and after.
+constexpr uint32_t kStageWords = 32 * (kSqnMaxN / 32);      // 32 KB: 32 rows at the largest n
 
 __device__ __forceinline__ void stage_rows(const SqnArgs &A, const uint32_t *idx, uint32_t i0, uint32_t cnt,
                                            uint32_t *rows)
@@ -196,7 +196,8 @@ __global__ __launch_bounds__(kRunBlock) void sqn_run_kernel(SqnArgs A)
     __shared__ double s_Ri[kSqnMaxM * kSqnMaxM];         // R^-1 (upper triangular)
     __shared__ double s_C[kSqnMaxM * kSqnMaxM];          // R^-T (D + gamma Y'Y) R^-1
     __shared__ double s_cs[kSqnMaxM], s_cy[kSqnMaxM];    // coefficients of S and Y in H g
-    __shared__ uint32_t s_rows[kStageRows * (kSqnMaxN / 32)];   // a chunk of sampled rows' bits
+    __shared__ uint32_t s_rows[kStageWords];             // a chunk of sampled rows' bits
+    const uint32_t chunk = kStageWords / A.xw;           // rows per chunk: 32 at n = 8192, 2048 at n = 50
 
     const uint32_t rep = blockIdx.x;
     const uint32_t tid = threadIdx.x, T = blockDim.x;
@@ -242,9 +243,9 @@ __global__ __launch_bounds__(kRunBlock) void sqn_run_kernel(SqnArgs A)
 #pragma unroll
             for (int c = 0; c < 4; ++c) g[e][c] = 0.0;
         }
-        // Eq. (12): the rows in order, staged through LDS kStageRows at a time
-        for (uint32_t i0 = 0; i0 < A.b; i0 += kStageRows) {
-            const uint32_t cnt = min(kStageRows, A.b - i0);
+        // Eq. (12): the rows in order, staged through LDS a chunk at a time
+        for (uint32_t i0 = 0; i0 < A.b; i0 += chunk) {
+            const uint32_t cnt = min(chunk, A.b - i0);
             __syncthreads();
             stage_rows(A, s_idx, i0, cnt, s_rows);
             __syncthreads();
@@ -366,15 +367,15 @@ __global__ __launch_bounds__(kRunBlock) void sqn_run_kernel(SqnArgs A)
                     s_coef[i] = c * (1.0 - c) * s_coef[i];
                 }
                 __syncthreads();
-                // Eq. (13) applied to s (the rows in order, staged through LDS kStageRows at a time),
+                // Eq. (13) applied to s (the rows in order, staged through LDS a chunk at a time),
                 // into the ring and staged
                 double y[EQ][4];
 #pragma unroll
                 for (int e = 0; e < EQ; ++e)
 #pragma unroll
                     for (int c = 0; c < 4; ++c) y[e][c] = 0.0;
-                for (uint32_t i0 = 0; i0 < A.bH; i0 += kStageRows) {
-                    const uint32_t cnt = min(kStageRows, A.bH - i0);
+                for (uint32_t i0 = 0; i0 < A.bH; i0 += chunk) {
+                    const uint32_t cnt = min(chunk, A.bH - i0);
                     __syncthreads();
                     stage_rows(A, s_idx, i0, cnt, s_rows);
                     __syncthreads();
