@@ -48,8 +48,7 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     # stand-alone issue-rate probe behind the ALU roofline figures
     probe = os.path.join(HERE, "valu_rate_probe")
-    subprocess.check_call([hipcc(), "--offload-arch=" + ARCH, "-O3", "-o", probe + ".tmp",
-                           os.path.join(HERE, "csrc", "valu_rate_probe.hip")])
+    subprocess.check_call([hipcc()] + flags() + ["-o", probe + ".tmp", os.path.join(HERE, "csrc", "valu_rate_probe.hip")])
     os.replace(probe + ".tmp", probe)
     return LIB
 

@@ -17,6 +17,9 @@ constexpr int kSqnChunk = 8;                // values per workgroup reduction
 constexpr int kSqnLossBlock = 256;          // threads of the loss kernel
 constexpr uint32_t kSqnLossRows = 512;      // rows per workgroup of the loss kernels
 constexpr uint32_t kSqnManySnap = 64;       // stored iterates from which the loss runs a lane per iterate
+constexpr uint32_t kSqnHessianPitch = 65;   // LDS pitch (doubles) of the product kernel's k-major blocks
+constexpr uint32_t kSqnComputeUnits = 256;  // compute units of the MI355X
+constexpr uint32_t kSqnLdsPerCu = 160 * 1024;   // LDS bytes per compute unit
 
 struct SqnArgs {
     uint32_t n, ld, nq;                     // features; row stride (a multiple of 4); quads ld / 4

@@ -1,6 +1,7 @@
-// valu_rate_probe.hip -- issue rate of single VALU instructions on gfx950: 8 independent chains
-// per lane, 8 waves per SIMD, timed with HIP events. Supports the ALU roofline of the path kernels
-// (the per-normal instruction mix weighted by these rates gives the kernel's issue ceiling).
+// valu_rate_probe.hip -- issue rate of single VALU instructions on gfx950 (and of the FP64 matrix
+// instruction): 8 independent chains per lane, 8 waves per SIMD, timed with HIP events. Supports the
+// ALU roofline of the path kernels (the per-normal instruction mix weighted by these rates gives the
+// kernel's issue ceiling) and the matrix-core ceiling of the SQN product kernel.
 #include <hip/hip_runtime.h>
 #include <cstdio>
 #include <cstdint>
@@ -39,6 +40,12 @@ __global__ void k_sqrt(uint32_t* o, uint32_t s){ float a[CH]; for(int c=0;c<CH;+
 __global__ void k_fma64(uint32_t* o, uint32_t s){ double a[CH]; double x=1.0+s*1e-9; for(int c=0;c<CH;++c)a[c]=threadIdx.x+c;
   BODY(asm volatile("v_fma_f64 %0, %0, %1, %1" : "+v"(a[c]) : "v"(x)));
   uint32_t r=0; for(int c=0;c<CH;++c) r^=(uint32_t)__double_as_longlong(a[c]); o[blockIdx.x*blockDim.x+threadIdx.x]=r; }
+// FP64 matrix rate: 8 independent accumulators per wavefront of v_mfma_f64_16x16x4f64 (2,048 flops each)
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+__global__ void k_mfma64(uint32_t* o, uint32_t s){ f64x4 acc[CH]; for(int c=0;c<CH;++c) acc[c]=f64x4{0.0,0.0,0.0,0.0};
+  const double x=1.0+s*1e-9+threadIdx.x*1e-12, y=1.0-threadIdx.x*1e-12;
+  BODY(acc[c]=__builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[c], 0, 0, 0));
+  uint32_t r=0; for(int c=0;c<CH;++c) r^=(uint32_t)__double_as_longlong(acc[c][0]+acc[c][3]); o[blockIdx.x*blockDim.x+threadIdx.x]=r; }
 typedef void(*K)(uint32_t*,uint32_t);
 #define CHECK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { printf("%s: %s\n", #x, hipGetErrorString(e_)); return 1; } } while (0)
 int main(){
@@ -54,6 +61,14 @@ int main(){
     CHECK(hipEventSynchronize(b)); float ms; CHECK(hipEventElapsedTime(&ms, a, b));
     double ops = (double)blocks*threads*ITER*CH;
     printf("%-16s %8.3f ms  %8.3f Tlane-ops/s\n", e.n, ms, ops/(ms*1e-3)/1e12);
+  }
+  {
+    hipLaunchKernelGGL(k_mfma64, dim3(blocks), dim3(threads), 0, 0, o, 3u);
+    CHECK(hipDeviceSynchronize());
+    CHECK(hipEventRecord(a)); hipLaunchKernelGGL(k_mfma64, dim3(blocks), dim3(threads), 0, 0, o, 3u); CHECK(hipEventRecord(b));
+    CHECK(hipEventSynchronize(b)); float ms; CHECK(hipEventElapsedTime(&ms, a, b));
+    double flops = (double)blocks*(threads/64)*ITER*CH*2048.0;
+    printf("%-16s %8.3f ms  %8.3f TFLOP/s\n", "v_mfma_f64_16x16x4f64", ms, flops/(ms*1e-3)/1e12);
   }
   hipError_t err = hipGetLastError(); printf("status %s\n", hipGetErrorString(err));
   CHECK(hipFree(o));

@@ -174,12 +174,13 @@ def test_sqn_many_replications(ctx):
     assert abs(st.f_mean[0] - g["F_ckpt"][0].mean()) <= 1e-13 * g["F_ckpt"][0].mean()
 
 
-@pytest.mark.parametrize("n,M,K", [(37, 4, 120), (300, 25, 200), (1000, 7, 150), (4100, 3, 60)])
+@pytest.mark.parametrize("n,M,K", [(37, 4, 120), (300, 25, 200), (1000, 7, 150), (4100, 3, 60), (700, 32, 360)])
 def test_sqn_explicit_hessian(ctx, n, M, K):
     """Algorithm 4's matrix formed on the device (sim_sqn_hessian) from the pairs each replication
     holds, against the oracle's explicit chain of BFGS updates over the same pairs (read back from
     the device's ring, oldest first): Frobenius-relative 1e-10, gamma of the newest pair, the secant
-    equation H y_t = s_t, symmetry."""
+    equation H y_t = s_t, symmetry. M = 32 with 35 pairs computed fills the ring: the product kernel's
+    largest operand blocks (k = 64)."""
     X, z = workloads.sqn_dataset(17, n, min(30 * n, 6000))
     say(f"[sqn] explicit H n={n} M={M} K={K}")
     ctx.sqn_load(X, z)
