@@ -723,99 +723,80 @@ __global__ __launch_bounds__(256) void sqn_uv_kernel(SqnArgs A, uint32_t rep, ui
 
 // H[a][b] = gamma [a == b] + sum_k V[a][k] Ut[b][k] in 64 x 64 tiles. Workgroup (g, y) owns the 64
 // rows of row block y and the column tiles g, g + G, ... (G groups chosen so that the whole grid is
-// resident at once): V's block is staged in LDS once, and the next column tile's Ut block is loaded
-// into registers while the products of the current one run. Each wavefront computes a 32 x 32 quarter
-// as 2 x 2 tiles of v_mfma_f64_16x16x4f64 (A operand: row lane % 16, k lane / 16; B operand: k lane / 16,
+// resident at once): V's block is staged in LDS once; each wavefront then walks the tiles on its own,
+// with no barrier: it loads its B operands for the whole tile from Ut (L2-resident, 52 KB per 64
+// columns at k = 52) into registers, runs the products with A read from LDS, and stores its results
+// from the accumulators, 16 consecutive columns per row. Each wavefront computes a 32 x 32 quarter as
+// 2 x 2 tiles of v_mfma_f64_16x16x4f64 (A operand: row lane % 16, k lane / 16; B operand: k lane / 16,
 // column lane % 16; result register i: row lane / 16 + 4 i, column lane % 16, as measured on gfx950 --
-// unlike the 4 (lane / 16) + i rows of the binary32 16x16x4 form) and stores it from its registers,
-// 16 consecutive columns per row.
-__global__ __launch_bounds__(256, 3) void sqn_hessian_mfma_kernel(uint32_t n, uint32_t ldh, uint32_t Kp,
+// unlike the 4 (lane / 16) + i rows of the binary32 16x16x4 form).
+__global__ __launch_bounds__(256, 4) void sqn_hessian_mfma_kernel(uint32_t n, uint32_t ldh, uint32_t Kp,
                                                                   const double *V, const double *Ut,
                                                                   const double *gamma_p, double *H)
 {
-    // 64 rows of V (and of Ut) are contiguous (64 Kp doubles): 16-byte loads, stored k-major in LDS
-    // with a pitch of 65 doubles, so the 16 rows an operand read spans fall in consecutive banks. The
-    // two blocks take 2 Kp 65 doubles of dynamic LDS (54 KB at Kp = 52: three workgroups per compute unit).
+    // 64 rows of V are contiguous (64 Kp doubles): 16-byte loads, stored k-major in LDS with a pitch of
+    // 65 doubles, so the 16 rows an operand read spans fall in consecutive banks (Kp 65 doubles of
+    // dynamic LDS: 27 KB at Kp = 52).
     constexpr uint32_t P = kSqnHessianPitch;
     constexpr uint32_t kPass = 32 * 2 * kSqnMaxM / 256;              // 16-byte pairs per thread at Kp = 64
-    extern __shared__ double s_dyn[];
-    double *s_A = s_dyn, *s_B = s_dyn + Kp * P;
+    constexpr uint32_t kSteps = 2 * kSqnMaxM / 4;                    // k steps of 4 at Kp = 64
+    extern __shared__ double s_A[];
     const uint32_t nt = (n + 63) / 64, G = gridDim.x;
     const uint32_t ra = blockIdx.y * 64, tid = threadIdx.x;
-    const uint32_t nrow = 32 * Kp;                                   // 16-byte pairs of a 64-row block
-
-    // all loads of a block are issued before the first wait
-    auto load_block = [&](const double *src, uint32_t r0, double2 (&x)[kPass]) {
-        const uint32_t nv = min(64u, n - r0) * Kp;
-        const double2 *g = reinterpret_cast<const double2 *>(src + static_cast<size_t>(r0) * Kp);
+    {
+        // all loads of the block are issued before the first wait
+        const uint32_t nv = min(64u, n - ra) * Kp;
+        const double2 *g = reinterpret_cast<const double2 *>(V + static_cast<size_t>(ra) * Kp);
+        double2 xa[kPass];
 #pragma unroll
         for (uint32_t p = 0; p < kPass; ++p) {
             const uint32_t u = tid + 256 * p;
-            x[p] = 2 * u < nv ? g[u] : make_double2(0.0, 0.0);
+            xa[p] = 2 * u < nv ? g[u] : make_double2(0.0, 0.0);
         }
-    };
-    auto stage_block = [&](const double2 (&x)[kPass], double *dst) {
 #pragma unroll
         for (uint32_t p = 0; p < kPass; ++p) {
             const uint32_t u = tid + 256 * p;
-            if (u < nrow) {
+            if (u < 32 * Kp) {
                 const uint32_t row = (2 * u) / Kp, k = (2 * u) % Kp; // Kp is a multiple of 4: k, k + 1 share the row
-                dst[k * P + row] = x[p].x;
-                dst[(k + 1) * P + row] = x[p].y;
+                s_A[k * P + row] = xa[p].x;
+                s_A[(k + 1) * P + row] = xa[p].y;
             }
         }
-    };
-
-    double2 xb[kPass];
-    {
-        double2 xa[kPass];
-        load_block(V, ra, xa);
-        load_block(Ut, blockIdx.x * 64, xb);
-        stage_block(xa, s_A);
     }
+    __syncthreads();                                                 // s_A is only read from here on
     const double gamma = *gamma_p;
     const uint32_t lane = tid & 63, wave = tid >> 6;
-    const uint32_t ta = (wave >> 1) * 32, tb = (wave & 1) * 32;      // the wavefront's quarter of the tile
+    const uint32_t ta = (wave >> 1) * 32, tb = (wave & 1) * 32;      // the wavefront's quarter of a tile
     const uint32_t lr = lane & 15, lk = lane >> 4;
+    const uint32_t steps = Kp / 4;
     for (uint32_t cb = blockIdx.x; cb < nt; cb += G) {
-        __syncthreads();                                             // every wavefront is done with s_B
-        stage_block(xb, s_B);
-        __syncthreads();
-        if (cb + G < nt) load_block(Ut, (cb + G) * 64, xb);
-
+        const uint32_t rb = cb * 64;
+        double bv[kSteps][2];
+#pragma unroll
+        for (uint32_t st = 0; st < kSteps; ++st)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const uint32_t col = rb + tb + 16 * y + lr;
+                bv[st][y] = (st < steps && col < n) ? Ut[static_cast<size_t>(col) * Kp + 4 * st + lk] : 0.0;
+            }
         f64x4 acc[2][2];
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
             for (int y = 0; y < 2; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
-        // the operands of step kb + 4 are read from LDS while the products of step kb run
-        double av[2], bv[2];
 #pragma unroll
-        for (int x = 0; x < 2; ++x) {
-            av[x] = s_A[lk * P + ta + 16 * x + lr];
-            bv[x] = s_B[lk * P + tb + 16 * x + lr];
-        }
-        for (uint32_t kb = 0; kb < Kp; kb += 4) {
-            double an[2] = {0.0, 0.0}, bn[2] = {0.0, 0.0};
-            if (kb + 4 < Kp) {
+        for (uint32_t st = 0; st < kSteps; ++st) {
+            if (st < steps) {
+                double av[2];
 #pragma unroll
-                for (int x = 0; x < 2; ++x) {
-                    an[x] = s_A[(kb + 4 + lk) * P + ta + 16 * x + lr];
-                    bn[x] = s_B[(kb + 4 + lk) * P + tb + 16 * x + lr];
-                }
-            }
+                for (int x = 0; x < 2; ++x) av[x] = s_A[(4 * st + lk) * P + ta + 16 * x + lr];
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
+                for (int x = 0; x < 2; ++x)
 #pragma unroll
-                for (int y = 0; y < 2; ++y)
-                    acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
-#pragma unroll
-            for (int x = 0; x < 2; ++x) {
-                av[x] = an[x];
-                bv[x] = bn[x];
+                    for (int y = 0; y < 2; ++y)
+                        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[st][y], acc[x][y], 0, 0, 0);
             }
         }
-        const uint32_t rb = cb * 64;
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -847,16 +828,10 @@ int launch_sqn_hessian(const SqnArgs &A, uint32_t rep, uint32_t head, uint32_t m
     else
         hipLaunchKernelGGL(sqn_uv_kernel<double>, dim3((A.n + 3) / 4), dim3(256), 0, s, A, rep, head, m, Kp, W, gamma, V, Ut);
     // column groups: one tile per workgroup while nt^2 workgroups fit at once, fewer groups beyond
-    // that (resident workgroups: as many as the LDS of a compute unit holds, at most three)
+    // that (resident workgroups: as many as the LDS of a compute unit holds, at most four)
     const uint32_t nt = (A.n + 63) / 64;
-    const uint32_t lds = 2 * Kp * kSqnHessianPitch * sizeof(double);
-    // above 64 KB (Kp = 64 at M = 32) the launch needs the kernel's dynamic-LDS limit raised, once
-    static const hipError_t lds_limit =
-        hipFuncSetAttribute(reinterpret_cast<const void *>(sqn_hessian_mfma_kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            static_cast<int>(2 * 2 * kSqnMaxM * kSqnHessianPitch * sizeof(double)));
-    if (lds_limit != hipSuccess) return -1;
-    const uint32_t slots = kSqnComputeUnits * std::min(3u, kSqnLdsPerCu / lds);
+    const uint32_t lds = Kp * kSqnHessianPitch * sizeof(double);
+    const uint32_t slots = kSqnComputeUnits * std::min(4u, kSqnLdsPerCu / lds);
     const uint32_t groups = std::min(nt, std::max(1u, slots / nt));
     hipLaunchKernelGGL(sqn_hessian_mfma_kernel, dim3(groups, nt), dim3(256), lds, s, A.n, ldh, Kp, V, Ut, gamma, H);
     return hipGetLastError() == hipSuccess ? 0 : -1;
