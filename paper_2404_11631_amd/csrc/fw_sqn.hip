@@ -724,13 +724,13 @@ __global__ __launch_bounds__(256) void sqn_uv_kernel(SqnArgs A, uint32_t rep, ui
 // H[a][b] = gamma [a == b] + sum_k V[a][k] Ut[b][k] in 64 x 64 tiles. Workgroup (g, y) owns the 64
 // rows of row block y and the column tiles g, g + G, ... (G groups chosen so that the whole grid is
 // resident at once): V's block is staged in LDS once; each wavefront then walks the tiles on its own,
-// with no barrier: it loads its B operands for the whole tile from Ut (L2-resident, 52 KB per 64
-// columns at k = 52) into registers, runs the products with A read from LDS, and stores its results
-// from the accumulators, 16 consecutive columns per row. Each wavefront computes a 32 x 32 quarter as
+// with no barrier: it loads its B operands from Ut (L2-resident) into registers, half of k at a
+// time (so that five workgroups fit a compute unit), runs the products with A read from LDS, and
+// stores its results from the accumulators, 16 consecutive columns per row. Each wavefront computes a 32 x 32 quarter as
 // 2 x 2 tiles of v_mfma_f64_16x16x4f64 (A operand: row lane % 16, k lane / 16; B operand: k lane / 16,
 // column lane % 16; result register i: row lane / 16 + 4 i, column lane % 16, as measured on gfx950 --
 // unlike the 4 (lane / 16) + i rows of the binary32 16x16x4 form).
-__global__ __launch_bounds__(256, 4) void sqn_hessian_mfma_kernel(uint32_t n, uint32_t ldh, uint32_t Kp,
+__global__ __launch_bounds__(256, 5) void sqn_hessian_mfma_kernel(uint32_t n, uint32_t ldh, uint32_t Kp,
                                                                   const double *V, const double *Ut,
                                                                   const double *gamma_p, double *H)
 {
@@ -739,7 +739,7 @@ __global__ __launch_bounds__(256, 4) void sqn_hessian_mfma_kernel(uint32_t n, ui
     // dynamic LDS: 27 KB at Kp = 52).
     constexpr uint32_t P = kSqnHessianPitch;
     constexpr uint32_t kPass = 32 * 2 * kSqnMaxM / 256;              // 16-byte pairs per thread at Kp = 64
-    constexpr uint32_t kSteps = 2 * kSqnMaxM / 4;                    // k steps of 4 at Kp = 64
+    constexpr uint32_t kHalf = 2 * kSqnMaxM / 8;                     // half the k steps of 4 at Kp = 64
     extern __shared__ double s_A[];
     const uint32_t nt = (n + 63) / 64, G = gridDim.x;
     const uint32_t ra = blockIdx.y * 64, tid = threadIdx.x;
@@ -771,30 +771,34 @@ __global__ __launch_bounds__(256, 4) void sqn_hessian_mfma_kernel(uint32_t n, ui
     const uint32_t steps = Kp / 4;
     for (uint32_t cb = blockIdx.x; cb < nt; cb += G) {
         const uint32_t rb = cb * 64;
-        double bv[kSteps][2];
-#pragma unroll
-        for (uint32_t st = 0; st < kSteps; ++st)
-#pragma unroll
-            for (int y = 0; y < 2; ++y) {
-                const uint32_t col = rb + tb + 16 * y + lr;
-                bv[st][y] = (st < steps && col < n) ? Ut[static_cast<size_t>(col) * Kp + 4 * st + lk] : 0.0;
-            }
         f64x4 acc[2][2];
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
             for (int y = 0; y < 2; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+        // the k range in two halves of at most kHalf steps: the B operands of a half in registers
+        for (uint32_t h0 = 0; h0 < steps; h0 += kHalf) {
+            double bv[kHalf][2];
 #pragma unroll
-        for (uint32_t st = 0; st < kSteps; ++st) {
-            if (st < steps) {
-                double av[2];
+            for (uint32_t s2 = 0; s2 < kHalf; ++s2)
 #pragma unroll
-                for (int x = 0; x < 2; ++x) av[x] = s_A[(4 * st + lk) * P + ta + 16 * x + lr];
+                for (int y = 0; y < 2; ++y) {
+                    const uint32_t st = h0 + s2, col = rb + tb + 16 * y + lr;
+                    bv[s2][y] = (st < steps && col < n) ? Ut[static_cast<size_t>(col) * Kp + 4 * st + lk] : 0.0;
+                }
 #pragma unroll
-                for (int x = 0; x < 2; ++x)
+            for (uint32_t s2 = 0; s2 < kHalf; ++s2) {
+                const uint32_t st = h0 + s2;
+                if (st < steps) {
+                    double av[2];
 #pragma unroll
-                    for (int y = 0; y < 2; ++y)
-                        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[st][y], acc[x][y], 0, 0, 0);
+                    for (int x = 0; x < 2; ++x) av[x] = s_A[(4 * st + lk) * P + ta + 16 * x + lr];
+#pragma unroll
+                    for (int x = 0; x < 2; ++x)
+#pragma unroll
+                        for (int y = 0; y < 2; ++y)
+                            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[s2][y], acc[x][y], 0, 0, 0);
+                }
             }
         }
 #pragma unroll
@@ -828,10 +832,10 @@ int launch_sqn_hessian(const SqnArgs &A, uint32_t rep, uint32_t head, uint32_t m
     else
         hipLaunchKernelGGL(sqn_uv_kernel<double>, dim3((A.n + 3) / 4), dim3(256), 0, s, A, rep, head, m, Kp, W, gamma, V, Ut);
     // column groups: one tile per workgroup while nt^2 workgroups fit at once, fewer groups beyond
-    // that (resident workgroups: as many as the LDS of a compute unit holds, at most four)
+    // that (resident workgroups: as many as the LDS of a compute unit holds, at most five)
     const uint32_t nt = (A.n + 63) / 64;
     const uint32_t lds = Kp * kSqnHessianPitch * sizeof(double);
-    const uint32_t slots = kSqnComputeUnits * std::min(4u, kSqnLdsPerCu / lds);
+    const uint32_t slots = kSqnComputeUnits * std::min(5u, kSqnLdsPerCu / lds);
     const uint32_t groups = std::min(nt, std::max(1u, slots / nt));
     hipLaunchKernelGGL(sqn_hessian_mfma_kernel, dim3(groups, nt), dim3(256), lds, s, A.n, ldh, Kp, V, Ut, gamma, H);
     return hipGetLastError() == hipSuccess ? 0 : -1;
