@@ -460,12 +460,14 @@ def sqn_shape_leg(ctx, sim, runs: int, warmup: int, throughput_sizes=(5_000,), s
             if n in throughput_sizes and bH == w["bH"][0]:
                 # Algorithm 4's matrix formed from the pairs of that run (sim_sqn_hessian): the n x n
                 # product on the FP64 matrix cores, 2 n^2 Kp flops (Kp = 2m rounded up to 4) and the
-                # 8 n^2 bytes of H written
+                # 8 n^2 bytes of H written, over the call's four launches (the product kernel alone is
+                # in the kernel trace)
                 hs = [ctx.sqn_hessian(0, copy=False) for _ in range(runs + 1)][1:]
                 hms = sum(h["device_ms"] for h in hs) / len(hs)
                 m = hs[0]["m"]
                 Kp = (2 * m + 3) // 4 * 4
                 entry["hessian"] = {"m": m, "device_ms": hms,
+                                    "scope": "four launches: Gram entries, middle matrix, U and V, product",
                                     "tflops": 2.0 * n * n * Kp / (hms * 1e-3) / 1e12,
                                     "frac_fp64_mfma": 2.0 * n * n * Kp / (hms * 1e-3) / PEAK_F64,
                                     "write_GBps": 8.0 * n * n / (hms * 1e-3) / 1e9}
