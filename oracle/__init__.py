@@ -146,6 +146,8 @@ def lib():
         L.or_draw_returns.argtypes = [ctypes.POINTER(Problem), ctypes.c_uint64, ctypes.c_uint64, dp]
         L.or_sample_gradient.argtypes = [ctypes.POINTER(Problem), ctypes.c_uint64, ctypes.c_uint64,
                                          dp, dp, dp, dp]
+        L.or_sample_gradient_bound.argtypes = [ctypes.POINTER(Problem), ctypes.c_uint64, ctypes.c_uint64,
+                                               dp, ctypes.c_double, dp, dp]
         L.or_objective.argtypes = [ctypes.POINTER(Problem), dp]
         L.or_objective.restype = ctypes.c_double
         L.or_path.argtypes = [ctypes.POINTER(Problem), ctypes.c_uint64, ctypes.c_uint64,
@@ -263,6 +265,15 @@ class OracleProblem:
         lib().or_sample_gradient(ctypes.byref(self.p), rep, epoch, _dptr(w), _dptr(g), _dptr(rbar),
                                  _dptr(sw))
         return g, rbar, sw
+
+    def gradient_bound(self, rep, epoch, w, uroff):
+        """(gradient, bound): the sample gradient at w and the rounding bound the replay rule of
+        `path` applies there for a system with unit roundoff `uroff`."""
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        g = np.zeros(self.d)
+        b = ctypes.c_double()
+        lib().or_sample_gradient_bound(ctypes.byref(self.p), rep, epoch, _dptr(w), uroff, _dptr(g), ctypes.byref(b))
+        return g, b.value
 
     def draw_returns(self, rep, epoch):
         R = np.zeros((self.N, self.d))

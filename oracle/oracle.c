@@ -194,6 +194,72 @@ static int cv_reference_decision(const or_problem *p, const double *z, double *z
     return pick;
 }
 
+/* Rounding bound of a system that evaluates the sample gradient of Eq. (4)-(5) at w with unit
+ * roundoff uroff (0: no bound), every sum taken in absolute values. It follows the gradient through
+ * the noise coordinates y of R_i = mu + L y_i, which covers both evaluation orders a system may use:
+ * return space (Sigma_hat w from the centred R_i) and noise space (L applied to sums of y, with
+ * v = L'w); for a diagonal L the two coincide. The factor 8 (N + d + 8) is the accumulation depth
+ * of the longest sum times a safety factor. vabs, habs: d doubles of work space; pabs: N. */
+static double gradient_rounding_bound(const or_problem *p, const double *noise, const double *w, const double *g,
+                                      double uroff, double *vabs, double *pabs, double *habs)
+{
+    const int d = p->d, N = p->N;
+    if (!(uroff > 0.0)) return 0.0;
+    const double kappa = 8.0 * (double)(N + d + 8);
+    double amax = 0.0;
+    double wabs = 0.0;
+    for (int j = 0; j < d; ++j) wabs += fabs(w[j]);
+    for (int m = 0; m < d; ++m) {            /* |L|' |w| */
+        double acc = 0.0;
+        for (int l = m; l < d; ++l) acc += fabs(p->chol[l * d + m]) * fabs(w[l]);
+        vabs[m] = acc;
+    }
+    for (int i = 0; i < N; ++i) {            /* |y_i|' |L|' |w| */
+        double acc = 0.0;
+        for (int m = 0; m < d; ++m) acc += fabs(noise[(size_t)i * d + m]) * vabs[m];
+        pabs[i] = acc;
+    }
+    for (int k = 0; k < d; ++k) {
+        double quad = 0.0, lin = 0.0;
+        for (int i = 0; i < N; ++i) {
+            quad += fabs(noise[(size_t)i * d + k]) * pabs[i];
+            lin += fabs(noise[(size_t)i * d + k]);
+        }
+        habs[k] = 2.0 * p->lambda * quad / (double)(N - 1) + lin / (double)N;
+    }
+    for (int j = 0; j < d; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k <= j; ++k) acc += fabs(p->chol[j * d + k]) * habs[k];
+        double aj = acc + fabs(p->mu[j]) + fabs(g[j]);
+        if (aj > amax) amax = aj;
+    }
+    return kappa * uroff * amax * (1.0 + wabs);
+}
+
+void or_sample_gradient_bound(const or_problem *p, uint64_t rep, uint64_t epoch, const double *w, double uroff,
+                              double *grad, double *bound)
+{
+    const int d = p->d, N = p->N;
+    double *Rmat = (double *)malloc(sizeof(double) * (size_t)N * d);
+    double *noise = (double *)malloc(sizeof(double) * (size_t)N * d);
+    double *rbar = (double *)malloc(sizeof(double) * (size_t)d);
+    double *sw = (double *)malloc(sizeof(double) * (size_t)d);
+    double *vabs = (double *)malloc(sizeof(double) * (size_t)d);
+    double *habs = (double *)malloc(sizeof(double) * (size_t)d);
+    double *pabs = (double *)malloc(sizeof(double) * (size_t)N);
+    draw_returns(p, rep, epoch, Rmat, noise, NULL);
+    sample_statistics(p, Rmat, w, rbar, sw);
+    for (int j = 0; j < d; ++j) grad[j] = 2.0 * p->lambda * sw[j] - rbar[j];
+    *bound = gradient_rounding_bound(p, noise, w, grad, uroff, vabs, pabs, habs);
+    free(pabs);
+    free(habs);
+    free(vabs);
+    free(sw);
+    free(rbar);
+    free(noise);
+    free(Rmat);
+}
+
 /* ---------------------------------------------------------------------------------------------
  * Algorithm 1, one replication.
  * ------------------------------------------------------------------------------------------- */
@@ -228,7 +294,6 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
     out->min_margin = INFINITY;
     for (int j = 0; j < d; ++j) w[j] = p->w0 ? p->w0[j] : 0.0;   /* initialize w_0 */
 
-    const double kappa = 8.0 * (double)(N + d + 8);   /* accumulation depth times a safety factor */
     int ck = 0;
     for (uint64_t t = 0; t < T; ++t) {
         const uint64_t epoch = t / (uint64_t)M;        /* k = t div M, m = t mod M */
@@ -262,42 +327,7 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
         double margin = second - best;
         if (margin < out->min_margin) out->min_margin = margin;
 
-        /* rounding bound of a system that evaluates this gradient with unit roundoff uroff,
-         * with every sum taken in absolute values. It follows the gradient through the noise
-         * coordinates y of R_i = mu + L y_i, which covers both evaluation orders a system may use:
-         * return space (Sigma_hat w from the centred R_i) and noise space (L applied to sums of y,
-         * with v = L'w); for a diagonal L the two coincide. */
-        double bound = 0.0;
-        if (uroff > 0.0) {
-            double amax = 0.0;
-            double wabs = 0.0;
-            for (int j = 0; j < d; ++j) wabs += fabs(w[j]);
-            for (int m = 0; m < d; ++m) {            /* |L|' |w| */
-                double acc = 0.0;
-                for (int l = m; l < d; ++l) acc += fabs(p->chol[l * d + m]) * fabs(w[l]);
-                vabs[m] = acc;
-            }
-            for (int i = 0; i < N; ++i) {            /* |y_i|' |L|' |w| */
-                double acc = 0.0;
-                for (int m = 0; m < d; ++m) acc += fabs(noise[(size_t)i * d + m]) * vabs[m];
-                pabs[i] = acc;
-            }
-            for (int k = 0; k < d; ++k) {
-                double quad = 0.0, lin = 0.0;
-                for (int i = 0; i < N; ++i) {
-                    quad += fabs(noise[(size_t)i * d + k]) * pabs[i];
-                    lin += fabs(noise[(size_t)i * d + k]);
-                }
-                habs[k] = 2.0 * p->lambda * quad / (double)(N - 1) + lin / (double)N;
-            }
-            for (int j = 0; j < d; ++j) {
-                double acc = 0.0;
-                for (int k = 0; k <= j; ++k) acc += fabs(p->chol[j * d + k]) * habs[k];
-                double aj = acc + fabs(p->mu[j]) + fabs(g[j]);
-                if (aj > amax) amax = aj;
-            }
-            bound = kappa * uroff * amax * (1.0 + wabs);
-        }
+        const double bound = gradient_rounding_bound(p, noise, w, g, uroff, vabs, pabs, habs);
         int ambiguous = (margin <= 2.0 * bound);
         if (ambiguous) out->n_ambiguous++;
         if (replay && replay[t] != (uint8_t)a) {

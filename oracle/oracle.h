@@ -113,6 +113,12 @@ void or_draw_returns(const or_problem *p, uint64_t rep, uint64_t epoch, double *
 void or_sample_gradient(const or_problem *p, uint64_t rep, uint64_t epoch, const double *w,
                         double *grad, double *rbar, double *sigma_w);
 
+/* The same gradient and the rounding bound or_path applies at that point for a system with unit
+ * roundoff uroff (2^-24 binary32, 2^-53 binary64): a bound on the error of any evaluation order
+ * of Eq. (4)-(5), in return or noise coordinates. */
+void or_sample_gradient_bound(const or_problem *p, uint64_t rep, uint64_t epoch, const double *w, double uroff,
+                              double *grad, double *bound);
+
 /* True objective Eq. (3) with the risk coefficient lambda: lambda |L'w|^2 - mu'w. */
 double or_objective(const or_problem *p, const double *w);
 

@@ -1,14 +1,17 @@
 """Builds the HIP library libsim.so for gfx950, in place next to this file.
 
-    python -m paper_2404_11631_amd.build
+    python -m paper_2404_11631_amd.build            the library
+    python -m paper_2404_11631_amd.build --probe    also the stand-alone VALU issue-rate probe
 
-Every HIP source is compiled with packed-FP32 instruction selection disabled.
+Every HIP source is compiled with packed-FP32 instruction selection disabled. Translation units
+compile in parallel (one hipcc process per source, at most 8 at once).
 """
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -32,26 +35,43 @@ def flags():
             "-I", os.path.join(ROOT, "include")]
 
 
+def _jobs() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(8, n))
+
+
 def build(verbose: bool = False) -> str:
-    objs = []
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    for src in SOURCES:
+
+    def compile_one(src: str) -> str:
         obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [hipcc()] + flags() + lang + ["-c", os.path.join(HERE, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     subprocess.check_call([hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)
-    # stand-alone issue-rate probe behind the ALU roofline figures
+    return LIB
+
+
+def build_probe() -> str:
+    """The stand-alone issue-rate probe behind the ALU roofline figures (not part of the library)."""
     probe = os.path.join(HERE, "valu_rate_probe")
     subprocess.check_call([hipcc()] + flags() + ["-o", probe + ".tmp", os.path.join(HERE, "csrc", "valu_rate_probe.hip")])
     os.replace(probe + ".tmp", probe)
-    return LIB
+    return probe
 
 
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    if "--probe" in sys.argv:
+        print(build_probe())
