@@ -187,11 +187,11 @@ typedef struct {
  * dispatcher is the work queue), replications of heavy instances split across several lanes, then
  * one per-instance reduction in fixed order.
  * Each instance uses its instance_id as stream domain and the common noise `seed`.
- * Supported: FP32 state, diagonal Sigma, d <= 32, T <= 2^32-2, per-instance R < 2^32,
- * 1 <= n_inst <= 65536. Decision logs follow each instance's log_rep_begin/log_rep_count.
- * Asynchronous on the context's stream. cfg may be NULL.
- * This build returns SIM_EUNSUPPORTED: the device path is switched off (see sim_plan_batch for the
- * plan it would run). */
+ * Supported: FP32 state, diagonal Sigma, d <= 32, T <= 131071 (the signature is held in 33 bits),
+ * per-instance R < 2^32, 1 <= n_inst <= 65536. Decision logs follow each instance's
+ * log_rep_begin/log_rep_count. Asynchronous on the context's stream. cfg may be NULL. The plan is
+ * checked on the host (tile ranges, lanes and replications per tile, slots, normal numbering)
+ * before anything is uploaded. */
 int sim_run_batch(sim_ctx *ctx, uint32_t n_inst, const sim_params *p, const uint64_t *R,
                   const uint64_t *T, uint64_t seed, const sim_batch_config *cfg);
 

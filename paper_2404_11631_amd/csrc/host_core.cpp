@@ -77,6 +77,10 @@ int validate(char *err, const sim_params *p, uint64_t R, uint64_t T)
     }
     if (p->n_samples < 2) return fail(err, SIM_EINVAL, "n_samples must be >= 2 (Eq. (4) divides by N-1)");
     if (p->n_samples > (1u << 24)) return fail(err, SIM_EINVAL, "n_samples above 2^24");
+    // a replication's normals of one epoch are numbered in 32 bits: N d Gaussian numerators, then
+    // N nu chi-square normals for t noise
+    if ((uint64_t)p->n_samples * (p->d + (p->noise == SIM_NOISE_T ? p->nu : 0u)) > 0xFFFFFFF0ull)
+        return fail(err, SIM_EINVAL, "N (d + nu) normals per epoch above 2^32 - 16");
     if (p->resample_every < 1) return fail(err, SIM_EINVAL, "resample_every must be >= 1");
     if (p->noise != SIM_NOISE_GAUSS && p->noise != SIM_NOISE_T) return fail(err, SIM_EINVAL, "unknown noise");
     if (p->noise == SIM_NOISE_T && (p->nu < 3 || p->nu > 1024))
@@ -581,6 +585,60 @@ double lane_cost(const sim_params &p, uint64_t T, uint32_t P)
     return (double)T * (20.0 * normals + 15.0 * p.d + 6.0 * p.d * stages);
 }
 
+// Every bound the tile kernels read from the plan, checked on the finished tables before any
+// upload: the tile range of each class launch, the lanes per replication and replications per
+// wavefront, the replication range of each tile, the slot permutation and its per-instance
+// ranges, the signature width (33 bits) and the numbering of each lane's normals.
+static int check_plan(char *err, uint32_t n_inst, const sim_params *p, const uint64_t *R, const uint64_t *T,
+                      const BatchPlan &P)
+{
+    const uint64_t n = P.n_tiles;
+    if (P.tiles.size() != n || P.class_begin[0] != 0 || P.class_begin[8] != n)
+        return fail(err, SIM_EINVAL, "plan: class ranges do not cover the tiles");
+    for (int c = 0; c < 8; ++c)
+        if (P.class_begin[c] > P.class_begin[c + 1]) return fail(err, SIM_EINVAL, "plan: class ranges decrease");
+    if (P.slot_begin.size() != (size_t)n_inst + 1 || P.slot_begin[0] != 0 || P.slot_begin[n_inst] != n)
+        return fail(err, SIM_EINVAL, "plan: slot ranges do not cover the tiles");
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        if (P.slot_begin[i] > P.slot_begin[i + 1]) return fail(err, SIM_EINVAL, "plan: slot ranges decrease");
+        if (T[i] > kMaxBatchT)
+            return fail(err, SIM_EUNSUPPORTED, "instance %u: T=%llu above %llu in a batch (33-bit signature)", i,
+                        (unsigned long long)T[i], (unsigned long long)kMaxBatchT);
+        if (P.desc[i].R != R[i] || P.desc[i].T != T[i] || P.desc[i].d != p[i].d || P.desc[i].N != p[i].n_samples)
+            return fail(err, SIM_EINVAL, "plan: descriptor %u disagrees with the parameters", i);
+    }
+    std::vector<uint8_t> seen(n, 0);
+    std::vector<uint64_t> reps(n_inst, 0);
+    int c = 0;
+    for (uint64_t q = 0; q < n; ++q) {
+        while (q >= P.class_begin[c + 1]) ++c;
+        const Tile &tl = P.tiles[q];
+        if (tl.inst >= n_inst) return fail(err, SIM_EINVAL, "plan: tile %llu names instance %u", (unsigned long long)q, tl.inst);
+        const sim_params &pi = p[tl.inst];
+        const uint32_t L = tl.P;
+        if (L < 1 || L > 64 || (L & (L - 1))) return fail(err, SIM_EINVAL, "plan: tile %llu has %u lanes per replication", (unsigned long long)q, L);
+        if (tl.nrep < 1 || tl.nrep * L > 64) return fail(err, SIM_EINVAL, "plan: tile %llu holds %u replications", (unsigned long long)q, tl.nrep);
+        if ((uint64_t)tl.rep0 + tl.nrep > R[tl.inst]) return fail(err, SIM_EINVAL, "plan: tile %llu exceeds R", (unsigned long long)q);
+        if (tl.slot >= n || seen[tl.slot] || tl.slot < P.slot_begin[tl.inst] || tl.slot >= P.slot_begin[tl.inst + 1])
+            return fail(err, SIM_EINVAL, "plan: tile %llu has slot %u", (unsigned long long)q, tl.slot);
+        seen[tl.slot] = 1;
+        const bool tn = pi.noise == SIM_NOISE_T;
+        const uint32_t width = 4u << tl.bucket;
+        if (tl.bucket > 3 || pi.d > width || (int)(2u * tl.bucket + (tn ? 1u : 0u)) != c)
+            return fail(err, SIM_EINVAL, "plan: tile %llu in the wrong class", (unsigned long long)q);
+        const uint64_t chunk = chunk_of(pi.n_samples, pi.d, L, tn);
+        if (chunk * L < pi.n_samples) return fail(err, SIM_EINVAL, "plan: tile %llu leaves samples out", (unsigned long long)q);
+        // highest normal a lane reads: its chunk's numerators (and chi-square normals), plus a block
+        const uint64_t top = (uint64_t)pi.n_samples * pi.d + (tn ? (chunk * L) * pi.nu : 0) + chunk * L * pi.d + 4;
+        if (top > 0xFFFFFFFFull) return fail(err, SIM_EINVAL, "plan: tile %llu numbers normals past 2^32", (unsigned long long)q);
+        reps[tl.inst] += tl.nrep;
+    }
+    for (uint32_t i = 0; i < n_inst; ++i)
+        if (reps[i] != R[i]) return fail(err, SIM_EINVAL, "plan: instance %u covers %llu of %llu replications", i,
+                                         (unsigned long long)reps[i], (unsigned long long)R[i]);
+    return SIM_OK;
+}
+
 static int plan_batch_impl(char *err, uint32_t n_inst, const sim_params *p, const uint64_t *R, const uint64_t *T,
                            uint64_t seed, const sim_batch_config *cfg, uint32_t n_cu, BatchPlan &out)
 {
@@ -593,6 +651,9 @@ static int plan_batch_impl(char *err, uint32_t n_inst, const sim_params *p, cons
         if (p[i].state_precision != SIM_FP32)
             return fail(err, SIM_EUNSUPPORTED, "instance %u: batched runs use FP32 state", i);
         if (p[i].d > 32) return fail(err, SIM_EUNSUPPORTED, "instance %u: d > 32 in a batch", i);
+        if (T[i] > kMaxBatchT)
+            return fail(err, SIM_EUNSUPPORTED, "instance %u: T above %llu in a batch (33-bit signature)", i,
+                        (unsigned long long)kMaxBatchT);
         if (p[i].chol) return fail(err, SIM_EUNSUPPORTED, "instance %u: batched runs take diagonal Sigma", i);
         if (p[i].flags & SIM_CV_FEATURES)
             return fail(err, SIM_EUNSUPPORTED, "instance %u: batched runs do not write features", i);
@@ -707,7 +768,7 @@ static int plan_batch_impl(char *err, uint32_t n_inst, const sim_params *p, cons
         out.class_begin[cls(order[q]) + 1]++;
     }
     for (uint32_t c = 0; c < 8; ++c) out.class_begin[c + 1] += out.class_begin[c];
-    return SIM_OK;
+    return check_plan(err, n_inst, p, R, T, out);
 }
 
 int plan_batch(char *err, uint32_t n_inst, const sim_params *p, const uint64_t *R, const uint64_t *T,

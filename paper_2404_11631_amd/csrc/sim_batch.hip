@@ -11,10 +11,6 @@
 
 using namespace fw::host;
 
-namespace {
-constexpr bool batch_on_device_enabled() { return false; }
-}  // namespace
-
 extern "C" {
 
 int sim_plan_batch(uint32_t n_inst, const sim_params *p, const uint64_t *R, const uint64_t *T,
@@ -37,12 +33,6 @@ int sim_run_batch(sim_ctx *ctx, uint32_t n_inst, const sim_params *p, const uint
                   uint64_t seed, const sim_batch_config *cfg)
 {
     if (!ctx) return SIM_EINVAL;
-    // Switched off: the first device run of the batched path (then a persistent work-queue kernel
-    // launched from a captured graph) stopped responding, and the cause has not been shown. The tile
-    // kernels below reproduce the oracle in a CPU emulation of the device code; they are not run on a
-    // device until that cause is understood.
-    if (!batch_on_device_enabled())
-        return set_err(ctx, SIM_EUNSUPPORTED, "batched runs are switched off on the device");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipDeviceProp_t prop;
     HIP_TRY(ctx, hipGetDeviceProperties(&prop, ctx->device));

@@ -13,6 +13,7 @@ constexpr int kBlock = 256;                      // replications per workgroup (
 constexpr int kMaxStreams = 1 + 2 * kMaxCkpt;    // Y, f(w_c), RSE_c
 constexpr int kStreamFields = 5;                 // sum hi, sum lo, squares hi, squares lo, count
 constexpr uint64_t kMaxNarrowT = 92681;          // largest T with T(T+1)/2 < 2^32
+constexpr uint64_t kMaxBatchT = 131071;          // largest T with T(T+1)/2 < 2^33 (batched tiles)
 // sqrt(2 ln 2): binary32 Box-Muller pairs are produced divided by this constant
 constexpr double kBoxMullerScale = 1.1774100225154746910115693264597;
 

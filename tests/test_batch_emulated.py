@@ -125,3 +125,27 @@ def test_plan_without_device():
     assert P2 == [8, 2]
     with pytest.raises(sim.SimError):
         sim.plan_batch([light], [10], [10], lanes_per_rep=[3])
+
+
+def test_plan_checks_full_uneven_workload():
+    """The uneven workload at full size (256 instances x 4,096 replications) passes the host-side
+    checks of every bound the tile kernels read; T above the 33-bit signature and a normal count
+    past 2^32 are refused before any launch."""
+    w = workloads.WORKLOADS["uneven"]
+    batch = workloads.uneven_batch(w["seed"], w["n_instances"], w["R"], w["d_range"], w["n_range"], w["t_range"])
+    probs = [sim.Problem(mu=b.mu, sigma=b.sigma, N=b.N, instance_id=b.instance) for b in batch]
+    P, nt = sim.plan_batch(probs, [b.R for b in batch], [b.T for b in batch], n_cu=256)
+    for b, p, n in zip(batch, P, nt):
+        assert p in (1, 2, 4, 8, 16, 32, 64)
+        assert n == -(-b.R // (64 // p))
+    for forced in (1, 64):
+        sim.plan_batch(probs, [b.R for b in batch], [b.T for b in batch], lanes_per_rep=[forced] * len(batch))
+    one = sim.Problem(mu=np.full(4, 0.5), sigma=np.full(4, 0.5), N=4)
+    sim.plan_batch([one], [64], [131_071])
+    with pytest.raises(sim.SimError) as e:
+        sim.plan_batch([one], [64], [131_072])
+    assert e.value.code == -5
+    big = sim.Problem(mu=np.full(32, 0.5), sigma=np.full(32, 0.5), N=1 << 24, noise=sim.NOISE_T, nu=1000)
+    with pytest.raises(sim.SimError) as e:
+        sim.plan_batch([big], [64], [10])
+    assert e.value.code == -1

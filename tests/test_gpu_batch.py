@@ -1,11 +1,5 @@
-"""Batched runs of uneven instances vs the CPU oracle.
-
-Skipped: the batched device path is switched off (sim_run_batch returns
-SIM_EUNSUPPORTED). Its first device run, an earlier persistent-kernel design launched from a captured
-graph, stopped responding and the cause has not been shown; the tile kernels that replaced it pass
-the same parity checks in a CPU emulation of the device code (tests/test_batch_emulated.py) but are
-not run on a device until that cause is understood.
-"""
+"""Batched runs of uneven instances vs the CPU oracle (Algorithm 1, Section 3.1, over instances
+of uneven horizon and size)."""
 import math
 import sys
 
@@ -16,9 +10,7 @@ import oracle
 from paper_2404_11631_amd import sim, workloads
 from tests import parity
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="batched device path switched off: an earlier design stopped "
-                                      "responding on the device and the cause is not shown")]
+pytestmark = pytest.mark.gpu
 
 
 def say(*a):
