@@ -202,6 +202,32 @@ int sim_plan_batch(uint32_t n_inst, const sim_params *p, const uint64_t *R, cons
                    const sim_batch_config *cfg, uint32_t n_cu, uint32_t *lanes_per_rep, uint32_t *n_tiles,
                    char *msg, size_t len);
 
+/* ---- no device allocation ------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. sim_run_noalloc runs sim_run's fused path (diagonal
+ * Sigma, FP32 state, no per-path records, logs or features) with every intermediate (instance
+ * descriptor, per-workgroup partial sums, finishing counter) in a library-owned static device
+ * array of SIM_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; its device address is
+ * taken once per device on the first call there. Nothing is allocated, no memset is issued: the
+ * call enqueues kernel launches only, asynchronously on hip_stream (NULL: the null stream) of
+ * `device`. R <= SIM_NOALLOC_MAX_R (larger R: SIM_EINVAL).
+ * Outputs (device memory, caller-owned, written by the launch):
+ *   f_ckpt  [n_checkpoints][R] f(w_c) per path (may be NULL when n_checkpoints == 0);
+ *   stats_f [(1 + 2 n_checkpoints) * 5 + 2] FP64 reduction fields (per stream Y, f(w_c), RSE_c:
+ *           sum hi, sum lo, squares hi, squares lo, count; then min Y, max Y);
+ *   stats_i [d + 3] decision totals (origin first), hitting count, hitting-step sum.
+ * sim_stats_from_raw turns host copies of stats_f and stats_i into sim_stats_out (kernel_ms 0).
+ * Every call on one GPU shares that GPU's array, which keeps the last call's contents: calls that
+ * overlap on one GPU (two streams, two threads) race and must be serialised by the caller.
+ * Errors are returned as codes; sim_noalloc_last_error gives the calling thread's last message. */
+#define SIM_NOALLOC_MAX_R 1048576u
+#define SIM_NOALLOC_SCRATCH_BYTES 4194304u
+int sim_run_noalloc(int device, void *hip_stream, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed,
+                    double *f_ckpt, double *stats_f, uint64_t *stats_i);
+int sim_noalloc_last_error(char *buf, size_t len);
+int sim_stats_from_raw(const sim_params *p, uint64_t R, uint64_t T, const double *stats_f,
+                       const uint64_t *stats_i, sim_stats_out *out);
+
 /* Statistics of instance `instance` of the last batched run (kernel_ms and path_steps_per_s
  * describe the whole batch); synchronises the stream. */
 int sim_batch_stats(sim_ctx *ctx, uint32_t instance, sim_stats_out *out);

@@ -199,7 +199,8 @@ EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_run_b
            "sim_mlp_set_params", "sim_mlp_get_params", "sim_mlp_forward", "sim_mlp_grad", "sim_cv_aux_draws",
            "sim_cv_law", "sim_run_wide", "sim_validate_wide", "sim_wide_stats", "sim_wide_paths",
            "sim_run_newsvendor", "sim_validate_newsvendor", "sim_nv_stats", "sim_nv_paths",
-           "sim_sqn_load", "sim_run_sqn", "sim_validate_sqn", "sim_sqn_stats", "sim_sqn_paths", "sim_sqn_hessian")
+           "sim_sqn_load", "sim_run_sqn", "sim_validate_sqn", "sim_sqn_stats", "sim_sqn_paths", "sim_sqn_hessian",
+           "sim_run_noalloc", "sim_noalloc_last_error", "sim_stats_from_raw")
 
 _lib = None
 
@@ -264,6 +265,10 @@ def load():
         L.sim_sqn_stats.argtypes = [vp, ctypes.POINTER(SimStats)]
         L.sim_sqn_paths.argtypes = [vp, ctypes.POINTER(SimSqnView)]
         L.sim_sqn_hessian.argtypes = [vp, u64, ctypes.POINTER(SimSqnHessianView)]
+        L.sim_run_noalloc.argtypes = [ctypes.c_int, vp, ctypes.POINTER(SimParams), u64, u64, u64, vp, vp, vp]
+        L.sim_noalloc_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+        L.sim_stats_from_raw.argtypes = [ctypes.POINTER(SimParams), u64, u64, _dp,
+                                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(SimStats)]
         _lib = L
     return _lib
 
@@ -295,6 +300,37 @@ class Problem:
     cv_ref: np.ndarray | None = None   # the features' reference gradient b
     instance_id: int = 0
     n_schedule: tuple | None = None    # sim_run_wide: sample size N_k of every epoch
+
+
+def noalloc_stats_fields(n_checkpoints: int) -> int:
+    """FP64 fields sim_run_noalloc writes to stats_f."""
+    return (1 + 2 * n_checkpoints) * 5 + 2
+
+
+def run_noalloc(device: int, stream, p: Problem, R: int, T: int, seed: int, f_ckpt: int, stats_f: int,
+                stats_i: int):
+    """sim_run_noalloc: device pointers in, nothing allocated by the library; asynchronous."""
+    sp, keep = Sim.params(p)
+    rc = load().sim_run_noalloc(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(sp), R, T, seed,
+                                ctypes.c_void_p(f_ckpt) if f_ckpt else None, ctypes.c_void_p(stats_f),
+                                ctypes.c_void_p(stats_i))
+    if rc:
+        buf = ctypes.create_string_buffer(512)
+        load().sim_noalloc_last_error(buf, 512)
+        raise SimError(rc, buf.value.decode())
+
+
+def stats_from_raw(p: Problem, R: int, T: int, stats_f, stats_i) -> "SimStats":
+    """sim_stats_from_raw on host copies of sim_run_noalloc's stats_f (float64) and stats_i (uint64)."""
+    sp, keep = Sim.params(p)
+    f = np.ascontiguousarray(stats_f, dtype=np.float64)
+    i = np.ascontiguousarray(stats_i, dtype=np.uint64)
+    st = SimStats()
+    rc = load().sim_stats_from_raw(ctypes.byref(sp), R, T, f.ctypes.data_as(_dp),
+                                   i.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), ctypes.byref(st))
+    if rc:
+        raise SimError(rc, "sim_stats_from_raw rejected the arguments")
+    return st
 
 
 def validate(p: Problem, R: int, T: int):

@@ -1,0 +1,105 @@
+"""sim_run_noalloc (no device allocation, intermediates in the library's static scratch array) vs
+sim_run on the same inputs: identical statistics and per-path checkpoint values, on two calls in a
+row, the second with a smaller input; sizes beyond the scratch limit are refused."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2404_11631_amd import sim, workloads
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("R", "T", "mean", "var", "ci95_halfwidth", "min", "max", "n_checkpoints", "tau_count", "tau_mean")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _same(a, b, d, nc):
+    for f in FIELDS:
+        assert getattr(a, f) == getattr(b, f), f
+    for c in range(nc):
+        for f in ("checkpoints", "f_mean", "f_sd", "rse_mean", "rse_sd", "rse_undefined"):
+            assert getattr(a, f)[c] == getattr(b, f)[c], (f, c)
+    assert list(a.decision_total)[: d + 1] == list(b.decision_total)[: d + 1]
+    assert a.f_star == b.f_star or (np.isnan(a.f_star) and np.isnan(b.f_star))
+
+
+class _Hip:
+    """Device buffers for the test through the HIP runtime the library itself links (not torch:
+    a torch imported after the library would share its runtime by soname)."""
+
+    def __init__(self):
+        import ctypes
+        self.ct = ctypes
+        sim.load()
+        self.L = ctypes.CDLL("libamdhip64.so.7")
+        vp = ctypes.c_void_p
+        self.L.hipMalloc.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t]
+        self.L.hipFree.argtypes = [vp]
+        self.L.hipMemcpy.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int]
+        self.L.hipMemset.argtypes = [vp, ctypes.c_int, ctypes.c_size_t]
+        self.bufs = []
+
+    def alloc(self, nbytes, fill=0xFF):
+        p = self.ct.c_void_p()
+        assert self.L.hipMalloc(self.ct.byref(p), nbytes) == 0
+        assert self.L.hipMemset(p, fill, nbytes) == 0
+        self.bufs.append(p)
+        return p.value
+
+    def get(self, ptr, dtype, n):
+        a = np.empty(n, dtype=dtype)
+        assert self.L.hipDeviceSynchronize() == 0
+        assert self.L.hipMemcpy(a.ctypes.data, ptr, a.nbytes, 2) == 0    # device to host
+        return a
+
+    def close(self):
+        for p in self.bufs:
+            self.L.hipFree(p)
+
+
+def test_noalloc_matches_sim_run():
+    ctx = sim.Sim(0)
+    hip = _Hip()
+    cases = [  # (d, N, R, T, checkpoints, seed): the second is smaller, and so is its output
+        (10, 10, 200_000, 300, (50, 100, 300), 11),
+        (3, 7, 1_000, 120, (7,), 12),
+    ]
+    try:
+        for k, (d, N, R, T, ck, seed) in enumerate(cases):
+            mu, sigma = workloads.diag_instance(seed, 0, d)
+            p = sim.Problem(mu=mu, sigma=sigma, N=N, checkpoints=ck, gap_eps=0.05)
+            say(f"[noalloc] call {k}: d={d} N={N} R={R} T={T} checkpoints={ck}")
+            ctx.run(p, R, T, seed)
+            ref = ctx.stats()
+            ref_f = ctx.paths()["f_ckpt"].copy()
+            nf = sim.noalloc_stats_fields(len(ck))
+            fck = hip.alloc(8 * len(ck) * R)
+            sf = hip.alloc(8 * nf)
+            si = hip.alloc(8 * (d + 3))
+            sim.run_noalloc(0, None, p, R, T, seed, fck, sf, si)
+            F = hip.get(sf, np.float64, nf)
+            I = hip.get(si, np.uint64, d + 3)
+            st = sim.stats_from_raw(p, R, T, F, I)
+            _same(st, ref, d, len(ck))
+            assert np.array_equal(hip.get(fck, np.float64, len(ck) * R).reshape(len(ck), R), ref_f)
+            say(f"[noalloc] call {k}: identical to sim_run (mean {st.mean:.12f})")
+    finally:
+        hip.close()
+        ctx.close()
+
+
+def test_noalloc_refuses_sizes_beyond_scratch():
+    mu, sigma = workloads.diag_instance(0, 0, 4)
+    p = sim.Problem(mu=mu, sigma=sigma, N=4)
+    with pytest.raises(sim.SimError) as e:
+        sim.run_noalloc(0, None, p, 1_048_577, 10, 0, 0, 1, 1)
+    assert e.value.code == -1 and "no-allocation limit" in str(e.value)
+    q = sim.Problem(mu=mu, sigma=sigma, N=4, keep_paths=True)
+    with pytest.raises(sim.SimError) as e:
+        sim.run_noalloc(0, None, q, 100, 10, 0, 0, 1, 1)
+    assert e.value.code == -5
