@@ -172,10 +172,17 @@ int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t 
  * would return, and writes the reason into msg (may be NULL). */
 int sim_validate(const sim_params *p, uint64_t R, uint64_t T, char *msg, size_t len);
 
+/* sim_batch_config.flags bit: the tile launch and the reduction are captured once into a HIP graph
+ * (kernel nodes only, captured on a library stream) and launched as one graph on the context's
+ * stream; the executable graph is kept and replayed while later calls have the same plan and
+ * buffers (new seeds and parameters travel in the uploaded descriptors). */
+#define SIM_BATCH_GRAPH 0x100u
+
 /* Knobs of a batched run (sim_run_batch); zero fields take the built-in cost model's choice. */
 typedef struct {
     uint32_t reserved;              /* must be 0 */
-    uint32_t flags;                 /* SIM_KEEP_PATHS for per-path records of every instance */
+    uint32_t flags;                 /* SIM_KEEP_PATHS for per-path records of every instance;
+                                       SIM_BATCH_GRAPH to launch through a captured HIP graph */
     double heavy_factor;            /* theta > 0: replications are split across lanes until one
                                        tile needs at most theta x the balanced run time (0: 0.5) */
     const uint8_t *lanes_per_rep;   /* [n_inst] lanes per replication, each 0 (model) or a power of
@@ -227,6 +234,27 @@ int sim_run_noalloc(int device, void *hip_stream, const sim_params *p, uint64_t 
 int sim_noalloc_last_error(char *buf, size_t len);
 int sim_stats_from_raw(const sim_params *p, uint64_t R, uint64_t T, const double *stats_f,
                        const uint64_t *stats_i, sim_stats_out *out);
+
+/* Measured choice of the batched plan's knob theta (sim_batch_config.heavy_factor: how far heavy
+ * instances are split over lanes). Every candidate of SIM_TUNE_THETAS is timed (device time between
+ * HIP events, best of two runs) on the same instances with each horizon divided by t_scale (>= 1;
+ * per-tile work then shrinks by the same factor for every instance, which keeps the plan's balance),
+ * without checkpoints, logs or per-path records; the fastest is returned. Results are cached as one
+ * JSON object per line in cache_path (may be NULL: no cache), keyed by a hash of the device name,
+ * the ABI version, the candidate list and every instance's (d, N, T, R, noise, nu); a call whose
+ * key is in the cache reads it and launches nothing. The tuning runs replace the context's last
+ * batched run. Synchronous. */
+#define SIM_TUNE_MAX_CAND 16u
+typedef struct {
+    double heavy_factor;                 /* the fastest theta */
+    uint32_t from_cache;                 /* 1: read from cache_path, nothing was run */
+    uint32_t n_candidates;
+    double cand_theta[SIM_TUNE_MAX_CAND];
+    double cand_ms[SIM_TUNE_MAX_CAND];   /* device ms of each candidate at the reduced horizons */
+    uint64_t key;                        /* the cache key */
+} sim_tune_out;
+int sim_tune_batch(sim_ctx *ctx, uint32_t n_inst, const sim_params *p, const uint64_t *R, const uint64_t *T,
+                   uint64_t seed, uint32_t t_scale, const char *cache_path, sim_tune_out *out);
 
 /* Statistics of instance `instance` of the last batched run (kernel_ms and path_steps_per_s
  * describe the whole batch); synchronises the stream. */

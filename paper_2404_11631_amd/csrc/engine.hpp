@@ -13,7 +13,7 @@
 namespace fw {
 int launch_fw_paths(const InstanceDesc &host_desc, const InstanceDesc *dev_desc, const RunBuffers &B,
                     bool fp64, hipStream_t stream, int *kernel_width);
-int launch_fw_batch(const BatchBuffers &B, const uint32_t *class_begin, hipStream_t stream);
+int launch_fw_batch(const BatchBuffers &B, hipStream_t stream);
 int launch_fw_dense(const InstanceDesc &host_desc, const InstanceDesc *dev_desc, const RunBuffers &B,
                     hipStream_t stream);
 constexpr int kDenseLanesPerRep = 4;                       // dense-L kernels: four lanes per replication
@@ -44,6 +44,11 @@ struct BatchState {
     uint32_t *slots_host = nullptr;           // pinned staging
     size_t slots_host_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // SIM_BATCH_GRAPH: the captured launches, kept while the kernel arguments are unchanged
+    hipStream_t capture = nullptr;
+    hipGraphExec_t exec = nullptr;
+    fw::BatchBuffers exec_args{};
+    uint64_t graph_launches = 0, graph_captures = 0;
 };
 
 // Control-variate surrogate, its training data and the estimator's buffers.

@@ -1,17 +1,22 @@
 // fw_batch.hip -- instances of uneven size and horizon, as wavefront tiles.
 //
-// Algorithm 1 (Section 3.1) exactly as in fw_paths.hip, reorganised for a batch of instances:
-//   * one wavefront per tile; the tiles of each (d bucket, noise) class are launched longest
-//     first, so the hardware dispatcher acts as the work queue;
-//   * a tile holds 64/P replications of one instance, P lanes per replication; each lane takes
-//     a contiguous chunk of the N samples (chunks are multiples of 4/gcd(d,4) samples, so every
-//     lane starts on a Philox block boundary and all lanes walk the stream in step), and the P
-//     partial sums s1, s2 are combined with an xor butterfly, after which every lane of the group
-//     holds the same bits and takes the same decision;
-//   * the integer signature S_j and the decision counts live in LDS, one slot per lane
-//     ([j][lane], conflict-free); the top bit of S_j (T up to 1e5 needs 33 bits) sits in a
-//     per-lane bit mask;
-//   * one kernel per class, specialised for d <= 4, 8, 16 and 32 (register arrays of that width);
+// Algorithm 1 (Section 3.1) as in fw_paths.hip, reorganised for a batch of instances with d up to
+// 32 in one kernel:
+//   * one wavefront per tile; every tile of the batch is in one launch, longest first, so the
+//     hardware dispatcher hands the heaviest tiles out first and fills in with the lighter ones;
+//   * a tile holds 64/P replications of one instance with P = Pa x Ps lanes per replication:
+//     Pa lanes split the assets (a lane holds at most 8 of them: their iterate, sample sums,
+//     signature and decision counts stay in registers), Ps lanes split the N samples into
+//     contiguous chunks;
+//   * the Pa lanes of a sample chunk draw its normals together: per round of G = 4/gcd(d,4)
+//     samples (a whole number of Philox blocks) each lane draws every Pa-th block into LDS, and
+//     each lane then reads its own assets' normals back; the sample's dot product with the
+//     iterate is summed over the Pa lanes with an xor butterfly;
+//   * after the samples the Ps partial sums are combined by an xor butterfly over the lanes that
+//     hold the same assets; the gradient's dot product, the minimum of the linear subproblem
+//     (lowest index among equal values), the gap and the objective at checkpoints are reduced over
+//     the Pa lanes the same way. Butterflies give every lane of a replication the same bits, so all
+//     of them take the same decision;
 //   * each tile writes its partial sums to a slot fixed by (instance, replication block), and a
 //     second kernel reduces every instance's slots in order, so the statistics do not depend on
 //     the order in which tiles ran.
@@ -25,168 +30,220 @@ namespace fw {
 
 constexpr int kWave = 64;
 constexpr int kBatchMaxD = 32;
+constexpr int kLaneAssets = 8;                 // assets held by one lane
+// LDS staging of one wavefront: a sub-group of Pa lanes draws G d <= 4 d <= 32 Pa normals per
+// round, and a wavefront has 64 / Pa sub-groups
+constexpr int kStageFloats = 32 * kWave;
 
-template <int D>
-struct TileLds {
-    uint32_t s_lo[D][kWave];        // signature S_j mod 2^32
-    uint32_t cnt[D + 1][kWave];     // decision counts, origin first
-};
-
-__device__ __forceinline__ double signature(uint32_t lo, uint32_t hibits, int j)
+__device__ __forceinline__ float bfly_sum(float x, uint32_t lo, uint32_t hi)
 {
-    return static_cast<double>(lo) + ((hibits >> j) & 1u ? 4294967296.0 : 0.0);
+    for (uint32_t m = lo; m < hi; m <<= 1) x += __shfl_xor(x, m, kWave);
+    return x;
 }
 
-// f(w) at w = c S, FP64 (Eq. (3), diagonal Sigma)
-template <int D>
-__device__ __forceinline__ double batch_objective(const InstanceDesc *__restrict__ P, const TileLds<D> &L,
-                                                  int lane, uint32_t hibits, int d, double c)
+__device__ __forceinline__ double bfly_sum(double x, uint32_t lo, uint32_t hi)
+{
+    for (uint32_t m = lo; m < hi; m <<= 1) x += __shfl_xor(x, m, kWave);
+    return x;
+}
+
+// f(w) at w = c S over this lane's assets, FP64 (Eq. (3), diagonal Sigma), summed over the Pa lanes
+__device__ __forceinline__ double tile_objective(const InstanceDesc *__restrict__ P, const uint32_t (&S)[kLaneAssets],
+                                                 uint32_t hibits, uint32_t a0, uint32_t acnt, uint32_t Pa, double c)
 {
     double quad = 0.0, lin = 0.0;
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-        if (j < d) {
-            const double w = signature(L.s_lo[j][lane], hibits, j) * c;
-            const double sw = P->sig_d[j] * w;
+    for (int k = 0; k < kLaneAssets; ++k) {
+        if (static_cast<uint32_t>(k) < acnt) {
+            const double sj = static_cast<double>(S[k]) + ((hibits >> k) & 1u ? 4294967296.0 : 0.0);
+            const double w = sj * c;
+            const double sw = P->sig_d[a0 + k] * w;
             quad += sw * sw;
-            lin += P->mu_d[j] * w;
+            lin += P->mu_d[a0 + k] * w;
         }
     }
+    quad = bfly_sum(quad, 1u, Pa);
+    lin = bfly_sum(lin, 1u, Pa);
     return P->lambda * quad - lin;
 }
 
-template <int D, int NOISE>
-__device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile, TileLds<D> &L)
+__device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile, float *stage)
 {
     const InstanceDesc *P = B.inst + tile.inst;
-    const int lane = threadIdx.x;
-    const uint32_t Pl = tile.P;
-    const uint32_t g = lane / Pl, p = lane % Pl;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t Pl = tile.P, Pa = tile.Pa;
+    const uint32_t g = lane / Pl;                  // replication within the tile
+    const uint32_t ps = (lane % Pl) / Pa;          // sample chunk
+    const uint32_t pa = lane % Pa;                 // asset slice
     const bool active = g < tile.nrep;
-    const bool leader = active && p == 0;
+    const bool owner = active && ps == 0;          // writes this lane's assets of the path record
+    const bool leader = owner && pa == 0;
     const uint32_t r = tile.rep0 + g;
-    const int d = static_cast<int>(P->d);
+    const uint32_t d = P->d;
+    const uint32_t a0 = pa * kLaneAssets;
+    const uint32_t acnt = a0 < d ? (d - a0 < kLaneAssets ? d - a0 : kLaneAssets) : 0u;
     const uint32_t N = P->N, M = P->M;
     const uint64_t T = P->T;
     const uint32_t k0 = static_cast<uint32_t>(P->seed), k1 = static_cast<uint32_t>(P->seed >> 32);
     const uint32_t dom = P->instance & 0xFFFFFFu;
     const uint32_t n_ckpt = P->n_ckpt;
+    const bool tnoise = P->noise != 0;
+    const uint32_t nu = P->nu;
     const bool logged = leader && (P->flags & 2u) && (static_cast<uint64_t>(r) - P->log_begin) < P->log_count;
 
-    // contiguous sample chunk of this lane, aligned to whole Philox blocks
-    const uint32_t align = NOISE ? 4u : ((d & 3) == 0 ? 1u : ((d & 1) == 0 ? 2u : 4u));
-    uint32_t chunk = (N + Pl - 1) / Pl;
+    // rounds of G samples hold a whole number of Philox blocks; lane chunks are whole rounds
+    const uint32_t G = (d & 3u) == 0 ? 1u : ((d & 1u) == 0 ? 2u : 4u);
+    const uint32_t align = tnoise ? 4u : G;
+    const uint32_t Ps = Pl / Pa;
+    uint32_t chunk = (N + Ps - 1) / Ps;
     chunk = (chunk + align - 1) / align * align;
-    const uint32_t i0 = p * chunk;
+    const uint32_t i0 = ps * chunk;
+    const uint32_t rounds = chunk / G;
+    const uint32_t nb = G * d / 4;                 // blocks per round
+    const uint32_t mb = (nb + Pa - 1) / Pa;        // blocks per lane per round (uniform)
+    float *sub = stage + (lane / Pa) * (32u * Pa); // this sub-group's staging area
 
+    uint32_t S[kLaneAssets], cnt[kLaneAssets];
 #pragma unroll
-    for (int j = 0; j < D; ++j) L.s_lo[j][lane] = 0u;
-#pragma unroll
-    for (int j = 0; j <= D; ++j) L.cnt[j][lane] = 0u;
-    uint32_t hibits = 0u;
+    for (int k = 0; k < kLaneAssets; ++k) S[k] = cnt[k] = 0u;
+    uint32_t cnt0 = 0u, hibits = 0u;
     uint32_t tau = kTauNone;
     uint32_t ck = 0;
     uint64_t next_ckpt = n_ckpt ? P->ckpt[0] : 0;
     uint32_t epoch = 0, m_in_epoch = 0;
 
     for (uint64_t t = 0; t < T; ++t) {
-        // reload the per-instance coefficients from the scalar cache every iteration instead of
-        // keeping 5 x D of them live across the sample loop
-        asm volatile("" ::: "memory");
         const float cw = t == 0 ? 0.0f
                                 : static_cast<float>(2.0 / (static_cast<double>(t) * static_cast<double>(t + 1)));
-        float v[D], s1[D], s2[D];
+        float w[kLaneAssets], v[kLaneAssets], s1[kLaneAssets], s2[kLaneAssets];
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            float w = 0.0f;
-            if (j < d) {
-                w = (t == 0) ? (P->has_w0 ? P->w0_f[j] : 0.0f)
-                             : (static_cast<float>(L.s_lo[j][lane]) + ((hibits >> j) & 1u ? 4294967296.0f : 0.0f)) * cw;
+        for (int k = 0; k < kLaneAssets; ++k) {
+            const bool in = static_cast<uint32_t>(k) < acnt;
+            float wk = 0.0f;
+            if (in) {
+                wk = (t == 0) ? (P->has_w0 ? P->w0_f[a0 + k] : 0.0f)
+                              : (static_cast<float>(S[k]) + ((hibits >> k) & 1u ? 4294967296.0f : 0.0f)) * cw;
             }
-            v[j] = (j < d) ? P->sz_f[j] * w : 0.0f;
-            s1[j] = 0.0f;
-            s2[j] = 0.0f;
+            w[k] = wk;
+            v[k] = in ? P->sz_f[a0 + k] * wk : 0.0f;
+            s1[k] = 0.0f;
+            s2[k] = 0.0f;
         }
 
-        NormalCursor<float> cur;
-        cur.seek(i0 * static_cast<uint32_t>(d), epoch, r, dom, k0, k1);
-        NormalCursor<float> ext;
-        if constexpr (NOISE == 1) ext.seek(N * static_cast<uint32_t>(d) + P->nu * i0, epoch, r, dom, k0, k1);
-#pragma unroll 1
-        for (uint32_t k = 0; k < chunk; ++k) {
-            const bool valid = i0 + k < N;
-            float z[D];
-#pragma unroll
-            for (int j = 0; j < D; ++j) z[j] = (j < d) ? cur.next(epoch, r, dom, k0, k1) : 0.0f;
-            if constexpr (NOISE == 1) {
-                float ss = 0.0f;
-#pragma unroll 1
-                for (uint32_t q = 0; q < P->nu; ++q) {
-                    const float e = ext.next(epoch, r, dom, k0, k1);
-                    ss = fmaf(e, e, ss);
+        const PhiloxRow row = philox_row(epoch, r, k0);
+        for (uint32_t rd = 0; rd < rounds; ++rd) {
+            const uint32_t ib = i0 + rd * G;                 // first sample of the round
+            const uint32_t blk0 = ib * d / 4;                // its first Philox block
+            // draw: blocks pa, pa + Pa, ... of the round, two at a time
+            for (uint32_t m = 0; m < mb; m += 2) {
+                const uint32_t b0 = pa + m * Pa, b1 = b0 + Pa;
+                const Block4<float> q0 = normals_block_row(row, blk0 + b0, dom, k0, k1);
+                const Block4<float> q1 = normals_block_row(row, blk0 + b1, dom, k0, k1);
+                if (b0 < nb) {
+                    sub[4 * b0 + 0] = q0.z[0];
+                    sub[4 * b0 + 1] = q0.z[1];
+                    sub[4 * b0 + 2] = q0.z[2];
+                    sub[4 * b0 + 3] = q0.z[3];
                 }
-                const float a = P->tscale_f * __builtin_amdgcn_rsqf(ss);
-#pragma unroll
-                for (int j = 0; j < D; ++j) z[j] *= a;
+                if (m + 1 < mb && b1 < nb) {
+                    sub[4 * b1 + 0] = q1.z[0];
+                    sub[4 * b1 + 1] = q1.z[1];
+                    sub[4 * b1 + 2] = q1.z[2];
+                    sub[4 * b1 + 3] = q1.z[3];
+                }
             }
-            if (valid) {
+            __syncthreads();
+            for (uint32_t sidx = 0; sidx < G; ++sidx) {
+                const uint32_t i = ib + sidx;
+                const bool valid = i < N;
+                float z[kLaneAssets];
+                const float *src = sub + sidx * d + a0;
+#pragma unroll
+                for (int k = 0; k < kLaneAssets; ++k) z[k] = static_cast<uint32_t>(k) < acnt ? src[k] : 0.0f;
+                if (tnoise) {
+                    NormalCursor<float> ext;
+                    ext.seek(N * d + nu * i, epoch, r, dom, k0, k1);
+                    float ss = 0.0f;
+#pragma unroll 1
+                    for (uint32_t q = 0; q < nu; ++q) {
+                        const float e = ext.next(epoch, r, dom, k0, k1);
+                        ss = fmaf(e, e, ss);
+                    }
+                    const float a = P->tscale_f * __builtin_amdgcn_rsqf(ss);
+#pragma unroll
+                    for (int k = 0; k < kLaneAssets; ++k) z[k] *= a;
+                }
                 float dot = 0.0f;
 #pragma unroll
-                for (int j = 0; j < D; ++j) dot = fmaf(z[j], v[j], dot);
+                for (int k = 0; k < kLaneAssets; ++k) dot = fmaf(z[k], v[k], dot);
+                dot = bfly_sum(dot, 1u, Pa);
+                if (valid) {
 #pragma unroll
-                for (int j = 0; j < D; ++j) {
-                    s1[j] += z[j];
-                    s2[j] = fmaf(z[j], dot, s2[j]);
+                    for (int k = 0; k < kLaneAssets; ++k) {
+                        s1[k] += z[k];
+                        s2[k] = fmaf(z[k], dot, s2[k]);
+                    }
                 }
             }
+            __syncthreads();
         }
-        // combine the P partial sums (xor butterfly: every lane of the group ends with equal bits)
-        for (uint32_t m = 1; m < Pl; m <<= 1) {
+        // combine the Ps sample chunks (lanes holding the same assets)
+        for (uint32_t m = Pa; m < Pl; m <<= 1) {
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                if (j < d) {
-                    s1[j] += __shfl_xor(s1[j], m, kWave);
-                    s2[j] += __shfl_xor(s2[j], m, kWave);
-                }
+            for (int k = 0; k < kLaneAssets; ++k) {
+                s1[k] += __shfl_xor(s1[k], m, kWave);
+                s2[k] += __shfl_xor(s2[k], m, kWave);
             }
         }
 
+        // gradient, linear subproblem over the vertices of W, Frank-Wolfe gap
         float dot1 = 0.0f;
 #pragma unroll
-        for (int j = 0; j < D; ++j) dot1 = fmaf(s1[j], v[j], dot1);
+        for (int k = 0; k < kLaneAssets; ++k) dot1 = fmaf(s1[k], v[k], dot1);
+        dot1 = bfly_sum(dot1, 1u, Pa);
         const float qn = dot1 * P->inv_n_f;
-        float gmin = 0.0f, gw = 0.0f;
-        int jmin = -1;
+        float gmin = INFINITY, gw = 0.0f;
+        uint32_t jmin = 0xFFFFFFFFu;
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if (j < d) {
-                const float gj = P->c2_f[j] * (s2[j] - s1[j] * qn) - P->mu_f[j] - P->c1_f[j] * s1[j];
-                if (jmin < 0 || gj < gmin) {
+        for (int k = 0; k < kLaneAssets; ++k) {
+            if (static_cast<uint32_t>(k) < acnt) {
+                const uint32_t j = a0 + k;
+                const float gj = P->c2_f[j] * (s2[k] - s1[k] * qn) - P->mu_f[j] - P->c1_f[j] * s1[k];
+                if (jmin == 0xFFFFFFFFu || gj < gmin) {
                     gmin = gj;
                     jmin = j;
                 }
-                const float w = (t == 0) ? (P->has_w0 ? P->w0_f[j] : 0.0f)
-                                         : (static_cast<float>(L.s_lo[j][lane]) + ((hibits >> j) & 1u ? 4294967296.0f : 0.0f)) * cw;
-                gw = fmaf(gj, w, gw);
+                gw = fmaf(gj, w[k], gw);
             }
         }
-        const int a = (gmin < 0.0f) ? jmin + 1 : 0;
+        for (uint32_t m = 1; m < Pa; m <<= 1) {
+            const float og = __shfl_xor(gmin, m, kWave);
+            const uint32_t oj = __shfl_xor(jmin, m, kWave);
+            if (og < gmin || (og == gmin && oj < jmin)) {
+                gmin = og;
+                jmin = oj;
+            }
+        }
+        gw = bfly_sum(gw, 1u, Pa);
+        const uint32_t a = (gmin < 0.0f) ? jmin + 1 : 0u;
         const float gap = gw - (gmin < 0.0f ? gmin : 0.0f);
         if (tau == kTauNone && gap <= static_cast<float>(P->gap_eps)) tau = static_cast<uint32_t>(t);
         if (logged) B.dlog[P->dlog_base + t * P->log_count + (r - P->log_begin)] = static_cast<uint8_t>(a);
 
-        if (active) {
-            L.cnt[a][lane] += 1u;
-            if (a > 0) {
-                const uint32_t old = L.s_lo[a - 1][lane];
-                const uint32_t now = old + static_cast<uint32_t>(t + 1);
-                L.s_lo[a - 1][lane] = now;
-                if (now < old) hibits |= 1u << (a - 1);
+        // step 2/(t+2): the signature absorbs the update
+        cnt0 += (a == 0u) ? 1u : 0u;
+#pragma unroll
+        for (int k = 0; k < kLaneAssets; ++k) {
+            if (a == a0 + k + 1) {
+                const uint32_t now = S[k] + static_cast<uint32_t>(t + 1);
+                if (now < S[k]) hibits |= 1u << k;
+                S[k] = now;
+                cnt[k] += 1u;
             }
         }
         if (t + 1 == next_ckpt) {
             const double c = 2.0 / (static_cast<double>(t + 1) * static_cast<double>(t + 2));
-            const double f = batch_objective<D>(P, L, lane, hibits, d, c);
+            const double f = tile_objective(P, S, hibits, a0, acnt, Pa, c);
             if (leader) B.fck[static_cast<uint64_t>(ck) * B.total_R + P->path_base + r] = f;
             ++ck;
             next_ckpt = ck < n_ckpt ? P->ckpt[ck] : 0;
@@ -196,16 +253,24 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
             ++epoch;
         }
     }
-    const double y = batch_objective<D>(P, L, lane, hibits, d, 2.0 / (static_cast<double>(T) * static_cast<double>(T + 1)));
+    const double y = tile_objective(P, S, hibits, a0, acnt, Pa, 2.0 / (static_cast<double>(T) * static_cast<double>(T + 1)));
 
-    if (leader && B.y) {
+    if (owner && B.y) {
         const uint64_t R = P->R;
-        B.y[P->path_base + r] = y;
-        B.tau[P->path_base + r] = tau;
-        for (int j = 0; j <= d; ++j) B.cnt[P->cnt_base + static_cast<uint64_t>(j) * R + r] = L.cnt[j][lane];
-        for (int j = 0; j < d; ++j)
-            B.wsum[P->wsum_base + static_cast<uint64_t>(j) * R + r] =
-                static_cast<uint64_t>(L.s_lo[j][lane]) | (static_cast<uint64_t>((hibits >> j) & 1u) << 32);
+        if (pa == 0) {
+            B.y[P->path_base + r] = y;
+            B.tau[P->path_base + r] = tau;
+            B.cnt[P->cnt_base + r] = cnt0;
+        }
+#pragma unroll
+        for (int k = 0; k < kLaneAssets; ++k) {
+            if (static_cast<uint32_t>(k) < acnt) {
+                const uint64_t j = a0 + k;
+                B.cnt[P->cnt_base + (j + 1) * R + r] = cnt[k];
+                B.wsum[P->wsum_base + j * R + r] =
+                    static_cast<uint64_t>(S[k]) | (static_cast<uint64_t>((hibits >> k) & 1u) << 32);
+            }
+        }
     }
 
     // tile partials (leaders only)
@@ -250,9 +315,17 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
         out.ymin = mn;
         out.ymax = mx;
     }
-    for (int j = 0; j <= kBatchMaxD; ++j) {
-        const uint64_t tot = wave_sum_u64((leader && j <= d && j <= D) ? L.cnt[j <= D ? j : 0][lane] : 0u);
-        if (lane == 0) out.dec[j] = tot;
+    {
+        const uint64_t tot = wave_sum_u64(leader ? cnt0 : 0u);
+        if (lane == 0) out.dec[0] = tot;
+    }
+    for (uint32_t j = 0; j < static_cast<uint32_t>(kBatchMaxD); ++j) {
+        uint32_t c = 0u;
+#pragma unroll
+        for (int k = 0; k < kLaneAssets; ++k)
+            if (a0 + k == j) c = cnt[k];
+        const uint64_t tot = wave_sum_u64((owner && j < d) ? c : 0u);
+        if (lane == 0) out.dec[j + 1] = tot;
     }
     const bool hit = leader && tau != kTauNone;
     const uint64_t tc = wave_sum_u64(hit ? 1u : 0u);
@@ -263,14 +336,12 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
     }
 }
 
-// One wavefront per tile: the tiles of one (d bucket, noise) class, longest first, so the hardware
-// dispatcher hands the heaviest tiles out first and fills in with the lighter ones.
-template <int D, int NOISE>
-__global__ __launch_bounds__(kWave) void fw_tile_kernel(BatchBuffers B, uint32_t first_tile)
+// One wavefront per tile, every tile of the batch, longest first.
+__global__ __launch_bounds__(kWave) void fw_tile_kernel(BatchBuffers B)
 {
-    __shared__ TileLds<D> L;
-    const Tile tile = B.tiles[first_tile + blockIdx.x];
-    run_tile<D, NOISE>(B, tile, L);
+    __shared__ float stage[kStageFloats];
+    const Tile tile = B.tiles[blockIdx.x];
+    run_tile(B, tile, stage);
 }
 
 // One workgroup per instance: its tile slots in order.
@@ -325,18 +396,10 @@ __global__ __launch_bounds__(kBlock) void fw_batch_reduce(BatchBuffers B)
     }
 }
 
-// tile kernels of every class present, then the per-instance reduction, in stream order;
-// class_begin[c] .. class_begin[c+1] are the tiles of class c = 2 bucket + noise
-int launch_fw_batch(const BatchBuffers &B, const uint32_t *class_begin, hipStream_t stream)
+// the tile kernel over every tile, then the per-instance reduction, in stream order
+int launch_fw_batch(const BatchBuffers &B, hipStream_t stream)
 {
-    using K = void (*)(BatchBuffers, uint32_t);
-    static const K kernels[8] = {fw_tile_kernel<4, 0>, fw_tile_kernel<4, 1>, fw_tile_kernel<8, 0>,
-                                 fw_tile_kernel<8, 1>, fw_tile_kernel<16, 0>, fw_tile_kernel<16, 1>,
-                                 fw_tile_kernel<32, 0>, fw_tile_kernel<32, 1>};
-    for (int c = 7; c >= 0; --c) {
-        const uint32_t n = class_begin[c + 1] - class_begin[c];
-        if (n) hipLaunchKernelGGL(kernels[c], dim3(n), dim3(kWave), 0, stream, B, class_begin[c]);
-    }
+    if (B.n_tiles) hipLaunchKernelGGL(fw_tile_kernel, dim3(B.n_tiles), dim3(kWave), 0, stream, B);
     hipLaunchKernelGGL(fw_batch_reduce, dim3(B.n_inst), dim3(kBlock), 0, stream, B);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }

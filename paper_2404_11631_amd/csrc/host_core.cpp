@@ -561,28 +561,44 @@ void fill_stats(sim_stats_out *out, const double *F, uint32_t nc, const uint64_t
 
 namespace {
 
-uint32_t bucket_of(uint32_t d) { return d <= 4 ? 0u : d <= 8 ? 1u : d <= 16 ? 2u : 3u; }
-
 uint32_t reps_per_tile(uint32_t P) { return 64u / P; }
+
+uint32_t log2u(uint32_t x)
+{
+    uint32_t k = 0;
+    while ((1u << k) < x) ++k;
+    return k;
+}
 
 }  // namespace
 
-uint32_t chunk_of(uint32_t N, uint32_t d, uint32_t P, bool t_noise)
+uint32_t asset_lanes(uint32_t d)
+{
+    uint32_t Pa = 1;
+    while (Pa * 8u < d) Pa *= 2;
+    return Pa;
+}
+
+uint32_t chunk_of(uint32_t N, uint32_t d, uint32_t Ps, bool t_noise)
 {
     const uint32_t align = t_noise ? 4u : ((d & 3u) == 0 ? 1u : ((d & 1u) == 0 ? 2u : 4u));
-    uint32_t c = (N + P - 1) / P;
+    uint32_t c = (N + Ps - 1) / Ps;
     return (c + align - 1) / align * align;
 }
 
-// Work of one lane of one tile, in VALU instructions: ~20 per normal, ~15 per asset per
-// iteration (gradient, vertex search, update), 6 per asset per butterfly stage.
+// Work of one lane of one tile per run, in VALU instructions: ~80 per Philox block drawn (four
+// normals), ~40 per sample read back (eight products and sums, butterfly steps), ~20 chi-square
+// normals' worth per t sample, ~150 per iteration for the gradient, subproblem and update, and
+// 32 per stage of the butterfly over the sample lanes.
 double lane_cost(const sim_params &p, uint64_t T, uint32_t P)
 {
     const bool t_noise = p.noise == SIM_NOISE_T;
-    const double chunk = chunk_of(p.n_samples, p.d, P, t_noise);
-    const double normals = chunk * (p.d + (t_noise ? p.nu : 0));
-    const double stages = std::log2((double)P);
-    return (double)T * (20.0 * normals + 15.0 * p.d + 6.0 * p.d * stages);
+    const uint32_t d = p.d, Pa = asset_lanes(d), Ps = P / Pa;
+    const uint32_t G = (d & 3u) == 0 ? 1u : ((d & 1u) == 0 ? 2u : 4u);
+    const double rounds = (double)chunk_of(p.n_samples, d, Ps, t_noise) / G;
+    const double blocks = std::ceil((double)(G * d / 4) / Pa);
+    const double per_round = 80.0 * blocks + G * (40.0 + 4.0 * log2u(Pa) + (t_noise ? 20.0 * p.nu : 0.0));
+    return (double)T * (rounds * per_round + 150.0 + 32.0 * log2u(Ps));
 }
 
 // Every bound the tile kernels read from the plan, checked on the finished tables before any
@@ -593,10 +609,7 @@ static int check_plan(char *err, uint32_t n_inst, const sim_params *p, const uin
                       const BatchPlan &P)
 {
     const uint64_t n = P.n_tiles;
-    if (P.tiles.size() != n || P.class_begin[0] != 0 || P.class_begin[8] != n)
-        return fail(err, SIM_EINVAL, "plan: class ranges do not cover the tiles");
-    for (int c = 0; c < 8; ++c)
-        if (P.class_begin[c] > P.class_begin[c + 1]) return fail(err, SIM_EINVAL, "plan: class ranges decrease");
+    if (P.tiles.size() != n) return fail(err, SIM_EINVAL, "plan: tile table size");
     if (P.slot_begin.size() != (size_t)n_inst + 1 || P.slot_begin[0] != 0 || P.slot_begin[n_inst] != n)
         return fail(err, SIM_EINVAL, "plan: slot ranges do not cover the tiles");
     for (uint32_t i = 0; i < n_inst; ++i) {
@@ -609,27 +622,28 @@ static int check_plan(char *err, uint32_t n_inst, const sim_params *p, const uin
     }
     std::vector<uint8_t> seen(n, 0);
     std::vector<uint64_t> reps(n_inst, 0);
-    int c = 0;
     for (uint64_t q = 0; q < n; ++q) {
-        while (q >= P.class_begin[c + 1]) ++c;
         const Tile &tl = P.tiles[q];
         if (tl.inst >= n_inst) return fail(err, SIM_EINVAL, "plan: tile %llu names instance %u", (unsigned long long)q, tl.inst);
         const sim_params &pi = p[tl.inst];
         const uint32_t L = tl.P;
         if (L < 1 || L > 64 || (L & (L - 1))) return fail(err, SIM_EINVAL, "plan: tile %llu has %u lanes per replication", (unsigned long long)q, L);
+        if (tl.Pa != asset_lanes(pi.d) || L % tl.Pa)
+            return fail(err, SIM_EINVAL, "plan: tile %llu splits %u assets over %u lanes", (unsigned long long)q, pi.d, tl.Pa);
         if (tl.nrep < 1 || tl.nrep * L > 64) return fail(err, SIM_EINVAL, "plan: tile %llu holds %u replications", (unsigned long long)q, tl.nrep);
         if ((uint64_t)tl.rep0 + tl.nrep > R[tl.inst]) return fail(err, SIM_EINVAL, "plan: tile %llu exceeds R", (unsigned long long)q);
         if (tl.slot >= n || seen[tl.slot] || tl.slot < P.slot_begin[tl.inst] || tl.slot >= P.slot_begin[tl.inst + 1])
             return fail(err, SIM_EINVAL, "plan: tile %llu has slot %u", (unsigned long long)q, tl.slot);
         seen[tl.slot] = 1;
         const bool tn = pi.noise == SIM_NOISE_T;
-        const uint32_t width = 4u << tl.bucket;
-        if (tl.bucket > 3 || pi.d > width || (int)(2u * tl.bucket + (tn ? 1u : 0u)) != c)
-            return fail(err, SIM_EINVAL, "plan: tile %llu in the wrong class", (unsigned long long)q);
-        const uint64_t chunk = chunk_of(pi.n_samples, pi.d, L, tn);
-        if (chunk * L < pi.n_samples) return fail(err, SIM_EINVAL, "plan: tile %llu leaves samples out", (unsigned long long)q);
-        // highest normal a lane reads: its chunk's numerators (and chi-square normals), plus a block
-        const uint64_t top = (uint64_t)pi.n_samples * pi.d + (tn ? (chunk * L) * pi.nu : 0) + chunk * L * pi.d + 4;
+        if (pi.d > 8u * tl.Pa || pi.d > 32u) return fail(err, SIM_EINVAL, "plan: tile %llu holds d=%u", (unsigned long long)q, pi.d);
+        const uint32_t Ps = L / tl.Pa;
+        const uint64_t chunk = chunk_of(pi.n_samples, pi.d, Ps, tn);
+        if (chunk * Ps < pi.n_samples) return fail(err, SIM_EINVAL, "plan: tile %llu leaves samples out", (unsigned long long)q);
+        // highest normal a lane draws: its chunk's numerators (one block past the last round with
+        // the second of a pair), and the chi-square normals of its chunk
+        const uint64_t top = (uint64_t)pi.n_samples * pi.d + (tn ? (chunk * Ps + 1) * pi.nu : 0) +
+                             chunk * Ps * pi.d + 4 * (2 * tl.Pa + 1);
         if (top > 0xFFFFFFFFull) return fail(err, SIM_EINVAL, "plan: tile %llu numbers normals past 2^32", (unsigned long long)q);
         reps[tl.inst] += tl.nrep;
     }
@@ -665,13 +679,16 @@ static int plan_batch_impl(char *err, uint32_t n_inst, const sim_params *p, cons
     }
     if (cfg && (!(cfg->heavy_factor >= 0.0) || !std::isfinite(cfg->heavy_factor)))
         return fail(err, SIM_EINVAL, "heavy_factor must be finite and >= 0");
-    if (cfg && (cfg->flags & ~(uint32_t)SIM_KEEP_PATHS)) return fail(err, SIM_EINVAL, "unknown batch flag bits");
+    if (cfg && (cfg->flags & ~(uint32_t)(SIM_KEEP_PATHS | SIM_BATCH_GRAPH)))
+        return fail(err, SIM_EINVAL, "unknown batch flag bits");
     if (cfg && cfg->reserved) return fail(err, SIM_EINVAL, "reserved field must be 0");
 
-    // lanes per replication: the smallest P whose per-lane work fits theta x the balanced time
+    // lanes per replication: the asset lanes d needs, times the smallest power of two of sample
+    // lanes whose per-lane work fits theta x the balanced run time
     const double n_simd = 4.0 * n_cu;
     const double theta = (cfg && cfg->heavy_factor > 0.0) ? cfg->heavy_factor : 0.5;
     out.P.assign(n_inst, 1u);
+    for (uint32_t i = 0; i < n_inst; ++i) out.P[i] = asset_lanes(p[i].d);
     for (int pass = 0; pass < 3; ++pass) {
         double total = 0.0;
         for (uint32_t i = 0; i < n_inst; ++i) {
@@ -680,14 +697,19 @@ static int plan_batch_impl(char *err, uint32_t n_inst, const sim_params *p, cons
         }
         const double target = theta * total / n_simd;
         for (uint32_t i = 0; i < n_inst; ++i) {
-            uint32_t P = 1;
+            uint32_t P = asset_lanes(p[i].d);
             while (P < 64 && lane_cost(p[i], T[i], P) > target) P *= 2;
             out.P[i] = P;
         }
     }
     if (cfg && cfg->lanes_per_rep)
         for (uint32_t i = 0; i < n_inst; ++i)
-            if (cfg->lanes_per_rep[i]) out.P[i] = cfg->lanes_per_rep[i];
+            if (cfg->lanes_per_rep[i]) {
+                if (cfg->lanes_per_rep[i] < asset_lanes(p[i].d))
+                    return fail(err, SIM_EINVAL, "instance %u: lanes_per_rep %u below the %u lanes its d=%u assets need",
+                                i, cfg->lanes_per_rep[i], asset_lanes(p[i].d), p[i].d);
+                out.P[i] = cfg->lanes_per_rep[i];
+            }
 
     out.tiles_of.assign(n_inst, 0u);
     out.slot_begin.assign(n_inst + 1, 0u);
@@ -750,24 +772,15 @@ static int plan_batch_impl(char *err, uint32_t n_inst, const sim_params *p, cons
             tl.slot = (uint32_t)k;
             tl.nrep = (uint16_t)std::min<uint64_t>(rpt, R[i] - (uint64_t)t * rpt);
             tl.P = (uint8_t)out.P[i];
-            tl.bucket = (uint8_t)bucket_of(p[i].d);
+            tl.Pa = (uint8_t)asset_lanes(p[i].d);
             cost[k] = c;
         }
     }
-    auto cls = [&](uint32_t q) { return 2u * tiles[q].bucket + (p[tiles[q].inst].noise == SIM_NOISE_T ? 1u : 0u); };
     std::vector<uint32_t> order(n_tiles);
     std::iota(order.begin(), order.end(), 0u);
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-        const uint32_t ca = cls(a), cb = cls(b);
-        return ca != cb ? ca < cb : cost[a] > cost[b];
-    });
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
     out.tiles.resize(n_tiles);
-    for (uint32_t c = 0; c < 9; ++c) out.class_begin[c] = 0;
-    for (uint64_t q = 0; q < n_tiles; ++q) {
-        out.tiles[q] = tiles[order[q]];
-        out.class_begin[cls(order[q]) + 1]++;
-    }
-    for (uint32_t c = 0; c < 8; ++c) out.class_begin[c + 1] += out.class_begin[c];
+    for (uint64_t q = 0; q < n_tiles; ++q) out.tiles[q] = tiles[order[q]];
     return check_plan(err, n_inst, p, R, T, out);
 }
 

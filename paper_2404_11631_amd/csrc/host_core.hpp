@@ -47,7 +47,11 @@ void fill_stats(sim_stats_out *out, const double *F, uint32_t n_ckpt, const uint
                 double ymax, const uint64_t *dec, uint32_t d, uint64_t tau_count, uint64_t tau_sum, uint64_t R,
                 uint64_t T, double fstar, double ms, double path_steps);
 
-uint32_t chunk_of(uint32_t N, uint32_t d, uint32_t P, bool t_noise);
+// lanes splitting the assets of one replication in a batched tile: 8 assets per lane at most
+uint32_t asset_lanes(uint32_t d);
+// samples per lane: ceil(N / Ps) rounded up to whole Philox-block rounds
+uint32_t chunk_of(uint32_t N, uint32_t d, uint32_t Ps, bool t_noise);
+// modelled VALU work of one lane of a batched tile with P lanes per replication
 double lane_cost(const sim_params &p, uint64_t T, uint32_t P);
 
 // The work plan of a batched run.
@@ -56,8 +60,7 @@ struct BatchPlan {
     std::vector<uint64_t> path_base, cnt_base, wsum_base, dlog_base;
     std::vector<InstanceDesc> desc;
     std::vector<double> fstar;
-    std::vector<Tile> tiles;             // grouped by class (2 bucket + noise), longest first
-    uint32_t class_begin[9] = {0};       // tiles of class c: [class_begin[c], class_begin[c+1])
+    std::vector<Tile> tiles;             // longest first
     uint32_t n_tiles = 0, max_ckpt = 1;
     uint64_t total_R = 0, total_steps = 0, cnt_total = 0, wsum_total = 0, dlog_total = 0;
 };

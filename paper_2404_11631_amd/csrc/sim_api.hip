@@ -151,6 +151,8 @@ void sim_destroy(sim_ctx *ctx)
     if (b.slots_host) (void)hipHostFree(b.slots_host);
     if (b.ev0) (void)hipEventDestroy(b.ev0);
     if (b.ev1) (void)hipEventDestroy(b.ev1);
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.capture) (void)hipStreamDestroy(b.capture);
     CvState &cv = ctx->cv;
     for (DevBuf *x : {&cv.theta, &cv.w1a, &cv.w2a, &cv.w2t, &cv.mom1, &cv.mom2, &cv.part, &cv.grad, &cv.loss_hist,
                       &cv.xtrain, &cv.ytrain, &cv.ttrain, &cv.xio, &cv.yio, &cv.hout, &cv.xaux, &cv.haux, &cv.mpart,

@@ -53,8 +53,8 @@ struct InstanceDesc {
 };
 
 // One wavefront's unit of work in a batched run: `nrep` replications of one instance starting at
-// rep0, with P lanes per replication (samples split across them). Tiles are stored grouped by
-// class (2 bucket + noise), longest first within a class; `slot` is the tile's place in
+// rep0, with P lanes per replication: Pa of them split the assets (8 per lane at most), P / Pa
+// split the samples. Tiles are stored longest first; `slot` is the tile's place in
 // instance-major replication order, which fixes the reduction order.
 struct Tile {
     uint32_t inst;
@@ -62,7 +62,7 @@ struct Tile {
     uint32_t slot;
     uint16_t nrep;
     uint8_t P;
-    uint8_t bucket;          // 0: d <= 4, 1: d <= 8, 2: d <= 16, 3: d <= 32
+    uint8_t Pa;
 };
 
 // Per-tile partial record of a batched run (one wavefront's replications of one instance).

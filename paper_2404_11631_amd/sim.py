@@ -62,6 +62,12 @@ class SimPathView(ctypes.Structure):
                 ("n_features", ctypes.c_uint32), ("pad_", ctypes.c_uint32)]
 
 
+class SimTuneOut(ctypes.Structure):
+    _fields_ = [("heavy_factor", ctypes.c_double), ("from_cache", ctypes.c_uint32),
+                ("n_candidates", ctypes.c_uint32), ("cand_theta", ctypes.c_double * 16),
+                ("cand_ms", ctypes.c_double * 16), ("key", ctypes.c_uint64)]
+
+
 class SimBatchConfig(ctypes.Structure):
     _fields_ = [("reserved", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("heavy_factor", ctypes.c_double), ("lanes_per_rep", ctypes.POINTER(ctypes.c_uint8))]
@@ -200,7 +206,7 @@ EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_run_b
            "sim_cv_law", "sim_run_wide", "sim_validate_wide", "sim_wide_stats", "sim_wide_paths",
            "sim_run_newsvendor", "sim_validate_newsvendor", "sim_nv_stats", "sim_nv_paths",
            "sim_sqn_load", "sim_run_sqn", "sim_validate_sqn", "sim_sqn_stats", "sim_sqn_paths", "sim_sqn_hessian",
-           "sim_run_noalloc", "sim_noalloc_last_error", "sim_stats_from_raw")
+           "sim_run_noalloc", "sim_noalloc_last_error", "sim_stats_from_raw", "sim_tune_batch")
 
 _lib = None
 
@@ -265,6 +271,9 @@ def load():
         L.sim_sqn_stats.argtypes = [vp, ctypes.POINTER(SimStats)]
         L.sim_sqn_paths.argtypes = [vp, ctypes.POINTER(SimSqnView)]
         L.sim_sqn_hessian.argtypes = [vp, u64, ctypes.POINTER(SimSqnHessianView)]
+        L.sim_tune_batch.argtypes = [vp, ctypes.c_uint32, ctypes.POINTER(SimParams), ctypes.POINTER(ctypes.c_uint64),
+                                     ctypes.POINTER(ctypes.c_uint64), u64, ctypes.c_uint32, ctypes.c_char_p,
+                                     ctypes.POINTER(SimTuneOut)]
         L.sim_run_noalloc.argtypes = [ctypes.c_int, vp, ctypes.POINTER(SimParams), u64, u64, u64, vp, vp, vp]
         L.sim_noalloc_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
         L.sim_stats_from_raw.argtypes = [ctypes.POINTER(SimParams), u64, u64, _dp,
@@ -361,7 +370,10 @@ def cv_law(p: Problem, T: int):
     return probs, s2.value, s4.value
 
 
-def _batch_args(problems, R, T, heavy_factor=0.0, lanes_per_rep=None, keep_paths=False):
+BATCH_GRAPH = 0x100
+
+
+def _batch_args(problems, R, T, heavy_factor=0.0, lanes_per_rep=None, keep_paths=False, graph=False):
     n = len(problems)
     arr = (SimParams * n)()
     keep = []
@@ -372,7 +384,7 @@ def _batch_args(problems, R, T, heavy_factor=0.0, lanes_per_rep=None, keep_paths
     Ra = (ctypes.c_uint64 * n)(*[int(x) for x in R])
     Ta = (ctypes.c_uint64 * n)(*[int(x) for x in T])
     cfg = SimBatchConfig()
-    cfg.flags = KEEP_PATHS if keep_paths else 0
+    cfg.flags = (KEEP_PATHS if keep_paths else 0) | (BATCH_GRAPH if graph else 0)
     cfg.heavy_factor = heavy_factor
     if lanes_per_rep is not None:
         lp = (ctypes.c_uint8 * n)(*[int(x) for x in lanes_per_rep])
@@ -590,13 +602,23 @@ class Sim:
         return out
 
     def run_batch(self, problems, R, T, seed: int, *, heavy_factor: float = 0.0,
-                  lanes_per_rep=None, keep_paths: bool = False):
-        """Uneven batch of instances (sim_run_batch)."""
+                  lanes_per_rep=None, keep_paths: bool = False, graph: bool = False):
+        """Uneven batch of instances (sim_run_batch); graph: launch through a captured HIP graph."""
         n, arr, Ra, Ta, cfg, keep = _batch_args(problems, R, T, heavy_factor, lanes_per_rep,
-                                                keep_paths)
+                                                keep_paths, graph)
         self._keep = keep
         self._batch_n = n
         self._check(self.L.sim_run_batch(self.h, n, arr, Ra, Ta, seed, ctypes.byref(cfg)))
+
+    def tune_batch(self, problems, R, T, seed: int, t_scale: int = 16, cache: str | None = None) -> dict:
+        """sim_tune_batch: the measured theta of the batched plan (cached in `cache`, JSON lines)."""
+        n, arr, Ra, Ta, cfg, keep = _batch_args(problems, R, T)
+        o = SimTuneOut()
+        self._check(self.L.sim_tune_batch(self.h, n, arr, Ra, Ta, seed, t_scale,
+                                          cache.encode() if cache else None, ctypes.byref(o)))
+        return {"heavy_factor": o.heavy_factor, "from_cache": bool(o.from_cache), "key": f"{o.key:016x}",
+                "t_scale": t_scale,
+                "candidates": [(o.cand_theta[c], o.cand_ms[c]) for c in range(o.n_candidates)]}
 
     def batch_stats(self, i: int) -> SimStats:
         st = SimStats()

@@ -25,13 +25,6 @@ static std::vector<sim_params> g_params;
 static std::vector<uint64_t> g_R, g_T;
 static char g_err[512];
 
-template <int D, int NOISE>
-static void run_class(const BatchBuffers &B, uint32_t begin, uint32_t end)
-{
-    for (uint32_t t = begin; t < end; ++t)
-        emu_run_block(64, t - begin, [&] { fw_tile_kernel<D, NOISE>(B, begin); });
-}
-
 extern "C" int emu_run_batch(uint32_t n_inst, const sim_params *p, const uint64_t *R, const uint64_t *T,
                              uint64_t seed, const sim_batch_config *cfg, int keep)
 {
@@ -65,15 +58,7 @@ extern "C" int emu_run_batch(uint32_t n_inst, const sim_params *p, const uint64_
     B.wsum = keep ? g_wsum.data() : nullptr;
     B.dlog = P.dlog_total ? g_dlog.data() : nullptr;
     B.final_stats = g_final.data();
-    const uint32_t *cb = P.class_begin;
-    run_class<4, 0>(B, cb[0], cb[1]);
-    run_class<4, 1>(B, cb[1], cb[2]);
-    run_class<8, 0>(B, cb[2], cb[3]);
-    run_class<8, 1>(B, cb[3], cb[4]);
-    run_class<16, 0>(B, cb[4], cb[5]);
-    run_class<16, 1>(B, cb[5], cb[6]);
-    run_class<32, 0>(B, cb[6], cb[7]);
-    run_class<32, 1>(B, cb[7], cb[8]);
+    for (uint32_t t = 0; t < P.n_tiles; ++t) emu_run_block(64, t, [&] { fw_tile_kernel(B); });
     for (uint32_t i = 0; i < n_inst; ++i) emu_run_block(256, i, [&] { fw_batch_reduce(B); });
     return 0;
 }

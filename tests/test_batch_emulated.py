@@ -26,7 +26,8 @@ CASES = [  # (d, N, T, R, lanes per replication, noise)
     (5, 7, 30, 12, 4, 0),
     (13, 9, 20, 6, 16, 0),
     (20, 11, 16, 3, 64, 0),
-    (32, 6, 12, 10, 2, 0),
+    (32, 6, 12, 10, 8, 0),
+    (17, 5, 10, 7, 4, 1),
     (4, 6, 20, 8, 4, 1),
     (7, 3, 30, 5, 0, 0),
 ]
@@ -121,8 +122,10 @@ def test_plan_without_device():
     P, nt = sim.plan_batch([light, heavy], [4096, 4096], [100, 100_000], n_cu=256)
     assert P[0] == 1 and P[1] > 1
     assert nt[0] == 4096 // 64 and nt[1] == 4096 // (64 // P[1])
-    P2, _ = sim.plan_batch([light, heavy], [4096, 4096], [100, 100_000], lanes_per_rep=[8, 2])
-    assert P2 == [8, 2]
+    P2, _ = sim.plan_batch([light, heavy], [4096, 4096], [100, 100_000], lanes_per_rep=[8, 4])
+    assert P2 == [8, 4]
+    with pytest.raises(sim.SimError):
+        sim.plan_batch([light, heavy], [4096, 4096], [100, 100_000], lanes_per_rep=[8, 2])
     with pytest.raises(sim.SimError):
         sim.plan_batch([light], [10], [10], lanes_per_rep=[3])
 
@@ -138,8 +141,10 @@ def test_plan_checks_full_uneven_workload():
     for b, p, n in zip(batch, P, nt):
         assert p in (1, 2, 4, 8, 16, 32, 64)
         assert n == -(-b.R // (64 // p))
-    for forced in (1, 64):
-        sim.plan_batch(probs, [b.R for b in batch], [b.T for b in batch], lanes_per_rep=[forced] * len(batch))
+    pa = [1 if b.d <= 8 else 2 if b.d <= 16 else 4 for b in batch]
+    for forced in (pa, [64] * len(batch)):
+        P, _ = sim.plan_batch(probs, [b.R for b in batch], [b.T for b in batch], lanes_per_rep=forced)
+        assert P == forced
     one = sim.Problem(mu=np.full(4, 0.5), sigma=np.full(4, 0.5), N=4)
     sim.plan_batch([one], [64], [131_071])
     with pytest.raises(sim.SimError) as e:
