@@ -94,10 +94,12 @@ typedef struct {
     uint64_t log_rep_begin;     /* SIM_DECISION_LOG: first logged replication */
     uint64_t log_rep_count;     /* SIM_DECISION_LOG: number of logged replications (<= 65536) */
     const double *cv_ref;       /* SIM_CV_FEATURES: [d] reference gradient b of the features */
-    const uint32_t *n_schedule; /* sim_run_wide only: sample size N_k of every epoch k < ceil(T / M),
-                                   each in [2, SIM_WIDE_MAX_N] (Algorithm 1's resampling step lets the
-                                   size adapt to k); NULL: n_samples in every epoch. Other entry
-                                   points reject a schedule with SIM_EUNSUPPORTED */
+    const uint32_t *n_schedule; /* sample size N_k of every epoch k < ceil(T / M) (Algorithm 1's
+                                   resampling step lets the size adapt to k), each in [2, 2^24] for
+                                   sim_run (diagonal Sigma, no control-variate features) and in
+                                   [2, SIM_WIDE_MAX_N] for sim_run_wide; NULL: n_samples in every
+                                   epoch. A dense factor, features, batches and sim_run_noalloc
+                                   reject a schedule with SIM_EUNSUPPORTED */
 } sim_params;
 
 /* FP64 statistics of one run. Means, variances and sums use compensated (double-double)

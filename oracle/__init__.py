@@ -47,7 +47,7 @@ class Problem(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("lam", ctypes.c_double), ("gap_eps", ctypes.c_double),
                 ("mu", ctypes.POINTER(ctypes.c_double)), ("chol", ctypes.POINTER(ctypes.c_double)),
                 ("w0", ctypes.POINTER(ctypes.c_double)), ("ckpt", ctypes.c_int64 * MAX_CKPT),
-                ("cv_ref", ctypes.POINTER(ctypes.c_double))]
+                ("cv_ref", ctypes.POINTER(ctypes.c_double)), ("n_sched", ctypes.POINTER(ctypes.c_int32))]
 
 
 class PathOut(ctypes.Structure):
@@ -211,7 +211,7 @@ class OracleProblem:
     """Keeps the numpy buffers of one problem alive next to its ctypes struct."""
 
     def __init__(self, mu, sigma=None, chol=None, *, N, M=1, lam=0.5, w0=None, noise=NOISE_GAUSS,
-                 nu=3, seed=0, instance=0, ckpt=(), gap_eps=1e-2, cv_ref=None):
+                 nu=3, seed=0, instance=0, ckpt=(), gap_eps=1e-2, cv_ref=None, n_sched=None):
         self.mu = np.ascontiguousarray(mu, dtype=np.float64)
         d = self.mu.shape[0]
         if chol is None:
@@ -228,6 +228,9 @@ class OracleProblem:
         p.w0 = _dptr(self.w0) if self.w0 is not None else ctypes.POINTER(ctypes.c_double)()
         self.cv_ref = None if cv_ref is None else np.ascontiguousarray(cv_ref, dtype=np.float64)
         p.cv_ref = _dptr(self.cv_ref) if self.cv_ref is not None else ctypes.POINTER(ctypes.c_double)()
+        self.n_sched = None if n_sched is None else np.ascontiguousarray(n_sched, dtype=np.int32)
+        p.n_sched = (self.n_sched.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)) if self.n_sched is not None
+                     else ctypes.POINTER(ctypes.c_int32)())
         for i, c in enumerate(ck):
             p.ckpt[i] = int(c)
         self.p = p

@@ -7,10 +7,11 @@
  * Monte Carlo estimate of E f(w_T) from Algorithm 1. Its features summarize the noise each path
  * consumed so that their joint law is known exactly. Per epoch e (E = ceil(T/M) epochs), with
  * zbar_e the sample mean of the epoch's Gaussian numerators:
- *   J_e = the vertex the linear subproblem over W picks for the fixed gradient b - L zbar_e (b a
- *         reference gradient fixed before the run): lowest index among equal minima, the origin
- *         when the minimum is >= 0. zbar_e ~ N(0, I/N) i.i.d. over epochs, so for diagonal
- *         L = diag(sigma) the J_e are i.i.d. categorical with probabilities p_c given by one-
+ *   J_e = the vertex the linear subproblem over W picks for the fixed gradient b - diag(L) zbar_e
+ *         (b a reference gradient fixed before the run; diag(L) = sigma for a diagonal factor, each
+ *         noise coordinate against its own diagonal entry for a dense one): lowest index among
+ *         equal minima, the origin when the minimum is >= 0. zbar_e ~ N(0, I/N) i.i.d. over
+ *         epochs, so the J_e are i.i.d. categorical with probabilities p_c given by one-
  *         dimensional integrals (or_cv_pick_probs);
  *   q_e = sum_j sum_i (z_eij - zbar_ej)^2 ~ chi-square(d (N-1)), independent of zbar_e.
  * The summaries are count_c = sum_t (t+1)^2 [J_e(t) = c] (the late iterations weigh most, as in

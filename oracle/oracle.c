@@ -166,8 +166,10 @@ double or_objective(const or_problem *p, const double *w)
 
 /* The epoch's reference decision for the control-variate features (see cv.c): the vertex the
  * linear subproblem picks for the fixed gradient cv_ref perturbed by this epoch's sample-mean noise,
- * cv_ref - L zbar (lowest index among equal minima, the origin when the minimum is >= 0), and the
- * gap between its value and the next best. */
+ * cv_ref_j - L_jj zbar_j (lowest index among equal minima, the origin when the minimum is >= 0), and
+ * the gap between its value and the next best. For a diagonal L this is cv_ref - L zbar; for a
+ * dense factor each noise coordinate is read against its own diagonal entry, which keeps the
+ * decisions' law in product form. */
 static int cv_reference_decision(const or_problem *p, const double *z, double *zbar, double *vals,
                                  double *margin)
 {
@@ -178,11 +180,7 @@ static int cv_reference_decision(const or_problem *p, const double *z, double *z
         zbar[j] = s / (double)N;
     }
     vals[0] = 0.0;                                   /* the origin */
-    for (int j = 0; j < d; ++j) {
-        double lz = 0.0;
-        for (int k = 0; k <= j; ++k) lz += p->chol[j * d + k] * zbar[k];
-        vals[j + 1] = p->cv_ref[j] - lz;
-    }
+    for (int j = 0; j < d; ++j) vals[j + 1] = p->cv_ref[j] - p->chol[j * d + j] * zbar[j];
     int best = 1;
     for (int c = 2; c <= d; ++c)
         if (vals[c] < vals[best]) best = c;
@@ -266,11 +264,22 @@ void or_sample_gradient_bound(const or_problem *p, uint64_t rep, uint64_t epoch,
 int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay, double uroff,
             or_path_out *out, uint8_t *decisions)
 {
-    const int d = p->d, N = p->N, M = p->M;
-    if (d < 1 || d > OR_MAX_D || N < 2 || M < 1 || T < 1 || p->n_ckpt < 0 ||
+    const int d = p->d, M = p->M;
+    if (d < 1 || d > OR_MAX_D || p->N < 2 || M < 1 || T < 1 || p->n_ckpt < 0 ||
         p->n_ckpt > OR_MAX_CKPT || !(p->lambda > 0.0))
         return -1;
     if (p->noise == OR_NOISE_T && p->nu < 3) return -1;
+    /* with a schedule, epoch k draws N_k samples: buffers hold the largest */
+    int N = p->N;
+    const uint64_t n_epochs = (T + (uint64_t)M - 1) / (uint64_t)M;
+    if (p->n_sched) {
+        N = 0;
+        for (uint64_t k = 0; k < n_epochs; ++k) {
+            if (p->n_sched[k] < 2) return -1;
+            if (p->n_sched[k] > N) N = p->n_sched[k];
+        }
+    }
+    or_problem pe = *p;      /* the problem as epoch k sees it: N = N_k */
 
     double *Rmat = (double *)malloc(sizeof(double) * (size_t)N * d);
     double *noise = (double *)malloc(sizeof(double) * (size_t)N * d);
@@ -298,8 +307,9 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
     for (uint64_t t = 0; t < T; ++t) {
         const uint64_t epoch = t / (uint64_t)M;        /* k = t div M, m = t mod M */
         if (t % (uint64_t)M == 0) {                    /* resample */
-            draw_returns(p, rep, epoch, Rmat, noise, zraw);
-            if (p->cv_ref) ref_pick = cv_reference_decision(p, zraw, zbar, rvals, &ref_margin);
+            if (p->n_sched) pe.N = p->n_sched[epoch];
+            draw_returns(&pe, rep, epoch, Rmat, noise, zraw);
+            if (p->cv_ref) ref_pick = cv_reference_decision(&pe, zraw, zbar, rvals, &ref_margin);
         }
         if (p->cv_ref) {                       /* weights (t+1)^2 and (t+1) on this epoch's pick */
             const double wt = (double)(t + 1) * (double)(t + 1);
@@ -309,7 +319,7 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
         }
 
         /* gradient of the sample objective at w_m */
-        sample_statistics(p, Rmat, w, rbar, sw);
+        sample_statistics(&pe, Rmat, w, rbar, sw);
         for (int j = 0; j < d; ++j) g[j] = 2.0 * p->lambda * sw[j] - rbar[j];
 
         /* linear subproblem over W: its vertices are the origin and e_1..e_d, so the minimiser
@@ -327,7 +337,7 @@ int or_path(const or_problem *p, uint64_t rep, uint64_t T, const uint8_t *replay
         double margin = second - best;
         if (margin < out->min_margin) out->min_margin = margin;
 
-        const double bound = gradient_rounding_bound(p, noise, w, g, uroff, vabs, pabs, habs);
+        const double bound = gradient_rounding_bound(&pe, noise, w, g, uroff, vabs, pabs, habs);
         int ambiguous = (margin <= 2.0 * bound);
         if (ambiguous) out->n_ambiguous++;
         if (replay && replay[t] != (uint8_t)a) {

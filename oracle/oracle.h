@@ -57,6 +57,9 @@ typedef struct {
     const double *w0;       /* d starting point in W, or NULL for the origin */
     int64_t ckpt[OR_MAX_CKPT]; /* iterate counts in [1, T] at which f(w_t) is recorded */
     const double *cv_ref;   /* d reference gradient of the control-variate features, or NULL */
+    /* Algorithm 1 lets the sample size N_k of epoch k adapt to k (the remark on its resampling
+     * step): n_sched[k] (>= 2) for every epoch k < ceil(T / M) of a run, or NULL for N throughout */
+    const int32_t *n_sched;
 } or_problem;
 
 /* reference decisions whose margin is below this are reported as ambiguous (cv_amb) */

@@ -309,11 +309,25 @@ int sim_cv_fit(sim_ctx *ctx, const sim_params *p, uint64_t T, uint64_t seed, con
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
         HIP_TRY(ctx, hipMemcpy(ws.data(), ctx->wsum.ptr, sizeof(uint64_t) * ws.size(), hipMemcpyDeviceToHost));
         const double c = 2.0 / ((double)T * (double)(T + 1));
-        for (uint32_t j = 0; j < p->d; ++j) {
+        const uint32_t d = p->d;
+        std::vector<double> wbar(d), v(d, 0.0);
+        for (uint32_t j = 0; j < d; ++j) {
             double acc = 0.0;
             for (uint64_t r = 0; r < kRefPilot; ++r) acc += (double)ws[j * kRefPilot + r];
-            const double wbar = c * acc / (double)kRefPilot;
-            cv.ref[j] = 2.0 * p->risk_coef * p->sigma[j] * p->sigma[j] * wbar - p->mu[j];
+            wbar[j] = c * acc / (double)kRefPilot;
+        }
+        if (p->chol) {
+            // Sigma wbar = L (L' wbar)
+            for (uint32_t k = 0; k < d; ++k)
+                for (uint32_t j = k; j < d; ++j) v[k] += p->chol[j * d + k] * wbar[j];
+            for (uint32_t j = 0; j < d; ++j) {
+                double sw = 0.0;
+                for (uint32_t k = 0; k <= j; ++k) sw += p->chol[j * d + k] * v[k];
+                cv.ref[j] = 2.0 * p->risk_coef * sw - p->mu[j];
+            }
+        } else {
+            for (uint32_t j = 0; j < d; ++j)
+                cv.ref[j] = 2.0 * p->risk_coef * p->sigma[j] * p->sigma[j] * wbar[j] - p->mu[j];
         }
     }
     sim_params q = *p;

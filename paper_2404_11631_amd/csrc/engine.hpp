@@ -109,6 +109,8 @@ struct sim_ctx {
     DevBuf y, fck, cnt, wsum, tau, dlog, part_f, part_i, done, final_f, final_i;
     DevBuf dense;                         // dense-L operands: Ag, Av (FP32), L (FP64)
     DevBuf feat;                          // control-variate features [(d+2)][R]
+    DevBuf sched;                         // per-epoch sample-size table (sim_params.n_schedule)
+    std::vector<unsigned char> sched_host; // its host copy, kept until the next run
     void *dense_host = nullptr;           // pinned staging of the same
     RunBuffers bufs{};
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;

@@ -58,13 +58,13 @@ __device__ __forceinline__ double tile_objective(const InstanceDesc *__restrict_
             const double sj = static_cast<double>(S[k]) + ((hibits >> k) & 1u ? 4294967296.0 : 0.0);
             const double w = sj * c;
             const double sw = P->sig_d[a0 + k] * w;
-            quad += sw * sw;
-            lin += P->mu_d[a0 + k] * w;
+            quad = fma(sw, sw, quad);
+            lin = fma(P->mu_d[a0 + k], w, lin);
         }
     }
     quad = bfly_sum(quad, 1u, Pa);
     lin = bfly_sum(lin, 1u, Pa);
-    return P->lambda * quad - lin;
+    return fma(P->lambda, quad, -lin);
 }
 
 __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile, float *stage)
@@ -145,7 +145,7 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
                     sub[4 * b0 + 2] = q0.z[2];
                     sub[4 * b0 + 3] = q0.z[3];
                 }
-                if (m + 1 < mb && b1 < nb) {
+                if (b1 < nb) {
                     sub[4 * b1 + 0] = q1.z[0];
                     sub[4 * b1 + 1] = q1.z[1];
                     sub[4 * b1 + 2] = q1.z[2];
@@ -208,7 +208,7 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
         for (int k = 0; k < kLaneAssets; ++k) {
             if (static_cast<uint32_t>(k) < acnt) {
                 const uint32_t j = a0 + k;
-                const float gj = P->c2_f[j] * (s2[k] - s1[k] * qn) - P->mu_f[j] - P->c1_f[j] * s1[k];
+                const float gj = fmaf(-P->c1_f[j], s1[k], fmaf(P->c2_f[j], fmaf(-s1[k], qn, s2[k]), -P->mu_f[j]));
                 if (jmin == 0xFFFFFFFFu || gj < gmin) {
                     gmin = gj;
                     jmin = j;

@@ -107,13 +107,23 @@ __device__ __forceinline__ double dense_objective(const InstanceDesc *P, const d
 
 // Three wavefronts per SIMD: the register budget (<= 168) that still holds the per-lane state
 // (16 assets x z, s1, s2, v at d = 64) without spilling in the sample loop.
-template <int D, int NOISE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3, 3)))
+//
+// FEAT writes the control-variate features of each path (sim.h): per epoch the reference decision
+// for cv_ref - D zbar, D = diag(L) (each noise coordinate against its own diagonal entry, so the
+// decisions stay i.i.d. with the product-form law of the diagonal case), from the sums of the
+// Gaussian numerators g1 (s1 itself for Gaussian noise); the per-category sums of (t+1)^2 are kept
+// in LDS in 32 bits (T <= 2343).
+// The feature variant at d = 64 needs the sums g1 beside z, s1, s2 and v: two wavefronts per SIMD
+// (<= 256 registers) keep it free of spills.
+template <int D, int NOISE, bool FEAT>
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu((FEAT && D == 64) ? 2 : 3, (FEAT && D == 64) ? 2 : 3)))
 void fw_dense_kernel(const InstanceDesc *P, RunBuffers B)
 {
     constexpr int H = D / 4;
     __shared__ uint32_t sS[D * kRB];          // signature S_j of each replication, [asset][replication]
     __shared__ uint16_t sC[(D + 1) * kRB];    // decision counts (T <= 65535), origin first
+    __shared__ uint32_t sF[FEAT ? (D + 1) * kRB : 1];   // features: sums of (t+1)^2 per category
     __shared__ double sm_f[2 * (kBlock / 64)];
     __shared__ uint64_t sm_i[kBlock / 64];
     __shared__ uint32_t sm_last;
@@ -142,6 +152,12 @@ void fw_dense_kernel(const InstanceDesc *P, RunBuffers B)
         sC[(dense_asset(p, k) + 1) * kRB + rep] = 0;
     }
     if (p == 0) sC[rep] = 0;
+    if constexpr (FEAT) {
+#pragma unroll
+        for (int k = 0; k < H; ++k) sF[(dense_asset(p, k) + 1) * kRB + rep] = 0u;
+        if (p == 0) sF[rep] = 0u;
+    }
+    uint64_t fcnt1 = 0;                       // (t+1)-weighted count of the most probable category
     uint32_t tau = kTauNone;
     uint32_t ck = 0;
     uint64_t next_ckpt = n_ckpt ? P->ckpt[0] : 0;
@@ -154,6 +170,7 @@ void fw_dense_kernel(const InstanceDesc *P, RunBuffers B)
         const float cw = t == 0 ? 0.0f
                                 : static_cast<float>(2.0 / (static_cast<double>(t) * static_cast<double>(t + 1)));
         float v[H], s1[H], s2[H];
+        float g1[(FEAT && NOISE == 1) ? H : 1];   // t noise: sums of the Gaussian numerators
         {
             float w[H];
 #pragma unroll
@@ -162,6 +179,7 @@ void fw_dense_kernel(const InstanceDesc *P, RunBuffers B)
                                 : static_cast<float>(sS[dense_asset(p, k) * kRB + rep]) * cw;
                 s1[k] = 0.0f;
                 s2[k] = 0.0f;
+                if constexpr (FEAT && NOISE == 1) g1[k] = 0.0f;
             }
             dense_product<D>(Av, w, v, lane);
         }
@@ -222,6 +240,42 @@ void fw_dense_kernel(const InstanceDesc *P, RunBuffers B)
                 if constexpr (NOISE == 1) s1[k] = fmaf(a, z[k], s1[k]);
                 else s1[k] += z[k];
                 s2[k] = fmaf(z[k], a2dot, s2[k]);
+                if constexpr (FEAT && NOISE == 1) g1[k] += z[k];
+            }
+        }
+
+        if constexpr (FEAT) {
+            if (m_in_epoch == 0) {
+                // the epoch's reference decision (lowest index among equal minima, the origin when the
+                // minimum is >= 0), weighted by the epoch's sums of (t+1)^2 and (t+1)
+                float vmin = INFINITY;
+                int vj = -1;
+#pragma unroll
+                for (int k = 0; k < H; ++k) {
+                    const int j = dense_asset(p, k);
+                    const float u = (NOISE == 1) ? g1[k] : s1[k];
+                    const float vv = fmaf(-P->cv_s[j], u, P->cv_b[j]);
+                    if (vj < 0 || vv < vmin || (vv == vmin && j < vj)) {
+                        vmin = vv;
+                        vj = j;
+                    }
+                }
+#pragma unroll
+                for (int x = 16; x <= 32; x <<= 1) {
+                    const float ov = __shfl_xor(vmin, x, 64);
+                    const int oj = __shfl_xor(vj, x, 64);
+                    if (ov < vmin || (ov == vmin && oj < vj)) {
+                        vmin = ov;
+                        vj = oj;
+                    }
+                }
+                const uint32_t pick = (vmin < 0.0f) ? static_cast<uint32_t>(vj + 1) : 0u;
+                const uint64_t t1 = (t + M < T) ? t + M : T;
+                const uint64_t w2 = (M == 1) ? (t + 1) * (t + 1)
+                                             : t1 * (t1 + 1) * (2 * t1 + 1) / 6 - t * (t + 1) * (2 * t + 1) / 6;
+                const uint64_t w1 = (M == 1) ? t + 1 : t1 * (t1 + 1) / 2 - t * (t + 1) / 2;
+                if (p == 0) sF[pick * kRB + rep] += static_cast<uint32_t>(w2);
+                fcnt1 += (pick == P->cv_top) ? w1 : 0u;
             }
         }
 
@@ -287,6 +341,25 @@ void fw_dense_kernel(const InstanceDesc *P, RunBuffers B)
                                         2.0 / (static_cast<double>(T) * static_cast<double>(T + 1)), sS);
     const bool leader = active && p == 0;
 
+    if constexpr (FEAT) {
+        // x_j for vertex e_j (category j+1, written by the lane owning asset j), x_d for the origin,
+        // x_{d+1} the (t+1)-weighted count of the most probable category; counts are exact in FP64
+        __syncthreads();
+        if (active) {
+#pragma unroll 1
+            for (int k = 0; k < H; ++k) {
+                const int j = dense_asset(p, k);
+                B.feat[static_cast<uint64_t>(j) * R + r64] = static_cast<float>(
+                    (static_cast<double>(sF[(j + 1) * kRB + rep]) - P->cv_mean[j + 1]) * P->cv_inv[j + 1]);
+            }
+            if (p == 0) {
+                B.feat[static_cast<uint64_t>(D) * R + r64] =
+                    static_cast<float>((static_cast<double>(sF[rep]) - P->cv_mean[0]) * P->cv_inv[0]);
+                B.feat[static_cast<uint64_t>(D + 1) * R + r64] =
+                    static_cast<float>((static_cast<double>(fcnt1) - P->cv_mean1) * P->cv_inv1);
+            }
+        }
+    }
     if (leader && (P->flags & 8u) && !(P->flags & 1u)) B.y[r64] = y;   // outcomes only
     if (active && (P->flags & 1u)) {
         if (p == 0) {
@@ -418,8 +491,13 @@ int launch_fw_dense(const InstanceDesc &host_desc, const InstanceDesc *dev_desc,
 {
     using K = void (*)(const InstanceDesc *, RunBuffers);
     K fn = nullptr;
-    if (host_desc.d == 64) fn = host_desc.noise ? fw_dense_kernel<64, 1> : fw_dense_kernel<64, 0>;
-    if (host_desc.d == 32) fn = host_desc.noise ? fw_dense_kernel<32, 1> : fw_dense_kernel<32, 0>;
+    const bool feat = (host_desc.flags & 4u) != 0;
+    if (host_desc.d == 64)
+        fn = feat ? (host_desc.noise ? fw_dense_kernel<64, 1, true> : fw_dense_kernel<64, 0, true>)
+                  : (host_desc.noise ? fw_dense_kernel<64, 1, false> : fw_dense_kernel<64, 0, false>);
+    if (host_desc.d == 32)
+        fn = feat ? (host_desc.noise ? fw_dense_kernel<32, 1, true> : fw_dense_kernel<32, 0, true>)
+                  : (host_desc.noise ? fw_dense_kernel<32, 1, false> : fw_dense_kernel<32, 0, false>);
     if (!fn) return -5;
     hipLaunchKernelGGL(fn, dim3(B.nblocks), dim3(kBlock), 0, stream, dev_desc, B);
     return hipGetLastError() == hipSuccess ? 0 : -3;

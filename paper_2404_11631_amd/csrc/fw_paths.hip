@@ -86,11 +86,11 @@ __device__ __forceinline__ double objective_from_signature(const InstanceDesc *_
         if (j < d) {
             const double w = static_cast<double>(S[j]) * c;
             const double sw = P->sig_d[j] * w;
-            quad += sw * sw;
-            lin += P->mu_d[j] * w;
+            quad = fma(sw, sw, quad);
+            lin = fma(P->mu_d[j], w, lin);
         }
     }
-    return P->lambda * quad - lin;
+    return fma(P->lambda, quad, -lin);
 }
 
 struct LaneResult {
@@ -99,14 +99,33 @@ struct LaneResult {
 };
 
 // One replication of Algorithm 1; returns Y and tau, leaves decision counts in cnt.
-template <int D, bool EXACT, typename Real, int NOISE, typename WS, bool FEAT>
+template <int D, bool EXACT, typename Real, int NOISE, typename WS, bool FEAT, bool SCHED>
 __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, const RunBuffers &B,
                                          uint32_t r, uint32_t (&cnt)[D + 1], WS (&S)[D],
                                          LaneResult &res, uint64_t *feat_cnt)
 {
     const Coef<Real> C{P};
     const int d = EXACT ? D : static_cast<int>(P->d);
-    const uint32_t N = P->N, M = P->M;
+    uint32_t N = P->N;
+    const uint32_t M = P->M;
+    // per-epoch sample sizes: N_k, 1/N_k and the coefficient rows of the current epoch
+    const Real *c1s = nullptr;
+    const Real *c2s = nullptr;
+    Real inv_ns = Real(0);
+    auto set_epoch = [&](uint32_t e) {
+        if constexpr (SCHED) {
+            N = B.sched_n[e];
+            if constexpr (std::is_same<Real, float>::value) {
+                inv_ns = B.sched_inv_f[e];
+                c1s = B.sched_c_f + static_cast<uint64_t>(e) * 2 * d;
+            } else {
+                inv_ns = B.sched_inv_d[e];
+                c1s = B.sched_c_d + static_cast<uint64_t>(e) * 2 * d;
+            }
+            c2s = c1s + d;
+        }
+    };
+    set_epoch(0);
     const uint64_t T = P->T;
     const uint32_t k0 = static_cast<uint32_t>(P->seed), k1 = static_cast<uint32_t>(P->seed >> 32);
     const uint32_t dom = P->instance & 0xFFFFFFu;   // domain 0: path noise
@@ -278,7 +297,7 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
         Real dot1 = Real(0);
 #pragma unroll
         for (int j = 0; j < D; ++j) dot1 = fma(s1[j], v[j], dot1);
-        const Real qn = dot1 * C.inv_n();
+        const Real qn = dot1 * (SCHED ? inv_ns : C.inv_n());
         Real gmin = Real(0);
         int jmin = -1;
         Real gw = Real(0);
@@ -287,7 +306,10 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
         for (int j = 0; j < D; ++j) {
             gv[j] = Real(0);
             if (j < d) {
-                const Real g = C.c2(j) * (s2[j] - s1[j] * qn) - C.mu(j) - C.c1(j) * s1[j];
+                // c2 (s2 - s1 qn) - mu - c1 s1 with every product fused explicitly, so that each
+                // kernel instantiation rounds it the same way
+                const Real c1j = SCHED ? c1s[j] : C.c1(j), c2j = SCHED ? c2s[j] : C.c2(j);
+                const Real g = fma(-c1j, s1[j], fma(c2j, fma(-s1[j], qn, s2[j]), -C.mu(j)));
                 if (jmin < 0 || g < gmin) {
                     gmin = g;
                     jmin = j;
@@ -325,6 +347,7 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
         if (++m_in_epoch == M) {
             m_in_epoch = 0;
             ++epoch;
+            if (t + 1 < T) set_epoch(epoch);
         }
     }
     res.y = objective_from_signature<D, EXACT, WS>(
@@ -349,7 +372,7 @@ __device__ __forceinline__ void run_path(const InstanceDesc *__restrict__ P, con
 // ---------------------------------------------------------------------------------------------
 // kernel: paths + per-workgroup partials + last-workgroup finalisation
 // ---------------------------------------------------------------------------------------------
-template <int D, bool EXACT, typename Real, int NOISE, typename WS, bool FEAT>
+template <int D, bool EXACT, typename Real, int NOISE, typename WS, bool FEAT, bool SCHED>
 __global__ __launch_bounds__(kBlock) void fw_paths_kernel(const InstanceDesc *__restrict__ P,
                                                           RunBuffers B)
 {
@@ -368,8 +391,8 @@ __global__ __launch_bounds__(kBlock) void fw_paths_kernel(const InstanceDesc *__
     WS S[D];
     LaneResult res{0.0, kTauNone};
     if (active) {
-        run_path<D, EXACT, Real, NOISE, WS, FEAT>(P, B, static_cast<uint32_t>(r), cnt, S, res,
-                                                  sm_feat + threadIdx.x);
+        run_path<D, EXACT, Real, NOISE, WS, FEAT, SCHED>(P, B, static_cast<uint32_t>(r), cnt, S, res,
+                                                         sm_feat + threadIdx.x);
         if ((P->flags & 8u) && !(P->flags & 1u)) B.y[r] = res.y;   // outcomes only
         if (P->flags & 1u) {
             B.y[r] = res.y;
@@ -507,10 +530,10 @@ __global__ __launch_bounds__(kBlock) void fw_paths_kernel(const InstanceDesc *__
 // ---------------------------------------------------------------------------------------------
 using KernelFn = void (*)(const InstanceDesc *, RunBuffers);
 
-template <int D, bool EXACT, typename Real, int NOISE, typename WS, bool FEAT>
+template <int D, bool EXACT, typename Real, int NOISE, typename WS, bool FEAT, bool SCHED = false>
 constexpr KernelFn kfn()
 {
-    return &fw_paths_kernel<D, EXACT, Real, NOISE, WS, FEAT>;
+    return &fw_paths_kernel<D, EXACT, Real, NOISE, WS, FEAT, SCHED>;
 }
 
 struct KernelChoice {
@@ -520,37 +543,52 @@ struct KernelChoice {
 };
 
 // Exact-width kernels pack each group of samples into whole Philox blocks at compile time; the
-// generic ones read the stream through a cursor and take d <= D at run time.
-template <typename Real, typename WS, bool FEAT>
+// generic ones read the stream through a cursor and take d <= D at run time. Runs with per-epoch
+// sample sizes (SCHED) use the generic kernels, whose per-sample arithmetic and order are the
+// exact-width kernels' (so a constant schedule reproduces the plain run bit for bit).
+template <typename Real, typename WS, bool FEAT, bool SCHED>
 static KernelChoice choose_gauss(uint32_t d)
 {
-    switch (d) {
-    case 1: return {kfn<1, true, Real, 0, WS, FEAT>(), 1, true};
-    case 2: return {kfn<2, true, Real, 0, WS, FEAT>(), 2, true};
-    case 3: return {kfn<3, true, Real, 0, WS, FEAT>(), 3, true};
-    case 4: return {kfn<4, true, Real, 0, WS, FEAT>(), 4, true};
-    case 5: return {kfn<5, true, Real, 0, WS, FEAT>(), 5, true};
-    case 6: return {kfn<6, true, Real, 0, WS, FEAT>(), 6, true};
-    case 8: return {kfn<8, true, Real, 0, WS, FEAT>(), 8, true};
-    case 10: return {kfn<10, true, Real, 0, WS, FEAT>(), 10, true};
-    case 12: return {kfn<12, true, Real, 0, WS, FEAT>(), 12, true};
-    case 16: return {kfn<16, true, Real, 0, WS, FEAT>(), 16, true};
-    default: break;
+    if constexpr (!SCHED) {
+        switch (d) {
+        case 1: return {kfn<1, true, Real, 0, WS, FEAT>(), 1, true};
+        case 2: return {kfn<2, true, Real, 0, WS, FEAT>(), 2, true};
+        case 3: return {kfn<3, true, Real, 0, WS, FEAT>(), 3, true};
+        case 4: return {kfn<4, true, Real, 0, WS, FEAT>(), 4, true};
+        case 5: return {kfn<5, true, Real, 0, WS, FEAT>(), 5, true};
+        case 6: return {kfn<6, true, Real, 0, WS, FEAT>(), 6, true};
+        case 8: return {kfn<8, true, Real, 0, WS, FEAT>(), 8, true};
+        case 10: return {kfn<10, true, Real, 0, WS, FEAT>(), 10, true};
+        case 12: return {kfn<12, true, Real, 0, WS, FEAT>(), 12, true};
+        case 16: return {kfn<16, true, Real, 0, WS, FEAT>(), 16, true};
+        default: break;
+        }
     }
-    if (d <= 16) return {kfn<16, false, Real, 0, WS, FEAT>(), 16, false};
+    if (d <= 16) return {kfn<16, false, Real, 0, WS, FEAT, SCHED>(), 16, false};
     if constexpr (sizeof(Real) == 4)
-        if (d <= 32) return {kfn<32, false, Real, 0, WS, FEAT>(), 32, false};
+        if (d <= 32) return {kfn<32, false, Real, 0, WS, FEAT, SCHED>(), 32, false};
     return {nullptr, 0, false};
 }
 
-template <typename Real, typename WS, bool FEAT>
+template <typename Real, typename WS, bool FEAT, bool SCHED>
 static KernelChoice choose_t(uint32_t d)
 {
-    if (d <= 8) return {kfn<8, false, Real, 1, WS, FEAT>(), 8, false};
-    if (d <= 16) return {kfn<16, false, Real, 1, WS, FEAT>(), 16, false};
+    if (d <= 8) return {kfn<8, false, Real, 1, WS, FEAT, SCHED>(), 8, false};
+    if (d <= 16) return {kfn<16, false, Real, 1, WS, FEAT, SCHED>(), 16, false};
     if constexpr (sizeof(Real) == 4)
-        if (d <= 32) return {kfn<32, false, Real, 1, WS, FEAT>(), 32, false};
+        if (d <= 32) return {kfn<32, false, Real, 1, WS, FEAT, SCHED>(), 32, false};
     return {nullptr, 0, false};
+}
+
+template <bool SCHED>
+static KernelChoice choose_plain(uint32_t d, uint32_t noise, bool fp64, bool wide)
+{
+    if (noise == 0) {
+        if (fp64) return wide ? choose_gauss<double, uint64_t, false, SCHED>(d) : choose_gauss<double, uint32_t, false, SCHED>(d);
+        return wide ? choose_gauss<float, uint64_t, false, SCHED>(d) : choose_gauss<float, uint32_t, false, SCHED>(d);
+    }
+    if (fp64) return wide ? choose_t<double, uint64_t, false, SCHED>(d) : choose_t<double, uint32_t, false, SCHED>(d);
+    return wide ? choose_t<float, uint64_t, false, SCHED>(d) : choose_t<float, uint32_t, false, SCHED>(d);
 }
 
 // Returns 0 and launches, or a negative code: -5 unsupported shape, -3 launch failure.
@@ -562,15 +600,13 @@ int launch_fw_paths(const InstanceDesc &host_desc, const InstanceDesc *dev_desc,
     const bool feat = (host_desc.flags & 4u) != 0;
     KernelChoice kc{nullptr, 0, false};
     if (feat) {
-        if (fp64 || wide) return -5;
-        kc = host_desc.noise == 0 ? choose_gauss<float, uint32_t, true>(host_desc.d)
-                                  : choose_t<float, uint32_t, true>(host_desc.d);
-    } else if (host_desc.noise == 0) {
-        if (fp64) kc = wide ? choose_gauss<double, uint64_t, false>(host_desc.d) : choose_gauss<double, uint32_t, false>(host_desc.d);
-        else kc = wide ? choose_gauss<float, uint64_t, false>(host_desc.d) : choose_gauss<float, uint32_t, false>(host_desc.d);
+        if (fp64 || wide || B.sched_n) return -5;
+        kc = host_desc.noise == 0 ? choose_gauss<float, uint32_t, true, false>(host_desc.d)
+                                  : choose_t<float, uint32_t, true, false>(host_desc.d);
+    } else if (B.sched_n) {
+        kc = choose_plain<true>(host_desc.d, host_desc.noise, fp64, wide);
     } else {
-        if (fp64) kc = wide ? choose_t<double, uint64_t, false>(host_desc.d) : choose_t<double, uint32_t, false>(host_desc.d);
-        else kc = wide ? choose_t<float, uint64_t, false>(host_desc.d) : choose_t<float, uint32_t, false>(host_desc.d);
+        kc = choose_plain<false>(host_desc.d, host_desc.noise, fp64, wide);
     }
     if (!kc.fn) return -5;
     if (kernel_width) *kernel_width = kc.D;

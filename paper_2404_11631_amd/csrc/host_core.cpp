@@ -33,8 +33,6 @@ int validate(char *err, const sim_params *p, uint64_t R, uint64_t T)
     if (p->abi_version != SIM_ABI_VERSION)
         return fail(err, SIM_EINVAL, "abi_version %u != %u", p->abi_version, SIM_ABI_VERSION);
     if (p->d < 1 || p->d > SIM_MAX_D) return fail(err, SIM_EINVAL, "d=%u outside [1, 64]", p->d);
-    if (p->n_schedule)
-        return fail(err, SIM_EUNSUPPORTED, "n_schedule: per-epoch sample sizes run on sim_run_wide only");
     if (R < 1 || R > 0xFFFFFFFFull) return fail(err, SIM_EINVAL, "R=%llu outside [1, 2^32)", (unsigned long long)R);
     if (T < 1 || T > 0xFFFFFFFEull) return fail(err, SIM_EINVAL, "T=%llu outside [1, 2^32-2]", (unsigned long long)T);
     if (!p->mu) return fail(err, SIM_EINVAL, "mu is NULL");
@@ -77,6 +75,23 @@ int validate(char *err, const sim_params *p, uint64_t R, uint64_t T)
     }
     if (p->n_samples < 2) return fail(err, SIM_EINVAL, "n_samples must be >= 2 (Eq. (4) divides by N-1)");
     if (p->n_samples > (1u << 24)) return fail(err, SIM_EINVAL, "n_samples above 2^24");
+    if (p->n_schedule) {
+        // per-epoch sample sizes N_k (the remark on Algorithm 1's resampling step): the per-lane
+        // kernels with a diagonal Sigma, without control-variate features
+        if (p->chol) return fail(err, SIM_EUNSUPPORTED, "n_schedule with a dense factor");
+        if (p->flags & SIM_CV_FEATURES) return fail(err, SIM_EUNSUPPORTED, "n_schedule with control-variate features");
+        if (p->resample_every < 1) return fail(err, SIM_EINVAL, "resample_every must be >= 1");
+        const uint64_t epochs = (T + p->resample_every - 1) / p->resample_every;
+        if (epochs > (1u << 24)) return fail(err, SIM_EINVAL, "n_schedule: more than 2^24 epochs");
+        for (uint64_t e = 0; e < epochs; ++e) {
+            const uint32_t n = p->n_schedule[e];
+            if (n < 2 || n > (1u << 24))
+                return fail(err, SIM_EINVAL, "n_schedule[%llu] = %u outside [2, 2^24]", (unsigned long long)e, n);
+            if ((uint64_t)n * (p->d + (p->noise == SIM_NOISE_T ? p->nu : 0u)) > 0xFFFFFFF0ull)
+                return fail(err, SIM_EINVAL, "n_schedule[%llu]: N (d + nu) normals per epoch above 2^32 - 16",
+                            (unsigned long long)e);
+        }
+    }
     // a replication's normals of one epoch are numbered in 32 bits: N d Gaussian numerators, then
     // N nu chi-square normals for t noise
     if ((uint64_t)p->n_samples * (p->d + (p->noise == SIM_NOISE_T ? p->nu : 0u)) > 0xFFFFFFF0ull)
@@ -100,15 +115,21 @@ int validate(char *err, const sim_params *p, uint64_t R, uint64_t T)
     if (p->flags & SIM_CV_FEATURES) {
         if (p->state_precision != SIM_FP32)
             return fail(err, SIM_EUNSUPPORTED, "control-variate features need FP32 state");
-        if (p->chol) return fail(err, SIM_EUNSUPPORTED, "control-variate features need diagonal Sigma");
-        if (p->d > 32) return fail(err, SIM_EUNSUPPORTED, "control-variate features need d <= 32");
-        if (T > kMaxNarrowT)
-            return fail(err, SIM_EUNSUPPORTED, "control-variate features need T <= %llu", (unsigned long long)kMaxNarrowT);
+        if (p->chol) {
+            if (T > kMaxDenseFeatT)
+                return fail(err, SIM_EUNSUPPORTED, "control-variate features with a dense factor need T <= %llu",
+                            (unsigned long long)kMaxDenseFeatT);
+        } else {
+            if (p->d > 32) return fail(err, SIM_EUNSUPPORTED, "control-variate features need d <= 32");
+            if (T > kMaxNarrowT)
+                return fail(err, SIM_EUNSUPPORTED, "control-variate features need T <= %llu",
+                            (unsigned long long)kMaxNarrowT);
+        }
         if (!p->cv_ref) return fail(err, SIM_EINVAL, "control-variate features need cv_ref");
         for (uint32_t j = 0; j < p->d; ++j) {
             if (!finite(p->cv_ref[j])) return fail(err, SIM_EINVAL, "cv_ref[%u] not finite", j);
-            if (!(p->sigma[j] > 0.0))
-                return fail(err, SIM_EUNSUPPORTED, "control-variate features need every sigma_j > 0");
+            if (!(cv_scale(p, j) > 0.0))
+                return fail(err, SIM_EUNSUPPORTED, "control-variate features need every sigma_j (or L_jj) > 0");
         }
     }
     if (p->instance_id >= (1u << 24)) return fail(err, SIM_EINVAL, "instance_id must be < 2^24");
@@ -246,6 +267,41 @@ int validate_sqn(char *err, const sim_sqn_params *p, uint64_t N, uint32_t n, uin
     return SIM_OK;
 }
 
+void fill_schedule(const sim_params *p, uint64_t T, std::vector<unsigned char> &buf, SchedLayout &L)
+{
+    const uint64_t E = (T + p->resample_every - 1) / p->resample_every;
+    const uint32_t d = p->d;
+    auto up = [](uint64_t x) { return (x + 255) / 256 * 256; };
+    L.epochs = E;
+    L.off_n = 0;
+    L.off_inv_f = up(L.off_n + 4 * E);
+    L.off_inv_d = up(L.off_inv_f + 4 * E);
+    L.off_c_f = up(L.off_inv_d + 8 * E);
+    L.off_c_d = up(L.off_c_f + 4 * E * 2 * d);
+    L.bytes = up(L.off_c_d + 8 * E * 2 * d);
+    buf.assign(L.bytes, 0);
+    uint32_t *n = reinterpret_cast<uint32_t *>(buf.data() + L.off_n);
+    float *inv_f = reinterpret_cast<float *>(buf.data() + L.off_inv_f);
+    double *inv_d = reinterpret_cast<double *>(buf.data() + L.off_inv_d);
+    float *cf = reinterpret_cast<float *>(buf.data() + L.off_c_f);
+    double *cd = reinterpret_cast<double *>(buf.data() + L.off_c_d);
+    const double kappa = fw::kBoxMullerScale;
+    for (uint64_t e = 0; e < E; ++e) {
+        // the coefficients of fill_desc with N = N_k, rounded the same way
+        const double N = (double)p->n_schedule[e];
+        n[e] = p->n_schedule[e];
+        inv_f[e] = (float)(1.0 / N);
+        inv_d[e] = 1.0 / N;
+        for (uint32_t j = 0; j < d; ++j) {
+            const double sg = p->sigma[j], sz = kappa * sg;
+            cf[e * 2 * d + j] = (float)(sz / N);
+            cf[e * 2 * d + d + j] = (float)(2.0 * p->risk_coef * sz / (N - 1.0));
+            cd[e * 2 * d + j] = sg / N;
+            cd[e * 2 * d + d + j] = 2.0 * p->risk_coef * sg / (N - 1.0);
+        }
+    }
+}
+
 void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed)
 {
     std::memset(&D, 0, sizeof(D));
@@ -277,7 +333,7 @@ void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uin
         const CvLaw law = cv_law(p, T);
         for (uint32_t j = 0; j < p->d; ++j) {
             D.cv_b[j] = (float)p->cv_ref[j];
-            D.cv_s[j] = (float)(p->sigma[j] * kappa / N);
+            D.cv_s[j] = (float)(cv_scale(p, j) * kappa / N);
         }
         for (uint32_t c = 0; c <= p->d; ++c) {
             D.cv_mean[c] = law.mean[c];
@@ -440,12 +496,14 @@ void cv_pick_probs(uint32_t d, const double *b, const double *s, double *p)
     }
 }
 
+double cv_scale(const sim_params *p, uint32_t j) { return p->chol ? p->chol[j * p->d + j] : p->sigma[j]; }
+
 CvLaw cv_law(const sim_params *p, uint64_t T)
 {
     CvLaw L;
     const uint32_t d = p->d, M = p->resample_every;
     std::vector<double> s(d);
-    for (uint32_t j = 0; j < d; ++j) s[j] = p->sigma[j] / std::sqrt((double)p->n_samples);
+    for (uint32_t j = 0; j < d; ++j) s[j] = cv_scale(p, j) / std::sqrt((double)p->n_samples);
     cv_pick_probs(d, p->cv_ref, s.data(), L.p);
     // per epoch e: W2_e, W1_e = sums of (t+1)^2 and (t+1) over its iterations;
     // S2 = sum W2_e, S4 = sum W2_e^2, S1 = sum W1_e, S11 = sum W1_e^2
@@ -662,6 +720,7 @@ static int plan_batch_impl(char *err, uint32_t n_inst, const sim_params *p, cons
     for (uint32_t i = 0; i < n_inst; ++i) {
         int rc = validate(err, &p[i], R[i], T[i]);
         if (rc) return rc;
+        if (p[i].n_schedule) return fail(err, SIM_EUNSUPPORTED, "instance %u: n_schedule in a batch", i);
         if (p[i].state_precision != SIM_FP32)
             return fail(err, SIM_EUNSUPPORTED, "instance %u: batched runs use FP32 state", i);
         if (p[i].d > 32) return fail(err, SIM_EUNSUPPORTED, "instance %u: d > 32 in a batch", i);

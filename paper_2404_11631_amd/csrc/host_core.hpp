@@ -24,6 +24,15 @@ int validate_wide(char *err, const sim_params *p, uint64_t R, uint64_t T);
 int validate_newsvendor(char *err, const sim_nv_params *p, uint64_t R, uint64_t T);
 int validate_sqn(char *err, const sim_sqn_params *p, uint64_t N, uint32_t n, uint64_t R, uint64_t K);
 void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed);
+// Per-epoch table of a sample-size schedule (sim_params.n_schedule): N_k, 1/N_k and the
+// coefficients c1 = sigma/N_k, c2 = 2 lambda sigma/(N_k - 1) of every epoch k, in both
+// precisions, rounded exactly as fill_desc rounds the plain run's (so a constant schedule
+// reproduces it bit for bit). Byte offsets of each array in one buffer.
+struct SchedLayout {
+    uint64_t epochs = 0, bytes = 0;
+    uint64_t off_n = 0, off_inv_f = 0, off_inv_d = 0, off_c_f = 0, off_c_d = 0;   // c: [E][2 d] (c1 | c2)
+};
+void fill_schedule(const sim_params *p, uint64_t T, std::vector<unsigned char> &buf, SchedLayout &L);
 // Law of the control-variate features of a run (diagonal Sigma, reference gradient p->cv_ref):
 // reference-decision probabilities p (0 origin, j+1 vertex e_j) and their running sums, the
 // weights S2 = sum_e W2_e, S4 = sum_e W2_e^2, S1 = sum_e W1_e, S11 = sum_e W1_e^2 (W2_e, W1_e the
@@ -34,6 +43,12 @@ struct CvLaw {
     uint32_t top;
     uint64_t epochs;
 };
+// The per-asset scale of the features' reference decision: sigma_j, or L_jj for a dense factor
+// (the decision then reads each noise coordinate against its own diagonal entry, which keeps the
+// product form of the law).
+double cv_scale(const sim_params *p, uint32_t j);
+// dense features keep their per-category sums of (t+1)^2 in 32 bits: T(T+1)(2T+1)/6 < 2^32
+constexpr uint64_t kMaxDenseFeatT = 2343;
 void cv_pick_probs(uint32_t d, const double *b, const double *s, double *p);
 CvLaw cv_law(const sim_params *p, uint64_t T);
 

@@ -365,21 +365,23 @@ __global__ __launch_bounds__(256) void mlp_init_kernel(MlpDev m, uint64_t seed, 
 // Draws k0 .. k0+n-1 from the exact joint law of the path features (stream domain 2 of the seed):
 // per epoch e a category from the 53-bit uniform ((a >> 5) 2^26 + (b >> 6) + 1/2) 2^-53 of words
 // (a, b) = (x0, x1) for even e, (x2, x3) for odd e of Philox block (e/2, 1, k, ...), weighted by the
-// epoch's sums of (t+1)^2 (every category) and (t+1) (category `top`). D bounds d.
-template <int D>
-__global__ __launch_bounds__(256) void cv_aux_kernel(AuxLaw law, uint64_t k0, uint64_t n, float *x, uint64_t ldx)
+// epoch's sums of (t+1)^2 (every category) and (t+1) (category `top`). D bounds d; BS threads per
+// workgroup; CT the per-category counter (32 bits only where T(T+1)(2T+1)/6 < 2^32: d = 64 arises
+// only with a dense factor, whose features need T <= 2343).
+template <int D, int BS, typename CT>
+__global__ __launch_bounds__(BS) void cv_aux_kernel(AuxLaw law, uint64_t k0, uint64_t n, float *x, uint64_t ldx)
 {
     constexpr int LEN = D + 1;                 // categories 0..D; entries beyond d hold 2 (never <= u)
-    constexpr int TOP = (LEN > 32) ? 64 : (LEN > 16) ? 32 : (LEN > 8) ? 16 : (LEN > 4) ? 8 : 4;
+    constexpr int TOP = (LEN > 64) ? 128 : (LEN > 32) ? 64 : (LEN > 16) ? 32 : (LEN > 8) ? 16 : (LEN > 4) ? 8 : 4;
     __shared__ double s_cum[LEN];
-    __shared__ uint64_t s_cnt[LEN * 256];      // [category][thread]: integer sums of (t+1)^2
+    __shared__ CT s_cnt[LEN * BS];             // [category][thread]: integer sums of (t+1)^2
     const int tid = threadIdx.x;
     const int d = law.d;
-    if (tid < LEN) s_cum[tid] = (tid <= d) ? law.cum[tid] : 2.0;
+    for (int c = tid; c < LEN; c += BS) s_cum[c] = (c <= d) ? law.cum[c] : 2.0;
 #pragma unroll
-    for (int c = 0; c < LEN; ++c) s_cnt[c * 256 + tid] = 0;
+    for (int c = 0; c < LEN; ++c) s_cnt[c * BS + tid] = 0;
     __syncthreads();
-    const uint64_t idx = static_cast<uint64_t>(blockIdx.x) * 256 + tid;
+    const uint64_t idx = static_cast<uint64_t>(blockIdx.x) * BS + tid;
     if (idx >= n) return;
     const uint32_t k = static_cast<uint32_t>(k0 + idx);
     const uint32_t dom = (2u << 24) | (law.instance & 0xFFFFFFu);
@@ -404,12 +406,12 @@ __global__ __launch_bounds__(256) void cv_aux_kernel(AuxLaw law, uint64_t k0, ui
         const uint64_t w2 = (M == 1) ? (t0 + 1) * (t0 + 1)
                                      : t1 * (t1 + 1) * (2 * t1 + 1) / 6 - t0 * (t0 + 1) * (2 * t0 + 1) / 6;
         const uint64_t w1 = (M == 1) ? t0 + 1 : t1 * (t1 + 1) / 2 - t0 * (t0 + 1) / 2;
-        s_cnt[c * 256 + tid] += w2;
+        s_cnt[c * BS + tid] += static_cast<CT>(w2);
         cnt1 += (c == top) ? w1 : 0u;
     }
     for (int c = 0; c <= d; ++c) {
         const uint64_t row = (c == 0) ? static_cast<uint64_t>(d) : static_cast<uint64_t>(c - 1);
-        x[row * ldx + idx] = static_cast<float>((static_cast<double>(s_cnt[c * 256 + tid]) - law.mean[c]) * law.inv[c]);
+        x[row * ldx + idx] = static_cast<float>((static_cast<double>(s_cnt[c * BS + tid]) - law.mean[c]) * law.inv[c]);
     }
     x[static_cast<uint64_t>(d + 1) * ldx + idx] = static_cast<float>((static_cast<double>(cnt1) - law.mean1) * law.inv1);
 }
@@ -529,10 +531,13 @@ int launch_cv_aux(const AuxLaw &law, uint64_t k0, uint64_t n, float *x, uint64_t
 {
     if (n == 0) return 0;
     const dim3 g(static_cast<uint32_t>((n + 255) / 256)), b(256);
-    if (law.d <= 4) hipLaunchKernelGGL(cv_aux_kernel<4>, g, b, 0, st, law, k0, n, x, ldx);
-    else if (law.d <= 8) hipLaunchKernelGGL(cv_aux_kernel<8>, g, b, 0, st, law, k0, n, x, ldx);
-    else if (law.d <= 16) hipLaunchKernelGGL(cv_aux_kernel<16>, g, b, 0, st, law, k0, n, x, ldx);
-    else if (law.d <= 32) hipLaunchKernelGGL(cv_aux_kernel<32>, g, b, 0, st, law, k0, n, x, ldx);
+    if (law.d <= 4) hipLaunchKernelGGL((cv_aux_kernel<4, 256, uint64_t>), g, b, 0, st, law, k0, n, x, ldx);
+    else if (law.d <= 8) hipLaunchKernelGGL((cv_aux_kernel<8, 256, uint64_t>), g, b, 0, st, law, k0, n, x, ldx);
+    else if (law.d <= 16) hipLaunchKernelGGL((cv_aux_kernel<16, 256, uint64_t>), g, b, 0, st, law, k0, n, x, ldx);
+    else if (law.d <= 32) hipLaunchKernelGGL((cv_aux_kernel<32, 256, uint64_t>), g, b, 0, st, law, k0, n, x, ldx);
+    else if (law.d <= 64 && law.T <= 2343)
+        hipLaunchKernelGGL((cv_aux_kernel<64, 128, uint32_t>), dim3(static_cast<uint32_t>((n + 127) / 128)), dim3(128), 0,
+                           st, law, k0, n, x, ldx);
     else return -5;
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }

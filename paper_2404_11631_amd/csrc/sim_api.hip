@@ -135,7 +135,7 @@ void sim_destroy(sim_ctx *ctx)
     else (void)hipDeviceSynchronize();
     for (DevBuf *b : {&ctx->y, &ctx->fck, &ctx->cnt, &ctx->wsum, &ctx->tau, &ctx->dlog, &ctx->part_f,
                       &ctx->part_i, &ctx->done, &ctx->final_f, &ctx->final_i, &ctx->dense,
-                      &ctx->feat})
+                      &ctx->feat, &ctx->sched})
         free_buf(*b);
     if (ctx->dense_host) (void)hipHostFree(ctx->dense_host);
     if (ctx->desc_dev) (void)hipFree(ctx->desc_dev);
@@ -234,6 +234,19 @@ int run_impl(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t
         HIP_TRY(ctx, hipMemcpyAsync(ctx->dense.ptr, ctx->dense_host, dense_bytes, hipMemcpyHostToDevice, ctx->stream));
     }
 
+    // per-epoch sample sizes: the table is uploaded from a host copy kept until the next run
+    // (every run first waits for the previous one on the stream)
+    SchedLayout sl;
+    if (p->n_schedule) {
+        try {
+            fill_schedule(p, T, ctx->sched_host, sl);
+        } catch (const std::bad_alloc &) {
+            return set_err(ctx, SIM_ENOMEM, "host memory for the sample-size table");
+        }
+        if ((rc = ensure(ctx, ctx->sched, sl.bytes))) return rc;
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->sched.ptr, ctx->sched_host.data(), sl.bytes, hipMemcpyHostToDevice, ctx->stream));
+    }
+
     fill_desc(*ctx->desc_host, p, R, T, seed);
     ctx->desc_host->flags |= internal;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->desc_dev, ctx->desc_host, sizeof(InstanceDesc), hipMemcpyHostToDevice, ctx->stream));
@@ -256,6 +269,12 @@ int run_impl(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t
     B.dense_g = dense ? (const float *)ctx->dense.ptr : nullptr;
     B.dense_v = dense ? (const float *)ctx->dense.ptr + dense_f : nullptr;
     B.dense_l64 = dense ? (const double *)((const float *)ctx->dense.ptr + 2 * dense_f) : nullptr;
+    const unsigned char *sb = static_cast<const unsigned char *>(ctx->sched.ptr);
+    B.sched_n = p->n_schedule ? reinterpret_cast<const uint32_t *>(sb + sl.off_n) : nullptr;
+    B.sched_inv_f = p->n_schedule ? reinterpret_cast<const float *>(sb + sl.off_inv_f) : nullptr;
+    B.sched_inv_d = p->n_schedule ? reinterpret_cast<const double *>(sb + sl.off_inv_d) : nullptr;
+    B.sched_c_f = p->n_schedule ? reinterpret_cast<const float *>(sb + sl.off_c_f) : nullptr;
+    B.sched_c_d = p->n_schedule ? reinterpret_cast<const double *>(sb + sl.off_c_d) : nullptr;
 
     HIP_TRY(ctx, hipEventRecord(ctx->ev_start, ctx->stream));
     int width = 0;
@@ -271,6 +290,7 @@ int run_impl(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t
 
     ctx->last = *p;
     ctx->last.mu = ctx->last.sigma = ctx->last.chol = ctx->last.w0 = nullptr;
+    ctx->last.n_schedule = nullptr;
     for (uint32_t j = 0; j < d; ++j) {
         ctx->last_mu[j] = p->mu[j];
         ctx->last_sigma[j] = dense ? 0.0 : p->sigma[j];

@@ -93,6 +93,7 @@ int sim_run_noalloc(int device, void *hip_stream, const sim_params *p, uint64_t 
     if (p->chol) return noalloc_fail(SIM_EUNSUPPORTED, "the no-allocation path takes a diagonal Sigma");
     if (p->state_precision != SIM_FP32) return noalloc_fail(SIM_EUNSUPPORTED, "the no-allocation path runs FP32 state");
     if (p->flags) return noalloc_fail(SIM_EUNSUPPORTED, "the no-allocation path keeps no per-path records, logs or features");
+    if (p->n_schedule) return noalloc_fail(SIM_EUNSUPPORTED, "the no-allocation path takes one sample size");
     if (!stats_f || !stats_i) return noalloc_fail(SIM_EINVAL, "stats_f and stats_i are required");
     if (p->n_checkpoints && !f_ckpt) return noalloc_fail(SIM_EINVAL, "f_ckpt is required with checkpoints");
     int n = 0;

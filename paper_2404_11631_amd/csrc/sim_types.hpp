@@ -116,6 +116,12 @@ struct RunBuffers {
     const float *dense_g;
     const float *dense_v;
     const double *dense_l64;
+    // per-epoch sample sizes (NULL without a schedule): N_k, 1/N_k, and [E][2 d] rows c1 | c2
+    const uint32_t *sched_n;
+    const float *sched_inv_f;
+    const double *sched_inv_d;
+    const float *sched_c_f;
+    const double *sched_c_d;
 };
 
 }  // namespace fw

@@ -34,13 +34,15 @@ def pick_probability(w, mu, sigma, N, lam, nodes=80):
 
 
 def wsum_law(T, mu, sigma, N, lam, w0=0.0):
-    """Exact probability vector over S_T in [0, T(T+1)/2]."""
+    """Exact probability vector over S_T in [0, T(T+1)/2]. N is the sample size of every step, or
+    a sequence of T sizes (a schedule with fresh samples every step)."""
     prob = np.zeros(1)
     prob[0] = 1.0
     for t in range(T):
         S = np.arange(prob.shape[0])
         w = np.full(prob.shape[0], w0) if t == 0 else 2.0 * S / (t * (t + 1.0))
-        p1 = pick_probability(w, mu, sigma, N, lam)
+        Nt = int(N[t]) if hasattr(N, "__len__") else N
+        p1 = pick_probability(w, mu, sigma, Nt, lam)
         new = np.zeros(prob.shape[0] + t + 1)
         new[: prob.shape[0]] += prob * (1.0 - p1)
         new[t + 1: t + 1 + prob.shape[0]] += prob * p1

@@ -22,7 +22,8 @@ def oracle_problem(p, seed):
     chol = p.chol if p.chol is not None else np.diag(np.asarray(p.sigma, dtype=np.float64))
     return oracle.OracleProblem(p.mu, chol=chol, N=p.N, M=p.M, lam=p.lam, w0=p.w0, noise=p.noise,
                                 nu=p.nu, seed=seed, instance=p.instance_id,
-                                ckpt=p.checkpoints, gap_eps=p.gap_eps, cv_ref=p.cv_ref)
+                                ckpt=p.checkpoints, gap_eps=p.gap_eps, cv_ref=p.cv_ref,
+                                n_sched=p.n_schedule)
 
 
 def uroff(p):

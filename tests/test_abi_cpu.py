@@ -169,8 +169,9 @@ def test_wide_validation(lib):
 
 
 def test_sample_size_schedule_validation(lib):
-    """Per-epoch sample sizes N_k: every entry of the ceil(T/M) epochs in [2, 1024] on the wide path;
-    every other entry point rejects a schedule as unsupported."""
+    """Per-epoch sample sizes N_k: every entry of the ceil(T/M) epochs in [2, 1024] on the wide path,
+    in [2, 2^24] on the per-lane path with a diagonal Sigma; a dense factor, control-variate
+    features and batches reject a schedule as unsupported."""
     mu, sig = workloads.diag_instance(0, 0, 64, "paper")
     sch = [2 + k for k in range(50)]
     assert sim.validate_wide(sim.Problem(mu=mu, sigma=sig, N=10, n_schedule=sch), 1, 50)[0] == 0
@@ -181,7 +182,16 @@ def test_sample_size_schedule_validation(lib):
     bad[49] = 1025
     assert sim.validate_wide(sim.Problem(mu=mu, sigma=sig, N=10, n_schedule=bad), 1, 50)[0] == -1
     assert sim.validate_wide(sim.Problem(mu=mu, sigma=sig, N=10, n_schedule=bad), 1, 49)[0] == 0   # 49 epochs
-    assert sim.validate(sim.Problem(mu=mu[:8], sigma=sig[:8], N=10, n_schedule=sch), 10, 50)[0] == -5
+    assert sim.validate(sim.Problem(mu=mu[:8], sigma=sig[:8], N=10, n_schedule=sch), 10, 50)[0] == 0
+    assert sim.validate(sim.Problem(mu=mu[:8], sigma=sig[:8], N=10, M=4, n_schedule=sch[:13]), 10, 50)[0] == 0
+    assert sim.validate(sim.Problem(mu=mu[:8], sigma=sig[:8], N=10, n_schedule=bad[:49] + [1]), 10, 50)[0] == -1
+    L = np.tril(np.ones((32, 32))) * 0.1
+    assert sim.validate(sim.Problem(mu=mu[:32], chol=L, N=10, n_schedule=sch), 10, 50)[0] == -5
+    assert sim.validate(sim.Problem(mu=mu[:8], sigma=sig[:8], N=10, n_schedule=sch, cv_features=True,
+                                    cv_ref=-mu[:8]), 10, 50)[0] == -5
+    with pytest.raises(sim.SimError) as e:
+        sim.plan_batch([sim.Problem(mu=mu[:8], sigma=sig[:8], N=10, n_schedule=sch)], [64], [50])
+    assert e.value.code == -5
 
 
 def test_newsvendor_validation(lib):

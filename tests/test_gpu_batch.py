@@ -38,9 +38,9 @@ SMALL = [  # (d, N, T, R, P, noise)
     (8, 4, 120, 64, 8, 0),
     (13, 9, 100, 40, 16, 0),
     (20, 11, 80, 33, 64, 0),
-    (32, 6, 60, 65, 2, 0),
+    (32, 6, 60, 65, 8, 0),
     (4, 6, 100, 50, 4, 1),
-    (17, 5, 60, 30, 1, 1),
+    (17, 5, 60, 30, 4, 1),
     (7, 3, 150, 90, 0, 0),     # 0: the cost model chooses
 ]
 
@@ -69,8 +69,9 @@ def test_small_batch_parity(ctx):
 
 
 def test_batch_equals_single_run_at_one_lane(ctx):
-    """P = 1 runs the same arithmetic in the same order as sim_run: identical bits."""
-    d, N, T, R = 10, 10, 400, 300
+    """One lane per replication (d <= 8) runs the same arithmetic in the same order as sim_run:
+    identical bits."""
+    d, N, T, R = 8, 10, 400, 300
     p = make(3, d, N, ckpt=(100, 400))
     p.keep_paths = True
     ctx.run(p, R, T, 5)
@@ -94,7 +95,7 @@ def test_batch_composition_invariance(ctx):
     ctx.run_batch([A, Bp, Cp], [200, 100, 150], [120, 300, 60], seed=7, lanes_per_rep=[4, 2, 8], keep_paths=True)
     ya = ctx.batch_paths(0)["y"].copy()
     sa = ctx.batch_stats(0)
-    ctx.run_batch([Cp, A], [150, 200], [60, 120], seed=7, lanes_per_rep=[1, 4], keep_paths=True, )
+    ctx.run_batch([Cp, A], [150, 200], [60, 120], seed=7, lanes_per_rep=[4, 4], keep_paths=True)
     yb = ctx.batch_paths(1)["y"]
     sb = ctx.batch_stats(1)
     assert np.array_equal(ya, yb)
@@ -148,3 +149,63 @@ def test_uneven_full_size(ctx):
             for k in range(3):
                 parity.check_rep(op, g, b.R - 3 + k, b.T, oracle.U32, decisions=g["decisions"][:, k])
             say(f"[batch] instance {i} (d={b.d} N={b.N} T={b.T} P={g['lanes_per_rep']}) matches the oracle")
+
+
+def test_tuner_measures_and_caches(ctx, tmp_path):
+    """sim_tune_batch times every theta candidate on reduced horizons, returns the fastest, writes
+    it to the cache, and a second call with the same instances reads the cache without running."""
+    probs = [make(i, d, N) for i, (d, N) in enumerate([(3, 5), (12, 40), (30, 20), (7, 2)])]
+    R, T = [512, 256, 256, 1024], [400, 3000, 2000, 200]
+    cache = str(tmp_path / "tune.json")
+    a = ctx.tune_batch(probs, R, T, seed=3, t_scale=4, cache=cache)
+    say(f"[batch] tuner: theta {a['heavy_factor']} from {a['candidates']}")
+    assert not a["from_cache"] and len(a["candidates"]) >= 4
+    assert all(ms > 0 for _, ms in a["candidates"])
+    assert a["heavy_factor"] == min(a["candidates"], key=lambda c: c[1])[0]
+    b = ctx.tune_batch(probs, R, T, seed=3, t_scale=4, cache=cache)
+    assert b["from_cache"] and b["heavy_factor"] == a["heavy_factor"] and b["key"] == a["key"]
+    c = ctx.tune_batch(probs, R, [t + 1 for t in T], seed=3, t_scale=4, cache=cache)
+    assert not c["from_cache"] and c["key"] != a["key"]
+    # the tuned plan runs and matches the oracle on a logged replication of the heaviest instance
+    p = make(1, 12, 40, ckpt=(100, 3000), log=(0, 2))
+    probs[1] = p
+    ctx.run_batch(probs, R, T, seed=3, heavy_factor=a["heavy_factor"], keep_paths=True)
+    g = ctx.batch_paths(1)
+    op = parity.oracle_problem(p, 3)
+    for k in range(2):
+        parity.check_rep(op, g, k, T[1], oracle.U32, decisions=g["decisions"][:, k])
+
+
+def test_graph_launch_replays_match_eager(ctx):
+    """SIM_BATCH_GRAPH: the captured launch, replayed several times with other eager work and
+    synchronisations between the replays, gives the eager run's bits every time; a new seed
+    travels in the descriptors of the same graph."""
+    probs = [make(20 + i, d, N, ckpt=(20, t)) for i, (d, N, t) in enumerate([(4, 6, 150), (11, 9, 90), (25, 5, 60)])]
+    R, T = [200, 130, 70], [150, 90, 60]
+
+    def snap():
+        out = []
+        for i in range(len(probs)):
+            st = ctx.batch_stats(i)
+            g = ctx.batch_paths(i)
+            out.append((st.mean, st.var, tuple(st.decision_total), g["y"].copy(), g["cnt"].copy()))
+        return out
+
+    def same(a, b):
+        for x, y in zip(a, b):
+            assert x[0] == y[0] and x[1] == y[1] and x[2] == y[2]
+            assert np.array_equal(x[3], y[3]) and np.array_equal(x[4], y[4])
+
+    ctx.run_batch(probs, R, T, seed=41, keep_paths=True)
+    eager = snap()
+    ctx.run_batch(probs, R, T, seed=42, keep_paths=True)
+    eager42 = snap()
+    other = make(30, 6, 4)
+    for k in range(3):
+        say(f"[batch] graph replay {k}")
+        ctx.run_batch(probs, R, T, seed=41, keep_paths=True, graph=True)
+        same(snap(), eager)
+        ctx.run(other, 500, 80, 9 + k)         # eager work between replays
+        ctx.stats()
+    ctx.run_batch(probs, R, T, seed=42, keep_paths=True, graph=True)
+    same(snap(), eager42)

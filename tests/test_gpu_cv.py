@@ -187,6 +187,20 @@ def test_aux_draws_match_oracle(ctx, d, N, M, T, n):
     assert np.all(err <= 2e-6 + 1e-6 * np.abs(ref))
 
 
+def test_aux_draws_dense_factor_match_oracle(ctx):
+    """d = 64 with a dense factor (the stress shape): the law of the features reads L_jj."""
+    d, N, T, n = 64, 100, 1000, 300
+    mu, L = workloads.dense_instance(0, 0, d)
+    b = _ref(mu, np.diag(L))
+    p = sim.Problem(mu=mu, chol=L, N=N, noise=sim.NOISE_T, nu=3, instance_id=6, cv_ref=b)
+    x = ctx.cv_aux_draws(p, T, 124, 77, n)
+    P = oracle.OracleProblem(mu, chol=L, N=N, noise=oracle.NOISE_T, nu=3, seed=124, instance=6, cv_ref=b)
+    ref, _, _ = oracle.CvLaw(P, T).aux(77, n)
+    err = np.abs(x.T.astype(np.float64) - ref)
+    say(f"[cv] aux dense d={d} T={T}: max err {err.max():.2e}")
+    assert np.all(err <= 2e-6 + 1e-6 * np.abs(ref))
+
+
 def test_cv_fit_and_estimate(ctx):
     """Train on the device, fit beta on a pilot, estimate: the estimator's arithmetic matches the
     oracle's on the same arrays, h matches the oracle's surrogate on the same features, the estimate
@@ -219,3 +233,58 @@ def test_cv_fit_and_estimate(ctx):
         f"variance gain {gain:.2f}, rho2 {st.rho2:.3f}, {st.kernel_ms:.1f} ms")
     assert abs(st.mean_cv - st.mean_plain) <= 4.5 * joint
     assert gain > 1.2
+
+
+@pytest.mark.parametrize("case", [
+    dict(d=32, N=6, M=1, T=80, R=128, noise=sim.NOISE_GAUSS),
+    dict(d=64, N=5, M=2, T=40, R=64, noise=sim.NOISE_T),
+], ids=lambda c: f"dense{c['d']}N{c['N']}M{c['M']}{'t' if c['noise'] else 'g'}")
+def test_dense_features_match_oracle(ctx, case):
+    """Features of the dense-factor kernel (reference decisions read each noise coordinate against
+    L_jj) against the oracle's, path by path, with the oracle replaying the logged decisions."""
+    d, R, T = case["d"], case["R"], case["T"]
+    mu, L = workloads.dense_instance(12, d, d)
+    b = _ref(mu, np.diag(L))
+    p = sim.Problem(mu=mu, chol=L, N=case["N"], M=case["M"], noise=case["noise"], nu=3,
+                    checkpoints=(T,), gap_eps=0.05, instance_id=50 + d, keep_paths=True,
+                    log_reps=(0, R), cv_features=True, cv_ref=b)
+    say(f"[cv] dense features d={d} N={case['N']} M={case['M']} noise={case['noise']} R={R} T={T}")
+    ctx.run(p, R, T, 78)
+    g = ctx.paths()
+    assert g["x"].shape == (d + 2, R)
+    P = parity.oracle_problem(p, 78)
+    law = oracle.CvLaw(P, T)
+    inv = 1.0 / np.sqrt(law.S4 * np.maximum(law.probs * (1 - law.probs), 1e-4))
+    amb1 = 1.0 / math.sqrt(law.S11 * max(law.probs[law.top] * (1 - law.probs[law.top]), 1e-4))
+    err, amb = 0.0, 0
+    for r in range(R):
+        o = parity.check_rep(P, g, r, T, oracle.U32, decisions=g["decisions"][:, r])
+        ref = law.path_features(o)
+        e = np.abs(g["x"][:, r].astype(np.float64) - ref)
+        tol = FEAT_ATOL + 1e-6 * np.abs(ref)
+        tol[: d + 1] += o.cv_amb * inv.max()
+        tol[d + 1] += math.sqrt(o.cv_amb) * amb1 * 4
+        amb += o.cv_amb > 0
+        err = max(err, e.max())
+        assert np.all(e <= tol), f"rep {r}: feature errors {e}"
+    say(f"[cv] dense max feature error {err:.2e}; replications with a near-tie reference decision: {amb}")
+
+
+def test_dense_cv_fit_and_estimate(ctx):
+    """The control variate on the dense-factor kernel (stress shape at a reduced horizon): trained on
+    the device, the estimate agrees with the plain mean of the same paths within their joint CI;
+    the variance ratio is reported."""
+    d, N, T = 64, 100, 60
+    mu, L = workloads.dense_instance(0, 0, d)
+    p = sim.Problem(mu=mu, chol=L, N=N, noise=sim.NOISE_T, nu=3)
+    fit = ctx.cv_fit(p, T, 5, n_runs=1, epochs=4, R_train=1 << 16, R_pilot=1 << 15, batch=4096, lr=2e-3)
+    say(f"[cv] dense fit: loss {fit.loss_first_epoch:.4f} -> {fit.loss_last_epoch:.4f}, beta {fit.beta:.3f}, "
+        f"rho2 {fit.rho2:.3f}")
+    R, R_aux = 1 << 15, 1 << 19
+    st = ctx.run_cv(p, R, T, 105, R_aux)
+    joint = math.sqrt(st.ci95_plain ** 2 + st.ci95_cv ** 2) / 1.96
+    gain = (st.var_plain / R) / st.var_est
+    say(f"[cv] dense plain {st.mean_plain:.6f} +- {st.ci95_plain:.2e}, cv {st.mean_cv:.6f} +- {st.ci95_cv:.2e}, "
+        f"variance gain {gain:.3f}, rho2 {st.rho2:.3f}")
+    assert abs(st.mean_cv - st.mean_plain) <= 4.5 * joint
+    assert math.isfinite(gain) and gain > 0

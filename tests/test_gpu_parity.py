@@ -199,3 +199,38 @@ def test_paper_scale_full_size(ctx):
             assert math.isclose(st.rse_mean[c], math.fsum(rse) / len(rse), rel_tol=1e-12, abs_tol=1e-300)
     hit = g["tau"] != sim.TAU_NONE
     assert st.tau_count == int(hit.sum())
+
+
+@pytest.mark.parametrize("kind,d,M,noise,precision", [
+    ("growing", 10, 1, sim.NOISE_GAUSS, sim.FP32),
+    ("geometric", 7, 2, sim.NOISE_GAUSS, sim.FP32),
+    ("growing", 5, 1, sim.NOISE_T, sim.FP32),
+    ("geometric", 12, 3, sim.NOISE_GAUSS, sim.FP64),
+])
+def test_sample_size_schedule_matches_oracle(ctx, kind, d, M, noise, precision):
+    """Per-epoch sample sizes N_k (the remark on Algorithm 1's resampling step) on the per-lane
+    kernel: every replication against the oracle with the same schedule."""
+    T, R = 240, 300
+    E = -(-T // M)
+    sched = [2 + k // 2 for k in range(E)] if kind == "growing" else [min(200, int(3 * 1.06 ** k)) for k in range(E)]
+    mu, sigma = workloads.diag_instance(31, d, d)
+    p = sim.Problem(mu=mu, sigma=sigma, N=sched[0], M=M, noise=noise, nu=4, precision=precision,
+                    checkpoints=(60, T), gap_eps=0.05, n_schedule=tuple(sched))
+    st, g, amb = run_and_compare(ctx, p, R, T, 13)
+    say(f"[parity] schedule {kind}: N from {sched[0]} to {sched[-1]}, replayed {amb}")
+
+
+@pytest.mark.parametrize("d,noise", [(10, sim.NOISE_GAUSS), (3, sim.NOISE_GAUSS), (20, sim.NOISE_T)])
+def test_constant_schedule_is_the_plain_run(ctx, d, noise):
+    """A schedule with N in every epoch gives the plain run's bits (its kernel takes the per-epoch
+    coefficients from the table, rounded as the plain run's are)."""
+    T, R, N = 150, 500, 9
+    mu, sigma = workloads.diag_instance(32, d, d)
+    base = dict(mu=mu, sigma=sigma, N=N, noise=noise, nu=3, checkpoints=(50, T), keep_paths=True)
+    ctx.run(sim.Problem(**base), R, T, 21)
+    a, sa = ctx.paths(), ctx.stats()
+    ctx.run(sim.Problem(**base, n_schedule=tuple([N] * T)), R, T, 21)
+    b, sb = ctx.paths(), ctx.stats()
+    for k in ("y", "cnt", "wsum", "tau", "f_ckpt"):
+        assert np.array_equal(a[k], b[k]), k
+    assert sa.mean == sb.mean and sa.var == sb.var

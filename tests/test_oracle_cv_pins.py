@@ -334,3 +334,28 @@ def test_beta_closed_form():
     assert math.isclose(b, -2.5, rel_tol=1e-12) and math.isclose(r2, 1.0, rel_tol=1e-12)
     b, r2 = oracle.cv_beta(g.normal(size=500), H)
     assert abs(b) < 0.25 and r2 < 0.05
+
+
+def test_dense_factor_features_follow_the_product_law():
+    """With a dense factor the reference decision reads each noise coordinate against L_jj, so the
+    counts follow the same product-form law as with L = diag(L_jj), whatever the off-diagonal
+    entries; the paths themselves use the full L."""
+    d, N, M, T, R = 3, 4, 1, 30, 3000
+    mu, sigma = _instance(d)
+    g = np.random.default_rng(5)
+    L = np.diag(sigma) + np.tril(g.uniform(-0.4, 0.4, (d, d)), -1)
+    P = oracle.OracleProblem(mu, chol=L, N=N, M=M, seed=8, instance=4, cv_ref=_ref(mu, sigma, N))
+    outs = P.run(R, T)
+    C = np.array([[o.cv_count[c] for c in range(d + 1)] for o in outs])
+    C1 = np.array([[o.cv_count1[c] for c in range(d + 1)] for o in outs])
+    law = oracle.CvLaw(P, T)
+    assert np.allclose(C.sum(1), law.S2)
+    _check_moments(C, C1, law)
+    # one iteration: the pick is the argmin of b - diag(L) zbar over the vertices and the origin
+    b = _ref(mu, sigma, N)
+    for r in range(20):
+        o = P.path(r, 1)
+        Z = oracle.normals(8, 0, 4, r, 0, 0, N * d).reshape(N, d)
+        v = b - np.diag(L) * Z.mean(axis=0)
+        cat = int(v.argmin()) + 1 if v.min() < 0 else 0
+        assert [o.cv_count[c] for c in range(d + 1)] == [1.0 if c == cat else 0.0 for c in range(d + 1)]

@@ -387,3 +387,65 @@ def test_ambiguity_replay_protocol():
     bad[150] = (bad[150] + 1) % (d + 1)
     worse = P.path(2, T, replay=bad, uroff=oracle.U64)
     assert worse.n_mismatch >= 1 and worse.first_mismatch == 150
+
+
+# ------------------------------------------------------------------------------------------
+# Per-epoch sample sizes N_k (the remark on Algorithm 1's resampling step)
+# ------------------------------------------------------------------------------------------
+def test_constant_schedule_is_the_plain_run():
+    d, T, M = 4, 90, 3
+    mu, sigma = workloads.diag_instance(3, 1, d)
+    plain = oracle.OracleProblem(mu, sigma, N=6, M=M, seed=7, ckpt=(30, 90), gap_eps=0.05)
+    sched = oracle.OracleProblem(mu, sigma, N=6, M=M, seed=7, ckpt=(30, 90), gap_eps=0.05,
+                                 n_sched=[6] * (T // M))
+    for r in range(5):
+        a, b = plain.path(r, T), sched.path(r, T)
+        assert a.y == b.y and list(a.cnt) == list(b.cnt) and list(a.wsum) == list(b.wsum)
+        assert a.tau == b.tau and list(a.f_ckpt) == list(b.f_ckpt)
+
+
+def test_schedule_draws_epoch_k_with_its_own_size():
+    """An epoch with N_k samples draws normals 0 .. N_k d - 1 of its stream: the first decision of a
+    schedule starting at N_0 equals the plain run's with N = N_0, and the runs part once N_k moves."""
+    d, T = 3, 40
+    mu, sigma = workloads.diag_instance(4, 2, d)
+    grow = [2 + k for k in range(T)]
+    sched = oracle.OracleProblem(mu, sigma, N=2, seed=9, n_sched=grow)
+    for r in range(40):
+        _, ds = sched.path(r, 1, want_decisions=True)
+        _, dp = oracle.OracleProblem(mu, sigma, N=2, seed=9).path(r, 1, want_decisions=True)
+        assert ds[0] == dp[0]
+    same = sum(sched.path(r, T).y == oracle.OracleProblem(mu, sigma, N=2, seed=9).path(r, T).y for r in range(40))
+    assert same < 40
+    with pytest.raises(ValueError):
+        oracle.OracleProblem(mu, sigma, N=2, seed=9, n_sched=[2, 1] + grow[2:]).path(0, T)
+
+
+@pytest.mark.parametrize("sched", ["growing", "geometric"])
+def test_d1_schedule_matches_exact_law(sched):
+    """d = 1, fresh samples every step with N_t from a schedule: the oracle's S_T against the exact
+    dynamic program with the same per-step sample sizes."""
+    mu, sigma, lam, T, R = 0.3, 0.8, 0.5, 20, 20_000
+    Ns = [2 + t for t in range(T)] if sched == "growing" else [int(2 * 1.25 ** t) for t in range(T)]
+    P = oracle.OracleProblem([mu], [sigma], N=2, lam=lam, seed=4048, n_sched=Ns)
+    outs = P.run(R, T)
+    S = np.array([o.wsum[0] for o in outs])
+    law = exact_d1.wsum_law(T, mu, sigma, Ns, lam)
+    # the constant-N law is visibly different, so the test can tell a schedule that is ignored
+    const = exact_d1.wsum_law(T, mu, sigma, 2, lam)
+    idx = np.arange(law.shape[0])
+    assert abs((law * idx).sum() - (const * idx).sum()) > 6 * math.sqrt((law * idx ** 2).sum() / R)
+    exp = law * R
+    obs = np.bincount(S, minlength=law.shape[0]).astype(float)
+    cells_o, cells_e, acc_o, acc_e = [], [], 0.0, 0.0
+    for i in range(law.shape[0]):
+        acc_o += obs[i]
+        acc_e += exp[i]
+        if acc_e >= 20:
+            cells_o.append(acc_o)
+            cells_e.append(acc_e)
+            acc_o = acc_e = 0.0
+    cells_o[-1] += acc_o
+    cells_e[-1] += acc_e
+    chi2 = float(np.sum((np.array(cells_o) - np.array(cells_e)) ** 2 / np.array(cells_e)))
+    assert stats.chi2(len(cells_o) - 1).sf(chi2) > 1e-4
