@@ -7,10 +7,12 @@ fused with its cross-path reduction, followed by sim_stats; every step draws fre
 
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--cpu-seconds 20] [--no-cpu-baseline]
 
-The line also carries the control-variate leg ("cv", skip with --no-cv), the sweeps over the
-Section 4.1 shapes of Task 1 ("paper_shape"), Task 2 ("newsvendor_shape") and Task 3
-("sqn_shape"), and Table 2's RSE statistic over seven replications of each task ("table2"), all
-skipped with --no-paper-shape.
+The line also carries: each statistic's error against FP64 references ("stats"); the
+control-variate leg ("cv", skip with --no-cv); the sweeps over the Section 4.1 shapes of Task 1
+("paper_shape"), Task 2 ("newsvendor_shape") and Task 3 ("sqn_shape"), and Table 2's RSE
+statistic over seven replications of each task ("table2"), all skipped with --no-paper-shape; the
+uneven workload in one batched launch with its measured plan ("uneven", --no-uneven); the
+dense-L t(3) stress workload at R = 1e7 ("stress", --no-stress).
 
 Other measurements (not the headline line):
     --workload stress [--reps R]   the dense-L, t(3) stress workload (d = 64, N = 100, T = 1e3)
@@ -21,7 +23,9 @@ Other measurements (not the headline line):
     --workload sqn_shape           Task 3 (Algorithms 3-4) at Section 4.1's settings: n = 50 .. 5000
                                    features, N = 30 n, K = 2000, b_H = 300 / 600
     --workload uneven              the 256 uneven instances on the plain path, instance by instance
-                                   over four streams
+                                   over four streams (the comparison without batching)
+    --workload uneven_batch [--heavy-factor a,b,..] [--tune]
+                                   the 256 uneven instances in one batched launch, per theta
     --copy-probe BYTES             one plain device-to-device copy of BYTES, for calibrating the
                                    FETCH_SIZE / WRITE_SIZE counters against known traffic
 """
@@ -54,6 +58,8 @@ PEAK_OPS = 256 * 2.4e9 * 128
 PEAK_HBM = 8.0e12
 # dense FP64 matrix-core rate of one MI355X, flop/s
 PEAK_F64 = 78.6e12
+# dense FP32 matrix-core rate of one MI355X, flop/s
+PEAK_F32_MFMA = 157.3e12
 
 
 def ops_per_path_step(d: int, N: int) -> float:
@@ -107,13 +113,42 @@ def copy_probe(nbytes: int):
     print(json.dumps({"copy_probe_bytes": n * 4}), flush=True)
 
 
+def host_cpus():
+    """What the host offers this process: logical CPUs (nproc), the affinity set, the cgroup CPU
+    quota (cores' worth of time, None when unlimited) and the CPU model."""
+    nproc = os.cpu_count() or 1
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = nproc
+    quota = None
+    try:
+        q, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = int(q) / int(period)
+    except (OSError, ValueError):
+        pass
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = aff if quota is None else max(1, min(aff, int(math.floor(quota + 1e-9))))
+    return {"nproc": nproc, "affinity": aff, "cgroup_quota_cpus": quota, "model": model, "usable": usable}
+
+
 def cpu_baseline(w, mu, sigma, seconds: float):
-    """The oracle as it stands, on the host cores, over a bounded sample of replications."""
+    """The oracle as it stands, on every host core this process may use (one thread per core of
+    the affinity set, capped by the cgroup CPU quota), over a bounded sample of replications."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
 
-    threads = min(16, os.cpu_count() or 1)
+    host = host_cpus()
+    threads = host["usable"]
     P = oracle.OracleProblem(mu, sigma, N=w["N"], seed=w["seed"], ckpt=w["checkpoints"])
     T = w["T"]
     # calibrate: one path on one thread
@@ -131,8 +166,100 @@ def cpu_baseline(w, mu, sigma, seconds: float):
         list(ex.map(work, range(threads)))
     el = time.perf_counter() - t0
     return {"value": n * T / el, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+            "nproc": host["nproc"], "affinity": host["affinity"], "cgroup_quota_cpus": host["cgroup_quota_cpus"],
+            "cpu_model": host["model"], "single_thread_path_steps_per_s": T / one,
             "sample": f"{n} replications x T={T} of the paper-scale workload "
-                      f"({per_thread} per thread), serial FP64 oracle, {el:.1f} s wall"}
+                      f"({per_thread} per thread on {threads} threads), serial FP64 oracle, {el:.1f} s wall"}
+
+
+def parity_leg(ctx, sim, w, mu, sigma, n_log: int = 96):
+    """Each statistic's error at the paper-scale workload (Algorithm 1, Section 3.1, binary32 state)
+    against binary64 references, two ways.
+
+    (a) The FP64 oracle run without replay on n_log replications of the benchmarked launch (the
+        middle of the replication range, decisions logged): per path the decisions that differ, the
+        steps whose LMO margin lies within the rounding bound (ambiguous), Y's relative error; then
+        mean, variance, checkpoint means and RSE means of those paths, GPU vs oracle. The replayed
+        oracle (logged decision adopted at ambiguous steps) must then agree everywhere else.
+    (b) The same launch with binary64 state on the device over all R replications (its decisions
+        match the oracle bit for bit in the parity tests): the full-R statistics' relative change."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+
+    R, T, N, seed, ck = w["R"], w["T"], w["N"], w["seed"], w["checkpoints"]
+    begin = R // 2 - n_log // 2
+    p = sim.Problem(mu=mu, sigma=sigma, N=N, M=w["M"], precision=sim.FP32, checkpoints=ck, keep_paths=True,
+                    log_reps=(begin, n_log))
+    ctx.run(p, R, T, seed)
+    st = ctx.stats()
+    g = ctx.paths()
+    P = oracle.OracleProblem(mu, sigma, N=N, M=w["M"], seed=seed, ckpt=ck)
+
+    def one(k):
+        r = begin + k
+        free, dec = P.path(r, T, uroff=oracle.U32, want_decisions=True)
+        rep = P.path(r, T, replay=g["decisions"][:, k], uroff=oracle.U32)
+        return free, dec, rep
+
+    threads = host_cpus()["usable"]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(one, range(n_log)))
+    oracle_s = time.perf_counter() - t0
+    outs = (oracle.PathOut * n_log)()
+    diff_steps = diff_paths = amb_steps = amb_paths = rep_mismatch = 0
+    y_err = []
+    for k, (free, dec, rep) in enumerate(res):
+        r = begin + k
+        outs[k] = free
+        dsteps = int(np.count_nonzero(dec[:T] != g["decisions"][:T, k]))
+        diff_steps += dsteps
+        diff_paths += dsteps > 0
+        amb_steps += int(free.n_ambiguous)
+        amb_paths += free.n_ambiguous > 0
+        rep_mismatch += int(rep.n_mismatch)
+        y_err.append(abs(g["y"][r] - free.y) / abs(free.y))
+    ost = P.reduce(outs, T)
+    Y = g["y"][begin:begin + n_log]
+    F = g["f_ckpt"][:, begin:begin + n_log]
+    m = math.fsum(Y) / n_log
+    var = math.fsum((Y - m) ** 2) / (n_log - 1)
+
+    def rel(a, b):
+        return abs(a - b) / abs(b) if b != 0 else abs(a - b)
+
+    errs = {"mean": rel(m, ost.mean), "var": rel(var, ost.var)}
+    for c, t in enumerate(ck):
+        fm = math.fsum(F[c]) / n_log
+        ok = F[c] != 0
+        rse = ((F[c][ok] - Y[ok]) / F[c][ok]) ** 2
+        errs[f"f_mean@{t}"] = rel(fm, ost.f_mean[c])
+        errs[f"rse_mean@{t}"] = rel(math.fsum(rse) / max(1, len(rse)), ost.rse_mean[c])
+    sample = {"paths": n_log, "replications": [begin, begin + n_log], "oracle_s": oracle_s, "threads": threads,
+              "paths_with_differing_decisions": diff_paths, "differing_steps": diff_steps,
+              "ambiguous_paths": amb_paths, "ambiguous_path_fraction": amb_paths / n_log,
+              "ambiguous_steps": amb_steps, "ambiguous_step_fraction": amb_steps / (n_log * T),
+              "replay_unambiguous_mismatches": rep_mismatch,
+              "y_rel_err_max": max(y_err), "y_rel_err_median": float(np.median(y_err)),
+              "stat_rel_err": errs, "stat_rel_err_max": max(errs.values())}
+
+    # (b) binary64 state over all replications, same seed
+    p64 = sim.Problem(mu=mu, sigma=sigma, N=N, M=w["M"], precision=sim.FP64, checkpoints=ck)
+    ctx.run(p64, R, T, seed)
+    s64 = ctx.stats()
+    full = {"R": R, "fp64_kernel_ms": s64.kernel_ms, "mean": rel(st.mean, s64.mean), "var": rel(st.var, s64.var),
+            "mean_shift_over_ci95": abs(st.mean - s64.mean) / s64.ci95_halfwidth}
+    for c, t in enumerate(ck):
+        full[f"f_mean@{t}"] = rel(st.f_mean[c], s64.f_mean[c])
+        full[f"rse_mean@{t}"] = rel(st.rse_mean[c], s64.rse_mean[c])
+    d = len(mu)
+    full["decision_total_rel_diff_max"] = max(
+        abs(int(a) - int(b)) / max(1, int(b)) for a, b in zip(list(st.decision_total)[:d + 1],
+                                                          list(s64.decision_total)[:d + 1]))
+    return {"vs_fp64_oracle_sample": sample, "vs_fp64_state_full_R": full}
 
 
 def main():
@@ -143,13 +270,19 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="paper_scale",
-                    choices=("paper_scale", "stress", "paper_shape", "newsvendor_shape", "sqn_shape", "uneven"))
+                    choices=("paper_scale", "stress", "paper_shape", "newsvendor_shape", "sqn_shape", "uneven",
+                             "uneven_batch"))
+    ap.add_argument("--tune", action="store_true", help="uneven_batch: take theta from the measuring tuner")
+    ap.add_argument("--heavy-factor", default="0", help="uneven_batch: theta of the tile plan, or a comma "
+                    "list of them (0: the library's default)")
     ap.add_argument("--no-paper-shape", action="store_true", help="skip the Section 4.1 shape sweeps")
-    ap.add_argument("--reps", type=int, default=0, help="replications (stress only; 0: the full 1e7)")
+    ap.add_argument("--reps", type=int, default=0, help="replications of the stress workload (0: the full 1e7)")
     ap.add_argument("--sqn-sizes", default="", help="feature counts of the sqn_shape workload (comma list; "
                     "default: all of Section 4.1's)")
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--no-cv", action="store_true", help="skip the control-variate leg")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--no-stress", action="store_true", help="skip the stress leg")
     ap.add_argument("--cv-train-runs", type=int, default=10, help="training simulations of 1e6 paths")
     ap.add_argument("--cv-epochs", type=int, default=4)
     args = ap.parse_args()
@@ -166,6 +299,19 @@ def main():
         return
     if args.workload == "uneven":
         uneven_plain(args)
+        return
+    if args.workload == "uneven_batch":
+        import torch
+
+        from paper_2404_11631_amd import sim
+
+        torch.cuda.init()
+        ctx = sim.Sim(0, torch.cuda.current_stream().cuda_stream)
+        if args.tune:
+            print(json.dumps(uneven_batch_leg(ctx, sim, tune=True)), flush=True)
+        for hf in (float(x) for x in str(args.heavy_factor).split(",") if float(x) >= 0 and not args.tune):
+            print(json.dumps(uneven_batch_leg(ctx, sim, hf)), flush=True)
+        ctx.close()
         return
     if args.workload in ("paper_shape", "newsvendor_shape", "sqn_shape"):
         import torch
@@ -208,11 +354,14 @@ def main():
         kernel_ms.append(st.kernel_ms)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    par = parity_leg(ctx, sim, w, mu, sigma)
     cv = None if args.no_cv else cv_leg(ctx, sim, w, mu, sigma, args)
     shape = None if args.no_paper_shape else paper_shape_leg(ctx, sim, 2, 1)
     nv_shape = None if args.no_paper_shape else newsvendor_shape_leg(ctx, sim, 2, 1)
     sqn_shape = None if args.no_paper_shape else sqn_shape_leg(ctx, sim, 2, 1)
     table2 = None if args.no_paper_shape else table2_leg(ctx, sim)
+    uneven = None if args.no_uneven else uneven_batch_leg(ctx, sim, tune=True)
+    stress_r = None if args.no_stress else stress_leg(ctx, sim, args.reps or workloads.WORKLOADS["stress"]["R"])
     ctx.close()
 
     ms_step = 1e3 * wall / args.steps
@@ -238,7 +387,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / PEAK_OPS, "traffic": measured_traffic(),
                      "kernel_ms": kavg, "ops_per_path_step": ops_per_path_step(d, N)},
-        "stats": {"mean": st.mean, "ci95_halfwidth": st.ci95_halfwidth, "f_star": st.f_star},
+        "stats": {"mean": st.mean, "ci95_halfwidth": st.ci95_halfwidth, "f_star": st.f_star, **par},
     }
     if cv is not None:
         line["cv"] = cv
@@ -250,32 +399,50 @@ def main():
         line["sqn_shape"] = sqn_shape
     if table2 is not None:
         line["table2"] = table2
+    if uneven is not None:
+        line["uneven"] = uneven
+    if stress_r is not None:
+        line["stress"] = stress_r
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, mu, sigma, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 
+def _pool(parts):
+    """Pooled (n, mean, unbiased variance) of independent groups given as (n, mean, var)."""
+    n = sum(k for k, _, _ in parts)
+    m = sum(k * x for k, x, _ in parts) / n
+    ss = sum((k - 1) * v + k * (x - m) ** 2 for k, x, v in parts)
+    return n, m, ss / max(1, n - 1)
+
+
 def cv_leg(ctx, sim, w, mu, sigma, args):
-    """Wall time to a 95% CI half-width h for E f(w_T) on the paper-scale instance, plain Monte
-    Carlo vs the control variate, each by Stein's two-stage procedure: a pilot of 2^16 paths
-    estimates the standard deviation, then a fresh run of R* = ceil((1.96 s / h)^2) paths. The
-    control-variate form's pilot and main run include features, surrogate evaluation and the draws
-    from the features' law; its one-off training (simulation of the pairs, Adam, beta on a
-    held-out run) is reported separately. Reported at h = 1e-3 and at the h for which the plain
-    form needs 1e6 paths (below ~1e5 paths both forms are bound by one path's latency)."""
+    """Wall time to a 95% CI half-width h for E f(w_T) on the paper-scale instance (T = 1e4, d = N =
+    10): plain Monte Carlo, the MLP control variate, and a linear (least-squares) control variate
+    on the same d+2 features. Each form runs stages of fresh paths (at least 4,096 per stage),
+    pools them, and stops at the first stage after which its realized half-width is <= h; the next
+    stage is sized from the pooled variance. The wall time covers every stage (for the MLP form:
+    features, surrogate evaluation and draws from the features' known law; for the linear form:
+    features and the residuals). One-off costs are reported apart: training the surrogate (pairs
+    simulated, Adam, beta on a held-out run), fitting the linear coefficients (on the same
+    held-out pilot), and the calibration of the aux draws per path.
+
+    Features have mean 0 under their exact law, so the linear form needs no aux draws:
+    Y_lin = mean(Y - b'x). Reported at h = 1e-3 and at the h for which plain Monte Carlo needs
+    about 1e6 paths (below ~1e5 paths every form is bound by one path's latency)."""
+    import numpy as np
     import torch
 
     T, N = w["T"], w["N"]
+    d = len(mu)
     p = sim.Problem(mu=mu, sigma=sigma, N=N, M=w["M"], precision=sim.FP32, checkpoints=(T,))
     cvw = __import__("paper_2404_11631_amd.workloads", fromlist=["WORKLOADS"]).WORKLOADS["control_variate"]
     eval_seed = cvw["seed"]
+    R_min = 4096
 
-    def timed(fn):
+    def sync_time():
         torch.cuda.synchronize()
-        t = time.perf_counter()
-        out = fn()
-        torch.cuda.synchronize()
-        return out, time.perf_counter() - t
+        return time.perf_counter()
 
     t0 = time.perf_counter()
     fit = ctx.cv_fit(p, T, 1, n_runs=args.cv_train_runs, epochs=args.cv_epochs, R_train=1_000_000,
@@ -284,49 +451,88 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
     print(f"[cv] trained on {fit.n_train} pairs: loss {fit.loss_first_epoch:.4f} -> {fit.loss_last_epoch:.4f}, "
           f"beta {fit.beta:.3f}, pilot rho2 {fit.rho2:.3f}, {train_wall:.1f} s", file=sys.stderr, flush=True)
 
+    # calibration on a held-out pilot (untimed, like training): cost of an aux draw relative to a
+    # path, and the linear coefficients b by least squares of Y on (1, x)
     pilot_R = 1 << 16
-
-    def plain_run(R, seed):
-        ctx.run(p, R, T, seed)
-        return ctx.stats()
-
-    def cv_run(R, seed, R_aux):
-        return ctx.run_cv(p, R, T, seed, R_aux)
-
-    # pilots (each form's own): standard deviation of Y, and of Y - beta h with the aux variance
-    ps, plain_pilot_s = timed(lambda: plain_run(pilot_R, eval_seed + 1))
-    cs, cv_pilot_s = timed(lambda: cv_run(pilot_R, eval_seed + 2, 1 << 20))
-    s_plain = math.sqrt(ps.var)
-    s_resid = math.sqrt(max(cs.var_resid, 0.0))
-    beta2_vh = cs.beta ** 2 * cs.var_h_aux
-    # aux draws per path: the variance-per-cost optimum sqrt(beta^2 var(h) / (c var(Y - beta h))), c the
-    # cost of one draw relative to one path, measured on the pilot
+    t0 = sync_time()
+    cs = ctx.run_cv(p, pilot_R, T, eval_seed + 2, 1 << 20)
+    cal = ctx.cv_paths()
+    X = np.vstack([np.ones(pilot_R), cal["x"].astype(np.float64)]).T
+    coef, *_ = np.linalg.lstsq(X, cal["y"], rcond=None)
+    lin_b = coef[1:]
+    calib_s = sync_time() - t0
+    beta = cs.beta
+    beta2_vh = beta ** 2 * cs.var_h_aux
     c_aux = (cs.aux_ms / (1 << 20)) / (cs.paths_ms / pilot_R)
     ratio = min(100.0, max(1.0, math.sqrt(beta2_vh / (c_aux * max(cs.var_resid, 1e-300)))))
-    out = {"workload": "control_variate", "instance": "paper_scale (seed 0)", "T": T, "d": len(mu), "N": N,
+    s_plain = math.sqrt(cs.var_plain)
+    pf = sim.Problem(mu=mu, sigma=sigma, N=N, M=w["M"], precision=sim.FP32, checkpoints=(T,), keep_paths=True,
+                     cv_features=True, cv_ref=np.array(fit.ref[:d]))
+
+    def plain_stage(R, seed):
+        ctx.run(p, R, T, seed)
+        st = ctx.stats()
+        return (R, st.mean, st.var), None
+
+    def mlp_stage(R, seed):
+        o = ctx.run_cv(p, R, T, seed, min(max(2, math.ceil(ratio * R)), 1 << 31))
+        return (o.R, o.mean_resid, o.var_resid), (o.R_aux, o.mean_h_aux, o.var_h_aux)
+
+    def lin_stage(R, seed):
+        ctx.run(pf, R, T, seed)
+        g = ctx.paths()
+        res = g["y"] - lin_b @ g["x"].astype(np.float64)
+        return (R, math.fsum(res) / R, float(np.var(res, ddof=1))), None
+
+    def sequential(stage, h, seed0):
+        t = sync_time()
+        parts, aux, k, R_next = [], [], 0, R_min
+        while True:
+            a, b = stage(R_next, seed0 + 1000 * k)
+            parts.append(a)
+            if b is not None:
+                aux.append(b)
+            k += 1
+            n, m, v = _pool(parts)
+            var_est = v / n
+            if aux:
+                na, ma, va = _pool(aux)
+                m += beta * ma
+                var_est += beta ** 2 * va / na
+            ci = 1.96 * math.sqrt(var_est)
+            if ci <= h or k >= 8:
+                break
+            # paths still needed at the pooled variance per path, with a 2% margin
+            R_next = max(R_min, math.ceil(1.02 * n * (ci / h) ** 2) - n)
+        wall = sync_time() - t
+        return {"R": n, "stages": k, "mean": m, "ci95": ci, "met": ci <= h, "wall_s": wall,
+                "R_aux": sum(x[0] for x in aux) if aux else 0}
+
+    # the linear form's rho^2 on fresh paths (its own held-out check)
+    ctx.run(pf, pilot_R, T, eval_seed + 7)
+    g = ctx.paths()
+    res = g["y"] - lin_b @ g["x"].astype(np.float64)
+    rho2_lin = 1.0 - float(np.var(res, ddof=1)) / float(np.var(g["y"], ddof=1))
+    out = {"workload": "control_variate", "instance": "paper_scale (seed 0)", "T": T, "d": d, "N": N,
            "train": {"pairs": fit.n_train, "steps": fit.steps, "epochs": args.cv_epochs, "wall_s": train_wall,
                      "sim_ms": fit.sim_ms, "train_ms": fit.train_ms, "loss_first_epoch": fit.loss_first_epoch,
                      "loss_last_epoch": fit.loss_last_epoch, "beta": fit.beta, "pilot_rho2": fit.rho2},
-           "pilot_paths": pilot_R, "sd_plain": s_plain, "sd_resid": s_resid,
-           "variance_ratio": ps.var / max(cs.var_resid, 1e-300), "aux_per_path": None,
-           "aux_cost_per_path": c_aux, "targets": []}
+           "calibration_s": calib_s, "sd_plain": s_plain, "rho2_mlp": cs.rho2, "rho2_linear": rho2_lin,
+           "variance_ratio_mlp": cs.var_plain / max(cs.var_resid, 1e-300),
+           "variance_ratio_linear": 1.0 / max(1.0 - rho2_lin, 1e-300), "aux_per_path": ratio,
+           "aux_cost_per_path": c_aux, "min_paths_per_stage": R_min, "targets": []}
     for h in (1e-3, 1.96 * s_plain / 1000.0):
-        r_plain = max(2, math.ceil((1.96 * s_plain / h) ** 2))
-        r_cv = max(2, math.ceil((1.96 / h) ** 2 * (cs.var_resid + beta2_vh / ratio)))
-        r_aux = min(max(2, math.ceil(ratio * r_cv)), 1 << 31)
-        out["aux_per_path"] = ratio
-        pm, plain_s = timed(lambda: plain_run(r_plain, eval_seed + 3))
-        cm, cv_s = timed(lambda: cv_run(r_cv, eval_seed + 4, r_aux))
-        out["targets"].append({
-            "h": h,
-            "plain": {"R": r_plain, "pilot_s": plain_pilot_s, "main_s": plain_s, "total_s": plain_pilot_s + plain_s,
-                      "mean": pm.mean, "ci95": pm.ci95_halfwidth},
-            "cv": {"R": r_cv, "R_aux": r_aux, "pilot_s": cv_pilot_s, "main_s": cv_s, "total_s": cv_pilot_s + cv_s,
-                   "mean": cm.mean_cv, "ci95": cm.ci95_cv, "plain_mean_same_paths": cm.mean_plain},
-            "speedup": (plain_pilot_s + plain_s) / (cv_pilot_s + cv_s),
-        })
-        print(f"[cv] h={h:.2e}: plain R={r_plain} {plain_pilot_s + plain_s:.3f} s, cv R={r_cv} "
-              f"{cv_pilot_s + cv_s:.3f} s", file=sys.stderr, flush=True)
+        row = {"h": h}
+        for name, stage, seed0 in (("plain", plain_stage, eval_seed + 3), ("cv", mlp_stage, eval_seed + 4),
+                                   ("cv_linear", lin_stage, eval_seed + 5)):
+            row[name] = sequential(stage, h, seed0)
+        row["speedup"] = row["plain"]["wall_s"] / row["cv"]["wall_s"]
+        row["speedup_linear"] = row["plain"]["wall_s"] / row["cv_linear"]["wall_s"]
+        out["targets"].append(row)
+        print(f"[cv] h={h:.3e}: plain R={row['plain']['R']} {row['plain']['wall_s']:.3f} s "
+              f"ci {row['plain']['ci95']:.3e}; mlp R={row['cv']['R']} {row['cv']['wall_s']:.3f} s "
+              f"ci {row['cv']['ci95']:.3e}; linear R={row['cv_linear']['R']} {row['cv_linear']['wall_s']:.3f} s "
+              f"ci {row['cv_linear']['ci95']:.3e}", file=sys.stderr, flush=True)
     return out
 
 
@@ -549,6 +755,56 @@ def table2_leg(ctx, sim):
     return out
 
 
+def uneven_batch_leg(ctx, sim, heavy_factor: float = 0.0, lanes=None, tune: bool = False):
+    """The uneven workload (256 instances: d ~ U{2..32}, N ~ U{2..50}, T log-uniform in [100, 1e5],
+    4096 replications each) in one sim_run_batch call: wavefront tiles of every instance, heavy
+    instances split over several lanes per replication, longest tiles first, then the per-instance
+    reduction. Wall time of the call to the last statistics read back; device time between the
+    run's HIP events; ALU roofline of the method's algorithmic work over the device time."""
+    import torch
+
+    from paper_2404_11631_amd import workloads
+
+    w = workloads.WORKLOADS["uneven"]
+    batch = workloads.uneven_batch(w["seed"], w["n_instances"], w["R"], w["d_range"], w["n_range"], w["t_range"])
+    probs = [sim.Problem(mu=b.mu, sigma=b.sigma, N=b.N, M=1, precision=sim.FP32, instance_id=b.instance)
+             for b in batch]
+    R = [b.R for b in batch]
+    T = [b.T for b in batch]
+    tuned = None
+    if tune:
+        # the measured plan knob, outside the timed region (cached across runs of the same box)
+        import tempfile
+        t0 = time.perf_counter()
+        tuned = ctx.tune_batch(probs, R, T, seed=w["seed"] + 1, t_scale=16,
+                               cache=os.path.join(tempfile.gettempdir(), "sim_batch_tune.json"))
+        tuned["wall_s"] = time.perf_counter() - t0
+        heavy_factor = tuned["heavy_factor"]
+    # library set-up and buffers: one small batch of the same classes
+    ctx.run_batch(probs[:4], [64] * 4, [100] * 4, seed=1)
+    ctx.batch_stats(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.run_batch(probs, R, T, seed=w["seed"], heavy_factor=heavy_factor, lanes_per_rep=lanes)
+    sts = [ctx.batch_stats(i) for i in range(len(batch))]
+    wall = time.perf_counter() - t0
+    kms = sts[0].kernel_ms
+    plan_P = [ctx.batch_paths(i)["lanes_per_rep"] for i in range(len(batch))]
+    steps = sum(b.R * b.T for b in batch)
+    ops = sum(b.R * b.T * ops_per_path_step(b.d, b.N) for b in batch)
+    heavy = max(range(len(batch)), key=lambda i: batch[i].T * batch[i].N * batch[i].d)
+    return {"workload": "uneven", "instances": len(batch), "R": w["R"], "path_steps": steps,
+            "normals": sum(b.R * b.T * b.N * b.d for b in batch), "wall_s": wall, "kernel_ms": kms,
+            "path_steps_per_s": steps / wall,
+            "roofline": {"bound": "alu", "achieved": ops / (kms * 1e-3) / 1e12, "peak": PEAK_OPS / 1e12,
+                         "unit": "TOP/s", "frac": ops / (kms * 1e-3) / PEAK_OPS},
+            "heavy_factor": heavy_factor or 0.5, "tuner": tuned,
+            "lanes_per_rep_histogram": {str(p): plan_P.count(p) for p in sorted(set(plan_P))},
+            "heaviest_instance": {"i": heavy, "d": batch[heavy].d, "N": batch[heavy].N, "T": batch[heavy].T,
+                                  "lanes_per_rep": plan_P[heavy]},
+            "mean_of_instance_0": sts[0].mean}
+
+
 def uneven_plain(args):
     """The uneven workload (256 instances: d ~ U{2..32}, N ~ U{2..50}, T log-uniform in [100, 1e5],
     4096 replications each) on the plain fused path, instance by instance: four contexts on four
@@ -607,49 +863,87 @@ def uneven_plain(args):
     print(json.dumps(line), flush=True)
 
 
+def stress_cv(ctx, sim, p, T: int, seed: int, R_eval: int = 1 << 20):
+    """The control variate on the stress shape (dense factor, t(3)): the MLP trained on the device
+    from 2^20 simulated pairs, then one estimate over R_eval fresh paths with the aux draws sized as
+    in the paper-scale leg; reports the variance ratio it reaches (the plain mean of the same paths
+    is the judge of its bias)."""
+    t0 = time.perf_counter()
+    fit = ctx.cv_fit(p, T, seed + 1, n_runs=1, epochs=4, R_train=1 << 20, R_pilot=1 << 16, batch=4096, lr=2e-3)
+    train_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    st = ctx.run_cv(p, R_eval, T, seed + 2, 4 * R_eval)
+    wall = time.perf_counter() - t0
+    joint = math.sqrt(st.ci95_plain ** 2 + st.ci95_cv ** 2)
+    print(f"[stress] cv: rho2 {st.rho2:.4f}, variance gain {(st.var_plain / st.R) / st.var_est:.3f}, "
+          f"train {train_s:.1f} s", file=sys.stderr, flush=True)
+    return {"train_pairs": fit.n_train, "train_s": train_s, "train_sim_ms": fit.sim_ms, "train_ms": fit.train_ms,
+            "pilot_rho2": fit.rho2, "beta": st.beta, "R": st.R, "R_aux": st.R_aux, "rho2": st.rho2,
+            "variance_gain": (st.var_plain / st.R) / st.var_est, "mean_plain": st.mean_plain,
+            "ci95_plain": st.ci95_plain, "mean_cv": st.mean_cv, "ci95_cv": st.ci95_cv,
+            "cv_minus_plain_over_joint_ci95": (st.mean_cv - st.mean_plain) / joint, "wall_s": wall,
+            "paths_ms": st.paths_ms, "aux_ms": st.aux_ms,
+            "path_steps_per_s_with_features": st.R * T / (st.paths_ms * 1e-3)}
+
+
+def stress_leg(ctx, sim, R: int, runs: int = 1, warmup: int = 0, cv: bool = True):
+    """The stress workload (d = 64 dense L with Sigma = L L', standardized t(3) noise, N = 100,
+    T = 1e3, R = 1e7 by default) on the dense-L kernel: per iteration the two d x d products
+    v = L'w and g = L h run on the FP32 matrix cores, the normals on the vector ALUs. Reports the
+    device time per run, path-steps/s, the ALU roofline of the method's algorithmic work and the
+    matrix-core share (4 d^2 flops per path-step against the dense FP32 matrix peak)."""
+    import torch
+
+    from paper_2404_11631_amd import workloads
+
+    w = workloads.WORKLOADS["stress"]
+    T, d, N, nu, seed = w["T"], w["d"], w["N"], w["nu"], w["seed"]
+    mu, L = workloads.dense_instance(seed, 0, d)
+    p = sim.Problem(mu=mu, chol=L, N=N, M=w["M"], noise=sim.NOISE_T, nu=nu, checkpoints=w["checkpoints"])
+    for k in range(warmup):
+        ctx.run(p, min(R, 1 << 20), T, seed + 1000 + k)
+        ctx.stats()
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    for k in range(runs):
+        ctx.run(p, R, T, seed + k)
+        st = ctx.stats()
+        kernel_ms.append(st.kernel_ms)
+        print(f"[stress] run {k}: R={R} {st.kernel_ms:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kavg = sum(kernel_ms) / len(kernel_ms)
+    alg = ops_per_path_step_dense(d, N, nu) * R * T
+    mfma = 4.0 * d * d * R * T
+    cv_out = stress_cv(ctx, sim, p, T, seed) if cv else None
+    return {"cv": cv_out, "workload": "stress", "R": R, "T": T, "d": d, "N": N, "noise": f"t({nu})", "L": "dense lower-triangular",
+            "seed": seed, "runs": runs, "wall_s": wall, "kernel_ms": kavg, "path_steps_per_s": R * T * runs / wall,
+            "roofline": {"bound": "alu", "achieved": alg / (kavg * 1e-3) / 1e12, "peak": PEAK_OPS / 1e12,
+                         "unit": "TOP/s", "frac": alg / (kavg * 1e-3) / PEAK_OPS,
+                         "ops_per_path_step": ops_per_path_step_dense(d, N, nu)},
+            "mfma": {"achieved": mfma / (kavg * 1e-3) / 1e12, "peak": PEAK_F32_MFMA / 1e12, "unit": "TFLOP/s",
+                     "frac": mfma / (kavg * 1e-3) / PEAK_F32_MFMA, "flops_per_path_step": 4 * d * d},
+            "stats": {"mean": st.mean, "ci95_halfwidth": st.ci95_halfwidth,
+                      "decision_total_origin": int(st.decision_total[0])}}
+
+
 def stress(args):
-    """The stress workload: d = 64 dense L (Sigma = L L'), standardized t(3) noise, N = 100, T = 1e3,
-    R = 1e7 (or --reps); the two d x d products per iteration run on the matrix cores."""
+    """The stress workload alone (see stress_leg), one JSON line."""
     import torch
 
     from paper_2404_11631_amd import sim, workloads
 
     w = workloads.WORKLOADS["stress"]
-    R = args.reps or w["R"]
-    T, d, N, nu, seed = w["T"], w["d"], w["N"], w["nu"], w["seed"]
-    mu, L = workloads.dense_instance(seed, 0, d)
     torch.cuda.init()
-    stream = torch.cuda.current_stream()
-    ctx = sim.Sim(0, stream.cuda_stream)
-    p = sim.Problem(mu=mu, chol=L, N=N, M=w["M"], noise=sim.NOISE_T, nu=nu, checkpoints=w["checkpoints"])
-    for k in range(args.warmup):
-        ctx.run(p, R, T, seed + 1000 + k)
-        ctx.stats()
-    torch.cuda.synchronize()
-    kernel_ms = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ctx.run(p, R, T, seed + k)
-        st = ctx.stats()
-        kernel_ms.append(st.kernel_ms)
-        print(f"[stress] step {k}: {st.kernel_ms:.1f} ms", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    ctx = sim.Sim(0, torch.cuda.current_stream().cuda_stream)
+    leg = stress_leg(ctx, sim, args.reps or w["R"], max(1, args.steps), args.warmup)
     ctx.close()
-    kavg = sum(kernel_ms) / len(kernel_ms)
-    alg = ops_per_path_step_dense(d, N, nu) * R * T
-    line = {
-        "metric": "path-steps/s, dense-L t(3) stress workload",
-        "value": R * T * args.steps / wall, "unit": "path-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "stress", "R": R, "T": T, "d": d, "N": N, "noise": f"t({nu})",
-                   "L": "dense lower-triangular", "seed": seed},
-        "roofline": {"bound": "alu", "achieved": alg / (kavg * 1e-3) / 1e12, "peak": PEAK_OPS / 1e12,
-                     "unit": "TOP/s", "frac": alg / (kavg * 1e-3) / PEAK_OPS, "traffic": None,
-                     "kernel_ms": kavg, "ops_per_path_step": ops_per_path_step_dense(d, N, nu)},
-        "stats": {"mean": st.mean, "ci95_halfwidth": st.ci95_halfwidth},
-    }
+    line = {"metric": "path-steps/s, dense-L t(3) stress workload", "value": leg["path_steps_per_s"],
+            "unit": "path-steps/s", "n_gpus": 1, "steps": leg["runs"], "warmup": args.warmup,
+            "ms_per_step": 1e3 * leg["wall_s"] / leg["runs"], "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic", "config": {k: leg[k] for k in ("workload", "R", "T", "d", "N", "noise", "L", "seed")},
+            "roofline": leg["roofline"], "mfma": leg["mfma"], "stats": leg["stats"], "cv": leg["cv"]}
     print(json.dumps(line), flush=True)
 
 
