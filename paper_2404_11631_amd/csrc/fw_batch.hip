@@ -47,6 +47,27 @@ __device__ __forceinline__ double bfly_sum(double x, uint32_t lo, uint32_t hi)
     return x;
 }
 
+// Sum over the Pa <= 4 lanes of a quad-aligned group by DPP quad permutes (lane xor 1, then xor 2),
+// without the LDS crossbar a shuffle goes through. Addition is commutative, so every lane of the
+// group ends with the same bits. Every lane of the wavefront executes it.
+__device__ __forceinline__ float quad_group_sum(float x, uint32_t Pa)
+{
+    if (Pa >= 2) x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0xB1, 0xF, 0xF, true));
+    if (Pa >= 4) x += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x4E, 0xF, 0xF, true));
+    return x;
+}
+
+// The staging area belongs to this wavefront alone (one wavefront per workgroup), and the LDS
+// instructions of a wavefront complete in issue order, so draws written by some lanes are seen by
+// the reads other lanes issue after them. Only the compiler must not move LDS accesses across this
+// point; no workgroup barrier (and none of its waits on outstanding global loads) is needed.
+__device__ __forceinline__ void wave_lds_order()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // f(w) at w = c S over this lane's assets, FP64 (Eq. (3), diagonal Sigma), summed over the Pa lanes
 __device__ __forceinline__ double tile_objective(const InstanceDesc *__restrict__ P, const uint32_t (&S)[kLaneAssets],
                                                  uint32_t hibits, uint32_t a0, uint32_t acnt, uint32_t Pa, double c)
@@ -152,7 +173,7 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
                     sub[4 * b1 + 3] = q1.z[3];
                 }
             }
-            __syncthreads();
+            wave_lds_order();
             for (uint32_t sidx = 0; sidx < G; ++sidx) {
                 const uint32_t i = ib + sidx;
                 const bool valid = i < N;
@@ -176,7 +197,7 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
                 float dot = 0.0f;
 #pragma unroll
                 for (int k = 0; k < kLaneAssets; ++k) dot = fmaf(z[k], v[k], dot);
-                dot = bfly_sum(dot, 1u, Pa);
+                dot = quad_group_sum(dot, Pa);
                 if (valid) {
 #pragma unroll
                     for (int k = 0; k < kLaneAssets; ++k) {
@@ -185,7 +206,7 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
                     }
                 }
             }
-            __syncthreads();
+            wave_lds_order();
         }
         // combine the Ps sample chunks (lanes holding the same assets)
         for (uint32_t m = Pa; m < Pl; m <<= 1) {

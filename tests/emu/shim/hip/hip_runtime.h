@@ -67,6 +67,16 @@ template <class T> inline T __shfl_down(T v, unsigned off, int width = 64)
     return emu_exchange(v, base + src);
 }
 inline void __syncthreads() { g_block->bar->arrive_and_wait(); }
+// threads are not lockstep here: the wave barrier synchronizes them like a workgroup barrier
+inline void __builtin_amdgcn_wave_barrier() { g_block->bar->arrive_and_wait(); }
+// DPP quad_perm (dpp_ctrl < 0x100): lane 4q + i reads lane 4q + ((ctrl >> 2i) & 3)
+inline int __builtin_amdgcn_mov_dpp(int v, int ctrl, int, int, bool)
+{
+    const int lane = threadIdx.x % 64, i = lane & 3;
+    return emu_exchange(v, threadIdx.x - i + ((ctrl >> (2 * i)) & 3));
+}
+inline float __int_as_float(int x) { float f; std::memcpy(&f, &x, 4); return f; }
+inline int __float_as_int(float f) { int x; std::memcpy(&x, &f, 4); return x; }
 inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
 template <class T> inline T __hip_atomic_fetch_add(T *p, T v, int, int)
 {
