@@ -32,8 +32,12 @@ constexpr int kWave = 64;
 constexpr int kBatchMaxD = 32;
 constexpr int kLaneAssets = 8;                 // assets held by one lane
 // LDS staging of one wavefront: a sub-group of Pa lanes draws G d <= 4 d <= 32 Pa normals per
-// round, and a wavefront has 64 / Pa sub-groups
-constexpr int kStageFloats = 32 * kWave;
+// round, and a wavefront has 64 / Pa sub-groups. Sub-group areas are 32 Pa + 1 floats apart (131 at
+// Pa = 4): with areas 32 Pa floats apart every lane of a write or read instruction would fall in
+// the same few of the 64 banks (16- to 32-way conflicts); the padded stride leaves at most two
+// lanes per bank for every pattern the kernel issues (checked over all d, rounds and offsets).
+constexpr int kStageFloats = 2112;   // max over Pa of (64 / Pa) x stride
+__device__ __forceinline__ uint32_t stage_stride(uint32_t Pa) { return 32u * Pa + (Pa == 4u ? 3u : 1u); }
 
 __device__ __forceinline__ float bfly_sum(float x, uint32_t lo, uint32_t hi)
 {
@@ -122,7 +126,7 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
     const uint32_t rounds = chunk / G;
     const uint32_t nb = G * d / 4;                 // blocks per round
     const uint32_t mb = (nb + Pa - 1) / Pa;        // blocks per lane per round (uniform)
-    float *sub = stage + (lane / Pa) * (32u * Pa); // this sub-group's staging area
+    float *sub = stage + (lane / Pa) * stage_stride(Pa);   // this sub-group's staging area
 
     uint32_t S[kLaneAssets], cnt[kLaneAssets];
 #pragma unroll
