@@ -282,6 +282,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0)
     ap.add_argument("--no-cv", action="store_true", help="skip the control-variate leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--no-parity", action="store_true", help="skip the statistics-error leg")
     ap.add_argument("--no-stress", action="store_true", help="skip the stress leg")
     ap.add_argument("--cv-train-runs", type=int, default=10, help="training simulations of 1e6 paths")
     ap.add_argument("--cv-epochs", type=int, default=4)
@@ -354,7 +355,7 @@ def main():
         kernel_ms.append(st.kernel_ms)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    par = parity_leg(ctx, sim, w, mu, sigma)
+    par = {} if args.no_parity else parity_leg(ctx, sim, w, mu, sigma)
     cv = None if args.no_cv else cv_leg(ctx, sim, w, mu, sigma, args)
     shape = None if args.no_paper_shape else paper_shape_leg(ctx, sim, 2, 1)
     nv_shape = None if args.no_paper_shape else newsvendor_shape_leg(ctx, sim, 2, 1)

@@ -116,15 +116,22 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
     const uint32_t nu = P->nu;
     const bool logged = leader && (P->flags & 2u) && (static_cast<uint64_t>(r) - P->log_begin) < P->log_count;
 
-    // rounds of G samples hold a whole number of Philox blocks; lane chunks are whole rounds
+    // G = 4/gcd(d,4) samples hold a whole number of Philox blocks; lane chunks start on such a
+    // group. A round is the largest multiple of G samples whose normals fit the sub-group's 32 Pa
+    // floats of staging: the blocks a round does not divide evenly among the Pa lanes (drawn and
+    // discarded) are then a small share of its draws.
     const uint32_t G = (d & 3u) == 0 ? 1u : ((d & 1u) == 0 ? 2u : 4u);
     const uint32_t align = tnoise ? 4u : G;
     const uint32_t Ps = Pl / Pa;
     uint32_t chunk = (N + Ps - 1) / Ps;
     chunk = (chunk + align - 1) / align * align;
     const uint32_t i0 = ps * chunk;
-    const uint32_t rounds = chunk / G;
-    const uint32_t nb = G * d / 4;                 // blocks per round
+    const uint32_t i_end = (i0 + chunk < N) ? i0 + chunk : N;   // this lane's samples: [i0, i_end)
+    uint32_t Gr = (32u * Pa) / d / G * G;
+    Gr = Gr < G ? G : Gr;
+    Gr = Gr > chunk ? chunk : Gr;                  // chunk is a multiple of G
+    const uint32_t rounds = (chunk + Gr - 1) / Gr;
+    const uint32_t nb = Gr * d / 4;                // blocks per round
     const uint32_t mb = (nb + Pa - 1) / Pa;        // blocks per lane per round (uniform)
     float *sub = stage + (lane / Pa) * stage_stride(Pa);   // this sub-group's staging area
 
@@ -157,7 +164,7 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
 
         const PhiloxRow row = philox_row(epoch, r, k0);
         for (uint32_t rd = 0; rd < rounds; ++rd) {
-            const uint32_t ib = i0 + rd * G;                 // first sample of the round
+            const uint32_t ib = i0 + rd * Gr;                // first sample of the round
             const uint32_t blk0 = ib * d / 4;                // its first Philox block
             // draw: blocks pa, pa + Pa, ... of the round, two at a time
             for (uint32_t m = 0; m < mb; m += 2) {
@@ -178,9 +185,9 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
                 }
             }
             wave_lds_order();
-            for (uint32_t sidx = 0; sidx < G; ++sidx) {
+            for (uint32_t sidx = 0; sidx < Gr; ++sidx) {
                 const uint32_t i = ib + sidx;
-                const bool valid = i < N;
+                const bool valid = i < i_end;
                 float z[kLaneAssets];
                 const float *src = sub + sidx * d + a0;
 #pragma unroll

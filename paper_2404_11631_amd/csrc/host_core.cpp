@@ -698,10 +698,11 @@ static int check_plan(char *err, uint32_t n_inst, const sim_params *p, const uin
         const uint32_t Ps = L / tl.Pa;
         const uint64_t chunk = chunk_of(pi.n_samples, pi.d, Ps, tn);
         if (chunk * Ps < pi.n_samples) return fail(err, SIM_EINVAL, "plan: tile %llu leaves samples out", (unsigned long long)q);
-        // highest normal a lane draws: its chunk's numerators (one block past the last round with
-        // the second of a pair), and the chi-square normals of its chunk
-        const uint64_t top = (uint64_t)pi.n_samples * pi.d + (tn ? (chunk * Ps + 1) * pi.nu : 0) +
-                             chunk * Ps * pi.d + 4 * (2 * tl.Pa + 1);
+        // highest normal a lane draws: its chunk's numerators with the overrun of its last round
+        // (at most 32 Pa normals) and the second block of a pair, and the chi-square normals of
+        // the same samples
+        const uint64_t top = (uint64_t)pi.n_samples * pi.d + (tn ? (chunk * Ps + 32 * tl.Pa + 1) * pi.nu : 0) +
+                             chunk * Ps * pi.d + 32 * tl.Pa + 4 * (2 * tl.Pa + 1);
         if (top > 0xFFFFFFFFull) return fail(err, SIM_EINVAL, "plan: tile %llu numbers normals past 2^32", (unsigned long long)q);
         reps[tl.inst] += tl.nrep;
     }
