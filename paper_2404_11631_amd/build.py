@@ -63,12 +63,16 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-def build_probe() -> str:
-    """The stand-alone issue-rate probe behind the ALU roofline figures (not part of the library)."""
-    probe = os.path.join(HERE, "valu_rate_probe")
-    subprocess.check_call([hipcc()] + flags() + ["-o", probe + ".tmp", os.path.join(HERE, "csrc", "valu_rate_probe.hip")])
-    os.replace(probe + ".tmp", probe)
-    return probe
+def build_probe() -> list:
+    """The stand-alone probes behind the roofline figures (not part of the library): VALU issue
+    rates, and the cost of a dependent kernel launch."""
+    out = []
+    for name in ("valu_rate_probe", "launch_floor_probe"):
+        probe = os.path.join(HERE, name)
+        subprocess.check_call([hipcc()] + flags() + ["-o", probe + ".tmp", os.path.join(HERE, "csrc", name + ".hip")])
+        os.replace(probe + ".tmp", probe)
+        out.append(probe)
+    return out
 
 
 if __name__ == "__main__":

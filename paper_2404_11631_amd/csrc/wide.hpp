@@ -53,6 +53,37 @@ struct WideEpoch {
     uint32_t par;                               // buffer of the iteration's workgroup partials (t & 1)
 };
 
+// The launches of a run of T iterations (resample every M; N samples, or n_schedule[epoch]): for each
+// t, iter(t, epoch, E, cw, from_w0, fold_prev) (w_t = cw S, w_0 at t = 0 when from_w0; fold_prev: the
+// sample launch first takes the step of iteration t - 1); step(t) where that step cannot wait for
+// the next iteration (an objective evaluation follows, or t is the last iteration); objective(c, slot)
+// at w = c S for every checkpoint equal to t + 1. Each callback returns 0 or an error, which ends the
+// sequence and is returned.
+template <class Iter, class Step, class Objective>
+int wide_sequence(uint32_t N, const uint32_t *n_schedule, uint64_t M, uint64_t T, bool has_w0, uint32_t n_ckpt,
+                  const uint64_t *checkpoints, Iter iter, Step step, Objective objective)
+{
+    uint32_t ck = 0;
+    bool pending = false;
+    for (uint64_t t = 0; t < T; ++t) {
+        const float cw = t == 0 ? 0.0f : static_cast<float>(2.0 / (static_cast<double>(t) * static_cast<double>(t + 1)));
+        const uint64_t e = t / M;
+        const uint32_t Ne = n_schedule ? n_schedule[e] : N;
+        const WideEpoch E{Ne, static_cast<float>(1.0 / Ne), static_cast<float>(static_cast<double>(N) / Ne),
+                          static_cast<float>((N - 1.0) / (Ne - 1.0)), static_cast<uint32_t>(t & 1)};
+        if (int rc = iter(t, static_cast<uint32_t>(e), E, cw, t == 0 && has_w0, pending)) return rc;
+        const bool objective_next = ck < n_ckpt && checkpoints[ck] == t + 1;
+        pending = !(objective_next || t + 1 == T);
+        if (!pending)
+            if (int rc = step(t)) return rc;
+        while (ck < n_ckpt && checkpoints[ck] == t + 1) {
+            if (int rc = objective(2.0 / (static_cast<double>(t + 1) * static_cast<double>(t + 2)), ck)) return rc;
+            ++ck;
+        }
+    }
+    return 0;
+}
+
 // One iteration without its step (sample, dot, gradient): w_t = cw S (or w_0 at t = 0 when from_w0),
 // epoch = t div M of size E; with fold_prev the sample launch first takes the step of iteration t - 1.
 int launch_wide_iteration(const WideArgs &A, uint64_t t, uint32_t epoch, const WideEpoch &E, float cw, bool from_w0,

@@ -147,30 +147,25 @@ int sim_run_wide(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint
     HIP_TRY(ctx, hipStreamSynchronize(st));
 
     const fw::WideArgs A = wide_args(w, p, R, T, seed);
-    const uint64_t M = p->resample_every;
     HIP_TRY(ctx, hipEventRecord(w.ev0, st));
     // The step of iteration t runs inside the next iteration's sample launch unless an objective
     // evaluation needs the updated signature first or t is the last iteration.
-    uint32_t ck = 0;
-    bool pending = false;
-    for (uint64_t t = 0; t < T; ++t) {
-        const float cw = t == 0 ? 0.0f : static_cast<float>(2.0 / (static_cast<double>(t) * static_cast<double>(t + 1)));
-        const uint64_t e = t / M;
-        const uint32_t Ne = p->n_schedule ? p->n_schedule[e] : N;
-        const fw::WideEpoch E{Ne, static_cast<float>(1.0 / Ne), static_cast<float>(static_cast<double>(N) / Ne),
-                              static_cast<float>((N - 1.0) / (Ne - 1.0)), static_cast<uint32_t>(t & 1)};
-        if (fw::launch_wide_iteration(A, t, static_cast<uint32_t>(e), E, cw, t == 0 && p->w0 != nullptr, pending, st))
-            return set_err(ctx, SIM_EDEVICE, "wide launch failed at t=%llu", (unsigned long long)t);
-        const bool objective_next = ck < nc && p->checkpoints[ck] == t + 1;
-        pending = !(objective_next || t + 1 == T);
-        if (!pending && fw::launch_wide_step(A, t, st))
-            return set_err(ctx, SIM_EDEVICE, "wide step launch failed at t=%llu", (unsigned long long)t);
-        while (ck < nc && p->checkpoints[ck] == t + 1) {
-            const double c = 2.0 / (static_cast<double>(t + 1) * static_cast<double>(t + 2));
-            if (fw::launch_wide_objective(A, c, ck, st)) return set_err(ctx, SIM_EDEVICE, "wide objective launch failed");
-            ++ck;
-        }
-    }
+    const int lrc = fw::wide_sequence(
+        N, p->n_schedule, p->resample_every, T, p->w0 != nullptr, nc, p->checkpoints,
+        [&](uint64_t t, uint32_t e, const fw::WideEpoch &E, float cw, bool from_w0, bool fold_prev) {
+            return fw::launch_wide_iteration(A, t, e, E, cw, from_w0, fold_prev, st)
+                       ? set_err(ctx, SIM_EDEVICE, "wide launch failed at t=%llu", (unsigned long long)t)
+                       : 0;
+        },
+        [&](uint64_t t) {
+            return fw::launch_wide_step(A, t, st)
+                       ? set_err(ctx, SIM_EDEVICE, "wide step launch failed at t=%llu", (unsigned long long)t)
+                       : 0;
+        },
+        [&](double c, uint32_t slot) {
+            return fw::launch_wide_objective(A, c, slot, st) ? set_err(ctx, SIM_EDEVICE, "wide objective launch failed") : 0;
+        });
+    if (lrc) return lrc;
     if (fw::launch_wide_objective(A, 2.0 / (static_cast<double>(T) * static_cast<double>(T + 1)), nc, st) ||
         fw::launch_wide_finalize(A, nc, st))
         return set_err(ctx, SIM_EDEVICE, "wide finalize launch failed");

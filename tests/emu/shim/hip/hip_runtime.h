@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <algorithm>
 #include <functional>
+#include <memory>
 #include <thread>
 #include <vector>
 
@@ -20,6 +22,8 @@
 #define __HIP_MEMORY_SCOPE_AGENT 0
 
 struct Dim3emu { unsigned x, y, z; };
+struct float4 { float x, y, z, w; };
+inline float4 make_float4(float x, float y, float z, float w) { return float4{x, y, z, w}; }
 extern thread_local Dim3emu threadIdx;
 extern thread_local Dim3emu blockIdx;
 typedef int hipError_t;
@@ -33,19 +37,24 @@ template <class F> hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int *
 // lockstep exchange for shuffles: every thread of the block calls the shuffle at the same point
 struct EmuBlock {
     int nthreads;
-    std::barrier<> *bar;
+    std::barrier<> *bar;                  // the workgroup (__syncthreads)
     std::vector<uint64_t> slot;
+    std::vector<std::barrier<> *> wave;   // one per wavefront of 64 threads (shuffles)
+    std::vector<std::barrier<> *> half;   // one per half wavefront (width-32 shuffles)
 };
 extern EmuBlock *g_block;
 
-template <class T> inline T emu_exchange(T v, int src)
+// Every lane of the group a shuffle spans takes part in it: the wavefront, or the half wavefront for
+// width-32 shuffles (kernels whose half wavefronts follow control flow of their own).
+template <class T> inline T emu_exchange(T v, int src, int width = 64)
 {
     uint64_t bits = 0;
     std::memcpy(&bits, &v, sizeof(T));
+    std::barrier<> *b = width == 32 ? g_block->half[threadIdx.x / 32] : g_block->wave[threadIdx.x / 64];
     g_block->slot[threadIdx.x] = bits;
-    g_block->bar->arrive_and_wait();
+    b->arrive_and_wait();
     uint64_t got = g_block->slot[src];
-    g_block->bar->arrive_and_wait();
+    b->arrive_and_wait();
     T out;
     std::memcpy(&out, &got, sizeof(T));
     return out;
@@ -53,18 +62,18 @@ template <class T> inline T emu_exchange(T v, int src)
 template <class T> inline T __shfl(T v, int src, int width = 64)
 {
     int base = threadIdx.x / width * width;
-    return emu_exchange(v, base + (src % width));
+    return emu_exchange(v, base + (src % width), width);
 }
 template <class T> inline T __shfl_xor(T v, unsigned m, int width = 64)
 {
     int lane = threadIdx.x % width, base = threadIdx.x - lane;
-    return emu_exchange(v, base + ((lane ^ m) % width));
+    return emu_exchange(v, base + ((lane ^ m) % width), width);
 }
 template <class T> inline T __shfl_down(T v, unsigned off, int width = 64)
 {
     int lane = threadIdx.x % width, base = threadIdx.x - lane;
     int src = lane + (int)off < width ? lane + (int)off : lane;
-    return emu_exchange(v, base + src);
+    return emu_exchange(v, base + src, width);
 }
 inline void __syncthreads() { g_block->bar->arrive_and_wait(); }
 // threads are not lockstep here: the wave barrier synchronizes them like a workgroup barrier
@@ -78,6 +87,7 @@ inline int __builtin_amdgcn_mov_dpp(int v, int ctrl, int, int, bool)
 inline float __int_as_float(int x) { float f; std::memcpy(&f, &x, 4); return f; }
 inline int __float_as_int(float f) { int x; std::memcpy(&x, &f, 4); return x; }
 inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
+inline void __builtin_amdgcn_fence(int, const char *) { std::atomic_thread_fence(std::memory_order_seq_cst); }
 template <class T> inline T __hip_atomic_fetch_add(T *p, T v, int, int)
 {
     return std::atomic_ref<T>(*p).fetch_add(v);
@@ -107,14 +117,23 @@ using std::fma; using std::fmin; using std::fmax; using std::sqrt; using std::lo
 inline float fmaf(float a, float b, float c) { return std::fma(a, b, c); }
 
 // runs kernel body f on a block of n threads in lockstep
-inline void emu_run_block(int n, unsigned bx, const std::function<void()> &f)
+inline void emu_run_block(int n, unsigned bx, const std::function<void()> &f, unsigned by = 0)
 {
     std::barrier<> bar(n);
-    EmuBlock blk{n, &bar, std::vector<uint64_t>(n)};
+    std::vector<std::unique_ptr<std::barrier<>>> waves;
+    EmuBlock blk{n, &bar, std::vector<uint64_t>(n), {}};
+    for (int w = 0; w < (n + 63) / 64; ++w) {
+        waves.emplace_back(new std::barrier<>(std::min(64, n - 64 * w)));
+        blk.wave.push_back(waves.back().get());
+    }
+    for (int h = 0; h < (n + 31) / 32; ++h) {
+        waves.emplace_back(new std::barrier<>(std::min(32, n - 32 * h)));
+        blk.half.push_back(waves.back().get());
+    }
     g_block = &blk;
     std::vector<std::thread> th;
     for (int i = 0; i < n; ++i)
-        th.emplace_back([&, i] { threadIdx = {(unsigned)i, 0, 0}; blockIdx = {bx, 0, 0}; f(); });
+        th.emplace_back([&, i] { threadIdx = {(unsigned)i, 0, 0}; blockIdx = {bx, by, 0}; f(); });
     for (auto &t : th) t.join();
     g_block = nullptr;
 }
