@@ -159,6 +159,16 @@ typedef struct {
  * for the null stream). */
 int sim_create(int device, void *hip_stream, sim_ctx **out);
 
+/* sim_create with a cap on the context's device memory: every buffer later calls allocate for it
+ * (per-path records, partial sums, staging of every path) may total at most workspace_bytes
+ * (0: no cap). A call that would go past it returns SIM_ENOMEM before launching anything and leaves
+ * the context as it was, usable with smaller inputs. SIM_ENOMEM here also when the context's own
+ * set-up buffers do not fit. */
+int sim_create_ex(int device, void *hip_stream, uint64_t workspace_bytes, sim_ctx **out);
+
+/* The bytes of device memory the context's buffers hold now. */
+int sim_workspace_bytes(sim_ctx *ctx, uint64_t *used);
+
 /* Replaces the stream later calls launch on. */
 int sim_set_stream(sim_ctx *ctx, void *hip_stream);
 
@@ -169,6 +179,27 @@ int sim_set_stream(sim_ctx *ctx, void *hip_stream);
  * FP64; a dense factor with d = 32 or 64, FP32, T <= 65535. Others return SIM_EUNSUPPORTED (many
  * assets on a few replications: sim_run_wide). */
 int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed);
+
+/* sim_run with its results in caller device memory (for instance tensors of the caller's framework)
+ * instead of the context's, launched on the context's stream (sim_set_stream):
+ *   f_ckpt  [n_checkpoints][R] f(w_c) per path (may be NULL when n_checkpoints == 0);
+ *   stats_f [(1 + 2 n_checkpoints) * 5 + 2] and stats_i [d + 3]: the FP64 reduction fields and the
+ *           decision totals, hitting count and hitting-step sum, in sim_run_noalloc's layouts
+ *           (sim_stats_from_raw turns host copies of them into sim_stats_out).
+ * Partial sums and the per-path records that flags ask for stay in the context; sim_paths serves
+ * the records as after sim_run (with f_ckpt NULL), and sim_stats returns SIM_ESTATE until the next
+ * sim_run. The caller's buffers must stay valid until the stream has passed the run. Same shapes,
+ * checks and errors as sim_run. */
+int sim_run_into(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed, double *f_ckpt,
+                 double *stats_f, uint64_t *stats_i);
+
+/* Draws an instance's mu[d] and sigma[d] from `seed` on the host: SIM_REGIME_UNIT, mu_j and sigma_j
+ * ~ U(0, 1); SIM_REGIME_PAPER, Section 4.1's mu_j ~ U(-1, 1) and sigma_j ~ U(0, 0.025). The
+ * generator is SplitMix64 (Steele, Lea and Flood, 2014), 53-bit uniforms, all of mu before sigma.
+ * Returns SIM_EINVAL for d = 0, NULL outputs or an unknown regime. */
+#define SIM_REGIME_UNIT 0
+#define SIM_REGIME_PAPER 1
+int sim_param_gen(uint32_t d, int regime, uint64_t seed, double *mu, double *sigma);
 
 /* Checks a parameter set exactly as sim_run does, without a device. Returns 0 or the code sim_run
  * would return, and writes the reason into msg (may be NULL). */

@@ -120,6 +120,9 @@ struct sim_ctx {
     bool last_diag = true;
     uint64_t R = 0, T = 0;
     int kernel_width = 0;
+    uint64_t ws_limit = 0;                // sim_create_ex: cap on the bytes of the context's buffers (0: none)
+    uint64_t ws_used = 0;                 // bytes the context's buffers hold now
+    bool last_into = false;               // the last sim_run wrote its statistics to caller memory
     BatchState batch;
     CvState cv;
     WideState wide;
@@ -130,7 +133,13 @@ struct sim_ctx {
 
 namespace fw {
 namespace host {
-int run_impl(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed, uint32_t internal);
+// Caller device memory for a run's outputs (sim_run_into); NULL members use the context's buffers.
+struct RunInto {
+    double *fck = nullptr, *final_f = nullptr;
+    uint64_t *final_i = nullptr;
+};
+int run_impl(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed, uint32_t internal,
+             const RunInto *into = nullptr);
 int set_err(sim_ctx *ctx, int code, const char *fmt, ...);
 int ensure(sim_ctx *ctx, DevBuf &b, size_t bytes);
 void free_buf(DevBuf &b);

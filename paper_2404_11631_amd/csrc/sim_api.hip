@@ -29,8 +29,12 @@ int ensure(sim_ctx *ctx, DevBuf &b, size_t bytes)
 {
     if (bytes == 0) bytes = 8;
     if (b.bytes >= bytes) return SIM_OK;
+    if (ctx->ws_limit && ctx->ws_used - b.bytes + bytes > ctx->ws_limit)
+        return set_err(ctx, SIM_ENOMEM, "the context's workspace limit of %llu bytes cannot hold a buffer of %zu bytes "
+                       "(%llu in use)", (unsigned long long)ctx->ws_limit, bytes, (unsigned long long)ctx->ws_used);
     if (b.ptr) {
         HIP_TRY(ctx, hipFree(b.ptr));
+        ctx->ws_used -= b.bytes;
         b.ptr = nullptr;
         b.bytes = 0;
     }
@@ -40,6 +44,7 @@ int ensure(sim_ctx *ctx, DevBuf &b, size_t bytes)
         return set_err(ctx, SIM_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
     b.bytes = bytes;
+    ctx->ws_used += bytes;
     return SIM_OK;
 }
 
@@ -109,6 +114,56 @@ int sim_create(int device, void *hip_stream, sim_ctx **out)
     if (hipMemset(ctx->done.ptr, 0, 64) != hipSuccess) return fail(SIM_EDEVICE);
     if (hipDeviceSynchronize() != hipSuccess) return fail(SIM_EDEVICE);
     *out = ctx;
+    return SIM_OK;
+}
+
+int sim_create_ex(int device, void *hip_stream, uint64_t workspace_bytes, sim_ctx **out)
+{
+    const int rc = sim_create(device, hip_stream, out);
+    if (rc) return rc;
+    sim_ctx *ctx = *out;
+    if (workspace_bytes && ctx->ws_used > workspace_bytes) {
+        sim_destroy(ctx);
+        *out = nullptr;
+        return SIM_ENOMEM;
+    }
+    ctx->ws_limit = workspace_bytes;
+    return SIM_OK;
+}
+
+int sim_param_gen(uint32_t d, int regime, uint64_t seed, double *mu, double *sigma)
+{
+    if (d == 0 || !mu || !sigma) return SIM_EINVAL;
+    double lo_mu, hi_mu, hi_sig;
+    if (regime == SIM_REGIME_UNIT) {
+        lo_mu = 0.0;
+        hi_mu = 1.0;
+        hi_sig = 1.0;
+    } else if (regime == SIM_REGIME_PAPER) {
+        lo_mu = -1.0;
+        hi_mu = 1.0;
+        hi_sig = 0.025;
+    } else {
+        return SIM_EINVAL;
+    }
+    // SplitMix64 (Steele, Lea and Flood, 2014); the top 53 bits give a uniform on [0, 1)
+    uint64_t x = seed;
+    auto next = [&x]() {
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return static_cast<double>((z ^ (z >> 31)) >> 11) * 0x1.0p-53;
+    };
+    for (uint32_t j = 0; j < d; ++j) mu[j] = lo_mu + (hi_mu - lo_mu) * next();
+    for (uint32_t j = 0; j < d; ++j) sigma[j] = hi_sig * next();
+    return SIM_OK;
+}
+
+int sim_workspace_bytes(sim_ctx *ctx, uint64_t *used)
+{
+    if (!ctx || !used) return SIM_EINVAL;
+    *used = ctx->ws_used;
     return SIM_OK;
 }
 
@@ -187,7 +242,8 @@ namespace host {
 
 // One run of Algorithm 1 over R replications; `internal` adds descriptor flag bits the public
 // flags do not carry (kFlagYOnly).
-int run_impl(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed, uint32_t internal)
+int run_impl(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed, uint32_t internal,
+             const RunInto *into)
 {
     if (!ctx) return SIM_EINVAL;
     int rc = validate(ctx->err, p, R, T);
@@ -253,7 +309,7 @@ int run_impl(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t
 
     RunBuffers &B = ctx->bufs;
     B.y = want_y ? (double *)ctx->y.ptr : nullptr;
-    B.fck = (double *)ctx->fck.ptr;
+    B.fck = (into && into->fck) ? into->fck : (double *)ctx->fck.ptr;
     B.cnt = keep ? (uint32_t *)ctx->cnt.ptr : nullptr;
     B.wsum = keep ? (uint64_t *)ctx->wsum.ptr : nullptr;
     B.tau = keep ? (uint32_t *)ctx->tau.ptr : nullptr;
@@ -262,8 +318,8 @@ int run_impl(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t
     B.part_f = (double *)ctx->part_f.ptr;
     B.part_i = (uint64_t *)ctx->part_i.ptr;
     B.done = (uint32_t *)ctx->done.ptr;
-    B.final_f = (double *)ctx->final_f.ptr;
-    B.final_i = (uint64_t *)ctx->final_i.ptr;
+    B.final_f = (into && into->final_f) ? into->final_f : (double *)ctx->final_f.ptr;
+    B.final_i = (into && into->final_i) ? into->final_i : (uint64_t *)ctx->final_i.ptr;
     B.nblocks = nblocks;
     B.n_streams = n_streams;
     B.dense_g = dense ? (const float *)ctx->dense.ptr : nullptr;
@@ -300,6 +356,7 @@ int run_impl(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t
     ctx->T = T;
     ctx->kernel_width = width;
     ctx->have_run = true;
+    ctx->last_into = into != nullptr;
     return SIM_OK;
 }
 
@@ -313,10 +370,25 @@ int sim_run(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t 
     return run_impl(ctx, p, R, T, seed, 0u);
 }
 
+int sim_run_into(sim_ctx *ctx, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed, double *f_ckpt,
+                 double *stats_f, uint64_t *stats_i)
+{
+    if (!ctx) return SIM_EINVAL;
+    if (!p || !stats_f || !stats_i) return set_err(ctx, SIM_EINVAL, "params, stats_f and stats_i are required");
+    if (p->n_checkpoints && !f_ckpt) return set_err(ctx, SIM_EINVAL, "f_ckpt is required with checkpoints");
+    fw::host::RunInto into;
+    into.fck = p->n_checkpoints ? f_ckpt : nullptr;
+    into.final_f = stats_f;
+    into.final_i = stats_i;
+    return run_impl(ctx, p, R, T, seed, 0u, &into);
+}
+
 int sim_stats(sim_ctx *ctx, sim_stats_out *out)
 {
     if (!ctx || !out) return SIM_EINVAL;
     if (!ctx->have_run) return set_err(ctx, SIM_ESTATE, "no run yet");
+    if (ctx->last_into)
+        return set_err(ctx, SIM_ESTATE, "the last run wrote its statistics to caller memory (sim_stats_from_raw)");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipEventSynchronize(ctx->ev_stop));
     const uint32_t d = ctx->last.d, nc = ctx->last.n_checkpoints;
@@ -348,7 +420,7 @@ int sim_paths(sim_ctx *ctx, sim_path_view *out)
     out->n_checkpoints = ctx->last.n_checkpoints;
     const bool keep = (ctx->last.flags & SIM_KEEP_PATHS) != 0;
     out->y = keep ? (const double *)ctx->y.ptr : nullptr;
-    out->f_ckpt = ctx->last.n_checkpoints ? (const double *)ctx->fck.ptr : nullptr;
+    out->f_ckpt = (ctx->last.n_checkpoints && !ctx->last_into) ? (const double *)ctx->fck.ptr : nullptr;
     out->f_ckpt_stride = ctx->R;
     out->cnt = keep ? (const uint32_t *)ctx->cnt.ptr : nullptr;
     out->wsum = keep ? (const uint64_t *)ctx->wsum.ptr : nullptr;

@@ -206,7 +206,8 @@ EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_run_b
            "sim_cv_law", "sim_run_wide", "sim_validate_wide", "sim_wide_stats", "sim_wide_paths",
            "sim_run_newsvendor", "sim_validate_newsvendor", "sim_nv_stats", "sim_nv_paths",
            "sim_sqn_load", "sim_run_sqn", "sim_validate_sqn", "sim_sqn_stats", "sim_sqn_paths", "sim_sqn_hessian",
-           "sim_run_noalloc", "sim_noalloc_last_error", "sim_stats_from_raw", "sim_tune_batch")
+           "sim_run_noalloc", "sim_noalloc_last_error", "sim_stats_from_raw", "sim_tune_batch",
+           "sim_create_ex", "sim_workspace_bytes", "sim_run_into", "sim_param_gen")
 
 _lib = None
 
@@ -278,6 +279,10 @@ def load():
         L.sim_noalloc_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
         L.sim_stats_from_raw.argtypes = [ctypes.POINTER(SimParams), u64, u64, _dp,
                                          ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(SimStats)]
+        L.sim_create_ex.argtypes = [ctypes.c_int, vp, u64, ctypes.POINTER(vp)]
+        L.sim_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.sim_run_into.argtypes = [vp, ctypes.POINTER(SimParams), u64, u64, u64, vp, vp, vp]
+        L.sim_param_gen.argtypes = [ctypes.c_uint32, ctypes.c_int, u64, _dp, _dp]
         _lib = L
     return _lib
 
@@ -327,6 +332,19 @@ def run_noalloc(device: int, stream, p: Problem, R: int, T: int, seed: int, f_ck
         buf = ctypes.create_string_buffer(512)
         load().sim_noalloc_last_error(buf, 512)
         raise SimError(rc, buf.value.decode())
+
+
+REGIME_UNIT, REGIME_PAPER = 0, 1
+
+
+def param_gen(d: int, regime: int, seed: int):
+    """sim_param_gen: (mu, sigma) float64 arrays of length d drawn on the host."""
+    mu = np.zeros(d)
+    sigma = np.zeros(d)
+    rc = load().sim_param_gen(d, regime, seed, mu.ctypes.data_as(_dp), sigma.ctypes.data_as(_dp))
+    if rc:
+        raise SimError(rc, "sim_param_gen rejected the arguments")
+    return mu, sigma
 
 
 def stats_from_raw(p: Problem, R: int, T: int, stats_f, stats_i) -> "SimStats":
@@ -408,14 +426,33 @@ def plan_batch(problems, R, T, n_cu=256, **kw):
 class Sim:
     """A context on one device; ``run`` launches asynchronously, ``stats``/``paths`` synchronise."""
 
-    def __init__(self, device: int = 0, stream=None):
+    def __init__(self, device: int = 0, stream=None, workspace_bytes: int = 0):
+        """workspace_bytes > 0: sim_create_ex, the context's device buffers capped at that size."""
         self.L = load()
         h = ctypes.c_void_p()
-        rc = self.L.sim_create(device, ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        s = ctypes.c_void_p(stream) if stream else None
+        if workspace_bytes:
+            rc = self.L.sim_create_ex(device, s, workspace_bytes, ctypes.byref(h))
+        else:
+            rc = self.L.sim_create(device, s, ctypes.byref(h))
         if rc:
             raise SimError(rc, self.L.sim_strerror(rc).decode())
         self.h = h
         self._keep = None
+
+    def workspace_bytes(self) -> int:
+        """Device bytes the context's buffers hold now (sim_workspace_bytes)."""
+        v = ctypes.c_uint64()
+        self._check(self.L.sim_workspace_bytes(self.h, ctypes.byref(v)))
+        return v.value
+
+    def run_into(self, p: Problem, R: int, T: int, seed: int, f_ckpt: int, stats_f: int, stats_i: int):
+        """sim_run_into: results into caller device memory (pointers), on the context's stream."""
+        sp, keep = self.params(p)
+        self._keep = keep
+        self._check(self.L.sim_run_into(self.h, ctypes.byref(sp), R, T, seed,
+                                        ctypes.c_void_p(f_ckpt) if f_ckpt else None, ctypes.c_void_p(stats_f),
+                                        ctypes.c_void_p(stats_i)))
 
     def close(self):
         if self.h:

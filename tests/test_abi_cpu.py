@@ -277,3 +277,34 @@ def test_cv_feature_validation(lib):
     assert sim.validate(sim.Problem(mu=mu, sigma=sigma, N=4, cv_features=True, cv_ref=b,
                                     precision=sim.FP64), 10, 100)[0] == -5
     assert sim.validate(sim.Problem(mu=mu, sigma=sigma, N=4, cv_features=True, cv_ref=b), 10, 100_000)[0] == -5
+
+
+def test_create_ex_without_gpu_fails_cleanly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    rc = lib.sim_create_ex(0, None, 1 << 20, ctypes.byref(h))
+    assert rc != 0 and not h.value
+
+
+def test_param_gen_regimes():
+    """sim_param_gen: the paper's ranges (Section 4.1) and U(0,1); a fixed seed gives fixed values,
+    another seed others; the sample moments of 1e5 draws match those of the uniform law (five
+    standard errors)."""
+    d = 100_000
+    for regime, (lo, hi), smax in ((sim.REGIME_UNIT, (0.0, 1.0), 1.0), (sim.REGIME_PAPER, (-1.0, 1.0), 0.025)):
+        mu, sigma = sim.param_gen(d, regime, 7)
+        assert mu.min() >= lo and mu.max() < hi and sigma.min() >= 0.0 and sigma.max() < smax
+        for x, a, b in ((mu, lo, hi), (sigma, 0.0, smax)):
+            m, v = (a + b) / 2, (b - a) ** 2 / 12
+            assert abs(x.mean() - m) < 5 * np.sqrt(v / d)
+            assert abs(x.var() - v) < 5 * np.sqrt((b - a) ** 4 / 180 / d)
+        mu2, sigma2 = sim.param_gen(d, regime, 7)
+        assert np.array_equal(mu, mu2) and np.array_equal(sigma, sigma2)
+        mu3, _ = sim.param_gen(d, regime, 8)
+        assert not np.array_equal(mu, mu3)
+    with pytest.raises(sim.SimError):
+        sim.param_gen(10, 5, 0)
+    with pytest.raises(sim.SimError):
+        sim.param_gen(0, sim.REGIME_UNIT, 0)

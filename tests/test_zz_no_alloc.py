@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from paper_2404_11631_amd import sim, workloads
+from tests.hipmem import Hip as _Hip
 
 pytestmark = pytest.mark.gpu
 
@@ -26,40 +27,6 @@ def _same(a, b, d, nc):
             assert getattr(a, f)[c] == getattr(b, f)[c], (f, c)
     assert list(a.decision_total)[: d + 1] == list(b.decision_total)[: d + 1]
     assert a.f_star == b.f_star or (np.isnan(a.f_star) and np.isnan(b.f_star))
-
-
-class _Hip:
-    """Device buffers for the test through the HIP runtime the library itself links (not torch:
-    a torch imported after the library would share its runtime by soname)."""
-
-    def __init__(self):
-        import ctypes
-        self.ct = ctypes
-        sim.load()
-        self.L = ctypes.CDLL("libamdhip64.so.7")
-        vp = ctypes.c_void_p
-        self.L.hipMalloc.argtypes = [ctypes.POINTER(vp), ctypes.c_size_t]
-        self.L.hipFree.argtypes = [vp]
-        self.L.hipMemcpy.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int]
-        self.L.hipMemset.argtypes = [vp, ctypes.c_int, ctypes.c_size_t]
-        self.bufs = []
-
-    def alloc(self, nbytes, fill=0xFF):
-        p = self.ct.c_void_p()
-        assert self.L.hipMalloc(self.ct.byref(p), nbytes) == 0
-        assert self.L.hipMemset(p, fill, nbytes) == 0
-        self.bufs.append(p)
-        return p.value
-
-    def get(self, ptr, dtype, n):
-        a = np.empty(n, dtype=dtype)
-        assert self.L.hipDeviceSynchronize() == 0
-        assert self.L.hipMemcpy(a.ctypes.data, ptr, a.nbytes, 2) == 0    # device to host
-        return a
-
-    def close(self):
-        for p in self.bufs:
-            self.L.hipFree(p)
 
 
 def test_noalloc_matches_sim_run():
