@@ -6,8 +6,9 @@ the oracle's own only where the interval of another vertex's value reaches the c
 intervals widen by one count wherever a demand sample's normal lies within binary32 reach of the
 threshold (x_j - mu_j)/sigma_j; everywhere else it must be the oracle's vertex. Counts and
 signatures then match exactly, f(x_T) and f(x_c) to 1e-11 relative (Eq. (6) in FP64 from the exact
-signature on both sides), tau inside the bound's range, statistics to 1e-10 / 1e-8. At Section 4.1's
-largest shape (1e6 products, S = 50, K = 1500) the oracle checks sampled iterations.
+signature on both sides), tau inside the bound's range, statistics to 1e-10 / 1e-8. Section 4.1's
+1e4-product run (S = 25, K = 1500) is replayed in full; at its largest shape (1e6 products, S = 50,
+K = 1500) the oracle checks sampled iterations.
 """
 import sys
 
@@ -74,6 +75,7 @@ def run_and_compare(ctx, inst, R, T, seed, S, M=1, x0=None, ckpt=(), instance=0)
     dict(n=1000, S=7, M=3, T=150, R=2, ckpt=(150,)),          # 250 quads: a ragged workgroup
     dict(n=4096, S=50, T=100, R=1, ckpt=(100,), x0=True),
     dict(n=20000, S=25, T=60, R=1, ckpt=()),
+    dict(n=10_000, S=25, T=1500, R=1, ckpt=(50, 100, 500, 1000, 1500)),   # Section 4.1 Task 2, n = 1e4: the full run
 ])
 def test_newsvendor_against_oracle(ctx, case):
     c = dict(case)

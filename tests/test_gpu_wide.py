@@ -6,8 +6,9 @@ Protocol: the oracle for this shape (oracle/wide.c) replays the device's decisio
 outside the oracle's rounding bound for a binary32 system must be the oracle's own (bit-exact
 vertex), counts and signatures must then match exactly, f(w_T) and f(w_c) to 1e-11 relative (FP64
 from the exact signature on both sides), tau inside the bound's range, statistics to 1e-10 / 1e-8.
-At the full Section 4.1 shape (d = 1e5, N = 50, K = 1500) the oracle checks sampled iterations:
-the gradient at the device's own iterate and the vertex the device took there.
+Section 4.1's d = 1e4 run (N = 25, K = 1500) is replayed in full; at its largest shape (d = 1e5,
+N = 50, K = 1500) the oracle checks sampled iterations: the gradient at the device's own iterate and
+the vertex the device took there.
 """
 import sys
 
@@ -91,6 +92,7 @@ def run_and_compare(ctx, p, R, T, seed):
     dict(d=500, N=25, T=150, R=3, ckpt=(150,)),                 # 125 quads: a ragged last workgroup
     dict(d=1000, N=7, M=3, T=120, R=2, w0=True, lam=1.0, ckpt=(7, 120)),
     dict(d=4096, N=50, T=60, R=1, ckpt=(60,), regime="unit"),
+    dict(d=10_000, N=25, T=1500, R=1, ckpt=(50, 100, 500, 1000, 1500)),   # Section 4.1, d = 1e4: the full run
 ])
 def test_wide_against_oracle(ctx, case):
     c = dict(case)
