@@ -277,3 +277,25 @@ def test_binary32_pairs_stay_close_and_round_where_stated():
     early_a = oracle.SqnOracle(X, z, **kw).run(0, 20)
     early_b = oracle.SqnOracle(X, z, pairs_fp32=True, **kw).run(0, 20)
     assert np.array_equal(early_a["w"], early_b["w"])
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=50, K=400, M=5, ckpt=(200, 400)),
+    dict(n=37, N=1110, K=120, L=5, M=4, b=17, bH=33),
+    dict(n=1000, N=30000, K=60, M=3, bH=600),
+])
+def test_binary32_pairs_perturbation_on_the_device_cases(case):
+    """The tolerance the device runs with binary32 pairs are held to against the binary64 method:
+    the oracle's two modes differ by at most 1e-5 of the iterate and 1e-6 of the loss on the same
+    configurations (two replications each), with the same number of pairs."""
+    c = dict(case)
+    n = c.pop("n")
+    X, z = workloads.sqn_dataset(18, n, c.pop("N", None))
+    K = c.pop("K")
+    kw = dict(L=c.get("L", 10), M=c.get("M", 25), b=c.get("b", 50), bH=c.get("bH", 300), seed=23, ckpt=c.get("ckpt", ()))
+    for r in range(2):
+        a = oracle.SqnOracle(X, z, **kw).run(r, K)
+        b = oracle.SqnOracle(X, z, pairs_fp32=True, **kw).run(r, K)
+        assert a["pairs"] == b["pairs"]
+        assert np.linalg.norm(a["w"] - b["w"]) <= 1e-5 * np.linalg.norm(a["w"])
+        assert abs(a["F"] - b["F"]) <= 1e-6 * a["F"]
