@@ -463,6 +463,51 @@ int sim_validate_newsvendor(const sim_nv_params *p, uint64_t R, uint64_t T, char
 int sim_nv_stats(sim_ctx *ctx, sim_stats_out *out);
 int sim_nv_paths(sim_ctx *ctx, sim_wide_view *out);
 
+/* Algorithm 2 over Eq. (7)'s general constraint set X = {A x <= C, x >= 0} with M resource rows.
+ * The linear subproblem min_{s in X} s'g is solved on the device each iteration. The solver is the
+ * revised simplex in FP64 on the standard form [A I][s; slack] = C, one workgroup per replication,
+ * warm-started from the previous iteration's optimal basis (the first from the slack basis). It
+ * enters the column of most negative reduced cost (lowest index among equal ones), switching to the
+ * lowest index with a negative reduced cost (Bland's rule) after 2M + 2 degenerate pivots in a row.
+ * It leaves by the smallest ratio (lowest basis position among equal ones), with at most
+ * SIM_NV_LP_MAX_PIVOTS pivots per iteration. The gradient is Eq. (9) in FP64 from the same demand
+ * samples as sim_run_newsvendor, compared with x_j in FP64. The iterate x is kept in FP64 and
+ * updated as x + gamma (s - x) with gamma = 2/(t+2), separately rounded (no fused operations).
+ * Y = f(x_T) and the checkpoints f(x_c) come from Eq. (6).
+ * The params' c and C are not used (c may be NULL). Requires: 1 <= M <= SIM_NV_MAX_RES, A >= 0
+ * with a positive entry in every column (X is then bounded), C > 0, x0 in X, n <= SIM_NV_LP_MAX_N,
+ * R T <= 2^24. Asynchronous on the context's stream. Results: sim_nv_lp_stats (f_star NaN;
+ * decision_total[0] counts the iterations whose vertex is the origin) and sim_nv_lp_paths. */
+#define SIM_NV_MAX_RES 8u
+#define SIM_NV_LP_MAX_N 262144u
+#define SIM_NV_LP_MAX_PIVOTS 64u
+typedef struct {
+    uint32_t n_resources;       /* M */
+    uint32_t pad_;
+    const double *A;            /* [M][n] row-major resource use per unit */
+    const double *C;            /* [M] resource levels */
+} sim_nv_constraints;
+
+int sim_run_newsvendor_lp(sim_ctx *ctx, const sim_nv_params *p, const sim_nv_constraints *con, uint64_t R,
+                          uint64_t T, uint64_t seed);
+int sim_validate_newsvendor_lp(const sim_nv_params *p, const sim_nv_constraints *con, uint64_t R, uint64_t T,
+                               char *msg, size_t len);
+
+typedef struct {
+    uint64_t R, T;
+    uint32_t n, n_resources, n_checkpoints, pad_;
+    const double *y;            /* [R] f(x_T) */
+    const double *f_ckpt;       /* [n_checkpoints][R] */
+    const double *x;            /* [R][n] x_T */
+    const uint32_t *tau;        /* [R] first iteration with Frank-Wolfe gap <= gap_eps, or SIM_TAU_NONE */
+    const uint32_t *basis;      /* [R][T][M] the optimal basis of each iteration: j < n product j, n + i slack i */
+    const double *value;        /* [R][T][M] the basic variables' values: the vertex s has s_j = value where basis = j */
+    const uint32_t *pivots;     /* [R][T] pivots taken; SIM_NV_LP_MAX_PIVOTS + 1 marks a subproblem left unsolved */
+} sim_nv_lp_view;
+
+int sim_nv_lp_stats(sim_ctx *ctx, sim_stats_out *out);
+int sim_nv_lp_paths(sim_ctx *ctx, sim_nv_lp_view *out);
+
 /* ---- Algorithms 3-4: stochastic quasi-Newton classification (Section 3.3, Task 3) ------------
  * Logistic loss Eq. (10)-(11), F(w) = (1/N) sum_i log(1 + e^{-x_i'w}) + (1 - z_i) x_i'w, over N rows
  * of n binary features; mini-batch gradient Eq. (12) over b rows; sub-sampled Hessian Eq. (13) over

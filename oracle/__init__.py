@@ -183,6 +183,8 @@ def lib():
                                  ctypes.c_double, ctypes.POINTER(NvOut), ctypes.POINTER(ctypes.c_uint32)]
         L.or_nv_gradient.argtypes = [ctypes.POINTER(NvProblem), u64, u64, dp, dp, ctypes.POINTER(ctypes.c_uint32)]
         L.or_nv_gradient.restype = None
+        L.or_nv_gradient_bound.argtypes = [ctypes.POINTER(NvProblem), u64, u64, dp, ctypes.c_double, dp]
+        L.or_nv_gradient_bound.restype = None
         L.or_nv_cost.argtypes = [ctypes.POINTER(NvProblem), dp]
         L.or_nv_cost.restype = ctypes.c_double
         u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -403,6 +405,116 @@ class NvOracle:
     def cost(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64)
         return lib().or_nv_cost(ctypes.byref(self.p), _dptr(x))
+
+
+class NvLpOracle:
+    """Algorithm 2 over Eq. (7)'s general constraint set X = {A x <= C, x >= 0} with M resource rows.
+    Test infrastructure: Eq. (9)'s gradient comes from the C oracle's demand samples (or_nv_gradient,
+    with its binary32 uncertainty or_nv_gradient_bound). The linear subproblem min_{s in X} s'g is
+    solved by scipy's linprog (HiGHS), a library LP primitive. The step is 2/(t+2) and the update
+    x + gamma (s - x), each operation rounded on its own (numpy does not fuse them). Eq. (6) comes
+    from or_nv_cost."""
+
+    FIELDS = ("mu", "sigma", "k", "h", "v")
+
+    def __init__(self, inst: dict, A, C, *, S, M=1, x0=None, seed=0, instance=0, ckpt=(), gap_eps=1e-2):
+        self.arrays = {f: np.ascontiguousarray(inst[f], dtype=np.float64) for f in self.FIELDS}
+        n = self.arrays["mu"].shape[0]
+        self.arrays["c"] = np.ones(n)             # the single-row fields are not used here
+        self.A = np.ascontiguousarray(A, dtype=np.float64).reshape(-1, n)
+        self.Cv = np.ascontiguousarray(C, dtype=np.float64).reshape(-1)
+        self.x0 = np.zeros(n) if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+        ck = list(ckpt)
+        if len(ck) > MAX_CKPT:
+            raise ValueError("at most 8 checkpoints")
+        p = NvProblem()
+        p.n, p.S, p.M, p.instance, p.n_ckpt, p.seed = n, S, M, instance, len(ck), seed
+        p.C, p.gap_eps = 1.0, gap_eps
+        for f in self.FIELDS + ("c",):
+            setattr(p, f, _dptr(self.arrays[f]))
+        p.x0 = ctypes.POINTER(ctypes.c_double)()
+        for i, c in enumerate(ck):
+            p.ckpt[i] = int(c)
+        self.p = p
+        self.n, self.S, self.M, self.ckpt, self.gap_eps = n, S, M, ck, gap_eps
+
+    def gradient(self, rep, epoch, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        g = np.zeros(self.n)
+        cnt = np.zeros(self.n, dtype=np.uint32)
+        lib().or_nv_gradient(ctypes.byref(self.p), rep, epoch, _dptr(x), _dptr(g),
+                             cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+        return g, cnt
+
+    def bound(self, rep, epoch, x, u):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        e = np.zeros(self.n)
+        lib().or_nv_gradient_bound(ctypes.byref(self.p), rep, epoch, _dptr(x), u, _dptr(e))
+        return e
+
+    def cost(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().or_nv_cost(ctypes.byref(self.p), _dptr(x))
+
+    def lp(self, g):
+        """(min s'g over X, a minimiser) by HiGHS with tight tolerances."""
+        from scipy.optimize import linprog
+        res = linprog(g, A_ub=self.A, b_ub=self.Cv, bounds=(0, None), method="highs",
+                      options=dict(primal_feasibility_tolerance=1e-10, dual_feasibility_tolerance=1e-10))
+        if res.status != 0:
+            raise RuntimeError(f"linprog: {res.message}")
+        return float(res.fun), np.asarray(res.x, dtype=np.float64)
+
+    def path(self, rep, T, replay=None, uroff=0.0, rtol=1e-9):
+        """One replication. With replay = (basis [T][M], value [T][M]) of a device run, each iteration's
+        recorded vertex is checked and then followed. It must be feasible, and its value under this
+        oracle's gradient must lie within the bound of the LP optimum: the gradient's uncertainty
+        (uroff) over the vertex and over the optimiser, plus rtol of the values. Without replay the
+        oracle follows its own LP solution."""
+        n, A, Cv = self.n, self.A, self.Cv
+        x = self.x0.copy()
+        f_ckpt, ck = [], 0
+        tau_lo = tau_hi = tau = None
+        n_mismatch, first_mismatch, worst = 0, -1, 0.0
+        for t in range(T):
+            epoch = t // self.M
+            g, _ = self.gradient(rep, epoch, x)
+            e = self.bound(rep, epoch, x, uroff) if uroff > 0 else np.zeros(n)
+            vstar, sstar = self.lp(g)
+            if replay is not None:
+                basis, value = replay
+                s = np.zeros(n)
+                for b, v in zip(basis[t], value[t]):
+                    if b < n:
+                        s[b] = v
+                feasible = bool(np.all(s >= 0.0) and np.all(A @ s <= Cv * (1.0 + rtol) + 1e-300))
+                val = float(g @ s)
+                slack = float(e @ (s + sstar)) + rtol * (abs(vstar) + float(np.abs(g) @ (s + sstar)))
+                excess = (val - vstar) / max(slack, 1e-300)
+                worst = max(worst, excess)
+                if not (feasible and vstar - slack <= val <= vstar + slack):
+                    n_mismatch += 1
+                    if first_mismatch < 0:
+                        first_mismatch = t
+            else:
+                s = sstar
+            gap = float(g @ x) - float(g @ s)
+            gap_bound = float(e @ (x + s)) + rtol * float(np.abs(g) @ (x + s))
+            if tau is None and gap <= self.gap_eps:
+                tau = t
+            if tau_lo is None and gap <= self.gap_eps + gap_bound:
+                tau_lo = t
+            if tau_hi is None and gap <= self.gap_eps - gap_bound:
+                tau_hi = t
+            gamma = 2.0 / (t + 2.0)
+            x = x + gamma * (s - x)
+            while ck < len(self.ckpt) and self.ckpt[ck] == t + 1:
+                f_ckpt.append(self.cost(x))
+                ck += 1
+        none = TAU_NONE
+        return dict(y=self.cost(x), f_ckpt=np.array(f_ckpt), x=x, tau=none if tau is None else tau,
+                    tau_lo=none if tau_lo is None else tau_lo, tau_hi=none if tau_hi is None else tau_hi,
+                    n_mismatch=n_mismatch, first_mismatch=first_mismatch, worst_excess=worst)
 
 
 class SqnOracle:

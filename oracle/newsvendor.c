@@ -87,6 +87,19 @@ static double nv_uncertainty(const or_nv_problem *p, const double *z, const doub
     return e / p->c[j];
 }
 
+void or_nv_gradient_bound(const or_nv_problem *p, uint64_t rep, uint64_t epoch, const double *x, double u,
+                          double *e)
+{
+    const size_t m = (size_t)p->S * (size_t)p->n;
+    double *z = (double *)malloc(sizeof(double) * m);
+    double *d = (double *)malloc(sizeof(double) * m);
+    nv_demands(p, rep, epoch, z, d);
+    /* nv_uncertainty is in units of g_j / c_j: multiply back (c is 1 where the caller has no row) */
+    for (int64_t j = 0; j < p->n; ++j) e[j] = nv_uncertainty(p, z, x, j, u) * p->c[j];
+    free(d);
+    free(z);
+}
+
 void or_nv_gradient(const or_nv_problem *p, uint64_t rep, uint64_t epoch, const double *x, double *g,
                     uint32_t *count)
 {

@@ -218,6 +218,11 @@ typedef struct {
 int or_nv_path(const or_nv_problem *p, uint64_t rep, uint64_t T, const uint32_t *replay, double uroff,
                or_nv_out *out, uint32_t *decisions);
 
+/* The uncertainty of each g_j of Eq. (9) at x for a system that draws the normals in binary32
+ * (unit roundoff u): e_j = |h_j + v_j| / S times the number of samples whose normal lies within binary32
+ * reach of the threshold (x_j - mu_j)/sigma_j, plus the rounding of g_j itself. */
+void or_nv_gradient_bound(const or_nv_problem *p, uint64_t rep, uint64_t epoch, const double *x, double u,
+                          double *e);
 /* Eq. (9) at x for (rep, epoch): the gradient estimate and (count may be NULL) the sample counts. */
 void or_nv_gradient(const or_nv_problem *p, uint64_t rep, uint64_t epoch, const double *x, double *g,
                     uint32_t *count);

@@ -87,6 +87,16 @@ struct NvState {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 
+// Buffers and description of the last general-constraint newsvendor run (sim_run_newsvendor_lp).
+struct NvLpState {
+    bool have = false;
+    sim_nv_params params{};               // pointers cleared
+    uint32_t M = 0, nwg = 0;
+    uint64_t R = 0, T = 0;
+    DevBuf prod_d, Am, Cv, x, g, basis, rec_basis, rec_value, rec_piv, tau, origin, cost_part, fval, stats, origin_total;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
 // Data set and buffers of the last stochastic quasi-Newton run (sim_sqn_load, sim_run_sqn).
 struct SqnState {
     bool have_data = false, have = false;
@@ -127,6 +137,7 @@ struct sim_ctx {
     CvState cv;
     WideState wide;
     NvState nv;
+    NvLpState nvlp;
     SqnState sqn;
 };
 

@@ -94,6 +94,24 @@ __device__ __forceinline__ uint32_t nv_reduce_step(const NvArgs &A, uint32_t r, 
     return a;
 }
 
+// f_j(x) of Eq. (6) for normal demand N(mu, sg^2), closed form: k x + h E(x - xi)^+ + v E(xi - x)^+.
+__device__ __forceinline__ double nv_product_cost(double x, double mu, double sg, double k, double h, double v)
+{
+    double over, under;
+    if (sg > 0.0) {
+        const double z = (x - mu) / sg;
+        const double pdf = 0.39894228040143267794 * exp(-0.5 * z * z);
+        const double cdf = 0.5 * erfc(-z * 0.70710678118654752440);
+        const double upper = 0.5 * erfc(z * 0.70710678118654752440);
+        over = sg * (z * cdf + pdf);
+        under = sg * (pdf - z * upper);
+    } else {
+        over = x > mu ? x - mu : 0.0;
+        under = mu > x ? mu - x : 0.0;
+    }
+    return k * x + h * over + v * under;
+}
+
 // The records of the step of iteration t with vertex a (one thread).
 __device__ __forceinline__ void nv_record_step(const NvArgs &A, uint32_t r, uint64_t t, uint32_t a, float gap)
 {
@@ -218,20 +236,7 @@ __global__ __launch_bounds__(kBlock) void nv_cost_kernel(NvArgs A, double c)
     double total = 0.0;
     for (uint32_t j = blockIdx.x * kNvCostChunk + tid; j < j1; j += kBlock) {
         const double x = A.xs_d[j] * (static_cast<double>(S[j]) * c);
-        const double mu = A.mu_d[j], sg = A.sig_d[j];
-        double over, under;
-        if (sg > 0.0) {
-            const double z = (x - mu) / sg;
-            const double pdf = 0.39894228040143267794 * exp(-0.5 * z * z);
-            const double cdf = 0.5 * erfc(-z * 0.70710678118654752440);
-            const double upper = 0.5 * erfc(z * 0.70710678118654752440);
-            over = sg * (z * cdf + pdf);
-            under = sg * (pdf - z * upper);
-        } else {
-            over = x > mu ? x - mu : 0.0;
-            under = mu > x ? mu - x : 0.0;
-        }
-        total += A.k_d[j] * x + A.h_d[j] * over + A.v_d[j] * under;
+        total += nv_product_cost(x, A.mu_d[j], A.sig_d[j], A.k_d[j], A.h_d[j], A.v_d[j]);
     }
     double h = total, l = 0.0;
     block_sum_dd(h, l, sm);
@@ -257,22 +262,21 @@ __global__ __launch_bounds__(kBlock) void nv_cost_sum_kernel(NvArgs A, uint32_t 
 }
 
 // Streams of Y, f(x_c) and RSE_c over the replications in order, in the layout of the per-lane
-// kernels (sum hi/lo, squares hi/lo, count), min and max of Y, and the origin's total.
-__global__ void nv_finalize_kernel(NvArgs A, uint32_t n_ckpt)
+// kernels (sum hi/lo, squares hi/lo, count), then min and max of Y (one thread).
+__device__ void nv_stream_stats(const double *fval, uint32_t R, uint32_t n_ckpt, double *stats)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double *Y = A.fval + static_cast<uint64_t>(n_ckpt) * A.R;
+    const double *Y = fval + static_cast<uint64_t>(n_ckpt) * R;
     const uint32_t n_streams = 1 + 2 * n_ckpt;
     for (uint32_t s = 0; s < n_streams; ++s) {
         double h = 0.0, l = 0.0, qh = 0.0, ql = 0.0, n = 0.0;
-        for (uint32_t r = 0; r < A.R; ++r) {
+        for (uint32_t r = 0; r < R; ++r) {
             double x;
             if (s == 0) {
                 x = Y[r];
             } else if (s <= n_ckpt) {
-                x = A.fval[static_cast<uint64_t>(s - 1) * A.R + r];
+                x = fval[static_cast<uint64_t>(s - 1) * R + r];
             } else {
-                const double f = A.fval[static_cast<uint64_t>(s - 1 - n_ckpt) * A.R + r];
+                const double f = fval[static_cast<uint64_t>(s - 1 - n_ckpt) * R + r];
                 if (f == 0.0) continue;
                 const double e = (f - Y[r]) / f;
                 x = e * e;
@@ -281,7 +285,7 @@ __global__ void nv_finalize_kernel(NvArgs A, uint32_t n_ckpt)
             dd_add(qh, ql, x * x, fma(x, x, -(x * x)));
             n += 1.0;
         }
-        double *o = A.stats + s * kStreamFields;
+        double *o = stats + s * kStreamFields;
         o[0] = h;
         o[1] = l;
         o[2] = qh;
@@ -289,15 +293,405 @@ __global__ void nv_finalize_kernel(NvArgs A, uint32_t n_ckpt)
         o[4] = n;
     }
     double mn = INFINITY, mx = -INFINITY;
-    uint64_t origin = 0;
-    for (uint32_t r = 0; r < A.R; ++r) {
+    for (uint32_t r = 0; r < R; ++r) {
         mn = fmin(mn, Y[r]);
         mx = fmax(mx, Y[r]);
-        origin += A.cnt[static_cast<uint64_t>(r) * (A.n + 1)];
     }
-    A.stats[n_streams * kStreamFields] = mn;
-    A.stats[n_streams * kStreamFields + 1] = mx;
+    stats[n_streams * kStreamFields] = mn;
+    stats[n_streams * kStreamFields + 1] = mx;
+}
+
+// The statistics and the origin's total.
+__global__ void nv_finalize_kernel(NvArgs A, uint32_t n_ckpt)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    nv_stream_stats(A.fval, A.R, n_ckpt, A.stats);
+    uint64_t origin = 0;
+    for (uint32_t r = 0; r < A.R; ++r) origin += A.cnt[static_cast<uint64_t>(r) * (A.n + 1)];
     *A.origin_total = origin;
+}
+
+// ---- Algorithm 2 over X = {A x <= C, x >= 0} with M resource rows (Eq. (7)) --------------------
+//
+// The iterate is kept in FP64 (x + gamma (s - x), each operation rounded on its own), the gradient
+// Eq. (9) in FP64 from the same demand samples as above, and the linear subproblem
+// min_{s in X} s'g is a revised simplex in FP64 on [A I][s; slack] = C, one workgroup per
+// replication: the basis matrix of the previous iteration's optimal basis is rebuilt and inverted
+// (Gauss-Jordan with partial pivoting) at the start, so the state carried between iterations is the
+// basis alone; pricing is a pass over the n + M columns per pivot.
+
+namespace {
+
+// x + gamma (s - x) with each operation rounded on its own (contraction into a fused multiply-add is
+// off here), so that any other implementation of the same formula in FP64 gets the same bits.
+__device__ __forceinline__ double nv_lp_move(double x, double s, double gamma)
+{
+#pragma clang fp contract(off)
+    const double step = gamma * (s - x);
+    return x + step;
+}
+
+// Eq. (9): (k - v) + ((h + v) count) / S, each operation rounded on its own.
+__device__ __forceinline__ double nv_lp_grad(double km, double hv, uint32_t count, uint32_t S)
+{
+#pragma clang fp contract(off)
+    const double part = (hv * static_cast<double>(count)) / static_cast<double>(S);
+    return km + part;
+}
+
+// s_j of the vertex recorded for iteration t of replication r: the basic value where the basis
+// holds product j, else 0.
+__device__ __forceinline__ double nv_lp_vertex(const NvLpArgs &A, uint32_t r, uint64_t t, uint32_t j)
+{
+    const uint64_t o = (static_cast<uint64_t>(r) * A.T + t) * A.M;
+    double s = 0.0;
+    for (uint32_t i = 0; i < A.M; ++i)
+        if (A.rec_basis[o + i] == j) s = A.rec_value[o + i];
+    return s;
+}
+
+}  // namespace
+
+// Iteration t's gradient (grid: workgroups of kNvBlock threads over the product quads, by
+// replication). With fold_prev each thread first moves its four products to x_t with the vertex of
+// iteration t - 1.
+__global__ __launch_bounds__(kNvBlock) void nv_lp_gradient_kernel(NvLpArgs A, uint64_t t, uint32_t epoch,
+                                                                  int fold_prev)
+{
+    const uint32_t r = blockIdx.y;
+    const uint32_t q = blockIdx.x * kNvBlock + threadIdx.x;
+    if (q >= A.nq) return;
+    const uint32_t j0 = 4 * q;
+    double *x = A.x + static_cast<uint64_t>(r) * A.n;
+    double xv[4], thr[4];
+    const double gamma = fold_prev ? 2.0 / (static_cast<double>(t - 1) + 2.0) : 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t j = j0 + k;
+        xv[k] = x[j];
+        if (fold_prev) {
+            xv[k] = nv_lp_move(xv[k], nv_lp_vertex(A, r, t - 1, j), gamma);
+            x[j] = xv[k];
+        }
+        // sigma_j = 0 has an infinite scale: the threshold is +-infinity, and +infinity (every sample
+        // counted) where x_j equals the demand exactly
+        thr[k] = (xv[k] - A.mu_d[j]) * A.isk_d[j];
+        if (thr[k] != thr[k]) thr[k] = INFINITY;
+    }
+    const PhiloxRow row = philox_row(epoch, r, A.k0);
+    uint32_t count[4] = {0u, 0u, 0u, 0u};
+    for (uint32_t s = 0; s < A.S; ++s) {
+        const Block4<float> z = normals_block_row(row, s * A.nq + q, A.dom, A.k0, A.k1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) count[k] += (static_cast<double>(z.z[k]) <= thr[k]) ? 1u : 0u;
+    }
+    double *g = A.g + static_cast<uint64_t>(r) * A.n;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t j = j0 + k;
+        // (k - v) + ((h + v) count) / S, each operation rounded on its own
+        g[j] = nv_lp_grad(A.km_d[j], A.hv_d[j], count[k], A.S);
+    }
+}
+
+// The update of iteration t alone: x_{t+1} = x_t + gamma_t (s_t - x_t).
+__global__ __launch_bounds__(kNvBlock) void nv_lp_update_kernel(NvLpArgs A, uint64_t t)
+{
+    const uint32_t r = blockIdx.y;
+    const uint32_t j = blockIdx.x * kNvBlock + threadIdx.x;
+    if (j >= A.n) return;
+    double *x = A.x + static_cast<uint64_t>(r) * A.n;
+    x[j] = nv_lp_move(x[j], nv_lp_vertex(A, r, t, j), 2.0 / (static_cast<double>(t) + 2.0));
+}
+
+namespace {
+
+// (value, column) minimum with the lowest column among equal values: associative and commutative,
+// so any reduction order gives the same pair.
+__device__ __forceinline__ void nv_lp_better(double &v, uint32_t &j, double ov, uint32_t oj)
+{
+    if (ov < v || (ov == v && oj < j)) {
+        v = ov;
+        j = oj;
+    }
+}
+
+// Column q of [A I]: A's column for a product, the unit vector for a slack.
+__device__ __forceinline__ double nv_lp_col(const NvLpArgs &A, uint32_t q, uint32_t i)
+{
+    return q < A.n ? A.Am[static_cast<uint64_t>(i) * A.n + q] : (q - A.n == i ? 1.0 : 0.0);
+}
+
+}  // namespace
+
+// Iteration t's linear subproblem for replication blockIdx.x (kNvLpBlock threads).
+__global__ __launch_bounds__(kNvLpBlock) void nv_lp_subproblem_kernel(NvLpArgs A, uint64_t t)
+{
+    __shared__ double sB[kNvLpMaxM][2 * kNvLpMaxM];     // [basis matrix | inverse] during Gauss-Jordan
+    __shared__ double sxb[kNvLpMaxM], sy[kNvLpMaxM], sd[kNvLpMaxM], sprow[kNvLpMaxM];
+    __shared__ uint32_t sbasis[kNvLpMaxM];
+    __shared__ double wv[kNvLpBlock / 64];
+    __shared__ uint32_t wj[kNvLpBlock / 64];
+    __shared__ double s_gx;
+    __shared__ uint32_t s_q, s_leave, s_stop;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t r = blockIdx.x, M = A.M, n = A.n;
+    const double *g = A.g + static_cast<uint64_t>(r) * n;
+    const double *x = A.x + static_cast<uint64_t>(r) * n;
+
+    // g'x of the current iterate, in a fixed order (threads in order, then a tree of wavefronts)
+    {
+        double acc = 0.0;
+        for (uint32_t j = tid; j < n; j += kNvLpBlock) acc = __dadd_rn(acc, __dmul_rn(g[j], x[j]));
+        for (int m = 1; m < 64; m <<= 1) acc = __dadd_rn(acc, __shfl_xor(acc, m, 64));
+        if (lane == 0) wv[wave] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < kNvLpBlock / 64; ++w) s = __dadd_rn(s, wv[w]);
+            s_gx = s;
+        }
+        __syncthreads();
+    }
+
+    // the previous optimal basis (the slack basis at t = 0), its matrix inverted in place
+    if (tid < M) sbasis[tid] = t == 0 ? n + tid : A.basis[static_cast<uint64_t>(r) * M + tid];
+    __syncthreads();
+    if (tid < M * M) {
+        const uint32_t i = tid / M, k = tid % M;
+        sB[i][k] = nv_lp_col(A, sbasis[k], i);
+        sB[i][M + k] = i == k ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (uint32_t c = 0; c < M; ++c) {
+        if (tid == 0) {               // partial pivoting: the largest |entry| of column c at or below row c
+            uint32_t p = c;
+            for (uint32_t i = c + 1; i < M; ++i)
+                if (fabs(sB[i][c]) > fabs(sB[p][c])) p = i;
+            s_stop = fabs(sB[p][c]) > 0.0 ? 0u : 1u;
+            if (p != c)
+                for (uint32_t k = 0; k < 2 * M; ++k) {
+                    const double tmp = sB[c][k];
+                    sB[c][k] = sB[p][k];
+                    sB[p][k] = tmp;
+                }
+        }
+        __syncthreads();
+        if (s_stop) break;
+        const double piv = sB[c][c];
+        __syncthreads();
+        if (tid < 2 * M) sB[c][tid] = __ddiv_rn(sB[c][tid], piv);
+        __syncthreads();
+        // each row's multiplier is read before any thread changes column c
+        const uint32_t gi = tid / (2 * M), gk = tid % (2 * M);
+        const double f = tid < M * 2 * M ? sB[gi][c] : 0.0;
+        __syncthreads();
+        if (tid < M * 2 * M && gi != c) sB[gi][gk] = __dsub_rn(sB[gi][gk], __dmul_rn(f, sB[c][gk]));
+        __syncthreads();
+    }
+    if (s_stop) {                     // a singular basis matrix cannot come from the pivots below; restart from the slacks
+        if (tid < M * M) {
+            const uint32_t i = tid / M, k = tid % M;
+            sB[i][M + k] = i == k ? 1.0 : 0.0;
+        }
+        if (tid < M) sbasis[tid] = n + tid;
+        __syncthreads();
+    }
+    // x_B = B^-1 C, clamped at 0
+    if (tid < M) {
+        double v = 0.0;
+        for (uint32_t k = 0; k < M; ++k) v = __dadd_rn(v, __dmul_rn(sB[tid][M + k], A.Cv[k]));
+        sxb[tid] = v > 0.0 ? v : 0.0;
+    }
+    __syncthreads();
+
+    uint32_t pivots = 0, degenerate = 0;
+    bool solved = false;
+    for (;;) {
+        // y' = c_B' B^-1 (c_B: the gradient of basic products, 0 for slacks)
+        if (tid < M) {
+            double v = 0.0;
+            for (uint32_t i = 0; i < M; ++i) {
+                const double cb = sbasis[i] < n ? g[sbasis[i]] : 0.0;
+                v = __dadd_rn(v, __dmul_rn(cb, sB[i][M + tid]));
+            }
+            sy[tid] = v;
+        }
+        __syncthreads();
+        // pricing over the n + M columns: the most negative reduced cost (Dantzig), or after 2M + 2
+        // degenerate pivots in a row the lowest column with a negative one (Bland)
+        const bool bland = degenerate > 2 * M + 2;
+        double bv = INFINITY;
+        uint32_t bj = 0xFFFFFFFFu;
+        for (uint32_t j = tid; j < n + M; j += kNvLpBlock) {
+            double rc;
+            if (j < n) {
+                rc = g[j];
+                for (uint32_t k = 0; k < M; ++k) rc = __dsub_rn(rc, __dmul_rn(sy[k], A.Am[static_cast<uint64_t>(k) * n + j]));
+            } else {
+                rc = -sy[j - n];
+            }
+            if (rc < -A.eps_r) nv_lp_better(bv, bj, bland ? 0.0 : rc, j);
+        }
+        for (int m = 1; m < 64; m <<= 1) {
+            const double ov = __shfl_xor(bv, m, 64);
+            const uint32_t oj = __shfl_xor(bj, m, 64);
+            nv_lp_better(bv, bj, ov, oj);
+        }
+        if (lane == 0) {
+            wv[wave] = bv;
+            wj[wave] = bj;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double v = wv[0];
+            uint32_t j = wj[0];
+            for (int w = 1; w < kNvLpBlock / 64; ++w) nv_lp_better(v, j, wv[w], wj[w]);
+            s_q = j;
+        }
+        __syncthreads();
+        const uint32_t q = s_q;
+        if (q == 0xFFFFFFFFu) {       // no negative reduced cost: optimal
+            solved = true;
+            break;
+        }
+        if (pivots == A.max_pivots) break;
+        // d = B^-1 A_q, then the ratio test: the smallest x_B,i / d_i over d_i > eps_d (lowest i among equal ratios)
+        if (tid < M) {
+            double v = 0.0;
+            for (uint32_t k = 0; k < M; ++k) v = __dadd_rn(v, __dmul_rn(sB[tid][M + k], nv_lp_col(A, q, k)));
+            sd[tid] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t leave = 0xFFFFFFFFu;
+            double best = INFINITY;
+            for (uint32_t i = 0; i < M; ++i)
+                if (sd[i] > A.eps_d) {
+                    const double ratio = __ddiv_rn(sxb[i], sd[i]);
+                    if (ratio < best) {
+                        best = ratio;
+                        leave = i;
+                    }
+                }
+            s_leave = leave;
+        }
+        __syncthreads();
+        const uint32_t lv = s_leave;
+        if (lv == 0xFFFFFFFFu) break;   // unbounded direction: impossible when every column has a positive entry
+        const double dl = sd[lv];
+        const double theta = __ddiv_rn(sxb[lv], dl);
+        // the pivot: row lv divided by d_lv, the others reduced by it; x_B and the basis likewise
+        if (tid < M) sprow[tid] = __ddiv_rn(sB[lv][M + tid], dl);
+        __syncthreads();
+        if (tid < M * M) {
+            const uint32_t i = tid / M, k = tid % M;
+            sB[i][M + k] = i == lv ? sprow[k] : __dsub_rn(sB[i][M + k], __dmul_rn(sd[i], sprow[k]));
+        }
+        if (tid < M) {
+            const double v = tid == lv ? theta : __dsub_rn(sxb[tid], __dmul_rn(sd[tid], theta));
+            sxb[tid] = v > 0.0 ? v : 0.0;
+        }
+        if (tid == 0) sbasis[lv] = q;
+        degenerate = theta == 0.0 ? degenerate + 1 : 0;
+        ++pivots;
+        __syncthreads();
+    }
+
+    // records, the Frank-Wolfe gap g'x - g's and tau
+    if (tid < M) {
+        const uint64_t o = (static_cast<uint64_t>(r) * A.T + t) * M + tid;
+        A.rec_basis[o] = sbasis[tid];
+        A.rec_value[o] = sxb[tid];
+        A.basis[static_cast<uint64_t>(r) * M + tid] = sbasis[tid];
+    }
+    if (tid == 0) {
+        A.rec_piv[static_cast<uint64_t>(r) * A.T + t] = solved ? pivots : A.max_pivots + 1;
+        double gs = 0.0;
+        bool origin = true;
+        for (uint32_t i = 0; i < M; ++i)
+            if (sbasis[i] < n && sxb[i] > 0.0) {
+                gs = __dadd_rn(gs, __dmul_rn(g[sbasis[i]], sxb[i]));
+                origin = false;
+            }
+        if (origin) A.origin[r] += 1u;
+        const double gap = __dsub_rn(s_gx, gs);
+        if (A.tau[r] == kTauNone && gap <= A.gap_eps) A.tau[r] = static_cast<uint32_t>(t);
+    }
+}
+
+// f(x) of Eq. (6) at the current iterate, FP64: workgroup blockIdx.x of replication blockIdx.y sums
+// products [kNvCostChunk blockIdx.x, +kNvCostChunk) into a double-double partial.
+__global__ __launch_bounds__(kBlock) void nv_lp_cost_kernel(NvLpArgs A)
+{
+    __shared__ double sm[2 * (kBlock / 64)];
+    const uint32_t r = blockIdx.y, tid = threadIdx.x;
+    const double *x = A.x + static_cast<uint64_t>(r) * A.n;
+    const uint32_t j1 = min(A.n, (blockIdx.x + 1) * kNvCostChunk);
+    double total = 0.0;
+    for (uint32_t j = blockIdx.x * kNvCostChunk + tid; j < j1; j += kBlock)
+        total += nv_product_cost(x[j], A.mu_d[j], A.sig_d[j], A.k_d[j], A.h_d[j], A.v_d[j]);
+    double h = total, l = 0.0;
+    block_sum_dd(h, l, sm);
+    if (tid == 0) {
+        const uint32_t nc = (A.n + kNvCostChunk - 1) / kNvCostChunk;
+        double *o = A.cost_part + 2 * (static_cast<uint64_t>(r) * nc + blockIdx.x);
+        o[0] = h;
+        o[1] = l;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void nv_lp_cost_sum_kernel(NvLpArgs A, uint32_t slot)
+{
+    __shared__ double sm[2 * (kBlock / 64)];
+    const uint32_t r = blockIdx.x, tid = threadIdx.x;
+    const uint32_t nc = (A.n + kNvCostChunk - 1) / kNvCostChunk;
+    const double *p = A.cost_part + 2 * static_cast<uint64_t>(r) * nc;
+    double h = 0.0, l = 0.0;
+    for (uint32_t b = tid; b < nc; b += kBlock) dd_add(h, l, p[2 * b], p[2 * b + 1]);
+    block_sum_dd(h, l, sm);
+    if (tid == 0) A.fval[static_cast<uint64_t>(slot) * A.R + r] = h + l;
+}
+
+__global__ void nv_lp_finalize_kernel(NvLpArgs A, uint32_t n_ckpt)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    nv_stream_stats(A.fval, A.R, n_ckpt, A.stats);
+    uint64_t origin = 0;
+    for (uint32_t r = 0; r < A.R; ++r) origin += A.origin[r];
+    *A.origin_total = origin;
+}
+
+int launch_nv_lp_gradient(const NvLpArgs &A, uint64_t t, uint32_t epoch, bool fold_prev, hipStream_t s)
+{
+    hipLaunchKernelGGL(nv_lp_gradient_kernel, dim3(A.nwg, A.R), dim3(kNvBlock), 0, s, A, t, epoch, fold_prev ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_nv_lp_subproblem(const NvLpArgs &A, uint64_t t, hipStream_t s)
+{
+    hipLaunchKernelGGL(nv_lp_subproblem_kernel, dim3(A.R), dim3(kNvLpBlock), 0, s, A, t);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_nv_lp_update(const NvLpArgs &A, uint64_t t, hipStream_t s)
+{
+    hipLaunchKernelGGL(nv_lp_update_kernel, dim3((A.n + kNvBlock - 1) / kNvBlock, A.R), dim3(kNvBlock), 0, s, A, t);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_nv_lp_cost(const NvLpArgs &A, uint32_t slot, hipStream_t s)
+{
+    const uint32_t nc = (A.n + kNvCostChunk - 1) / kNvCostChunk;
+    hipLaunchKernelGGL(nv_lp_cost_kernel, dim3(nc, A.R), dim3(kBlock), 0, s, A);
+    hipLaunchKernelGGL(nv_lp_cost_sum_kernel, dim3(A.R), dim3(kBlock), 0, s, A, slot);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_nv_lp_finalize(const NvLpArgs &A, uint32_t n_ckpt, hipStream_t s)
+{
+    hipLaunchKernelGGL(nv_lp_finalize_kernel, dim3(1), dim3(64), 0, s, A, n_ckpt);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_nv_sample(const NvArgs &A, uint64_t t, uint32_t epoch, float cw, bool from_x0, bool fold_prev, hipStream_t s)

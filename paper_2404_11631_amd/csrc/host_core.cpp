@@ -196,7 +196,8 @@ int validate_wide(char *err, const sim_params *p, uint64_t R, uint64_t T)
     return SIM_OK;
 }
 
-int validate_newsvendor(char *err, const sim_nv_params *p, uint64_t R, uint64_t T)
+// The checks shared by both forms of Algorithm 2; `one_row`: the single resource row c'x <= C.
+static int validate_nv_common(char *err, const sim_nv_params *p, uint64_t R, uint64_t T, bool one_row)
 {
     if (!p) return fail(err, SIM_EINVAL, "params is NULL");
     if (p->abi_version != SIM_ABI_VERSION)
@@ -207,22 +208,22 @@ int validate_newsvendor(char *err, const sim_nv_params *p, uint64_t R, uint64_t 
         return fail(err, SIM_EINVAL, "R=%llu outside [1, %u]", (unsigned long long)R, SIM_WIDE_MAX_R);
     if (T < 1 || T > 0xFFFFFFFEull) return fail(err, SIM_EINVAL, "T=%llu outside [1, 2^32-2]", (unsigned long long)T);
     if (R * T > (1ull << 30)) return fail(err, SIM_EINVAL, "R T above 2^30 (the decision record)");
-    if (!p->mu || !p->sigma || !p->k || !p->h || !p->v || !p->c)
-        return fail(err, SIM_EINVAL, "mu, sigma, k, h, v and c are required");
-    if (!finite(p->C) || !(p->C > 0.0)) return fail(err, SIM_EINVAL, "C must be finite and > 0");
+    if (!p->mu || !p->sigma || !p->k || !p->h || !p->v || (one_row && !p->c))
+        return fail(err, SIM_EINVAL, one_row ? "mu, sigma, k, h, v and c are required" : "mu, sigma, k, h and v are required");
+    if (one_row && (!finite(p->C) || !(p->C > 0.0))) return fail(err, SIM_EINVAL, "C must be finite and > 0");
     for (uint32_t j = 0; j < p->n; ++j) {
         if (!finite(p->mu[j]) || !finite(p->k[j]) || !finite(p->h[j]) || !finite(p->v[j]))
             return fail(err, SIM_EINVAL, "product %u: mu, k, h, v must be finite", j);
         if (!finite(p->sigma[j]) || p->sigma[j] < 0.0) return fail(err, SIM_EINVAL, "sigma[%u] must be finite and >= 0", j);
-        if (!finite(p->c[j]) || !(p->c[j] > 0.0)) return fail(err, SIM_EINVAL, "c[%u] must be finite and > 0", j);
+        if (one_row && (!finite(p->c[j]) || !(p->c[j] > 0.0))) return fail(err, SIM_EINVAL, "c[%u] must be finite and > 0", j);
     }
     if (p->x0) {
         double used = 0.0;
         for (uint32_t j = 0; j < p->n; ++j) {
             if (!finite(p->x0[j]) || p->x0[j] < 0.0) return fail(err, SIM_EINVAL, "x0[%u] outside X", j);
-            used += p->c[j] * p->x0[j];
+            if (one_row) used += p->c[j] * p->x0[j];
         }
-        if (used > p->C * (1.0 + 1e-12)) return fail(err, SIM_EINVAL, "x0 uses %g > C", used);
+        if (one_row && used > p->C * (1.0 + 1e-12)) return fail(err, SIM_EINVAL, "x0 uses %g > C", used);
     }
     if (p->n_samples < 1 || p->n_samples > SIM_NV_MAX_S)
         return fail(err, SIM_EINVAL, "n_samples must be in [1, %u]", SIM_NV_MAX_S);
@@ -236,6 +237,40 @@ int validate_newsvendor(char *err, const sim_nv_params *p, uint64_t R, uint64_t 
     }
     if (!finite(p->gap_eps) || p->gap_eps < 0.0) return fail(err, SIM_EINVAL, "gap_eps must be finite and >= 0");
     if (p->instance_id >= (1u << 24)) return fail(err, SIM_EINVAL, "instance_id must be < 2^24");
+    return SIM_OK;
+}
+
+int validate_newsvendor(char *err, const sim_nv_params *p, uint64_t R, uint64_t T)
+{
+    return validate_nv_common(err, p, R, T, true);
+}
+
+int validate_newsvendor_lp(char *err, const sim_nv_params *p, const sim_nv_constraints *con, uint64_t R, uint64_t T)
+{
+    if (int rc = validate_nv_common(err, p, R, T, false)) return rc;
+    if (!con) return fail(err, SIM_EINVAL, "constraints are NULL");
+    const uint32_t M = con->n_resources, n = p->n;
+    if (M < 1 || M > SIM_NV_MAX_RES) return fail(err, SIM_EINVAL, "n_resources=%u outside [1, %u]", M, SIM_NV_MAX_RES);
+    if (n > SIM_NV_LP_MAX_N) return fail(err, SIM_EUNSUPPORTED, "n=%u above %u on the general-constraint path", n, SIM_NV_LP_MAX_N);
+    if (R * T > (1ull << 24)) return fail(err, SIM_EINVAL, "R T above 2^24 (the vertex record)");
+    if (!con->A || !con->C) return fail(err, SIM_EINVAL, "A and C are required");
+    for (uint32_t i = 0; i < M; ++i)
+        if (!finite(con->C[i]) || !(con->C[i] > 0.0)) return fail(err, SIM_EINVAL, "C[%u] must be finite and > 0", i);
+    for (uint32_t j = 0; j < n; ++j) {
+        bool pos = false;
+        for (uint32_t i = 0; i < M; ++i) {
+            const double a = con->A[static_cast<size_t>(i) * n + j];
+            if (!finite(a) || a < 0.0) return fail(err, SIM_EINVAL, "A[%u][%u] must be finite and >= 0", i, j);
+            pos = pos || a > 0.0;
+        }
+        if (!pos) return fail(err, SIM_EINVAL, "product %u uses no resource: X would be unbounded", j);
+    }
+    if (p->x0)
+        for (uint32_t i = 0; i < M; ++i) {
+            double used = 0.0;
+            for (uint32_t j = 0; j < n; ++j) used += con->A[static_cast<size_t>(i) * n + j] * p->x0[j];
+            if (used > con->C[i] * (1.0 + 1e-12)) return fail(err, SIM_EINVAL, "x0 uses %g > C[%u] of resource %u", used, i, i);
+        }
     return SIM_OK;
 }
 

@@ -22,6 +22,7 @@ int validate(char *err, const sim_params *p, uint64_t R, uint64_t T);
 int validate_wide(char *err, const sim_params *p, uint64_t R, uint64_t T);
 // Algorithm 2, the newsvendor (sim_run_newsvendor)
 int validate_newsvendor(char *err, const sim_nv_params *p, uint64_t R, uint64_t T);
+int validate_newsvendor_lp(char *err, const sim_nv_params *p, const sim_nv_constraints *con, uint64_t R, uint64_t T);
 int validate_sqn(char *err, const sim_sqn_params *p, uint64_t N, uint32_t n, uint64_t R, uint64_t K);
 void fill_desc(InstanceDesc &D, const sim_params *p, uint64_t R, uint64_t T, uint64_t seed);
 // Per-epoch table of a sample-size schedule (sim_params.n_schedule): N_k, 1/N_k and the

@@ -215,6 +215,12 @@ void sim_destroy(sim_ctx *ctx)
         free_buf(*x);
     for (hipEvent_t e : {cv.ev0, cv.ev1, cv.ev_a, cv.ev_b})
         if (e) (void)hipEventDestroy(e);
+    NvLpState &lp = ctx->nvlp;
+    for (DevBuf *x : {&lp.prod_d, &lp.Am, &lp.Cv, &lp.x, &lp.g, &lp.basis, &lp.rec_basis, &lp.rec_value, &lp.rec_piv,
+                      &lp.tau, &lp.origin, &lp.cost_part, &lp.fval, &lp.stats, &lp.origin_total})
+        free_buf(*x);
+    for (hipEvent_t e : {lp.ev0, lp.ev1})
+        if (e) (void)hipEventDestroy(e);
     WideState &wd = ctx->wide;
     for (DevBuf *x : {&wd.asset_f, &wd.asset_d, &wd.S, &wd.cnt, &wd.tau, &wd.dec, &wd.s1, &wd.part_dot, &wd.part_qn,
                       &wd.dot, &wd.qn, &wd.wg_g, &wd.wg_j, &wd.wg_gw, &wd.fval, &wd.stats, &wd.origin})

@@ -126,11 +126,13 @@ def nv_params(inst: dict, S: int, M: int = 1, x0=None, checkpoints=(), gap_eps: 
     sp = SimNvParams()
     sp.abi_version = ABI_VERSION
     for f in ("mu", "sigma", "k", "h", "v", "c"):
+        if f == "c" and inst.get("c") is None:        # the general-constraint path does not use c, C
+            continue
         a = np.ascontiguousarray(inst[f], dtype=np.float64)
         keep.append(a)
         setattr(sp, f, a.ctypes.data_as(_dp))
     sp.n = keep[0].shape[0]
-    sp.C = float(inst["C"])
+    sp.C = float(inst.get("C", 0.0))
     if x0 is not None:
         a = np.ascontiguousarray(x0, dtype=np.float64)
         keep.append(a)
@@ -149,6 +151,42 @@ def validate_newsvendor(inst: dict, R: int, T: int, **kw):
     sp, keep = nv_params(inst, **kw)
     buf = ctypes.create_string_buffer(512)
     rc = load().sim_validate_newsvendor(ctypes.byref(sp), R, T, buf, 512)
+    return rc, buf.value.decode()
+
+
+class SimNvConstraints(ctypes.Structure):
+    _fields_ = [("n_resources", ctypes.c_uint32), ("pad_", ctypes.c_uint32), ("A", _dp), ("C", _dp)]
+
+
+class SimNvLpView(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_uint64), ("T", ctypes.c_uint64), ("n", ctypes.c_uint32),
+                ("n_resources", ctypes.c_uint32), ("n_checkpoints", ctypes.c_uint32), ("pad_", ctypes.c_uint32),
+                ("y", ctypes.c_void_p), ("f_ckpt", ctypes.c_void_p), ("x", ctypes.c_void_p), ("tau", ctypes.c_void_p),
+                ("basis", ctypes.c_void_p), ("value", ctypes.c_void_p), ("pivots", ctypes.c_void_p)]
+
+
+NV_LP_MAX_PIVOTS = 64
+
+
+def nv_constraints(A, C):
+    """sim_nv_constraints over A [M][n] and C [M]; returns the struct and the arrays it points into."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    C = np.ascontiguousarray(C, dtype=np.float64).reshape(-1)
+    if A.ndim != 2 or A.shape[0] != C.shape[0]:
+        raise ValueError("A must be [M][n] and C [M]")
+    con = SimNvConstraints()
+    con.n_resources = A.shape[0]
+    con.A = A.ctypes.data_as(_dp)
+    con.C = C.ctypes.data_as(_dp)
+    return con, [A, C]
+
+
+def validate_newsvendor_lp(inst: dict, A, C, R: int, T: int, **kw):
+    """(code, message) of the checks sim_run_newsvendor_lp applies, without a device."""
+    sp, keep = nv_params(inst, **kw)
+    con, keep2 = nv_constraints(A, C)
+    buf = ctypes.create_string_buffer(512)
+    rc = load().sim_validate_newsvendor_lp(ctypes.byref(sp), ctypes.byref(con), R, T, buf, 512)
     return rc, buf.value.decode()
 
 
@@ -207,7 +245,8 @@ EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_run_b
            "sim_run_newsvendor", "sim_validate_newsvendor", "sim_nv_stats", "sim_nv_paths",
            "sim_sqn_load", "sim_run_sqn", "sim_validate_sqn", "sim_sqn_stats", "sim_sqn_paths", "sim_sqn_hessian",
            "sim_run_noalloc", "sim_noalloc_last_error", "sim_stats_from_raw", "sim_tune_batch",
-           "sim_create_ex", "sim_workspace_bytes", "sim_run_into", "sim_param_gen")
+           "sim_create_ex", "sim_workspace_bytes", "sim_run_into", "sim_param_gen",
+           "sim_run_newsvendor_lp", "sim_validate_newsvendor_lp", "sim_nv_lp_stats", "sim_nv_lp_paths")
 
 _lib = None
 
@@ -283,6 +322,12 @@ def load():
         L.sim_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
         L.sim_run_into.argtypes = [vp, ctypes.POINTER(SimParams), u64, u64, u64, vp, vp, vp]
         L.sim_param_gen.argtypes = [ctypes.c_uint32, ctypes.c_int, u64, _dp, _dp]
+        L.sim_run_newsvendor_lp.argtypes = [vp, ctypes.POINTER(SimNvParams), ctypes.POINTER(SimNvConstraints), u64, u64,
+                                            u64]
+        L.sim_validate_newsvendor_lp.argtypes = [ctypes.POINTER(SimNvParams), ctypes.POINTER(SimNvConstraints), u64, u64,
+                                                 ctypes.c_char_p, ctypes.c_size_t]
+        L.sim_nv_lp_stats.argtypes = [vp, ctypes.POINTER(SimStats)]
+        L.sim_nv_lp_paths.argtypes = [vp, ctypes.POINTER(SimNvLpView)]
         _lib = L
     return _lib
 
@@ -556,6 +601,31 @@ class Sim:
         v = SimWideView()
         self._check(self.L.sim_nv_paths(self.h, ctypes.byref(v)))
         return self._wide_view(v)
+
+    def run_newsvendor_lp(self, inst: dict, A, C, R: int, T: int, seed: int, **kw):
+        """Algorithm 2 over {A x <= C, x >= 0} (sim_run_newsvendor_lp); kw as nv_params."""
+        sp, keep = nv_params(inst, **kw)
+        con, keep2 = nv_constraints(A, C)
+        self._keep = keep + keep2
+        self._check(self.L.sim_run_newsvendor_lp(self.h, ctypes.byref(sp), ctypes.byref(con), R, T, seed))
+
+    def nv_lp_stats(self) -> SimStats:
+        st = SimStats()
+        self._check(self.L.sim_nv_lp_stats(self.h, ctypes.byref(st)))
+        return st
+
+    def nv_lp_paths(self) -> dict:
+        """Host copies of the last general-constraint newsvendor run's records."""
+        v = SimNvLpView()
+        self._check(self.L.sim_nv_lp_paths(self.h, ctypes.byref(v)))
+        R, T, n, M, nc = v.R, v.T, v.n, v.n_resources, v.n_checkpoints
+        out = {"y": self._copy(v.y, np.float64, R), "x": self._copy(v.x, np.float64, R * n).reshape(R, n),
+               "tau": self._copy(v.tau, np.uint32, R),
+               "basis": self._copy(v.basis, np.uint32, R * T * M).reshape(R, T, M),
+               "value": self._copy(v.value, np.float64, R * T * M).reshape(R, T, M),
+               "pivots": self._copy(v.pivots, np.uint32, R * T).reshape(R, T)}
+        out["f_ckpt"] = (self._copy(v.f_ckpt, np.float64, nc * R).reshape(nc, R) if nc else np.zeros((0, R)))
+        return out
 
     def sqn_load(self, X, z):
         """Uploads the classification data set: X [N][n] and z [N], bytes 0 or 1 (sim_sqn_load)."""

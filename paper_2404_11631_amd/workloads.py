@@ -68,6 +68,20 @@ def newsvendor_instance(seed: int, instance: int, n: int):
     return dict(mu=mu, sigma=sigma, k=k, h=h, v=v, c=k.copy(), C=0.5 * float(np.dot(k, mu)))
 
 
+def newsvendor_constraints(seed: int, instance: int, n: int, M: int):
+    """Eq. (7)'s technology matrix for M resources, which the paper leaves open: row 0 the budget in
+    money (c = k of newsvendor_instance with the same seed and instance), rows 1..M-1 other resources
+    with use a_ij ~ U(0.5, 2) per unit; each level C_i = 0.5 sum_j a_ij mu_j (half of stocking every
+    product at its mean demand). Returns (A float64 [M][n], C float64 [M])."""
+    inst = newsvendor_instance(seed, instance, n)
+    g = _rng(seed, instance, 6)
+    A = np.empty((M, n))
+    A[0] = inst["k"]
+    if M > 1:
+        A[1:] = g.uniform(0.5, 2.0, (M - 1, n))
+    return A, 0.5 * (A @ inst["mu"])
+
+
 def sqn_dataset(seed: int, n: int, N: int | None = None, density: float | None = None):
     """Task 3's synthetic classification data (Section 4.1): N = 30 n rows of n binary features, labels
     from a random linear combination of the features with 10% label noise. Here: features i.i.d.

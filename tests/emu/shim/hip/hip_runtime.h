@@ -113,7 +113,12 @@ inline uint32_t __builtin_amdgcn_bitop3_b32(uint32_t a, uint32_t b, uint32_t c, 
     return r;
 }
 inline void sincospi(double x, double *s, double *c) { *s = std::sin(M_PI * x); *c = std::cos(M_PI * x); }
-using std::fma; using std::fmin; using std::fmax; using std::sqrt; using std::log;
+using std::fma; using std::fmin; using std::fmax; using std::sqrt; using std::log; using std::min;
+// binary64 operations rounded on their own (the host compiles these without contraction)
+inline double __dadd_rn(double a, double b) { volatile double r = a + b; return r; }
+inline double __dsub_rn(double a, double b) { volatile double r = a - b; return r; }
+inline double __dmul_rn(double a, double b) { volatile double r = a * b; return r; }
+inline double __ddiv_rn(double a, double b) { volatile double r = a / b; return r; }
 inline float fmaf(float a, float b, float c) { return std::fma(a, b, c); }
 
 // runs kernel body f on a block of n threads in lockstep

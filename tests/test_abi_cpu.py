@@ -308,3 +308,28 @@ def test_param_gen_regimes():
         sim.param_gen(10, 5, 0)
     with pytest.raises(sim.SimError):
         sim.param_gen(0, sim.REGIME_UNIT, 0)
+
+
+def test_newsvendor_lp_validation(lib):
+    n = 16
+    inst = workloads.newsvendor_instance(1, 0, n)
+    A, C = workloads.newsvendor_constraints(1, 0, n, 3)
+    ok = dict(S=5)
+    assert sim.validate_newsvendor_lp(inst, A, C, 2, 100, **ok)[0] == 0
+    general = {k: v for k, v in inst.items() if k not in ("c", "C")}      # c and C are not needed
+    assert sim.validate_newsvendor_lp(general, A, C, 2, 100, **ok)[0] == 0
+    bad = A.copy()
+    bad[1, 2] = -1.0
+    assert sim.validate_newsvendor_lp(inst, bad, C, 2, 100, **ok)[0] == -1
+    zero = A.copy()
+    zero[:, 5] = 0.0
+    assert sim.validate_newsvendor_lp(inst, zero, C, 2, 100, **ok)[0] == -1
+    assert sim.validate_newsvendor_lp(inst, A, np.array([1.0, 0.0, 1.0]), 2, 100, **ok)[0] == -1
+    A9, C9 = workloads.newsvendor_constraints(1, 0, n, 9)
+    assert sim.validate_newsvendor_lp(inst, A9, C9, 2, 100, **ok)[0] == -1
+    assert sim.validate_newsvendor_lp(inst, A, C, 64, 1 << 19, **ok)[0] == -1        # R T above 2^24
+    x0 = np.full(n, 1e6)
+    assert sim.validate_newsvendor_lp(inst, A, C, 1, 10, x0=x0, **ok)[0] == -1
+    big = workloads.newsvendor_instance(1, 0, 262148)
+    Ab, Cb = workloads.newsvendor_constraints(1, 0, 262148, 1)
+    assert sim.validate_newsvendor_lp(big, Ab, Cb, 1, 10, **ok)[0] == -5

@@ -1,0 +1,89 @@
+"""Algorithm 2 over Eq. (7)'s general constraint set (the device's simplex kernels in fw_newsvendor.hip)
+in a CPU emulation of the device, vs the oracle.
+
+The device source and the library's launch sequence (nv_lp_sequence) are compiled for the host
+against tests/emu/shim, each workgroup run as lockstep threads. The oracle (oracle.NvLpOracle: the C
+oracle's gradient, HiGHS for the linear subproblem) checks every iteration's recorded vertex, which
+must be feasible and optimal within the bound for its own gradient. It then follows that vertex, so
+the iterates must match bit for bit. This checks the kernels' logic without a GPU; it says nothing
+about device timing.
+"""
+import ctypes
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_11631_amd import sim, workloads
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+@pytest.fixture(scope="module")
+def emu():
+    gxx = shutil.which("g++")
+    if not gxx:
+        pytest.skip("g++ not available")
+    d = tempfile.mkdtemp(prefix="nvlp_emu_")
+    so = os.path.join(d, "libemunv.so")
+    subprocess.check_call([gxx, "-std=c++20", "-O2", "-fPIC", "-shared", "-I", os.path.join(HERE, "emu", "shim"),
+                           "-I", os.path.join(ROOT, "include"), "-o", so, os.path.join(HERE, "emu", "emu_nv_lp.cpp"),
+                           os.path.join(ROOT, "paper_2404_11631_amd", "csrc", "host_core.cpp"), "-lpthread"])
+    L = ctypes.CDLL(so)
+    L.emu_run_nv_lp.argtypes = [ctypes.POINTER(sim.SimNvParams), ctypes.POINTER(sim.SimNvConstraints),
+                                ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+    L.emu_nv_lp_paths.argtypes = [ctypes.c_void_p] * 7
+    L.emu_nv_lp_error.restype = ctypes.c_char_p
+    yield L
+    shutil.rmtree(d, ignore_errors=True)
+
+
+def run(L, inst, A, C, R, T, seed, **kw):
+    sp, keep = sim.nv_params(inst, **kw)
+    con, keep2 = sim.nv_constraints(A, C)
+    rc = L.emu_run_nv_lp(ctypes.byref(sp), ctypes.byref(con), R, T, seed)
+    assert rc == 0, (rc, L.emu_nv_lp_error())
+    n, M, nc = len(inst["mu"]), A.shape[0], len(kw.get("checkpoints", ()))
+    out = {"y": np.zeros(R), "f_ckpt": np.zeros((nc, R)), "x": np.zeros((R, n)), "tau": np.zeros(R, np.uint32),
+           "basis": np.zeros((R, T, M), np.uint32), "value": np.zeros((R, T, M)), "pivots": np.zeros((R, T), np.uint32)}
+    L.emu_nv_lp_paths(*(out[k].ctypes.data for k in ("y", "f_ckpt", "x", "tau", "basis", "value", "pivots")))
+    return out
+
+
+def compare(g, inst, A, C, R, T, seed, S, M=1, x0=None, ckpt=()):
+    O = oracle.NvLpOracle(inst, A, C, S=S, M=M, x0=x0, seed=seed, ckpt=ckpt)
+    for r in range(R):
+        assert np.all(g["pivots"][r] <= sim.NV_LP_MAX_PIVOTS), "a subproblem was left unsolved"
+        o = O.path(r, T, replay=(g["basis"][r], g["value"][r]), uroff=oracle.U32)
+        assert o["n_mismatch"] == 0, (r, o["first_mismatch"], o["worst_excess"])
+        assert np.array_equal(g["x"][r], o["x"]), (r, np.abs(g["x"][r] - o["x"]).max())
+        assert g["y"][r] == pytest.approx(o["y"], rel=1e-11)
+        for c in range(len(ckpt)):
+            assert g["f_ckpt"][c, r] == pytest.approx(o["f_ckpt"][c], rel=1e-11)
+        assert o["tau_lo"] <= int(g["tau"][r]) <= o["tau_hi"], (g["tau"][r], o["tau_lo"], o["tau_hi"])
+
+
+CASES = [  # n, M resources, S, resample every, T, R, x0
+    dict(n=8, m=2, S=25, Mr=1, T=10, R=2, x0=False),
+    dict(n=12, m=1, S=9, Mr=2, T=8, R=1, x0=True),
+    dict(n=264, m=3, S=5, Mr=1, T=6, R=1, x0=False),     # two gradient workgroups, ragged
+    dict(n=20, m=8, S=7, Mr=3, T=6, R=1, x0=False),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"n{c['n']}_M{c['m']}" for c in CASES])
+def test_general_constraint_kernels_match_oracle(emu, case):
+    n, m, S, Mr, T, R = case["n"], case["m"], case["S"], case["Mr"], case["T"], case["R"]
+    inst = workloads.newsvendor_instance(3, 0, n)
+    A, C = workloads.newsvendor_constraints(3, 0, n, m)
+    x0 = None
+    if case["x0"]:
+        x0 = np.full(n, 0.25 * float(np.min(C / A.sum(axis=1))))
+    ckpt = (T // 2, T)
+    g = run(emu, inst, A, C, R, T, 13, S=S, M=Mr, x0=x0, checkpoints=ckpt)
+    compare(g, inst, A, C, R, T, 13, S, M=Mr, x0=x0, ckpt=ckpt)

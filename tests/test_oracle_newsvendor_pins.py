@@ -160,3 +160,66 @@ def test_long_run_reaches_the_constrained_optimum():
     o = O.path(0, 3000)
     assert o["y"] >= fstar - 1e-9
     assert (o["y"] - fstar) / abs(fstar) < 2e-3
+
+
+# ---- Eq. (7) with M resource rows ---------------------------------------------------------------
+
+def test_lp_primitive_against_vertex_enumeration():
+    """The general oracle's linear subproblem (HiGHS) against brute force over every basis of the
+    standard form [A I][s; slack] = C (n = 6 products, M = 2 rows): the smallest s'g over the feasible
+    basic solutions, for gradients of both signs."""
+    import itertools
+    n, M = 6, 2
+    I = inst(n, seed=4)
+    A, C = workloads.newsvendor_constraints(4, 0, n, M)
+    O = oracle.NvLpOracle(I, A, C, S=5)
+    full = np.hstack([A, np.eye(M)])
+    rng = np.random.default_rng(1)
+    for trial in range(40):
+        g = rng.normal(size=n) - (0.5 if trial % 2 else -0.2)
+        best = 0.0                                  # the origin (the slack basis)
+        for cols in itertools.combinations(range(n + M), M):
+            B = full[:, cols]
+            if abs(np.linalg.det(B)) < 1e-12:
+                continue
+            xb = np.linalg.solve(B, C)
+            if np.any(xb < -1e-12):
+                continue
+            s = np.zeros(n + M)
+            s[list(cols)] = xb
+            best = min(best, float(g @ s[:n]))
+        val, s = O.lp(g)
+        assert val == pytest.approx(best, rel=1e-9, abs=1e-12)
+        assert np.all(s >= -1e-12) and np.all(A @ s <= C * (1 + 1e-9))
+        assert float(g @ s) == pytest.approx(val, rel=1e-9, abs=1e-12)
+
+
+def test_one_row_general_path_equals_the_ratio_rule_path():
+    """With A = c (one row) the general oracle's vertices are the ratio rule's: the two oracle paths
+    give the same iterates and outcomes."""
+    n, T = 12, 150
+    I = inst(n, seed=2)
+    single = oracle.NvOracle(I, S=9, M=2, seed=5, ckpt=(50, 150)).path(0, T)
+    general = oracle.NvLpOracle(I, I["c"][None, :], [I["C"]], S=9, M=2, seed=5, ckpt=(50, 150)).path(0, T)
+    assert general["y"] == pytest.approx(single["y"], rel=1e-10)
+    assert np.allclose(general["f_ckpt"], single["f_ckpt"], rtol=1e-10)
+    xT = (I["C"] / I["c"]) * 2.0 * single["wsum"].astype(np.float64) / (T * (T + 1.0))
+    assert np.allclose(general["x"], xT, rtol=1e-9, atol=1e-9 * float(np.max(I["C"] / I["c"])))
+
+
+def test_general_constraints_long_run_reaches_the_optimum():
+    """With many samples and iterations the iterate's cost approaches the optimum of Eq. (7) over
+    {A x <= C, x >= 0} (three rows; the optimum by SLSQP on Eq. (6) in closed form) from above."""
+    n, M = 4, 3
+    I = inst(n, seed=11)
+    A, C = workloads.newsvendor_constraints(11, 0, n, M)
+    O = oracle.NvLpOracle(I, A, C, S=400, seed=2)
+    res = optimize.minimize(O.cost, np.zeros(n), method="SLSQP", bounds=[(0, None)] * n,
+                            constraints=[dict(type="ineq", fun=lambda x: C - A @ x, jac=lambda x: -A)],
+                            options=dict(ftol=1e-14, maxiter=500))
+    assert res.success
+    fstar = res.fun
+    o = O.path(0, 3000)
+    assert np.all(A @ o["x"] <= C * (1 + 1e-12)) and np.all(o["x"] >= 0)
+    assert o["y"] >= fstar - 1e-7 * abs(fstar)
+    assert (o["y"] - fstar) / abs(fstar) < 3e-3
