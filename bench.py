@@ -9,7 +9,8 @@ fused with its cross-path reduction, followed by sim_stats; every step draws fre
 
 The line also carries: each statistic's error against FP64 references ("stats"); the
 control-variate leg ("cv", skip with --no-cv); the sweeps over the Section 4.1 shapes of Task 1
-("paper_shape"), Task 2 ("newsvendor_shape") and Task 3 ("sqn_shape"), and Table 2's RSE
+("paper_shape"), Task 2 ("newsvendor_shape"; over three resource rows, "newsvendor_lp_shape") and
+Task 3 ("sqn_shape"), and Table 2's RSE
 statistic over seven replications of each task ("table2"), all skipped with --no-paper-shape; the
 uneven workload in one batched launch with its measured plan ("uneven", --no-uneven); the
 dense-L t(3) stress workload at R = 1e7 ("stress", --no-stress).
@@ -20,6 +21,7 @@ Other measurements (not the headline line):
                                    K = 1500, on the wide path (--steps runs per size)
     --workload newsvendor_shape    Task 2 (Algorithm 2) at Section 4.1's shape: n = 1e2 .. 1e6
                                    products, K = 1500
+    --workload newsvendor_lp_shape Task 2 over three resource rows (Eq. (7) in general): n = 1e2 .. 1e4
     --workload sqn_shape           Task 3 (Algorithms 3-4) at Section 4.1's settings: n = 50 .. 5000
                                    features, N = 30 n, K = 2000, b_H = 300 / 600
     --workload uneven              the 256 uneven instances on the plain path, instance by instance
@@ -270,7 +272,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="paper_scale",
-                    choices=("paper_scale", "stress", "paper_shape", "newsvendor_shape", "sqn_shape", "uneven",
+                    choices=("paper_scale", "stress", "paper_shape", "newsvendor_shape", "newsvendor_lp_shape", "sqn_shape", "uneven",
                              "uneven_batch"))
     ap.add_argument("--tune", action="store_true", help="uneven_batch: take theta from the measuring tuner")
     ap.add_argument("--heavy-factor", default="0", help="uneven_batch: theta of the tile plan, or a comma "
@@ -314,7 +316,7 @@ def main():
             print(json.dumps(uneven_batch_leg(ctx, sim, hf)), flush=True)
         ctx.close()
         return
-    if args.workload in ("paper_shape", "newsvendor_shape", "sqn_shape"):
+    if args.workload in ("paper_shape", "newsvendor_shape", "newsvendor_lp_shape", "sqn_shape"):
         import torch
 
         from paper_2404_11631_amd import sim
@@ -322,7 +324,7 @@ def main():
         torch.cuda.init()
         ctx = sim.Sim(0, torch.cuda.current_stream().cuda_stream)
         leg = {"paper_shape": paper_shape_leg, "newsvendor_shape": newsvendor_shape_leg,
-               "sqn_shape": sqn_shape_leg}[args.workload]
+               "newsvendor_lp_shape": newsvendor_lp_shape_leg, "sqn_shape": sqn_shape_leg}[args.workload]
         kw = {}
         if args.workload == "sqn_shape" and args.sqn_sizes:
             kw["sizes"] = tuple(int(x) for x in args.sqn_sizes.split(","))
@@ -359,6 +361,7 @@ def main():
     cv = None if args.no_cv else cv_leg(ctx, sim, w, mu, sigma, args)
     shape = None if args.no_paper_shape else paper_shape_leg(ctx, sim, 2, 1)
     nv_shape = None if args.no_paper_shape else newsvendor_shape_leg(ctx, sim, 2, 1)
+    nv_lp_shape = None if args.no_paper_shape else newsvendor_lp_shape_leg(ctx, sim, 2, 1)
     sqn_shape = None if args.no_paper_shape else sqn_shape_leg(ctx, sim, 2, 1)
     table2 = None if args.no_paper_shape else table2_leg(ctx, sim)
     uneven = None if args.no_uneven else uneven_batch_leg(ctx, sim, tune=True)
@@ -396,6 +399,8 @@ def main():
         line["paper_shape"] = shape
     if nv_shape is not None:
         line["newsvendor_shape"] = nv_shape
+    if nv_lp_shape is not None:
+        line["newsvendor_lp_shape"] = nv_lp_shape
     if sqn_shape is not None:
         line["sqn_shape"] = sqn_shape
     if table2 is not None:
@@ -606,6 +611,41 @@ def newsvendor_shape_leg(ctx, sim, runs: int, warmup: int):
                              "iterations_per_s": T / (kavg * 1e-3), "samples_per_s": S * n * T / (kavg * 1e-3),
                              "alu_frac": ops / (kavg * 1e-3) / PEAK_OPS, "Y": st.mean})
         print(f"[newsvendor_shape] n={n} S={S}: {kavg:.1f} ms per run", file=sys.stderr, flush=True)
+    return out
+
+
+def newsvendor_lp_shape_leg(ctx, sim, runs: int, warmup: int):
+    """Algorithm 2 over Eq. (7)'s general constraint set with M = 3 resource rows
+    (sim_run_newsvendor_lp: the linear subproblem solved on the device by a revised simplex per
+    replication): one replication of n products, K = 1500, S = 25. Per size: device time of the run,
+    the wall time of the call, and the simplex pivots per iteration."""
+    from paper_2404_11631_amd import workloads
+
+    w = workloads.WORKLOADS["newsvendor_lp_shape"]
+    T, seed, m = w["T"], w["seed"], w["resources"]
+    out = {"workload": "newsvendor_lp_shape", "T": T, "R": w["R"], "resources": m, "S": w["S"], "runs": runs,
+           "sizes": []}
+    for n in w["sizes"]:
+        inst = workloads.newsvendor_instance(seed, 0, n)
+        A, C = workloads.newsvendor_constraints(seed, 0, n, m)
+        kw = dict(S=w["S"], M=w["M"], checkpoints=w["checkpoints"])
+        for k in range(warmup):
+            ctx.run_newsvendor_lp(inst, A, C, w["R"], T, seed + 1000 + k, **kw)
+            ctx.nv_lp_stats()
+        kms, walls = [], []
+        for k in range(runs):
+            t0 = time.perf_counter()
+            ctx.run_newsvendor_lp(inst, A, C, w["R"], T, seed + k, **kw)
+            st = ctx.nv_lp_stats()
+            walls.append(time.perf_counter() - t0)
+            kms.append(st.kernel_ms)
+        piv = ctx.nv_lp_paths()["pivots"]
+        kavg = sum(kms) / len(kms)
+        out["sizes"].append({"n": n, "device_ms": kavg, "wall_ms": 1e3 * sum(walls) / len(walls),
+                             "iterations_per_s": T / (kavg * 1e-3), "pivots_per_iteration": float(piv.mean()),
+                             "max_pivots": int(piv.max()), "Y": st.mean})
+        print(f"[newsvendor_lp_shape] n={n} M={m}: {kavg:.1f} ms per run, {piv.mean():.2f} pivots per iteration",
+              file=sys.stderr, flush=True)
     return out
 
 

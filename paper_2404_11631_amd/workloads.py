@@ -154,6 +154,9 @@ WORKLOADS = {
     "newsvendor_shape": dict(R=1, T=1_500, sizes=(100, 1_000, 10_000, 100_000, 1_000_000),
                              S={100: 25, 1_000: 25, 10_000: 25, 100_000: 25, 1_000_000: 50}, M=1,
                              checkpoints=(50, 100, 500, 1000, 1500), seed=0),
+    # Task 2 over Eq. (7)'s general constraint set: M = 3 resource rows (newsvendor_constraints)
+    "newsvendor_lp_shape": dict(R=1, T=1_500, sizes=(100, 1_000, 10_000), S=25, M=1, resources=3,
+                                checkpoints=(50, 100, 500, 1000, 1500), seed=0),
     # Task 3 (Algorithms 3-4) at Section 4.1's settings: n features, N = 30 n rows, K = 2000
     "sqn_shape": dict(K=2_000, sizes=(50, 500, 1_000, 5_000), L=10, M=25, b=50, bH=(300, 600), beta=2.0,
                       checkpoints=(50, 100, 500, 1000, 2000), R_batch=1024, seed=0),
