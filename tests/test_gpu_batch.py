@@ -117,6 +117,30 @@ def test_batch_errors(ctx):
     assert e.value.code == -1
 
 
+def test_batch_maximum_horizon(ctx):
+    """T = 131071, the longest horizon the batched kernels hold (the signature's 33rd bit): a zero-noise
+    instance whose one chosen asset reaches S = T (T+1)/2 > 2^32 (closed form), and a noisy one at 2 and
+    4 lanes per replication against the oracle's replay."""
+    T = 131_071
+    mu, _ = workloads.diag_instance(5, 0, 2)
+    z = sim.Problem(mu=mu, sigma=np.zeros(2), N=2, checkpoints=(T,), instance_id=0)
+    noisy = make(1, 6, 3, ckpt=(1000, T), log=(0, 4))
+    wide = make(2, 12, 2, ckpt=(T,), log=(0, 2))
+    say(f"[batch] maximum horizon T={T}")
+    ctx.run_batch([z, noisy, wide], [64, 16, 8], [T, T, T], seed=4, lanes_per_rep=[1, 2, 4], keep_paths=True)
+    g = ctx.batch_paths(0)
+    best = int(np.argmax(mu))
+    assert np.all(g["cnt"][best + 1] == T) and np.all(g["wsum"][best] == T * (T + 1) // 2)
+    assert T * (T + 1) // 2 > 2 ** 32
+    assert np.allclose(g["y"], -mu[best], rtol=0, atol=1e-15)
+    for i, (p, n_log) in enumerate([(noisy, 4), (wide, 2)], start=1):
+        g = ctx.batch_paths(i)
+        op = parity.oracle_problem(p, 4)
+        for r in range(n_log):
+            parity.check_rep(op, g, r, T, oracle.U32, decisions=g["decisions"][:, r])
+        say(f"[batch] instance {i} (d={len(p.mu)}, P={g['lanes_per_rep']}) matches the oracle at T={T}")
+
+
 def test_uneven_full_size(ctx):
     """The uneven workload at full size: 256 instances x 4,096 replications, T log-uniform on
     [100, 1e5]; replications of several instances are checked
