@@ -13,7 +13,9 @@ control-variate leg ("cv", skip with --no-cv); the sweeps over the Section 4.1 s
 Task 3 ("sqn_shape"), and Table 2's RSE
 statistic over seven replications of each task ("table2"), all skipped with --no-paper-shape; the
 uneven workload in one batched launch with its measured plan ("uneven", --no-uneven); the
-dense-L t(3) stress workload at R = 1e7 ("stress", --no-stress).
+dense-L t(3) stress workload at R = 1e7 ("stress", --no-stress); the oracle on every host core
+("cpu_baseline") and on one thread per configuration, extrapolated to each full workload
+("oracle_single_core"), both skipped with --no-cpu-baseline.
 
 Other measurements (not the headline line):
     --workload stress [--reps R]   the dense-L, t(3) stress workload (d = 64, N = 100, T = 1e3)
@@ -172,6 +174,64 @@ def cpu_baseline(w, mu, sigma, seconds: float):
             "cpu_model": host["model"], "single_thread_path_steps_per_s": T / one,
             "sample": f"{n} replications x T={T} of the paper-scale workload "
                       f"({per_thread} per thread on {threads} threads), serial FP64 oracle, {el:.1f} s wall"}
+
+
+def oracle_single_core():
+    """The serial FP64 oracle on one host thread, per configuration:
+    - the tiny workload (d = 2, N = 2, T = 100, R = 1,000) in full;
+    - the paper-scale workload on one replication of T = 10,000;
+    - the uneven workload on one replication of each of 8 instances spread over the cost order;
+    - the dense-L t(3) stress workload on one replication of T = 1,000.
+    Each reports path-steps/s (normals/s for the uneven sample) and the full configuration's time
+    extrapolated at that rate (by path-steps; by normals for the uneven workload)."""
+    import numpy as np
+
+    import oracle
+    from paper_2404_11631_amd import workloads
+
+    out = {"threads": 1, "kind": "oracle", "precision": "fp64"}
+
+    def timed(f):
+        t0 = time.perf_counter()
+        f()
+        return time.perf_counter() - t0
+
+    c1 = workloads.WORKLOADS["tiny"]
+    mu, sg = workloads.diag_instance(c1["seed"], 0, c1["d"])
+    P = oracle.OracleProblem(mu, sg, N=c1["N"], seed=c1["seed"], ckpt=c1["checkpoints"])
+    el = timed(lambda: P.run(c1["R"], c1["T"], r0=0))
+    out["tiny"] = {"path_steps_per_s": c1["R"] * c1["T"] / el, "full_s": el, "sample": "the whole workload"}
+
+    c2 = workloads.WORKLOADS["paper_scale"]
+    mu, sg = workloads.diag_instance(c2["seed"], 0, c2["d"])
+    P = oracle.OracleProblem(mu, sg, N=c2["N"], seed=c2["seed"], ckpt=c2["checkpoints"])
+    el = timed(lambda: P.run(1, c2["T"], r0=0))
+    rate = c2["T"] / el
+    out["paper_scale"] = {"path_steps_per_s": rate, "full_s": c2["R"] * c2["T"] / rate,
+                          "sample": "one replication of T = 10,000"}
+
+    c3 = workloads.WORKLOADS["uneven"]
+    batch = workloads.uneven_batch(c3["seed"], c3["n_instances"], c3["R"], c3["d_range"], c3["n_range"], c3["t_range"])
+    order = np.argsort([b.T * b.N * b.d for b in batch])
+    pick = [batch[int(order[k])] for k in range(0, len(batch), len(batch) // 8)][:8]
+    normals = sum(b.N * b.d * b.T for b in pick)
+    el = 0.0
+    for b in pick:
+        P = oracle.OracleProblem(b.mu, b.sigma, N=b.N, seed=c3["seed"], instance=b.instance)
+        el += timed(lambda: P.run(1, b.T, r0=0))
+    total_normals = sum(b.R * b.N * b.d * b.T for b in batch)
+    out["uneven"] = {"normals_per_s": normals / el, "full_s": total_normals / (normals / el),
+                     "sample": "one replication of each of 8 instances spread over the cost order"}
+
+    c5 = workloads.WORKLOADS["stress"]
+    mu, L = workloads.dense_instance(c5["seed"], 0, c5["d"])
+    P = oracle.OracleProblem(mu, chol=L, N=c5["N"], noise=oracle.NOISE_T, nu=c5["nu"], seed=c5["seed"],
+                             ckpt=c5["checkpoints"])
+    el = timed(lambda: P.run(1, c5["T"], r0=0))
+    rate = c5["T"] / el
+    out["stress"] = {"path_steps_per_s": rate, "full_s": c5["R"] * c5["T"] / rate,
+                     "sample": "one replication of T = 1,000"}
+    return out
 
 
 def parity_leg(ctx, sim, w, mu, sigma, n_log: int = 96):
@@ -411,6 +471,7 @@ def main():
         line["stress"] = stress_r
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, mu, sigma, args.cpu_seconds)
+        line["oracle_single_core"] = oracle_single_core()
     print(json.dumps(line), flush=True)
 
 
