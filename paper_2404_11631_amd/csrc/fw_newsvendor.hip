@@ -316,7 +316,8 @@ __global__ void nv_finalize_kernel(NvArgs A, uint32_t n_ckpt)
 // The iterate is kept in FP64 (x + gamma (s - x), each operation rounded on its own), the gradient
 // Eq. (9) in FP64 from the same demand samples as above, and the linear subproblem
 // min_{s in X} s'g is a revised simplex in FP64 on [A I][s; slack] = C, one workgroup per
-// replication: the basis matrix of the previous iteration's optimal basis is rebuilt and inverted
+// replication (256 threads up to 2,048 products, 1,024 above): the basis matrix of the previous
+// iteration's optimal basis is rebuilt and inverted
 // (Gauss-Jordan with partial pivoting) at the start, so the state carried between iterations is the
 // basis alone; pricing is a pass over the n + M columns per pivot.
 
@@ -424,14 +425,15 @@ __device__ __forceinline__ double nv_lp_col(const NvLpArgs &A, uint32_t q, uint3
 
 }  // namespace
 
-// Iteration t's linear subproblem for replication blockIdx.x (kNvLpBlock threads).
-__global__ __launch_bounds__(kNvLpBlock) void nv_lp_subproblem_kernel(NvLpArgs A, uint64_t t)
+// Iteration t's linear subproblem for replication blockIdx.x (BLOCK threads).
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void nv_lp_subproblem_kernel(NvLpArgs A, uint64_t t)
 {
     __shared__ double sB[kNvLpMaxM][2 * kNvLpMaxM];     // [basis matrix | inverse] during Gauss-Jordan
     __shared__ double sxb[kNvLpMaxM], sy[kNvLpMaxM], sd[kNvLpMaxM], sprow[kNvLpMaxM];
     __shared__ uint32_t sbasis[kNvLpMaxM];
-    __shared__ double wv[kNvLpBlock / 64];
-    __shared__ uint32_t wj[kNvLpBlock / 64];
+    __shared__ double wv[BLOCK / 64];
+    __shared__ uint32_t wj[BLOCK / 64];
     __shared__ double s_gx;
     __shared__ uint32_t s_q, s_leave, s_stop;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
@@ -442,13 +444,13 @@ __global__ __launch_bounds__(kNvLpBlock) void nv_lp_subproblem_kernel(NvLpArgs A
     // g'x of the current iterate, in a fixed order (threads in order, then a tree of wavefronts)
     {
         double acc = 0.0;
-        for (uint32_t j = tid; j < n; j += kNvLpBlock) acc = __dadd_rn(acc, __dmul_rn(g[j], x[j]));
+        for (uint32_t j = tid; j < n; j += BLOCK) acc = __dadd_rn(acc, __dmul_rn(g[j], x[j]));
         for (int m = 1; m < 64; m <<= 1) acc = __dadd_rn(acc, __shfl_xor(acc, m, 64));
         if (lane == 0) wv[wave] = acc;
         __syncthreads();
         if (tid == 0) {
             double s = 0.0;
-            for (int w = 0; w < kNvLpBlock / 64; ++w) s = __dadd_rn(s, wv[w]);
+            for (int w = 0; w < BLOCK / 64; ++w) s = __dadd_rn(s, wv[w]);
             s_gx = s;
         }
         __syncthreads();
@@ -523,7 +525,7 @@ __global__ __launch_bounds__(kNvLpBlock) void nv_lp_subproblem_kernel(NvLpArgs A
         const bool bland = degenerate > 2 * M + 2;
         double bv = INFINITY;
         uint32_t bj = 0xFFFFFFFFu;
-        for (uint32_t j = tid; j < n + M; j += kNvLpBlock) {
+        for (uint32_t j = tid; j < n + M; j += BLOCK) {
             double rc;
             if (j < n) {
                 rc = g[j];
@@ -546,7 +548,7 @@ __global__ __launch_bounds__(kNvLpBlock) void nv_lp_subproblem_kernel(NvLpArgs A
         if (tid == 0) {
             double v = wv[0];
             uint32_t j = wj[0];
-            for (int w = 1; w < kNvLpBlock / 64; ++w) nv_lp_better(v, j, wv[w], wj[w]);
+            for (int w = 1; w < BLOCK / 64; ++w) nv_lp_better(v, j, wv[w], wj[w]);
             s_q = j;
         }
         __syncthreads();
@@ -670,7 +672,10 @@ int launch_nv_lp_gradient(const NvLpArgs &A, uint64_t t, uint32_t epoch, bool fo
 
 int launch_nv_lp_subproblem(const NvLpArgs &A, uint64_t t, hipStream_t s)
 {
-    hipLaunchKernelGGL(nv_lp_subproblem_kernel, dim3(A.R), dim3(kNvLpBlock), 0, s, A, t);
+    if (A.n <= kNvLpSmallN)
+        hipLaunchKernelGGL(nv_lp_subproblem_kernel<kNvLpBlockSmall>, dim3(A.R), dim3(kNvLpBlockSmall), 0, s, A, t);
+    else
+        hipLaunchKernelGGL(nv_lp_subproblem_kernel<kNvLpBlockLarge>, dim3(A.R), dim3(kNvLpBlockLarge), 0, s, A, t);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -49,7 +49,11 @@ int launch_nv_cost(const NvArgs &A, double c, uint32_t slot, hipStream_t s);
 int launch_nv_finalize(const NvArgs &A, uint32_t n_ckpt, hipStream_t s);
 
 // ---- Algorithm 2 over X = {A x <= C, x >= 0} with M resource rows (Eq. (7)) --------------------
-constexpr int kNvLpBlock = 1024;                // threads of the subproblem workgroup (one per replication)
+// threads of the subproblem workgroup (one per replication): few products leave a pricing pass
+// short, and then four wavefronts' barriers cost less than sixteen's
+constexpr int kNvLpBlockSmall = 256;
+constexpr int kNvLpBlockLarge = 1024;
+constexpr uint32_t kNvLpSmallN = 2048;          // products up to which the small workgroup runs
 constexpr uint32_t kNvLpMaxM = 8;
 
 struct NvLpArgs {

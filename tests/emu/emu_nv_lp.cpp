@@ -129,7 +129,10 @@ extern "C" int emu_run_nv_lp(const sim_nv_params *p, const sim_nv_constraints *c
             return 0;
         },
         [&](uint64_t t) {
-            grid(A.R, 1, kNvLpBlock, [&] { nv_lp_subproblem_kernel(A, t); });
+            if (A.n <= kNvLpSmallN)
+                grid(A.R, 1, kNvLpBlockSmall, [&] { nv_lp_subproblem_kernel<kNvLpBlockSmall>(A, t); });
+            else
+                grid(A.R, 1, kNvLpBlockLarge, [&] { nv_lp_subproblem_kernel<kNvLpBlockLarge>(A, t); });
             return 0;
         },
         [&](uint64_t t) {

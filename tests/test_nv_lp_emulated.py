@@ -71,8 +71,9 @@ def compare(g, inst, A, C, R, T, seed, S, M=1, x0=None, ckpt=()):
 CASES = [  # n, M resources, S, resample every, T, R, x0
     dict(n=8, m=2, S=25, Mr=1, T=10, R=2, x0=False),
     dict(n=12, m=1, S=9, Mr=2, T=8, R=1, x0=True),
-    dict(n=264, m=3, S=5, Mr=1, T=6, R=1, x0=False),     # two gradient workgroups, ragged
+    dict(n=264, m=3, S=5, Mr=1, T=6, R=1, x0=False),     # two gradient workgroups, ragged; 256-thread subproblem
     dict(n=20, m=8, S=7, Mr=3, T=6, R=1, x0=False),
+    dict(n=2052, m=2, S=3, Mr=1, T=3, R=1, x0=False),   # above 2,048 products: the 1,024-thread subproblem
 ]
 
 
