@@ -466,7 +466,7 @@ int sim_nv_paths(sim_ctx *ctx, sim_wide_view *out);
 /* Algorithm 2 over Eq. (7)'s general constraint set X = {A x <= C, x >= 0} with M resource rows.
  * The linear subproblem min_{s in X} s'g is solved on the device each iteration. The solver is the
  * revised simplex in FP64 on the standard form [A I][s; slack] = C, one workgroup per replication,
- * warm-started from the previous iteration's optimal basis (the first from the slack basis). It
+ * started from the slack basis each iteration. It
  * enters the column of most negative reduced cost (lowest index among equal ones), switching to the
  * lowest index with a negative reduced cost (Bland's rule) after 2M + 2 degenerate pivots in a row.
  * It leaves by the smallest ratio (lowest basis position among equal ones), with at most

@@ -93,7 +93,7 @@ struct NvLpState {
     sim_nv_params params{};               // pointers cleared
     uint32_t M = 0, nwg = 0;
     uint64_t R = 0, T = 0;
-    DevBuf prod_d, Am, Cv, x, g, basis, rec_basis, rec_value, rec_piv, tau, origin, cost_part, fval, stats, origin_total;
+    DevBuf prod_d, Am, Cv, x, g, rec_basis, rec_value, rec_piv, tau, origin, cost_part, fval, stats, origin_total;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 

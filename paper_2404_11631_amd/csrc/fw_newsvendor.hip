@@ -316,10 +316,8 @@ __global__ void nv_finalize_kernel(NvArgs A, uint32_t n_ckpt)
 // The iterate is kept in FP64 (x + gamma (s - x), each operation rounded on its own), the gradient
 // Eq. (9) in FP64 from the same demand samples as above, and the linear subproblem
 // min_{s in X} s'g is a revised simplex in FP64 on [A I][s; slack] = C, one workgroup per
-// replication (256 threads up to 2,048 products, 1,024 above): the basis matrix of the previous
-// iteration's optimal basis is rebuilt and inverted
-// (Gauss-Jordan with partial pivoting) at the start, so the state carried between iterations is the
-// basis alone; pricing is a pass over the n + M columns per pivot.
+// replication (256 threads up to 2,048 products, 1,024 above), started from the slack basis each
+// iteration; pricing is a pass over the n + M columns per pivot.
 
 namespace {
 
@@ -429,13 +427,13 @@ __device__ __forceinline__ double nv_lp_col(const NvLpArgs &A, uint32_t q, uint3
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void nv_lp_subproblem_kernel(NvLpArgs A, uint64_t t)
 {
-    __shared__ double sB[kNvLpMaxM][2 * kNvLpMaxM];     // [basis matrix | inverse] during Gauss-Jordan
+    __shared__ double sB[kNvLpMaxM][2 * kNvLpMaxM];     // columns M..2M-1: the basis inverse
     __shared__ double sxb[kNvLpMaxM], sy[kNvLpMaxM], sd[kNvLpMaxM], sprow[kNvLpMaxM];
     __shared__ uint32_t sbasis[kNvLpMaxM];
     __shared__ double wv[BLOCK / 64];
     __shared__ uint32_t wj[BLOCK / 64];
     __shared__ double s_gx;
-    __shared__ uint32_t s_q, s_leave, s_stop;
+    __shared__ uint32_t s_q, s_leave;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const uint32_t r = blockIdx.x, M = A.M, n = A.n;
     const double *g = A.g + static_cast<uint64_t>(r) * n;
@@ -456,54 +454,15 @@ __global__ __launch_bounds__(BLOCK) void nv_lp_subproblem_kernel(NvLpArgs A, uin
         __syncthreads();
     }
 
-    // the previous optimal basis (the slack basis at t = 0), its matrix inverted in place
-    if (tid < M) sbasis[tid] = t == 0 ? n + tid : A.basis[static_cast<uint64_t>(r) * M + tid];
-    __syncthreads();
+    // the slack basis: B = I, so B^-1 = I and x_B = C (a fresh start every iteration: the resampled
+    // gradient moves the optimum to other products, so the previous basis is no better a start)
     if (tid < M * M) {
         const uint32_t i = tid / M, k = tid % M;
-        sB[i][k] = nv_lp_col(A, sbasis[k], i);
         sB[i][M + k] = i == k ? 1.0 : 0.0;
     }
-    __syncthreads();
-    for (uint32_t c = 0; c < M; ++c) {
-        if (tid == 0) {               // partial pivoting: the largest |entry| of column c at or below row c
-            uint32_t p = c;
-            for (uint32_t i = c + 1; i < M; ++i)
-                if (fabs(sB[i][c]) > fabs(sB[p][c])) p = i;
-            s_stop = fabs(sB[p][c]) > 0.0 ? 0u : 1u;
-            if (p != c)
-                for (uint32_t k = 0; k < 2 * M; ++k) {
-                    const double tmp = sB[c][k];
-                    sB[c][k] = sB[p][k];
-                    sB[p][k] = tmp;
-                }
-        }
-        __syncthreads();
-        if (s_stop) break;
-        const double piv = sB[c][c];
-        __syncthreads();
-        if (tid < 2 * M) sB[c][tid] = __ddiv_rn(sB[c][tid], piv);
-        __syncthreads();
-        // each row's multiplier is read before any thread changes column c
-        const uint32_t gi = tid / (2 * M), gk = tid % (2 * M);
-        const double f = tid < M * 2 * M ? sB[gi][c] : 0.0;
-        __syncthreads();
-        if (tid < M * 2 * M && gi != c) sB[gi][gk] = __dsub_rn(sB[gi][gk], __dmul_rn(f, sB[c][gk]));
-        __syncthreads();
-    }
-    if (s_stop) {                     // a singular basis matrix cannot come from the pivots below; restart from the slacks
-        if (tid < M * M) {
-            const uint32_t i = tid / M, k = tid % M;
-            sB[i][M + k] = i == k ? 1.0 : 0.0;
-        }
-        if (tid < M) sbasis[tid] = n + tid;
-        __syncthreads();
-    }
-    // x_B = B^-1 C, clamped at 0
     if (tid < M) {
-        double v = 0.0;
-        for (uint32_t k = 0; k < M; ++k) v = __dadd_rn(v, __dmul_rn(sB[tid][M + k], A.Cv[k]));
-        sxb[tid] = v > 0.0 ? v : 0.0;
+        sbasis[tid] = n + tid;
+        sxb[tid] = A.Cv[tid];
     }
     __syncthreads();
 
@@ -605,7 +564,6 @@ __global__ __launch_bounds__(BLOCK) void nv_lp_subproblem_kernel(NvLpArgs A, uin
         const uint64_t o = (static_cast<uint64_t>(r) * A.T + t) * M + tid;
         A.rec_basis[o] = sbasis[tid];
         A.rec_value[o] = sxb[tid];
-        A.basis[static_cast<uint64_t>(r) * M + tid] = sbasis[tid];
     }
     if (tid == 0) {
         A.rec_piv[static_cast<uint64_t>(r) * A.T + t] = solved ? pivots : A.max_pivots + 1;

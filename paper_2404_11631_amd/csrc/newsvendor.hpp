@@ -72,7 +72,6 @@ struct NvLpArgs {
     // state of each replication
     double *x;                                  // [R][n] the iterate
     double *g;                                  // [R][n] the iteration's gradient Eq. (9)
-    uint32_t *basis;                            // [R][M] the last optimal basis (j < n product, n + i slack)
     uint32_t *rec_basis;                        // [R][T][M] each iteration's basis
     double *rec_value;                          // [R][T][M] and its basic variables
     uint32_t *rec_piv;                          // [R][T] pivots taken (max_pivots + 1: not solved)

@@ -265,7 +265,7 @@ int sim_run_newsvendor_lp(sim_ctx *ctx, const sim_nv_params *p, const sim_nv_con
     int rc;
     if ((rc = ensure(ctx, w.prod_d, sizeof(double) * pd.size())) || (rc = ensure(ctx, w.Am, sizeof(double) * M * N)) ||
         (rc = ensure(ctx, w.Cv, sizeof(double) * M)) || (rc = ensure(ctx, w.x, sizeof(double) * R * N)) ||
-        (rc = ensure(ctx, w.g, sizeof(double) * R * N)) || (rc = ensure(ctx, w.basis, sizeof(uint32_t) * R * M)) ||
+        (rc = ensure(ctx, w.g, sizeof(double) * R * N)) ||
         (rc = ensure(ctx, w.rec_basis, sizeof(uint32_t) * R * T * M)) ||
         (rc = ensure(ctx, w.rec_value, sizeof(double) * R * T * M)) ||
         (rc = ensure(ctx, w.rec_piv, sizeof(uint32_t) * R * T)) || (rc = ensure(ctx, w.tau, sizeof(uint32_t) * R)) ||
@@ -313,7 +313,6 @@ int sim_run_newsvendor_lp(sim_ctx *ctx, const sim_nv_params *p, const sim_nv_con
     A.Cv = static_cast<const double *>(w.Cv.ptr);
     A.x = static_cast<double *>(w.x.ptr);
     A.g = static_cast<double *>(w.g.ptr);
-    A.basis = static_cast<uint32_t *>(w.basis.ptr);
     A.rec_basis = static_cast<uint32_t *>(w.rec_basis.ptr);
     A.rec_value = static_cast<double *>(w.rec_value.ptr);
     A.rec_piv = static_cast<uint32_t *>(w.rec_piv.ptr);

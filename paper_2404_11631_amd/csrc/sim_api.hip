@@ -216,7 +216,7 @@ void sim_destroy(sim_ctx *ctx)
     for (hipEvent_t e : {cv.ev0, cv.ev1, cv.ev_a, cv.ev_b})
         if (e) (void)hipEventDestroy(e);
     NvLpState &lp = ctx->nvlp;
-    for (DevBuf *x : {&lp.prod_d, &lp.Am, &lp.Cv, &lp.x, &lp.g, &lp.basis, &lp.rec_basis, &lp.rec_value, &lp.rec_piv,
+    for (DevBuf *x : {&lp.prod_d, &lp.Am, &lp.Cv, &lp.x, &lp.g, &lp.rec_basis, &lp.rec_value, &lp.rec_piv,
                       &lp.tau, &lp.origin, &lp.cost_part, &lp.fval, &lp.stats, &lp.origin_total})
         free_buf(*x);
     for (hipEvent_t e : {lp.ev0, lp.ev1})

@@ -20,7 +20,7 @@ namespace {
 
 struct NvLpEmu {
     std::vector<double> pd, Am, Cv, x, g, rec_value, cost_part, fval, stats;
-    std::vector<uint32_t> basis, rec_basis, rec_piv, tau, origin;
+    std::vector<uint32_t> rec_basis, rec_piv, tau, origin;
     uint64_t origin_total = 0;
     uint32_t n = 0, M = 0, nc = 0;
     uint64_t R = 0, T = 0;
@@ -61,7 +61,6 @@ extern "C" int emu_run_nv_lp(const sim_nv_params *p, const sim_nv_constraints *c
     e.x.resize(R * N);
     for (uint64_t r = 0; r < R; ++r) std::copy(e.pd.begin() + 8 * N, e.pd.begin() + 9 * N, e.x.begin() + r * N);
     e.g.assign(R * N, NAN);
-    e.basis.assign(R * M, 0xEEEEEEEEu);
     e.rec_basis.assign(R * T * M, 0xEEEEEEEEu);
     e.rec_value.assign(R * T * M, NAN);
     e.rec_piv.assign(R * T, 0xEEEEEEEEu);
@@ -100,7 +99,6 @@ extern "C" int emu_run_nv_lp(const sim_nv_params *p, const sim_nv_constraints *c
     A.Cv = e.Cv.data();
     A.x = e.x.data();
     A.g = e.g.data();
-    A.basis = e.basis.data();
     A.rec_basis = e.rec_basis.data();
     A.rec_value = e.rec_value.data();
     A.rec_piv = e.rec_piv.data();
