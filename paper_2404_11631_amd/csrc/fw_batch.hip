@@ -37,6 +37,8 @@ constexpr int kLaneAssets = 8;                 // assets held by one lane
 // the same few of the 64 banks (16- to 32-way conflicts); the padded stride leaves at most two
 // lanes per bank for every pattern the kernel issues (checked over all d, rounds and offsets).
 constexpr int kStageFloats = 2112;   // max over Pa of (64 / Pa) x stride
+// rows of a tile's coefficient table in LDS (binary32, indexed by asset, zero past d)
+constexpr int kCoefSz = 0, kCoefC1 = 1, kCoefC2 = 2, kCoefMu = 3, kCoefW0 = 4, kCoefRows = 5;
 __device__ __forceinline__ uint32_t stage_stride(uint32_t Pa) { return 32u * Pa + (Pa == 4u ? 3u : 1u); }
 
 __device__ __forceinline__ float bfly_sum(float x, uint32_t lo, uint32_t hi)
@@ -92,7 +94,7 @@ __device__ __forceinline__ double tile_objective(const InstanceDesc *__restrict_
     return fma(P->lambda, quad, -lin);
 }
 
-__device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile, float *stage)
+__device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile, float *stage, float (*coef)[kBatchMaxD])
 {
     const InstanceDesc *P = B.inst + tile.inst;
     const uint32_t lane = threadIdx.x;
@@ -115,6 +117,22 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
     const bool tnoise = P->noise != 0;
     const uint32_t nu = P->nu;
     const bool logged = leader && (P->flags & 2u) && (static_cast<uint64_t>(r) - P->log_begin) < P->log_count;
+    const uint64_t log_count = P->log_count, log_at = P->dlog_base + (static_cast<uint64_t>(r) - P->log_begin);
+    const bool has_w0 = P->has_w0 != 0;
+    const float inv_n = P->inv_n_f, gap_eps = static_cast<float>(P->gap_eps), tscale = P->tscale_f;
+
+    // The instance's binary32 coefficients, copied once into this wavefront's LDS and zero past d,
+    // so the iteration reads them unconditionally (a0 + k < 4 x 8 = kBatchMaxD) and its reads issue
+    // together: read from the descriptor under per-asset guards, each would wait for the one before.
+    if (lane < static_cast<uint32_t>(kBatchMaxD)) {
+        const bool in = lane < d;
+        coef[kCoefSz][lane] = in ? P->sz_f[lane] : 0.0f;
+        coef[kCoefC1][lane] = in ? P->c1_f[lane] : 0.0f;
+        coef[kCoefC2][lane] = in ? P->c2_f[lane] : 0.0f;
+        coef[kCoefMu][lane] = in ? P->mu_f[lane] : 0.0f;
+        coef[kCoefW0][lane] = (in && has_w0) ? P->w0_f[lane] : 0.0f;
+    }
+    wave_lds_order();
 
     // G = 4/gcd(d,4) samples hold a whole number of Philox blocks; lane chunks start on such a
     // group. A round is the largest multiple of G samples whose normals fit the sub-group's 32 Pa
@@ -147,17 +165,14 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
     for (uint64_t t = 0; t < T; ++t) {
         const float cw = t == 0 ? 0.0f
                                 : static_cast<float>(2.0 / (static_cast<double>(t) * static_cast<double>(t + 1)));
+        // past this lane's assets S = 0 and the coefficients are 0: w = v = 0 there, as required
         float w[kLaneAssets], v[kLaneAssets], s1[kLaneAssets], s2[kLaneAssets];
 #pragma unroll
         for (int k = 0; k < kLaneAssets; ++k) {
-            const bool in = static_cast<uint32_t>(k) < acnt;
-            float wk = 0.0f;
-            if (in) {
-                wk = (t == 0) ? (P->has_w0 ? P->w0_f[a0 + k] : 0.0f)
-                              : (static_cast<float>(S[k]) + ((hibits >> k) & 1u ? 4294967296.0f : 0.0f)) * cw;
-            }
+            const float wk = (t == 0) ? coef[kCoefW0][a0 + k]
+                                      : (static_cast<float>(S[k]) + ((hibits >> k) & 1u ? 4294967296.0f : 0.0f)) * cw;
             w[k] = wk;
-            v[k] = in ? P->sz_f[a0 + k] * wk : 0.0f;
+            v[k] = coef[kCoefSz][a0 + k] * wk;
             s1[k] = 0.0f;
             s2[k] = 0.0f;
         }
@@ -201,7 +216,7 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
                         const float e = ext.next(epoch, r, dom, k0, k1);
                         ss = fmaf(e, e, ss);
                     }
-                    const float a = P->tscale_f * __builtin_amdgcn_rsqf(ss);
+                    const float a = tscale * __builtin_amdgcn_rsqf(ss);
 #pragma unroll
                     for (int k = 0; k < kLaneAssets; ++k) z[k] *= a;
                 }
@@ -233,14 +248,21 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
 #pragma unroll
         for (int k = 0; k < kLaneAssets; ++k) dot1 = fmaf(s1[k], v[k], dot1);
         dot1 = bfly_sum(dot1, 1u, Pa);
-        const float qn = dot1 * P->inv_n_f;
+        const float qn = dot1 * inv_n;
+        float c1[kLaneAssets], c2[kLaneAssets], mu[kLaneAssets];
+#pragma unroll
+        for (int k = 0; k < kLaneAssets; ++k) {
+            c1[k] = coef[kCoefC1][a0 + k];
+            c2[k] = coef[kCoefC2][a0 + k];
+            mu[k] = coef[kCoefMu][a0 + k];
+        }
         float gmin = INFINITY, gw = 0.0f;
         uint32_t jmin = 0xFFFFFFFFu;
 #pragma unroll
         for (int k = 0; k < kLaneAssets; ++k) {
             if (static_cast<uint32_t>(k) < acnt) {
                 const uint32_t j = a0 + k;
-                const float gj = fmaf(-P->c1_f[j], s1[k], fmaf(P->c2_f[j], fmaf(-s1[k], qn, s2[k]), -P->mu_f[j]));
+                const float gj = fmaf(-c1[k], s1[k], fmaf(c2[k], fmaf(-s1[k], qn, s2[k]), -mu[k]));
                 if (jmin == 0xFFFFFFFFu || gj < gmin) {
                     gmin = gj;
                     jmin = j;
@@ -259,8 +281,8 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
         gw = bfly_sum(gw, 1u, Pa);
         const uint32_t a = (gmin < 0.0f) ? jmin + 1 : 0u;
         const float gap = gw - (gmin < 0.0f ? gmin : 0.0f);
-        if (tau == kTauNone && gap <= static_cast<float>(P->gap_eps)) tau = static_cast<uint32_t>(t);
-        if (logged) B.dlog[P->dlog_base + t * P->log_count + (r - P->log_begin)] = static_cast<uint8_t>(a);
+        if (tau == kTauNone && gap <= gap_eps) tau = static_cast<uint32_t>(t);
+        if (logged) B.dlog[log_at + t * log_count] = static_cast<uint8_t>(a);
 
         // step 2/(t+2): the signature absorbs the update
         cnt0 += (a == 0u) ? 1u : 0u;
@@ -372,8 +394,9 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
 __global__ __launch_bounds__(kWave) void fw_tile_kernel(BatchBuffers B)
 {
     __shared__ float stage[kStageFloats];
+    __shared__ float coef[kCoefRows][kBatchMaxD];
     const Tile tile = B.tiles[blockIdx.x];
-    run_tile(B, tile, stage);
+    run_tile(B, tile, stage, coef);
 }
 
 // One workgroup per instance: its tile slots in order.
