@@ -483,6 +483,10 @@ def _pool(parts):
     return n, m, ss / max(1, n - 1)
 
 
+SPLIT_LANES = 16          # lanes per path for small plain stages (assets x sample chunks)
+SPLIT_MAX_PATHS = 8192    # above this the fused kernel (one lane per path) fills the chip
+
+
 def cv_leg(ctx, sim, w, mu, sigma, args):
     """Wall time to a 95% CI half-width h for E f(w_T) on the paper-scale instance (T = 1e4, d = N =
     10): plain Monte Carlo, the MLP control variate, and a linear (least-squares) control variate
@@ -496,7 +500,11 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
 
     Features have mean 0 under their exact law, so the linear form needs no aux draws:
     Y_lin = mean(Y - b'x). Reported at h = 1e-3 and at the h for which plain Monte Carlo needs
-    about 1e6 paths (below ~1e5 paths every form is bound by one path's latency)."""
+    about 1e6 paths (below ~1e5 paths every form is bound by one path's latency).
+
+    The plain form runs a stage of at most SPLIT_MAX_PATHS paths on the batched tile kernel with
+    SPLIT_LANES lanes per path (one path's latency is then shorter), larger stages on the fused
+    kernel; `plain_one_lane` is the same estimator always on the fused kernel, for comparison."""
     import numpy as np
     import torch
 
@@ -536,9 +544,20 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
     pf = sim.Problem(mu=mu, sigma=sigma, N=N, M=w["M"], precision=sim.FP32, checkpoints=(T,), keep_paths=True,
                      cv_features=True, cv_ref=np.array(fit.ref[:d]))
 
-    def plain_stage(R, seed):
+    def plain_one_lane_stage(R, seed):
         ctx.run(p, R, T, seed)
         st = ctx.stats()
+        return (R, st.mean, st.var), None
+
+    def plain_stage(R, seed):
+        # A stage this small leaves most SIMDs idle on the fused kernel (one lane per path), and each
+        # path's T dependent iterations set the wall time: spread each path over 16 lanes of the
+        # batched tile kernel instead (assets x sample chunks). Larger stages fill the chip and
+        # take the fused kernel, which has the higher throughput.
+        if R > SPLIT_MAX_PATHS:
+            return plain_one_lane_stage(R, seed)
+        ctx.run_batch([p], [R], [T], seed=seed, lanes_per_rep=[SPLIT_LANES])
+        st = ctx.batch_stats(0)
         return (R, st.mean, st.var), None
 
     def mlp_stage(R, seed):
@@ -575,6 +594,8 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
         return {"R": n, "stages": k, "mean": m, "ci95": ci, "met": ci <= h, "wall_s": wall,
                 "R_aux": sum(x[0] for x in aux) if aux else 0}
 
+    plain_stage(R_min, eval_seed + 9)   # first use of the tile kernel in this process, untimed
+
     # the linear form's rho^2 on fresh paths (its own held-out check)
     ctx.run(pf, pilot_R, T, eval_seed + 7)
     g = ctx.paths()
@@ -587,11 +608,13 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
            "calibration_s": calib_s, "sd_plain": s_plain, "rho2_mlp": cs.rho2, "rho2_linear": rho2_lin,
            "variance_ratio_mlp": cs.var_plain / max(cs.var_resid, 1e-300),
            "variance_ratio_linear": 1.0 / max(1.0 - rho2_lin, 1e-300), "aux_per_path": ratio,
-           "aux_cost_per_path": c_aux, "min_paths_per_stage": R_min, "targets": []}
+           "aux_cost_per_path": c_aux, "min_paths_per_stage": R_min,
+           "plain_split": {"lanes_per_path": SPLIT_LANES, "max_paths": SPLIT_MAX_PATHS}, "targets": []}
     for h in (1e-3, 1.96 * s_plain / 1000.0):
         row = {"h": h}
         for name, stage, seed0 in (("plain", plain_stage, eval_seed + 3), ("cv", mlp_stage, eval_seed + 4),
-                                   ("cv_linear", lin_stage, eval_seed + 5)):
+                                   ("cv_linear", lin_stage, eval_seed + 5),
+                                   ("plain_one_lane", plain_one_lane_stage, eval_seed + 3)):
             row[name] = sequential(stage, h, seed0)
         row["speedup"] = row["plain"]["wall_s"] / row["cv"]["wall_s"]
         row["speedup_linear"] = row["plain"]["wall_s"] / row["cv_linear"]["wall_s"]
@@ -599,7 +622,8 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
         print(f"[cv] h={h:.3e}: plain R={row['plain']['R']} {row['plain']['wall_s']:.3f} s "
               f"ci {row['plain']['ci95']:.3e}; mlp R={row['cv']['R']} {row['cv']['wall_s']:.3f} s "
               f"ci {row['cv']['ci95']:.3e}; linear R={row['cv_linear']['R']} {row['cv_linear']['wall_s']:.3f} s "
-              f"ci {row['cv_linear']['ci95']:.3e}", file=sys.stderr, flush=True)
+              f"ci {row['cv_linear']['ci95']:.3e}; plain one lane per path {row['plain_one_lane']['wall_s']:.3f} s",
+              file=sys.stderr, flush=True)
     return out
 
 
