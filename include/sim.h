@@ -545,6 +545,19 @@ typedef struct {
  * Asynchronous on the context's stream. SIM_ESTATE without data. */
 int sim_run_sqn(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, uint64_t seed);
 
+/* The same run (Algorithm 3 with Algorithm 4's H_t, Section 3.3) for few replications, each spread
+ * over many workgroups: every workgroup owns a 256-feature slice of w, of the gradient and of the
+ * stored pairs, and the dot products that need the whole vector (the sampled rows' x_i'w, S'g and
+ * Y'g, the new pair's products) are summed over the slices in a following launch, in slice order.
+ * One to two launches per iteration and three more at the end of a window. sim_run_sqn keeps one
+ * workgroup per replication, which streams the stored pairs through a single compute unit; this
+ * entry point is for the paper's single runs. Results differ from sim_run_sqn's only in the order
+ * of those sums (the sampled rows are the same). Same parameters, outputs (sim_sqn_stats,
+ * sim_sqn_paths, sim_sqn_hessian) and errors as sim_run_sqn, and 1 <= R <= SIM_SQN_SPLIT_MAX_R
+ * (else SIM_EINVAL). Asynchronous on the context's stream; the host issues every launch. */
+#define SIM_SQN_SPLIT_MAX_R 64
+int sim_run_sqn_split(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, uint64_t seed);
+
 /* Checks a parameter set exactly as sim_run_sqn does for data of N rows and n features, without a
  * device. */
 int sim_validate_sqn(const sim_sqn_params *p, uint64_t N, uint32_t n, uint64_t R, uint64_t K, char *msg,

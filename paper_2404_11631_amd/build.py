@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsim.so")
 SOURCES = ["csrc/fw_paths.hip", "csrc/fw_batch.hip", "csrc/fw_dense.hip", "csrc/mlp.hip", "csrc/sim_api.hip", "csrc/sim_batch.hip", "csrc/sim_noalloc.hip", "csrc/cv_api.hip", "csrc/fw_wide.hip", "csrc/wide_api.hip", "csrc/fw_newsvendor.hip", "csrc/nv_api.hip",
-           "csrc/fw_sqn.hip", "csrc/sqn_api.hip",
+           "csrc/fw_sqn.hip", "csrc/fw_sqn_split.hip", "csrc/sqn_api.hip",
            "csrc/host_core.cpp"]
 ARCH = "gfx950"
 

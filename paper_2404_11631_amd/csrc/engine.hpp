@@ -107,6 +107,7 @@ struct SqnState {
     uint32_t nblk = 0;
     DevBuf X, z, S, Y, wprev, acc, wsnap, wt, pairs, loss_part, fval, stats;
     DevBuf H, hscratch;                   // sim_sqn_hessian: the n x n matrix and its work space
+    DevBuf sw, sg, sxpart, sdpart, shpart, sypart, ssmall;   // sim_run_sqn_split: iterate, gradient, partial sums, small matrices
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr;
 };
 

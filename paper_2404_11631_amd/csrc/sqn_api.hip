@@ -11,6 +11,7 @@
 
 #include "engine.hpp"
 #include "sqn.hpp"
+#include "sqn_split.hpp"
 
 using namespace fw::host;
 
@@ -80,7 +81,9 @@ int sim_validate_sqn(const sim_sqn_params *p, uint64_t N, uint32_t n, uint64_t R
     return rc;
 }
 
-int sim_run_sqn(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, uint64_t seed)
+// Validation, the run's buffers and the kernels' arguments, shared by both run entry points.
+static int sqn_prepare(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, uint64_t seed,
+                       fw::SqnArgs &A)
 {
     if (!ctx) return SIM_EINVAL;
     SqnState &q = ctx->sqn;
@@ -105,7 +108,7 @@ int sim_run_sqn(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, u
         (rc = ensure(ctx, q.stats, sizeof(double) * (fw::kMaxStreams * fw::kStreamFields + 2))))
         return rc;
 
-    fw::SqnArgs A{};
+    A = fw::SqnArgs{};
     A.n = q.n;
     A.ld = q.ld;
     A.nq = q.ld / 4;
@@ -144,18 +147,73 @@ int sim_run_sqn(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, u
     A.fval = static_cast<double *>(q.fval.ptr);
     A.stats = static_cast<double *>(q.stats.ptr);
 
+    return SIM_OK;
+}
+
+// The loss launches after the iterations, and the record of the run.
+static int sqn_finish(sim_ctx *ctx, const sim_sqn_params *p, const fw::SqnArgs &A, uint64_t R, uint64_t K)
+{
+    SqnState &q = ctx->sqn;
     hipStream_t st = ctx->stream;
-    HIP_TRY(ctx, hipEventRecord(q.ev0, st));
-    if (fw::launch_sqn_run(A, st)) return set_err(ctx, SIM_EDEVICE, "SQN launch failed");
     HIP_TRY(ctx, hipEventRecord(q.ev1, st));
     if (fw::launch_sqn_loss(A, st)) return set_err(ctx, SIM_EDEVICE, "SQN loss launch failed");
     HIP_TRY(ctx, hipEventRecord(q.ev2, st));
     q.params = *p;
     q.R = R;
     q.K = K;
-    q.nblk = nblk;
+    q.nblk = A.nblk;
     q.have = true;
     return SIM_OK;
+}
+
+int sim_run_sqn(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, uint64_t seed)
+{
+    if (!ctx) return SIM_EINVAL;
+    fw::SqnArgs A;
+    if (int rc = sqn_prepare(ctx, p, R, K, seed, A)) return rc;
+    SqnState &q = ctx->sqn;
+    hipStream_t st = ctx->stream;
+    HIP_TRY(ctx, hipEventRecord(q.ev0, st));
+    if (fw::launch_sqn_run(A, st)) return set_err(ctx, SIM_EDEVICE, "SQN launch failed");
+    return sqn_finish(ctx, p, A, R, K);
+}
+
+int sim_run_sqn_split(sim_ctx *ctx, const sim_sqn_params *p, uint64_t R, uint64_t K, uint64_t seed)
+{
+    if (!ctx) return SIM_EINVAL;
+    if (R > fw::kSplitMaxR)
+        return set_err(ctx, SIM_EINVAL, "R=%llu above %u, the replications of a split run", (unsigned long long)R,
+                       fw::kSplitMaxR);
+    fw::SqnArgs A;
+    if (int rc = sqn_prepare(ctx, p, R, K, seed, A)) return rc;
+    SqnState &q = ctx->sqn;
+    fw::SqnSplit P{};
+    P.A = A;
+    P.W = fw::sqn_split_slices(A.nq);
+    const size_t ld = A.ld, W = P.W;
+    int rc;
+    if ((rc = ensure(ctx, q.sw, sizeof(double) * R * ld)) || (rc = ensure(ctx, q.sg, sizeof(double) * R * ld)) ||
+        (rc = ensure(ctx, q.sxpart, sizeof(double) * 2 * R * A.b * W)) ||
+        (rc = ensure(ctx, q.sdpart, sizeof(double) * R * 2 * A.M * W)) ||
+        (rc = ensure(ctx, q.shpart, sizeof(double) * R * 2 * A.bH * W)) ||
+        (rc = ensure(ctx, q.sypart, sizeof(double) * R * 3 * A.M * W)) ||
+        (rc = ensure(ctx, q.ssmall, sizeof(double) * R * fw::kSqnSmall)))
+        return rc;
+    P.w = static_cast<double *>(q.sw.ptr);
+    P.g = static_cast<double *>(q.sg.ptr);
+    P.xpart = static_cast<double *>(q.sxpart.ptr);
+    P.dpart = static_cast<double *>(q.sdpart.ptr);
+    P.hpart = static_cast<double *>(q.shpart.ptr);
+    P.ypart = static_cast<double *>(q.sypart.ptr);
+    P.small = static_cast<double *>(q.ssmall.ptr);
+    hipStream_t st = ctx->stream;
+    HIP_TRY(ctx, hipEventRecord(q.ev0, st));
+    const int lrc = fw::sqn_split_sequence(K, A.L, A.M, A.n_ckpt, A.ckpt,
+                                           [&](fw::SqnSplitKernel kind, const fw::SqnSplitStep &step) {
+                                               return fw::launch_sqn_split(P, kind, step, st);
+                                           });
+    if (lrc) return set_err(ctx, SIM_EDEVICE, "SQN split launch failed: %s", hipGetErrorString(hipGetLastError()));
+    return sqn_finish(ctx, p, A, R, K);
 }
 
 int sim_sqn_stats(sim_ctx *ctx, sim_stats_out *out)

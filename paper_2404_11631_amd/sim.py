@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libsim.so")
 ABI_VERSION = 4
 MAX_D = 64
 MAX_CKPT = 8
+SQN_SPLIT_MAX_R = 64      # SIM_SQN_SPLIT_MAX_R: replications of a split SQN run
 TAU_NONE = 0xFFFFFFFF
 NOISE_GAUSS, NOISE_T = 0, 1
 FP32, FP64 = 0, 1
@@ -243,7 +244,7 @@ EXPORTS = ("sim_create", "sim_set_stream", "sim_run", "sim_validate", "sim_run_b
            "sim_mlp_set_params", "sim_mlp_get_params", "sim_mlp_forward", "sim_mlp_grad", "sim_cv_aux_draws",
            "sim_cv_law", "sim_run_wide", "sim_validate_wide", "sim_wide_stats", "sim_wide_paths",
            "sim_run_newsvendor", "sim_validate_newsvendor", "sim_nv_stats", "sim_nv_paths",
-           "sim_sqn_load", "sim_run_sqn", "sim_validate_sqn", "sim_sqn_stats", "sim_sqn_paths", "sim_sqn_hessian",
+           "sim_sqn_load", "sim_run_sqn", "sim_run_sqn_split", "sim_validate_sqn", "sim_sqn_stats", "sim_sqn_paths", "sim_sqn_hessian",
            "sim_run_noalloc", "sim_noalloc_last_error", "sim_stats_from_raw", "sim_tune_batch",
            "sim_create_ex", "sim_workspace_bytes", "sim_run_into", "sim_param_gen",
            "sim_run_newsvendor_lp", "sim_validate_newsvendor_lp", "sim_nv_lp_stats", "sim_nv_lp_paths")
@@ -306,6 +307,7 @@ def load():
         u8p = ctypes.POINTER(ctypes.c_uint8)
         L.sim_sqn_load.argtypes = [vp, u8p, u8p, u64, ctypes.c_uint32]
         L.sim_run_sqn.argtypes = [vp, ctypes.POINTER(SimSqnParams), u64, u64, u64]
+        L.sim_run_sqn_split.argtypes = [vp, ctypes.POINTER(SimSqnParams), u64, u64, u64]
         L.sim_validate_sqn.argtypes = [ctypes.POINTER(SimSqnParams), u64, ctypes.c_uint32, u64, u64, ctypes.c_char_p,
                                        ctypes.c_size_t]
         L.sim_sqn_stats.argtypes = [vp, ctypes.POINTER(SimStats)]
@@ -636,10 +638,12 @@ class Sim:
         u8p = ctypes.POINTER(ctypes.c_uint8)
         self._check(self.L.sim_sqn_load(self.h, X.ctypes.data_as(u8p), z.ctypes.data_as(u8p), X.shape[0], X.shape[1]))
 
-    def run_sqn(self, R: int, K: int, seed: int, **kw):
-        """Algorithms 3-4 (sim_run_sqn) on the loaded data; kw as sqn_params."""
+    def run_sqn(self, R: int, K: int, seed: int, split: bool = False, **kw):
+        """Algorithms 3-4 on the loaded data; kw as sqn_params. split: each replication spread over
+        many workgroups (sim_run_sqn_split), else one workgroup per replication (sim_run_sqn)."""
         sp = sqn_params(**kw)
-        self._check(self.L.sim_run_sqn(self.h, ctypes.byref(sp), R, K, seed))
+        fn = self.L.sim_run_sqn_split if split else self.L.sim_run_sqn
+        self._check(fn(self.h, ctypes.byref(sp), R, K, seed))
 
     def sqn_stats(self) -> SimStats:
         st = SimStats()

@@ -24,8 +24,13 @@
 struct Dim3emu { unsigned x, y, z; };
 struct float4 { float x, y, z, w; };
 inline float4 make_float4(float x, float y, float z, float w) { return float4{x, y, z, w}; }
+struct uint4 { unsigned x, y, z, w; };
+struct double2 { double x, y; };
+inline double2 make_double2(double x, double y) { return double2{x, y}; }
+inline unsigned __umulhi(unsigned a, unsigned b) { return static_cast<unsigned>((static_cast<unsigned long long>(a) * b) >> 32); }
 extern thread_local Dim3emu threadIdx;
 extern thread_local Dim3emu blockIdx;
+inline thread_local Dim3emu blockDim{1, 1, 1};   // set for each emulated thread of a block
 typedef int hipError_t;
 typedef void *hipStream_t;
 #define hipSuccess 0
@@ -138,7 +143,7 @@ inline void emu_run_block(int n, unsigned bx, const std::function<void()> &f, un
     g_block = &blk;
     std::vector<std::thread> th;
     for (int i = 0; i < n; ++i)
-        th.emplace_back([&, i] { threadIdx = {(unsigned)i, 0, 0}; blockIdx = {bx, by, 0}; f(); });
+        th.emplace_back([&, i] { threadIdx = {(unsigned)i, 0, 0}; blockIdx = {bx, by, 0}; blockDim = {(unsigned)n, 1, 1}; f(); });
     for (auto &t : th) t.join();
     g_block = nullptr;
 }

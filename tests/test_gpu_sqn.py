@@ -42,13 +42,14 @@ def rel(a, b):
 
 
 def run_and_compare(ctx, X, z, R, K, seed, L=10, M=25, b=50, bH=300, beta=2.0, ckpt=(), instance=0, load=True,
-                    pairs_fp32=False):
+                    pairs_fp32=False, split=False):
     N, n = X.shape
-    say(f"[sqn] n={n} N={N} R={R} K={K} L={L} M={M} b={b} bH={bH} seed={seed} ckpt={ckpt} fp32 pairs={pairs_fp32}")
+    say(f"[sqn] n={n} N={N} R={R} K={K} L={L} M={M} b={b} bH={bH} seed={seed} ckpt={ckpt} fp32 pairs={pairs_fp32}"
+        f"{' split' if split else ''}")
     if load:
         ctx.sqn_load(X, z)
     ctx.run_sqn(R, K, seed, L=L, M=M, b=b, bH=bH, beta=beta, checkpoints=ckpt, instance_id=instance,
-                pairs_fp32=pairs_fp32)
+                pairs_fp32=pairs_fp32, split=split)
     st = ctx.sqn_stats()
     g = ctx.sqn_paths()
     assert np.all(g["w_pad"] == 0.0)
@@ -277,3 +278,88 @@ def test_paper_shape_sampled(ctx):
     h = ctx.sqn_hessian(0, copy=False)
     say(f"[sqn] paper shape: H_t with m={h['m']} pairs formed in {h['device_ms']:.3f} ms")
     assert h["m"] == 25
+
+
+# ---- the split path (sim_run_sqn_split): each replication over many one-wavefront workgroups ----
+
+SPLIT_CASES = [
+    dict(n=50, R=3, K=200, ckpt=(50, 100, 200)),                              # one slice, ring not full
+    dict(n=50, R=2, K=400, M=5, ckpt=(400,)),                                 # the ring wraps
+    dict(n=37, N=1110, R=2, K=120, L=5, M=4, b=17, bH=33, ckpt=(7, 60)),      # ragged quads
+    dict(n=24, N=700, R=2, K=60, L=1, M=1, b=9, bH=5),                        # a pair every iteration
+    dict(n=1000, N=30000, R=2, K=60, M=3, bH=600, ckpt=(30,)),                # four slices, the last ragged
+    dict(n=4100, N=5000, R=1, K=40, M=3, ckpt=(25,)),                         # 17 slices
+    dict(n=9, N=1, R=2, K=40, L=4, M=3, b=3, bH=2),                           # one row
+    dict(n=16, N=200, R=2, K=1),                                              # a single gradient step
+    dict(n=20, N=600, R=1, K=400, L=2, M=32, b=1024, bH=1024),                # largest M, b and b_H
+    dict(n=8192, N=300, R=1, K=25, L=5, M=3, b=40, bH=60),                    # largest n: 32 slices
+    dict(n=1000, N=30000, R=2, K=60, M=3, bH=600, ckpt=(30,), pairs_fp32=True),
+]
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES, ids=[f"n{c['n']}_R{c['R']}_K{c['K']}" + ("_f32" if c.get("pairs_fp32")
+                                                                                    else "") for c in SPLIT_CASES])
+def test_sqn_split_against_oracle(ctx, case):
+    c = dict(case)
+    n = c.pop("n")
+    X, z = workloads.sqn_dataset(11, n, c.pop("N", None))
+    run_and_compare(ctx, X, z, c.pop("R"), c.pop("K"), 21, split=True, **c)
+
+
+def test_sqn_split_matches_one_workgroup(ctx):
+    """Both paths on the same data and seed: the same pair counts, iterates within 1e-11 (they differ
+    only in the order of the dot products' sums), and the split run's pairs give Algorithm 4's
+    matrix like the oracle's chain."""
+    X, z = workloads.sqn_dataset(19, 700, 21000)
+    ctx.sqn_load(X, z)
+    kw = dict(M=6, bH=400, checkpoints=(90,))
+    ctx.run_sqn(2, 180, 4, **kw)
+    a = ctx.sqn_paths()
+    ctx.run_sqn(2, 180, 4, split=True, **kw)
+    b = ctx.sqn_paths()
+    assert np.array_equal(a["pairs"], b["pairs"])
+    for r in range(2):
+        assert rel(b["w"][r], a["w"][r]) <= 1e-11, (r, rel(b["w"][r], a["w"][r]))
+        assert abs(b["F"][r] - a["F"][r]) <= 1e-12 * a["F"][r]
+    assert np.all(b["w_pad"] == 0.0)
+    h = ctx.sqn_hessian(1)
+    ref = oracle.SqnOracle.hessian_approx(b["S"][1], b["Y"][1])
+    assert np.linalg.norm(h["H"] - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_sqn_split_rejects(ctx):
+    X, z = workloads.sqn_dataset(20, 40)
+    ctx.sqn_load(X, z)
+    with pytest.raises(sim.SimError) as e:
+        ctx.run_sqn(sim.SQN_SPLIT_MAX_R + 1, 10, 1, split=True)
+    assert e.value.code == -1
+    with pytest.raises(sim.SimError):
+        ctx.run_sqn(1, 10, 1, split=True, L=0)
+
+
+def test_paper_shape_split(ctx):
+    """Section 4.1's largest Task 3 run on the split path: the first 35 iterations against the oracle;
+    the full K = 2000 run through the loss at every checkpoint recomputed by the oracle at the
+    device's iterate, its decrease, the pair count, and the final loss against the one-workgroup
+    path's (1e-8: the two sum in different orders over 2000 iterations)."""
+    n = 5000
+    X, z = workloads.sqn_dataset(0, n)
+    say(f"[sqn] paper shape split n={n} N={X.shape[0]}")
+    ctx.sqn_load(X, z)
+    run_and_compare(ctx, X, z, 1, 35, 0, bH=600, ckpt=(20,), load=False, split=True)
+    ck = (50, 100, 500, 1000, 2000)
+    ctx.run_sqn(1, 2000, 0, bH=600, checkpoints=ck, split=True)
+    st = ctx.sqn_stats()
+    g = ctx.sqn_paths()
+    say(f"[sqn] paper shape split: {st.kernel_ms:.1f} ms for 2000 iterations, F = {g['F'][0]:.6f}")
+    assert int(g["pairs"][0]) == 199
+    O = oracle.SqnOracle(X, z)
+    for c, k in enumerate(ck):
+        f = O.loss(g["w_ckpt"][c, 0])
+        assert abs(g["F_ckpt"][c, 0] - f) <= 1e-12 * f, (k, g["F_ckpt"][c, 0], f)
+    assert np.all(np.diff(g["F_ckpt"][1:, 0]) < 0) and g["F"][0] < np.log(2.0)
+    ctx.run_sqn(1, 2000, 0, bH=600, checkpoints=ck)
+    one = ctx.sqn_paths()
+    say(f"[sqn] paper shape: split vs one workgroup, w rel {rel(g['w'][0], one['w'][0]):.2e}, "
+        f"F rel {abs(g['F'][0] - one['F'][0]) / one['F'][0]:.2e}")
+    assert abs(g["F"][0] - one["F"][0]) <= 1e-8 * one["F"][0]
