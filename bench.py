@@ -758,7 +758,8 @@ def sqn_bytes(n: int, K: int, L: int, M: int, b: int, bH: int, pair_bytes: int =
 def sqn_shape_leg(ctx, sim, runs: int, warmup: int, throughput_sizes=(5_000,), sizes=None):
     """Task 3 (Algorithms 3-4) at Section 4.1's settings on sim_run_sqn: per feature count n (N = 30 n
     rows, M = 25, L = 10, b = 50, beta = 2, K = 2000) and b_H in {300, 600}, the device time of one
-    run (the paper's single replication), and at the sizes in `throughput_sizes` the throughput of
+    run (the paper's single replication) on one workgroup and, under `split`, with the replication
+    spread over many workgroups (sim_run_sqn_split), and at the sizes in `throughput_sizes` the throughput of
     R = 1024 replications in one launch (replication-iterations per second) against HBM bandwidth,
     with sqn_bytes as the algorithmic traffic. The loss evaluations at the checkpoints are timed
     apart (loss_ms)."""
@@ -789,6 +790,21 @@ def sqn_shape_leg(ctx, sim, runs: int, warmup: int, throughput_sizes=(5_000,), s
             entry = {"n": n, "N": 30 * n, "bH": bH, "device_ms": kavg, "wall_ms": 1e3 * sum(walls) / len(walls),
                      "iterations_per_s": K / (kavg * 1e-3), "F": st.mean,
                      "F_ckpt": [st.f_mean[c] for c in range(len(w["checkpoints"]))]}
+            # the same runs with the replication spread over many workgroups (sim_run_sqn_split)
+            for k in range(warmup):
+                ctx.run_sqn(1, K, seed + 1000 + k, split=True, **kw)
+                ctx.sqn_stats()
+            sk, sw = [], []
+            for k in range(runs):
+                t0 = time.perf_counter()
+                ctx.run_sqn(1, K, seed + k, split=True, **kw)
+                ss = ctx.sqn_stats()
+                sw.append(time.perf_counter() - t0)
+                sk.append(ss.kernel_ms)
+            savg = sum(sk) / len(sk)
+            entry["split"] = {"device_ms": savg, "wall_ms": 1e3 * sum(sw) / len(sw),
+                              "iterations_per_s": K / (savg * 1e-3), "F": ss.mean,
+                              "speedup_vs_one_workgroup": kavg / savg}
             if n in throughput_sizes and bH == w["bH"][0]:
                 # Algorithm 4's matrix formed from the pairs of that run (sim_sqn_hessian): the n x n
                 # product on the FP64 matrix cores, 2 n^2 Kp flops (Kp = 2m rounded up to 4) and the
@@ -835,7 +851,7 @@ def sqn_shape_leg(ctx, sim, runs: int, warmup: int, throughput_sizes=(5_000,), s
                     "roofline": {"bound": "hbm", "achieved": alg32 / (favg * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
                                  "unit": "GB/s", "frac": alg32 / (favg * 1e-3) / PEAK_HBM, "bytes_per_rep": alg32 / R}}
             out["sizes"].append(entry)
-            print(f"[sqn_shape] n={n} bH={bH}: {kavg:.1f} ms per run"
+            print(f"[sqn_shape] n={n} bH={bH}: {kavg:.1f} ms per run (split: {savg:.1f} ms)"
                   + (f", R={entry['batch']['R']}: {entry['batch']['device_ms']:.1f} ms" if "batch" in entry else ""),
                   file=sys.stderr, flush=True)
     return out

@@ -2,7 +2,7 @@
 // the device arguments of fw_sqn_split.hip and the launch sequence, shared by the library
 // (sqn_api.hip) and the CPU emulation of the kernels.
 //
-// Each workgroup (one wavefront) owns a slice of 64 feature quads of w, of the gradient, of the
+// Each workgroup (four wavefronts) owns a slice of 64 feature quads of w, of the gradient, of the
 // window sum and of the stored pairs; everything that needs the whole vector (the rows' dot
 // products x_i'w, S'g and Y'g, the new pair's dot products) is summed over slices in a later launch,
 // slice by slice in order, from per-slice partial sums in HBM. An iteration k is:
@@ -29,7 +29,9 @@
 
 namespace fw {
 
-constexpr uint32_t kSplitQuads = 64;                    // quads per slice = threads per workgroup
+constexpr uint32_t kSplitQuads = 64;                    // quads per slice
+constexpr uint32_t kSplitWaves = 4;                     // wavefronts per workgroup (one slice)
+constexpr uint32_t kSplitThreads = kSplitQuads * kSplitWaves;
 constexpr uint32_t kSplitMaxSlices = kSqnMaxN / 4 / kSplitQuads;   // 32
 constexpr uint32_t kSplitMaxR = SIM_SQN_SPLIT_MAX_R;    // replications per split run
 constexpr size_t kSqnSmall = 4 * static_cast<size_t>(kSqnMaxM) * kSqnMaxM + 8;   // per replication

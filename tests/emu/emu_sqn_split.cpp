@@ -34,7 +34,7 @@ int run(SqnSplit &P, uint64_t K)
     const uint32_t W = P.W, R = P.A.R;
     auto grid = [&](uint32_t nx, const std::function<void()> &body) {
         for (uint32_t r = 0; r < R; ++r)
-            for (uint32_t b = nx; b-- > 0;) emu_run_block(kSplitQuads, b, body, r);
+            for (uint32_t b = nx; b-- > 0;) emu_run_block(kSplitThreads, b, body, r);
     };
     return sqn_split_sequence(K, P.A.L, P.A.M, P.A.n_ckpt, P.A.ckpt, [&](SqnSplitKernel kind, const SqnSplitStep &st) {
         switch (kind) {
