@@ -82,7 +82,7 @@ struct NvState {
     bool have = false;
     sim_nv_params params{};               // pointers cleared
     uint64_t R = 0, T = 0;
-    uint32_t nwg = 0;
+    uint32_t nwg = 0, P = 1;              // sample workgroups; lanes per quad
     DevBuf prod_f, prod_d, S, cnt, tau, dec, wg_r, wg_j, wg_gx, cost_part, fval, stats, origin;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };

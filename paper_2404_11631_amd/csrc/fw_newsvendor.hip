@@ -59,37 +59,40 @@ __device__ __forceinline__ float wave_sum(float x)
 __device__ __forceinline__ uint32_t nv_reduce_step(const NvArgs &A, uint32_t r, uint32_t par, float *smr, float *smx,
                                                    uint32_t *smj, float &gap)
 {
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const uint64_t base = (static_cast<uint64_t>(par) * A.R + r) * A.nwg;
     float rm = INFINITY, gs = 0.0f;
     uint32_t jm = 0xFFFFFFFFu;
     for (uint32_t g = tid; g < A.nwg; g += kNvBlock) {
         const float x = A.wg_r[base + g];
-        if (x < rm) {
+        const uint32_t xj = A.wg_j[base + g];
+        if (x < rm || (x == rm && xj < jm)) {
             rm = x;
-            jm = A.wg_j[base + g];
+            jm = xj;
         }
         gs += A.wg_gx[base + g];
     }
-    smr[tid] = rm;
-    smj[tid] = jm;
-    smx[tid] = gs;
-    __syncthreads();
-    for (int h = kNvBlock / 2; h > 0; h >>= 1) {
-        if (tid < static_cast<uint32_t>(h)) {
-            const float o = smr[tid + h];
-            const uint32_t oj = smj[tid + h];
-            if (o < smr[tid] || (o == smr[tid] && oj < smj[tid])) {
-                smr[tid] = o;
-                smj[tid] = oj;
-            }
-            smx[tid] += smx[tid + h];
-        }
-        __syncthreads();
+    // smallest ratio (lowest product among equal ones) and the sum: within each wavefront, then over
+    // the wavefronts in order, the same in every thread
+    wave_argmin(rm, jm);
+    gs = wave_sum(gs);
+    if (lane == 0) {
+        smr[wave] = rm;
+        smj[wave] = jm;
+        smx[wave] = gs;
     }
-    const float best = smr[0];
-    const uint32_t a = (best < 0.0f) ? smj[0] + 1u : 0u;
-    gap = smx[0] - (best < 0.0f ? A.C * best : 0.0f);
+    __syncthreads();
+    float best = smr[0], gsum = smx[0];
+    uint32_t bj = smj[0];
+    for (int w = 1; w < kNvBlock / 64; ++w) {
+        if (smr[w] < best || (smr[w] == best && smj[w] < bj)) {
+            best = smr[w];
+            bj = smj[w];
+        }
+        gsum += smx[w];
+    }
+    const uint32_t a = (best < 0.0f) ? bj + 1u : 0u;
+    gap = gsum - (best < 0.0f ? A.C * best : 0.0f);
     __syncthreads();                                    // smr/smj/smx may be reused after this
     return a;
 }
@@ -112,12 +115,14 @@ __device__ __forceinline__ double nv_product_cost(double x, double mu, double sg
     return k * x + h * over + v * under;
 }
 
-// The records of the step of iteration t with vertex a (one thread).
-__device__ __forceinline__ void nv_record_step(const NvArgs &A, uint32_t r, uint64_t t, uint32_t a, float gap)
+// The records of the step of iteration t with vertex a (one thread), tau_now being the replication's
+// hitting time as read before. The count is a single-writer atomic add, which nothing waits for.
+__device__ __forceinline__ void nv_record_step(const NvArgs &A, uint32_t r, uint64_t t, uint32_t a, float gap,
+                                               uint32_t tau_now)
 {
-    if (A.tau[r] == kTauNone && gap <= A.gap_eps) A.tau[r] = static_cast<uint32_t>(t);
+    if (tau_now == kTauNone && gap <= A.gap_eps) A.tau[r] = static_cast<uint32_t>(t);
     A.dec[static_cast<uint64_t>(r) * A.T + t] = a;
-    A.cnt[static_cast<uint64_t>(r) * (A.n + 1) + a] += 1u;
+    atomicAdd(A.cnt + static_cast<uint64_t>(r) * (A.n + 1) + a, 1u);
 }
 
 }  // namespace
@@ -135,16 +140,47 @@ __global__ __launch_bounds__(kNvBlock) void nv_sample_kernel(NvArgs A, uint32_t 
     __shared__ uint32_t st_j[kNvBlock];
     const uint32_t tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const uint32_t r = blockIdx.y, g = blockIdx.x;
-    const uint32_t q = g * kNvBlock + tid;
+    // P consecutive lanes per quad (aligned groups within a wavefront), quads in ascending order
+    const uint32_t P = A.P, sub = tid % P;
+    const uint32_t q = g * (kNvBlock / P) + tid / P;
     const bool active = q < A.nq;
+    const bool lead = sub == 0;                         // the lane that carries the quad after its counts are summed
     const uint32_t j0 = 4 * q;
+
+    // The quad's coefficients and signature words, loaded before the step's reduction and all at
+    // once (n is a multiple of 4 and every array starts 16-byte aligned, so a quad is one 16-byte
+    // word per coefficient). A thread past the last quad loads the last quad and discards it.
+    const uint32_t jc = 4 * (active ? q : A.nq - 1);
+    const float4 mu4 = *reinterpret_cast<const float4 *>(A.mu_f + jc);
+    const float4 isk4 = *reinterpret_cast<const float4 *>(A.isk_f + jc);
+    const float4 a4 = *reinterpret_cast<const float4 *>(A.a_f + jc);
+    const float4 b4 = *reinterpret_cast<const float4 *>(A.b_f + jc);
+    const float4 ic4 = *reinterpret_cast<const float4 *>(A.ic_f + jc);
+    const float4 xs4 = *reinterpret_cast<const float4 *>((from_x0 ? A.x0_f : A.xs_f) + jc);
+    uint64_t *sig = A.S_sig + static_cast<uint64_t>(r) * A.n + jc;
+    const ulonglong2 s01 = reinterpret_cast<const ulonglong2 *>(sig)[0];
+    const ulonglong2 s23 = reinterpret_cast<const ulonglong2 *>(sig)[1];
+    uint64_t S4[4] = {s01.x, s01.y, s23.x, s23.y};
+    const bool recorder = g == 0 && tid == 0 && prev_t >= 0;
+    const uint32_t tau_now = recorder ? A.tau[r] : kTauNone;
+    const float mu[4] = {mu4.x, mu4.y, mu4.z, mu4.w}, isk[4] = {isk4.x, isk4.y, isk4.z, isk4.w};
+    const float ca[4] = {a4.x, a4.y, a4.z, a4.w}, cb[4] = {b4.x, b4.y, b4.z, b4.w};
+    const float ic[4] = {ic4.x, ic4.y, ic4.z, ic4.w}, xs[4] = {xs4.x, xs4.y, xs4.z, xs4.w};
 
     if (prev_t >= 0) {
         float gap;
         const uint32_t a = nv_reduce_step(A, r, par ^ 1u, st_r, st_x, st_j, gap);
-        if (g == 0 && tid == 0) nv_record_step(A, r, static_cast<uint64_t>(prev_t), a, gap);
-        if (a > 0 && active && a - 1 >= j0 && a - 1 < j0 + 4)
-            A.S_sig[static_cast<uint64_t>(r) * A.n + (a - 1)] += static_cast<uint64_t>(prev_t) + 1;
+        if (recorder) nv_record_step(A, r, static_cast<uint64_t>(prev_t), a, gap, tau_now);
+        if (a > 0 && active && a - 1 >= j0 && a - 1 < j0 + 4) {
+            // the chosen product's signature absorbs the step (selects, not a dynamic register index)
+            const uint32_t k = a - 1 - j0;
+            const uint64_t add = static_cast<uint64_t>(prev_t) + 1;
+            S4[0] += k == 0 ? add : 0;
+            S4[1] += k == 1 ? add : 0;
+            S4[2] += k == 2 ? add : 0;
+            S4[3] += k == 3 ? add : 0;
+            if (lead) sig[k] = k == 0 ? S4[0] : k == 1 ? S4[1] : k == 2 ? S4[2] : S4[3];
+        }
     }
 
     float x[4], thr[4];
@@ -153,30 +189,34 @@ __global__ __launch_bounds__(kNvBlock) void nv_sample_kernel(NvArgs A, uint32_t 
         x[k] = 0.0f;
         thr[k] = 0.0f;
         if (active) {
-            const uint32_t j = j0 + k;
-            x[k] = from_x0 ? A.x0_f[j]
-                           : A.xs_f[j] * (static_cast<float>(static_cast<double>(A.S_sig[static_cast<uint64_t>(r) * A.n + j])) * cw);
+            x[k] = from_x0 ? xs[k] : xs[k] * (static_cast<float>(static_cast<double>(S4[k])) * cw);
             // sigma_j = 0 stores an infinite scale: the threshold is then +-infinity, and +infinity
             // (every sample counted) where x_j equals the demand exactly
-            thr[k] = (x[k] - A.mu_f[j]) * A.isk_f[j];
+            thr[k] = (x[k] - mu[k]) * isk[k];
             if (thr[k] != thr[k]) thr[k] = INFINITY;
         }
     }
     const PhiloxRow row = philox_row(epoch, r, A.k0);
+    // the quad's samples s = sub, sub + P, ...; the counts are integers, so their sum over the P lanes
+    // is exact whatever the split
     uint32_t count[4] = {0u, 0u, 0u, 0u};
-    for (uint32_t s = 0; s < A.S; ++s) {
+    for (uint32_t s = sub; s < A.S; s += P) {
         const Block4<float> z = normals_block_row(row, s * A.nq + q, A.dom, A.k0, A.k1);
 #pragma unroll
         for (int k = 0; k < 4; ++k) count[k] += (z.z[k] <= thr[k]) ? 1u : 0u;
     }
+    for (uint32_t m = 1; m < P; m <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) count[k] += __shfl_xor(count[k], m, 64);
+    }
     float rmin = INFINITY, gx = 0.0f;
     uint32_t jmin = 0xFFFFFFFFu;
-    if (active) {
+    if (active && lead) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const uint32_t j = j0 + k;
-            const float gj = A.a_f[j] + A.b_f[j] * static_cast<float>(count[k]);
-            const float rj = gj * A.ic_f[j];
+            const float gj = ca[k] + cb[k] * static_cast<float>(count[k]);
+            const float rj = gj * ic[k];
             if (rj < rmin) {
                 rmin = rj;
                 jmin = j;
@@ -219,7 +259,7 @@ __global__ __launch_bounds__(kNvBlock) void nv_step_kernel(NvArgs A, uint64_t t,
     float gap;
     const uint32_t a = nv_reduce_step(A, r, par, smr, smx, smj, gap);
     if (threadIdx.x == 0) {
-        nv_record_step(A, r, t, a, gap);
+        nv_record_step(A, r, t, a, gap, A.tau[r]);
         if (a > 0) A.S_sig[static_cast<uint64_t>(r) * A.n + (a - 1)] += t + 1;
     }
 }

@@ -7,7 +7,17 @@
 
 namespace fw {
 
-constexpr int kNvBlock = 256;                   // threads per workgroup, one quad of products each
+constexpr int kNvBlock = 256;                   // threads per workgroup: kNvBlock / P quads of products
+constexpr uint32_t kNvMaxLanes = 16;            // lanes per quad at most
+
+// Lanes per quad for n/4 quads and R replications: the smallest power of two that gives ~65536
+// threads (a wavefront per SIMD on every compute unit), at most kNvMaxLanes and at most S.
+inline uint32_t nv_lanes_per_quad(uint32_t nq, uint64_t R, uint32_t S)
+{
+    uint32_t P = 1;
+    while (P < kNvMaxLanes && 2 * P <= S && static_cast<uint64_t>(nq) * R * P < 65536u) P *= 2;
+    return P;
+}
 constexpr uint32_t kNvMaxR = 64;
 constexpr uint32_t kNvMaxS = 1024;
 constexpr uint64_t kNvMaxN = 1ull << 24;
@@ -16,6 +26,7 @@ constexpr uint32_t kNvCostChunk = 4096;         // products per workgroup of the
 
 struct NvArgs {
     uint32_t n, nq, S, nwg, R;                  // products, quads, samples per product, workgroups
+    uint32_t P;                                 // lanes per quad (a power of two <= kNvMaxLanes), splitting its samples
     uint32_t k0, k1, dom;                       // Philox key; counter word 3 (domain 4 | instance)
     float C, gap_eps;
     // per product, binary32: threshold scale 1/(sqrt(2 ln 2) sigma), k - v, (h + v)/S, 1/c, C/c, x_0

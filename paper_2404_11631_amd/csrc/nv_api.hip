@@ -25,6 +25,7 @@ fw::NvArgs nv_args(NvState &w, const sim_nv_params *p, uint64_t R, uint64_t T, u
     A.nq = n / 4;
     A.S = p->n_samples;
     A.nwg = w.nwg;
+    A.P = w.P;
     A.R = static_cast<uint32_t>(R);
     A.k0 = static_cast<uint32_t>(seed);
     A.k1 = static_cast<uint32_t>(seed >> 32);
@@ -84,7 +85,9 @@ int sim_run_newsvendor(sim_ctx *ctx, const sim_nv_params *p, uint64_t R, uint64_
     if (!w.ev1) HIP_TRY(ctx, hipEventCreate(&w.ev1));
     const uint32_t n = p->n, nc = p->n_checkpoints;
     const uint32_t nq = n / 4;
-    w.nwg = (nq + fw::kNvBlock - 1) / fw::kNvBlock;
+    w.P = fw::nv_lanes_per_quad(nq, R, p->n_samples);
+    const uint32_t quads_per_wg = fw::kNvBlock / w.P;
+    w.nwg = (nq + quads_per_wg - 1) / quads_per_wg;
     const size_t N = n;
 
     // per product: binary32 coefficients (the normals carry the factor 1/sqrt(2 ln 2)), binary64 for Eq. (6)

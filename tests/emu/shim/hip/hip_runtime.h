@@ -26,6 +26,8 @@ struct float4 { float x, y, z, w; };
 inline float4 make_float4(float x, float y, float z, float w) { return float4{x, y, z, w}; }
 struct uint4 { unsigned x, y, z, w; };
 struct double2 { double x, y; };
+struct ulonglong2 { unsigned long long x, y; };
+template <class T> inline T atomicAdd(T *p, T v) { return std::atomic_ref<T>(*p).fetch_add(v); }
 inline double2 make_double2(double x, double y) { return double2{x, y}; }
 inline unsigned __umulhi(unsigned a, unsigned b) { return static_cast<unsigned>((static_cast<unsigned long long>(a) * b) >> 32); }
 extern thread_local Dim3emu threadIdx;
