@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_reduce.hpp"
+#include "sim.h"
 #include "device_rng.hpp"
 #include "sim_types.hpp"
 #include "wide.hpp"
@@ -53,18 +54,67 @@ __device__ __forceinline__ void half_argmin(float &g, uint32_t &j)
     }
 }
 
-// w_t of four consecutive assets j0..j0+3 and v = sz .* w_t
-__device__ __forceinline__ void wide_iterate(const WideArgs &A, uint32_t r, uint32_t j0, bool active, float cw,
-                                             bool from_w0, float (&w)[4], float (&v)[4])
+// Sum and (value, index) minimum over the 64 lanes of a wavefront, lowest index among equal values.
+__device__ __forceinline__ float wave64_sum(float x)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+__device__ __forceinline__ void wave64_argmin(float &g, uint32_t &j)
+{
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        const float og = __shfl_xor(g, m, 64);
+        const uint32_t oj = __shfl_xor(j, m, 64);
+        if (og < g || (og == g && oj < j)) {
+            g = og;
+            j = oj;
+        }
+    }
+}
+
+// A quad's signature words, scaled sigma and start point, loaded together (d is a multiple of 4 and
+// every array starts 16-byte aligned, so each is one or two 16-byte words); qc is a quad in range.
+struct WideQuad {
+    uint64_t S[4];
+    float sz[4], w0[4];
+};
+
+__device__ __forceinline__ WideQuad wide_load_quad(const WideArgs &A, uint32_t r, uint32_t qc)
+{
+    WideQuad Q;
+    const ulonglong2 *sp = reinterpret_cast<const ulonglong2 *>(A.S + static_cast<uint64_t>(r) * A.d + 4 * qc);
+    const ulonglong2 s01 = sp[0], s23 = sp[1];
+    const float4 sz = *reinterpret_cast<const float4 *>(A.sz_f + 4 * qc);
+    const float4 w0 = *reinterpret_cast<const float4 *>(A.w0_f + 4 * qc);
+    Q.S[0] = s01.x;
+    Q.S[1] = s01.y;
+    Q.S[2] = s23.x;
+    Q.S[3] = s23.y;
+    Q.sz[0] = sz.x;
+    Q.sz[1] = sz.y;
+    Q.sz[2] = sz.z;
+    Q.sz[3] = sz.w;
+    Q.w0[0] = w0.x;
+    Q.w0[1] = w0.y;
+    Q.w0[2] = w0.z;
+    Q.w0[3] = w0.w;
+    return Q;
+}
+
+// w_t of the quad's four assets and v = sz .* w_t (zero for a quad past the last)
+__device__ __forceinline__ void wide_iterate(const WideQuad &Q, bool active, float cw, bool from_w0, float (&w)[4],
+                                             float (&v)[4])
 {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         w[k] = 0.0f;
         v[k] = 0.0f;
         if (active) {
-            w[k] = from_w0 ? A.w0_f[j0 + k]
-                           : static_cast<float>(static_cast<double>(A.S[static_cast<uint64_t>(r) * A.d + j0 + k])) * cw;
-            v[k] = A.sz_f[j0 + k] * w[k];
+            w[k] = from_w0 ? Q.w0[k] : static_cast<float>(static_cast<double>(Q.S[k])) * cw;
+            v[k] = Q.sz[k] * w[k];
         }
     }
 }
@@ -77,47 +127,52 @@ __device__ __forceinline__ void wide_iterate(const WideArgs &A, uint32_t r, uint
 __device__ __forceinline__ uint32_t wide_reduce_step(const WideArgs &A, uint32_t r, uint32_t par, float *smg, float *smw,
                                                      uint32_t *smj, float &gap)
 {
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
     const uint64_t base = (static_cast<uint64_t>(par) * A.R + r) * A.nwg;
     float gmin = INFINITY, gw = 0.0f;
     uint32_t jmin = 0xFFFFFFFFu;
     for (uint32_t g = tid; g < A.nwg; g += kWideBlock) {
         const float x = A.wg_g[base + g];
-        if (x < gmin) {
+        const uint32_t xj = A.wg_j[base + g];
+        if (x < gmin || (x == gmin && xj < jmin)) {
             gmin = x;
-            jmin = A.wg_j[base + g];
+            jmin = xj;
         }
         gw += A.wg_gw[base + g];
     }
-    smg[tid] = gmin;
-    smj[tid] = jmin;
-    smw[tid] = gw;
-    __syncthreads();
-    for (int h = kWideBlock / 2; h > 0; h >>= 1) {
-        if (tid < static_cast<uint32_t>(h)) {
-            const float og = smg[tid + h];
-            const uint32_t oj = smj[tid + h];
-            if (og < smg[tid] || (og == smg[tid] && oj < smj[tid])) {
-                smg[tid] = og;
-                smj[tid] = oj;
-            }
-            smw[tid] += smw[tid + h];
-        }
-        __syncthreads();
+    // within each wavefront, then over the wavefronts in order (the same in every thread)
+    wave64_argmin(gmin, jmin);
+    gw = wave64_sum(gw);
+    if (lane == 0) {
+        smg[wave] = gmin;
+        smj[wave] = jmin;
+        smw[wave] = gw;
     }
-    const float gm = smg[0];
-    const uint32_t a = (gm < 0.0f) ? smj[0] + 1u : 0u;
-    gap = smw[0] - (gm < 0.0f ? gm : 0.0f);
+    __syncthreads();
+    float gm = smg[0], gws = smw[0];
+    uint32_t jm = smj[0];
+    for (int w = 1; w < kWideBlock / 64; ++w) {
+        if (smg[w] < gm || (smg[w] == gm && smj[w] < jm)) {
+            gm = smg[w];
+            jm = smj[w];
+        }
+        gws += smw[w];
+    }
+    const uint32_t a = (gm < 0.0f) ? jm + 1u : 0u;
+    gap = gws - (gm < 0.0f ? gm : 0.0f);
     __syncthreads();                                    // smg/smj/smw may be reused after this
     return a;
 }
 
 // The records of the step of iteration t with vertex a (one thread).
-__device__ __forceinline__ void wide_record_step(const WideArgs &A, uint32_t r, uint64_t t, uint32_t a, float gap)
+// tau_now: the replication's hitting time as read before; the count is a single-writer atomic add,
+// which nothing waits for.
+__device__ __forceinline__ void wide_record_step(const WideArgs &A, uint32_t r, uint64_t t, uint32_t a, float gap,
+                                                 uint32_t tau_now)
 {
-    if (A.tau[r] == kTauNone && gap <= A.gap_eps) A.tau[r] = static_cast<uint32_t>(t);
+    if (tau_now == kTauNone && gap <= A.gap_eps) A.tau[r] = static_cast<uint32_t>(t);
     A.dec[static_cast<uint64_t>(r) * A.T + t] = a;
-    A.cnt[static_cast<uint64_t>(r) * (A.d + 1) + a] += 1u;
+    atomicAdd(A.cnt + static_cast<uint64_t>(r) * (A.d + 1) + a, 1u);
 }
 
 }  // namespace
@@ -136,16 +191,29 @@ __global__ __launch_bounds__(kWideBlock) void wide_sample_kernel(WideArgs A, uin
     const uint32_t q = g * kWideQuads + aq;
     const bool active = q < A.nq;
     const uint32_t j0 = 4 * q;
+    // the quad's signature and coefficients, loaded before the step's reduction (a thread past the
+    // last quad loads the last quad and discards it)
+    WideQuad Q = wide_load_quad(A, r, active ? q : A.nq - 1);
+    const bool recorder = g == 0 && tid == 0 && prev_t >= 0;
+    const uint32_t tau_now = recorder ? A.tau[r] : kTauNone;
     if (prev_t >= 0) {
         float gap;
         const uint32_t a = wide_reduce_step(A, r, par ^ 1u, sm, sm + kWideBlock, st_j, gap);
-        if (g == 0 && tid == 0) wide_record_step(A, r, static_cast<uint64_t>(prev_t), a, gap);
-        if (a > 0 && c == 0 && active && a - 1 >= j0 && a - 1 < j0 + 4)
-            A.S[static_cast<uint64_t>(r) * A.d + (a - 1)] += static_cast<uint64_t>(prev_t) + 1;
-        __syncthreads();                                // the signature is read below by all chunks
+        if (recorder) wide_record_step(A, r, static_cast<uint64_t>(prev_t), a, gap, tau_now);
+        if (a > 0 && active && a - 1 >= j0 && a - 1 < j0 + 4) {
+            // every chunk's copy of the quad absorbs the step; the first chunk stores it
+            const uint32_t k = a - 1 - j0;
+            const uint64_t add = static_cast<uint64_t>(prev_t) + 1;
+            Q.S[0] += k == 0 ? add : 0;
+            Q.S[1] += k == 1 ? add : 0;
+            Q.S[2] += k == 2 ? add : 0;
+            Q.S[3] += k == 3 ? add : 0;
+            if (c == 0)
+                A.S[static_cast<uint64_t>(r) * A.d + (a - 1)] = k == 0 ? Q.S[0] : k == 1 ? Q.S[1] : k == 2 ? Q.S[2] : Q.S[3];
+        }
     }
     float w[4], v[4];
-    wide_iterate(A, r, j0, active, cw, from_w0 != 0, w, v);
+    wide_iterate(Q, active, cw, from_w0 != 0, w, v);
 
     const PhiloxRow row = philox_row(epoch, r, A.k0);
     float s1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -206,18 +274,31 @@ __global__ __launch_bounds__(kWideBlock) void wide_gradient_kernel(WideArgs A, u
                                                                    int from_w0)
 {
     __shared__ float sm[kWideBlock * 4];
+    __shared__ float s_dot[SIM_WIDE_MAX_N];
     const uint32_t tid = threadIdx.x, c = tid / kWideQuads, aq = tid % kWideQuads;
     const uint32_t r = blockIdx.y, g = blockIdx.x;
     const uint32_t q = g * kWideQuads + aq;
     const bool active = q < A.nq;
     const uint32_t j0 = 4 * q;
 
-    const PhiloxRow row = philox_row(epoch, r, A.k0);
+    // every load of the launch before the first wait: the quad's signature, coefficients and s1, the
+    // replication's s1'v, and the sample dot products (into LDS)
+    const uint32_t qc = active ? q : A.nq - 1;
+    const WideQuad Q = wide_load_quad(A, r, qc);
+    const float4 s1q = *reinterpret_cast<const float4 *>(A.s1 + static_cast<uint64_t>(r) * A.d + 4 * qc);
+    const float4 c1q = *reinterpret_cast<const float4 *>(A.c1_f + 4 * qc);
+    const float4 c2q = *reinterpret_cast<const float4 *>(A.c2_f + 4 * qc);
+    const float4 muq = *reinterpret_cast<const float4 *>(A.mu_f + 4 * qc);
+    const float qn_r = A.qn[r];
     const float *dot = A.dot + static_cast<uint64_t>(r) * A.N;
+    for (uint32_t i = tid; i < E.n; i += kWideBlock) s_dot[i] = dot[i];
+    __syncthreads();
+
+    const PhiloxRow row = philox_row(epoch, r, A.k0);
     float s2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
     for (uint32_t i = c; i < E.n; i += kWideChunks) {
         const Block4<float> z = normals_block_row(row, i * A.nq + q, A.dom, A.k0, A.k1);
-        const float di = dot[i];
+        const float di = s_dot[i];
 #pragma unroll
         for (int k = 0; k < 4; ++k) s2[k] = fmaf(z.z[k], di, s2[k]);
     }
@@ -226,8 +307,10 @@ __global__ __launch_bounds__(kWideBlock) void wide_gradient_kernel(WideArgs A, u
     __syncthreads();
     if (c == 0) {
         float w[4], v[4];
-        wide_iterate(A, r, j0, active, cw, from_w0 != 0, w, v);
-        const float qn = A.qn[r] * E.inv_n;
+        wide_iterate(Q, active, cw, from_w0 != 0, w, v);
+        const float qn = qn_r * E.inv_n;
+        const float s1a[4] = {s1q.x, s1q.y, s1q.z, s1q.w}, c1a[4] = {c1q.x, c1q.y, c1q.z, c1q.w};
+        const float c2a[4] = {c2q.x, c2q.y, c2q.z, c2q.w}, mua[4] = {muq.x, muq.y, muq.z, muq.w};
         float gmin = INFINITY, gw = 0.0f;
         uint32_t jmin = 0xFFFFFFFFu;
 #pragma unroll
@@ -236,8 +319,8 @@ __global__ __launch_bounds__(kWideBlock) void wide_gradient_kernel(WideArgs A, u
             for (int cc = 1; cc < kWideChunks; ++cc) s2k += sm[(cc * kWideQuads + aq) * 4 + k];
             if (active) {
                 const uint32_t j = j0 + k;
-                const float s1k = A.s1[static_cast<uint64_t>(r) * A.d + j];
-                const float gj = (A.c2_f[j] * E.sc2) * (s2k - s1k * qn) - A.mu_f[j] - (A.c1_f[j] * E.sc1) * s1k;
+                const float s1k = s1a[k];
+                const float gj = (c2a[k] * E.sc2) * (s2k - s1k * qn) - mua[k] - (c1a[k] * E.sc1) * s1k;
                 if (gj < gmin) {
                     gmin = gj;
                     jmin = j;
@@ -266,7 +349,7 @@ __global__ __launch_bounds__(kWideBlock) void wide_step_kernel(WideArgs A, uint6
     float gap;
     const uint32_t a = wide_reduce_step(A, r, par, smg, smw, smj, gap);
     if (threadIdx.x == 0) {
-        wide_record_step(A, r, t, a, gap);
+        wide_record_step(A, r, t, a, gap, A.tau[r]);
         if (a > 0) A.S[static_cast<uint64_t>(r) * A.d + (a - 1)] += t + 1;
     }
 }
