@@ -91,7 +91,7 @@ struct NvState {
 struct NvLpState {
     bool have = false;
     sim_nv_params params{};               // pointers cleared
-    uint32_t M = 0, nwg = 0;
+    uint32_t M = 0, nwg = 0, P = 1;       // resource rows; gradient workgroups; lanes per quad
     uint64_t R = 0, T = 0;
     DevBuf prod_d, Am, Cv, x, g, rec_basis, rec_value, rec_piv, tau, origin, cost_part, fval, stats, origin_total;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;

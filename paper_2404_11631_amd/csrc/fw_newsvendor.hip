@@ -391,45 +391,89 @@ __device__ __forceinline__ double nv_lp_vertex(const NvLpArgs &A, uint32_t r, ui
 
 }  // namespace
 
-// Iteration t's gradient (grid: workgroups of kNvBlock threads over the product quads, by
-// replication). With fold_prev each thread first moves its four products to x_t with the vertex of
-// iteration t - 1.
+// Iteration t's gradient (grid: workgroups of kNvBlock threads over the product quads, P consecutive
+// lanes per quad, by replication). With fold_prev each quad is first moved to x_t with the vertex of
+// iteration t - 1. Every load is issued before the first wait: the previous vertex's basis and
+// values, the quad's iterate and coefficients. The quad's S samples are split over its P lanes and
+// the integer counts summed exactly, so the gradient does not depend on P.
 __global__ __launch_bounds__(kNvBlock) void nv_lp_gradient_kernel(NvLpArgs A, uint64_t t, uint32_t epoch,
                                                                   int fold_prev)
 {
-    const uint32_t r = blockIdx.y;
-    const uint32_t q = blockIdx.x * kNvBlock + threadIdx.x;
-    if (q >= A.nq) return;
-    const uint32_t j0 = 4 * q;
+    const uint32_t r = blockIdx.y, tid = threadIdx.x;
+    const uint32_t P = A.P, sub = tid % P;
+    const uint32_t q = blockIdx.x * (kNvBlock / P) + tid / P;
+    const bool active = q < A.nq;
+    const bool lead = sub == 0;                         // stores the quad's iterate and gradient
+    const uint32_t j0 = 4 * (active ? q : A.nq - 1);    // past the last quad: the last, discarded
     double *x = A.x + static_cast<uint64_t>(r) * A.n;
-    double xv[4], thr[4];
+
+    uint32_t vb[kNvLpMaxM];
+    double vv[kNvLpMaxM];
+    if (fold_prev) {
+        const uint64_t o = (static_cast<uint64_t>(r) * A.T + (t - 1)) * A.M;
+#pragma unroll
+        for (uint32_t i = 0; i < kNvLpMaxM; ++i) {
+            vb[i] = A.rec_basis[o + (i < A.M ? i : 0)];
+            vv[i] = A.rec_value[o + (i < A.M ? i : 0)];
+        }
+    }
+    double xv[4], mu[4], isk[4], km[4], hv[4];
+    auto load_quad = [&](const double *p, double (&v)[4]) {
+        const double2 a = reinterpret_cast<const double2 *>(p + j0)[0];
+        const double2 b = reinterpret_cast<const double2 *>(p + j0)[1];
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = b.x;
+        v[3] = b.y;
+    };
+    load_quad(x, xv);
+    load_quad(A.mu_d, mu);
+    load_quad(A.isk_d, isk);
+    load_quad(A.km_d, km);
+    load_quad(A.hv_d, hv);
+
+    double thr[4];
     const double gamma = fold_prev ? 2.0 / (static_cast<double>(t - 1) + 2.0) : 0.0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const uint32_t j = j0 + k;
-        xv[k] = x[j];
         if (fold_prev) {
-            xv[k] = nv_lp_move(xv[k], nv_lp_vertex(A, r, t - 1, j), gamma);
-            x[j] = xv[k];
+            // s_j of the previous vertex: the basic value where the basis holds product j, else 0
+            double sj = 0.0;
+#pragma unroll
+            for (uint32_t i = 0; i < kNvLpMaxM; ++i)
+                if (i < A.M && vb[i] == j0 + k) sj = vv[i];
+            xv[k] = nv_lp_move(xv[k], sj, gamma);
         }
         // sigma_j = 0 has an infinite scale: the threshold is +-infinity, and +infinity (every sample
         // counted) where x_j equals the demand exactly
-        thr[k] = (xv[k] - A.mu_d[j]) * A.isk_d[j];
+        thr[k] = (xv[k] - mu[k]) * isk[k];
         if (thr[k] != thr[k]) thr[k] = INFINITY;
+    }
+    // every thread of the workgroup has read x (its value is already used above) before the moved
+    // iterate is stored: lanes of the same quad and, past the last quad, lanes reading the last one
+    if (fold_prev) __syncthreads();
+    if (fold_prev && active && lead) {
+        reinterpret_cast<double2 *>(x + j0)[0] = make_double2(xv[0], xv[1]);
+        reinterpret_cast<double2 *>(x + j0)[1] = make_double2(xv[2], xv[3]);
     }
     const PhiloxRow row = philox_row(epoch, r, A.k0);
     uint32_t count[4] = {0u, 0u, 0u, 0u};
-    for (uint32_t s = 0; s < A.S; ++s) {
-        const Block4<float> z = normals_block_row(row, s * A.nq + q, A.dom, A.k0, A.k1);
+    for (uint32_t s = sub; s < A.S; s += P) {
+        const Block4<float> z = normals_block_row(row, s * A.nq + (j0 / 4), A.dom, A.k0, A.k1);
 #pragma unroll
         for (int k = 0; k < 4; ++k) count[k] += (static_cast<double>(z.z[k]) <= thr[k]) ? 1u : 0u;
     }
-    double *g = A.g + static_cast<uint64_t>(r) * A.n;
+    for (uint32_t m = 1; m < P; m <<= 1) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t j = j0 + k;
-        // (k - v) + ((h + v) count) / S, each operation rounded on its own
-        g[j] = nv_lp_grad(A.km_d[j], A.hv_d[j], count[k], A.S);
+        for (int k = 0; k < 4; ++k) count[k] += __shfl_xor(count[k], m, 64);
+    }
+    if (active && lead) {
+        double gq[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) gq[k] = nv_lp_grad(km[k], hv[k], count[k], A.S);   // (k - v) + ((h + v) count) / S
+        double *g = A.g + static_cast<uint64_t>(r) * A.n;
+        reinterpret_cast<double2 *>(g + j0)[0] = make_double2(gq[0], gq[1]);
+        reinterpret_cast<double2 *>(g + j0)[1] = make_double2(gq[2], gq[3]);
     }
 }
 

@@ -69,6 +69,7 @@ constexpr uint32_t kNvLpMaxM = 8;
 
 struct NvLpArgs {
     uint32_t n, nq, S, nwg, R, M;
+    uint32_t P;                                 // lanes per quad in the gradient launch (nv_lanes_per_quad)
     uint32_t k0, k1, dom;                       // Philox key; counter word 3 (domain 4 | instance)
     uint32_t max_pivots;
     double gap_eps;

@@ -241,7 +241,8 @@ int sim_run_newsvendor_lp(sim_ctx *ctx, const sim_nv_params *p, const sim_nv_con
     if (!w.ev1) HIP_TRY(ctx, hipEventCreate(&w.ev1));
     const uint32_t n = p->n, nc = p->n_checkpoints, M = con->n_resources;
     const size_t N = n;
-    w.nwg = (n / 4 + fw::kNvBlock - 1) / fw::kNvBlock;
+    w.P = fw::nv_lanes_per_quad(n / 4, R, p->n_samples);
+    w.nwg = (n / 4 + fw::kNvBlock / w.P - 1) / (fw::kNvBlock / w.P);
 
     // per product, binary64: mean, threshold scale, k - v, h + v, sigma, k, h, v, x_0
     const double kappa = fw::kBoxMullerScale;
@@ -293,6 +294,7 @@ int sim_run_newsvendor_lp(sim_ctx *ctx, const sim_nv_params *p, const sim_nv_con
     A.nq = n / 4;
     A.S = p->n_samples;
     A.nwg = w.nwg;
+    A.P = w.P;
     A.R = static_cast<uint32_t>(R);
     A.M = M;
     A.k0 = static_cast<uint32_t>(seed);

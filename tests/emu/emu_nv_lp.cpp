@@ -75,7 +75,8 @@ extern "C" int emu_run_nv_lp(const sim_nv_params *p, const sim_nv_constraints *c
     A.n = n;
     A.nq = n / 4;
     A.S = p->n_samples;
-    A.nwg = (n / 4 + kNvBlock - 1) / kNvBlock;
+    A.P = nv_lanes_per_quad(n / 4, R, p->n_samples);
+    A.nwg = (n / 4 + kNvBlock / A.P - 1) / (kNvBlock / A.P);
     A.R = static_cast<uint32_t>(R);
     A.M = M;
     A.k0 = static_cast<uint32_t>(seed);
