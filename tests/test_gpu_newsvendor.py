@@ -143,3 +143,18 @@ def test_paper_shape_sampled(ctx):
     assert np.array_equal(g["wsum"][0].astype(np.float64), Ssig)
     xT = xs * Ssig * (2.0 / (T * (T + 1.0)))
     assert close(g["y"][0], O.cost(xT), 1e-11, 1e-9)
+
+
+def test_newsvendor_lane_split_invariance(ctx):
+    """The sample launch splits each quad's S samples over P lanes, P chosen from n/4 and R (here 16
+    at R = 1 and 4 at R = 8 for 1e4 products). The counts are integers, so replication 0's decisions,
+    counts, signatures and objective are the same bits either way; the stream of a replication does
+    not depend on R."""
+    inst = workloads.newsvendor_instance(6, 0, 10_000)
+    ctx.run_newsvendor(inst, 1, 200, 9, S=25, checkpoints=(100, 200))
+    a = ctx.nv_paths()
+    ctx.run_newsvendor(inst, 8, 200, 9, S=25, checkpoints=(100, 200))
+    b = ctx.nv_paths()
+    assert np.array_equal(a["decisions"][0], b["decisions"][0])
+    assert np.array_equal(a["cnt"][0], b["cnt"][0]) and np.array_equal(a["wsum"][0], b["wsum"][0])
+    assert a["y"][0] == b["y"][0] and np.array_equal(a["f_ckpt"][:, 0], b["f_ckpt"][:, 0])

@@ -108,3 +108,19 @@ def test_newsvendor_lp_errors(ctx):
         ctx.run_newsvendor_lp(inst, A0, C, 1, 10, 0, S=5)     # a product using no resource
     with pytest.raises(sim.SimError):
         ctx.run_newsvendor_lp(inst, A, -C, 1, 10, 0, S=5)
+
+
+def test_newsvendor_lp_lane_split_invariance(ctx):
+    """The gradient launch splits each quad's S samples over P lanes (16 at R = 1 and 4 at R = 8 for
+    1e4 products); the integer counts make replication 0's gradients, hence its bases, basic values,
+    pivots and iterate, the same bits either way."""
+    n, m = 10_000, 3
+    inst = workloads.newsvendor_instance(7, 0, n)
+    A, C = workloads.newsvendor_constraints(7, 0, n, m)
+    ctx.run_newsvendor_lp(inst, A, C, 1, 60, 5, S=25, checkpoints=(60,))
+    a = ctx.nv_lp_paths()
+    ctx.run_newsvendor_lp(inst, A, C, 8, 60, 5, S=25, checkpoints=(60,))
+    b = ctx.nv_lp_paths()
+    assert np.array_equal(a["basis"][0], b["basis"][0]) and np.array_equal(a["value"][0], b["value"][0])
+    assert np.array_equal(a["pivots"][0], b["pivots"][0]) and np.array_equal(a["x"][0], b["x"][0])
+    assert a["y"][0] == b["y"][0]
