@@ -113,14 +113,16 @@ def test_sqn_edge_cases(ctx, case):
         assert np.all(g["pairs"] <= 1)
 
 
-def test_sqn_single_feature(ctx):
+@pytest.mark.parametrize("split", [False, True], ids=["one_workgroup", "split"])
+def test_sqn_single_feature(ctx, split):
     """One feature: a window whose Hessian rows all have x = 0 gives y = 0, so gamma = s'y / y'y is
     0/0 and the method (which uses every pair as formed) breaks down; the device must break down in
-    the same replication as the oracle, with the same pair count, and agree where it does not."""
+    the same replication as the oracle, with the same pair count, and agree where it does not (on
+    both paths)."""
     X, z = workloads.sqn_dataset(30, 1, 40)
     ctx.sqn_load(X, z)
     O = oracle.SqnOracle(X, z, L=3, M=2, b=5, bH=7, seed=2)
-    ctx.run_sqn(2, 50, 2, L=3, M=2, b=5, bH=7)
+    ctx.run_sqn(2, 50, 2, L=3, M=2, b=5, bH=7, split=split)
     g = ctx.sqn_paths()
     for r in range(2):
         o = O.run(r, 50)
