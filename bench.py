@@ -483,14 +483,15 @@ def _pool(parts):
     return n, m, ss / max(1, n - 1)
 
 
-SPLIT_LANES = 16          # lanes per path for small plain stages (assets x sample chunks)
+WAVE_MAX_PATHS = 1024     # plain stages up to here: a path per wavefront (64 lanes, an asset per lane)
+SPLIT_LANES = 16          # lanes per path for larger small plain stages (assets x sample chunks)
 SPLIT_MAX_PATHS = 8192    # above this the fused kernel (one lane per path) fills the chip
 
 
 def cv_leg(ctx, sim, w, mu, sigma, args):
     """Wall time to a 95% CI half-width h for E f(w_T) on the paper-scale instance (T = 1e4, d = N =
     10): plain Monte Carlo, the MLP control variate, and a linear (least-squares) control variate
-    on the same d+2 features. Each form runs stages of fresh paths (at least 4,096 per stage),
+    on the same d+2 features. Each form runs stages of fresh paths (at least 1,024 per stage),
     pools them, and stops at the first stage after which its realized half-width is <= h; the next
     stage is sized from the pooled variance. The wall time covers every stage (for the MLP form:
     features, surrogate evaluation and draws from the features' known law; for the linear form:
@@ -502,9 +503,10 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
     Y_lin = mean(Y - b'x). Reported at h = 1e-3 and at the h for which plain Monte Carlo needs
     about 1e6 paths (below ~1e5 paths every form is bound by one path's latency).
 
-    The plain form runs a stage of at most SPLIT_MAX_PATHS paths on the batched tile kernel with
-    SPLIT_LANES lanes per path (one path's latency is then shorter), larger stages on the fused
-    kernel; `plain_one_lane` is the same estimator always on the fused kernel, for comparison."""
+    The plain form runs a stage of at most WAVE_MAX_PATHS paths with a path per wavefront, of at most
+    SPLIT_MAX_PATHS paths on the batched tile kernel with SPLIT_LANES lanes per path (one path's
+    latency is then shorter), larger stages on the fused kernel; `plain_one_lane` is the same
+    estimator always on the fused kernel, for comparison. Stages hold at least 1,024 paths."""
     import numpy as np
     import torch
 
@@ -513,7 +515,7 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
     p = sim.Problem(mu=mu, sigma=sigma, N=N, M=w["M"], precision=sim.FP32, checkpoints=(T,))
     cvw = __import__("paper_2404_11631_amd.workloads", fromlist=["WORKLOADS"]).WORKLOADS["control_variate"]
     eval_seed = cvw["seed"]
-    R_min = 4096
+    R_min = 1024
 
     def sync_time():
         torch.cuda.synchronize()
@@ -551,12 +553,12 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
 
     def plain_stage(R, seed):
         # A stage this small leaves most SIMDs idle on the fused kernel (one lane per path), and each
-        # path's T dependent iterations set the wall time: spread each path over 16 lanes of the
-        # batched tile kernel instead (assets x sample chunks). Larger stages fill the chip and
-        # take the fused kernel, which has the higher throughput.
+        # path's T dependent iterations set the wall time: spread each path over a wavefront (up to
+        # WAVE_MAX_PATHS paths, one wavefront per SIMD) or over 16 lanes of the batched tile kernel.
+        # Larger stages fill the chip and take the fused kernel, which has the higher throughput.
         if R > SPLIT_MAX_PATHS:
             return plain_one_lane_stage(R, seed)
-        ctx.run_batch([p], [R], [T], seed=seed, lanes_per_rep=[SPLIT_LANES])
+        ctx.run_batch([p], [R], [T], seed=seed, lanes_per_rep=[64 if R <= WAVE_MAX_PATHS else SPLIT_LANES])
         st = ctx.batch_stats(0)
         return (R, st.mean, st.var), None
 
@@ -594,7 +596,7 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
         return {"R": n, "stages": k, "mean": m, "ci95": ci, "met": ci <= h, "wall_s": wall,
                 "R_aux": sum(x[0] for x in aux) if aux else 0}
 
-    plain_stage(R_min, eval_seed + 9)   # first use of the tile kernel in this process, untimed
+    plain_stage(R_min, eval_seed + 9)   # first use of the batched kernels in this process, untimed
 
     # the linear form's rho^2 on fresh paths (its own held-out check)
     ctx.run(pf, pilot_R, T, eval_seed + 7)
@@ -609,7 +611,8 @@ def cv_leg(ctx, sim, w, mu, sigma, args):
            "variance_ratio_mlp": cs.var_plain / max(cs.var_resid, 1e-300),
            "variance_ratio_linear": 1.0 / max(1.0 - rho2_lin, 1e-300), "aux_per_path": ratio,
            "aux_cost_per_path": c_aux, "min_paths_per_stage": R_min,
-           "plain_split": {"lanes_per_path": SPLIT_LANES, "max_paths": SPLIT_MAX_PATHS}, "targets": []}
+           "plain_split": {"wave_max_paths": WAVE_MAX_PATHS, "lanes_per_path": SPLIT_LANES,
+                           "max_paths": SPLIT_MAX_PATHS}, "targets": []}
     for h in (1e-3, 1.96 * s_plain / 1000.0):
         row = {"h": h}
         for name, stage, seed0 in (("plain", plain_stage, eval_seed + 3), ("cv", mlp_stage, eval_seed + 4),

@@ -36,7 +36,7 @@ constexpr int kLaneAssets = 8;                 // assets held by one lane
 // Pa = 4): with areas 32 Pa floats apart every lane of a write or read instruction would fall in
 // the same few of the 64 banks (16- to 32-way conflicts); the padded stride leaves at most two
 // lanes per bank for every pattern the kernel issues (checked over all d, rounds and offsets).
-constexpr int kStageFloats = 2112;   // max over Pa of (64 / Pa) x stride
+constexpr int kStageFloats = kBatchStageFloats;   // max over Pa of (64 / Pa) x stride
 // rows of a tile's coefficient table in LDS (binary32, indexed by asset, zero past d)
 constexpr int kCoefSz = 0, kCoefC1 = 1, kCoefC2 = 2, kCoefMu = 3, kCoefW0 = 4, kCoefRows = 5;
 __device__ __forceinline__ uint32_t stage_stride(uint32_t Pa) { return 32u * Pa + (Pa == 4u ? 3u : 1u); }
@@ -390,6 +390,183 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
     }
 }
 
+// Sum over the 32 lanes of each half wavefront (every lane gets its half's sum).
+__device__ __forceinline__ float half_sum32(float x)
+{
+#pragma unroll
+    for (int m = 1; m < 32; m <<= 1) x += __shfl_xor(x, m, 32);
+    return x;
+}
+
+__device__ __forceinline__ double half_sum32(double x)
+{
+#pragma unroll
+    for (int m = 1; m < 32; m <<= 1) x += __shfl_xor(x, m, 32);
+    return x;
+}
+
+// One replication per wavefront (every tile of P = 64 lanes, Gaussian noise, N d + 3 <= the
+// staging area): lane j < d holds asset j (d <= 32, so the assets sit in the first half wavefront).
+// An iteration draws the epoch's N d normals into LDS (a Philox block per lane at a time), lane i
+// forms sample i's dot product with v = sz .* w, lane j the sums over the samples of z_ij and
+// z_ij (z_i'v); the gradient, its minimum (lowest index among equal values) and g'w are reduced
+// over the first half wavefront. Same formulas as the tile kernel, summed in a different order.
+__device__ __forceinline__ void run_wave(const BatchBuffers &B, const Tile tile, float *zs, float *vs, float *dots)
+{
+    const InstanceDesc *P = B.inst + tile.inst;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t r = tile.rep0;
+    const uint32_t d = P->d, N = P->N, M = P->M, nd = N * d, nb = (nd + 3) / 4;
+    const uint64_t T = P->T;
+    const uint32_t k0 = static_cast<uint32_t>(P->seed), k1 = static_cast<uint32_t>(P->seed >> 32);
+    const uint32_t dom = P->instance & 0xFFFFFFu;
+    const uint32_t n_ckpt = P->n_ckpt;
+    const bool logged = lane == 0 && (P->flags & 2u) && (static_cast<uint64_t>(r) - P->log_begin) < P->log_count;
+    const uint64_t log_count = P->log_count, log_at = P->dlog_base + (static_cast<uint64_t>(r) - P->log_begin);
+    const bool in = lane < d;
+    const uint32_t jc = in ? lane : 0u;
+    const float sz = in ? P->sz_f[jc] : 0.0f, c1 = P->c1_f[jc], c2 = P->c2_f[jc], mu = P->mu_f[jc];
+    const float w0 = (in && P->has_w0) ? P->w0_f[jc] : 0.0f;
+    const double sig_d = in ? P->sig_d[jc] : 0.0, mu_d = in ? P->mu_d[jc] : 0.0, lambda = P->lambda;
+    const float inv_n = P->inv_n_f, gap_eps = static_cast<float>(P->gap_eps);
+
+    uint32_t S = 0u, cnt = 0u, cnt0 = 0u, hib = 0u;
+    uint32_t tau = kTauNone, ck = 0, epoch = 0, m_in_epoch = 0;
+    uint64_t next_ckpt = n_ckpt ? P->ckpt[0] : 0;
+    // f(w) at w = c S, FP64 (Eq. (3), diagonal Sigma), summed over the assets' lanes
+    auto objective = [&](double c) {
+        const double w = (static_cast<double>(S) + (hib ? 4294967296.0 : 0.0)) * c;
+        const double sw = sig_d * w;
+        const double quad = half_sum32(in ? sw * sw : 0.0);
+        const double lin = half_sum32(in ? mu_d * w : 0.0);
+        return fma(lambda, quad, -lin);
+    };
+
+    for (uint64_t t = 0; t < T; ++t) {
+        const float cw = t == 0 ? 0.0f
+                                : static_cast<float>(2.0 / (static_cast<double>(t) * static_cast<double>(t + 1)));
+        const float w = (t == 0) ? w0 : (static_cast<float>(S) + (hib ? 4294967296.0f : 0.0f)) * cw;
+        const float v = sz * w;
+        if (lane < 32) vs[lane] = v;
+        const PhiloxRow row = philox_row(epoch, r, k0);
+        for (uint32_t b = lane; b < nb; b += kWave) {
+            const Block4<float> q = normals_block_row(row, b, dom, k0, k1);
+            zs[4 * b + 0] = q.z[0];
+            zs[4 * b + 1] = q.z[1];
+            zs[4 * b + 2] = q.z[2];
+            zs[4 * b + 3] = q.z[3];
+        }
+        wave_lds_order();
+        for (uint32_t i = lane; i < N; i += kWave) {
+            float dot = 0.0f;
+#pragma unroll 8
+            for (uint32_t j = 0; j < d; ++j) dot = fmaf(zs[i * d + j], vs[j], dot);
+            dots[i] = dot;
+        }
+        wave_lds_order();
+        float s1 = 0.0f, s2 = 0.0f;
+        if (in) {
+#pragma unroll 8
+            for (uint32_t i = 0; i < N; ++i) {
+                const float z = zs[i * d + lane];
+                s1 += z;
+                s2 = fmaf(z, dots[i], s2);
+            }
+        }
+        wave_lds_order();                               // zs, vs and dots are rewritten next iteration
+        const float qn = half_sum32(s1 * v) * inv_n;
+        float g = INFINITY;
+        uint32_t jg = 0xFFFFFFFFu;
+        if (in) {
+            g = fmaf(-c1, s1, fmaf(c2, fmaf(-s1, qn, s2), -mu));
+            jg = lane;
+        }
+        const float gw = half_sum32(in ? g * w : 0.0f);
+#pragma unroll
+        for (int m = 1; m < 32; m <<= 1) {
+            const float og = __shfl_xor(g, m, 32);
+            const uint32_t oj = __shfl_xor(jg, m, 32);
+            if (og < g || (og == g && oj < jg)) {
+                g = og;
+                jg = oj;
+            }
+        }
+        const uint32_t a = (g < 0.0f) ? jg + 1 : 0u;
+        const float gap = gw - (g < 0.0f ? g : 0.0f);
+        if (tau == kTauNone && gap <= gap_eps) tau = static_cast<uint32_t>(t);
+        if (logged) B.dlog[log_at + t * log_count] = static_cast<uint8_t>(a);
+        // step 2/(t+2): the signature absorbs the update
+        cnt0 += (a == 0u) ? 1u : 0u;
+        if (a == lane + 1) {
+            const uint32_t now = S + static_cast<uint32_t>(t + 1);
+            if (now < S) hib = 1u;
+            S = now;
+            cnt += 1u;
+        }
+        if (t + 1 == next_ckpt) {
+            const double f = objective(2.0 / (static_cast<double>(t + 1) * static_cast<double>(t + 2)));
+            if (lane == 0) B.fck[static_cast<uint64_t>(ck) * B.total_R + P->path_base + r] = f;
+            ++ck;
+            next_ckpt = ck < n_ckpt ? P->ckpt[ck] : 0;
+        }
+        if (++m_in_epoch == M) {
+            m_in_epoch = 0;
+            ++epoch;
+        }
+    }
+    const double y = objective(2.0 / (static_cast<double>(T) * static_cast<double>(T + 1)));
+
+    if (B.y) {
+        const uint64_t R = P->R;
+        if (lane == 0) {
+            B.y[P->path_base + r] = y;
+            B.tau[P->path_base + r] = tau;
+            B.cnt[P->cnt_base + r] = cnt0;
+        }
+        if (in) {
+            B.cnt[P->cnt_base + (static_cast<uint64_t>(lane) + 1) * R + r] = cnt;
+            B.wsum[P->wsum_base + static_cast<uint64_t>(lane) * R + r] =
+                static_cast<uint64_t>(S) | (static_cast<uint64_t>(hib) << 32);
+        }
+    }
+
+    // the tile's partial record (one replication): its streams, extremes, decision totals and tau
+    TilePartial &out = B.partials[tile.slot];
+    if (lane == 0) {
+        for (uint32_t s = 0; s < kTileStreams; ++s) {
+            double *o = out.f + s * kStreamFields;
+            if (s >= 1 + 2 * n_ckpt) {
+                for (int f = 0; f < kStreamFields; ++f) o[f] = 0.0;
+                continue;
+            }
+            double x;
+            bool valid = true;
+            if (s == 0) {
+                x = y;
+            } else if (s <= n_ckpt) {
+                x = B.fck[static_cast<uint64_t>(s - 1) * B.total_R + P->path_base + r];
+            } else {
+                const double f = B.fck[static_cast<uint64_t>(s - 1 - n_ckpt) * B.total_R + P->path_base + r];
+                valid = (f != 0.0);
+                const double e = valid ? (f - y) / f : 0.0;
+                x = e * e;
+            }
+            if (!valid) x = 0.0;
+            o[0] = x;
+            o[1] = 0.0;
+            o[2] = x * x;
+            o[3] = fma(x, x, -(x * x));
+            o[4] = valid ? 1.0 : 0.0;
+        }
+        out.ymin = y;
+        out.ymax = y;
+        out.dec[0] = cnt0;
+        out.tau_count = tau != kTauNone ? 1u : 0u;
+        out.tau_sum = tau != kTauNone ? tau : 0u;
+    }
+    if (lane < static_cast<uint32_t>(kBatchMaxD)) out.dec[lane + 1] = in ? cnt : 0u;
+}
+
 // One wavefront per tile, every tile of the batch, longest first.
 __global__ __launch_bounds__(kWave) void fw_tile_kernel(BatchBuffers B)
 {
@@ -397,6 +574,16 @@ __global__ __launch_bounds__(kWave) void fw_tile_kernel(BatchBuffers B)
     __shared__ float coef[kCoefRows][kBatchMaxD];
     const Tile tile = B.tiles[blockIdx.x];
     run_tile(B, tile, stage, coef);
+}
+
+// One replication per wavefront, every tile of a batch that qualifies (BatchBuffers.wave_mode).
+__global__ __launch_bounds__(kWave) void fw_wave_kernel(BatchBuffers B)
+{
+    __shared__ float zs[kStageFloats];
+    __shared__ float vs[32];
+    __shared__ float dots[kStageFloats];
+    const Tile tile = B.tiles[blockIdx.x];
+    run_wave(B, tile, zs, vs, dots);
 }
 
 // One workgroup per instance: its tile slots in order.
@@ -454,7 +641,10 @@ __global__ __launch_bounds__(kBlock) void fw_batch_reduce(BatchBuffers B)
 // the tile kernel over every tile, then the per-instance reduction, in stream order
 int launch_fw_batch(const BatchBuffers &B, hipStream_t stream)
 {
-    if (B.n_tiles) hipLaunchKernelGGL(fw_tile_kernel, dim3(B.n_tiles), dim3(kWave), 0, stream, B);
+    if (B.n_tiles) {
+        if (B.wave_mode) hipLaunchKernelGGL(fw_wave_kernel, dim3(B.n_tiles), dim3(kWave), 0, stream, B);
+        else hipLaunchKernelGGL(fw_tile_kernel, dim3(B.n_tiles), dim3(kWave), 0, stream, B);
+    }
     hipLaunchKernelGGL(fw_batch_reduce, dim3(B.n_inst), dim3(kBlock), 0, stream, B);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }

@@ -871,6 +871,13 @@ static int plan_batch_impl(char *err, uint32_t n_inst, const sim_params *p, cons
             cost[k] = c;
         }
     }
+    // the one-wavefront form (a replication per wavefront, an asset per lane) when every instance
+    // asks for 64 lanes per replication, has Gaussian noise and its N d normals fit the staging area
+    out.wave_mode = n_tiles > 0;
+    for (uint32_t i = 0; i < n_inst; ++i)
+        if (out.P[i] != 64 || p[i].noise != SIM_NOISE_GAUSS ||
+            (uint64_t)p[i].n_samples * p[i].d + 3 > kBatchStageFloats)
+            out.wave_mode = false;
     std::vector<uint32_t> order(n_tiles);
     std::iota(order.begin(), order.end(), 0u);
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });

@@ -78,6 +78,7 @@ struct BatchPlan {
     std::vector<double> fstar;
     std::vector<Tile> tiles;             // longest first
     uint32_t n_tiles = 0, max_ckpt = 1;
+    bool wave_mode = false;              // every instance at 64 lanes per replication, Gaussian, N d small
     uint64_t total_R = 0, total_steps = 0, cnt_total = 0, wsum_total = 0, dlog_total = 0;
 };
 

@@ -103,6 +103,7 @@ int sim_run_batch(sim_ctx *ctx, uint32_t n_inst, const sim_params *p, const uint
     B.wsum = b.keep ? (uint64_t *)b.wsum.ptr : nullptr;
     B.dlog = P.dlog_total ? (uint8_t *)b.dlog.ptr : nullptr;
     B.final_stats = (fw::TilePartial *)b.final_stats.ptr;
+    B.wave_mode = P.wave_mode ? 1u : 0u;
 
     HIP_TRY(ctx, hipMemcpyAsync(b.inst.ptr, b.inst_host, sizeof(InstanceDesc) * n_inst, hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(b.tiles.ptr, b.tiles_host, sizeof(fw::Tile) * n_tiles, hipMemcpyHostToDevice, ctx->stream));
@@ -112,7 +113,8 @@ int sim_run_batch(sim_ctx *ctx, uint32_t n_inst, const sim_params *p, const uint
     const bool same_args = A.inst == B.inst && A.tiles == B.tiles && A.n_tiles == B.n_tiles && A.n_inst == B.n_inst &&
                            A.partials == B.partials && A.slot_begin == B.slot_begin && A.fck == B.fck &&
                            A.total_R == B.total_R && A.y == B.y && A.tau == B.tau && A.cnt == B.cnt &&
-                           A.wsum == B.wsum && A.dlog == B.dlog && A.final_stats == B.final_stats;
+                           A.wsum == B.wsum && A.dlog == B.dlog && A.final_stats == B.final_stats &&
+                           A.wave_mode == B.wave_mode;
     if (graph && (!b.exec || !same_args)) {
         // capture the two kernel launches on the library's own stream (default priority)
         if (b.exec) {

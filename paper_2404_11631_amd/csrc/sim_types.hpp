@@ -89,7 +89,12 @@ struct BatchBuffers {
     uint64_t *wsum;           // KEEP_PATHS: concatenated [d_i][R_i]
     uint8_t *dlog;            // DECISION_LOG: concatenated [T_i][log_count_i]
     TilePartial *final_stats; // [n_inst] reduced per instance
+    uint32_t wave_mode;       // 1: every tile is one replication on a wavefront (fw_wave_kernel)
 };
+
+// LDS staging of a batched tile's normals (floats per wavefront). A replication qualifies for the
+// one-wavefront form when its N d normals (rounded up to a Philox block) fit in it.
+constexpr uint32_t kBatchStageFloats = 2112;
 
 // Descriptor flag bits: 1 keep per-path records, 2 decision log, 4 control-variate features,
 // 8 outcomes Y only (set by the library for its own control-variate runs).

@@ -154,3 +154,37 @@ def test_plan_checks_full_uneven_workload():
     with pytest.raises(sim.SimError) as e:
         sim.plan_batch([big], [64], [10])
     assert e.value.code == -1
+
+
+WAVE_CASES = [  # (d, N, T, R, M): every instance at 64 lanes per replication, Gaussian noise
+    (10, 10, 40, 3, 1),
+    (2, 100, 25, 2, 2),       # N > 64: a lane forms two samples' dot products
+    (32, 65, 12, 2, 1),       # d = 32 (the largest), N d + 3 = 2083 of the 2112 staged floats
+    (7, 9, 30, 3, 3),         # d not a multiple of 4: Philox blocks span samples
+]
+
+
+def test_wave_kernel_matches_oracle(emu):
+    """The one-wavefront form (fw_wave_kernel: a replication per wavefront, an asset per lane), chosen
+    when every instance asks for 64 lanes per replication with Gaussian noise and N d within the
+    staging area, against the oracle under the same replay protocol."""
+    probs, R, T = [], [], []
+    for i, (d, N, t, r, M) in enumerate(WAVE_CASES):
+        mu, sigma = workloads.diag_instance(78, i, d)
+        w0 = np.full(d, 0.5 / d) if i == 3 else None
+        probs.append(sim.Problem(mu=mu, sigma=sigma, N=N, M=M, checkpoints=(5, t), gap_eps=0.05, w0=w0,
+                                 instance_id=20 + i, log_reps=(0, r)))
+        R.append(r)
+        T.append(t)
+    n, a, Ra, Ta, cfg, keep = sim._batch_args(probs, R, T, lanes_per_rep=[64] * len(probs), keep_paths=True)
+    assert emu.emu_run_batch(n, a, Ra, Ta, 41, ctypes.byref(cfg), 1) == 0
+    for i, p in enumerate(probs):
+        st = sim.SimStats()
+        emu.emu_batch_stats(i, ctypes.byref(st))
+        g = _paths(emu, i)
+        assert g["lanes_per_rep"] == 64
+        op = parity.oracle_problem(p, 41)
+        outs = (oracle.PathOut * R[i])()
+        for r in range(R[i]):
+            outs[r] = parity.check_rep(op, g, r, T[i], oracle.U32, decisions=g["decisions"][:, r])
+        parity.check_stats(st, op.reduce(outs, T[i]), len(p.checkpoints), len(p.mu), g["tau"])

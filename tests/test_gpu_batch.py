@@ -233,3 +233,50 @@ def test_graph_launch_replays_match_eager(ctx):
         ctx.stats()
     ctx.run_batch(probs, R, T, seed=42, keep_paths=True, graph=True)
     same(snap(), eager42)
+
+
+WAVE = [  # (d, N, T, R, M): every instance at 64 lanes per replication, Gaussian noise
+    (10, 10, 400, 40, 1),
+    (2, 100, 200, 20, 2),      # N > 64
+    (32, 65, 100, 12, 1),      # d = 32, N d + 3 = 2083 of the 2112 staged floats
+    (7, 9, 300, 30, 3),        # Philox blocks span samples
+]
+
+
+def test_wave_kernel_parity(ctx):
+    """The one-wavefront form (fw_wave_kernel), which the batch takes when every instance asks for 64
+    lanes per replication with Gaussian noise and N d within the staging area, against the oracle
+    under the replay protocol; then the paper-scale instance (d = N = 10) over its full horizon
+    T = 1e4, as the control-variate leg's plain stage runs it."""
+    probs, R, T = [], [], []
+    for i, (d, N, t, r, M) in enumerate(WAVE):
+        mu, sigma = workloads.diag_instance(78, i, d)
+        w0 = np.full(d, 0.5 / d) if i == 3 else None
+        probs.append(sim.Problem(mu=mu, sigma=sigma, N=N, M=M, checkpoints=(10, t), gap_eps=0.05, w0=w0,
+                                 instance_id=20 + i, log_reps=(0, r)))
+        R.append(r)
+        T.append(t)
+    say(f"[batch] wave form, {len(probs)} instances")
+    ctx.run_batch(probs, R, T, seed=41, lanes_per_rep=[64] * len(probs), keep_paths=True)
+    for i, p in enumerate(probs):
+        st = ctx.batch_stats(i)
+        g = ctx.batch_paths(i)
+        assert g["lanes_per_rep"] == 64
+        op = parity.oracle_problem(p, 41)
+        outs = (oracle.PathOut * R[i])()
+        for r in range(R[i]):
+            outs[r] = parity.check_rep(op, g, r, T[i], oracle.U32, decisions=g["decisions"][:, r])
+        parity.check_stats(st, op.reduce(outs, T[i]), len(p.checkpoints), len(p.mu), g["tau"])
+        say(f"[batch] wave instance {i} d={len(p.mu)} N={p.N} ok")
+    w = workloads.WORKLOADS["paper_scale"]
+    mu, sigma = workloads.diag_instance(w["seed"], 0, w["d"])
+    p = sim.Problem(mu=mu, sigma=sigma, N=w["N"], checkpoints=(5000, w["T"]), log_reps=(0, 8))
+    ctx.run_batch([p], [8], [w["T"]], seed=3, lanes_per_rep=[64], keep_paths=True)
+    st = ctx.batch_stats(0)
+    g = ctx.batch_paths(0)
+    op = parity.oracle_problem(p, 3)
+    outs = (oracle.PathOut * 8)()
+    for r in range(8):
+        outs[r] = parity.check_rep(op, g, r, w["T"], oracle.U32, decisions=g["decisions"][:, r])
+    parity.check_stats(st, op.reduce(outs, w["T"]), len(p.checkpoints), len(p.mu), g["tau"])
+    say(f"[batch] wave form at the paper-scale instance, T = {w['T']}: ok ({st.kernel_ms:.1f} ms)")
