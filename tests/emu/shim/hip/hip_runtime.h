@@ -85,11 +85,29 @@ template <class T> inline T __shfl_down(T v, unsigned off, int width = 64)
 inline void __syncthreads() { g_block->bar->arrive_and_wait(); }
 // threads are not lockstep here: the wave barrier synchronizes them like a workgroup barrier
 inline void __builtin_amdgcn_wave_barrier() { g_block->bar->arrive_and_wait(); }
-// DPP quad_perm (dpp_ctrl < 0x100): lane 4q + i reads lane 4q + ((ctrl >> 2i) & 3)
+// DPP: quad_perm (dpp_ctrl < 0x100), lane 4q + i reads lane 4q + ((ctrl >> 2i) & 3); row_mirror
+// (0x140), lane i of a 16-lane row reads lane 15 - i; row_half_mirror (0x141), lane i of an 8-lane
+// half row reads lane 7 - i
 inline int __builtin_amdgcn_mov_dpp(int v, int ctrl, int, int, bool)
 {
-    const int lane = threadIdx.x % 64, i = lane & 3;
-    return emu_exchange(v, threadIdx.x - i + ((ctrl >> (2 * i)) & 3));
+    const int lane = threadIdx.x % 64, base = threadIdx.x - lane;
+    int src;
+    if (ctrl == 0x140) src = (lane & ~15) | (15 - (lane & 15));
+    else if (ctrl == 0x141) src = (lane & ~7) | (7 - (lane & 7));
+    else src = (lane & ~3) | ((ctrl >> (2 * (lane & 3))) & 3);
+    return emu_exchange(v, base + src);
+}
+// v_permlane16_swap with both operands x: the pair (x[lane & ~16], x[lane | 16])
+struct EmuPair32 {
+    uint32_t v[2];
+    uint32_t operator[](int i) const { return v[i]; }
+};
+inline EmuPair32 __builtin_amdgcn_permlane16_swap(uint32_t x, uint32_t, bool, bool)
+{
+    const int lane = threadIdx.x % 64, base = threadIdx.x - lane;
+    const uint32_t lo = (uint32_t)emu_exchange((int)x, base + (lane & ~16));
+    const uint32_t hi = (uint32_t)emu_exchange((int)x, base + (lane | 16));
+    return EmuPair32{{lo, hi}};
 }
 inline float __int_as_float(int x) { float f; std::memcpy(&f, &x, 4); return f; }
 inline int __float_as_int(float f) { int x; std::memcpy(&x, &f, 4); return x; }
