@@ -25,6 +25,7 @@
 #include "device_reduce.hpp"
 #include "device_rng.hpp"
 #include "sim_types.hpp"
+#include "wave_dpp.hpp"
 
 namespace fw {
 
@@ -390,55 +391,11 @@ __device__ __forceinline__ void run_tile(const BatchBuffers &B, const Tile tile,
     }
 }
 
-// Sum over the 32 lanes of each half wavefront (every lane gets its half's sum), on DPP and the
-// 16-lane row swap, without the LDS crossbar: lane ^ 1 and lane ^ 2 (quad permutes), the other quad
-// of each 8 (half-row mirror), the other 8 of each 16 (row mirror), the other 16 (row swap). Each
-// step adds a lane's value to its partner's, so every lane of a group ends with the same bits.
-template <int CTRL>
-__device__ __forceinline__ float dpp_step(float x)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
-}
+// Sums and (value, index) minima over the 32 lanes of each half wavefront on DPP and the 16-lane row
+// swap (wave_dpp.hpp); the FP64 sum keeps the shuffle butterfly (checkpoints only).
+__device__ __forceinline__ float half_sum32(float x) { return dpp_sum32(x); }
 
-__device__ __forceinline__ float half_sum32(float x)
-{
-    x += dpp_step<0xB1>(x);
-    x += dpp_step<0x4E>(x);
-    x += dpp_step<0x141>(x);
-    x += dpp_step<0x140>(x);
-    const auto h = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
-    return __uint_as_float(h[0]) + __uint_as_float(h[1]);
-}
-
-template <int CTRL>
-__device__ __forceinline__ void argmin_step(float &g, uint32_t &j)
-{
-    const float og = dpp_step<CTRL>(g);
-    const uint32_t oj = static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(j), CTRL, 0xF, 0xF, true));
-    if (og < g || (og == g && oj < j)) {
-        g = og;
-        j = oj;
-    }
-}
-
-// (value, index) minimum over the 32 lanes of each half wavefront, lowest index among equal values,
-// with the same exchanges (the rule is symmetric, so every lane ends with the same pair)
-__device__ __forceinline__ void half_argmin32(float &g, uint32_t &j)
-{
-    argmin_step<0xB1>(g, j);
-    argmin_step<0x4E>(g, j);
-    argmin_step<0x141>(g, j);
-    argmin_step<0x140>(g, j);
-    const auto hg = __builtin_amdgcn_permlane16_swap(__float_as_uint(g), __float_as_uint(g), false, false);
-    const auto hj = __builtin_amdgcn_permlane16_swap(j, j, false, false);
-    const bool upper = (threadIdx.x & 16u) != 0u;
-    const float og = __uint_as_float(upper ? hg[0] : hg[1]);
-    const uint32_t oj = upper ? hj[0] : hj[1];
-    if (og < g || (og == g && oj < j)) {
-        g = og;
-        j = oj;
-    }
-}
+__device__ __forceinline__ void half_argmin32(float &g, uint32_t &j) { dpp_argmin32(g, j); }
 
 __device__ __forceinline__ double half_sum32(double x)
 {

@@ -25,31 +25,18 @@
 #include "device_rng.hpp"
 #include "newsvendor.hpp"
 #include "sim_types.hpp"
+#include "wave_dpp.hpp"
 
 namespace fw {
 
 namespace {
 
-// (value, index) minimum over a wavefront, lowest index among equal values; every lane gets it.
-__device__ __forceinline__ void wave_argmin(float &g, uint32_t &j)
-{
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        const float og = __shfl_xor(g, m, 64);
-        const uint32_t oj = __shfl_xor(j, m, 64);
-        if (og < g || (og == g && oj < j)) {
-            g = og;
-            j = oj;
-        }
-    }
-}
+// (value, index) minimum over a wavefront, lowest index among equal values, and a sum over it; every
+// lane gets the result. The DPP exchanges pair lanes as the xor butterfly 1, 2, ..., 32 does, so
+// the sums' rounding is that butterfly's.
+__device__ __forceinline__ void wave_argmin(float &g, uint32_t &j) { dpp_argmin64(g, j); }
 
-__device__ __forceinline__ float wave_sum(float x)
-{
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) x += __shfl_xor(x, m, 64);
-    return x;
-}
+__device__ __forceinline__ float wave_sum(float x) { return dpp_sum64(x); }
 
 // The step of iteration t over the workgroup partials of replication r (buffer par): the smallest
 // ratio (lowest product among equal values; the workgroups cover ascending product ranges, so strict
@@ -205,10 +192,8 @@ __global__ __launch_bounds__(kNvBlock) void nv_sample_kernel(NvArgs A, uint32_t 
 #pragma unroll
         for (int k = 0; k < 4; ++k) count[k] += (z.z[k] <= thr[k]) ? 1u : 0u;
     }
-    for (uint32_t m = 1; m < P; m <<= 1) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) count[k] += __shfl_xor(count[k], m, 64);
-    }
+    for (int k = 0; k < 4; ++k) count[k] = dpp_sum_lanes(count[k], P);
     float rmin = INFINITY, gx = 0.0f;
     uint32_t jmin = 0xFFFFFFFFu;
     if (active && lead) {
@@ -463,10 +448,8 @@ __global__ __launch_bounds__(kNvBlock) void nv_lp_gradient_kernel(NvLpArgs A, ui
 #pragma unroll
         for (int k = 0; k < 4; ++k) count[k] += (static_cast<double>(z.z[k]) <= thr[k]) ? 1u : 0u;
     }
-    for (uint32_t m = 1; m < P; m <<= 1) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) count[k] += __shfl_xor(count[k], m, 64);
-    }
+    for (int k = 0; k < 4; ++k) count[k] = dpp_sum_lanes(count[k], P);
     if (active && lead) {
         double gq[4];
 #pragma unroll

@@ -26,54 +26,24 @@
 #include "sim.h"
 #include "device_rng.hpp"
 #include "sim_types.hpp"
+#include "wave_dpp.hpp"
 #include "wide.hpp"
 
 namespace fw {
 
 namespace {
 
-// Sum over the 32 lanes of a half wavefront (the lanes of one sample chunk); every lane gets it.
-__device__ __forceinline__ float half_sum(float x)
-{
-#pragma unroll
-    for (int m = 1; m < 32; m <<= 1) x += __shfl_xor(x, m, 32);
-    return x;
-}
+// Sums and (value, index) minima (lowest index among equal values) over the 32 lanes of a half
+// wavefront (the lanes of one sample chunk) or over the 64 of a wavefront; every lane gets the
+// result. The DPP exchanges pair lanes as the xor butterfly 1, 2, ... does, so the sums' rounding is
+// that butterfly's.
+__device__ __forceinline__ float half_sum(float x) { return dpp_sum32(x); }
 
-// (value, index) minimum over the 32 lanes of a half wavefront, lowest index among equal values.
-__device__ __forceinline__ void half_argmin(float &g, uint32_t &j)
-{
-#pragma unroll
-    for (int m = 1; m < 32; m <<= 1) {
-        const float og = __shfl_xor(g, m, 32);
-        const uint32_t oj = __shfl_xor(j, m, 32);
-        if (og < g || (og == g && oj < j)) {
-            g = og;
-            j = oj;
-        }
-    }
-}
+__device__ __forceinline__ void half_argmin(float &g, uint32_t &j) { dpp_argmin32(g, j); }
 
-// Sum and (value, index) minimum over the 64 lanes of a wavefront, lowest index among equal values.
-__device__ __forceinline__ float wave64_sum(float x)
-{
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) x += __shfl_xor(x, m, 64);
-    return x;
-}
+__device__ __forceinline__ float wave64_sum(float x) { return dpp_sum64(x); }
 
-__device__ __forceinline__ void wave64_argmin(float &g, uint32_t &j)
-{
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        const float og = __shfl_xor(g, m, 64);
-        const uint32_t oj = __shfl_xor(j, m, 64);
-        if (og < g || (og == g && oj < j)) {
-            g = og;
-            j = oj;
-        }
-    }
-}
+__device__ __forceinline__ void wave64_argmin(float &g, uint32_t &j) { dpp_argmin64(g, j); }
 
 // A quad's signature words, scaled sigma and start point, loaded together (d is a multiple of 4 and
 // every array starts 16-byte aligned, so each is one or two 16-byte words); qc is a quad in range.

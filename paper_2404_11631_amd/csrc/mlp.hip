@@ -22,6 +22,7 @@
 #include "device_reduce.hpp"
 #include "device_rng.hpp"
 #include "mlp.hpp"
+#include "wave_dpp.hpp"
 
 namespace fw {
 
@@ -116,7 +117,9 @@ __device__ __forceinline__ float forward_rows(const MlpDev &m, const float *x, u
         a2[i] += b2[out_unit(i, h)];
         part = fmaf(w3[out_unit(i, h)], gelu(a2[i]), part);
     }
-    return part + __shfl_xor(part, 32, 64) + m.theta[m.off_b3];
+    // the two halves' partial sums over the hidden units: lane ^ 32 by the 32-lane swap
+    const auto hp = __builtin_amdgcn_permlane32_swap(__float_as_uint(part), __float_as_uint(part), false, false);
+    return (__uint_as_float(hp[0]) + __uint_as_float(hp[1])) + m.theta[m.off_b3];
 }
 
 template <int KS1>
@@ -132,13 +135,9 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(MlpDev m, const float 
     if (valid && lane < 32) out[row] = shift + scale * o;
 }
 
-// Sum over the 32 rows of one half-wavefront; every lane of the half gets the total.
-__device__ __forceinline__ float half_sum(float v)
-{
-#pragma unroll
-    for (int m = 1; m < 32; m <<= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
+// Sum over the 32 rows of one half-wavefront; every lane of the half gets the total (DPP and the
+// 16-lane row swap; the pairing is the xor butterfly's, so is the rounding).
+__device__ __forceinline__ float half_sum(float v) { return dpp_sum32(v); }
 
 // Loss and gradient partials of one workgroup (128 rows): part[blockIdx][P + 1], loss at P.
 // Rows: q = q0 + 128 blockIdx + 32 wave + j, data row (a q + c) mod n_data, valid while q < q_end.

@@ -95,7 +95,7 @@ inline int __builtin_amdgcn_mov_dpp(int v, int ctrl, int, int, bool)
     if (ctrl == 0x140) src = (lane & ~15) | (15 - (lane & 15));
     else if (ctrl == 0x141) src = (lane & ~7) | (7 - (lane & 7));
     else src = (lane & ~3) | ((ctrl >> (2 * (lane & 3))) & 3);
-    return emu_exchange(v, base + src);
+    return emu_exchange(v, base + src, 32);   // within a half wavefront: a half may call it alone
 }
 // v_permlane16_swap with both operands x: the pair (x[lane & ~16], x[lane | 16])
 struct EmuPair32 {
@@ -105,8 +105,16 @@ struct EmuPair32 {
 inline EmuPair32 __builtin_amdgcn_permlane16_swap(uint32_t x, uint32_t, bool, bool)
 {
     const int lane = threadIdx.x % 64, base = threadIdx.x - lane;
-    const uint32_t lo = (uint32_t)emu_exchange((int)x, base + (lane & ~16));
-    const uint32_t hi = (uint32_t)emu_exchange((int)x, base + (lane | 16));
+    const uint32_t lo = (uint32_t)emu_exchange((int)x, base + (lane & ~16), 32);
+    const uint32_t hi = (uint32_t)emu_exchange((int)x, base + (lane | 16), 32);
+    return EmuPair32{{lo, hi}};
+}
+// v_permlane32_swap with both operands x: the pair (x[lane & ~32], x[lane | 32])
+inline EmuPair32 __builtin_amdgcn_permlane32_swap(uint32_t x, uint32_t, bool, bool)
+{
+    const int lane = threadIdx.x % 64, base = threadIdx.x - lane;
+    const uint32_t lo = (uint32_t)emu_exchange((int)x, base + (lane & ~32));
+    const uint32_t hi = (uint32_t)emu_exchange((int)x, base + (lane | 32));
     return EmuPair32{{lo, hi}};
 }
 inline float __int_as_float(int x) { float f; std::memcpy(&f, &x, 4); return f; }
