@@ -406,14 +406,18 @@ __device__ __forceinline__ double half_sum32(double x)
 
 // One replication per wavefront (every tile of P = 64 lanes, Gaussian noise, N d + 3 <= the
 // staging area): lane j < d holds asset j (d <= 32, so the assets sit in the first half wavefront).
-// An iteration draws the epoch's N d normals into LDS (a Philox block per lane at a time), lane i
-// forms sample i's dot product with v = sz .* w, lane j the sums over the samples of z_ij and
-// z_ij (z_i'v); the gradient, its minimum (lowest index among equal values) and g'w are reduced
+// Lane i forms sample i's dot product with v = sz .* w, lane j the sums over the samples of z_ij
+// and z_ij (z_i'v); the gradient, its minimum (lowest index among equal values) and g'w are reduced
 // over the first half wavefront. Same formulas as the tile kernel, summed in a different order.
+// A second wavefront of the workgroup draws the next epoch's N d normals (a Philox block per lane
+// at a time) into the other of two LDS buffers while the first runs the iteration on the current
+// one; one workgroup barrier per iteration hands the buffers over. The normals do not depend on
+// the iterate, so the draw leaves the iteration's dependent chain.
 __device__ __forceinline__ void run_wave(const BatchBuffers &B, const Tile tile, float *zs, float *vs, float *dots)
 {
     const InstanceDesc *P = B.inst + tile.inst;
-    const uint32_t lane = threadIdx.x;
+    const uint32_t lane = threadIdx.x % kWave;
+    const bool drawer = threadIdx.x >= kWave;          // the second wavefront: the next epoch's normals
     const uint32_t r = tile.rep0;
     const uint32_t d = P->d, N = P->N, M = P->M, nd = N * d, nb = (nd + 3) / 4;
     const uint64_t T = P->T;
@@ -432,6 +436,7 @@ __device__ __forceinline__ void run_wave(const BatchBuffers &B, const Tile tile,
     uint32_t S = 0u, cnt = 0u, cnt0 = 0u, hib = 0u;
     uint32_t tau = kTauNone, ck = 0, epoch = 0, m_in_epoch = 0;
     uint64_t next_ckpt = n_ckpt ? P->ckpt[0] : 0;
+    float cw = 0.0f;   // w_t = cw S for t >= 1
     // f(w) at w = c S, FP64 (Eq. (3), diagonal Sigma), summed over the assets' lanes
     auto objective = [&](double c) {
         const double w = (static_cast<double>(S) + (hib ? 4294967296.0 : 0.0)) * c;
@@ -441,70 +446,89 @@ __device__ __forceinline__ void run_wave(const BatchBuffers &B, const Tile tile,
         return fma(lambda, quad, -lin);
     };
 
-    for (uint64_t t = 0; t < T; ++t) {
-        const float cw = t == 0 ? 0.0f
-                                : static_cast<float>(2.0 / (static_cast<double>(t) * static_cast<double>(t + 1)));
-        const float w = (t == 0) ? w0 : (static_cast<float>(S) + (hib ? 4294967296.0f : 0.0f)) * cw;
-        const float v = sz * w;
-        if (lane < 32) vs[lane] = v;
-        const PhiloxRow row = philox_row(epoch, r, k0);
-        for (uint32_t b = lane; b < nb; b += kWave) {
+    // the normals of epoch e into buffer e mod 2, blocks b = first, first + stride, ...
+    auto draw = [&](uint32_t e, uint32_t first, uint32_t stride) {
+        const PhiloxRow row = philox_row(e, r, k0);
+        float *dst = zs + (e & 1u) * kStageFloats;
+        for (uint32_t b = first; b < nb; b += stride) {
             const Block4<float> q = normals_block_row(row, b, dom, k0, k1);
-            zs[4 * b + 0] = q.z[0];
-            zs[4 * b + 1] = q.z[1];
-            zs[4 * b + 2] = q.z[2];
-            zs[4 * b + 3] = q.z[3];
+            dst[4 * b + 0] = q.z[0];
+            dst[4 * b + 1] = q.z[1];
+            dst[4 * b + 2] = q.z[2];
+            dst[4 * b + 3] = q.z[3];
         }
-        wave_lds_order();
-        for (uint32_t i = lane; i < N; i += kWave) {
-            float dot = 0.0f;
+    };
+    draw(0u, threadIdx.x, 2 * kWave);
+    __syncthreads();
+
+    for (uint64_t t = 0; t < T; ++t) {
+        if (drawer) {
+            // epoch + 1 goes to the buffer the iteration does not read; it was last read before the
+            // previous barrier
+            if (m_in_epoch + 1 == M && t + 1 < T) draw(epoch + 1, lane, kWave);
+        } else {
+            const float *zc = zs + (epoch & 1u) * kStageFloats;
+            const float w = (t == 0) ? w0 : (static_cast<float>(S) + (hib ? 4294967296.0f : 0.0f)) * cw;
+            const float v = sz * w;
+            if (lane < 32) vs[lane] = v;
+            wave_lds_order();
+            for (uint32_t i = lane; i < N; i += kWave) {
+                float dot = 0.0f;
 #pragma unroll 8
-            for (uint32_t j = 0; j < d; ++j) dot = fmaf(zs[i * d + j], vs[j], dot);
-            dots[i] = dot;
-        }
-        wave_lds_order();
-        float s1 = 0.0f, s2 = 0.0f;
-        if (in) {
-#pragma unroll 8
-            for (uint32_t i = 0; i < N; ++i) {
-                const float z = zs[i * d + lane];
-                s1 += z;
-                s2 = fmaf(z, dots[i], s2);
+                for (uint32_t j = 0; j < d; ++j) dot = fmaf(zc[i * d + j], vs[j], dot);
+                dots[i] = dot;
             }
+            wave_lds_order();
+            float s1 = 0.0f, s2 = 0.0f;
+            if (in) {
+#pragma unroll 8
+                for (uint32_t i = 0; i < N; ++i) {
+                    const float z = zc[i * d + lane];
+                    s1 += z;
+                    s2 = fmaf(z, dots[i], s2);
+                }
+            }
+            wave_lds_order();                               // vs and dots are rewritten next iteration
+            // the next iteration's scale 2/((t+1)(t+2)), its FP64 division beside the reductions
+            // rather than at the head of the next iteration's chain
+            const float cw_next =
+                static_cast<float>(2.0 / (static_cast<double>(t + 1) * static_cast<double>(t + 2)));
+            const float qn = half_sum32(s1 * v) * inv_n;
+            float g = INFINITY;
+            uint32_t jg = 0xFFFFFFFFu;
+            if (in) {
+                g = fmaf(-c1, s1, fmaf(c2, fmaf(-s1, qn, s2), -mu));
+                jg = lane;
+            }
+            const float gw = half_sum32(in ? g * w : 0.0f);
+            half_argmin32(g, jg);
+            const uint32_t a = (g < 0.0f) ? jg + 1 : 0u;
+            const float gap = gw - (g < 0.0f ? g : 0.0f);
+            if (tau == kTauNone && gap <= gap_eps) tau = static_cast<uint32_t>(t);
+            if (logged) B.dlog[log_at + t * log_count] = static_cast<uint8_t>(a);
+            // step 2/(t+2): the signature absorbs the update
+            cnt0 += (a == 0u) ? 1u : 0u;
+            if (a == lane + 1) {
+                const uint32_t now = S + static_cast<uint32_t>(t + 1);
+                if (now < S) hib = 1u;
+                S = now;
+                cnt += 1u;
+            }
+            if (t + 1 == next_ckpt) {
+                const double f = objective(2.0 / (static_cast<double>(t + 1) * static_cast<double>(t + 2)));
+                if (lane == 0) B.fck[static_cast<uint64_t>(ck) * B.total_R + P->path_base + r] = f;
+                ++ck;
+                next_ckpt = ck < n_ckpt ? P->ckpt[ck] : 0;
+            }
+            cw = cw_next;
         }
-        wave_lds_order();                               // zs, vs and dots are rewritten next iteration
-        const float qn = half_sum32(s1 * v) * inv_n;
-        float g = INFINITY;
-        uint32_t jg = 0xFFFFFFFFu;
-        if (in) {
-            g = fmaf(-c1, s1, fmaf(c2, fmaf(-s1, qn, s2), -mu));
-            jg = lane;
-        }
-        const float gw = half_sum32(in ? g * w : 0.0f);
-        half_argmin32(g, jg);
-        const uint32_t a = (g < 0.0f) ? jg + 1 : 0u;
-        const float gap = gw - (g < 0.0f ? g : 0.0f);
-        if (tau == kTauNone && gap <= gap_eps) tau = static_cast<uint32_t>(t);
-        if (logged) B.dlog[log_at + t * log_count] = static_cast<uint8_t>(a);
-        // step 2/(t+2): the signature absorbs the update
-        cnt0 += (a == 0u) ? 1u : 0u;
-        if (a == lane + 1) {
-            const uint32_t now = S + static_cast<uint32_t>(t + 1);
-            if (now < S) hib = 1u;
-            S = now;
-            cnt += 1u;
-        }
-        if (t + 1 == next_ckpt) {
-            const double f = objective(2.0 / (static_cast<double>(t + 1) * static_cast<double>(t + 2)));
-            if (lane == 0) B.fck[static_cast<uint64_t>(ck) * B.total_R + P->path_base + r] = f;
-            ++ck;
-            next_ckpt = ck < n_ckpt ? P->ckpt[ck] : 0;
-        }
+        __syncthreads();   // both wavefronts: the drawn buffer is complete and the read one is free
         if (++m_in_epoch == M) {
             m_in_epoch = 0;
             ++epoch;
         }
     }
+    if (drawer) return;
     const double y = objective(2.0 / (static_cast<double>(T) * static_cast<double>(T + 1)));
 
     if (B.y) {
@@ -567,10 +591,11 @@ __global__ __launch_bounds__(kWave) void fw_tile_kernel(BatchBuffers B)
     run_tile(B, tile, stage, coef);
 }
 
-// One replication per wavefront, every tile of a batch that qualifies (BatchBuffers.wave_mode).
-__global__ __launch_bounds__(kWave) void fw_wave_kernel(BatchBuffers B)
+// One replication per workgroup of two wavefronts (the iteration, the next epoch's normals), every
+// tile of a batch that qualifies (BatchBuffers.wave_mode).
+__global__ __launch_bounds__(2 * kWave) void fw_wave_kernel(BatchBuffers B)
 {
-    __shared__ float zs[kStageFloats];
+    __shared__ float zs[2 * kStageFloats];
     __shared__ float vs[32];
     __shared__ float dots[kStageFloats];
     const Tile tile = B.tiles[blockIdx.x];
@@ -633,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void fw_batch_reduce(BatchBuffers B)
 int launch_fw_batch(const BatchBuffers &B, hipStream_t stream)
 {
     if (B.n_tiles) {
-        if (B.wave_mode) hipLaunchKernelGGL(fw_wave_kernel, dim3(B.n_tiles), dim3(kWave), 0, stream, B);
+        if (B.wave_mode) hipLaunchKernelGGL(fw_wave_kernel, dim3(B.n_tiles), dim3(2 * kWave), 0, stream, B);
         else hipLaunchKernelGGL(fw_tile_kernel, dim3(B.n_tiles), dim3(kWave), 0, stream, B);
     }
     hipLaunchKernelGGL(fw_batch_reduce, dim3(B.n_inst), dim3(kBlock), 0, stream, B);

@@ -60,7 +60,7 @@ extern "C" int emu_run_batch(uint32_t n_inst, const sim_params *p, const uint64_
     B.final_stats = g_final.data();
     B.wave_mode = P.wave_mode ? 1u : 0u;
     for (uint32_t t = 0; t < P.n_tiles; ++t)
-        emu_run_block(64, t, [&] { if (B.wave_mode) fw_wave_kernel(B); else fw_tile_kernel(B); });
+        emu_run_block(B.wave_mode ? 128 : 64, t, [&] { if (B.wave_mode) fw_wave_kernel(B); else fw_tile_kernel(B); });
     for (uint32_t i = 0; i < n_inst; ++i) emu_run_block(256, i, [&] { fw_batch_reduce(B); });
     return 0;
 }

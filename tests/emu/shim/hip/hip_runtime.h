@@ -83,8 +83,8 @@ template <class T> inline T __shfl_down(T v, unsigned off, int width = 64)
     return emu_exchange(v, base + src, width);
 }
 inline void __syncthreads() { g_block->bar->arrive_and_wait(); }
-// threads are not lockstep here: the wave barrier synchronizes them like a workgroup barrier
-inline void __builtin_amdgcn_wave_barrier() { g_block->bar->arrive_and_wait(); }
+// threads are not lockstep here: the wave barrier synchronizes the wavefront's 64 threads
+inline void __builtin_amdgcn_wave_barrier() { g_block->wave[threadIdx.x / 64]->arrive_and_wait(); }
 // DPP: quad_perm (dpp_ctrl < 0x100), lane 4q + i reads lane 4q + ((ctrl >> 2i) & 3); row_mirror
 // (0x140), lane i of a 16-lane row reads lane 15 - i; row_half_mirror (0x141), lane i of an 8-lane
 // half row reads lane 7 - i
