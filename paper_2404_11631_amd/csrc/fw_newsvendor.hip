@@ -510,7 +510,7 @@ __global__ __launch_bounds__(BLOCK) void nv_lp_subproblem_kernel(NvLpArgs A, uin
     {
         double acc = 0.0;
         for (uint32_t j = tid; j < n; j += BLOCK) acc = __dadd_rn(acc, __dmul_rn(g[j], x[j]));
-        for (int m = 1; m < 64; m <<= 1) acc = __dadd_rn(acc, __shfl_xor(acc, m, 64));
+        acc = dpp_sum64(acc);   // the xor butterfly's pairing, on DPP and the lane swaps
         if (lane == 0) wv[wave] = acc;
         __syncthreads();
         if (tid == 0) {
@@ -561,11 +561,7 @@ __global__ __launch_bounds__(BLOCK) void nv_lp_subproblem_kernel(NvLpArgs A, uin
             }
             if (rc < -A.eps_r) nv_lp_better(bv, bj, bland ? 0.0 : rc, j);
         }
-        for (int m = 1; m < 64; m <<= 1) {
-            const double ov = __shfl_xor(bv, m, 64);
-            const uint32_t oj = __shfl_xor(bj, m, 64);
-            nv_lp_better(bv, bj, ov, oj);
-        }
+        dpp_argmin64(bv, bj);   // nv_lp_better's rule, the xor butterfly's pairing
         if (lane == 0) {
             wv[wave] = bv;
             wj[wave] = bj;

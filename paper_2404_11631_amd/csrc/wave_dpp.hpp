@@ -25,6 +25,35 @@ __device__ __forceinline__ uint32_t dpp_move(uint32_t x)
     return static_cast<uint32_t>(__builtin_amdgcn_mov_dpp(static_cast<int>(x), CTRL, 0xF, 0xF, true));
 }
 
+// binary64 values move as their two 32-bit halves
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x)
+{
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(x));
+    const uint32_t lo = dpp_move<CTRL>(static_cast<uint32_t>(b)), hi = dpp_move<CTRL>(static_cast<uint32_t>(b >> 32));
+    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
+}
+
+// the values of lane & ~16 and lane | 16 (16-lane swap), or lane & ~32 and lane | 32 (32-lane swap)
+template <bool WIDE>
+__device__ __forceinline__ void lane_swap(double x, double &first, double &second)
+{
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(x));
+    const uint32_t lo = static_cast<uint32_t>(b), hi = static_cast<uint32_t>(b >> 32);
+    uint32_t l0, l1, h0, h1;
+    if constexpr (WIDE) {
+        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        l0 = l[0], l1 = l[1], h0 = h[0], h1 = h[1];
+    } else {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        l0 = l[0], l1 = l[1], h0 = h[0], h1 = h[1];
+    }
+    first = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(h0) << 32) | l0));
+    second = __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(h1) << 32) | l1));
+}
+
 // lanes in groups of 16 hold their group's sum
 __device__ __forceinline__ float dpp_sum16(float x)
 {
@@ -98,6 +127,46 @@ __device__ __forceinline__ void dpp_argmin64(float &g, uint32_t &j)
     const auto hj = __builtin_amdgcn_permlane32_swap(j, j, false, false);
     const bool upper = (threadIdx.x & 32u) != 0u;
     argmin_take(g, j, __uint_as_float(upper ? hg[0] : hg[1]), upper ? hj[0] : hj[1]);
+}
+
+// binary64 sum over the wavefront, rounded to nearest at every step
+__device__ __forceinline__ double dpp_sum64(double x)
+{
+    x = __dadd_rn(x, dpp_move<0xB1>(x));
+    x = __dadd_rn(x, dpp_move<0x4E>(x));
+    x = __dadd_rn(x, dpp_move<0x141>(x));
+    x = __dadd_rn(x, dpp_move<0x140>(x));
+    double a, b;
+    lane_swap<false>(x, a, b);
+    x = __dadd_rn(a, b);
+    lane_swap<true>(x, a, b);
+    return __dadd_rn(a, b);
+}
+
+__device__ __forceinline__ void argmin_take(double &g, uint32_t &j, double og, uint32_t oj)
+{
+    if (og < g || (og == g && oj < j)) {
+        g = og;
+        j = oj;
+    }
+}
+
+// binary64 (value, index) minimum over the wavefront, lowest index among equal values
+__device__ __forceinline__ void dpp_argmin64(double &g, uint32_t &j)
+{
+    argmin_take(g, j, dpp_move<0xB1>(g), dpp_move<0xB1>(j));
+    argmin_take(g, j, dpp_move<0x4E>(g), dpp_move<0x4E>(j));
+    argmin_take(g, j, dpp_move<0x141>(g), dpp_move<0x141>(j));
+    argmin_take(g, j, dpp_move<0x140>(g), dpp_move<0x140>(j));
+    double a, b;
+    lane_swap<false>(g, a, b);
+    auto hj = __builtin_amdgcn_permlane16_swap(j, j, false, false);
+    bool upper = (threadIdx.x & 16u) != 0u;
+    argmin_take(g, j, upper ? a : b, upper ? hj[0] : hj[1]);
+    lane_swap<true>(g, a, b);
+    hj = __builtin_amdgcn_permlane32_swap(j, j, false, false);
+    upper = (threadIdx.x & 32u) != 0u;
+    argmin_take(g, j, upper ? a : b, upper ? hj[0] : hj[1]);
 }
 
 }  // namespace fw

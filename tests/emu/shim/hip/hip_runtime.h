@@ -128,6 +128,8 @@ template <class T> inline T __hip_atomic_fetch_add(T *p, T v, int, int)
 template <class T> inline void __hip_atomic_store(T *p, T v, int, int) { std::atomic_ref<T>(*p).store(v); }
 template <class T> inline T __hip_atomic_load(T *p, int, int) { return std::atomic_ref<T>(*p).load(); }
 inline float __uint_as_float(uint32_t x) { float f; std::memcpy(&f, &x, 4); return f; }
+inline long long __double_as_longlong(double d) { long long x; std::memcpy(&x, &d, 8); return x; }
+inline double __longlong_as_double(long long x) { double d; std::memcpy(&d, &x, 8); return d; }
 inline uint32_t __float_as_uint(float f) { uint32_t x; std::memcpy(&x, &f, 4); return x; }
 inline float __builtin_amdgcn_sqrtf(float x) { return std::sqrt(x); }
 inline float __builtin_amdgcn_logf(float x) { return std::log2(x); }
