@@ -226,8 +226,9 @@ typedef struct {
  * launch of every tile, longest first (the hardware dispatcher is the work queue), replications of
  * heavy instances split across several lanes (assets x sample chunks), then one per-instance
  * reduction in fixed order. When every instance asks for 64 lanes per replication, has Gaussian
- * noise and N d + 3 <= 2112, each replication instead runs on a wavefront of its own with an asset
- * per lane (the latency form, for few replications); the results follow the same protocol.
+ * noise and N d + 3 <= 2112, each replication instead runs on a workgroup of its own: a wavefront
+ * with an asset per lane, and a second one that draws the next epoch's normals (the latency form,
+ * for few replications); the results follow the same protocol.
  * Each instance uses its instance_id as stream domain and the common noise `seed`.
  * Supported: FP32 state, diagonal Sigma, d <= 32, T <= 131071 (the signature is held in 33 bits),
  * per-instance R < 2^32, 1 <= n_inst <= 65536. Decision logs follow each instance's
